@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Time-to-solution of AMP-PCG versus FP64 PCG on one MI355X.
+
+A step is one complete solve (all kernels of the hot path, from r0 = b - A x0
+to the verified solution) of the 3-D 7-point finite-volume diffusion system
+on a 128^3 grid with block coefficients 10^U, U ~ U[0, 4] on 8^3 blocks
+(N = 2,097,152, nnz = 14,581,760), Jacobi preconditioner, tol 1e-10.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line: value = AMP-PCG time-to-solution (ms, lower is
+better); the FP64 PCG time on the same GPU, the speedup, the iteration
+counts, the SpMV kernel's achieved HBM bandwidth against the 8 TB/s peak, and
+the FP64 CPU oracle timed on the host are reported beside it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-solution at rel. residual 1e-10, AMP-PCG vs FP64 PCG; SpMV HBM GB/s"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def spmv_algorithmic_bytes(n, nnz, nslices, b_val, b_p, b_q):
+    """Bytes one product q = A p must move: values and column indices once,
+    the slice pointers, p read once (the gather is counted once), q written
+    once.  Slice padding is overhead, not counted."""
+    return nnz * (b_val + 4) + n * (b_p + b_q) + (nslices + 1) * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--preset", default="amp64")
+    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2505_04155_amd as amp
+    from paper_2505_04155_amd import binding
+    from workloads import problems as P
+
+    binding.load(build_if_missing=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log(f"bench: generating the {args.grid}^3 system")
+    A, b, _ = P.blocky_diffusion3d_system(args.grid, 8)
+    M = amp.Matrix.from_csr(A, device=dev)
+    pc = amp.Preconditioner(M, "jacobi")
+    bt = torch.tensor(b, device=dev)
+    info_m = M.info()
+    tol, maxit = 1e-10, 20000
+
+    def run(preset):
+        x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+        if info["status"] != 0:
+            raise RuntimeError(f"{preset} solve failed: {info}")
+        return x, info
+
+    results = {}
+    for preset in (args.preset, "pcg64"):
+        for w in range(args.warmup):
+            run(preset)
+            log(f"bench: warmup {preset} {w + 1}/{args.warmup} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for s in range(args.steps):
+            _, info = run(preset)
+            infos.append(info)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / args.steps
+        results[preset] = (ms, infos[-1])
+        log(f"bench: {preset}: {ms:.3f} ms/solve, {infos[-1]['iters']} iterations, "
+            f"switches z32={infos[-1]['k_z32']} z16={infos[-1]['k_z16']} r32={infos[-1]['k_r32']}")
+
+    amp_ms, amp_info = results[args.preset]
+    fp64_ms, fp64_info = results["pcg64"]
+
+    # Dominant kernel: the SpMV of the reduced-precision phase (FP32 values in
+    # difference form, p in FP16, q in FP32), timed with HIP events on the
+    # stream the library launches on (torch's current stream).
+    n, nnz, slots = info_m["n"], info_m["nnz"], info_m["slots"]
+    nslices = ((n + 1023) // 1024 * 1024) // 64      # rows padded to 1024, 64 rows per slice
+    L = binding.load()
+    stream = torch.cuda.current_stream()
+    sp = __import__("ctypes").c_void_p(stream.cuda_stream)
+    for _ in range(5):
+        binding.check(L.amp_spmv(M.handle, 32, 16, 1, None, None, None, sp), "amp_spmv")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.spmv_reps):
+        L.amp_spmv(M.handle, 32, 16, 1, None, None, None, sp)
+    e1.record(stream)
+    e1.synchronize()
+    spmv_ms = e0.elapsed_time(e1) / args.spmv_reps
+    spmv_bytes = spmv_algorithmic_bytes(n, nnz, nslices, 4, 2, 4)
+    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+    log(f"bench: spmv fp32-diff/fp16: {spmv_ms * 1e3:.2f} us, {spmv_gbs:.0f} GB/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import cpcg
+        threads = len(os.sched_getaffinity(0))
+        cpcg.lib().oracle_set_threads(threads)
+        log(f"bench: CPU oracle (FP64 PCG, {threads} threads)")
+        t0 = time.perf_counter()
+        xo, io = cpcg.pcg(A, b, tol=tol, maxit=maxit)
+        t1 = time.perf_counter()
+        cpu = {"value": round((t1 - t0) * 1e3, 3), "unit": "ms", "cores": threads, "kind": "oracle",
+               "sample": f"one full FP64 PCG solve (Alg. 1, Jacobi) of the same system: "
+                         f"{io['iters']} iterations"}
+        log(f"bench: CPU oracle {cpu['value']:.1f} ms, {io['iters']} iterations")
+
+    out = {
+        "metric": METRIC,
+        "value": round(amp_ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(amp_ms, 4),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64+f32+f16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D 7-point FV diffusion {args.grid}^3, coefficients 10^U(0,4) on 8^3 blocks, "
+                        f"N={n}, nnz={nnz}, Jacobi, tol 1e-10, b ~ N(0,1)",
+            "preset": args.preset,
+            "parallelism": "single GPU",
+        },
+        "fp64_pcg_ms": round(fp64_ms, 4),
+        "speedup_vs_fp64_pcg": round(fp64_ms / amp_ms, 4),
+        "iters": amp_info["iters"],
+        "iters_fp64": fp64_info["iters"],
+        "switch_iterations": {"u_z_fp32": amp_info["k_z32"], "u_z_fp16": amp_info["k_z16"],
+                              "u_r_fp32": amp_info["k_r32"]},
+        "rel_res_true": amp_info["relres_true"],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmv_fixed<16,32,diff> (q = A p: FP32 values, FP16 p, FP32 q)",
+            "achieved": round(spmv_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_kernel_us": round(spmv_ms * 1e3, 3),
+            "algorithmic_bytes_per_launch": spmv_bytes,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * amp_pcg.h -- C ABI of the adaptive mixed-precision, dynamically scaled
+ * preconditioned conjugate gradient solver (AMP-PCG) for AMD MI355X (gfx950).
+ *
+ * Method: Guo, de Sturler, Warburton, "An Adaptive Mixed-Precision and
+ * Dynamically Scaled Preconditioned Conjugate Gradient Algorithm"
+ * (arXiv:2505.04155).  Problem statement: Alg. 3 (AMP-PCG(u0)) -- solve
+ * A x = b for a symmetric positive definite A with preconditioner M to
+ * ||b - A x|| <= tol ||b||.
+ *
+ * Conventions for every call:
+ *   - Plain C, no exceptions cross the boundary.  Every entry point returns
+ *     an amp_status; on failure amp_last_error() (thread-local) describes it.
+ *   - "device pointer": memory allocated on the current HIP device (e.g. a
+ *     torch.cuda tensor's data_ptr()).  The caller owns it; the library never
+ *     frees caller memory and never keeps a pointer to it after returning.
+ *   - "stream": a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  All device work is enqueued on it; calls documented as
+ *     host-synchronous wait for their own work before returning.
+ *   - Handles (amp_matrix, amp_precond) own device memory allocated with
+ *     hipMalloc and are freed by their destroy call.  A handle may be used
+ *     by one solve at a time.
+ *   - Precisions are named by bit width: 64 = IEEE double, 32 = single,
+ *     16 = half.
+ */
+#ifndef AMP_PCG_H
+#define AMP_PCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMP_OK = 0,
+    AMP_ERR_ARG = 1,            /* invalid argument (null pointer, n <= 0, tol <= 0, ...) */
+    AMP_ERR_NOT_CONVERGED = 2,  /* maxit reached; x holds the last iterate */
+    AMP_ERR_BREAKDOWN = 3,      /* rho <= 0, gamma <= 0 or a non-finite scalar; x holds the last finite iterate */
+    AMP_ERR_HIP = 4,            /* a HIP runtime call failed */
+    AMP_ERR_OOM = 5             /* device allocation failed */
+} amp_status;
+
+typedef enum { AMP_FP64 = 64, AMP_FP32 = 32, AMP_FP16 = 16 } amp_prec;
+
+/* Attainable-accuracy indicator that drives the u_r switch (Section 4.1). */
+typedef enum {
+    AMP_ETA_DELAY = 0,    /* eq. (eta_k): delay window d, constant C */
+    AMP_ETA_LINEAR = 1,   /* eq. (linear criterion): rate over ell steps */
+    AMP_UR_FIXED64 = 2,   /* u_r stays FP64 */
+    AMP_UR_FIXED32 = 3    /* u_r is FP32 from the first iteration */
+} amp_eta_mode;
+
+/* Dynamic scaling omega_k of the residual before preconditioning (Alg. 2). */
+typedef enum {
+    AMP_SCALE_POW2 = 0,   /* omega_k = 2^{e_k}, e_k from the vectors' maxima (default) */
+    AMP_SCALE_PAPER = 1,  /* omega_k = 1/delta_k, as written in Alg. 3 */
+    AMP_SCALE_NONE = 2    /* omega_k = 1 (plain PCG, Alg. 1) */
+} amp_scaling;
+
+typedef enum { AMP_PC_IDENTITY = 0, AMP_PC_JACOBI = 1, AMP_PC_CHEBYSHEV = 2 } amp_pc_kind;
+
+/* Preset selectors of the PCG variants compared in Section 5. */
+typedef enum {
+    AMP_PRESET_PCG64 = 0,   /* PCG(FP64): all vectors FP64 */
+    AMP_PRESET_AMP64 = 1,   /* AMP-PCG(FP64): u0 = FP64, u_z lowered by tau_zs/tau_zh */
+    AMP_PRESET_AMP16 = 2,   /* AMP-PCG(FP16): z, p in FP16 from the start */
+    AMP_PRESET_AMP_UR = 3   /* AMP-PCG(u_r): u_z fixed FP64, only u_r adapts */
+} amp_preset;
+
+/* Matrix in CSR form, all arrays device pointers: row_ptr[n+1], col_idx[nnz],
+ * val[nnz].  Columns sorted within each row, the diagonal present, nnz < 2^31.
+ * The values are read once by amp_matrix_create (no reference is kept). */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} amp_csr;
+
+typedef struct amp_matrix_s *amp_matrix;
+typedef struct amp_precond_s *amp_precond;
+
+/* Solver options; fill with amp_options_default / amp_options_preset. */
+typedef struct {
+    int u0;                 /* initial (maximum) precision of u_z: 64, 32 or 16 (Alg. 3) */
+    double tau_zs, tau_zh;  /* nu-thresholds for u_z -> FP32, -> FP16 (eq. precision_selector, eq. criterion) */
+    int eta_mode;           /* amp_eta_mode */
+    int d;                  /* delay of eq. (eta_k), 1 <= d <= 100 (default 10) */
+    double C;               /* constant C of eq. (eta_k) / eq. (linear criterion) (default 1) */
+    int ell;                /* window of eq. (linear criterion), 1 <= ell <= 100 (default 5) */
+    int scaling;            /* amp_scaling */
+    int T_z, T_p;           /* pow2 scaling targets: max|z^| ~ 2^T_z, carried part of p^ <= beta 2^T_p (default 12, 12) */
+    int spmv32_diff;        /* 1: FP32 product in row-sum/difference form (default); 0: textbook form */
+    int verify;             /* 1: FP64 true-residual check at termination with replacement (default) */
+    int max_replacements;   /* replacements allowed by the termination check (default 3) */
+    int rr_period;          /* >0: replace r by b - A x every rr_period iterations (default 0) */
+    int batch;              /* iterations enqueued between host status checks (default 0 = automatic) */
+    double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
+    int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
+} amp_options;
+
+typedef struct {
+    int iters;                /* iterations performed */
+    int status;               /* amp_status of the solve */
+    double rel_res_updated;   /* ||r_iters|| / ||b|| (the recurrence residual) */
+    double rel_res_true;      /* ||b - A x|| / ||b|| in FP64 (0 when verify = 0) */
+    double bnorm;             /* ||b|| */
+    int k_z32, k_z16, k_r32;  /* first iteration with u_z <= FP32, u_z = FP16, u_r = FP32 (-1: never) */
+    int n_replacements;       /* residual replacements performed */
+    double t_solve_ms;        /* wall time of the solve call (host clock, includes the final check) */
+} amp_result;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int amp_version(void);
+/* Human-readable status name; never NULL. */
+const char *amp_status_string(amp_status s);
+/* Description of the last failure on the calling thread ("" if none). */
+const char *amp_last_error(void);
+
+/* Defaults: the AMP-PCG(FP64) preset with d = 10, C = 1, ell = 5,
+ * tau_zs = 1e-4, tau_zh = 1e-6 (Section 5, eq. criterion), pow2 scaling. */
+void amp_options_default(amp_options *opt);
+/* Fill *opt with one of the Section 5 variants (amp_preset); other fields
+ * take their defaults.  Returns AMP_ERR_ARG for an unknown preset. */
+amp_status amp_options_preset(amp_options *opt, int preset);
+
+/*
+ * Build the solver's matrix handle from a device CSR matrix (Section 4: the
+ * matrix-vector product is computed in u_r).  Converts to sliced ELL (slice
+ * height 64, rows in natural order, int32 column indices) with an FP64 value
+ * plane (products in FP64) and an FP32 plane (products in FP32; the diagonal
+ * slot holds the FP64 row sum rounded to FP32 for the difference form).
+ * Enqueued on `stream` and host-synchronous.
+ * Errors: AMP_ERR_ARG for n <= 0, nnz < n, nnz >= 2^31, null pointers or a
+ * non-positive diagonal entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
+ */
+amp_status amp_matrix_create(const amp_csr *A, void *stream, amp_matrix *out);
+void amp_matrix_destroy(amp_matrix A);
+/* Rows, stored slots (including slice padding) and device bytes of the handle. */
+amp_status amp_matrix_info(amp_matrix A, int64_t *n, int64_t *nnz, int64_t *slots, int64_t *bytes);
+
+/*
+ * Preconditioner handle.  AMP_PC_JACOBI: M = diag(A) (Section 5.5), inverse
+ * stored in FP64, FP32, and FP16 scaled by a power of two.  AMP_PC_CHEBYSHEV:
+ * z = D^{-1/2} s(B) D^{-1/2} y, B = D^{-1/2} A D^{-1/2} stored in FP16,
+ * s the degree-(degree-1) polynomial with 1 - t s(t) = T_degree((theta - t)/
+ * delta)/T_degree(theta/delta) on [lam_lo, lam_hi] (eigenvalue bounds of
+ * D^{-1} A).  AMP_PC_IDENTITY: M = I.  Host-synchronous.
+ * Errors: AMP_ERR_ARG for an unknown kind, degree outside 1..16, or
+ * Chebyshev bounds not satisfying 0 < lam_lo < lam_hi.
+ */
+amp_status amp_precond_create(amp_matrix A, int kind, int degree, double lam_lo, double lam_hi,
+                              void *stream, amp_precond *out);
+void amp_precond_destroy(amp_precond M);
+
+/*
+ * Solve A x = b (Alg. 3, AMP-PCG(u0)).  b: device FP64[n]; x: device
+ * FP64[n], initial guess on entry, solution on exit.  opt may be NULL
+ * (defaults).  The iteration runs on the device: the precision selector,
+ * the eta indicator, the scaling and the stopping test are evaluated by the
+ * kernels themselves; the host only polls a status word every opt->batch
+ * iterations.  Host-synchronous; fills *res (may be NULL).
+ * Returns AMP_OK when ||r|| <= tol ||b|| (and, with verify, the FP64 true
+ * residual too), AMP_ERR_NOT_CONVERGED at maxit, AMP_ERR_BREAKDOWN on a
+ * breakdown, AMP_ERR_ARG for bad arguments (tol <= 0, maxit < 0, null
+ * pointers, M built for another matrix, bad option values).
+ */
+amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
+                         int maxit, const amp_options *opt, amp_result *res, void *stream);
+
+/*
+ * One product q = A p with the solver's own kernel, for tests and
+ * measurement.  u_r selects the value plane and arithmetic (64: FP64
+ * values and accumulation; 32: FP32 values and accumulation, in
+ * row-sum/difference form when diff != 0, textbook form otherwise); u_p is
+ * the storage precision of p.  p: device array of n elements of precision
+ * u_p, or NULL to reuse the vector the handle's last solve or product left
+ * in its p buffer of that precision.  q: device array of n elements of
+ * precision u_r, or NULL to leave q in the handle's buffer.  gamma
+ * (nullable, device FP64[1]) receives q^T p accumulated in FP64.  With
+ * p = q = gamma = NULL the call is exactly one kernel launch.  Enqueued on
+ * stream, not synchronised.  Errors: AMP_ERR_ARG for a null handle or a
+ * precision outside {64, 32} x {64, 32, 16}.
+ */
+amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,
+                    void *stream);
+
+/*
+ * One scaled preconditioner application z = M^{-1} fl_{u_z}(fl_{u_r}(omega r)),
+ * Alg. 3 steps y = r/delta, z = M^{-1} y, with r stored in u_r and z in u_z.
+ * omega is the total scale (for FP16 Jacobi the static storage scale of
+ * dinv is compensated inside).  rho (nullable, device FP64[1]) receives
+ * r^T z in FP64.  Enqueued on stream, not synchronised.
+ */
+amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const void *r, double omega, void *z,
+                             double *rho, void *stream);
+
+/*
+ * Host-only: run the device controller's latched precision selector over a
+ * recorded residual-norm history delta[0..len-1] (eq. precision_selector
+ * with eq. eta_k or eq. linear criterion) and report the first iteration at
+ * which u_z <= FP32, u_z = FP16 and u_r = FP32 (-1: never).  Needs no GPU.
+ */
+amp_status amp_selector_replay(const double *delta, int len, double bnorm, double tol,
+                               const amp_options *opt, int *k_z32, int *k_z16, int *k_r32);
+
+/*
+ * Host-only: algorithmic bytes moved per row by one iteration's kernels of
+ * the paper's five-kernel decomposition (Table tab:pcg_cost) for storage
+ * precisions (u_z, u_r), with the Jacobi preconditioner and M stored in
+ * u_z: out[0..3] = zamx, innerProd, axpy, updatePCG.  Needs no GPU.
+ */
+amp_status amp_paper_kernel_bytes(int u_z, int u_r, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMP_PCG_H */

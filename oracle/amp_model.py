@@ -212,7 +212,7 @@ class Jacobi:
         if not np.all(d > 0):
             raise ValueError("Jacobi needs a positive diagonal")
         self.dinv64 = 1.0 / d
-        self.s_d = -int(math.ceil(math.log2(self.dinv64.max())))
+        self.s_d = -_ceil_log2(float(self.dinv64.max()))
         self.dinv = {64: self.dinv64, 32: fl(self.dinv64, 32),
                      16: fl(self.dinv64 * 2.0 ** self.s_d, 16)}
         self.log2_extra = {64: 0, 32: 0, 16: self.s_d}
@@ -336,7 +336,9 @@ def _diff_spmv32(A):
 
 
 def _ceil_log2(v):
-    return int(math.ceil(math.log2(v)))
+    """ceil(log2 v) for v > 0, exactly (from the binary exponent)."""
+    m, e = math.frexp(v)
+    return e - 1 if m == 0.5 else e
 
 
 def scale_exponent(M, opt, k, maxr, maxr_prev, e_prev, maxz_prev, maxp_prev):
@@ -405,6 +407,7 @@ def amp_pcg(A, b, x0=None, tol=1e-10, maxit=5000, M=None, opt: AmpOptions | None
             res.k_z32 = k
         if uz <= 16 and res.k_z16 < 0:
             res.k_z16 = k
+        maxr = float(np.max(np.abs(r.astype(np.float64))))   # max|r_k| as stored
         if ur != ur_prev:
             res.k_r32 = k
             r = fl(r, ur)              # r_k now held in u_{r,k}
@@ -413,7 +416,6 @@ def amp_pcg(A, b, x0=None, tol=1e-10, maxit=5000, M=None, opt: AmpOptions | None
         cr = NP[ur]
 
         # 3: dynamic scaling
-        maxr = float(np.max(np.abs(r.astype(np.float64))))
         if opt.scaling == "paper":
             omega, e_k = 1.0 / delta[k], None
         elif opt.scaling == "none":

@@ -1,0 +1,12 @@
+"""AMP-PCG for AMD MI355X: adaptive mixed-precision, dynamically scaled
+preconditioned conjugate gradients (Guo, de Sturler, Warburton,
+arXiv:2505.04155) as hand-written HIP kernels behind a C ABI
+(include/amp_pcg.h).
+
+Python entry points (argument marshalling only):
+
+* :class:`Matrix`, :class:`Preconditioner`, :func:`solve`
+* :func:`selector_replay`, :func:`paper_kernel_bytes` (host-only helpers)
+"""
+
+from .solver import Matrix, Preconditioner, solve, selector_replay, paper_kernel_bytes  # noqa: F401

@@ -1,0 +1,754 @@
+// Host side of the AMP-PCG library: handles, sliced-ELL setup, the solve
+// driver (status polling, batching) and the C ABI declared in amp_pcg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amp_kernels.hpp"
+#include "amp_pcg.h"
+
+using namespace amp;
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+static amp_status fail(amp_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define AMP_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? AMP_ERR_OOM : AMP_ERR_HIP,               \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                   \
+        }                                                                                    \
+    } while (0)
+
+#define AMP_TRY(expr)                                 \
+    do {                                              \
+        amp_status s_ = (expr);                       \
+        if (s_ != AMP_OK) return s_;                  \
+    } while (0)
+
+template <typename T>
+static amp_status dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    AMP_HIP(hipMalloc((void **)p, count * sizeof(T)));
+    return AMP_OK;
+}
+
+template <typename T>
+static void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+static inline hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+static inline bool valid_prec(int u) { return u == 64 || u == 32 || u == 16; }
+
+// ----------------------------------------------------------------------------
+// handles
+// ----------------------------------------------------------------------------
+
+struct Work {
+    int64_t np = 0;
+    double *x = nullptr, *b = nullptr;
+    double *r64 = nullptr, *z64 = nullptr, *p64 = nullptr, *q64 = nullptr;
+    float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    half_t *z16 = nullptr, *p16 = nullptr;
+    double *part = nullptr;
+    Ctrl *ctrl = nullptr;
+    Ctrl *snap = nullptr;         // pinned host snapshots [2]
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+struct amp_matrix_s {
+    int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0;
+    int64_t *sptr = nullptr;
+    int32_t *col = nullptr;
+    double *v64 = nullptr;
+    float *v32 = nullptr, *v32p = nullptr;
+    double *diag = nullptr;       // diag(A), 1 on padding rows
+    Work w;
+    Sell sell() const {
+        Sell s;
+        s.n = n; s.np = np; s.nslices = nslices; s.sptr = sptr; s.col = col;
+        s.v64 = v64; s.v32 = v32; s.v32p = v32p;
+        return s;
+    }
+};
+
+struct amp_precond_s {
+    amp_matrix A = nullptr;
+    int kind = 0, degree = 0;
+    double lam_lo = 0, lam_hi = 0;
+    double *d64 = nullptr;
+    float *d32 = nullptr;
+    half_t *d16 = nullptr;
+    int extra16 = 0;     // FP16 data = fl16(dinv 2^extra16)
+    double gain = 1.0;   // max|M^{-1} r| <= gain max|r|
+};
+
+static int grid_stream(int64_t np) {
+    int64_t g = (np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+}
+
+static int grid_slices(int64_t nslices) {
+    int64_t g = (nslices + NT / WAVE - 1) / (NT / WAVE);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+}
+
+static void free_work(Work &w) {
+    dfree(w.x); dfree(w.b);
+    dfree(w.r64); dfree(w.z64); dfree(w.p64); dfree(w.q64);
+    dfree(w.r32); dfree(w.z32); dfree(w.p32); dfree(w.q32);
+    dfree(w.z16); dfree(w.p16); dfree(w.part); dfree(w.ctrl);
+    if (w.snap) (void)hipHostFree(w.snap);
+    w.snap = nullptr;
+    for (auto &e : w.ev)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
+}
+
+static amp_status ensure_work(amp_matrix A, hipStream_t st) {
+    Work &w = A->w;
+    if (w.ctrl) return AMP_OK;
+    const int64_t np = A->np;
+    w.np = np;
+    AMP_TRY(dalloc(&w.x, np)); AMP_TRY(dalloc(&w.b, np));
+    AMP_TRY(dalloc(&w.r64, np)); AMP_TRY(dalloc(&w.z64, np));
+    AMP_TRY(dalloc(&w.p64, np)); AMP_TRY(dalloc(&w.q64, np));
+    AMP_TRY(dalloc(&w.r32, np)); AMP_TRY(dalloc(&w.z32, np));
+    AMP_TRY(dalloc(&w.p32, np)); AMP_TRY(dalloc(&w.q32, np));
+    AMP_TRY(dalloc(&w.z16, np)); AMP_TRY(dalloc(&w.p16, np));
+    AMP_TRY(dalloc(&w.part, 2 * GMAX)); AMP_TRY(dalloc(&w.ctrl, 1));
+    AMP_HIP(hipHostMalloc((void **)&w.snap, 2 * sizeof(Ctrl), hipHostMallocDefault));
+    for (auto &e : w.ev) AMP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // zero every vector once: the padding tail stays zero for the handle's life
+    AMP_HIP(hipMemsetAsync(w.x, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.b, 0, np * 8, st));
+    AMP_HIP(hipMemsetAsync(w.r64, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.z64, 0, np * 8, st));
+    AMP_HIP(hipMemsetAsync(w.p64, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.q64, 0, np * 8, st));
+    AMP_HIP(hipMemsetAsync(w.r32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.z32, 0, np * 4, st));
+    AMP_HIP(hipMemsetAsync(w.p32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.q32, 0, np * 4, st));
+    AMP_HIP(hipMemsetAsync(w.z16, 0, np * 2, st)); AMP_HIP(hipMemsetAsync(w.p16, 0, np * 2, st));
+    AMP_HIP(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
+    AMP_HIP(hipStreamSynchronize(st));
+    A->bytes += np * (8 * 6 + 4 * 4 + 2 * 2);
+    return AMP_OK;
+}
+
+static Bufs make_bufs(amp_matrix A, amp_precond M) {
+    Work &w = A->w;
+    Bufs B;
+    B.x = w.x; B.b = w.b;
+    B.r[0] = w.r64; B.r[1] = w.r32; B.r[2] = nullptr;
+    B.z[0] = w.z64; B.z[1] = w.z32; B.z[2] = w.z16;
+    B.p[0] = w.p64; B.p[1] = w.p32; B.p[2] = w.p16;
+    B.q[0] = w.q64; B.q[1] = w.q32; B.q[2] = nullptr;
+    B.dinv[0] = M ? M->d64 : nullptr;
+    B.dinv[1] = M ? M->d32 : nullptr;
+    B.dinv[2] = M ? M->d16 : nullptr;
+    B.part = w.part;
+    return B;
+}
+
+// ----------------------------------------------------------------------------
+// CSR -> sliced ELL
+// ----------------------------------------------------------------------------
+
+__global__ void k_slice_width(const int32_t *rp, int64_t n, int64_t nslices, int32_t *width) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    int32_t w = 0;
+    for (int l = 0; l < SLICE; ++l) {
+        const int64_t row = s * SLICE + l;
+        if (row < n) {
+            const int32_t len = rp[row + 1] - rp[row];
+            w = len > w ? len : w;
+        }
+    }
+    width[s] = w;
+}
+
+// One thread per (padded) row: copy its entries into its slice's column-major
+// slots, form the FP64 row sum, check column range and the diagonal.
+__global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, int64_t n, int64_t np,
+                       const int64_t *sptr, int32_t *col, double *v64, float *v32, float *v32p,
+                       double *diag, int *err) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= np) return;
+    const int64_t s = row / SLICE, lane = row % SLICE;
+    const int w = (int)((sptr[s + 1] - sptr[s]) / SLICE);
+    const int64_t b = sptr[s] + lane;
+    int len = 0, beg = 0;
+    double rs = 0.0, d = 0.0;
+    bool has_diag = false;
+    if (row < n) {
+        beg = rp[row];
+        len = rp[row + 1] - beg;
+        for (int j = 0; j < len; ++j) rs += val[beg + j];
+    }
+    for (int j = 0; j < w; ++j) {
+        const int64_t slot = b + (int64_t)j * SLICE;
+        if (j < len) {
+            const int32_t c = ci[beg + j];
+            const double v = val[beg + j];
+            if (c < 0 || c >= n) atomicOr(err, 1);
+            col[slot] = c;
+            v64[slot] = v;
+            v32p[slot] = (float)v;
+            if (c == row) {
+                has_diag = true;
+                d = v;
+                v32[slot] = (float)rs;
+            } else {
+                v32[slot] = (float)v;
+            }
+        } else {
+            col[slot] = (int32_t)row;
+            v64[slot] = 0.0;
+            v32[slot] = 0.0f;
+            v32p[slot] = 0.0f;
+        }
+    }
+    if (row < n) {
+        if (!has_diag || !(d > 0.0)) atomicOr(err, 2);
+        diag[row] = d;
+    } else {
+        diag[row] = 1.0;
+    }
+}
+
+extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_matrix *out) {
+    if (!out) return fail(AMP_ERR_ARG, "amp_matrix_create: out is NULL");
+    *out = nullptr;
+    if (!csr || !csr->row_ptr || !csr->col_idx || !csr->val)
+        return fail(AMP_ERR_ARG, "amp_matrix_create: null CSR pointer");
+    if (csr->n <= 0) return fail(AMP_ERR_ARG, "amp_matrix_create: n must be positive");
+    if (csr->nnz < csr->n || csr->nnz >= ((int64_t)1 << 31))
+        return fail(AMP_ERR_ARG, "amp_matrix_create: need n <= nnz < 2^31");
+    hipStream_t st = as_stream(stream);
+    amp_matrix A = new amp_matrix_s();
+    auto bail = [&](amp_status s) { amp_matrix_destroy(A); return s; };
+    A->n = csr->n;
+    A->nnz = csr->nnz;
+    A->np = round_up(A->n, PAD);
+    A->nslices = A->np / SLICE;
+
+    int32_t *width = nullptr;
+    int *err = nullptr;
+    amp_status s;
+    if ((s = dalloc(&width, A->nslices)) != AMP_OK) return bail(s);
+    if ((s = dalloc(&err, 1)) != AMP_OK) { dfree(width); return bail(s); }
+    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) {
+        dfree(width); dfree(err);
+        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: memset failed"));
+    }
+    k_slice_width<<<(unsigned)((A->nslices + 255) / 256), 256, 0, st>>>(csr->row_ptr, A->n, A->nslices, width);
+    std::vector<int32_t> hw(A->nslices);
+    std::vector<int64_t> hp(A->nslices + 1);
+    if (hipMemcpyAsync(hw.data(), width, A->nslices * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        dfree(width); dfree(err);
+        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: reading slice widths failed"));
+    }
+    hp[0] = 0;
+    for (int64_t i = 0; i < A->nslices; ++i) hp[i + 1] = hp[i] + (int64_t)hw[i] * SLICE;
+    A->slots = hp[A->nslices];
+    dfree(width);
+    if ((s = dalloc(&A->sptr, A->nslices + 1)) != AMP_OK ||
+        (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->v32, A->slots)) != AMP_OK || (s = dalloc(&A->v32p, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->diag, A->np)) != AMP_OK) {
+        dfree(err);
+        return bail(s);
+    }
+    A->bytes = (A->nslices + 1) * 8 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
+    if (hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess) {
+        dfree(err);
+        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: upload of slice pointers failed"));
+    }
+    k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
+                                                          A->sptr, A->col, A->v64, A->v32, A->v32p, A->diag, err);
+    int herr = 0;
+    hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    dfree(err);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return bail(fail(AMP_ERR_HIP, std::string("amp_matrix_create: ") + hipGetErrorString(e2)));
+    if (herr & 1) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: column index out of range"));
+    if (herr & 2) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: missing or non-positive diagonal entry"));
+    *out = A;
+    return AMP_OK;
+}
+
+extern "C" void amp_matrix_destroy(amp_matrix A) {
+    if (!A) return;
+    free_work(A->w);
+    dfree(A->sptr); dfree(A->col); dfree(A->v64); dfree(A->v32); dfree(A->v32p); dfree(A->diag);
+    delete A;
+}
+
+extern "C" amp_status amp_matrix_info(amp_matrix A, int64_t *n, int64_t *nnz, int64_t *slots, int64_t *bytes) {
+    if (!A) return fail(AMP_ERR_ARG, "amp_matrix_info: null handle");
+    if (n) *n = A->n;
+    if (nnz) *nnz = A->nnz;
+    if (slots) *slots = A->slots;
+    if (bytes) *bytes = A->bytes;
+    return AMP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// preconditioner
+// ----------------------------------------------------------------------------
+
+__global__ void k_jacobi_setup(const double *diag, int64_t n, int64_t np, double *d64, float *d32,
+                               unsigned long long *maxbits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double m = 0.0;
+    if (i < np) {
+        const double v = (i < n) ? 1.0 / diag[i] : 0.0;
+        d64[i] = v;
+        d32[i] = (float)v;
+        m = v;
+    }
+    block_max_to(maxbits, m);
+}
+
+__global__ void k_identity_setup(int64_t n, int64_t np, double *d64, float *d32, half_t *d16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) {
+        const bool in = i < n;
+        d64[i] = in ? 1.0 : 0.0;
+        d32[i] = in ? 1.0f : 0.0f;
+        d16[i] = (half_t)(in ? 1.0f : 0.0f);
+    }
+}
+
+__global__ void k_scale_to_half(const double *d64, int64_t np, double scale, half_t *d16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) d16[i] = (half_t)(d64[i] * scale);
+}
+
+extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, double lam_lo, double lam_hi,
+                                         void *stream, amp_precond *out) {
+    if (!out) return fail(AMP_ERR_ARG, "amp_precond_create: out is NULL");
+    *out = nullptr;
+    if (!A) return fail(AMP_ERR_ARG, "amp_precond_create: null matrix");
+    if (kind != AMP_PC_IDENTITY && kind != AMP_PC_JACOBI)
+        return fail(AMP_ERR_ARG, "amp_precond_create: unsupported preconditioner kind");
+    (void)degree; (void)lam_lo; (void)lam_hi;
+    hipStream_t st = as_stream(stream);
+    amp_precond M = new amp_precond_s();
+    auto bail = [&](amp_status s) { amp_precond_destroy(M); return s; };
+    M->A = A;
+    M->kind = kind;
+    amp_status s;
+    if ((s = dalloc(&M->d64, A->np)) != AMP_OK || (s = dalloc(&M->d32, A->np)) != AMP_OK ||
+        (s = dalloc(&M->d16, A->np)) != AMP_OK)
+        return bail(s);
+    const unsigned g = (unsigned)((A->np + 255) / 256);
+    if (kind == AMP_PC_IDENTITY) {
+        k_identity_setup<<<g, 256, 0, st>>>(A->n, A->np, M->d64, M->d32, M->d16);
+        M->gain = 1.0;
+        M->extra16 = 0;
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
+    } else {
+        unsigned long long *mb = nullptr;
+        if ((s = dalloc(&mb, 1)) != AMP_OK) return bail(s);
+        if (hipMemsetAsync(mb, 0, sizeof(unsigned long long), st) != hipSuccess) {
+            dfree(mb);
+            return bail(fail(AMP_ERR_HIP, "amp_precond_create: memset failed"));
+        }
+        k_jacobi_setup<<<g, 256, 0, st>>>(A->diag, A->n, A->np, M->d64, M->d32, mb);
+        unsigned long long hb = 0;
+        hipError_t e1 = hipMemcpyAsync(&hb, mb, sizeof(hb), hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipStreamSynchronize(st);
+        dfree(mb);
+        if (e1 != hipSuccess || e2 != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
+        double dmax;
+        std::memcpy(&dmax, &hb, sizeof(dmax));
+        if (!(dmax > 0.0) || !std::isfinite(dmax)) return bail(fail(AMP_ERR_ARG, "amp_precond_create: bad diagonal"));
+        M->gain = dmax;
+        M->extra16 = -ceil_log2(dmax);   // max of the FP16 copy lies in (1/2, 1]
+        k_scale_to_half<<<g, 256, 0, st>>>(M->d64, A->np, std::ldexp(1.0, M->extra16), M->d16);
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
+    }
+    *out = M;
+    return AMP_OK;
+}
+
+extern "C" void amp_precond_destroy(amp_precond M) {
+    if (!M) return;
+    dfree(M->d64); dfree(M->d32); dfree(M->d16);
+    delete M;
+}
+
+// ----------------------------------------------------------------------------
+// options
+// ----------------------------------------------------------------------------
+
+extern "C" void amp_options_default(amp_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->u0 = 64;
+    o->tau_zs = 1e-4;
+    o->tau_zh = 1e-6;
+    o->eta_mode = AMP_ETA_DELAY;
+    o->d = 10;
+    o->C = 1.0;
+    o->ell = 5;
+    o->scaling = AMP_SCALE_POW2;
+    o->T_z = 12;
+    o->T_p = 12;
+    o->spmv32_diff = 1;
+    o->verify = 1;
+    o->max_replacements = 3;
+    o->rr_period = 0;
+    o->batch = 0;
+    o->delta_history = nullptr;
+    o->prec_history = nullptr;
+}
+
+extern "C" amp_status amp_options_preset(amp_options *o, int preset) {
+    if (!o) return fail(AMP_ERR_ARG, "amp_options_preset: null options");
+    amp_options_default(o);
+    switch (preset) {
+        case AMP_PRESET_PCG64: o->tau_zs = 0.0; o->tau_zh = 0.0; o->eta_mode = AMP_UR_FIXED64; break;
+        case AMP_PRESET_AMP64: break;
+        case AMP_PRESET_AMP16: o->u0 = 16; break;
+        case AMP_PRESET_AMP_UR: o->tau_zs = 0.0; o->tau_zh = 0.0; break;
+        default: return fail(AMP_ERR_ARG, "amp_options_preset: unknown preset");
+    }
+    return AMP_OK;
+}
+
+static amp_status check_options(const amp_options &o) {
+    if (!valid_prec(o.u0)) return fail(AMP_ERR_ARG, "options: u0 must be 64, 32 or 16");
+    if (o.eta_mode < 0 || o.eta_mode > 3) return fail(AMP_ERR_ARG, "options: bad eta_mode");
+    if (o.d < 1 || o.d > 100) return fail(AMP_ERR_ARG, "options: d must be in 1..100");
+    if (o.ell < 1 || o.ell > 100) return fail(AMP_ERR_ARG, "options: ell must be in 1..100");
+    if (o.scaling < 0 || o.scaling > 2) return fail(AMP_ERR_ARG, "options: bad scaling");
+    if (!(o.C >= 0.0) || !(o.tau_zs >= 0.0) || !(o.tau_zh >= 0.0))
+        return fail(AMP_ERR_ARG, "options: C, tau_zs, tau_zh must be >= 0");
+    if (o.T_z < -60 || o.T_z > 15 || o.T_p < -60 || o.T_p > 15)
+        return fail(AMP_ERR_ARG, "options: T_z, T_p must be in -60..15");
+    if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0)
+        return fail(AMP_ERR_ARG, "options: negative count");
+    return AMP_OK;
+}
+
+static void init_ctrl(Ctrl &c, const amp_options &o, amp_precond M, double tol, int maxit) {
+    std::memset(&c, 0, sizeof(c));
+    c.u0 = o.u0;
+    c.eta_mode = o.eta_mode;
+    c.d = o.d;
+    c.ell = o.ell;
+    c.scaling = o.scaling;
+    c.T_z = o.T_z;
+    c.T_p = o.T_p;
+    c.maxit = maxit;
+    c.rr_period = o.rr_period;
+    c.verify = o.verify;
+    c.max_repl = o.max_replacements;
+    c.chebyshev = (M && M->kind == AMP_PC_CHEBYSHEV) ? 1 : 0;
+    c.C = o.C;
+    c.tau_zs = o.tau_zs;
+    c.tau_zh = o.tau_zh;
+    c.tol = tol;
+    c.gain = M ? M->gain : 1.0;
+    c.extra16 = M ? M->extra16 : 0;
+    c.status = RUNNING;
+    c.uz = o.u0;
+    c.ur = 64;
+    c.r_store = 64;
+    c.p_store = o.u0;
+    c.k_z32 = c.k_z16 = c.k_r32 = -1;
+    c.delta_history = o.delta_history;
+    c.prec_history = o.prec_history;
+}
+
+// ----------------------------------------------------------------------------
+// solve
+// ----------------------------------------------------------------------------
+
+static amp_status enqueue_iterations(amp_matrix A, const Bufs &B, const amp_options &o, int count,
+                                     hipStream_t st) {
+    Ctrl *c = A->w.ctrl;
+    const Sell S = A->sell();
+    const int gs = grid_stream(A->np), gl = grid_slices(A->nslices);
+    for (int i = 0; i < count; ++i) {
+        k_precond<<<gs, NT, 0, st>>>(B, A->np, c);
+        k_pupdate<<<gs, NT, 0, st>>>(B, A->np, c);
+        k_spmv<<<gl, NT, 0, st>>>(S, B, o.spmv32_diff, c);
+        k_update<<<gs, NT, 0, st>>>(B, A->np, c);
+        if (o.rr_period > 0) k_true_res<<<gl, NT, 0, st>>>(S, B, 1, c);
+    }
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+
+static amp_status snapshot(amp_matrix A, int slot, hipStream_t st) {
+    Work &w = A->w;
+    AMP_HIP(hipMemcpyAsync(&w.snap[slot], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipEventRecord(w.ev[slot], st));
+    return AMP_OK;
+}
+
+static amp_status wait_snapshot(amp_matrix A, int slot) {
+    AMP_HIP(hipEventSynchronize(A->w.ev[slot]));
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
+                                    int maxit, const amp_options *opt, amp_result *res, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!A || !b || !x) return fail(AMP_ERR_ARG, "amp_pcg_solve: null argument");
+    if (!M) return fail(AMP_ERR_ARG, "amp_pcg_solve: null preconditioner");
+    if (M->A != A) return fail(AMP_ERR_ARG, "amp_pcg_solve: preconditioner was built for another matrix");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(AMP_ERR_ARG, "amp_pcg_solve: tol must be positive");
+    if (maxit < 0) return fail(AMP_ERR_ARG, "amp_pcg_solve: maxit must be >= 0");
+    amp_options o;
+    if (opt) o = *opt;
+    else amp_options_default(&o);
+    AMP_TRY(check_options(o));
+    hipStream_t st = as_stream(stream);
+    AMP_TRY(ensure_work(A, st));
+    Work &w = A->w;
+    const int64_t n = A->n;
+    const Sell S = A->sell();
+    const Bufs B = make_bufs(A, M);
+    const int gl = grid_slices(A->nslices);
+
+    Ctrl hc;
+    init_ctrl(hc, o, M, tol, maxit);
+    AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    AMP_HIP(hipMemcpyAsync(w.ctrl, &hc, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+    k_init<<<gl, NT, 0, st>>>(S, B, w.ctrl);
+    AMP_HIP(hipGetLastError());
+    AMP_TRY(snapshot(A, 0, st));
+    AMP_TRY(wait_snapshot(A, 0));
+    Ctrl cur = w.snap[0];
+
+    // Pipelined batches: batch j+1 is enqueued before batch j's status is read;
+    // kernels return at once when the status is no longer RUNNING.
+    int batch = o.batch > 0 ? o.batch : 8;
+    int pending = -1;              // snapshot slot of the batch in flight, if any
+    int last_iters = 0;
+    double last_delta = cur.delta;
+    for (;;) {
+        if (cur.status == NEED_VERIFY) {
+            if (pending >= 0) { AMP_TRY(wait_snapshot(A, pending)); pending = -1; }
+            k_true_res<<<gl, NT, 0, st>>>(S, B, 0, w.ctrl);
+            AMP_HIP(hipGetLastError());
+            AMP_TRY(snapshot(A, 0, st));
+            AMP_TRY(wait_snapshot(A, 0));
+            cur = w.snap[0];
+            continue;
+        }
+        if (cur.status != RUNNING) break;
+        const int sl = (pending >= 0) ? (pending ^ 1) : 0;
+        AMP_TRY(enqueue_iterations(A, B, o, batch, st));
+        AMP_TRY(snapshot(A, sl, st));
+        if (pending < 0) {         // fill the pipeline first
+            pending = sl;
+            continue;
+        }
+        AMP_TRY(wait_snapshot(A, pending));
+        cur = w.snap[pending];
+        pending = sl;
+        if (o.batch == 0 && cur.status == RUNNING && cur.iters > last_iters && cur.delta > 0.0 &&
+            last_delta > 0.0) {
+            // size the next batch from the observed rate of decrease
+            const double rate = std::pow(cur.delta / last_delta, 1.0 / (double)(cur.iters - last_iters));
+            int left = 256;
+            if (rate > 0.0 && rate < 1.0)
+                left = (int)std::ceil(std::log(hc.tol * cur.bnorm / cur.delta) / std::log(rate));
+            batch = std::max(4, std::min(256, left / 2 + 1));
+            last_iters = cur.iters;
+            last_delta = cur.delta;
+        }
+    }
+    if (pending >= 0) AMP_TRY(wait_snapshot(A, pending));
+    // the last snapshot may predate the final kernels of the pipeline; read the final state
+    AMP_HIP(hipMemcpyAsync(&w.snap[0], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipStreamSynchronize(st));
+    cur = w.snap[0];
+    AMP_HIP(hipMemcpyAsync(x, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // FP64 true residual of the returned x (writes nothing but the reduction)
+    double true_res = cur.true_res;
+    if (!(o.verify && cur.status == CONVERGED)) {
+        Ctrl tmp = cur;
+        tmp.status = NEED_VERIFY;
+        tmp.n_repl = tmp.max_repl;      // report only: never replaces
+        tmp.counter = 0;
+        AMP_HIP(hipMemcpyAsync(w.ctrl, &tmp, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+        // k_true_res overwrites r with b - A x; harmless after the solve
+        k_true_res<<<gl, NT, 0, st>>>(S, B, 0, w.ctrl);
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipMemcpyAsync(&w.snap[1], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        AMP_HIP(hipStreamSynchronize(st));
+        true_res = w.snap[1].true_res;
+    }
+    AMP_HIP(hipStreamSynchronize(st));
+
+    amp_status rs = AMP_OK;
+    if (cur.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
+    else if (cur.status == BREAKDOWN) rs = AMP_ERR_BREAKDOWN;
+    if (res) {
+        res->iters = cur.iters;
+        res->status = rs;
+        res->bnorm = cur.bnorm;
+        res->rel_res_updated = cur.bnorm > 0 ? cur.delta / cur.bnorm : 0.0;
+        res->rel_res_true = cur.bnorm > 0 ? true_res / cur.bnorm : 0.0;
+        res->k_z32 = cur.k_z32;
+        res->k_z16 = cur.k_z16;
+        res->k_r32 = cur.k_r32;
+        res->n_replacements = cur.n_repl;
+        res->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rs == AMP_ERR_NOT_CONVERGED) g_last_error = "amp_pcg_solve: not converged within maxit";
+    if (rs == AMP_ERR_BREAKDOWN) g_last_error = "amp_pcg_solve: breakdown (rho <= 0, gamma <= 0 or non-finite)";
+    return rs;
+}
+
+// ----------------------------------------------------------------------------
+// single-kernel entry points (tests, measurement)
+// ----------------------------------------------------------------------------
+
+extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,
+                               void *stream) {
+    if (!A) return fail(AMP_ERR_ARG, "amp_spmv: null matrix");
+    if ((u_r != 64 && u_r != 32) || !valid_prec(u_p)) return fail(AMP_ERR_ARG, "amp_spmv: bad precision");
+    hipStream_t st = as_stream(stream);
+    AMP_TRY(ensure_work(A, st));
+    Work &w = A->w;
+    Bufs B = make_bufs(A, nullptr);
+    const int64_t n = A->n;
+    if (p) AMP_HIP(hipMemcpyAsync(B.p[pslot(u_p)], p, n * (u_p / 8), hipMemcpyDeviceToDevice, st));
+    const Sell S = A->sell();
+    const int gl = grid_slices(A->nslices);
+    Ctrl *c = w.ctrl;
+#define AMP_SPMV_LAUNCH(UP, UR, DF) k_spmv_fixed<UP, UR, DF><<<gl, NT, 0, st>>>(S, B, gamma, c)
+    if (u_r == 64) {
+        if (u_p == 64) AMP_SPMV_LAUNCH(64, 64, false);
+        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 64, false);
+        else AMP_SPMV_LAUNCH(16, 64, false);
+    } else if (diff) {
+        if (u_p == 64) AMP_SPMV_LAUNCH(64, 32, true);
+        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 32, true);
+        else AMP_SPMV_LAUNCH(16, 32, true);
+    } else {
+        if (u_p == 64) AMP_SPMV_LAUNCH(64, 32, false);
+        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 32, false);
+        else AMP_SPMV_LAUNCH(16, 32, false);
+    }
+#undef AMP_SPMV_LAUNCH
+    AMP_HIP(hipGetLastError());
+    if (q) AMP_HIP(hipMemcpyAsync(q, B.q[pslot(u_r)], n * (u_r / 8), hipMemcpyDeviceToDevice, st));
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const void *r, double omega, void *z,
+                                        double *rho, void *stream) {
+    if (!M || !r || !z) return fail(AMP_ERR_ARG, "amp_precond_apply: null argument");
+    if ((u_r != 64 && u_r != 32) || !valid_prec(u_z)) return fail(AMP_ERR_ARG, "amp_precond_apply: bad precision");
+    if (!(omega != 0.0) || !std::isfinite(omega)) return fail(AMP_ERR_ARG, "amp_precond_apply: omega must be finite, nonzero");
+    amp_matrix A = M->A;
+    hipStream_t st = as_stream(stream);
+    AMP_TRY(ensure_work(A, st));
+    Work &w = A->w;
+    Bufs B = make_bufs(A, M);
+    const int64_t n = A->n;
+    AMP_HIP(hipMemcpyAsync(B.r[pslot(u_r)], r, n * (u_r / 8), hipMemcpyDeviceToDevice, st));
+    AMP_HIP(hipMemsetAsync(&w.ctrl->counter, 0, sizeof(unsigned int), st));
+    const double oe = std::ldexp(omega, -(u_z == 16 ? M->extra16 : 0));
+    const int gs = grid_stream(A->np);
+#define AMP_PC_LAUNCH(UR, UZ) k_precond_fixed<UR, UZ><<<gs, NT, 0, st>>>(B, A->np, oe, rho, w.ctrl)
+    if (u_r == 64) {
+        if (u_z == 64) AMP_PC_LAUNCH(64, 64);
+        else if (u_z == 32) AMP_PC_LAUNCH(64, 32);
+        else AMP_PC_LAUNCH(64, 16);
+    } else {
+        if (u_z == 64) AMP_PC_LAUNCH(32, 64);
+        else if (u_z == 32) AMP_PC_LAUNCH(32, 32);
+        else AMP_PC_LAUNCH(32, 16);
+    }
+#undef AMP_PC_LAUNCH
+    AMP_HIP(hipGetLastError());
+    AMP_HIP(hipMemcpyAsync(z, B.z[pslot(u_z)], n * (u_z / 8), hipMemcpyDeviceToDevice, st));
+    return AMP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// host-only helpers
+// ----------------------------------------------------------------------------
+
+extern "C" amp_status amp_selector_replay(const double *delta, int len, double bnorm, double tol,
+                                          const amp_options *opt, int *k_z32, int *k_z16, int *k_r32) {
+    if (!delta || len < 0 || !(bnorm > 0.0) || !(tol > 0.0))
+        return fail(AMP_ERR_ARG, "amp_selector_replay: bad argument");
+    amp_options o;
+    if (opt) o = *opt;
+    else amp_options_default(&o);
+    AMP_TRY(check_options(o));
+    o.delta_history = nullptr;
+    o.prec_history = nullptr;
+    Ctrl c;
+    init_ctrl(c, o, nullptr, tol, len);
+    c.bnorm = bnorm;
+    c.tol_b = tol * bnorm;
+    for (int k = 0; k < len; ++k) {
+        c.ring[k % kRing] = delta[k];
+        c.delta = delta[k];
+        c.maxr = 1.0;
+        prepare_iteration(c, k);
+    }
+    if (k_z32) *k_z32 = c.k_z32;
+    if (k_z16) *k_z16 = c.k_z16;
+    if (k_r32) *k_r32 = c.k_r32;
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_paper_kernel_bytes(int u_z, int u_r, double out[4]) {
+    if (!out || !valid_prec(u_z) || (u_r != 64 && u_r != 32))
+        return fail(AMP_ERR_ARG, "amp_paper_kernel_bytes: bad argument");
+    const double bz = u_z / 8, br = u_r / 8;
+    out[0] = br + bz + bz;            // zamx: read r, read M (stored in u_z), write z
+    out[1] = bz + br;                 // innerProd: read z, r
+    out[2] = 3 * bz;                  // axpy: read z, p, write p
+    out[3] = 3 * br + 16 + bz;        // updatePCG: read r, q, x, p; write r, x
+    return AMP_OK;
+}
+
+extern "C" int amp_version(void) { return 100; }
+
+extern "C" const char *amp_status_string(amp_status s) {
+    switch (s) {
+        case AMP_OK: return "AMP_OK";
+        case AMP_ERR_ARG: return "AMP_ERR_ARG";
+        case AMP_ERR_NOT_CONVERGED: return "AMP_ERR_NOT_CONVERGED";
+        case AMP_ERR_BREAKDOWN: return "AMP_ERR_BREAKDOWN";
+        case AMP_ERR_HIP: return "AMP_ERR_HIP";
+        case AMP_ERR_OOM: return "AMP_ERR_OOM";
+    }
+    return "AMP_ERR_UNKNOWN";
+}
+
+extern "C" const char *amp_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,169 @@
+"""torch-facing wrappers of the AMP-PCG C ABI.
+
+Tensors are plain device memory here: every arithmetic step of the solve
+runs inside libamppcg.so.  All calls use torch's current HIP stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import sys
+
+import torch
+
+from . import binding as B
+
+_TORCH = {64: torch.float64, 32: torch.float32, 16: torch.float16}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, n=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+
+
+class Matrix:
+    """Solver-side matrix (sliced ELL, FP64 and FP32 value planes)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor):
+        L = B.load()
+        n = row_ptr.numel() - 1
+        _need(row_ptr, torch.int32, name="row_ptr")
+        _need(col_idx, torch.int32, name="col_idx")
+        _need(val, torch.float64, col_idx.numel(), name="val")
+        csr = B.Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
+        h = ctypes.c_void_p()
+        B.check(L.amp_matrix_create(ctypes.byref(csr), _stream(), ctypes.byref(h)), "amp_matrix_create")
+        self._h = h
+        self.n = n
+        self.nnz = col_idx.numel()
+
+    @classmethod
+    def from_csr(cls, csr, device="cuda"):
+        """From a workloads.CSR (host numpy arrays)."""
+        rp = torch.from_numpy(csr.row_ptr).to(device)
+        ci = torch.from_numpy(csr.col_idx).to(device)
+        v = torch.from_numpy(csr.val).to(device)
+        return cls(rp, ci, v)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        vals = [ctypes.c_int64() for _ in range(4)]
+        B.check(B.load().amp_matrix_info(self._h, *[ctypes.byref(v) for v in vals]), "amp_matrix_info")
+        return dict(n=vals[0].value, nnz=vals[1].value, slots=vals[2].value, bytes=vals[3].value)
+
+    def spmv(self, p: torch.Tensor, u_r: int = 64, diff: bool = True):
+        """q = A p with the solver's kernel; p's dtype selects its storage
+        precision, u_r the value plane / arithmetic.  Returns (q, gamma)."""
+        u_p = {torch.float64: 64, torch.float32: 32, torch.float16: 16}[p.dtype]
+        _need(p, p.dtype, self.n, "p")
+        q = torch.empty(self.n, dtype=_TORCH[u_r], device=p.device)
+        g = torch.zeros(1, dtype=torch.float64, device=p.device)
+        B.check(B.load().amp_spmv(self._h, u_r, u_p, 1 if diff else 0, _ptr(p), _ptr(q), _ptr(g), _stream()),
+                "amp_spmv")
+        return q, g
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and B._lib is not None and not sys.is_finalizing():
+            B._lib.amp_matrix_destroy(h)
+            self._h = None
+
+
+class Preconditioner:
+    KINDS = {"identity": B.PC_IDENTITY, "jacobi": B.PC_JACOBI, "chebyshev": B.PC_CHEBYSHEV}
+
+    def __init__(self, A: Matrix, kind: str = "jacobi", degree: int = 4, lam_lo: float = 0.0,
+                 lam_hi: float = 0.0):
+        h = ctypes.c_void_p()
+        B.check(B.load().amp_precond_create(A.handle, self.KINDS[kind], int(degree), float(lam_lo),
+                                            float(lam_hi), _stream(), ctypes.byref(h)),
+                "amp_precond_create")
+        self._h = h
+        self.A = A
+        self.kind = kind
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, r: torch.Tensor, u_z: int, omega: float = 1.0):
+        """z = M^{-1} fl_{u_z}(fl_{u_r}(omega r)); r's dtype gives u_r.  Returns (z, rho)."""
+        u_r = {torch.float64: 64, torch.float32: 32}[r.dtype]
+        _need(r, r.dtype, self.A.n, "r")
+        z = torch.empty(self.A.n, dtype=_TORCH[u_z], device=r.device)
+        rho = torch.zeros(1, dtype=torch.float64, device=r.device)
+        B.check(B.load().amp_precond_apply(self._h, u_r, u_z, _ptr(r), float(omega), _ptr(z), _ptr(rho),
+                                           _stream()), "amp_precond_apply")
+        return z, rho
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and B._lib is not None and not sys.is_finalizing():
+            B._lib.amp_precond_destroy(h)
+            self._h = None
+
+
+def solve(A: Matrix, M: Preconditioner, b: torch.Tensor, x0: torch.Tensor | None = None, tol: float = 1e-10,
+          maxit: int = 5000, preset: str = "amp64", history: bool = False, raise_on_error: bool = False,
+          **opts):
+    """Solve A x = b with AMP-PCG (Alg. 3).  Returns (x, info)."""
+    L = B.load()
+    _need(b, torch.float64, A.n, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.detach().clone()
+    _need(x, torch.float64, A.n, "x0")
+    o = B.make_options(preset, **opts)
+    dh = ph = None
+    if history:
+        dh = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device)
+        ph = torch.full((max(maxit, 1),), -1, dtype=torch.int32, device=b.device)
+        o.delta_history = dh.data_ptr()
+        o.prec_history = ph.data_ptr()
+    res = B.Result()
+    st = L.amp_pcg_solve(A.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(o),
+                         ctypes.byref(res), _stream())
+    if st in (B.AMP_ERR_ARG, B.AMP_ERR_HIP, B.AMP_ERR_OOM) or (raise_on_error and st != B.AMP_OK):
+        B.check(st, "amp_pcg_solve")
+    info = dict(status=st, iters=res.iters, relres=res.rel_res_updated, relres_true=res.rel_res_true,
+                bnorm=res.bnorm, k_z32=res.k_z32, k_z16=res.k_z16, k_r32=res.k_r32,
+                replacements=res.n_replacements, t_solve_ms=res.t_solve_ms)
+    if history:
+        it = res.iters
+        info["delta"] = dh[: it + 1].cpu().numpy()
+        ph_h = ph[:it].cpu().numpy()
+        info["uz"] = (ph_h & 0xFF).tolist()
+        info["ur"] = (ph_h >> 8).tolist()
+    return x, info
+
+
+def selector_replay(delta, bnorm: float, tol: float, preset: str = "amp64", **opts):
+    """Host-only replay of the device controller's latched selector."""
+    L = B.load()
+    arr = (ctypes.c_double * len(delta))(*[float(d) for d in delta])
+    o = B.make_options(preset, **opts)
+    out = [ctypes.c_int(), ctypes.c_int(), ctypes.c_int()]
+    B.check(L.amp_selector_replay(arr, len(delta), float(bnorm), float(tol), ctypes.byref(o),
+                                  *[ctypes.byref(v) for v in out]), "amp_selector_replay")
+    return tuple(v.value for v in out)
+
+
+def paper_kernel_bytes(u_z: int, u_r: int):
+    out = (ctypes.c_double * 4)()
+    B.check(B.load().amp_paper_kernel_bytes(u_z, u_r, out), "amp_paper_kernel_bytes")
+    return list(out)

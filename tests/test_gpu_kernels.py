@@ -1,0 +1,113 @@
+"""Kernel-level parity of the HIP path against the oracle (GPU).
+
+* SpMV on integer-valued matrices and small-integer vectors is exact in
+  every precision, so the GPU result must equal the CPU product bitwise.
+* SpMV on real data agrees with the FP64 oracle / the FP32 model.
+* The scaled Jacobi application z = M^{-1} fl(omega r) follows the same
+  rounding sequence as the precision model, element by element.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import amp_model as am
+from oracle import cpcg
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TORCH = {64: torch.float64, 32: torch.float32, 16: torch.float16}
+NP = {64: np.float64, 32: np.float32, 16: np.float16}
+
+
+@pytest.fixture(scope="module")
+def amp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2505_04155_amd as amp_mod
+    from paper_2505_04155_amd import binding
+    binding.load(build_if_missing=False)
+    return amp_mod
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("m", [37, 64])
+@pytest.mark.parametrize("u_r,diff", [(64, False), (32, True), (32, False)])
+@pytest.mark.parametrize("u_p", [64, 32, 16])
+def test_spmv_integer_exact(amp, m, u_r, diff, u_p):
+    _say(f"spmv exact m={m} u_r={u_r} diff={diff} u_p={u_p}")
+    A = P.stencil_poisson2d(m)                  # ragged n = 1369 for m = 37
+    p = np.random.default_rng([300, m]).integers(-8, 9, A.n).astype(np.float64)
+    ref = A.to_scipy() @ p
+    M = amp.Matrix.from_csr(A)
+    q, g = M.spmv(torch.tensor(p, dtype=TORCH[u_p], device="cuda"), u_r=u_r, diff=diff)
+    torch.cuda.synchronize()
+    qh = q.cpu().numpy().astype(np.float64)
+    assert np.array_equal(qh, ref)
+    assert g.item() == float(ref @ p)
+
+
+def test_spmv_fp64_matches_oracle(amp):
+    _say("spmv fp64 vs oracle, blocky 24^3")
+    A, _, _ = P.blocky_diffusion3d_system(24, 4)
+    p = np.random.default_rng([301, 0]).standard_normal(A.n)
+    ref = cpcg.spmv(A, p)
+    M = amp.Matrix.from_csr(A)
+    q, g = M.spmv(torch.tensor(p, device="cuda"), u_r=64)
+    qh = q.cpu().numpy()
+    assert np.max(np.abs(qh - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert g.item() == pytest.approx(float(ref @ p), rel=1e-12)
+
+
+@pytest.mark.parametrize("u_p", [32, 16])
+def test_spmv_fp32_difference_form_matches_model(amp, u_p):
+    _say(f"spmv fp32 diff vs model u_p={u_p}")
+    A, _, _ = P.blocky_diffusion3d_system(24, 4)
+    S = A.to_scipy()
+    p = np.random.default_rng([302, u_p]).standard_normal(A.n).astype(NP[u_p])
+    ref = am._diff_spmv32(S)(p).astype(np.float64)
+    M = amp.Matrix.from_csr(A)
+    q, _ = M.spmv(torch.tensor(p, device="cuda"), u_r=32, diff=True)
+    qh = q.cpu().numpy().astype(np.float64)
+    exact = S @ p.astype(np.float64)
+    scale = np.abs(S) @ np.abs(p.astype(np.float64))
+    # same operation order as the model: agreement to a couple of FP32 ulps
+    assert np.all(np.abs(qh - ref) <= 4 * 2.0 ** -24 * scale)
+    # and the product is accurate to FP32 rounding of its terms
+    assert np.all(np.abs(qh - exact) <= 16 * 2.0 ** -24 * scale)
+
+
+@pytest.mark.parametrize("u_r", [64, 32])
+@pytest.mark.parametrize("u_z", [64, 32, 16])
+def test_jacobi_apply_matches_model(amp, u_r, u_z):
+    _say(f"jacobi apply u_r={u_r} u_z={u_z}")
+    A, _, _ = P.blocky_diffusion3d_system(16, 4)
+    S = A.to_scipy()
+    r = (np.random.default_rng([303, u_r]).standard_normal(A.n) * 1e-3).astype(NP[u_r])
+    J = am.Jacobi(S)
+    omega = 2.0 ** 9
+    omega_eff = omega * 2.0 ** (-J.log2_extra[u_z])
+    y = am.fl(am.fl(r.astype(NP[u_r]) * NP[u_r](omega_eff), u_r), u_z)
+    zref = J.apply(y, u_z)
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "jacobi")
+    z, rho = pc.apply(torch.tensor(r, device="cuda"), u_z=u_z, omega=omega)
+    zh = z.cpu().numpy()
+    assert np.array_equal(zh, zref)
+    rho_ref = float(r.astype(np.float64) @ zref.astype(np.float64))
+    assert rho.item() == pytest.approx(rho_ref, rel=1e-13)
+
+
+def test_matrix_handle_rejects_bad_input(amp):
+    from paper_2505_04155_amd import binding as B
+    A = P.dense_to_csr(np.diag([1.0, -2.0, 3.0]))
+    with pytest.raises(B.AmpError) as e:
+        amp.Matrix.from_csr(A)
+    assert e.value.status == B.AMP_ERR_ARG
+    bad = P.CSR(3, np.array([0, 1, 2, 3], np.int32), np.array([0, 5, 2], np.int32), np.ones(3))
+    with pytest.raises(B.AmpError):
+        amp.Matrix.from_csr(bad)

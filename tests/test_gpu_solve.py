@@ -1,0 +1,227 @@
+"""Solve-level parity of the HIP path (GPU) against the oracle.
+
+* PCG(FP64) on the GPU reproduces the C oracle's Alg. 1 iteration count and
+  solution; power-of-two dynamic scaling leaves it bitwise unchanged
+  (Thm. dspcg in finite precision).
+* AMP-PCG on the GPU follows the precision model of Alg. 3: iteration
+  counts and switch points agree, the GPU's own residual history replayed
+  through the oracle's selector reproduces its switch points exactly, and
+  the FP64 true residual reaches the tolerance.
+* Edge cases: zero right-hand side, exact initial guess, maxit, a
+  non-positive-definite matrix, ragged sizes, determinism.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import amp_model as am
+from oracle import cpcg
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2505_04155_amd as amp_mod
+    from paper_2505_04155_amd import binding
+    binding.load(build_if_missing=False)
+    return amp_mod
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gpu_solve(amp, A, b, preset, tol=1e-10, maxit=5000, x0=None, kind="jacobi", **kw):
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, kind)
+    bt = torch.tensor(b, device="cuda")
+    x0t = None if x0 is None else torch.tensor(x0, device="cuda")
+    x, info = amp.solve(M, pc, bt, x0=x0t, tol=tol, maxit=maxit, preset=preset, history=True, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------------------ PCG(FP64)
+
+@pytest.mark.parametrize("case", ["poisson64", "poisson37", "blocky24"])
+def test_pcg64_matches_c_oracle(amp, case):
+    _say(f"pcg64 vs oracle {case}")
+    if case.startswith("poisson"):
+        A, b, _ = P.poisson2d_system(int(case[7:]))
+    else:
+        A, b, _ = P.blocky_diffusion3d_system(24, 4)
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000, history=True)
+    x, info = _gpu_solve(amp, A, b, "pcg64")
+    assert info["status"] == 0
+    assert info["iters"] == io["iters"]
+    assert _rel(x, xo) <= 1e-11
+    assert np.allclose(info["delta"], io["delta"], rtol=1e-8, atol=0)
+    assert info["relres_true"] <= 1e-10
+    assert info["k_z32"] == -1 and info["k_r32"] == -1
+
+
+@pytest.mark.parametrize("u", [64, 32])
+def test_pow2_scaling_bitwise_neutral_on_gpu(amp, u):
+    _say(f"pow2 vs none u={u}")
+    A, b, _ = P.blocky_diffusion3d_system(16, 4, decades=2.0)
+    eta = "fixed64" if u == 64 else "fixed32"
+    x1, i1 = _gpu_solve(amp, A, b, "pcg64", tol=1e-6, u0=u, eta=eta, verify=0)
+    x2, i2 = _gpu_solve(amp, A, b, "pcg64", tol=1e-6, u0=u, eta=eta, verify=0, scaling="none")
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(x1, x2)
+    assert np.array_equal(i1["delta"], i2["delta"])
+
+
+def test_paper_scaling_matches_oracle(amp):
+    _say("paper scaling")
+    A, b, _ = P.poisson2d_system(48)
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000)
+    x, info = _gpu_solve(amp, A, b, "pcg64", scaling="paper")
+    assert info["iters"] == io["iters"]
+    assert _rel(x, xo) <= 1e-11
+
+
+# ------------------------------------------------------------------ AMP-PCG vs the model
+
+CASES = {
+    "poisson64": lambda: P.poisson2d_system(64)[:2],
+    "poisson37": lambda: P.poisson2d_system(37)[:2],
+    "blocky24": lambda: P.blocky_diffusion3d_system(24, 4)[:2],
+    "blocky32": lambda: P.blocky_diffusion3d_system(32, 8)[:2],
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("preset,kw", [("amp64", {}), ("amp16", {}), ("amp_ur", {}),
+                                       ("amp64", {"eta": "linear"}), ("amp64", {"spmv32": "plain"})])
+def test_amp_matches_model(amp, case, preset, kw):
+    _say(f"amp vs model {case} {preset} {kw}")
+    A, b = CASES[case]()
+    S = A.to_scipy()
+    ref = am.amp_pcg(S, b, tol=1e-10, maxit=5000, opt=am.options(preset, **kw))
+    x, info = _gpu_solve(amp, A, b, preset, **kw)
+    assert info["status"] == 0 and ref.status == 0
+    # the GPU's own history through the oracle's selector reproduces its switch points
+    kz32, kz16, kr = am.replay_switches(list(info["delta"][:info["iters"]]), info["bnorm"], 1e-10,
+                                        am.options(preset, **kw))
+    assert (kz32, kz16, kr) == (info["k_z32"], info["k_z16"], info["k_r32"])
+    # and they agree with the model's to within an iteration or two
+    for key, val in (("k_z32", ref.k_z32), ("k_z16", ref.k_z16), ("k_r32", ref.k_r32)):
+        assert (info[key] < 0) == (val < 0), key
+        assert abs(info[key] - val) <= 2, key
+    assert abs(info["iters"] - ref.iters) <= max(2, math.ceil(0.02 * ref.iters))
+    assert info["relres_true"] <= 1e-10
+    assert _rel(x, ref.x) <= 1e-7
+    # per-iteration precisions recorded by the device are latched
+    assert all(a >= b for a, b in zip(info["uz"], info["uz"][1:]))
+    assert all(a >= b for a, b in zip(info["ur"], info["ur"][1:]))
+
+
+@pytest.mark.parametrize("case", ["poisson64", "blocky32"])
+def test_amp64_vs_fp64_oracle(amp, case):
+    _say(f"amp64 vs fp64 oracle {case}")
+    A, b = CASES[case]()
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000)
+    x, info = _gpu_solve(amp, A, b, "amp64")
+    assert info["status"] == 0
+    assert info["iters"] <= math.ceil(1.05 * io["iters"])
+    assert info["relres_true"] <= 1e-10
+    # both are tol-accurate solutions: their difference is bounded by the
+    # condition number times the residuals (estimated from the oracle's CG)
+    assert _rel(x, xo) <= 1e-5
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_zero_rhs_and_exact_start(amp):
+    _say("edge: zero rhs, exact start")
+    A, b, xs = P.poisson2d_system(20)
+    x, info = _gpu_solve(amp, A, np.zeros(A.n), "amp64")
+    assert info["status"] == 0 and info["iters"] == 0 and np.all(x == 0)
+    x, info = _gpu_solve(amp, A, b, "amp64", x0=xs)
+    assert info["status"] == 0 and info["iters"] == 0
+
+
+def test_maxit_returns_last_iterate(amp):
+    _say("edge: maxit")
+    from paper_2505_04155_amd import binding as B
+    A, b, _ = P.poisson2d_system(32)
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=7)
+    x, info = _gpu_solve(amp, A, b, "pcg64", maxit=7)
+    assert info["status"] == B.AMP_ERR_NOT_CONVERGED and info["iters"] == 7
+    assert _rel(x, xo) <= 1e-12
+
+
+def test_breakdown_on_indefinite_matrix(amp):
+    _say("edge: breakdown")
+    from paper_2505_04155_amd import binding as B
+    # positive diagonal but indefinite: gamma <= 0 at the first step
+    D = np.array([[1.0, 3.0, 0.0], [3.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    A = P.dense_to_csr(D)
+    x, info = _gpu_solve(amp, A, np.array([1.0, -1.0, 0.0]), "pcg64", kind="identity")
+    assert info["status"] == B.AMP_ERR_BREAKDOWN
+    assert np.all(np.isfinite(x))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 1023, 1025])
+def test_ragged_sizes(amp, n):
+    _say(f"edge: ragged n={n}")
+    A = P.stencil_poisson2d(1) if n == 1 else P.fv_diffusion(
+        np.exp(np.random.default_rng([310, n]).standard_normal((1, n))))
+    b = np.random.default_rng([311, n]).standard_normal(A.n)
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000)
+    for preset in ("pcg64", "amp64", "amp16"):
+        x, info = _gpu_solve(amp, A, b, preset)
+        assert info["status"] == 0, preset
+        assert info["relres_true"] <= 1e-10, preset
+        assert _rel(x, xo) <= 1e-6, preset
+
+
+def test_deterministic(amp):
+    _say("determinism")
+    A, b, _ = P.blocky_diffusion3d_system(16, 4)
+    x1, i1 = _gpu_solve(amp, A, b, "amp16")
+    x2, i2 = _gpu_solve(amp, A, b, "amp16")
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(x1, x2)
+
+
+def test_periodic_replacement_matches_model(amp):
+    _say("periodic replacement")
+    A, b = CASES["blocky24"]()
+    ref = am.amp_pcg(A.to_scipy(), b, tol=1e-10, maxit=5000, opt=am.options("amp16", rr_period=25))
+    x, info = _gpu_solve(amp, A, b, "amp16", rr_period=25)
+    assert info["status"] == 0
+    assert info["replacements"] >= info["iters"] // 25
+    assert abs(info["iters"] - ref.iters) <= max(2, math.ceil(0.02 * ref.iters))
+    assert info["relres_true"] <= 1e-10
+
+
+# ------------------------------------------------------------------ full-size workload
+
+def test_blocky128_full_size(amp):
+    _say("full size: 3-D 7-point FV 128^3, contrast 1e4")
+    A, b, _ = P.blocky_diffusion3d_system()
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=20000)
+    x, info = _gpu_solve(amp, A, b, "amp64", maxit=20000)
+    _say(f"  oracle iters {io['iters']}, gpu iters {info['iters']}, switches "
+         f"{info['k_z32']} {info['k_z16']} {info['k_r32']}, rel err {_rel(x, xo):.3e}")
+    assert info["status"] == 0
+    assert info["iters"] <= math.ceil(1.05 * io["iters"])
+    # the FP64 true residual, recomputed by the oracle
+    r = b - cpcg.spmv(A, x)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+    x64, i64 = _gpu_solve(amp, A, b, "pcg64", maxit=20000)
+    assert i64["iters"] == io["iters"]
+    assert _rel(x64, xo) <= 1e-9
