@@ -33,11 +33,32 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_algorithmic_bytes(n, nnz, nslices, b_val, b_p, b_q):
-    """Bytes one product q = A p must move: values and column indices once,
-    the slice pointers, p read once (the gather is counted once), q written
-    once.  Slice padding is overhead, not counted."""
-    return nnz * (b_val + 4) + n * (b_p + b_q) + (nslices + 1) * 8
+def spmv_algorithmic_bytes(n, nnz, nslices, b_val, b_z, b_q):
+    """Bytes one fused product step p = z + beta p_old, q = A p must move:
+    values and column indices once, the slice pointers, z and p_old read
+    once (the gathers are counted once), p and q written once.  Slice padding
+    is overhead, not counted."""
+    return nnz * (b_val + 4) + n * (3 * b_z + b_q) + (nslices + 1) * 8
+
+
+def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, nslices):
+    """Average duration (ms) of the library's product-step kernel over reps
+    back-to-back launches, and its algorithmic bytes per launch."""
+    import ctypes
+    L = binding.load()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    for _ in range(3):
+        binding.check(L.amp_spmv_step(M.handle, u_z, u_r, diff, 0.5, sp), "amp_spmv_step")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        L.amp_spmv_step(M.handle, u_z, u_r, diff, 0.5, sp)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bv = 8 if u_r == 64 else 4
+    return ms, spmv_algorithmic_bytes(n, nnz, nslices, bv, u_z // 8, u_r // 8)
 
 
 def main():
@@ -49,6 +70,8 @@ def main():
     ap.add_argument("--preset", default="amp64")
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["solve", "spmv"], default="solve",
+                    help="spmv: only the product kernels and a reference copy (for counter runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -82,6 +105,10 @@ def main():
             raise RuntimeError(f"{preset} solve failed: {info}")
         return x, info
 
+    if args.mode == "spmv":
+        spmv_only(args, amp, binding, M, pc, bt, torch)
+        return
+
     results = {}
     for preset in (args.preset, "pcg64"):
         for w in range(args.warmup):
@@ -103,26 +130,15 @@ def main():
     amp_ms, amp_info = results[args.preset]
     fp64_ms, fp64_info = results["pcg64"]
 
-    # Dominant kernel: the SpMV of the reduced-precision phase (FP32 values in
-    # difference form, p in FP16, q in FP32), timed with HIP events on the
-    # stream the library launches on (torch's current stream).
-    n, nnz, slots = info_m["n"], info_m["nnz"], info_m["slots"]
+    # Dominant kernel: the fused product step of the reduced-precision phase
+    # (p = z + beta p_old in FP16, q = A p with FP32 values in difference
+    # form, FP32 q), timed with HIP events on the stream the library launches
+    # on (torch's current stream) over spmv_reps back-to-back launches.
+    n, nnz = info_m["n"], info_m["nnz"]
     nslices = ((n + 1023) // 1024 * 1024) // 64      # rows padded to 1024, 64 rows per slice
-    L = binding.load()
-    stream = torch.cuda.current_stream()
-    sp = __import__("ctypes").c_void_p(stream.cuda_stream)
-    for _ in range(5):
-        binding.check(L.amp_spmv(M.handle, 32, 16, 1, None, None, None, sp), "amp_spmv")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.spmv_reps):
-        L.amp_spmv(M.handle, 32, 16, 1, None, None, None, sp)
-    e1.record(stream)
-    e1.synchronize()
-    spmv_ms = e0.elapsed_time(e1) / args.spmv_reps
-    spmv_bytes = spmv_algorithmic_bytes(n, nnz, nslices, 4, 2, 4)
+    spmv_ms, spmv_bytes = time_spmv_step(binding, M, torch, 16, 32, 1, args.spmv_reps, n, nnz, nslices)
     spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
-    log(f"bench: spmv fp32-diff/fp16: {spmv_ms * 1e3:.2f} us, {spmv_gbs:.0f} GB/s algorithmic")
+    log(f"bench: fused product step (p fp16, A fp32 diff): {spmv_ms * 1e3:.2f} us, {spmv_gbs:.0f} GB/s algorithmic")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -166,7 +182,7 @@ def main():
         "rel_res_true": amp_info["relres_true"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmv_fixed<16,32,diff> (q = A p: FP32 values, FP16 p, FP32 q)",
+            "kernel": "k_spmv_fixed<16,32,true>: p = z + beta p_old (FP16), q = A p (FP32 values, difference form)",
             "achieved": round(spmv_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -177,6 +193,36 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def spmv_only(args, amp, binding, M, pc, bt, torch):
+    """Product-step kernels alone, each launched spmv_reps times, plus a device
+    copy of a known size: the launches a counter run attributes bytes to."""
+    amp.solve(M, pc, bt, tol=1e-10, maxit=20000, preset=args.preset)   # fills the work buffers
+    info_m = M.info()
+    n, nnz = info_m["n"], info_m["nnz"]
+    nslices = ((n + 1023) // 1024 * 1024) // 64
+    out = {"mode": "spmv", "n": n, "nnz": nnz, "slots": info_m["slots"], "kernels": {}}
+    for (u_z, u_r, diff) in ((64, 64, 0), (16, 32, 1), (32, 32, 1)):
+        ms, nbytes = time_spmv_step(binding, M, torch, u_z, u_r, diff, args.spmv_reps, n, nnz, nslices)
+        us = ms * 1e3
+        out["kernels"][f"k_spmv_fixed<{u_z},{u_r},{'true' if diff else 'false'}>"] = {
+            "avg_us": round(us, 3), "algorithmic_bytes": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
+        log(f"product step u_z={u_z} u_r={u_r} diff={diff}: {us:.2f} us, {nbytes / us / 1e3:.0f} GB/s")
+    stream = torch.cuda.current_stream()
+    src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=bt.device)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.spmv_reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / args.spmv_reps
+    out["copy_256MiB"] = {"avg_us": round(us, 3), "bytes": 2 * src.numel() * 4,
+                          "GB/s": round(2 * src.numel() * 4 / us / 1e3, 1)}
+    log(f"copy 256 MiB: {us:.2f} us, {2 * src.numel() * 4 / us / 1e3:.0f} GB/s")
     print(json.dumps(out), flush=True)
 
 

@@ -189,6 +189,18 @@ amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, voi
                     void *stream);
 
 /*
+ * One iteration's fused product step on the handle's own work buffers,
+ * exactly as the solve's product kernel runs it with the precisions fixed:
+ * p_new = fl_{u_z}(z + beta p_old) (z, p_old: the vectors the last solve or
+ * product left in the handle), q = A p_new in u_r (FP32 in row-sum/
+ * difference form when diff != 0), gamma partial sums.  Meant for timing
+ * the solver's dominant kernel in isolation: one kernel launch, enqueued on
+ * stream, not synchronised.  Errors: AMP_ERR_ARG for a null handle or a
+ * precision outside {64, 32, 16} x {64, 32}.
+ */
+amp_status amp_spmv_step(amp_matrix A, int u_z, int u_r, int diff, double beta, void *stream);
+
+/*
  * One scaled preconditioner application z = M^{-1} fl_{u_z}(fl_{u_r}(omega r)),
  * Alg. 3 steps y = r/delta, z = M^{-1} y, with r stored in u_r and z in u_z.
  * omega is the total scale (for FP16 Jacobi the static storage scale of

@@ -23,7 +23,8 @@ One iteration k, in the paper's order (Alg. 3):
 3. y = omega_k r computed in u_r, stored in u_z.
 4. z = M^{-1} y computed and stored in u_z.
 5. rho = r^T z (FP64);  beta_{k-1} = rho_k / rho_{k-1} (k > 0).
-6. p = z + beta p computed and stored in u_z.
+6. p = z + beta p computed and stored in u_z (at a u_z switch p_{k-1} is
+   first rounded to the new u_z).
 7. q = A p computed and stored in u_r (A's values rounded to u_r,
    accumulation in u_r).
 8. gamma = q^T p, alpha = rho/gamma (FP64).
@@ -434,11 +435,13 @@ def amp_pcg(A, b, x0=None, tol=1e-10, maxit=5000, M=None, opt: AmpOptions | None
         # 5: rho, beta
         rho = float(np.dot(r.astype(np.float64), z.astype(np.float64)))
         beta = rho / rho_prev if k > 0 else 0.0
-        # 6: p = z + beta p in u_z
+        # 6: p = z + beta p in u_z (at a u_z switch p_{k-1} is first rounded to u_z)
         cz = NP[compute_type(uz)]
         if p is None:
             p = fl(z, uz)
         else:
+            if p.dtype != NP[uz]:
+                p = fl(p, uz)
             p = fl(z.astype(cz) + cz(beta) * p.astype(cz), uz)
         maxp_prev = float(np.max(np.abs(p.astype(np.float64))))
         e_prev, maxr_prev = e_k, maxr

@@ -22,7 +22,7 @@ PRESETS = {"pcg64": 0, "amp64": 1, "amp16": 2, "amp_ur": 3}
 EXPORTED = [
     "amp_version", "amp_status_string", "amp_last_error", "amp_options_default",
     "amp_options_preset", "amp_matrix_create", "amp_matrix_destroy", "amp_matrix_info",
-    "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv",
+    "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv", "amp_spmv_step",
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
 ]
 
@@ -94,6 +94,7 @@ def load(build_if_missing: bool = True):
         L.amp_pcg_solve.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(Result), vp]
         L.amp_spmv.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.amp_spmv_step.argtypes = [vp, i32, i32, i32, dbl, vp]
         L.amp_precond_apply.argtypes = [vp, i32, i32, vp, dbl, vp, vp, vp]
         L.amp_selector_replay.argtypes = [ctypes.POINTER(dbl), i32, dbl, dbl, ctypes.POINTER(Options),
                                           ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]

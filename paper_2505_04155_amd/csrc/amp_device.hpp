@@ -1,5 +1,5 @@
 // Device building blocks: precision types, sliced-ELL matrix view, block
-// reductions with a deterministic last-work-group finish.
+// reductions, XCD-aware work distribution.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,8 +15,9 @@ constexpr int NT = 256;      // threads per work-group of every kernel
 constexpr int WAVE = 64;     // CDNA wavefront width
 constexpr int SLICE = 64;    // sliced-ELL slice height (one row per lane)
 constexpr int VEC = 4;       // consecutive elements per thread in streaming kernels
-constexpr int GMAX = 2048;   // upper bound on work-groups of a reducing kernel
+constexpr int GMAX = 1024;   // upper bound on work-groups of a reducing kernel
 constexpr int PAD = NT * VEC;  // internal vectors are padded to a multiple of this
+constexpr int NXCD = 8;      // accelerator complex dies; work-groups are dealt to them round-robin
 
 template <int U> struct Prec;
 template <> struct Prec<64> { typedef double T; typedef double C; };
@@ -35,6 +36,28 @@ struct Sell {
     const float *v32p;   // FP32 values, plain
 };
 
+// Work-group index with consecutive indices on one XCD: dispatch deals
+// work-groups to the 8 XCDs round-robin, so hardware group b runs on XCD
+// b % 8; renumbering gives XCD x the contiguous block range
+// [x G/8, (x+1) G/8) and thus a contiguous row range (its L2 then holds the
+// rows' neighbours).  G must be a multiple of 8 for an exact split.
+__device__ __forceinline__ int xcd_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G % NXCD) return b;
+    return (b % NXCD) * (G / NXCD) + b / NXCD;
+}
+
+// [lo, hi) share of `total` units for work-group lb of G, in multiples of `quantum`.
+__device__ __forceinline__ void block_range(int64_t total, int64_t quantum, int lb, int G,
+                                            int64_t &lo, int64_t &hi) {
+    const int64_t units = (total + quantum - 1) / quantum;
+    const int64_t per = units / G, rem = units % G;
+    const int64_t u0 = lb * per + (lb < rem ? lb : rem);
+    const int64_t u1 = u0 + per + (lb < rem ? 1 : 0);
+    lo = u0 * quantum;
+    hi = u1 * quantum < total ? u1 * quantum : total;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -47,7 +70,7 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Sum over the work-group, identical order on every call; result in all threads.
+// Sum / max over the work-group in a fixed order; result in every thread.
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double sh[NT / WAVE];
     v = wave_sum(v);
@@ -61,45 +84,31 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-// Atomic max of a non-negative double through its bit pattern (order
-// independent, so deterministic).  NaN compares above +inf.
-__device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v_nonneg) {
-    unsigned long long bits = (unsigned long long)__double_as_longlong(v_nonneg);
-    atomicMax(dst, bits);
-}
-
-__device__ __forceinline__ double bits_to_double(unsigned long long b) {
-    return __longlong_as_double((long long)b);
-}
-
-// Block-level max then one atomic per work-group.
-__device__ __forceinline__ void block_max_to(unsigned long long *dst, double v) {
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double sh[NT / WAVE];
     v = wave_max(v);
-    if ((threadIdx.x % WAVE) == 0) atomic_max_abs(dst, v);
-}
-
-// Publish this work-group's partial sums and report whether it is the last
-// work-group to finish.  In the last work-group every thread may read all
-// partials afterwards.
-__device__ __forceinline__ bool arrive_last(Ctrl *c, double *part, const double *vals, int nv) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        for (int j = 0; j < nv; ++j) part[j * gridDim.x + blockIdx.x] = vals[j];
-        __threadfence();
-        unsigned int t = __hip_atomic_fetch_add(&c->counter, 1u, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == gridDim.x - 1);
-    }
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
     __syncthreads();
-    if (last) __threadfence();
-    return last;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / WAVE; ++i) t = fmax(t, sh[i]);
+    return t;
 }
 
-// Fixed-order total of one partial array (called by the whole last work-group).
-__device__ __forceinline__ double finish_sum(const double *part) {
+// Totals of a producer kernel's per-work-group partials (G of each), summed
+// (or maxed) in the same fixed order by every work-group that calls it.
+__device__ __forceinline__ double reduce_sum(const double *part, int G) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += NT) s += part[i];
+    for (int i = threadIdx.x; i < G; i += NT) s += part[i];
     return block_sum(s);
+}
+
+__device__ __forceinline__ double reduce_max(const double *part, int G) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < G; i += NT) s = fmax(s, part[i]);
+    return block_max(s);
 }
 
 }  // namespace amp

@@ -1,28 +1,42 @@
-// HIP kernels of one AMP-PCG iteration (Alg. 3), in the paper's order:
-//   k_precond   y = omega r (u_r), z = M^{-1} y (u_z), rho = r^T z   -- "zamx" + "innerProd"
-//   k_pupdate   p = z + beta p (u_z)                                 -- "axpy"
-//   k_spmv      q = A p (u_r), gamma = q^T p                          -- "Ax"
-//   k_update    x += alpha p (FP64), r -= alpha q (u_r), delta        -- "updatePCG"
-// plus k_init (r0 = b - A x0) and k_true_res (FP64 b - A x, residual
-// replacement).  Every kernel reads the precisions of the current iteration
-// from the device-resident controller and dispatches with a uniform branch,
-// so precision switches never need the host.  Scalars (rho, gamma, delta)
-// are finished by the last work-group to arrive, which also runs the
-// controller step.
+// HIP kernels of one AMP-PCG iteration (Alg. 3).  Three launches per
+// iteration, in the paper's order:
+//
+//   k_precond  [prologue: consume ||r_k||, max|r_k| -> convergence test,
+//               eta_k, precisionSelector, omega_k]
+//              y = omega r (u_r), z = M^{-1} y (u_z), partials of rho = r^T z
+//   k_spmv     [prologue: rho_k, beta_{k-1}]
+//              p = z + beta p (u_z, written for the own rows and recomputed
+//              on the fly at the gathered columns), q = A p (u_r), partials
+//              of gamma = q^T p
+//   k_update   [prologue: gamma, alpha]
+//              x += alpha p (FP64), r -= alpha q (u_r), partials of ||r||^2
+//
+// plus k_init (r0 = b - A x0) and k_true_res (FP64 b - A x for the
+// termination check, periodic replacement, or a report).
+//
+// Cross-work-group reductions use no atomics and no fences: every
+// work-group writes its partial sums; every work-group of the next kernel
+// adds all of them in the same fixed order and evaluates the controller
+// from identical inputs, so all reach identical decisions.  Work-group 0
+// writes the resulting state to a buffer that no work-group of the same
+// kernel reads.
 #pragma once
 
 #include "amp_device.hpp"
 
 namespace amp {
 
-// Pointers of every working vector, indexed by precision slot
-// (0: FP64, 1: FP32, 2: FP16).  Vectors are padded to np elements.
+// Working vectors, indexed by precision slot (0: FP64, 1: FP32, 2: FP16).
+// All are padded to np elements; p is double-buffered.
 struct Bufs {
     double *x;
     const double *b;
-    void *r[3], *z[3], *p[3], *q[3];
+    void *r[3], *z[3], *q[3];
+    void *p[3][2];
     const void *dinv[3];
-    double *part;   // 2 * GMAX partial sums
+    double *part_res;   // 3 x GMAX: sum a, sum b, max
+    double *part_pre;   // 2 x GMAX: rho, max|z|
+    double *part_spmv;  // 2 x GMAX: gamma, max|p|
 };
 
 __host__ __device__ constexpr int pslot(int u) { return u == 64 ? 0 : (u == 32 ? 1 : 2); }
@@ -40,131 +54,198 @@ __device__ __forceinline__ void st4(T *p, int64_t i, const V4<T> &x) {
     *reinterpret_cast<V4<T> *>(p + i) = x;
 }
 
-#define AMP_GRID_STRIDE(i, np)                                                            \
-    for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) * VEC; i < (np);           \
-         i += (int64_t)gridDim.x * NT * VEC)
+// Streaming loop over this work-group's contiguous element range.
+#define AMP_STREAM_LOOP(i, np)                                                          \
+    int64_t lo_, hi_;                                                                    \
+    block_range((np), (int64_t)NT * VEC, xcd_block(), gridDim.x, lo_, hi_);              \
+    for (int64_t i = lo_ + (int64_t)threadIdx.x * VEC; i < hi_; i += (int64_t)NT * VEC)
 
 // ----------------------------------------------------------------------------
-// controller epilogues (single thread of the last work-group)
+// state plumbing
 // ----------------------------------------------------------------------------
 
-__device__ inline void finish_iteration(Ctrl *c, double delta_new, double maxr_new) {
-    const int it = c->iters;
-    c->maxr_prev = c->maxr;
-    c->maxr = maxr_new;
-    c->delta = delta_new;
-    c->ring[it % kRing] = delta_new;
-    if (c->delta_history) c->delta_history[it] = delta_new;
-    if (delta_new <= c->tol_b) {
-        c->status = c->verify ? NEED_VERIFY : CONVERGED;
-        return;
+// Load the incoming state into LDS (all threads see it after the barrier).
+__device__ __forceinline__ void load_state(St &s, const St *in) {
+    if (threadIdx.x == 0) s = *in;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void store_state(const St &s, St *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = s;
+}
+
+// Record ||r_i|| (work-group 0 only; nobody reads index i in this kernel).
+__device__ __forceinline__ void record_delta(const Cfg &c, int i, double d) {
+    if (blockIdx.x == 0) {
+        c.ring[i % kRing] = d;
+        if (c.delta_history) c.delta_history[i] = d;
     }
-    if (!isfinite(delta_new)) {
-        c->status = BREAKDOWN;
-        return;
-    }
-    if (it >= c->maxit) {
-        c->status = MAXIT;
-        return;
-    }
-    prepare_iteration(*c, it);
 }
 
 // ----------------------------------------------------------------------------
 // sliced-ELL row products
 // ----------------------------------------------------------------------------
 
-// FP64 values, FP64 accumulation: sum_j a_ij p_j in slot order.
-template <typename TP>
-__device__ __forceinline__ double row_dot64(const Sell &A, int64_t base, int w, int64_t row,
-                                            const TP *p) {
+// q_i = sum_j a_ij p_j with FP64 values and accumulation, slot order.
+template <typename PF>
+__device__ __forceinline__ double row_dot64(const Sell &A, int64_t base, int w, PF pval) {
     double acc = 0.0;
-    for (int j = 0; j < w; ++j) {
+    int j = 0;
+    for (; j + 4 <= w; j += 4) {
+        int32_t c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = A.col[base + (int64_t)(j + u) * SLICE];
+            v[u] = A.v64[base + (int64_t)(j + u) * SLICE];
+        }
+        double pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = (double)pval(c[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * pj[u];
+    }
+    for (; j < w; ++j) {
         const int64_t s = base + (int64_t)j * SLICE;
-        acc += A.v64[s] * (double)p[A.col[s]];
+        acc += A.v64[s] * (double)pval(A.col[s]);
     }
     return acc;
 }
 
-// FP32 values, FP32 accumulation.  DIFF: off-diagonal slots contribute
-// a_ij (p_j - p_i) in slot order, then the diagonal slot's row sum s_i
-// contributes s_i p_i; otherwise the textbook sum_j a_ij p_j.
-template <typename TP, bool DIFF>
-__device__ __forceinline__ float row_dot32(const Sell &A, int64_t base, int w, int64_t row,
-                                           const TP *p) {
-    float acc = 0.0f;
-    if (DIFF) {
-        const float pi = (float)p[row];
-        float dterm = 0.0f;
-        for (int j = 0; j < w; ++j) {
-            const int64_t s = base + (int64_t)j * SLICE;
-            const int32_t cj = A.col[s];
-            const float v = A.v32[s];
-            const float pj = (float)p[cj];
-            if (cj == row) dterm = v * pj;
-            else acc += v * (pj - pi);
+// FP32 values and accumulation.  DIFF: off-diagonal slots add a_ij (p_j - p_i)
+// in slot order, then the diagonal slot's row sum s_i adds s_i p_i; padding
+// slots (col = row, value 0) add 0 exactly.  Otherwise the textbook form.
+template <bool DIFF, typename PF>
+__device__ __forceinline__ float row_dot32(const Sell &A, int64_t base, int w, int64_t row, float pi,
+                                           PF pval) {
+    const float *vals = DIFF ? A.v32 : A.v32p;
+    float acc = 0.0f, dterm = 0.0f;
+    int j = 0;
+    for (; j + 4 <= w; j += 4) {
+        int32_t c[4];
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = A.col[base + (int64_t)(j + u) * SLICE];
+            v[u] = vals[base + (int64_t)(j + u) * SLICE];
         }
-        acc = dterm + acc;
-    } else {
-        for (int j = 0; j < w; ++j) {
-            const int64_t s = base + (int64_t)j * SLICE;
-            acc += A.v32p[s] * (float)p[A.col[s]];
+        float pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = (float)pval(c[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!DIFF) acc += v[u] * pj[u];
+            else if (c[u] == row) dterm += v[u] * pj[u];
+            else acc += v[u] * (pj[u] - pi);
         }
     }
-    return acc;
+    for (; j < w; ++j) {
+        const int64_t s = base + (int64_t)j * SLICE;
+        const int32_t c = A.col[s];
+        const float v = vals[s];
+        const float pj = (float)pval(c);
+        if (!DIFF) acc += v * pj;
+        else if (c == row) dterm += v * pj;
+        else acc += v * (pj - pi);
+    }
+    return DIFF ? dterm + acc : acc;
 }
 
-#define AMP_SLICE_LOOP(A, row, base, w)                                                   \
-    const int lane_ = threadIdx.x % WAVE;                                                  \
-    const int64_t wave0_ = (int64_t)blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;         \
-    const int64_t wstride_ = (int64_t)gridDim.x * (NT / WAVE);                             \
-    for (int64_t sl_ = wave0_; sl_ < (A).nslices; sl_ += wstride_)                         \
-        for (int64_t base = (A).sptr[sl_] + lane_, row = sl_ * SLICE + lane_,             \
-                     w = ((A).sptr[sl_ + 1] - (A).sptr[sl_]) / SLICE, once_ = 1;           \
-             once_; once_ = 0)
+// Slices of this work-group: contiguous range, one slice per wave at a time.
+#define AMP_SLICE_LOOP(A, sl)                                                            \
+    int64_t slo_, shi_;                                                                  \
+    block_range((A).nslices, 1, xcd_block(), gridDim.x, slo_, shi_);                     \
+    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE)
 
 // ----------------------------------------------------------------------------
-// k_init: r0 = b - A x0 in FP64, ||b||^2, ||r0||^2, max|r0|
+// k_init: r0 = b - A x0 in FP64; partials ||r0||^2, ||b||^2, max|r0|
 // ----------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B, Ctrl *c) {
-    double sb = 0.0, sr = 0.0, mr = 0.0;
+__global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) {
+    double sr = 0.0, sb = 0.0, mr = 0.0;
     double *r = (double *)B.r[0];
-    AMP_SLICE_LOOP(A, row, base, w) {
-        const double t = B.b[row] - row_dot64(A, base, (int)w, row, B.x);
+    const double *x = B.x;
+    AMP_SLICE_LOOP(A, sl) {
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
+        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+        const double t = B.b[row] - row_dot64(A, base, w, [&](int32_t c) { return x[c]; });
         r[row] = t;
-        sb += B.b[row] * B.b[row];
         sr += t * t;
+        sb += B.b[row] * B.b[row];
         mr = fmax(mr, fabs(t));
     }
-    block_max_to(&c->maxbits[0], mr);
-    double v[2] = {block_sum(sb), block_sum(sr)};
-    if (arrive_last(c, B.part, v, 2)) {
-        const double tb = finish_sum(B.part);
-        const double tr = finish_sum(B.part + gridDim.x);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            c->bnorm = sqrt(tb);
-            c->tol_b = c->tol * c->bnorm;
-            c->delta = sqrt(tr);
-            c->maxr = bits_to_double(c->maxbits[0]);
-            c->maxr_prev = c->maxr;
-            c->maxbits[0] = 0;
-            c->ring[0] = c->delta;
-            if (c->delta_history) c->delta_history[0] = c->delta;
-            if (c->delta <= c->tol_b) c->status = CONVERGED;
-            else if (c->maxit <= 0) c->status = MAXIT;
-            else prepare_iteration(*c, 0);
-        }
+    sr = block_sum(sr);
+    sb = block_sum(sb);
+    mr = block_max(mr);
+    if (threadIdx.x == 0) {
+        B.part_res[blockIdx.x] = sr;
+        B.part_res[GMAX + blockIdx.x] = sb;
+        B.part_res[2 * GMAX + blockIdx.x] = mr;
     }
 }
 
 // ----------------------------------------------------------------------------
-// k_precond (Jacobi / identity): z = dinv (.) fl_uz(fl_ur(omega r)), rho = r^T z
+// k_precond
 // ----------------------------------------------------------------------------
 
+// Prologue: totals of the residual partials -> controller.  Sets s.status.
+__device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B) {
+    __shared__ int rec;
+    __shared__ double recv;
+    const int G = (s.kind == RES_UPDATE) ? c.g_stream : c.g_slice;
+    const double a = reduce_sum(B.part_res, G);
+    const double b = reduce_sum(B.part_res + GMAX, G);
+    const double m = reduce_max(B.part_res + 2 * GMAX, G);
+    if (threadIdx.x == 0) {
+        rec = -1;
+        if (s.kind == RES_INIT) {
+            s.bnorm = sqrt(b);
+            s.tol_b = c.tol * s.bnorm;
+            s.delta = sqrt(a);
+            s.maxr = m;
+            s.maxr_prev = m;
+            rec = 0;
+            recv = s.delta;
+            if (s.delta <= s.tol_b) s.status = CONVERGED;
+            else if (c.maxit <= 0) s.status = MAXIT;
+            else prepare_iteration(s, c, c.ring, 0);
+        } else if (s.kind == RES_UPDATE || s.kind == RES_PERIODIC) {
+            const double d = sqrt(s.kind == RES_UPDATE ? a : b);
+            if (s.kind == RES_PERIODIC) s.n_repl += 1;
+            rec = s.iters;
+            recv = d;
+            finish_iteration(s, c, c.ring, d, m);
+        } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
+            s.true_res = sqrt(a);
+            if (s.true_res <= s.tol_b) {
+                s.status = CONVERGED;
+            } else if (s.n_repl >= c.max_repl) {
+                s.status = MAXIT;
+            } else {
+                s.n_repl += 1;
+                s.delta = sqrt(b);
+                s.maxr = m;
+                rec = s.iters;
+                recv = s.delta;
+                if (s.iters >= c.maxit) {
+                    s.status = MAXIT;
+                } else {
+                    s.status = RUNNING;
+                    prepare_iteration(s, c, c.ring, s.iters);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && rec >= 0) {
+        record_delta(c, rec, recv);
+        if (blockIdx.x == 0 && s.status == RUNNING && c.prec_history) c.prec_history[s.k] = s.uz | (s.ur << 8);
+    }
+}
+
 template <int RS, int UR, int UZ>
-__device__ __forceinline__ void precond_body(const Ctrl *c, const Bufs &B, int64_t np, double &rho,
+__device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t np, double &rho,
                                              double &mz) {
     typedef typename Prec<RS>::T TRS;
     typedef typename Prec<UR>::T TR;
@@ -174,8 +255,8 @@ __device__ __forceinline__ void precond_body(const Ctrl *c, const Bufs &B, int64
     TR *rn = (TR *)B.r[pslot(UR)];
     TZ *z = (TZ *)B.z[pslot(UZ)];
     const TZ *dv = (const TZ *)B.dinv[pslot(UZ)];
-    const TR w = (TR)c->omega_eff;
-    AMP_GRID_STRIDE(i, np) {
+    const TR w = (TR)s.omega_eff;
+    AMP_STREAM_LOOP(i, np) {
         const V4<TRS> rv = ld4(r, i);
         const V4<TZ> dd = ld4(dv, i);
         V4<TZ> zz;
@@ -195,169 +276,180 @@ __device__ __forceinline__ void precond_body(const Ctrl *c, const Bufs &B, int64
     }
 }
 
-__global__ void __launch_bounds__(NT) k_precond(Bufs B, int64_t np, Ctrl *c) {
-    if (c->status != RUNNING) return;
-    const int rs = c->r_store, ur = c->ur, uz = c->uz;
+// At a u_z switch p_{k-1} is first rounded to the new u_z.
+template <int PS, int UZ>
+__device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np) {
+    typedef typename Prec<PS>::T TPS;
+    typedef typename Prec<UZ>::T TZ;
+    const TPS *po = (const TPS *)B.p[pslot(PS)][pb];
+    TZ *pn = (TZ *)B.p[pslot(UZ)][pb];
+    AMP_STREAM_LOOP(i, np) {
+        const V4<TPS> a = ld4(po, i);
+        V4<TZ> b;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) b.v[e] = (TZ)a.v[e];
+        st4(pn, i, b);
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    consume_residual(s, c, B);
+    __syncthreads();
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    const int rs = s.r_store, ur = s.ur, uz = s.uz;
     double rho = 0.0, mz = 0.0;
-#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(c, B, np, rho, mz)
-#define AMP_PC_Z(RS, UR)            \
-    if (uz == 64) AMP_PC(RS, UR, 64); \
-    else if (uz == 32) AMP_PC(RS, UR, 32); \
+#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, rho, mz)
+#define AMP_PC_Z(RS, UR)                  \
+    if (uz == 64) AMP_PC(RS, UR, 64);       \
+    else if (uz == 32) AMP_PC(RS, UR, 32);  \
     else AMP_PC(RS, UR, 16);
     if (rs == 64 && ur == 64) { AMP_PC_Z(64, 64) }
     else if (rs == 64) { AMP_PC_Z(64, 32) }
     else { AMP_PC_Z(32, 32) }
 #undef AMP_PC_Z
 #undef AMP_PC
-    block_max_to(&c->maxbits[1], mz);
-    double v[1] = {block_sum(rho)};
-    if (arrive_last(c, B.part, v, 1)) {
-        const double t = finish_sum(B.part);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            c->r_store = c->ur;
-            c->maxz = bits_to_double(c->maxbits[1]);
-            c->maxbits[1] = 0;
-            const double rp = c->rho;
-            c->rho_prev = rp;
-            c->rho = t;
-            c->beta = (c->k > 0) ? t / rp : 0.0;
-            if (!(t > 0.0) || !isfinite(c->beta)) c->status = BREAKDOWN;
-        }
+    const bool conv = (s.k > 0 && s.p_store != uz);
+    if (conv) {
+        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, np);
+        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, np);
+        else convert_p<32, 16>(B, s.pbuf, np);
     }
+    rho = block_sum(rho);
+    mz = block_max(mz);
+    if (threadIdx.x == 0) {
+        B.part_pre[blockIdx.x] = rho;
+        B.part_pre[GMAX + blockIdx.x] = mz;
+        s.r_store = s.ur;
+        if (conv) s.p_store = uz;
+    }
+    store_state(s, out);
 }
 
 // ----------------------------------------------------------------------------
-// k_pupdate: p_k = z_k + beta p_{k-1} in u_z (p_{k-1} held in p_store)
+// k_spmv: p = z + beta p_{k-1} (u_z), q = A p (u_r), gamma = q^T p
 // ----------------------------------------------------------------------------
 
-template <int PS, int UZ>
-__device__ __forceinline__ void pupdate_body(const Ctrl *c, const Bufs &B, int64_t np, double &mp) {
-    typedef typename Prec<PS>::T TPS;
+template <int UZ, int UR, bool DIFF>
+__device__ __forceinline__ void spmv_p_body(const Sell &A, const void *zv, const void *pov, void *pnv,
+                                            void *qv, bool first, double beta_d, double &gam,
+                                            double &mp) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
-    const TPS *po = (const TPS *)B.p[pslot(PS)];
-    TZ *pn = (TZ *)B.p[pslot(UZ)];
-    const TZ *z = (const TZ *)B.z[pslot(UZ)];
-    const bool first = (c->k == 0);
-    const CZ beta = (CZ)c->beta;
-    AMP_GRID_STRIDE(i, np) {
-        const V4<TZ> zz = ld4(z, i);
-        V4<TZ> pp;
-        if (first) {
-            pp = zz;
-        } else {
-            const V4<TPS> qo = ld4(po, i);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) pp.v[e] = (TZ)((CZ)zz.v[e] + beta * (CZ)qo.v[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) mp = fmax(mp, fabs((double)pp.v[e]));
-        st4(pn, i, pp);
-    }
-}
-
-__global__ void __launch_bounds__(NT) k_pupdate(Bufs B, int64_t np, Ctrl *c) {
-    if (c->status != RUNNING) return;
-    const int ps = (c->k == 0) ? c->uz : c->p_store, uz = c->uz;
-    double mp = 0.0;
-    if (ps == 64) {
-        if (uz == 64) pupdate_body<64, 64>(c, B, np, mp);
-        else if (uz == 32) pupdate_body<64, 32>(c, B, np, mp);
-        else pupdate_body<64, 16>(c, B, np, mp);
-    } else if (ps == 32) {
-        if (uz == 32) pupdate_body<32, 32>(c, B, np, mp);
-        else pupdate_body<32, 16>(c, B, np, mp);
-    } else {
-        pupdate_body<16, 16>(c, B, np, mp);
-    }
-    block_max_to(&c->maxbits[2], mp);
-}
-
-// ----------------------------------------------------------------------------
-// k_spmv: q = A p (u_r), gamma = q^T p (FP64)
-// ----------------------------------------------------------------------------
-
-template <int UP, int UR, bool DIFF>
-__device__ __forceinline__ void spmv_body(const Sell &A, const Bufs &B, double &gam) {
-    typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TQ;
-    const TP *p = (const TP *)B.p[pslot(UP)];
-    TQ *q = (TQ *)B.q[pslot(UR)];
-    AMP_SLICE_LOOP(A, row, base, w) {
-        TQ qv;
-        if (UR == 64) qv = (TQ)row_dot64(A, base, (int)w, row, p);
-        else qv = (TQ)row_dot32<TP, DIFF>(A, base, (int)w, row, p);
-        q[row] = qv;
-        gam += (double)qv * (double)p[row];
+    const TZ *z = (const TZ *)zv;
+    const TZ *po = (const TZ *)pov;
+    TZ *pn = (TZ *)pnv;
+    TQ *q = (TQ *)qv;
+    const CZ beta = (CZ)beta_d;
+    auto pval = [&](int64_t c) -> TZ {
+        if (first) return z[c];
+        return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
+    };
+    AMP_SLICE_LOOP(A, sl) {
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
+        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+        const TZ pi = pval(row);
+        if (pn) pn[row] = pi;
+        mp = fmax(mp, fabs((double)pi));
+        TQ qq;
+        if (UR == 64) qq = (TQ)row_dot64(A, base, w, pval);
+        else qq = (TQ)row_dot32<DIFF>(A, base, w, row, (float)pi, pval);
+        q[row] = qq;
+        gam += (double)qq * (double)pi;
     }
 }
 
-template <int UP, int UR, bool DIFF>
-__global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, Bufs B, double *gamma_out, Ctrl *c) {
-    double gam = 0.0;
-    spmv_body<UP, UR, DIFF>(A, B, gam);
-    double v[1] = {block_sum(gam)};
-    if (arrive_last(c, B.part, v, 1)) {
-        const double t = finish_sum(B.part);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            if (gamma_out) *gamma_out = t;
-        }
+__global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
     }
-}
-
-__global__ void __launch_bounds__(NT) k_spmv(Sell A, Bufs B, int diff, Ctrl *c) {
-    if (c->status != RUNNING) return;
-    const int up = c->uz, ur = c->ur;
-    double gam = 0.0;
+    const double rho = reduce_sum(B.part_pre, c.g_stream);
+    const double mz = reduce_max(B.part_pre + GMAX, c.g_stream);
+    if (threadIdx.x == 0) {
+        s.rho_prev = s.rho;
+        s.rho = rho;
+        s.beta = (s.k > 0) ? rho / s.rho_prev : 0.0;
+        s.maxz = mz;
+        if (!(rho > 0.0) || !isfinite(s.beta)) s.status = BREAKDOWN;
+    }
+    __syncthreads();
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    const int uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
+    const bool first = (s.k == 0);
+    double gam = 0.0, mp = 0.0;
+#define AMP_SP(UZ, UR, DF) \
+    spmv_p_body<UZ, UR, DF>(A, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], first, s.beta, gam, mp)
     if (ur == 64) {
-        if (up == 64) spmv_body<64, 64, false>(A, B, gam);
-        else if (up == 32) spmv_body<32, 64, false>(A, B, gam);
-        else spmv_body<16, 64, false>(A, B, gam);
-    } else if (diff) {
-        if (up == 64) spmv_body<64, 32, true>(A, B, gam);
-        else if (up == 32) spmv_body<32, 32, true>(A, B, gam);
-        else spmv_body<16, 32, true>(A, B, gam);
+        if (uz == 64) AMP_SP(64, 64, false);
+        else if (uz == 32) AMP_SP(32, 64, false);
+        else AMP_SP(16, 64, false);
+    } else if (c.diff) {
+        if (uz == 64) AMP_SP(64, 32, true);
+        else if (uz == 32) AMP_SP(32, 32, true);
+        else AMP_SP(16, 32, true);
     } else {
-        if (up == 64) spmv_body<64, 32, false>(A, B, gam);
-        else if (up == 32) spmv_body<32, 32, false>(A, B, gam);
-        else spmv_body<16, 32, false>(A, B, gam);
+        if (uz == 64) AMP_SP(64, 32, false);
+        else if (uz == 32) AMP_SP(32, 32, false);
+        else AMP_SP(16, 32, false);
     }
-    double v[1] = {block_sum(gam)};
-    if (arrive_last(c, B.part, v, 1)) {
-        const double t = finish_sum(B.part);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            c->gamma = t;
-            c->alpha = c->rho / t;
-            if (!(t > 0.0) || !isfinite(c->alpha)) c->status = BREAKDOWN;
-        }
+#undef AMP_SP
+    gam = block_sum(gam);
+    mp = block_max(mp);
+    if (threadIdx.x == 0) {
+        B.part_spmv[blockIdx.x] = gam;
+        B.part_spmv[GMAX + blockIdx.x] = mp;
     }
+    store_state(s, out);
+}
+
+// Stand-alone product (tests, measurement): with first = true, q = A z;
+// otherwise p = z + beta p_old as in the iteration.
+template <int UZ, int UR, bool DIFF>
+__global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
+                                                   int first, double beta, double *part) {
+    double gam = 0.0, mp = 0.0;
+    spmv_p_body<UZ, UR, DIFF>(A, z, po, pn, q, first != 0, beta, gam, mp);
+    gam = block_sum(gam);
+    if (threadIdx.x == 0 && part) part[blockIdx.x] = gam;
 }
 
 // ----------------------------------------------------------------------------
-// k_update: x += alpha p (FP64), r -= alpha q (u_r), delta = ||r||
+// k_update: x += alpha p (FP64), r -= alpha q (u_r); partials ||r||^2, max|r|
 // ----------------------------------------------------------------------------
 
 template <int UP, int UR>
-__device__ __forceinline__ void update_body(const Ctrl *c, const Bufs &B, int64_t np, double &dd,
-                                            double &mr) {
+__device__ __forceinline__ void update_body(double alpha, const Bufs &B, const void *pv, int64_t np,
+                                            double &dd, double &mr) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
-    const TP *p = (const TP *)B.p[pslot(UP)];
+    const TP *p = (const TP *)pv;
     TR *r = (TR *)B.r[pslot(UR)];
     const TR *q = (const TR *)B.q[pslot(UR)];
-    const double alpha = c->alpha;
     const TR a = (TR)alpha;
-    AMP_GRID_STRIDE(i, np) {
-        const V4<TP> pv = ld4(p, i);
+    AMP_STREAM_LOOP(i, np) {
+        const V4<TP> pv4 = ld4(p, i);
         V4<double> xv = ld4(B.x, i);
         V4<TR> rv = ld4(r, i);
         const V4<TR> qv = ld4(q, i);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            xv.v[e] = xv.v[e] + alpha * (double)pv.v[e];
+            xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
             const TR rn = (TR)(rv.v[e] - a * qv.v[e]);
             rv.v[e] = rn;
             dd += (double)rn * (double)rn;
@@ -368,112 +460,118 @@ __device__ __forceinline__ void update_body(const Ctrl *c, const Bufs &B, int64_
     }
 }
 
-__global__ void __launch_bounds__(NT) k_update(Bufs B, int64_t np, Ctrl *c) {
-    if (c->status != RUNNING) return;
-    const int up = c->uz, ur = c->ur;
+__global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    const double gam = reduce_sum(B.part_spmv, c.g_slice);
+    const double mp = reduce_max(B.part_spmv + GMAX, c.g_slice);
+    if (threadIdx.x == 0) {
+        s.gamma = gam;
+        s.alpha = s.rho / gam;
+        s.maxp = mp;
+        if (!(gam > 0.0) || !isfinite(s.alpha)) s.status = BREAKDOWN;
+    }
+    __syncthreads();
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    const int uz = s.uz, ur = s.ur;
+    const void *p = B.p[pslot(uz)][s.pbuf ^ 1];
     double dd = 0.0, mr = 0.0;
     if (ur == 64) {
-        if (up == 64) update_body<64, 64>(c, B, np, dd, mr);
-        else if (up == 32) update_body<32, 64>(c, B, np, dd, mr);
-        else update_body<16, 64>(c, B, np, dd, mr);
+        if (uz == 64) update_body<64, 64>(s.alpha, B, p, np, dd, mr);
+        else if (uz == 32) update_body<32, 64>(s.alpha, B, p, np, dd, mr);
+        else update_body<16, 64>(s.alpha, B, p, np, dd, mr);
     } else {
-        if (up == 64) update_body<64, 32>(c, B, np, dd, mr);
-        else if (up == 32) update_body<32, 32>(c, B, np, dd, mr);
-        else update_body<16, 32>(c, B, np, dd, mr);
+        if (uz == 64) update_body<64, 32>(s.alpha, B, p, np, dd, mr);
+        else if (uz == 32) update_body<32, 32>(s.alpha, B, p, np, dd, mr);
+        else update_body<16, 32>(s.alpha, B, p, np, dd, mr);
     }
-    block_max_to(&c->maxbits[0], mr);
-    double v[1] = {block_sum(dd)};
-    if (arrive_last(c, B.part, v, 1)) {
-        const double t = finish_sum(B.part);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            const double mrr = bits_to_double(c->maxbits[0]);
-            c->maxbits[0] = 0;
-            c->maxp = bits_to_double(c->maxbits[2]);
-            c->maxbits[2] = 0;
-            c->p_store = c->uz;
-            c->iters = c->k + 1;
-            if (c->rr_period > 0 && c->iters % c->rr_period == 0) {
-                c->rr_pending = 1;     // k_true_res (mode 1) completes the iteration
-            } else {
-                finish_iteration(c, sqrt(t), mrr);
-            }
-        }
+    dd = block_sum(dd);
+    mr = block_max(mr);
+    if (threadIdx.x == 0) {
+        B.part_res[blockIdx.x] = dd;
+        B.part_res[GMAX + blockIdx.x] = 0.0;
+        B.part_res[2 * GMAX + blockIdx.x] = mr;
+        s.pbuf ^= 1;
+        s.p_store = uz;
+        s.iters = s.k + 1;
+        s.kind = RES_UPDATE;
     }
+    store_state(s, out);
 }
 
 // ----------------------------------------------------------------------------
-// k_true_res: t = b - A x (FP64).  mode 0: termination check (with
-// replacement of r by t when the check fails); mode 1: periodic replacement
-// that completes the iteration (runs only when k_update deferred to it).
-// r is written as fl_{r_store}(t).
+// k_true_res: t = b - A x (FP64).  mode 0: termination check (runs only when
+// the state asks for it; r := fl(t) for a possible replacement); mode 1:
+// periodic replacement of r (completes the iteration); mode 2: report only
+// (writes nothing but partials).  Partials: ||t||^2, ||fl(t)||^2, max|fl(t)|.
 // ----------------------------------------------------------------------------
 
 template <int RS>
-__device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, double &st, double &ss,
-                                              double &mr) {
+__device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, bool write, double &st,
+                                              double &ss, double &mr) {
     typedef typename Prec<RS>::T TR;
     TR *r = (TR *)B.r[pslot(RS)];
-    AMP_SLICE_LOOP(A, row, base, w) {
-        const double t = B.b[row] - row_dot64(A, base, (int)w, row, B.x);
+    const double *x = B.x;
+    AMP_SLICE_LOOP(A, sl) {
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
+        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+        const double t = B.b[row] - row_dot64(A, base, w, [&](int32_t c) { return x[c]; });
         const TR tr = (TR)t;
-        r[row] = tr;
+        if (write) r[row] = tr;
         st += t * t;
         ss += (double)tr * (double)tr;
         mr = fmax(mr, fabs((double)tr));
     }
 }
 
-__global__ void __launch_bounds__(NT) k_true_res(Sell A, Bufs B, int mode, Ctrl *c) {
-    if (mode == 0 && c->status != NEED_VERIFY) return;
-    if (mode == 1 && (c->status != RUNNING || c->rr_pending == 0)) return;
+__global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    const bool run = (mode == 0 && s.status == NEED_VERIFY) || (mode == 1 && s.status == RUNNING) || mode == 2;
+    if (!run) {
+        store_state(s, out);
+        return;
+    }
     double st = 0.0, ss = 0.0, mr = 0.0;
-    if (c->r_store == 64) true_res_body<64>(A, B, st, ss, mr);
-    else true_res_body<32>(A, B, st, ss, mr);
-    block_max_to(&c->maxbits[3], mr);
-    double v[2] = {block_sum(st), block_sum(ss)};
-    if (arrive_last(c, B.part, v, 2)) {
-        const double tt = finish_sum(B.part);
-        const double ts = finish_sum(B.part + gridDim.x);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            const double mrr = bits_to_double(c->maxbits[3]);
-            c->maxbits[3] = 0;
-            c->true_res = sqrt(tt);
-            if (mode == 1) {
-                c->rr_pending = 0;
-                c->n_repl += 1;
-                finish_iteration(c, sqrt(ts), mrr);
-            } else if (c->true_res <= c->tol_b) {
-                c->status = CONVERGED;
-            } else if (c->n_repl >= c->max_repl) {
-                c->status = MAXIT;
-            } else {
-                c->n_repl += 1;
-                const double dn = sqrt(ts);
-                const int it = c->iters;
-                c->delta = dn;
-                c->maxr = mrr;
-                c->ring[it % kRing] = dn;
-                if (c->delta_history) c->delta_history[it] = dn;
-                if (it >= c->maxit) {
-                    c->status = MAXIT;
-                } else {
-                    c->status = RUNNING;
-                    prepare_iteration(*c, it);
-                }
-            }
+    if (s.r_store == 64) true_res_body<64>(A, B, mode != 2, st, ss, mr);
+    else true_res_body<32>(A, B, mode != 2, st, ss, mr);
+    st = block_sum(st);
+    ss = block_sum(ss);
+    mr = block_max(mr);
+    if (threadIdx.x == 0) {
+        B.part_res[blockIdx.x] = st;
+        B.part_res[GMAX + blockIdx.x] = ss;
+        B.part_res[2 * GMAX + blockIdx.x] = mr;
+        if (mode == 0) {
+            s.status = RUNNING;
+            s.kind = RES_VERIFY;
+        } else if (mode == 1) {
+            s.kind = RES_PERIODIC;
         }
     }
+    store_state(s, out);
+}
+
+// Fixed-order total of G partials into *out (one work-group).
+__global__ void __launch_bounds__(NT) k_reduce_to(const double *part, int G, int is_max, double *out) {
+    const double t = is_max ? reduce_max(part, G) : reduce_sum(part, G);
+    if (threadIdx.x == 0) *out = t;
 }
 
 // ----------------------------------------------------------------------------
-// standalone preconditioner application (tests / measurement)
+// stand-alone preconditioner application (tests / measurement)
 // ----------------------------------------------------------------------------
 
 template <int UR, int UZ>
-__global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double omega_eff,
-                                                      double *rho_out, Ctrl *c) {
+__global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double omega_eff, double *part) {
     typedef typename Prec<UR>::T TR;
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
@@ -482,7 +580,7 @@ __global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double
     const TZ *dv = (const TZ *)B.dinv[pslot(UZ)];
     const TR w = (TR)omega_eff;
     double rho = 0.0;
-    AMP_GRID_STRIDE(i, np) {
+    AMP_STREAM_LOOP(i, np) {
         const V4<TR> rv = ld4(r, i);
         const V4<TZ> dd = ld4(dv, i);
         V4<TZ> zz;
@@ -494,14 +592,8 @@ __global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double
         }
         st4(z, i, zz);
     }
-    double v[1] = {block_sum(rho)};
-    if (arrive_last(c, B.part, v, 1)) {
-        const double t = finish_sum(B.part);
-        if (threadIdx.x == 0) {
-            c->counter = 0;
-            if (rho_out) *rho_out = t;
-        }
-    }
+    rho = block_sum(rho);
+    if (threadIdx.x == 0) part[blockIdx.x] = rho;
 }
 
 }  // namespace amp

@@ -68,14 +68,21 @@ static inline bool valid_prec(int u) { return u == 64 || u == 32 || u == 16; }
 struct Work {
     int64_t np = 0;
     double *x = nullptr, *b = nullptr;
-    double *r64 = nullptr, *z64 = nullptr, *p64 = nullptr, *q64 = nullptr;
-    float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
-    half_t *z16 = nullptr, *p16 = nullptr;
-    double *part = nullptr;
-    Ctrl *ctrl = nullptr;
-    Ctrl *snap = nullptr;         // pinned host snapshots [2]
+    double *r64 = nullptr, *z64 = nullptr, *q64 = nullptr;
+    float *r32 = nullptr, *z32 = nullptr, *q32 = nullptr;
+    half_t *z16 = nullptr;
+    double *p64[2] = {nullptr, nullptr};
+    float *p32[2] = {nullptr, nullptr};
+    half_t *p16[2] = {nullptr, nullptr};
+    double *part = nullptr;       // 7 x GMAX partial sums (res 3, pre 2, spmv 2)
+    double *ring = nullptr;       // kRing residual norms
+    double *scalar = nullptr;     // one reduced scalar for the single-kernel entry points
+    St *st = nullptr;             // state chain: [init, pre, spmv, res, tr, report]
+    St *snap = nullptr;           // pinned host snapshots [2]
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
+
+enum { ST_INIT = 0, ST_PRE = 1, ST_SPMV = 2, ST_RES = 3, ST_TR = 4, ST_REPORT = 5, ST_COUNT = 6 };
 
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0;
@@ -104,21 +111,24 @@ struct amp_precond_s {
     double gain = 1.0;   // max|M^{-1} r| <= gain max|r|
 };
 
-static int grid_stream(int64_t np) {
-    int64_t g = (np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+// Work-group counts: enough for every unit of work, at most GMAX, and a
+// multiple of the XCD count when there are at least that many.
+static int fit_grid(int64_t g) {
+    g = std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+    if (g >= NXCD) g -= g % NXCD;
+    return (int)g;
 }
 
-static int grid_slices(int64_t nslices) {
-    int64_t g = (nslices + NT / WAVE - 1) / (NT / WAVE);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
-}
+static int grid_stream(int64_t np) { return fit_grid((np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC)); }
+
+static int grid_slices(int64_t nslices) { return fit_grid((nslices + NT / WAVE - 1) / (NT / WAVE)); }
 
 static void free_work(Work &w) {
     dfree(w.x); dfree(w.b);
-    dfree(w.r64); dfree(w.z64); dfree(w.p64); dfree(w.q64);
-    dfree(w.r32); dfree(w.z32); dfree(w.p32); dfree(w.q32);
-    dfree(w.z16); dfree(w.p16); dfree(w.part); dfree(w.ctrl);
+    dfree(w.r64); dfree(w.z64); dfree(w.q64);
+    dfree(w.r32); dfree(w.z32); dfree(w.q32); dfree(w.z16);
+    for (int i = 0; i < 2; ++i) { dfree(w.p64[i]); dfree(w.p32[i]); dfree(w.p16[i]); }
+    dfree(w.part); dfree(w.ring); dfree(w.scalar); dfree(w.st);
     if (w.snap) (void)hipHostFree(w.snap);
     w.snap = nullptr;
     for (auto &e : w.ev)
@@ -127,28 +137,35 @@ static void free_work(Work &w) {
 
 static amp_status ensure_work(amp_matrix A, hipStream_t st) {
     Work &w = A->w;
-    if (w.ctrl) return AMP_OK;
+    if (w.st) return AMP_OK;
     const int64_t np = A->np;
     w.np = np;
     AMP_TRY(dalloc(&w.x, np)); AMP_TRY(dalloc(&w.b, np));
-    AMP_TRY(dalloc(&w.r64, np)); AMP_TRY(dalloc(&w.z64, np));
-    AMP_TRY(dalloc(&w.p64, np)); AMP_TRY(dalloc(&w.q64, np));
-    AMP_TRY(dalloc(&w.r32, np)); AMP_TRY(dalloc(&w.z32, np));
-    AMP_TRY(dalloc(&w.p32, np)); AMP_TRY(dalloc(&w.q32, np));
-    AMP_TRY(dalloc(&w.z16, np)); AMP_TRY(dalloc(&w.p16, np));
-    AMP_TRY(dalloc(&w.part, 2 * GMAX)); AMP_TRY(dalloc(&w.ctrl, 1));
-    AMP_HIP(hipHostMalloc((void **)&w.snap, 2 * sizeof(Ctrl), hipHostMallocDefault));
+    AMP_TRY(dalloc(&w.r64, np)); AMP_TRY(dalloc(&w.z64, np)); AMP_TRY(dalloc(&w.q64, np));
+    AMP_TRY(dalloc(&w.r32, np)); AMP_TRY(dalloc(&w.z32, np)); AMP_TRY(dalloc(&w.q32, np));
+    AMP_TRY(dalloc(&w.z16, np));
+    for (int i = 0; i < 2; ++i) {
+        AMP_TRY(dalloc(&w.p64[i], np)); AMP_TRY(dalloc(&w.p32[i], np)); AMP_TRY(dalloc(&w.p16[i], np));
+    }
+    AMP_TRY(dalloc(&w.part, 7 * GMAX)); AMP_TRY(dalloc(&w.ring, kRing));
+    AMP_TRY(dalloc(&w.scalar, 1)); AMP_TRY(dalloc(&w.st, ST_COUNT));
+    AMP_HIP(hipHostMalloc((void **)&w.snap, 2 * sizeof(St), hipHostMallocDefault));
     for (auto &e : w.ev) AMP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // zero every vector once: the padding tail stays zero for the handle's life
     AMP_HIP(hipMemsetAsync(w.x, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.b, 0, np * 8, st));
     AMP_HIP(hipMemsetAsync(w.r64, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.z64, 0, np * 8, st));
-    AMP_HIP(hipMemsetAsync(w.p64, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.q64, 0, np * 8, st));
+    AMP_HIP(hipMemsetAsync(w.q64, 0, np * 8, st));
     AMP_HIP(hipMemsetAsync(w.r32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.z32, 0, np * 4, st));
-    AMP_HIP(hipMemsetAsync(w.p32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.q32, 0, np * 4, st));
-    AMP_HIP(hipMemsetAsync(w.z16, 0, np * 2, st)); AMP_HIP(hipMemsetAsync(w.p16, 0, np * 2, st));
-    AMP_HIP(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
+    AMP_HIP(hipMemsetAsync(w.q32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.z16, 0, np * 2, st));
+    for (int i = 0; i < 2; ++i) {
+        AMP_HIP(hipMemsetAsync(w.p64[i], 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.p32[i], 0, np * 4, st));
+        AMP_HIP(hipMemsetAsync(w.p16[i], 0, np * 2, st));
+    }
+    AMP_HIP(hipMemsetAsync(w.part, 0, 7 * GMAX * sizeof(double), st));
+    AMP_HIP(hipMemsetAsync(w.ring, 0, kRing * sizeof(double), st));
+    AMP_HIP(hipMemsetAsync(w.st, 0, ST_COUNT * sizeof(St), st));
     AMP_HIP(hipStreamSynchronize(st));
-    A->bytes += np * (8 * 6 + 4 * 4 + 2 * 2);
+    A->bytes += np * (8 * 5 + 4 * 3 + 2 + 2 * (8 + 4 + 2));
     return AMP_OK;
 }
 
@@ -158,12 +175,14 @@ static Bufs make_bufs(amp_matrix A, amp_precond M) {
     B.x = w.x; B.b = w.b;
     B.r[0] = w.r64; B.r[1] = w.r32; B.r[2] = nullptr;
     B.z[0] = w.z64; B.z[1] = w.z32; B.z[2] = w.z16;
-    B.p[0] = w.p64; B.p[1] = w.p32; B.p[2] = w.p16;
     B.q[0] = w.q64; B.q[1] = w.q32; B.q[2] = nullptr;
+    for (int i = 0; i < 2; ++i) { B.p[0][i] = w.p64[i]; B.p[1][i] = w.p32[i]; B.p[2][i] = w.p16[i]; }
     B.dinv[0] = M ? M->d64 : nullptr;
     B.dinv[1] = M ? M->d32 : nullptr;
     B.dinv[2] = M ? M->d16 : nullptr;
-    B.part = w.part;
+    B.part_res = w.part;
+    B.part_pre = w.part + 3 * GMAX;
+    B.part_spmv = w.part + 5 * GMAX;
     return B;
 }
 
@@ -317,17 +336,17 @@ extern "C" amp_status amp_matrix_info(amp_matrix A, int64_t *n, int64_t *nnz, in
 // preconditioner
 // ----------------------------------------------------------------------------
 
-__global__ void k_jacobi_setup(const double *diag, int64_t n, int64_t np, double *d64, float *d32,
-                               unsigned long long *maxbits) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(NT) k_jacobi_setup(const double *diag, int64_t n, int64_t np, double *d64,
+                                                     float *d32, double *part) {
     double m = 0.0;
-    if (i < np) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < np; i += (int64_t)gridDim.x * NT) {
         const double v = (i < n) ? 1.0 / diag[i] : 0.0;
         d64[i] = v;
         d32[i] = (float)v;
-        m = v;
+        m = fmax(m, v);
     }
-    block_max_to(maxbits, m);
+    m = block_max(m);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
 __global__ void k_identity_setup(int64_t n, int64_t np, double *d64, float *d32, half_t *d16) {
@@ -369,20 +388,16 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         M->extra16 = 0;
         if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
     } else {
-        unsigned long long *mb = nullptr;
-        if ((s = dalloc(&mb, 1)) != AMP_OK) return bail(s);
-        if (hipMemsetAsync(mb, 0, sizeof(unsigned long long), st) != hipSuccess) {
-            dfree(mb);
-            return bail(fail(AMP_ERR_HIP, "amp_precond_create: memset failed"));
-        }
-        k_jacobi_setup<<<g, 256, 0, st>>>(A->diag, A->n, A->np, M->d64, M->d32, mb);
-        unsigned long long hb = 0;
-        hipError_t e1 = hipMemcpyAsync(&hb, mb, sizeof(hb), hipMemcpyDeviceToHost, st);
+        double *part = nullptr;
+        if ((s = dalloc(&part, GMAX + 1)) != AMP_OK) return bail(s);
+        const int G = fit_grid((A->np + NT - 1) / NT);
+        k_jacobi_setup<<<G, NT, 0, st>>>(A->diag, A->n, A->np, M->d64, M->d32, part);
+        k_reduce_to<<<1, NT, 0, st>>>(part, G, 1, part + GMAX);
+        double dmax = 0.0;
+        hipError_t e1 = hipMemcpyAsync(&dmax, part + GMAX, sizeof(double), hipMemcpyDeviceToHost, st);
         hipError_t e2 = hipStreamSynchronize(st);
-        dfree(mb);
+        dfree(part);
         if (e1 != hipSuccess || e2 != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
-        double dmax;
-        std::memcpy(&dmax, &hb, sizeof(dmax));
         if (!(dmax > 0.0) || !std::isfinite(dmax)) return bail(fail(AMP_ERR_ARG, "amp_precond_create: bad diagonal"));
         M->gain = dmax;
         M->extra16 = -ceil_log2(dmax);   // max of the FP16 copy lies in (1/2, 1]
@@ -453,7 +468,8 @@ static amp_status check_options(const amp_options &o) {
     return AMP_OK;
 }
 
-static void init_ctrl(Ctrl &c, const amp_options &o, amp_precond M, double tol, int maxit) {
+static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double tol, int maxit) {
+    Cfg c;
     std::memset(&c, 0, sizeof(c));
     c.u0 = o.u0;
     c.eta_mode = o.eta_mode;
@@ -463,55 +479,75 @@ static void init_ctrl(Ctrl &c, const amp_options &o, amp_precond M, double tol, 
     c.T_z = o.T_z;
     c.T_p = o.T_p;
     c.maxit = maxit;
-    c.rr_period = o.rr_period;
     c.verify = o.verify;
     c.max_repl = o.max_replacements;
     c.chebyshev = (M && M->kind == AMP_PC_CHEBYSHEV) ? 1 : 0;
+    c.diff = o.spmv32_diff ? 1 : 0;
+    c.rr_period = o.rr_period;
+    c.extra16 = M ? M->extra16 : 0;
+    c.g_stream = A ? grid_stream(A->np) : 1;
+    c.g_slice = A ? grid_slices(A->nslices) : 1;
     c.C = o.C;
     c.tau_zs = o.tau_zs;
     c.tau_zh = o.tau_zh;
     c.tol = tol;
     c.gain = M ? M->gain : 1.0;
-    c.extra16 = M ? M->extra16 : 0;
-    c.status = RUNNING;
-    c.uz = o.u0;
-    c.ur = 64;
-    c.r_store = 64;
-    c.p_store = o.u0;
-    c.k_z32 = c.k_z16 = c.k_r32 = -1;
+    c.ring = A ? A->w.ring : nullptr;
     c.delta_history = o.delta_history;
     c.prec_history = o.prec_history;
+    return c;
+}
+
+static St init_state(const amp_options &o) {
+    St s;
+    std::memset(&s, 0, sizeof(s));
+    s.status = RUNNING;
+    s.kind = RES_INIT;
+    s.uz = o.u0;
+    s.ur = 64;
+    s.r_store = 64;
+    s.p_store = o.u0;
+    s.pbuf = 0;
+    s.k_z32 = s.k_z16 = s.k_r32 = -1;
+    return s;
 }
 
 // ----------------------------------------------------------------------------
 // solve
 // ----------------------------------------------------------------------------
 
-static amp_status enqueue_iterations(amp_matrix A, const Bufs &B, const amp_options &o, int count,
-                                     hipStream_t st) {
-    Ctrl *c = A->w.ctrl;
-    const Sell S = A->sell();
-    const int gs = grid_stream(A->np), gl = grid_slices(A->nslices);
+struct Driver {
+    amp_matrix A;
+    Cfg cfg;
+    Sell S;
+    Bufs B;
+    int gs, gl;
+    hipStream_t st;
+    St *in;            // state the next kernel reads
+    int host_k;        // iterations enqueued since the last resynchronisation
+};
+
+static amp_status enqueue_iterations(Driver &d, int count) {
+    Work &w = d.A->w;
     for (int i = 0; i < count; ++i) {
-        k_precond<<<gs, NT, 0, st>>>(B, A->np, c);
-        k_pupdate<<<gs, NT, 0, st>>>(B, A->np, c);
-        k_spmv<<<gl, NT, 0, st>>>(S, B, o.spmv32_diff, c);
-        k_update<<<gs, NT, 0, st>>>(B, A->np, c);
-        if (o.rr_period > 0) k_true_res<<<gl, NT, 0, st>>>(S, B, 1, c);
+        k_precond<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, d.in, &w.st[ST_PRE]);
+        k_spmv<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, &w.st[ST_PRE], &w.st[ST_SPMV]);
+        k_update<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, &w.st[ST_SPMV], &w.st[ST_RES]);
+        d.in = &w.st[ST_RES];
+        d.host_k += 1;
+        if (d.cfg.rr_period > 0 && d.host_k % d.cfg.rr_period == 0) {
+            k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &w.st[ST_TR]);
+            d.in = &w.st[ST_TR];
+        }
     }
     AMP_HIP(hipGetLastError());
     return AMP_OK;
 }
 
-static amp_status snapshot(amp_matrix A, int slot, hipStream_t st) {
-    Work &w = A->w;
-    AMP_HIP(hipMemcpyAsync(&w.snap[slot], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    AMP_HIP(hipEventRecord(w.ev[slot], st));
-    return AMP_OK;
-}
-
-static amp_status wait_snapshot(amp_matrix A, int slot) {
-    AMP_HIP(hipEventSynchronize(A->w.ev[slot]));
+static amp_status snapshot(Driver &d, int slot) {
+    Work &w = d.A->w;
+    AMP_HIP(hipMemcpyAsync(&w.snap[slot], d.in, sizeof(St), hipMemcpyDeviceToHost, d.st));
+    AMP_HIP(hipEventRecord(w.ev[slot], d.st));
     return AMP_OK;
 }
 
@@ -527,86 +563,87 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     if (opt) o = *opt;
     else amp_options_default(&o);
     AMP_TRY(check_options(o));
-    hipStream_t st = as_stream(stream);
-    AMP_TRY(ensure_work(A, st));
+    Driver d;
+    d.A = A;
+    d.st = as_stream(stream);
+    AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
     const int64_t n = A->n;
-    const Sell S = A->sell();
-    const Bufs B = make_bufs(A, M);
-    const int gl = grid_slices(A->nslices);
+    d.cfg = make_cfg(o, A, M, tol, maxit);
+    d.S = A->sell();
+    d.B = make_bufs(A, M);
+    d.gs = d.cfg.g_stream;
+    d.gl = d.cfg.g_slice;
+    d.host_k = 0;
 
-    Ctrl hc;
-    init_ctrl(hc, o, M, tol, maxit);
-    AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    AMP_HIP(hipMemcpyAsync(w.ctrl, &hc, sizeof(Ctrl), hipMemcpyHostToDevice, st));
-    k_init<<<gl, NT, 0, st>>>(S, B, w.ctrl);
+    const St s0 = init_state(o);
+    AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    AMP_HIP(hipMemcpyAsync(&w.st[ST_INIT], &s0, sizeof(St), hipMemcpyHostToDevice, d.st));
+    k_init<<<d.gl, NT, 0, d.st>>>(d.S, d.B);
     AMP_HIP(hipGetLastError());
-    AMP_TRY(snapshot(A, 0, st));
-    AMP_TRY(wait_snapshot(A, 0));
-    Ctrl cur = w.snap[0];
+    d.in = &w.st[ST_INIT];
 
-    // Pipelined batches: batch j+1 is enqueued before batch j's status is read;
-    // kernels return at once when the status is no longer RUNNING.
-    int batch = o.batch > 0 ? o.batch : 8;
-    int pending = -1;              // snapshot slot of the batch in flight, if any
+    // Pipelined batches: batch j+1 is enqueued before batch j's state is
+    // read; once the state leaves RUNNING every further kernel returns at once.
+    int batch = o.batch > 0 ? o.batch : 4;
+    int pending = -1;              // snapshot slot of the batch in flight
     int last_iters = 0;
-    double last_delta = cur.delta;
+    double last_delta = -1.0;
+    St cur = s0;
     for (;;) {
-        if (cur.status == NEED_VERIFY) {
-            if (pending >= 0) { AMP_TRY(wait_snapshot(A, pending)); pending = -1; }
-            k_true_res<<<gl, NT, 0, st>>>(S, B, 0, w.ctrl);
-            AMP_HIP(hipGetLastError());
-            AMP_TRY(snapshot(A, 0, st));
-            AMP_TRY(wait_snapshot(A, 0));
-            cur = w.snap[0];
-            continue;
-        }
-        if (cur.status != RUNNING) break;
         const int sl = (pending >= 0) ? (pending ^ 1) : 0;
-        AMP_TRY(enqueue_iterations(A, B, o, batch, st));
-        AMP_TRY(snapshot(A, sl, st));
-        if (pending < 0) {         // fill the pipeline first
+        AMP_TRY(enqueue_iterations(d, batch));
+        AMP_TRY(snapshot(d, sl));
+        if (pending < 0) {
             pending = sl;
             continue;
         }
-        AMP_TRY(wait_snapshot(A, pending));
+        AMP_HIP(hipEventSynchronize(w.ev[pending]));
         cur = w.snap[pending];
         pending = sl;
-        if (o.batch == 0 && cur.status == RUNNING && cur.iters > last_iters && cur.delta > 0.0 &&
-            last_delta > 0.0) {
-            // size the next batch from the observed rate of decrease
-            const double rate = std::pow(cur.delta / last_delta, 1.0 / (double)(cur.iters - last_iters));
-            int left = 256;
-            if (rate > 0.0 && rate < 1.0)
-                left = (int)std::ceil(std::log(hc.tol * cur.bnorm / cur.delta) / std::log(rate));
-            batch = std::max(4, std::min(256, left / 2 + 1));
-            last_iters = cur.iters;
-            last_delta = cur.delta;
+        if (cur.status == RUNNING) {
+            if (o.batch == 0 && cur.iters > last_iters && cur.delta > 0.0 && last_delta > 0.0) {
+                // size the next batch from the observed rate of decrease
+                const double rate = std::pow(cur.delta / last_delta, 1.0 / (double)(cur.iters - last_iters));
+                int left = 256;
+                if (rate > 0.0 && rate < 1.0)
+                    left = (int)std::ceil(std::log(tol * cur.bnorm / cur.delta) / std::log(rate));
+                batch = std::max(4, std::min(256, left / 2 + 1));
+            }
+            if (cur.iters > last_iters) {
+                last_iters = cur.iters;
+                last_delta = cur.delta;
+            }
+            continue;
         }
+        // the state left RUNNING: drain the pipeline and read the final state
+        AMP_HIP(hipEventSynchronize(w.ev[pending]));
+        cur = w.snap[pending];
+        pending = -1;
+        if (cur.status == NEED_VERIFY) {
+            k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
+            AMP_HIP(hipGetLastError());
+            d.in = &w.st[ST_TR];
+            d.host_k = cur.iters;
+            batch = 4;
+            continue;
+        }
+        break;
     }
-    if (pending >= 0) AMP_TRY(wait_snapshot(A, pending));
-    // the last snapshot may predate the final kernels of the pipeline; read the final state
-    AMP_HIP(hipMemcpyAsync(&w.snap[0], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    AMP_HIP(hipStreamSynchronize(st));
-    cur = w.snap[0];
-    AMP_HIP(hipMemcpyAsync(x, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // FP64 true residual of the returned x (writes nothing but the reduction)
+    AMP_HIP(hipMemcpyAsync(x, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    // FP64 true residual of the returned x, unless the termination check just formed it
     double true_res = cur.true_res;
     if (!(o.verify && cur.status == CONVERGED)) {
-        Ctrl tmp = cur;
-        tmp.status = NEED_VERIFY;
-        tmp.n_repl = tmp.max_repl;      // report only: never replaces
-        tmp.counter = 0;
-        AMP_HIP(hipMemcpyAsync(w.ctrl, &tmp, sizeof(Ctrl), hipMemcpyHostToDevice, st));
-        // k_true_res overwrites r with b - A x; harmless after the solve
-        k_true_res<<<gl, NT, 0, st>>>(S, B, 0, w.ctrl);
+        k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
+        k_reduce_to<<<1, NT, 0, d.st>>>(d.B.part_res, d.gl, 0, w.scalar);
         AMP_HIP(hipGetLastError());
-        AMP_HIP(hipMemcpyAsync(&w.snap[1], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        AMP_HIP(hipStreamSynchronize(st));
-        true_res = w.snap[1].true_res;
+        double t2 = 0.0;
+        AMP_HIP(hipMemcpyAsync(&t2, w.scalar, sizeof(double), hipMemcpyDeviceToHost, d.st));
+        AMP_HIP(hipStreamSynchronize(d.st));
+        true_res = std::sqrt(t2);
     }
-    AMP_HIP(hipStreamSynchronize(st));
+    AMP_HIP(hipStreamSynchronize(d.st));
 
     amp_status rs = AMP_OK;
     if (cur.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
@@ -632,6 +669,35 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
 // single-kernel entry points (tests, measurement)
 // ----------------------------------------------------------------------------
 
+template <int UZ, int UR, bool DF>
+static void launch_spmv_fixed(const Sell &S, int gl, const void *z, const void *po, void *pn, void *q, int first,
+                              double beta, double *part, hipStream_t st) {
+    k_spmv_fixed<UZ, UR, DF><<<gl, NT, 0, st>>>(S, z, po, pn, q, first, beta, part);
+}
+
+static amp_status dispatch_spmv(amp_matrix A, int u_r, int u_z, int diff, const void *z, const void *po, void *pn,
+                                void *q, int first, double beta, double *part, hipStream_t st) {
+    const Sell S = A->sell();
+    const int gl = grid_slices(A->nslices);
+#define AMP_L(UZ, UR, DF) launch_spmv_fixed<UZ, UR, DF>(S, gl, z, po, pn, q, first, beta, part, st)
+    if (u_r == 64) {
+        if (u_z == 64) AMP_L(64, 64, false);
+        else if (u_z == 32) AMP_L(32, 64, false);
+        else AMP_L(16, 64, false);
+    } else if (diff) {
+        if (u_z == 64) AMP_L(64, 32, true);
+        else if (u_z == 32) AMP_L(32, 32, true);
+        else AMP_L(16, 32, true);
+    } else {
+        if (u_z == 64) AMP_L(64, 32, false);
+        else if (u_z == 32) AMP_L(32, 32, false);
+        else AMP_L(16, 32, false);
+    }
+#undef AMP_L
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+
 extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,
                                void *stream) {
     if (!A) return fail(AMP_ERR_ARG, "amp_spmv: null matrix");
@@ -641,28 +707,28 @@ extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const v
     Work &w = A->w;
     Bufs B = make_bufs(A, nullptr);
     const int64_t n = A->n;
-    if (p) AMP_HIP(hipMemcpyAsync(B.p[pslot(u_p)], p, n * (u_p / 8), hipMemcpyDeviceToDevice, st));
-    const Sell S = A->sell();
-    const int gl = grid_slices(A->nslices);
-    Ctrl *c = w.ctrl;
-#define AMP_SPMV_LAUNCH(UP, UR, DF) k_spmv_fixed<UP, UR, DF><<<gl, NT, 0, st>>>(S, B, gamma, c)
-    if (u_r == 64) {
-        if (u_p == 64) AMP_SPMV_LAUNCH(64, 64, false);
-        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 64, false);
-        else AMP_SPMV_LAUNCH(16, 64, false);
-    } else if (diff) {
-        if (u_p == 64) AMP_SPMV_LAUNCH(64, 32, true);
-        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 32, true);
-        else AMP_SPMV_LAUNCH(16, 32, true);
-    } else {
-        if (u_p == 64) AMP_SPMV_LAUNCH(64, 32, false);
-        else if (u_p == 32) AMP_SPMV_LAUNCH(32, 32, false);
-        else AMP_SPMV_LAUNCH(16, 32, false);
+    // the product reads p from the handle's z buffer of precision u_p
+    if (p) AMP_HIP(hipMemcpyAsync(B.z[pslot(u_p)], p, n * (u_p / 8), hipMemcpyDeviceToDevice, st));
+    AMP_TRY(dispatch_spmv(A, u_r, u_p, diff, B.z[pslot(u_p)], nullptr, nullptr, B.q[pslot(u_r)], 1, 0.0,
+                          gamma ? B.part_spmv : nullptr, st));
+    if (gamma) {
+        k_reduce_to<<<1, NT, 0, st>>>(B.part_spmv, grid_slices(A->nslices), 0, gamma);
+        AMP_HIP(hipGetLastError());
     }
-#undef AMP_SPMV_LAUNCH
-    AMP_HIP(hipGetLastError());
     if (q) AMP_HIP(hipMemcpyAsync(q, B.q[pslot(u_r)], n * (u_r / 8), hipMemcpyDeviceToDevice, st));
+    (void)w;
     return AMP_OK;
+}
+
+extern "C" amp_status amp_spmv_step(amp_matrix A, int u_z, int u_r, int diff, double beta, void *stream) {
+    if (!A) return fail(AMP_ERR_ARG, "amp_spmv_step: null matrix");
+    if ((u_r != 64 && u_r != 32) || !valid_prec(u_z)) return fail(AMP_ERR_ARG, "amp_spmv_step: bad precision");
+    hipStream_t st = as_stream(stream);
+    AMP_TRY(ensure_work(A, st));
+    Bufs B = make_bufs(A, nullptr);
+    const int ps = pslot(u_z);
+    return dispatch_spmv(A, u_r, u_z, diff, B.z[ps], B.p[ps][0], B.p[ps][1], B.q[pslot(u_r)], 0, beta,
+                         B.part_spmv, st);
 }
 
 extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const void *r, double omega, void *z,
@@ -673,14 +739,12 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
     amp_matrix A = M->A;
     hipStream_t st = as_stream(stream);
     AMP_TRY(ensure_work(A, st));
-    Work &w = A->w;
     Bufs B = make_bufs(A, M);
     const int64_t n = A->n;
     AMP_HIP(hipMemcpyAsync(B.r[pslot(u_r)], r, n * (u_r / 8), hipMemcpyDeviceToDevice, st));
-    AMP_HIP(hipMemsetAsync(&w.ctrl->counter, 0, sizeof(unsigned int), st));
     const double oe = std::ldexp(omega, -(u_z == 16 ? M->extra16 : 0));
     const int gs = grid_stream(A->np);
-#define AMP_PC_LAUNCH(UR, UZ) k_precond_fixed<UR, UZ><<<gs, NT, 0, st>>>(B, A->np, oe, rho, w.ctrl)
+#define AMP_PC_LAUNCH(UR, UZ) k_precond_fixed<UR, UZ><<<gs, NT, 0, st>>>(B, A->np, oe, B.part_pre)
     if (u_r == 64) {
         if (u_z == 64) AMP_PC_LAUNCH(64, 64);
         else if (u_z == 32) AMP_PC_LAUNCH(64, 32);
@@ -691,6 +755,7 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
         else AMP_PC_LAUNCH(32, 16);
     }
 #undef AMP_PC_LAUNCH
+    if (rho) k_reduce_to<<<1, NT, 0, st>>>(B.part_pre, gs, 0, rho);
     AMP_HIP(hipGetLastError());
     AMP_HIP(hipMemcpyAsync(z, B.z[pslot(u_z)], n * (u_z / 8), hipMemcpyDeviceToDevice, st));
     return AMP_OK;
@@ -710,19 +775,20 @@ extern "C" amp_status amp_selector_replay(const double *delta, int len, double b
     AMP_TRY(check_options(o));
     o.delta_history = nullptr;
     o.prec_history = nullptr;
-    Ctrl c;
-    init_ctrl(c, o, nullptr, tol, len);
-    c.bnorm = bnorm;
-    c.tol_b = tol * bnorm;
+    Cfg c = make_cfg(o, nullptr, nullptr, tol, len);
+    std::vector<double> ring(kRing, 0.0);
+    St s = init_state(o);
+    s.bnorm = bnorm;
+    s.tol_b = tol * bnorm;
     for (int k = 0; k < len; ++k) {
-        c.ring[k % kRing] = delta[k];
-        c.delta = delta[k];
-        c.maxr = 1.0;
-        prepare_iteration(c, k);
+        s.delta = delta[k];
+        s.maxr = 1.0;
+        prepare_iteration(s, c, ring.data(), k);
+        ring[k % kRing] = delta[k];
     }
-    if (k_z32) *k_z32 = c.k_z32;
-    if (k_z16) *k_z16 = c.k_z16;
-    if (k_r32) *k_r32 = c.k_r32;
+    if (k_z32) *k_z32 = s.k_z32;
+    if (k_z16) *k_z16 = s.k_z16;
+    if (k_r32) *k_r32 = s.k_r32;
     return AMP_OK;
 }
 

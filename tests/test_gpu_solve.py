@@ -112,6 +112,12 @@ def test_amp_matches_model(amp, case, preset, kw):
     ref = am.amp_pcg(S, b, tol=1e-10, maxit=5000, opt=am.options(preset, **kw))
     x, info = _gpu_solve(amp, A, b, preset, **kw)
     assert info["status"] == 0 and ref.status == 0
+    gd, md = np.asarray(info["delta"]), np.asarray(ref.delta)
+    m = min(len(gd), len(md))
+    rel = np.abs(gd[:m] - md[:m]) / md[:m]
+    bad = np.nonzero(rel > 1e-3)[0]
+    _say(f"  gpu iters {info['iters']} model {ref.iters}; first |delta| divergence > 1e-3 at "
+         f"{bad[0] if bad.size else None}; early rel diffs {np.array2string(rel[:12], precision=1)}")
     # the GPU's own history through the oracle's selector reproduces its switch points
     kz32, kz16, kr = am.replay_switches(list(info["delta"][:info["iters"]]), info["bnorm"], 1e-10,
                                         am.options(preset, **kw))
