@@ -211,6 +211,46 @@ amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const void *r, dou
                              double *rho, void *stream);
 
 /*
+ * Refill the handle's values from a CSR matrix with the same sizes (n, nnz)
+ * and row lengths -- typically the same pattern with new values (a
+ * differentiable solve updating A(theta)).  Device pointers as in
+ * amp_matrix_create; host-synchronous.  Preconditioners built on the handle
+ * must then be refreshed with amp_precond_update.  Errors: AMP_ERR_ARG for
+ * null pointers, other sizes or row lengths, a bad column or diagonal.
+ */
+amp_status amp_matrix_update_values(amp_matrix A, const amp_csr *csr, void *stream);
+/* Recompute a preconditioner's data from its matrix's current values
+ * (host-synchronous). */
+amp_status amp_precond_update(amp_precond M, void *stream);
+
+/*
+ * Cell-centred finite-volume diffusion operator on a dim-dimensional box
+ * grid (dim = 2: nx x ny, nz ignored; dim = 3: nx x ny x nz), cells ordered
+ * x fastest, cell coefficient kappa = exp(theta): an interior face between
+ * cells i and j has T = 2 kappa_i kappa_j / (kappa_i + kappa_j), a face on
+ * the Dirichlet boundary T = 2 kappa_i; A_ii = sum of the cell's T,
+ * A_ij = -T_ij.  amp_fv_nnz (host-only) gives nnz; amp_fv_csr writes the CSR
+ * (row_ptr[n+1], col_idx[nnz] sorted, val[nnz]; device arrays owned by the
+ * caller) from theta (device FP32[n]).  Host-synchronous.
+ * Errors: AMP_ERR_ARG for dim not 2 or 3, non-positive sizes, null pointers
+ * or a grid whose nnz would not fit int32.
+ */
+amp_status amp_fv_nnz(int dim, int nx, int ny, int nz, int64_t *nnz);
+amp_status amp_fv_csr(int dim, int nx, int ny, int nz, const float *theta, int32_t *row_ptr,
+                      int32_t *col_idx, double *val, void *stream);
+/*
+ * Gradient of a loss L(x) through x = A(theta)^{-1} b, given x and the
+ * adjoint lambda = A^{-1} dL/dx (A symmetric): dtheta_i = sum over the
+ * faces of cell i of dL/dT * dT/dtheta_i with dL/dT_ij = -(lambda_i -
+ * lambda_j)(x_i - x_j), dT_ij/dtheta_i = 2 kappa_i kappa_j^2 / (kappa_i +
+ * kappa_j)^2, and for a boundary face dL/dT = -lambda_i x_i, dT/dtheta_i =
+ * 2 kappa_i.  FP64 accumulation, FP32 result dtheta[n] (device).  Enqueued
+ * on stream, not synchronised.
+ */
+amp_status amp_fv_grad_theta(int dim, int nx, int ny, int nz, const float *theta, const double *x,
+                             const double *lambda, float *dtheta, void *stream);
+
+/*
  * Host-only: run the device controller's latched precision selector over a
  * recorded residual-norm history delta[0..len-1] (eq. precision_selector
  * with eq. eta_k or eq. linear criterion) and report the first iteration at

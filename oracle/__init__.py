@@ -15,3 +15,4 @@ the GPU solver (``paper_2505_04155_amd``) and never imports it.
 
 from . import cpcg  # noqa: F401
 from . import amp_model  # noqa: F401
+from . import adjoint  # noqa: F401

@@ -24,6 +24,7 @@ EXPORTED = [
     "amp_options_preset", "amp_matrix_create", "amp_matrix_destroy", "amp_matrix_info",
     "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv", "amp_spmv_step",
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
+    "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
 ]
 
 
@@ -99,6 +100,11 @@ def load(build_if_missing: bool = True):
         L.amp_selector_replay.argtypes = [ctypes.POINTER(dbl), i32, dbl, dbl, ctypes.POINTER(Options),
                                           ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.amp_paper_kernel_bytes.argtypes = [i32, i32, ctypes.POINTER(dbl)]
+        L.amp_matrix_update_values.argtypes = [vp, ctypes.POINTER(Csr), vp]
+        L.amp_precond_update.argtypes = [vp, vp]
+        L.amp_fv_nnz.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64)]
+        L.amp_fv_csr.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.amp_fv_grad_theta.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
         for name in EXPORTED:
             if not hasattr(L, name):
                 raise RuntimeError(f"{path} does not export {name}")

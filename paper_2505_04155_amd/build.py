@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libamppcg.so")
 SOURCES = ["amp_pcg.hip"]
-HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp"]
+HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp", "amp_cheb.hpp", "amp_fv.hpp"]
 
 
 def hipcc() -> str:

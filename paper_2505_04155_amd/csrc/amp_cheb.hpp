@@ -1,0 +1,270 @@
+// Chebyshev polynomial preconditioner: z = D^{-1/2} s(B) D^{-1/2} y with
+// B = D^{-1/2} A D^{-1/2} stored in FP16 on A's sliced-ELL pattern, s the
+// degree-(m-1) polynomial whose residual polynomial 1 - t s(t) is the scaled
+// Chebyshev polynomial T_m((theta - t)/delta) / T_m(theta/delta) on
+// [lam_lo, lam_hi], evaluated by the three-term Chebyshev iteration for
+// B w = v from w = 0:
+//   res_0 = v, dir_0 = v / theta, w_0 = 0;  for k = 0..m-2:
+//   w_{k+1} = w_k + dir_k,  res_{k+1} = res_k - B dir_k,
+//   dir_{k+1} = c1_k dir_k + c2_k res_{k+1};   w_m = w_{m-1} + dir_{m-1}.
+// Work vectors are held in the arithmetic precision of u_z (FP64, or FP32
+// for u_z = FP32 / FP16); B products accumulate in that precision; z is
+// rounded to u_z.  One streaming kernel forms v, then m-1 product kernels
+// each take one step; the last one also forms z and the partials of rho.
+#pragma once
+
+#include "amp_kernels.hpp"
+
+namespace amp {
+
+constexpr int kChebMax = 16;
+
+struct Cheb {
+    const int64_t *sptr;
+    const int32_t *col;
+    const half_t *b16;       // B's values in FP16
+    const double *isq64;     // D^{-1/2}
+    const float *isq32;
+    void *v, *res, *w;       // work vectors (np doubles each, read as float for FP32)
+    void *dir[2];
+    int64_t np, nslices;
+    int degree;
+    double inv_theta;
+    double c1[kChebMax], c2[kChebMax];
+};
+
+// y = fl_uz(fl_ur(omega r)); v = isq (.) y in the work precision C.
+template <int RS, int UR, int UZ>
+__device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Cheb &P) {
+    typedef typename Prec<RS>::T TRS;
+    typedef typename Prec<UR>::T TR;
+    typedef typename Prec<UZ>::T TZ;
+    typedef typename Prec<UZ>::C CZ;
+    const TRS *r = (const TRS *)B.r[pslot(RS)];
+    TR *rn = (TR *)B.r[pslot(UR)];
+    CZ *v = (CZ *)P.v;
+    const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
+    const TR w = (TR)s.omega_eff;
+    AMP_STREAM_LOOP(i, P.np) {
+        const V4<TRS> rv = ld4(r, i);
+        const V4<CZ> iv = ld4(isq, i);
+        V4<CZ> vv;
+        V4<TR> rr;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const TR re = (TR)rv.v[e];
+            rr.v[e] = re;
+            const TZ y = (TZ)(re * w);
+            vv.v[e] = iv.v[e] * (CZ)y;
+        }
+        st4(v, i, vv);
+        if (RS != UR) st4(rn, i, rr);
+    }
+}
+
+// First kernel of a Chebyshev application inside the iteration: controller
+// prologue (like k_precond), then v.  standalone != 0 skips the prologue and
+// uses the incoming state's precisions and omega as given.
+__global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int standalone, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    if (!standalone) {
+        consume_residual(s, c, B);
+        __syncthreads();
+        if (s.status != RUNNING) {
+            store_state(s, out);
+            return;
+        }
+    }
+    const int rs = s.r_store, ur = s.ur, uz = s.uz;
+#define AMP_CV(RS, UR, UZ) cheb_v_body<RS, UR, UZ>(s, B, P)
+#define AMP_CV_Z(RS, UR)                  \
+    if (uz == 64) AMP_CV(RS, UR, 64);       \
+    else if (uz == 32) AMP_CV(RS, UR, 32);  \
+    else AMP_CV(RS, UR, 16);
+    if (rs == 64 && ur == 64) { AMP_CV_Z(64, 64) }
+    else if (rs == 64) { AMP_CV_Z(64, 32) }
+    else { AMP_CV_Z(32, 32) }
+#undef AMP_CV_Z
+#undef AMP_CV
+    const bool conv = (s.k > 0 && s.p_store != uz);
+    if (conv) {
+        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, P.np);
+        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, P.np);
+        else convert_p<32, 16>(B, s.pbuf, P.np);
+    }
+    if (threadIdx.x == 0) {
+        s.r_store = s.ur;
+        if (conv) s.p_store = uz;
+    }
+    store_state(s, out);
+}
+
+// One step k of the recurrence for this work-group's slices.
+template <int UZ>
+__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, int k, int first,
+                                               int last, int din, double &rho, double &mz) {
+    typedef typename Prec<UZ>::T TZ;
+    typedef typename Prec<UZ>::C CZ;
+    const CZ *v = (const CZ *)P.v;
+    CZ *res = (CZ *)P.res;
+    CZ *w = (CZ *)P.w;
+    const CZ *dk = (const CZ *)P.dir[din];
+    CZ *dn = (CZ *)P.dir[din ^ 1];
+    const CZ inv_theta = (CZ)P.inv_theta;
+    const CZ c1 = (CZ)P.c1[k], c2 = (CZ)P.c2[k];
+    const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
+    TZ *z = (TZ *)B.z[pslot(UZ)];
+    const int ur = s.ur;
+    auto dval = [&](int64_t j) -> CZ { return first ? v[j] * inv_theta : dk[j]; };
+    int64_t slo_, shi_;
+    block_range(P.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
+    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE) {
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = P.sptr[sl] + lane;
+        const int wd = (int)((P.sptr[sl + 1] - P.sptr[sl]) / SLICE);
+        CZ acc = (CZ)0;
+        int j = 0;
+        for (; j + 4 <= wd; j += 4) {
+            int32_t cc[4];
+            CZ bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cc[u] = P.col[base + (int64_t)(j + u) * SLICE];
+                bv[u] = (CZ)P.b16[base + (int64_t)(j + u) * SLICE];
+            }
+            CZ dj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dj[u] = dval(cc[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += bv[u] * dj[u];
+        }
+        for (; j < wd; ++j) {
+            const int64_t sidx = base + (int64_t)j * SLICE;
+            acc += (CZ)P.b16[sidx] * dval(P.col[sidx]);
+        }
+        const CZ d0 = dval(row);
+        const CZ wk = first ? (CZ)0 + d0 : w[row];
+        const CZ w1 = first ? wk : wk + d0;
+        const CZ rk = first ? v[row] : res[row];
+        const CZ r1 = rk - acc;
+        const CZ d1 = c1 * d0 + c2 * r1;
+        if (!last) {
+            w[row] = w1;
+            res[row] = r1;
+            dn[row] = d1;
+        } else {
+            const CZ wm = w1 + d1;
+            const TZ zz = (TZ)(isq[row] * wm);
+            z[row] = zz;
+            double rr;
+            if (ur == 64) rr = ((const double *)B.r[0])[row];
+            else rr = (double)((const float *)B.r[1])[row];
+            rho += rr * (double)zz;
+            mz = fmax(mz, fabs((double)zz));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_cheb_step(Bufs B, Cheb P, int k, int first, int last, int din,
+                                                  const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    double rho = 0.0, mz = 0.0;
+    if (s.uz == 64) cheb_step_body<64>(s, B, P, k, first, last, din, rho, mz);
+    else if (s.uz == 32) cheb_step_body<32>(s, B, P, k, first, last, din, rho, mz);
+    else cheb_step_body<16>(s, B, P, k, first, last, din, rho, mz);
+    if (last) {
+        rho = block_sum(rho);
+        mz = block_max(mz);
+        if (threadIdx.x == 0) {
+            B.part_pre[blockIdx.x] = rho;
+            B.part_pre[GMAX + blockIdx.x] = mz;
+        }
+    }
+    store_state(s, out);
+}
+
+// Degree 1: z = fl_uz(isq (.) (v / theta)), no product with B.
+template <int UZ>
+__device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const Cheb &P, double &rho,
+                                               double &mz) {
+    typedef typename Prec<UZ>::T TZ;
+    typedef typename Prec<UZ>::C CZ;
+    const CZ *v = (const CZ *)P.v;
+    const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
+    const CZ inv_theta = (CZ)P.inv_theta;
+    TZ *z = (TZ *)B.z[pslot(UZ)];
+    AMP_STREAM_LOOP(i, P.np) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const CZ d0 = v[i + e] * inv_theta;
+            const CZ wm = (CZ)0 + d0;
+            const TZ zz = (TZ)(isq[i + e] * wm);
+            z[i + e] = zz;
+            const double rr = (s.ur == 64) ? ((const double *)B.r[0])[i + e] : (double)((const float *)B.r[1])[i + e];
+            rho += rr * (double)zz;
+            mz = fmax(mz, fabs((double)zz));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_cheb_deg1(Bufs B, Cheb P, const St *in, St *out) {
+    __shared__ St s;
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out);
+        return;
+    }
+    double rho = 0.0, mz = 0.0;
+    if (s.uz == 64) cheb_deg1_body<64>(s, B, P, rho, mz);
+    else if (s.uz == 32) cheb_deg1_body<32>(s, B, P, rho, mz);
+    else cheb_deg1_body<16>(s, B, P, rho, mz);
+    rho = block_sum(rho);
+    mz = block_max(mz);
+    if (threadIdx.x == 0) {
+        B.part_pre[blockIdx.x] = rho;
+        B.part_pre[GMAX + blockIdx.x] = mz;
+    }
+    store_state(s, out);
+}
+
+// Setup: B's FP16 values on A's slots, b_ij = fl16((a_ij isq_i) isq_j);
+// isq = 1/sqrt(diag).  Partials of max isq for the scaling gain.
+__global__ void __launch_bounds__(NT) k_cheb_isq(const double *diag, int64_t n, int64_t np, double *isq64,
+                                                 float *isq32, double *part) {
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < np; i += (int64_t)gridDim.x * NT) {
+        const double v = (i < n) ? 1.0 / sqrt(diag[i]) : 0.0;
+        isq64[i] = v;
+        isq32[i] = (float)v;
+        m = fmax(m, v);
+    }
+    m = block_max(m);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64, half_t *b16) {
+    int64_t slo_, shi_;
+    block_range(A.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
+    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE) {
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
+        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+        const double si = isq64[row];
+        for (int j = 0; j < w; ++j) {
+            const int64_t sidx = base + (int64_t)j * SLICE;
+            b16[sidx] = (half_t)((A.v64[sidx] * si) * isq64[A.col[sidx]]);
+        }
+    }
+}
+
+}  // namespace amp

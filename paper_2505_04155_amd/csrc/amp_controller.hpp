@@ -31,6 +31,7 @@ struct Cfg {
     int u0, eta_mode, d, ell, scaling, T_z, T_p, maxit, verify, max_repl, chebyshev, diff;
     int rr_period, extra16;   // extra16: log2 of the FP16 preconditioner data's static scale
     int g_stream, g_slice;    // work-groups of the streaming / sliced-ELL kernels (= partial counts)
+    int g_pre;                // partials written by the preconditioning stage
     double C, tau_zs, tau_zh, tol, gain;
     double *ring;             // ||r_t|| for the last kRing iterations (device)
     double *delta_history;    // nullable
@@ -153,8 +154,7 @@ AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, in
 }
 
 // Consume the residual of the iteration just finished (iteration iters-1):
-// record it, test for convergence, and prepare the next iteration.  Returns
-// true when the caller must record delta in the ring at index s.iters.
+// test for convergence and prepare the next iteration.
 AMP_HD inline void finish_iteration(St &s, const Cfg &c, const double *ring, double delta_new,
                                     double maxr_new) {
     s.maxr_prev = s.maxr;

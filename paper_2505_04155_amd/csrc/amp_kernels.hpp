@@ -376,8 +376,8 @@ __global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in
         store_state(s, out);
         return;
     }
-    const double rho = reduce_sum(B.part_pre, c.g_stream);
-    const double mz = reduce_max(B.part_pre + GMAX, c.g_stream);
+    const double rho = reduce_sum(B.part_pre, c.g_pre);
+    const double mz = reduce_max(B.part_pre + GMAX, c.g_pre);
     if (threadIdx.x == 0) {
         s.rho_prev = s.rho;
         s.rho = rho;

@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include "amp_cheb.hpp"
+#include "amp_fv.hpp"
 #include "amp_kernels.hpp"
 #include "amp_pcg.h"
 
@@ -82,7 +84,10 @@ struct Work {
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-enum { ST_INIT = 0, ST_PRE = 1, ST_SPMV = 2, ST_RES = 3, ST_TR = 4, ST_REPORT = 5, ST_COUNT = 6 };
+enum {
+    ST_INIT = 0, ST_PRE = 1, ST_SPMV = 2, ST_RES = 3, ST_TR = 4, ST_REPORT = 5,
+    ST_PREI = 6, ST_CH0 = 7, ST_CH1 = 8, ST_COUNT = 9
+};
 
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0;
@@ -109,6 +114,20 @@ struct amp_precond_s {
     half_t *d16 = nullptr;
     int extra16 = 0;     // FP16 data = fl16(dinv 2^extra16)
     double gain = 1.0;   // max|M^{-1} r| <= gain max|r|
+    // Chebyshev
+    half_t *b16 = nullptr;
+    double *isq64 = nullptr;
+    float *isq32 = nullptr;
+    double *cv = nullptr, *cres = nullptr, *cw = nullptr, *cdir[2] = {nullptr, nullptr};
+    double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
+    Cheb cheb() const {
+        Cheb P;
+        P.sptr = A->sptr; P.col = A->col; P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
+        P.v = cv; P.res = cres; P.w = cw; P.dir[0] = cdir[0]; P.dir[1] = cdir[1];
+        P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
+        for (int i = 0; i < kChebMax; ++i) { P.c1[i] = c1[i]; P.c2[i] = c2[i]; }
+        return P;
+    }
 };
 
 // Work-group counts: enough for every unit of work, at most GMAX, and a
@@ -220,6 +239,10 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
     if (row < n) {
         beg = rp[row];
         len = rp[row + 1] - beg;
+        if (len > w) {             // only possible when refilling with another pattern
+            atomicOr(err, 4);
+            return;
+        }
         for (int j = 0; j < len; ++j) rs += val[beg + j];
     }
     for (int j = 0; j < w; ++j) {
@@ -364,53 +387,105 @@ __global__ void k_scale_to_half(const double *d64, int64_t np, double scale, hal
     if (i < np) d16[i] = (half_t)(d64[i] * scale);
 }
 
+// Values of the preconditioner that depend on A's entries (also rerun by
+// amp_precond_update after amp_matrix_update_values).
+static amp_status setup_values(amp_precond M, hipStream_t st) {
+    amp_matrix A = M->A;
+    const int64_t np = A->np;
+    const unsigned g = (unsigned)((np + 255) / 256);
+    if (M->kind == AMP_PC_IDENTITY) {
+        k_identity_setup<<<g, 256, 0, st>>>(A->n, np, M->d64, M->d32, M->d16);
+        M->gain = 1.0;
+        M->extra16 = 0;
+        AMP_HIP(hipStreamSynchronize(st));
+        return AMP_OK;
+    }
+    double *part = nullptr;
+    AMP_TRY(dalloc(&part, GMAX + 1));
+    const int G = fit_grid((np + NT - 1) / NT);
+    if (M->kind == AMP_PC_JACOBI) {
+        k_jacobi_setup<<<G, NT, 0, st>>>(A->diag, A->n, np, M->d64, M->d32, part);
+    } else {
+        k_cheb_isq<<<G, NT, 0, st>>>(A->diag, A->n, np, M->isq64, M->isq32, part);
+        k_cheb_values<<<grid_slices(A->nslices), NT, 0, st>>>(A->sell(), M->isq64, M->b16);
+    }
+    k_reduce_to<<<1, NT, 0, st>>>(part, G, 1, part + GMAX);
+    double mx = 0.0;
+    hipError_t e1 = hipMemcpyAsync(&mx, part + GMAX, sizeof(double), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    dfree(part);
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(AMP_ERR_HIP, "preconditioner setup failed");
+    if (!(mx > 0.0) || !std::isfinite(mx)) return fail(AMP_ERR_ARG, "preconditioner setup: bad diagonal");
+    if (M->kind == AMP_PC_JACOBI) {
+        M->gain = mx;
+        M->extra16 = -ceil_log2(mx);   // max of the FP16 copy lies in (1/2, 1]
+        k_scale_to_half<<<g, 256, 0, st>>>(M->d64, np, std::ldexp(1.0, M->extra16), M->d16);
+        AMP_HIP(hipStreamSynchronize(st));
+    } else {
+        M->gain = mx * mx / M->lam_lo;  // |s(t)| <= 1/lam_lo on [lam_lo, lam_hi], times max D^{-1}
+        M->extra16 = 0;
+    }
+    return AMP_OK;
+}
+
 extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, double lam_lo, double lam_hi,
                                          void *stream, amp_precond *out) {
     if (!out) return fail(AMP_ERR_ARG, "amp_precond_create: out is NULL");
     *out = nullptr;
     if (!A) return fail(AMP_ERR_ARG, "amp_precond_create: null matrix");
-    if (kind != AMP_PC_IDENTITY && kind != AMP_PC_JACOBI)
-        return fail(AMP_ERR_ARG, "amp_precond_create: unsupported preconditioner kind");
-    (void)degree; (void)lam_lo; (void)lam_hi;
+    if (kind != AMP_PC_IDENTITY && kind != AMP_PC_JACOBI && kind != AMP_PC_CHEBYSHEV)
+        return fail(AMP_ERR_ARG, "amp_precond_create: unknown preconditioner kind");
+    if (kind == AMP_PC_CHEBYSHEV) {
+        if (degree < 1 || degree > kChebMax) return fail(AMP_ERR_ARG, "amp_precond_create: degree must be in 1..16");
+        if (!(lam_lo > 0.0) || !(lam_hi > lam_lo) || !std::isfinite(lam_hi))
+            return fail(AMP_ERR_ARG, "amp_precond_create: need 0 < lam_lo < lam_hi");
+    }
     hipStream_t st = as_stream(stream);
     amp_precond M = new amp_precond_s();
     auto bail = [&](amp_status s) { amp_precond_destroy(M); return s; };
     M->A = A;
     M->kind = kind;
+    const int64_t np = A->np;
     amp_status s;
-    if ((s = dalloc(&M->d64, A->np)) != AMP_OK || (s = dalloc(&M->d32, A->np)) != AMP_OK ||
-        (s = dalloc(&M->d16, A->np)) != AMP_OK)
-        return bail(s);
-    const unsigned g = (unsigned)((A->np + 255) / 256);
-    if (kind == AMP_PC_IDENTITY) {
-        k_identity_setup<<<g, 256, 0, st>>>(A->n, A->np, M->d64, M->d32, M->d16);
-        M->gain = 1.0;
-        M->extra16 = 0;
-        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
+    if (kind == AMP_PC_CHEBYSHEV) {
+        M->degree = degree;
+        M->lam_lo = lam_lo;
+        M->lam_hi = lam_hi;
+        if ((s = dalloc(&M->b16, A->slots)) != AMP_OK || (s = dalloc(&M->isq64, np)) != AMP_OK ||
+            (s = dalloc(&M->isq32, np)) != AMP_OK || (s = dalloc(&M->cv, np)) != AMP_OK ||
+            (s = dalloc(&M->cres, np)) != AMP_OK || (s = dalloc(&M->cw, np)) != AMP_OK ||
+            (s = dalloc(&M->cdir[0], np)) != AMP_OK || (s = dalloc(&M->cdir[1], np)) != AMP_OK)
+            return bail(s);
+        // coefficients of the three-term recurrence
+        const double theta = 0.5 * (lam_hi + lam_lo), delta = 0.5 * (lam_hi - lam_lo), sigma = theta / delta;
+        double rho = 1.0 / sigma;
+        M->inv_theta = 1.0 / theta;
+        for (int k = 0; k + 1 < degree; ++k) {
+            const double rho_n = 1.0 / (2.0 * sigma - rho);
+            M->c1[k] = rho_n * rho;
+            M->c2[k] = 2.0 * rho_n / delta;
+            rho = rho_n;
+        }
     } else {
-        double *part = nullptr;
-        if ((s = dalloc(&part, GMAX + 1)) != AMP_OK) return bail(s);
-        const int G = fit_grid((A->np + NT - 1) / NT);
-        k_jacobi_setup<<<G, NT, 0, st>>>(A->diag, A->n, A->np, M->d64, M->d32, part);
-        k_reduce_to<<<1, NT, 0, st>>>(part, G, 1, part + GMAX);
-        double dmax = 0.0;
-        hipError_t e1 = hipMemcpyAsync(&dmax, part + GMAX, sizeof(double), hipMemcpyDeviceToHost, st);
-        hipError_t e2 = hipStreamSynchronize(st);
-        dfree(part);
-        if (e1 != hipSuccess || e2 != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
-        if (!(dmax > 0.0) || !std::isfinite(dmax)) return bail(fail(AMP_ERR_ARG, "amp_precond_create: bad diagonal"));
-        M->gain = dmax;
-        M->extra16 = -ceil_log2(dmax);   // max of the FP16 copy lies in (1/2, 1]
-        k_scale_to_half<<<g, 256, 0, st>>>(M->d64, A->np, std::ldexp(1.0, M->extra16), M->d16);
-        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AMP_ERR_HIP, "amp_precond_create: setup failed"));
+        if ((s = dalloc(&M->d64, np)) != AMP_OK || (s = dalloc(&M->d32, np)) != AMP_OK ||
+            (s = dalloc(&M->d16, np)) != AMP_OK)
+            return bail(s);
     }
+    if ((s = setup_values(M, st)) != AMP_OK) return bail(s);
     *out = M;
     return AMP_OK;
+}
+
+extern "C" amp_status amp_precond_update(amp_precond M, void *stream) {
+    if (!M) return fail(AMP_ERR_ARG, "amp_precond_update: null handle");
+    return setup_values(M, as_stream(stream));
 }
 
 extern "C" void amp_precond_destroy(amp_precond M) {
     if (!M) return;
     dfree(M->d64); dfree(M->d32); dfree(M->d16);
+    dfree(M->b16); dfree(M->isq64); dfree(M->isq32);
+    dfree(M->cv); dfree(M->cres); dfree(M->cw); dfree(M->cdir[0]); dfree(M->cdir[1]);
     delete M;
 }
 
@@ -487,6 +562,7 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.extra16 = M ? M->extra16 : 0;
     c.g_stream = A ? grid_stream(A->np) : 1;
     c.g_slice = A ? grid_slices(A->nslices) : 1;
+    c.g_pre = (M && M->kind == AMP_PC_CHEBYSHEV && M->degree > 1) ? c.g_slice : c.g_stream;
     c.C = o.C;
     c.tau_zs = o.tau_zs;
     c.tau_zh = o.tau_zh;
@@ -518,6 +594,7 @@ static St init_state(const amp_options &o) {
 
 struct Driver {
     amp_matrix A;
+    amp_precond M;
     Cfg cfg;
     Sell S;
     Bufs B;
@@ -527,10 +604,31 @@ struct Driver {
     int host_k;        // iterations enqueued since the last resynchronisation
 };
 
+// One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
+static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
+    Work &w = d.A->w;
+    const Cheb P = d.M->cheb();
+    const int m = d.M->degree;
+    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, P, standalone, in, &w.st[ST_PREI]);
+    if (m == 1) {
+        k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, P, &w.st[ST_PREI], out);
+        return;
+    }
+    for (int k = 0; k + 1 < m; ++k) {
+        St *si = (k == 0) ? &w.st[ST_PREI] : &w.st[(k - 1) % 2 ? ST_CH1 : ST_CH0];
+        St *so = (k == m - 2) ? out : &w.st[k % 2 ? ST_CH1 : ST_CH0];
+        k_cheb_step<<<d.gl, NT, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
+    }
+}
+
 static amp_status enqueue_iterations(Driver &d, int count) {
     Work &w = d.A->w;
     for (int i = 0; i < count; ++i) {
-        k_precond<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, d.in, &w.st[ST_PRE]);
+        if (d.M->kind == AMP_PC_CHEBYSHEV) {
+            enqueue_chebyshev(d, 0, d.in, &w.st[ST_PRE]);
+        } else {
+            k_precond<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, d.in, &w.st[ST_PRE]);
+        }
         k_spmv<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, &w.st[ST_PRE], &w.st[ST_SPMV]);
         k_update<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, &w.st[ST_SPMV], &w.st[ST_RES]);
         d.in = &w.st[ST_RES];
@@ -565,6 +663,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     AMP_TRY(check_options(o));
     Driver d;
     d.A = A;
+    d.M = M;
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
@@ -739,25 +838,141 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
     amp_matrix A = M->A;
     hipStream_t st = as_stream(stream);
     AMP_TRY(ensure_work(A, st));
+    Work &w = A->w;
     Bufs B = make_bufs(A, M);
     const int64_t n = A->n;
     AMP_HIP(hipMemcpyAsync(B.r[pslot(u_r)], r, n * (u_r / 8), hipMemcpyDeviceToDevice, st));
     const double oe = std::ldexp(omega, -(u_z == 16 ? M->extra16 : 0));
     const int gs = grid_stream(A->np);
-#define AMP_PC_LAUNCH(UR, UZ) k_precond_fixed<UR, UZ><<<gs, NT, 0, st>>>(B, A->np, oe, B.part_pre)
-    if (u_r == 64) {
-        if (u_z == 64) AMP_PC_LAUNCH(64, 64);
-        else if (u_z == 32) AMP_PC_LAUNCH(64, 32);
-        else AMP_PC_LAUNCH(64, 16);
+    int gpre = gs;
+    if (M->kind == AMP_PC_CHEBYSHEV) {
+        amp_options o;
+        amp_options_default(&o);
+        Driver d;
+        d.A = A;
+        d.M = M;
+        d.st = st;
+        d.cfg = make_cfg(o, A, M, 1.0, 1);
+        d.S = A->sell();
+        d.B = B;
+        d.gs = d.cfg.g_stream;
+        d.gl = d.cfg.g_slice;
+        d.in = &w.st[ST_RES];
+        d.host_k = 0;
+        St s0 = init_state(o);
+        s0.uz = u_z;
+        s0.ur = u_r;
+        s0.r_store = u_r;
+        s0.p_store = u_z;
+        s0.omega_eff = oe;
+        AMP_HIP(hipMemcpyAsync(&w.st[ST_RES], &s0, sizeof(St), hipMemcpyHostToDevice, st));
+        enqueue_chebyshev(d, 1, &w.st[ST_RES], &w.st[ST_PRE]);
+        gpre = d.cfg.g_pre;
+        AMP_HIP(hipStreamSynchronize(st));  // s0 lives on the host stack
     } else {
-        if (u_z == 64) AMP_PC_LAUNCH(32, 64);
-        else if (u_z == 32) AMP_PC_LAUNCH(32, 32);
-        else AMP_PC_LAUNCH(32, 16);
-    }
+#define AMP_PC_LAUNCH(UR, UZ) k_precond_fixed<UR, UZ><<<gs, NT, 0, st>>>(B, A->np, oe, B.part_pre)
+        if (u_r == 64) {
+            if (u_z == 64) AMP_PC_LAUNCH(64, 64);
+            else if (u_z == 32) AMP_PC_LAUNCH(64, 32);
+            else AMP_PC_LAUNCH(64, 16);
+        } else {
+            if (u_z == 64) AMP_PC_LAUNCH(32, 64);
+            else if (u_z == 32) AMP_PC_LAUNCH(32, 32);
+            else AMP_PC_LAUNCH(32, 16);
+        }
 #undef AMP_PC_LAUNCH
-    if (rho) k_reduce_to<<<1, NT, 0, st>>>(B.part_pre, gs, 0, rho);
+    }
+    if (rho) k_reduce_to<<<1, NT, 0, st>>>(B.part_pre, gpre, 0, rho);
     AMP_HIP(hipGetLastError());
     AMP_HIP(hipMemcpyAsync(z, B.z[pslot(u_z)], n * (u_z / 8), hipMemcpyDeviceToDevice, st));
+    return AMP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// finite-volume operator from log-coefficients, and its adjoint gradient
+// ----------------------------------------------------------------------------
+
+static amp_status make_grid(int dim, int nx, int ny, int nz, Grid &g) {
+    if (dim != 2 && dim != 3) return fail(AMP_ERR_ARG, "fv: dim must be 2 or 3");
+    if (nx < 1 || ny < 1 || (dim == 3 && nz < 1)) return fail(AMP_ERR_ARG, "fv: grid sizes must be positive");
+    g.dim = dim;
+    g.n[0] = nx;
+    g.n[1] = ny;
+    g.n[2] = dim == 3 ? nz : 1;
+    g.stride[0] = 1;
+    g.stride[1] = nx;
+    g.stride[2] = (int64_t)nx * ny;
+    g.cells = (int64_t)nx * ny * g.n[2];
+    if (g.cells >= ((int64_t)1 << 31) / 8) return fail(AMP_ERR_ARG, "fv: grid too large for int32 indices");
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_fv_nnz(int dim, int nx, int ny, int nz, int64_t *nnz) {
+    Grid g;
+    AMP_TRY(make_grid(dim, nx, ny, nz, g));
+    if (!nnz) return fail(AMP_ERR_ARG, "amp_fv_nnz: null output");
+    int64_t faces = 0;
+    for (int a = 0; a < dim; ++a) faces += (g.cells / g.n[a]) * (int64_t)(g.n[a] - 1);
+    *nnz = g.cells + 2 * faces;
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_fv_csr(int dim, int nx, int ny, int nz, const float *theta, int32_t *row_ptr,
+                                 int32_t *col_idx, double *val, void *stream) {
+    Grid g;
+    AMP_TRY(make_grid(dim, nx, ny, nz, g));
+    if (!theta || !row_ptr || !col_idx || !val) return fail(AMP_ERR_ARG, "amp_fv_csr: null pointer");
+    hipStream_t st = as_stream(stream);
+    // row pointers: 1 + number of neighbours inside the grid, prefix-summed on the host
+    std::vector<int32_t> rp(g.cells + 1);
+    rp[0] = 0;
+    int64_t acc = 0;
+    for (int64_t i = 0; i < g.cells; ++i) {
+        int64_t c[3] = {i % g.n[0], (i / g.n[0]) % g.n[1], dim == 3 ? i / ((int64_t)g.n[0] * g.n[1]) : 0};
+        int cnt = 1;
+        for (int a = 0; a < dim; ++a) cnt += (c[a] > 0) + (c[a] < g.n[a] - 1);
+        acc += cnt;
+        rp[i + 1] = (int32_t)acc;
+    }
+    AMP_HIP(hipMemcpyAsync(row_ptr, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    k_fv_values<<<(unsigned)((g.cells + NT - 1) / NT), NT, 0, st>>>(g, theta, row_ptr, col_idx, val);
+    AMP_HIP(hipGetLastError());
+    AMP_HIP(hipStreamSynchronize(st));  // rp lives on the host stack
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_fv_grad_theta(int dim, int nx, int ny, int nz, const float *theta, const double *x,
+                                        const double *lambda, float *dtheta, void *stream) {
+    Grid g;
+    AMP_TRY(make_grid(dim, nx, ny, nz, g));
+    if (!theta || !x || !lambda || !dtheta) return fail(AMP_ERR_ARG, "amp_fv_grad_theta: null pointer");
+    k_fv_grad<<<(unsigned)((g.cells + NT - 1) / NT), NT, 0, as_stream(stream)>>>(g, theta, x, lambda, dtheta);
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_matrix_update_values(amp_matrix A, const amp_csr *csr, void *stream) {
+    if (!A || !csr || !csr->row_ptr || !csr->col_idx || !csr->val)
+        return fail(AMP_ERR_ARG, "amp_matrix_update_values: null argument");
+    if (csr->n != A->n || csr->nnz != A->nnz)
+        return fail(AMP_ERR_ARG, "amp_matrix_update_values: size differs from the handle's");
+    hipStream_t st = as_stream(stream);
+    int *err = nullptr;
+    AMP_TRY(dalloc(&err, 1));
+    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) {
+        dfree(err);
+        return fail(AMP_ERR_HIP, "amp_matrix_update_values: memset failed");
+    }
+    k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
+                                                          A->sptr, A->col, A->v64, A->v32, A->v32p, A->diag, err);
+    int herr = 0;
+    hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    dfree(err);
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(AMP_ERR_HIP, "amp_matrix_update_values: fill failed");
+    if (herr & 4) return fail(AMP_ERR_ARG, "amp_matrix_update_values: row lengths differ from the handle's");
+    if (herr & 1) return fail(AMP_ERR_ARG, "amp_matrix_update_values: column index out of range");
+    if (herr & 2) return fail(AMP_ERR_ARG, "amp_matrix_update_values: missing or non-positive diagonal entry");
     return AMP_OK;
 }
 

@@ -1,0 +1,118 @@
+"""Chebyshev-preconditioned AMP-PCG on the anisotropic Q1 workload (GPU).
+
+* One preconditioner application equals the precision model's, element by
+  element (FP16 B, work vectors in the arithmetic precision of u_z).
+* The solve agrees with the model and with the FP64 oracle (Alg. 1 with
+  the same polynomial), and reaches the manufactured solution.
+* The full 256^3 system: FP64 true residual (recomputed by the oracle's
+  product) and the error against x*; iteration count against the oracle's
+  stored reference.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import amp_model as am
+from oracle import cpcg
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+NP = {64: np.float64, 32: np.float32, 16: np.float16}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def amp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2505_04155_amd as amp_mod
+    from paper_2505_04155_amd import binding
+    binding.load(build_if_missing=False)
+    return amp_mod
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("degree", [1, 2, 4])
+@pytest.mark.parametrize("u_r,u_z", [(64, 64), (64, 16), (32, 32), (32, 16)])
+def test_chebyshev_apply_matches_model(amp, degree, u_r, u_z):
+    _say(f"chebyshev apply degree={degree} u_r={u_r} u_z={u_z}")
+    A, b, xs, (lo, hi) = P.q1_system(18)
+    S = A.to_scipy()
+    C = am.Chebyshev(S, lo, hi, degree)
+    r = (np.random.default_rng([400, degree]).standard_normal(A.n) * 1e-2).astype(NP[u_r])
+    omega = 2.0 ** 7
+    y = am.fl(am.fl(r.astype(NP[u_r]) * NP[u_r](omega), u_r), u_z)
+    zref = C.apply(y, u_z).astype(np.float64)
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=degree, lam_lo=lo, lam_hi=hi)
+    z, rho = pc.apply(torch.tensor(r, device="cuda"), u_z=u_z, omega=omega)
+    zh = z.cpu().numpy().astype(np.float64)
+    ulp = {64: 2.0 ** -52, 32: 2.0 ** -23, 16: 2.0 ** -10}[u_z]
+    err = np.abs(zh - zref) / np.maximum(np.abs(zref), 1e-30)
+    _say(f"  max rel diff {err.max():.3e}, exact fraction {np.mean(zh == zref):.4f}")
+    assert np.max(np.abs(zh - zref)) <= 4 * ulp * np.max(np.abs(zref))
+    assert rho.item() == pytest.approx(float(r.astype(np.float64) @ zh), rel=1e-12)
+
+
+@pytest.mark.parametrize("preset", ["pcg64", "amp64", "amp16"])
+def test_chebyshev_solve_parity(amp, preset):
+    _say(f"chebyshev solve {preset}")
+    A, b, xs, (lo, hi) = P.q1_system(24)
+    S = A.to_scipy()
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=lo, lam_hi=hi)
+    ref = am.amp_pcg(S, b, tol=1e-10, maxit=5000, M=am.Chebyshev(S, lo, hi, 4), opt=am.options(preset))
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=5000, preset=preset,
+                        history=True)
+    x = x.cpu().numpy()
+    _say(f"  gpu {info['iters']} model {ref.iters} oracle {io['iters']}; switches "
+         f"{info['k_z32']} {info['k_z16']} {info['k_r32']} / model {ref.k_z32} {ref.k_z16} {ref.k_r32}")
+    assert info["status"] == 0
+    assert info["relres_true"] <= 1e-10
+    assert abs(info["iters"] - ref.iters) <= max(2, math.ceil(0.02 * ref.iters))
+    if preset != "amp16":
+        assert info["iters"] <= math.ceil(1.05 * io["iters"])
+    kz32, kz16, kr = am.replay_switches(list(info["delta"][:info["iters"]]), info["bnorm"], 1e-10,
+                                        am.options(preset))
+    assert (kz32, kz16, kr) == (info["k_z32"], info["k_z16"], info["k_r32"])
+    kappa = 1.25 * hi / lo                       # bound for the preconditioned operator
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 2e-10
+
+
+def test_q1_full_size(amp):
+    _say("full size: Q1 anisotropic 256^3, degree-4 Chebyshev")
+    ref = {}
+    path = os.path.join(GOLDEN, "q1_256_chebyshev4.txt")
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                ref[k] = float(v)
+    A, b, xs, (lo, hi) = P.q1_system(256)
+    _say(f"  generated n={A.n} nnz={A.nnz}")
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    bt = torch.tensor(b, device="cuda")
+    for preset in ("amp64", "pcg64"):
+        x, info = amp.solve(M, pc, bt, tol=1e-10, maxit=20000, preset=preset)
+        xh = x.cpu().numpy()
+        r = b - cpcg.spmv(A, xh)
+        rel = float(np.linalg.norm(r) / np.linalg.norm(b))
+        err = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
+        _say(f"  {preset}: {info['iters']} iterations (oracle {ref.get('iters')}), {info['t_solve_ms']:.1f} ms, "
+             f"true rel. residual {rel:.3e}, error vs x* {err:.3e}, switches "
+             f"{info['k_z32']} {info['k_z16']} {info['k_r32']}")
+        assert info["status"] == 0
+        assert rel <= 1e-10 * (1 + 1e-6)
+        if "iters" in ref:
+            assert info["iters"] <= math.ceil(1.05 * ref["iters"])
+        assert err <= 1e-5
