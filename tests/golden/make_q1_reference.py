@@ -32,7 +32,7 @@ def main():
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "q1_256_chebyshev4.txt")
     with open(out, "w") as f:
         f.write("# FP64 oracle PCG (Alg. 1) on the anisotropic Q1 workload: 256^3 interior nodes,\n")
-        f.write("# K = diag(1, 1e-2, 1e-3), degree-4 Chebyshev on the closed-form D^-1 A bounds,\n")
+        f.write("# K = diag(1, 1e-2, 1e-3), degree-4 Chebyshev on [lam_min, 1.05 lam_max] of D^-1 A (closed form),\n")
         f.write("# x* ~ U[-1,1] (seed [3, 1]), b = A x*, x0 = 0, tol 1e-10.\n")
         f.write("# Written by tests/golden/make_q1_reference.py.\n")
         f.write(f"iters {info['iters']}\n")

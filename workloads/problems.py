@@ -309,13 +309,22 @@ def blocky_diffusion3d_system(n: int = 128, block: int = 8, decades: float = 4.0
     return A, b, kappa
 
 
+CHEB_HI_MARGIN = 1.05
+
+
 def q1_system(n: int = 256):
     """Anisotropic Q1 system, manufactured solution.
-    Returns (A, b, x_star, (lam_min, lam_max) of D^{-1}A)."""
+    Returns (A, b, x_star, (lam_lo, lam_hi)): the Chebyshev interval for
+    D^{-1}A, lam_lo the exact smallest eigenvalue and lam_hi the exact
+    largest one times CHEB_HI_MARGIN.  The preconditioner polynomial s(t)
+    turns negative from t = lam_hi + lam_lo on, and rounding the
+    preconditioner's matrix to FP16 moves the top of the spectrum by more
+    than lam_lo, so the exact bounds would make M indefinite."""
     A = q1_anisotropic(n)
     x_star = rng_for(3, 1).uniform(-1.0, 1.0, A.n)
     b = A.to_scipy() @ x_star
-    return A, b, x_star, q1_anisotropic_bounds(n)
+    lo, hi = q1_anisotropic_bounds(n)
+    return A, b, x_star, (lo, CHEB_HI_MARGIN * hi)
 
 
 def batched_systems(count: int = 512, side_min: int = 32, side_max: int = 512,
