@@ -33,15 +33,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_algorithmic_bytes(n, nnz, nslices, b_val, b_z, b_q):
+def spmv_algorithmic_bytes(n, nnz, meta_bytes, b_val, b_z, b_q):
     """Bytes one fused product step p = z + beta p_old, q = A p must move:
-    values and column indices once, the slice pointers, z and p_old read
-    once (the gathers are counted once), p and q written once.  Slice padding
-    is overhead, not counted."""
-    return nnz * (b_val + 4) + n * (3 * b_z + b_q) + (nslices + 1) * 8
+    every nonzero's value once, the column metadata of the handle's layout
+    once (int32 indices of index-mode slices, the shared offset lists of
+    offset-mode slices, the slice pointers), z and p_old read once (the
+    gathers are counted once), p and q written once.  Slice padding is
+    overhead, not counted."""
+    return nnz * b_val + meta_bytes + n * (3 * b_z + b_q)
 
 
-def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, nslices):
+def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, meta_bytes):
     """Average duration (ms) of the library's product-step kernel over reps
     back-to-back launches, and its algorithmic bytes per launch."""
     import ctypes
@@ -58,7 +60,7 @@ def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, nslices):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     bv = 8 if u_r == 64 else 4
-    return ms, spmv_algorithmic_bytes(n, nnz, nslices, bv, u_z // 8, u_r // 8)
+    return ms, spmv_algorithmic_bytes(n, nnz, meta_bytes, bv, u_z // 8, u_r // 8)
 
 
 def main():
@@ -135,8 +137,8 @@ def main():
     # form, FP32 q), timed with HIP events on the stream the library launches
     # on (torch's current stream) over spmv_reps back-to-back launches.
     n, nnz = info_m["n"], info_m["nnz"]
-    nslices = ((n + 1023) // 1024 * 1024) // 64      # rows padded to 1024, 64 rows per slice
-    spmv_ms, spmv_bytes = time_spmv_step(binding, M, torch, 16, 32, 1, args.spmv_reps, n, nnz, nslices)
+    spmv_ms, spmv_bytes = time_spmv_step(binding, M, torch, 16, 32, 1, args.spmv_reps, n, nnz,
+                                         info_m["meta_bytes"])
     spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     log(f"bench: fused product step (p fp16, A fp32 diff): {spmv_ms * 1e3:.2f} us, {spmv_gbs:.0f} GB/s algorithmic")
 
@@ -202,10 +204,10 @@ def spmv_only(args, amp, binding, M, pc, bt, torch):
     amp.solve(M, pc, bt, tol=1e-10, maxit=20000, preset=args.preset)   # fills the work buffers
     info_m = M.info()
     n, nnz = info_m["n"], info_m["nnz"]
-    nslices = ((n + 1023) // 1024 * 1024) // 64
-    out = {"mode": "spmv", "n": n, "nnz": nnz, "slots": info_m["slots"], "kernels": {}}
+    out = {"mode": "spmv", "matrix": info_m, "kernels": {}}
     for (u_z, u_r, diff) in ((64, 64, 0), (16, 32, 1), (32, 32, 1)):
-        ms, nbytes = time_spmv_step(binding, M, torch, u_z, u_r, diff, args.spmv_reps, n, nnz, nslices)
+        ms, nbytes = time_spmv_step(binding, M, torch, u_z, u_r, diff, args.spmv_reps, n, nnz,
+                                    info_m["meta_bytes"])
         us = ms * 1e3
         out["kernels"][f"k_spmv_fixed<{u_z},{u_r},{'true' if diff else 'false'}>"] = {
             "avg_us": round(us, 3), "algorithmic_bytes": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}

@@ -70,7 +70,8 @@ typedef enum {
 } amp_preset;
 
 /* Matrix in CSR form, all arrays device pointers: row_ptr[n+1], col_idx[nnz],
- * val[nnz].  Columns sorted within each row, the diagonal present, nnz < 2^31.
+ * val[nnz].  Columns strictly ascending within each row (no duplicates), the
+ * diagonal present, nnz < 2^31.
  * The values are read once by amp_matrix_create (no reference is kept). */
 typedef struct {
     int32_t n;
@@ -98,8 +99,13 @@ typedef struct {
     int max_replacements;   /* replacements allowed by the termination check (default 3) */
     int rr_period;          /* >0: replace r by b - A x every rr_period iterations (default 0) */
     int batch;              /* iterations enqueued between host status checks (default 0 = automatic) */
+    int group_rows;         /* rows per work-group, a multiple of 256: every kernel of the solve then
+                               runs G = ceil(n_padded / group_rows) work-groups (at most 1024).
+                               Default 0: automatic (single solve: per-kernel counts filling the
+                               chip; batched solve: 4096) */
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
+    double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */
 } amp_options;
 
 typedef struct {
@@ -130,17 +136,37 @@ amp_status amp_options_preset(amp_options *opt, int preset);
 /*
  * Build the solver's matrix handle from a device CSR matrix (Section 4: the
  * matrix-vector product is computed in u_r).  Converts to sliced ELL (slice
- * height 64, rows in natural order, int32 column indices) with an FP64 value
- * plane (products in FP64) and an FP32 plane (products in FP32; the diagonal
- * slot holds the FP64 row sum rounded to FP32 for the difference form).
+ * height 64, rows in natural order) with an FP64 value plane (products in
+ * FP64) and an FP32 plane (products in FP32; the diagonal slot holds the
+ * FP64 row sum rounded to FP32 for the difference form).  A slice whose rows
+ * share a short list of column offsets (col - row, at most 32, at most two
+ * more than its longest row) stores that list once instead of a column index
+ * per entry (stencil matrices: every slice); other slices keep int32 column
+ * indices.
  * Enqueued on `stream` and host-synchronous.
- * Errors: AMP_ERR_ARG for n <= 0, nnz < n, nnz >= 2^31, null pointers or a
- * non-positive diagonal entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
+ * The CSR is validated on the device before any entry is read through it:
+ * row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing; columns in [0, n) and
+ * strictly ascending within each row.
+ * Errors: AMP_ERR_ARG for n <= 0, nnz < n, nnz >= 2^31, null pointers, a CSR
+ * failing the validation above, or a missing or non-positive diagonal
+ * entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
  */
 amp_status amp_matrix_create(const amp_csr *A, void *stream, amp_matrix *out);
+/* As amp_matrix_create; flags bit 0 keeps every slice in index mode (no
+ * shared per-slice column-offset lists). */
+amp_status amp_matrix_create_ex(const amp_csr *A, int flags, void *stream, amp_matrix *out);
 void amp_matrix_destroy(amp_matrix A);
-/* Rows, stored slots (including slice padding) and device bytes of the handle. */
-amp_status amp_matrix_info(amp_matrix A, int64_t *n, int64_t *nnz, int64_t *slots, int64_t *bytes);
+/* Layout of a matrix handle. */
+typedef struct {
+    int64_t n, nnz;
+    int64_t slots;          /* stored entries including slice padding */
+    int64_t bytes;          /* device bytes held by the handle (with its work vectors once solved) */
+    int64_t nslices;        /* 64-row slices (rows padded to a multiple of 1024) */
+    int64_t offset_slices;  /* slices stored with a shared column-offset list */
+    int64_t meta_bytes;     /* column metadata one product reads: 4 B per index-mode slot,
+                               the offset lists, 12 B per slice of pointers, plus 8 */
+} amp_matrix_stats;
+amp_status amp_matrix_info(amp_matrix A, amp_matrix_stats *out);
 
 /*
  * Preconditioner handle.  AMP_PC_JACOBI: M = diag(A) (Section 5.5), inverse
@@ -170,6 +196,28 @@ void amp_precond_destroy(amp_precond M);
  */
 amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
                          int maxit, const amp_options *opt, amp_result *res, void *stream);
+
+/*
+ * Solve nsys independent systems A[i] x[i] = b[i] (Alg. 3 for each) in one
+ * lockstep iteration: every kernel launch advances every unfinished system,
+ * each system keeping its own scalars, precisions, switch points, scaling
+ * and convergence state; finished systems leave the launch grid between
+ * batches of iterations.  A, M: host arrays of nsys distinct handles (M[i]
+ * built on A[i]; Jacobi or identity).  b, x: host arrays of nsys device
+ * pointers (FP64, n_i elements; x[i] holds x0 on entry and the solution on
+ * exit).  tol: host array of nsys tolerances.  opt as for amp_pcg_solve
+ * (histories must be NULL); opt->group_rows sets rows per work-group.
+ * res: host array of nsys results (nullable), each with its own status and
+ * rel_res_true (always computed).  Each system follows exactly the
+ * arithmetic of amp_pcg_solve with its work-group count.  Host-synchronous.
+ * Returns AMP_OK if every system converged, else AMP_ERR_BREAKDOWN if any
+ * broke down, else AMP_ERR_NOT_CONVERGED; AMP_ERR_ARG for nsys < 1, null
+ * or repeated handles, a Chebyshev preconditioner, tol <= 0, maxit < 0,
+ * non-null histories or bad option values.
+ */
+amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const amp_precond *M, const double *const *b,
+                                 double *const *x, const double *tol, int maxit, const amp_options *opt,
+                                 amp_result *res, void *stream);
 
 /*
  * One product q = A p with the solver's own kernel, for tests and

@@ -314,6 +314,9 @@ class AmpResult:
     uz: list = field(default_factory=list)
     ur: list = field(default_factory=list)
     omega: list = field(default_factory=list)
+    rho: list = field(default_factory=list)
+    gamma: list = field(default_factory=list)
+    alpha: list = field(default_factory=list)
 
 
 def _diff_spmv32(A):
@@ -451,6 +454,9 @@ def amp_pcg(A, b, x0=None, tol=1e-10, maxit=5000, M=None, opt: AmpOptions | None
         gamma = float(np.dot(q.astype(np.float64), p.astype(np.float64)))
         with np.errstate(all="ignore"):
             alpha = rho / gamma if gamma != 0.0 else math.inf
+        res.rho.append(rho)
+        res.gamma.append(gamma)
+        res.alpha.append(alpha)
         if not (rho > 0.0) or not (gamma > 0.0) or not math.isfinite(alpha):
             iters = k
             return finish(ST_BREAKDOWN)

@@ -5,8 +5,8 @@ arXiv:2505.04155) as hand-written HIP kernels behind a C ABI
 
 Python entry points (argument marshalling only):
 
-* :class:`Matrix`, :class:`Preconditioner`, :func:`solve`
+* :class:`Matrix`, :class:`Preconditioner`, :func:`solve`, :func:`solve_batched`
 * :func:`selector_replay`, :func:`paper_kernel_bytes` (host-only helpers)
 """
 
-from .solver import Matrix, Preconditioner, solve, selector_replay, paper_kernel_bytes  # noqa: F401
+from .solver import Matrix, Preconditioner, solve, solve_batched, selector_replay, paper_kernel_bytes  # noqa: F401

@@ -21,10 +21,11 @@ PRESETS = {"pcg64": 0, "amp64": 1, "amp16": 2, "amp_ur": 3}
 
 EXPORTED = [
     "amp_version", "amp_status_string", "amp_last_error", "amp_options_default",
-    "amp_options_preset", "amp_matrix_create", "amp_matrix_destroy", "amp_matrix_info",
+    "amp_options_preset", "amp_matrix_create", "amp_matrix_create_ex", "amp_matrix_destroy", "amp_matrix_info",
     "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv", "amp_spmv_step",
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
+    "amp_pcg_solve_batched",
 ]
 
 
@@ -39,8 +40,8 @@ class Options(ctypes.Structure):
                 ("ell", ctypes.c_int), ("scaling", ctypes.c_int), ("T_z", ctypes.c_int),
                 ("T_p", ctypes.c_int), ("spmv32_diff", ctypes.c_int), ("verify", ctypes.c_int),
                 ("max_replacements", ctypes.c_int), ("rr_period", ctypes.c_int),
-                ("batch", ctypes.c_int), ("delta_history", ctypes.c_void_p),
-                ("prec_history", ctypes.c_void_p)]
+                ("batch", ctypes.c_int), ("group_rows", ctypes.c_int), ("delta_history", ctypes.c_void_p),
+                ("prec_history", ctypes.c_void_p), ("scalar_history", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -49,6 +50,11 @@ class Result(ctypes.Structure):
                 ("bnorm", ctypes.c_double), ("k_z32", ctypes.c_int), ("k_z16", ctypes.c_int),
                 ("k_r32", ctypes.c_int), ("n_replacements", ctypes.c_int),
                 ("t_solve_ms", ctypes.c_double)]
+
+
+class MatrixStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("n", "nnz", "slots", "bytes", "nslices", "offset_slices", "meta_bytes")]
 
 
 _lib = None
@@ -86,14 +92,18 @@ def load(build_if_missing: bool = True):
         L.amp_options_default.restype = None
         L.amp_options_preset.argtypes = [ctypes.POINTER(Options), i32]
         L.amp_matrix_create.argtypes = [ctypes.POINTER(Csr), vp, ctypes.POINTER(vp)]
+        L.amp_matrix_create_ex.argtypes = [ctypes.POINTER(Csr), i32, vp, ctypes.POINTER(vp)]
         L.amp_matrix_destroy.argtypes = [vp]
         L.amp_matrix_destroy.restype = None
-        L.amp_matrix_info.argtypes = [vp] + [ctypes.POINTER(i64)] * 4
+        L.amp_matrix_info.argtypes = [vp, ctypes.POINTER(MatrixStats)]
         L.amp_precond_create.argtypes = [vp, i32, i32, dbl, dbl, vp, ctypes.POINTER(vp)]
         L.amp_precond_destroy.argtypes = [vp]
         L.amp_precond_destroy.restype = None
         L.amp_pcg_solve.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(Result), vp]
+        L.amp_pcg_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                            ctypes.POINTER(vp), ctypes.POINTER(dbl), i32,
+                                            ctypes.POINTER(Options), ctypes.POINTER(Result), vp]
         L.amp_spmv.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.amp_spmv_step.argtypes = [vp, i32, i32, i32, dbl, vp]
         L.amp_precond_apply.argtypes = [vp, i32, i32, vp, dbl, vp, vp, vp]
@@ -141,7 +151,7 @@ def make_options(preset: str = "amp64", **kw) -> Options:
             o.spmv32_diff = 1 if v == "diff" else 0
         elif k == "tau_zs" or k == "tau_zh" or k == "C":
             setattr(o, k, float(v))
-        elif hasattr(o, k) and k not in ("delta_history", "prec_history"):
+        elif hasattr(o, k) and k not in ("delta_history", "prec_history", "scalar_history"):
             setattr(o, k, int(v))
         else:
             raise KeyError(f"unknown option {k}")

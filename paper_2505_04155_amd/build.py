@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libamppcg.so")
 SOURCES = ["amp_pcg.hip"]
-HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp", "amp_cheb.hpp", "amp_fv.hpp"]
+HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp", "amp_cheb.hpp", "amp_fv.hpp",
+           "amp_batch.hpp"]
 
 
 def hipcc() -> str:
@@ -39,6 +40,20 @@ def sources_mtime() -> float:
     paths.append(os.path.join(ROOT, "include", "amp_pcg.h"))
     paths.append(os.path.abspath(__file__))
     return max(os.path.getmtime(p) for p in paths)
+
+
+def source_digest() -> str:
+    """SHA-256 over the library's sources, header and compiler flags: names
+    the kernel build a stored measurement belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(SOURCES + HEADERS):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "amp_pcg.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(f for f in flags() if not f.startswith("/")).encode())
+    return h.hexdigest()[:16]
 
 
 def is_stale() -> bool:

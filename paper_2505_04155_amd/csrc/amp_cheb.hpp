@@ -22,6 +22,7 @@ constexpr int kChebMax = 16;
 struct Cheb {
     const int64_t *sptr;
     const int32_t *col;
+    const int32_t *soff, *offs;
     const half_t *b16;       // B's values in FP16
     const double *isq64;     // D^{-1/2}
     const float *isq32;
@@ -35,7 +36,7 @@ struct Cheb {
 
 // y = fl_uz(fl_ur(omega r)); v = isq (.) y in the work precision C.
 template <int RS, int UR, int UZ>
-__device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Cheb &P) {
+__device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Cheb &P, Wg wg) {
     typedef typename Prec<RS>::T TRS;
     typedef typename Prec<UR>::T TR;
     typedef typename Prec<UZ>::T TZ;
@@ -45,7 +46,7 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
     CZ *v = (CZ *)P.v;
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     const TR w = (TR)s.omega_eff;
-    AMP_STREAM_LOOP(i, P.np) {
+    AMP_STREAM_LOOP(i, P.np, wg) {
         const V4<TRS> rv = ld4(r, i);
         const V4<CZ> iv = ld4(isq, i);
         V4<CZ> vv;
@@ -67,21 +68,22 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
 // uses the incoming state's precisions and omega as given.
 __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int standalone, const St *in, St *out) {
     __shared__ St s;
+    const Wg wg = grid_wg();
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     if (!standalone) {
-        consume_residual(s, c, B);
+        consume_residual(s, c, B, wg);
         __syncthreads();
         if (s.status != RUNNING) {
-            store_state(s, out);
+            store_state(s, out, wg);
             return;
         }
     }
     const int rs = s.r_store, ur = s.ur, uz = s.uz;
-#define AMP_CV(RS, UR, UZ) cheb_v_body<RS, UR, UZ>(s, B, P)
+#define AMP_CV(RS, UR, UZ) cheb_v_body<RS, UR, UZ>(s, B, P, wg)
 #define AMP_CV_Z(RS, UR)                  \
     if (uz == 64) AMP_CV(RS, UR, 64);       \
     else if (uz == 32) AMP_CV(RS, UR, 32);  \
@@ -93,20 +95,20 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 #undef AMP_CV
     const bool conv = (s.k > 0 && s.p_store != uz);
     if (conv) {
-        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, P.np);
-        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, P.np);
-        else convert_p<32, 16>(B, s.pbuf, P.np);
+        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, P.np, wg);
+        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, P.np, wg);
+        else convert_p<32, 16>(B, s.pbuf, P.np, wg);
     }
     if (threadIdx.x == 0) {
         s.r_store = s.ur;
         if (conv) s.p_store = uz;
     }
-    store_state(s, out);
+    store_state(s, out, wg);
 }
 
 // One step k of the recurrence for this work-group's slices.
 template <int UZ>
-__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, int k, int first,
+__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int first,
                                                int last, int din, double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
@@ -122,19 +124,21 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     const int ur = s.ur;
     auto dval = [&](int64_t j) -> CZ { return first ? v[j] * inv_theta : dk[j]; };
     int64_t slo_, shi_;
-    block_range(P.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
-    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE) {
+    block_range(P.nslices, 1, wg.lb, wg.G, slo_, shi_);
+    const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    for (int64_t sl = sfirst; sl < shi_; sl += NT / WAVE) {
         const int lane = threadIdx.x % WAVE;
         const int64_t row = sl * SLICE + lane, base = P.sptr[sl] + lane;
         const int wd = (int)((P.sptr[sl + 1] - P.sptr[sl]) / SLICE);
+        const SliceCols sc = slice_cols(P.sptr, P.col, P.soff, P.offs, P.np, sl, lane);
         CZ acc = (CZ)0;
         int j = 0;
         for (; j + 4 <= wd; j += 4) {
-            int32_t cc[4];
+            int64_t cc[4];
             CZ bv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                cc[u] = P.col[base + (int64_t)(j + u) * SLICE];
+                cc[u] = sc(j + u);
                 bv[u] = (CZ)P.b16[base + (int64_t)(j + u) * SLICE];
             }
             CZ dj[4];
@@ -143,10 +147,7 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc += bv[u] * dj[u];
         }
-        for (; j < wd; ++j) {
-            const int64_t sidx = base + (int64_t)j * SLICE;
-            acc += (CZ)P.b16[sidx] * dval(P.col[sidx]);
-        }
+        for (; j < wd; ++j) acc += (CZ)P.b16[base + (int64_t)j * SLICE] * dval(sc(j));
         const CZ d0 = dval(row);
         const CZ wk = first ? (CZ)0 + d0 : w[row];
         const CZ w1 = first ? wk : wk + d0;
@@ -173,29 +174,30 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
 __global__ void __launch_bounds__(NT) k_cheb_step(Bufs B, Cheb P, int k, int first, int last, int din,
                                                   const St *in, St *out) {
     __shared__ St s;
+    const Wg wg = grid_wg();
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     double rho = 0.0, mz = 0.0;
-    if (s.uz == 64) cheb_step_body<64>(s, B, P, k, first, last, din, rho, mz);
-    else if (s.uz == 32) cheb_step_body<32>(s, B, P, k, first, last, din, rho, mz);
-    else cheb_step_body<16>(s, B, P, k, first, last, din, rho, mz);
+    if (s.uz == 64) cheb_step_body<64>(s, B, P, wg, k, first, last, din, rho, mz);
+    else if (s.uz == 32) cheb_step_body<32>(s, B, P, wg, k, first, last, din, rho, mz);
+    else cheb_step_body<16>(s, B, P, wg, k, first, last, din, rho, mz);
     if (last) {
         rho = block_sum(rho);
         mz = block_max(mz);
         if (threadIdx.x == 0) {
-            B.part_pre[blockIdx.x] = rho;
-            B.part_pre[GMAX + blockIdx.x] = mz;
+            B.part_pre[wg.lb] = rho;
+            B.part_pre[GMAX + wg.lb] = mz;
         }
     }
-    store_state(s, out);
+    store_state(s, out, wg);
 }
 
 // Degree 1: z = fl_uz(isq (.) (v / theta)), no product with B.
 template <int UZ>
-__device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const Cheb &P, double &rho,
+__device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, double &rho,
                                                double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
@@ -203,7 +205,7 @@ __device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     const CZ inv_theta = (CZ)P.inv_theta;
     TZ *z = (TZ *)B.z[pslot(UZ)];
-    AMP_STREAM_LOOP(i, P.np) {
+    AMP_STREAM_LOOP(i, P.np, wg) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const CZ d0 = v[i + e] * inv_theta;
@@ -219,22 +221,23 @@ __device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const
 
 __global__ void __launch_bounds__(NT) k_cheb_deg1(Bufs B, Cheb P, const St *in, St *out) {
     __shared__ St s;
+    const Wg wg = grid_wg();
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     double rho = 0.0, mz = 0.0;
-    if (s.uz == 64) cheb_deg1_body<64>(s, B, P, rho, mz);
-    else if (s.uz == 32) cheb_deg1_body<32>(s, B, P, rho, mz);
-    else cheb_deg1_body<16>(s, B, P, rho, mz);
+    if (s.uz == 64) cheb_deg1_body<64>(s, B, P, wg, rho, mz);
+    else if (s.uz == 32) cheb_deg1_body<32>(s, B, P, wg, rho, mz);
+    else cheb_deg1_body<16>(s, B, P, wg, rho, mz);
     rho = block_sum(rho);
     mz = block_max(mz);
     if (threadIdx.x == 0) {
-        B.part_pre[blockIdx.x] = rho;
-        B.part_pre[GMAX + blockIdx.x] = mz;
+        B.part_pre[wg.lb] = rho;
+        B.part_pre[GMAX + wg.lb] = mz;
     }
-    store_state(s, out);
+    store_state(s, out, wg);
 }
 
 // Setup: B's FP16 values on A's slots, b_ij = fl16((a_ij isq_i) isq_j);
@@ -256,13 +259,11 @@ __global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64,
     int64_t slo_, shi_;
     block_range(A.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
     for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE) {
-        const int lane = threadIdx.x % WAVE;
-        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
-        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
         const double si = isq64[row];
         for (int j = 0; j < w; ++j) {
             const int64_t sidx = base + (int64_t)j * SLICE;
-            b16[sidx] = (half_t)((A.v64[sidx] * si) * isq64[A.col[sidx]]);
+            b16[sidx] = (half_t)((A.v64[sidx] * si) * isq64[sc(j)]);
         }
     }
 }

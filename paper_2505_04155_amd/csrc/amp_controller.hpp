@@ -36,6 +36,7 @@ struct Cfg {
     double *ring;             // ||r_t|| for the last kRing iterations (device)
     double *delta_history;    // nullable
     int32_t *prec_history;    // nullable
+    double *scalar_history;   // nullable: omega, rho, gamma, alpha per iteration
 };
 
 // Iteration state.  Each kernel reads the state its predecessor wrote and
@@ -51,6 +52,8 @@ struct St {
     int k_z32, k_z16, k_r32, n_repl;
     int e, have_e;            // pow2 scaling exponent of iteration k
     int kind;                 // ResKind of the pending residual partials
+    int pad;
+    double omega;             // omega_k (without the static storage scale)
     double bnorm, tol_b;
     double rho, rho_prev, beta, gamma, alpha;
     double delta;             // ||r_k||
@@ -149,6 +152,7 @@ AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, in
         s.have_e = 1;
         omega = ldexp(1.0, e);
     }
+    s.omega = omega;
     int extra = (s.uz == 16) ? c.extra16 : 0;
     s.omega_eff = ldexp(omega, -extra);
 }

@@ -25,16 +25,55 @@ template <> struct Prec<32> { typedef float T; typedef float C; };
 template <> struct Prec<16> { typedef half_t T; typedef float C; };  // FP16 storage, FP32 arithmetic
 
 // Sliced ELL: slice s holds rows [64 s, 64 s + 64), its entries column-major
-// (slot sptr[s] + 64 j + lane is entry j of row 64 s + lane).  Padding slots
-// have col = row and value 0.
+// (slot sptr[s] + 64 j + lane is entry j of row 64 s + lane).  A slice is
+// stored in one of two modes:
+//  * index mode (soff[s] < 0): slot j of a row holds the row's j-th entry and
+//    its column in col[]; padding slots have col = row and value 0;
+//  * offset mode (soff[s] >= 0): slot j of every row of the slice holds the
+//    entry at column row + offs[soff[s] + j] (one shared, sorted list of
+//    column offsets per slice, value 0 where the row has no such entry), so
+//    no per-entry column index is read.  Stencil matrices in natural order
+//    store every slice this way.
 struct Sell {
     int64_t n, np, nslices;
     const int64_t *sptr;
     const int32_t *col;
+    const int32_t *soff;  // per slice: start of its offsets in offs, or -1
+    const int32_t *offs;
     const double *v64;   // FP64 values
     const float *v32;    // FP32 values, diagonal slot = fl32(row sum) (difference form)
     const float *v32p;   // FP32 values, plain
 };
+
+constexpr int kOffMax = 32;  // longest per-slice offset list
+
+// Column of slot j of one row in one slice (both storage modes).
+struct SliceCols {
+    const int32_t *col;   // index mode: &col[sptr[s] + lane]
+    const int32_t *offs;  // offset mode: &offs[soff[s]]
+    int64_t row, np;
+    bool omode;
+    __device__ __forceinline__ int64_t operator()(int j) const {
+        if (omode) {
+            const int64_t c = row + offs[j];
+            return (c >= 0 && c < np) ? c : row;
+        }
+        return col[(int64_t)j * 64];
+    }
+    __device__ __forceinline__ bool is_diag(int j, int64_t c) const { return omode ? offs[j] == 0 : c == row; }
+};
+
+__device__ __forceinline__ SliceCols slice_cols(const int64_t *sptr, const int32_t *col, const int32_t *soff,
+                                                const int32_t *offs, int64_t np, int64_t sl, int lane) {
+    SliceCols sc;
+    const int32_t so = soff[sl];
+    sc.omode = so >= 0;
+    sc.offs = offs + (so >= 0 ? so : 0);
+    sc.col = col + sptr[sl] + lane;
+    sc.row = sl * 64 + lane;
+    sc.np = np;
+    return sc;
+}
 
 // Work-group index with consecutive indices on one XCD: dispatch deals
 // work-groups to the 8 XCDs round-robin, so hardware group b runs on XCD
@@ -46,6 +85,15 @@ __device__ __forceinline__ int xcd_block() {
     if (G % NXCD) return b;
     return (b % NXCD) * (G / NXCD) + b / NXCD;
 }
+
+// A work-group's share of one system's work: logical index lb of G groups.
+// A single-system launch uses the whole grid (grid_wg); a batched launch
+// reads (system, lb) from its task table and G from the system's config.
+struct Wg {
+    int lb, G;
+};
+
+__device__ __forceinline__ Wg grid_wg() { return Wg{xcd_block(), (int)gridDim.x}; }
 
 // [lo, hi) share of `total` units for work-group lb of G, in multiples of `quantum`.
 __device__ __forceinline__ void block_range(int64_t total, int64_t quantum, int lb, int G,

@@ -55,9 +55,9 @@ __device__ __forceinline__ void st4(T *p, int64_t i, const V4<T> &x) {
 }
 
 // Streaming loop over this work-group's contiguous element range.
-#define AMP_STREAM_LOOP(i, np)                                                          \
+#define AMP_STREAM_LOOP(i, np, wg)                                                      \
     int64_t lo_, hi_;                                                                    \
-    block_range((np), (int64_t)NT * VEC, xcd_block(), gridDim.x, lo_, hi_);              \
+    block_range((np), (int64_t)NT * VEC, (wg).lb, (wg).G, lo_, hi_);                     \
     for (int64_t i = lo_ + (int64_t)threadIdx.x * VEC; i < hi_; i += (int64_t)NT * VEC)
 
 // ----------------------------------------------------------------------------
@@ -70,13 +70,13 @@ __device__ __forceinline__ void load_state(St &s, const St *in) {
     __syncthreads();
 }
 
-__device__ __forceinline__ void store_state(const St &s, St *out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *out = s;
+__device__ __forceinline__ void store_state(const St &s, St *out, Wg wg) {
+    if (wg.lb == 0 && threadIdx.x == 0) *out = s;
 }
 
 // Record ||r_i|| (work-group 0 only; nobody reads index i in this kernel).
-__device__ __forceinline__ void record_delta(const Cfg &c, int i, double d) {
-    if (blockIdx.x == 0) {
+__device__ __forceinline__ void record_delta(const Cfg &c, int i, double d, Wg wg) {
+    if (wg.lb == 0) {
         c.ring[i % kRing] = d;
         if (c.delta_history) c.delta_history[i] = d;
     }
@@ -88,15 +88,15 @@ __device__ __forceinline__ void record_delta(const Cfg &c, int i, double d) {
 
 // q_i = sum_j a_ij p_j with FP64 values and accumulation, slot order.
 template <typename PF>
-__device__ __forceinline__ double row_dot64(const Sell &A, int64_t base, int w, PF pval) {
+__device__ __forceinline__ double row_dot64(const Sell &A, const SliceCols &sc, int64_t base, int w, PF pval) {
     double acc = 0.0;
     int j = 0;
     for (; j + 4 <= w; j += 4) {
-        int32_t c[4];
+        int64_t c[4];
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            c[u] = A.col[base + (int64_t)(j + u) * SLICE];
+            c[u] = sc(j + u);
             v[u] = A.v64[base + (int64_t)(j + u) * SLICE];
         }
         double pj[4];
@@ -105,28 +105,25 @@ __device__ __forceinline__ double row_dot64(const Sell &A, int64_t base, int w, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += v[u] * pj[u];
     }
-    for (; j < w; ++j) {
-        const int64_t s = base + (int64_t)j * SLICE;
-        acc += A.v64[s] * (double)pval(A.col[s]);
-    }
+    for (; j < w; ++j) acc += A.v64[base + (int64_t)j * SLICE] * (double)pval(sc(j));
     return acc;
 }
 
 // FP32 values and accumulation.  DIFF: off-diagonal slots add a_ij (p_j - p_i)
 // in slot order, then the diagonal slot's row sum s_i adds s_i p_i; padding
-// slots (col = row, value 0) add 0 exactly.  Otherwise the textbook form.
+// slots (value 0) add 0 exactly.  Otherwise the textbook form.
 template <bool DIFF, typename PF>
-__device__ __forceinline__ float row_dot32(const Sell &A, int64_t base, int w, int64_t row, float pi,
+__device__ __forceinline__ float row_dot32(const Sell &A, const SliceCols &sc, int64_t base, int w, float pi,
                                            PF pval) {
     const float *vals = DIFF ? A.v32 : A.v32p;
     float acc = 0.0f, dterm = 0.0f;
     int j = 0;
     for (; j + 4 <= w; j += 4) {
-        int32_t c[4];
+        int64_t c[4];
         float v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            c[u] = A.col[base + (int64_t)(j + u) * SLICE];
+            c[u] = sc(j + u);
             v[u] = vals[base + (int64_t)(j + u) * SLICE];
         }
         float pj[4];
@@ -135,41 +132,45 @@ __device__ __forceinline__ float row_dot32(const Sell &A, int64_t base, int w, i
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (!DIFF) acc += v[u] * pj[u];
-            else if (c[u] == row) dterm += v[u] * pj[u];
+            else if (sc.is_diag(j + u, c[u])) dterm += v[u] * pj[u];
             else acc += v[u] * (pj[u] - pi);
         }
     }
     for (; j < w; ++j) {
-        const int64_t s = base + (int64_t)j * SLICE;
-        const int32_t c = A.col[s];
-        const float v = vals[s];
+        const int64_t c = sc(j);
+        const float v = vals[base + (int64_t)j * SLICE];
         const float pj = (float)pval(c);
         if (!DIFF) acc += v * pj;
-        else if (c == row) dterm += v * pj;
+        else if (sc.is_diag(j, c)) dterm += v * pj;
         else acc += v * (pj - pi);
     }
     return DIFF ? dterm + acc : acc;
 }
 
 // Slices of this work-group: contiguous range, one slice per wave at a time.
-#define AMP_SLICE_LOOP(A, sl)                                                            \
+#define AMP_SLICE_LOOP(A, sl, wg)                                                        \
     int64_t slo_, shi_;                                                                  \
-    block_range((A).nslices, 1, xcd_block(), gridDim.x, slo_, shi_);                     \
-    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE)
+    block_range((A).nslices, 1, (wg).lb, (wg).G, slo_, shi_);                            \
+    const int64_t sfirst_ = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   \
+    for (int64_t sl = sfirst_; sl < shi_; sl += NT / WAVE)
+
+#define AMP_SLICE_ROW(A, sl, lane, row, base, w, sc)                                     \
+    const int lane = threadIdx.x % WAVE;                                                 \
+    const int64_t row = (sl) * SLICE + lane, base = (A).sptr[sl] + lane;                 \
+    const int w = (int)(((A).sptr[(sl) + 1] - (A).sptr[sl]) / SLICE);                    \
+    const SliceCols sc = slice_cols((A).sptr, (A).col, (A).soff, (A).offs, (A).np, sl, lane)
 
 // ----------------------------------------------------------------------------
 // k_init: r0 = b - A x0 in FP64; partials ||r0||^2, ||b||^2, max|r0|
 // ----------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) {
+__device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) {
     double sr = 0.0, sb = 0.0, mr = 0.0;
     double *r = (double *)B.r[0];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl) {
-        const int lane = threadIdx.x % WAVE;
-        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
-        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
-        const double t = B.b[row] - row_dot64(A, base, w, [&](int32_t c) { return x[c]; });
+    AMP_SLICE_LOOP(A, sl, wg) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
+        const double t = B.b[row] - row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; });
         r[row] = t;
         sr += t * t;
         sb += B.b[row] * B.b[row];
@@ -179,18 +180,20 @@ __global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) {
     sb = block_sum(sb);
     mr = block_max(mr);
     if (threadIdx.x == 0) {
-        B.part_res[blockIdx.x] = sr;
-        B.part_res[GMAX + blockIdx.x] = sb;
-        B.part_res[2 * GMAX + blockIdx.x] = mr;
+        B.part_res[wg.lb] = sr;
+        B.part_res[GMAX + wg.lb] = sb;
+        B.part_res[2 * GMAX + wg.lb] = mr;
     }
 }
+
+__global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) { init_stage(A, B, grid_wg()); }
 
 // ----------------------------------------------------------------------------
 // k_precond
 // ----------------------------------------------------------------------------
 
 // Prologue: totals of the residual partials -> controller.  Sets s.status.
-__device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B) {
+__device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B, Wg wg) {
     __shared__ int rec;
     __shared__ double recv;
     const int G = (s.kind == RES_UPDATE) ? c.g_stream : c.g_slice;
@@ -203,6 +206,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             s.bnorm = sqrt(b);
             s.tol_b = c.tol * s.bnorm;
             s.delta = sqrt(a);
+            s.true_res = s.delta;   // r0 = b - A x0 is formed in FP64: it is the true residual
             s.maxr = m;
             s.maxr_prev = m;
             rec = 0;
@@ -239,13 +243,16 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
     }
     __syncthreads();
     if (threadIdx.x == 0 && rec >= 0) {
-        record_delta(c, rec, recv);
-        if (blockIdx.x == 0 && s.status == RUNNING && c.prec_history) c.prec_history[s.k] = s.uz | (s.ur << 8);
+        record_delta(c, rec, recv, wg);
+        if (wg.lb == 0 && s.status == RUNNING) {
+            if (c.prec_history) c.prec_history[s.k] = s.uz | (s.ur << 8);
+            if (c.scalar_history) c.scalar_history[4 * s.k] = s.omega;
+        }
     }
 }
 
 template <int RS, int UR, int UZ>
-__device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t np, double &rho,
+__device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t np, Wg wg, double &rho,
                                              double &mz) {
     typedef typename Prec<RS>::T TRS;
     typedef typename Prec<UR>::T TR;
@@ -256,7 +263,7 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
     TZ *z = (TZ *)B.z[pslot(UZ)];
     const TZ *dv = (const TZ *)B.dinv[pslot(UZ)];
     const TR w = (TR)s.omega_eff;
-    AMP_STREAM_LOOP(i, np) {
+    AMP_STREAM_LOOP(i, np, wg) {
         const V4<TRS> rv = ld4(r, i);
         const V4<TZ> dd = ld4(dv, i);
         V4<TZ> zz;
@@ -278,12 +285,12 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
 
 // At a u_z switch p_{k-1} is first rounded to the new u_z.
 template <int PS, int UZ>
-__device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np) {
+__device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np, Wg wg) {
     typedef typename Prec<PS>::T TPS;
     typedef typename Prec<UZ>::T TZ;
     const TPS *po = (const TPS *)B.p[pslot(PS)][pb];
     TZ *pn = (TZ *)B.p[pslot(UZ)][pb];
-    AMP_STREAM_LOOP(i, np) {
+    AMP_STREAM_LOOP(i, np, wg) {
         const V4<TPS> a = ld4(po, i);
         V4<TZ> b;
 #pragma unroll
@@ -292,22 +299,23 @@ __device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np) {
     }
 }
 
-__global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+__device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
+                                              Wg wg) {
     __shared__ St s;
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
-    consume_residual(s, c, B);
+    consume_residual(s, c, B, wg);
     __syncthreads();
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     const int rs = s.r_store, ur = s.ur, uz = s.uz;
     double rho = 0.0, mz = 0.0;
-#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, rho, mz)
+#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, wg, rho, mz)
 #define AMP_PC_Z(RS, UR)                  \
     if (uz == 64) AMP_PC(RS, UR, 64);       \
     else if (uz == 32) AMP_PC(RS, UR, 32);  \
@@ -319,19 +327,23 @@ __global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const
 #undef AMP_PC
     const bool conv = (s.k > 0 && s.p_store != uz);
     if (conv) {
-        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, np);
-        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, np);
-        else convert_p<32, 16>(B, s.pbuf, np);
+        if (s.p_store == 64 && uz == 32) convert_p<64, 32>(B, s.pbuf, np, wg);
+        else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, np, wg);
+        else convert_p<32, 16>(B, s.pbuf, np, wg);
     }
     rho = block_sum(rho);
     mz = block_max(mz);
     if (threadIdx.x == 0) {
-        B.part_pre[blockIdx.x] = rho;
-        B.part_pre[GMAX + blockIdx.x] = mz;
+        B.part_pre[wg.lb] = rho;
+        B.part_pre[GMAX + wg.lb] = mz;
         s.r_store = s.ur;
         if (conv) s.p_store = uz;
     }
-    store_state(s, out);
+    store_state(s, out, wg);
+}
+
+__global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+    precond_stage(c, B, np, in, out, grid_wg());
 }
 
 // ----------------------------------------------------------------------------
@@ -339,7 +351,7 @@ __global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const
 // ----------------------------------------------------------------------------
 
 template <int UZ, int UR, bool DIFF>
-__device__ __forceinline__ void spmv_p_body(const Sell &A, const void *zv, const void *pov, void *pnv,
+__device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, bool first, double beta_d, double &gam,
                                             double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -354,26 +366,25 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, const void *zv, const
         if (first) return z[c];
         return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
     };
-    AMP_SLICE_LOOP(A, sl) {
-        const int lane = threadIdx.x % WAVE;
-        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
-        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
+    AMP_SLICE_LOOP(A, sl, wg) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
         const TZ pi = pval(row);
         if (pn) pn[row] = pi;
         mp = fmax(mp, fabs((double)pi));
         TQ qq;
-        if (UR == 64) qq = (TQ)row_dot64(A, base, w, pval);
-        else qq = (TQ)row_dot32<DIFF>(A, base, w, row, (float)pi, pval);
+        if (UR == 64) qq = (TQ)row_dot64(A, sc, base, w, pval);
+        else qq = (TQ)row_dot32<DIFF>(A, sc, base, w, (float)pi, pval);
         q[row] = qq;
         gam += (double)qq * (double)pi;
     }
 }
 
-__global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
+__device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
+                                           Wg wg) {
     __shared__ St s;
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     const double rho = reduce_sum(B.part_pre, c.g_pre);
@@ -384,17 +395,18 @@ __global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in
         s.beta = (s.k > 0) ? rho / s.rho_prev : 0.0;
         s.maxz = mz;
         if (!(rho > 0.0) || !isfinite(s.beta)) s.status = BREAKDOWN;
+        if (wg.lb == 0 && c.scalar_history) c.scalar_history[4 * s.k + 1] = rho;
     }
     __syncthreads();
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     const int uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
     const bool first = (s.k == 0);
     double gam = 0.0, mp = 0.0;
 #define AMP_SP(UZ, UR, DF) \
-    spmv_p_body<UZ, UR, DF>(A, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], first, s.beta, gam, mp)
+    spmv_p_body<UZ, UR, DF>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], first, s.beta, gam, mp)
     if (ur == 64) {
         if (uz == 64) AMP_SP(64, 64, false);
         else if (uz == 32) AMP_SP(32, 64, false);
@@ -412,10 +424,14 @@ __global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in
     gam = block_sum(gam);
     mp = block_max(mp);
     if (threadIdx.x == 0) {
-        B.part_spmv[blockIdx.x] = gam;
-        B.part_spmv[GMAX + blockIdx.x] = mp;
+        B.part_spmv[wg.lb] = gam;
+        B.part_spmv[GMAX + wg.lb] = mp;
     }
-    store_state(s, out);
+    store_state(s, out, wg);
+}
+
+__global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
+    spmv_stage(c, A, B, in, out, grid_wg());
 }
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
@@ -424,9 +440,10 @@ template <int UZ, int UR, bool DIFF>
 __global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
                                                    int first, double beta, double *part) {
     double gam = 0.0, mp = 0.0;
-    spmv_p_body<UZ, UR, DIFF>(A, z, po, pn, q, first != 0, beta, gam, mp);
+    const Wg wg = grid_wg();
+    spmv_p_body<UZ, UR, DIFF>(A, wg, z, po, pn, q, first != 0, beta, gam, mp);
     gam = block_sum(gam);
-    if (threadIdx.x == 0 && part) part[blockIdx.x] = gam;
+    if (threadIdx.x == 0 && part) part[wg.lb] = gam;
 }
 
 // ----------------------------------------------------------------------------
@@ -434,7 +451,7 @@ __global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, const void *z, const 
 // ----------------------------------------------------------------------------
 
 template <int UP, int UR>
-__device__ __forceinline__ void update_body(double alpha, const Bufs &B, const void *pv, int64_t np,
+__device__ __forceinline__ void update_body(double alpha, const Bufs &B, const void *pv, int64_t np, Wg wg,
                                             double &dd, double &mr) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
@@ -442,7 +459,7 @@ __device__ __forceinline__ void update_body(double alpha, const Bufs &B, const v
     TR *r = (TR *)B.r[pslot(UR)];
     const TR *q = (const TR *)B.q[pslot(UR)];
     const TR a = (TR)alpha;
-    AMP_STREAM_LOOP(i, np) {
+    AMP_STREAM_LOOP(i, np, wg) {
         const V4<TP> pv4 = ld4(p, i);
         V4<double> xv = ld4(B.x, i);
         V4<TR> rv = ld4(r, i);
@@ -460,11 +477,12 @@ __device__ __forceinline__ void update_body(double alpha, const Bufs &B, const v
     }
 }
 
-__global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+__device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
+                                             Wg wg) {
     __shared__ St s;
     load_state(s, in);
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     const double gam = reduce_sum(B.part_spmv, c.g_slice);
@@ -474,36 +492,44 @@ __global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const 
         s.alpha = s.rho / gam;
         s.maxp = mp;
         if (!(gam > 0.0) || !isfinite(s.alpha)) s.status = BREAKDOWN;
+        if (wg.lb == 0 && c.scalar_history) {
+            c.scalar_history[4 * s.k + 2] = gam;
+            c.scalar_history[4 * s.k + 3] = s.alpha;
+        }
     }
     __syncthreads();
     if (s.status != RUNNING) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     const int uz = s.uz, ur = s.ur;
     const void *p = B.p[pslot(uz)][s.pbuf ^ 1];
     double dd = 0.0, mr = 0.0;
     if (ur == 64) {
-        if (uz == 64) update_body<64, 64>(s.alpha, B, p, np, dd, mr);
-        else if (uz == 32) update_body<32, 64>(s.alpha, B, p, np, dd, mr);
-        else update_body<16, 64>(s.alpha, B, p, np, dd, mr);
+        if (uz == 64) update_body<64, 64>(s.alpha, B, p, np, wg, dd, mr);
+        else if (uz == 32) update_body<32, 64>(s.alpha, B, p, np, wg, dd, mr);
+        else update_body<16, 64>(s.alpha, B, p, np, wg, dd, mr);
     } else {
-        if (uz == 64) update_body<64, 32>(s.alpha, B, p, np, dd, mr);
-        else if (uz == 32) update_body<32, 32>(s.alpha, B, p, np, dd, mr);
-        else update_body<16, 32>(s.alpha, B, p, np, dd, mr);
+        if (uz == 64) update_body<64, 32>(s.alpha, B, p, np, wg, dd, mr);
+        else if (uz == 32) update_body<32, 32>(s.alpha, B, p, np, wg, dd, mr);
+        else update_body<16, 32>(s.alpha, B, p, np, wg, dd, mr);
     }
     dd = block_sum(dd);
     mr = block_max(mr);
     if (threadIdx.x == 0) {
-        B.part_res[blockIdx.x] = dd;
-        B.part_res[GMAX + blockIdx.x] = 0.0;
-        B.part_res[2 * GMAX + blockIdx.x] = mr;
+        B.part_res[wg.lb] = dd;
+        B.part_res[GMAX + wg.lb] = 0.0;
+        B.part_res[2 * GMAX + wg.lb] = mr;
         s.pbuf ^= 1;
         s.p_store = uz;
         s.iters = s.k + 1;
         s.kind = RES_UPDATE;
     }
-    store_state(s, out);
+    store_state(s, out, wg);
+}
+
+__global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
+    update_stage(c, B, np, in, out, grid_wg());
 }
 
 // ----------------------------------------------------------------------------
@@ -514,16 +540,14 @@ __global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const 
 // ----------------------------------------------------------------------------
 
 template <int RS>
-__device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, bool write, double &st,
+__device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, Wg wg, bool write, double &st,
                                               double &ss, double &mr) {
     typedef typename Prec<RS>::T TR;
     TR *r = (TR *)B.r[pslot(RS)];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl) {
-        const int lane = threadIdx.x % WAVE;
-        const int64_t row = sl * SLICE + lane, base = A.sptr[sl] + lane;
-        const int w = (int)((A.sptr[sl + 1] - A.sptr[sl]) / SLICE);
-        const double t = B.b[row] - row_dot64(A, base, w, [&](int32_t c) { return x[c]; });
+    AMP_SLICE_LOOP(A, sl, wg) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
+        const double t = B.b[row] - row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; });
         const TR tr = (TR)t;
         if (write) r[row] = tr;
         st += t * t;
@@ -532,24 +556,25 @@ __device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, bool
     }
 }
 
-__global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
+__device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, const Bufs &B, int mode, const St *in,
+                                               St *out, Wg wg) {
     __shared__ St s;
     load_state(s, in);
     const bool run = (mode == 0 && s.status == NEED_VERIFY) || (mode == 1 && s.status == RUNNING) || mode == 2;
     if (!run) {
-        store_state(s, out);
+        store_state(s, out, wg);
         return;
     }
     double st = 0.0, ss = 0.0, mr = 0.0;
-    if (s.r_store == 64) true_res_body<64>(A, B, mode != 2, st, ss, mr);
-    else true_res_body<32>(A, B, mode != 2, st, ss, mr);
+    if (s.r_store == 64) true_res_body<64>(A, B, wg, mode != 2, st, ss, mr);
+    else true_res_body<32>(A, B, wg, mode != 2, st, ss, mr);
     st = block_sum(st);
     ss = block_sum(ss);
     mr = block_max(mr);
     if (threadIdx.x == 0) {
-        B.part_res[blockIdx.x] = st;
-        B.part_res[GMAX + blockIdx.x] = ss;
-        B.part_res[2 * GMAX + blockIdx.x] = mr;
+        B.part_res[wg.lb] = st;
+        B.part_res[GMAX + wg.lb] = ss;
+        B.part_res[2 * GMAX + wg.lb] = mr;
         if (mode == 0) {
             s.status = RUNNING;
             s.kind = RES_VERIFY;
@@ -557,7 +582,11 @@ __global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode
             s.kind = RES_PERIODIC;
         }
     }
-    store_state(s, out);
+    store_state(s, out, wg);
+}
+
+__global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
+    true_res_stage(c, A, B, mode, in, out, grid_wg());
 }
 
 // Fixed-order total of G partials into *out (one work-group).
@@ -580,7 +609,8 @@ __global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double
     const TZ *dv = (const TZ *)B.dinv[pslot(UZ)];
     const TR w = (TR)omega_eff;
     double rho = 0.0;
-    AMP_STREAM_LOOP(i, np) {
+    const Wg wg = grid_wg();
+    AMP_STREAM_LOOP(i, np, wg) {
         const V4<TR> rv = ld4(r, i);
         const V4<TZ> dd = ld4(dv, i);
         V4<TZ> zz;
@@ -593,7 +623,7 @@ __global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double
         st4(z, i, zz);
     }
     rho = block_sum(rho);
-    if (threadIdx.x == 0) part[blockIdx.x] = rho;
+    if (threadIdx.x == 0) part[wg.lb] = rho;
 }
 
 }  // namespace amp

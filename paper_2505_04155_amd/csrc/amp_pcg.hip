@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "amp_batch.hpp"
 #include "amp_cheb.hpp"
 #include "amp_fv.hpp"
 #include "amp_kernels.hpp"
@@ -90,9 +91,10 @@ enum {
 };
 
 struct amp_matrix_s {
-    int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0;
+    int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
     int64_t *sptr = nullptr;
     int32_t *col = nullptr;
+    int32_t *soff = nullptr, *offs = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr, *v32p = nullptr;
     double *diag = nullptr;       // diag(A), 1 on padding rows
@@ -100,6 +102,7 @@ struct amp_matrix_s {
     Sell sell() const {
         Sell s;
         s.n = n; s.np = np; s.nslices = nslices; s.sptr = sptr; s.col = col;
+        s.soff = soff; s.offs = offs;
         s.v64 = v64; s.v32 = v32; s.v32p = v32p;
         return s;
     }
@@ -122,7 +125,8 @@ struct amp_precond_s {
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
     Cheb cheb() const {
         Cheb P;
-        P.sptr = A->sptr; P.col = A->col; P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
+        P.sptr = A->sptr; P.col = A->col; P.soff = A->soff; P.offs = A->offs;
+        P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
         P.v = cv; P.res = cres; P.w = cw; P.dir[0] = cdir[0]; P.dir[1] = cdir[1];
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
         for (int i = 0; i < kChebMax; ++i) { P.c1[i] = c1[i]; P.c2[i] = c2[i]; }
@@ -209,63 +213,144 @@ static Bufs make_bufs(amp_matrix A, amp_precond M) {
 // CSR -> sliced ELL
 // ----------------------------------------------------------------------------
 
-__global__ void k_slice_width(const int32_t *rp, int64_t n, int64_t nslices, int32_t *width) {
+// One thread per row: row_ptr bounds and order (err bit 16; rp[0] = 0 and
+// rp[n] = nnz are checked by thread 0), then -- only for a row whose bounds
+// are sound, so every read stays inside col_idx -- columns in range (bit 1)
+// and strictly ascending (bit 32).
+__global__ void k_check_csr(const int32_t *rp, const int32_t *ci, int64_t n, int64_t nnz, int *err) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    if (row == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(err, 16);
+    const int32_t beg = rp[row], end = rp[row + 1];
+    if (beg < 0 || end < beg || (int64_t)end > nnz) {
+        atomicOr(err, 16);
+        return;
+    }
+    int32_t prev = -1;
+    for (int32_t j = beg; j < end; ++j) {
+        const int32_t c = ci[j];
+        if (c < 0 || c >= n) { atomicOr(err, 1); return; }
+        if (c <= prev) { atomicOr(err, 32); return; }
+        prev = c;
+    }
+}
+
+static amp_status check_csr(const amp_csr *csr, hipStream_t st, const char *who) {
+    int *err = nullptr;
+    AMP_TRY(dalloc(&err, 1));
+    int herr = 0;
+    hipError_t e0 = hipMemsetAsync(err, 0, sizeof(int), st);
+    if (e0 == hipSuccess) {
+        k_check_csr<<<(unsigned)((csr->n + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->n, csr->nnz,
+                                                                      err);
+        e0 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    }
+    hipError_t e1 = hipStreamSynchronize(st);
+    dfree(err);
+    if (e0 != hipSuccess || e1 != hipSuccess)
+        return fail(AMP_ERR_HIP, std::string(who) + ": CSR check failed: " + hipGetErrorString(e0 != hipSuccess ? e0 : e1));
+    if (herr & 16) return fail(AMP_ERR_ARG, std::string(who) + ": row_ptr is not a valid CSR row pointer for nnz");
+    if (herr & 1) return fail(AMP_ERR_ARG, std::string(who) + ": column index out of range");
+    if (herr & 32) return fail(AMP_ERR_ARG, std::string(who) + ": columns not strictly ascending within a row");
+    return AMP_OK;
+}
+
+// One thread per slice: the longest row, and the sorted union of the column
+// offsets (col - row) of the slice's rows (count -1 when it exceeds kOffMax).
+__global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, int64_t nslices, int32_t *maxlen,
+                             int32_t *ucount, int32_t *uoffs) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
-    int32_t w = 0;
+    int32_t w = 0, cnt = 0;
+    int32_t *u = uoffs + s * kOffMax;
     for (int l = 0; l < SLICE; ++l) {
         const int64_t row = s * SLICE + l;
-        if (row < n) {
-            const int32_t len = rp[row + 1] - rp[row];
-            w = len > w ? len : w;
+        if (row >= n) break;
+        const int32_t beg = rp[row], len = rp[row + 1] - beg;
+        w = len > w ? len : w;
+        for (int j = 0; j < len && cnt >= 0; ++j) {
+            const int64_t o64 = (int64_t)ci[beg + j] - row;
+            if (o64 < INT32_MIN || o64 > INT32_MAX) { cnt = -1; break; }
+            const int32_t o = (int32_t)o64;
+            int pos = 0;
+            while (pos < cnt && u[pos] < o) ++pos;
+            if (pos < cnt && u[pos] == o) continue;
+            if (cnt == kOffMax) { cnt = -1; break; }
+            for (int t = cnt; t > pos; --t) u[t] = u[t - 1];
+            u[pos] = o;
+            ++cnt;
         }
     }
-    width[s] = w;
+    maxlen[s] = w;
+    ucount[s] = cnt;
+}
+
+__global__ void k_copy_offsets(const int32_t *soff, const int32_t *ucount, const int32_t *uoffs, int64_t nslices,
+                               int32_t *offs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices || soff[s] < 0) return;
+    for (int j = 0; j < ucount[s]; ++j) offs[soff[s] + j] = uoffs[s * kOffMax + j];
 }
 
 // One thread per (padded) row: copy its entries into its slice's column-major
-// slots, form the FP64 row sum, check column range and the diagonal.
+// slots (index mode: entry order; offset mode: the slot of the entry's
+// offset), form the FP64 row sum, check columns, the diagonal and the slot
+// structure.  err bits: 1 column out of range, 2 missing or non-positive
+// diagonal, 4 entry that does not fit the slice layout.
 __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, int64_t n, int64_t np,
-                       const int64_t *sptr, int32_t *col, double *v64, float *v32, float *v32p,
-                       double *diag, int *err) {
+                       const int64_t *sptr, const int32_t *soff, const int32_t *offs, int32_t *col, double *v64,
+                       float *v32, float *v32p, double *diag, int *err) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= np) return;
     const int64_t s = row / SLICE, lane = row % SLICE;
     const int w = (int)((sptr[s + 1] - sptr[s]) / SLICE);
     const int64_t b = sptr[s] + lane;
+    const int32_t so = soff[s];
     int len = 0, beg = 0;
     double rs = 0.0, d = 0.0;
     bool has_diag = false;
     if (row < n) {
         beg = rp[row];
         len = rp[row + 1] - beg;
-        if (len > w) {             // only possible when refilling with another pattern
+        if (len > w) {
             atomicOr(err, 4);
             return;
         }
         for (int j = 0; j < len; ++j) rs += val[beg + j];
     }
+    // empty slots first
     for (int j = 0; j < w; ++j) {
         const int64_t slot = b + (int64_t)j * SLICE;
-        if (j < len) {
-            const int32_t c = ci[beg + j];
-            const double v = val[beg + j];
-            if (c < 0 || c >= n) atomicOr(err, 1);
-            col[slot] = c;
-            v64[slot] = v;
-            v32p[slot] = (float)v;
-            if (c == row) {
-                has_diag = true;
-                d = v;
-                v32[slot] = (float)rs;
-            } else {
-                v32[slot] = (float)v;
+        col[slot] = (int32_t)row;
+        v64[slot] = 0.0;
+        v32[slot] = 0.0f;
+        v32p[slot] = 0.0f;
+    }
+    for (int j = 0; j < len; ++j) {
+        const int32_t c = ci[beg + j];
+        const double v = val[beg + j];
+        if (c < 0 || c >= n) atomicOr(err, 1);
+        int js = j;
+        if (so >= 0) {
+            const int64_t o = (int64_t)c - row;
+            js = -1;
+            for (int t = 0; t < w; ++t)
+                if (offs[so + t] == o) { js = t; break; }
+            if (js < 0) {
+                atomicOr(err, 4);
+                return;
             }
+        }
+        const int64_t slot = b + (int64_t)js * SLICE;
+        col[slot] = c;
+        v64[slot] = v;
+        v32p[slot] = (float)v;
+        if (c == row) {
+            has_diag = true;
+            d = v;
+            v32[slot] = (float)rs;
         } else {
-            col[slot] = (int32_t)row;
-            v64[slot] = 0.0;
-            v32[slot] = 0.0f;
-            v32p[slot] = 0.0f;
+            v32[slot] = (float)v;
         }
     }
     if (row < n) {
@@ -276,7 +361,29 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
     }
 }
 
-extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_matrix *out) {
+static amp_status fill_values(amp_matrix A, const amp_csr *csr, hipStream_t st) {
+    AMP_TRY(check_csr(csr, st, "matrix fill"));
+    int *err = nullptr;
+    AMP_TRY(dalloc(&err, 1));
+    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) {
+        dfree(err);
+        return fail(AMP_ERR_HIP, "matrix fill: memset failed");
+    }
+    k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
+                                                          A->sptr, A->soff, A->offs, A->col, A->v64, A->v32,
+                                                          A->v32p, A->diag, err);
+    int herr = 0;
+    hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    dfree(err);
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(AMP_ERR_HIP, std::string("matrix fill: ") + hipGetErrorString(e2));
+    if (herr & 4) return fail(AMP_ERR_ARG, "matrix fill: entries do not fit the handle's slice layout");
+    if (herr & 1) return fail(AMP_ERR_ARG, "matrix fill: column index out of range");
+    if (herr & 2) return fail(AMP_ERR_ARG, "matrix fill: missing or non-positive diagonal entry");
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *stream, amp_matrix *out) {
     if (!out) return fail(AMP_ERR_ARG, "amp_matrix_create: out is NULL");
     *out = nullptr;
     if (!csr || !csr->row_ptr || !csr->col_idx || !csr->val)
@@ -291,67 +398,91 @@ extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_ma
     A->nnz = csr->nnz;
     A->np = round_up(A->n, PAD);
     A->nslices = A->np / SLICE;
+    const int64_t ns = A->nslices;
 
-    int32_t *width = nullptr;
-    int *err = nullptr;
-    amp_status s;
-    if ((s = dalloc(&width, A->nslices)) != AMP_OK) return bail(s);
-    if ((s = dalloc(&err, 1)) != AMP_OK) { dfree(width); return bail(s); }
-    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) {
-        dfree(width); dfree(err);
-        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: memset failed"));
-    }
-    k_slice_width<<<(unsigned)((A->nslices + 255) / 256), 256, 0, st>>>(csr->row_ptr, A->n, A->nslices, width);
-    std::vector<int32_t> hw(A->nslices);
-    std::vector<int64_t> hp(A->nslices + 1);
-    if (hipMemcpyAsync(hw.data(), width, A->nslices * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        dfree(width); dfree(err);
-        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: reading slice widths failed"));
-    }
-    hp[0] = 0;
-    for (int64_t i = 0; i < A->nslices; ++i) hp[i + 1] = hp[i] + (int64_t)hw[i] * SLICE;
-    A->slots = hp[A->nslices];
-    dfree(width);
-    if ((s = dalloc(&A->sptr, A->nslices + 1)) != AMP_OK ||
-        (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
-        (s = dalloc(&A->v32, A->slots)) != AMP_OK || (s = dalloc(&A->v32p, A->slots)) != AMP_OK ||
-        (s = dalloc(&A->diag, A->np)) != AMP_OK) {
-        dfree(err);
+    amp_status s = check_csr(csr, st, "amp_matrix_create");
+    if (s != AMP_OK) return bail(s);
+    int32_t *maxlen = nullptr, *ucount = nullptr, *uoffs = nullptr;
+    auto free_scan = [&]() { dfree(maxlen); dfree(ucount); dfree(uoffs); };
+    if ((s = dalloc(&maxlen, ns)) != AMP_OK || (s = dalloc(&ucount, ns)) != AMP_OK ||
+        (s = dalloc(&uoffs, ns * kOffMax)) != AMP_OK) {
+        free_scan();
         return bail(s);
     }
-    A->bytes = (A->nslices + 1) * 8 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
-    if (hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess) {
-        dfree(err);
-        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: upload of slice pointers failed"));
+    k_slice_scan<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, A->n, ns, maxlen, ucount,
+                                                             uoffs);
+    std::vector<int32_t> hml(ns), huc(ns), hso(ns);
+    std::vector<int64_t> hp(ns + 1);
+    if (hipMemcpyAsync(hml.data(), maxlen, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(huc.data(), ucount, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        free_scan();
+        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: reading the slice scan failed"));
     }
-    k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
-                                                          A->sptr, A->col, A->v64, A->v32, A->v32p, A->diag, err);
-    int herr = 0;
-    hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipError_t e2 = hipStreamSynchronize(st);
-    dfree(err);
-    if (e1 != hipSuccess || e2 != hipSuccess)
-        return bail(fail(AMP_ERR_HIP, std::string("amp_matrix_create: ") + hipGetErrorString(e2)));
-    if (herr & 1) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: column index out of range"));
-    if (herr & 2) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: missing or non-positive diagonal entry"));
+    // offset mode when the slice's offset list costs at most two padding slots per row
+    const bool allow = !(flags & 1);
+    int64_t noffs = 0;
+    hp[0] = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        const bool om = allow && huc[i] > 0 && huc[i] <= hml[i] + 2;
+        hso[i] = om ? (int32_t)noffs : -1;
+        if (om) { noffs += huc[i]; A->offset_slices += 1; }
+        const int64_t w = om ? huc[i] : hml[i];
+        hp[i + 1] = hp[i] + w * SLICE;
+    }
+    A->slots = hp[ns];
+    {
+        int64_t index_slots = 0;
+        for (int64_t i = 0; i < ns; ++i)
+            if (hso[i] < 0) index_slots += hp[i + 1] - hp[i];
+        A->meta_bytes = 4 * index_slots + 4 * noffs + 12 * ns + 8;
+    }
+    if (A->slots >= ((int64_t)1 << 31) * 2) {
+        free_scan();
+        return bail(fail(AMP_ERR_ARG, "amp_matrix_create: too many slots"));
+    }
+    if ((s = dalloc(&A->sptr, ns + 1)) != AMP_OK || (s = dalloc(&A->soff, ns)) != AMP_OK ||
+        (s = dalloc(&A->offs, noffs > 0 ? noffs : 1)) != AMP_OK || (s = dalloc(&A->col, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->v64, A->slots)) != AMP_OK || (s = dalloc(&A->v32, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->v32p, A->slots)) != AMP_OK || (s = dalloc(&A->diag, A->np)) != AMP_OK) {
+        free_scan();
+        return bail(s);
+    }
+    A->bytes = (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
+    if (hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess) {
+        free_scan();
+        return bail(fail(AMP_ERR_HIP, "amp_matrix_create: upload of slice tables failed"));
+    }
+    k_copy_offsets<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(A->soff, ucount, uoffs, ns, A->offs);
+    s = fill_values(A, csr, st);   // synchronises the stream (the host tables stay alive until then)
+    free_scan();
+    if (s != AMP_OK) return bail(s);
     *out = A;
     return AMP_OK;
+}
+
+extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_matrix *out) {
+    return amp_matrix_create_ex(csr, 0, stream, out);
 }
 
 extern "C" void amp_matrix_destroy(amp_matrix A) {
     if (!A) return;
     free_work(A->w);
-    dfree(A->sptr); dfree(A->col); dfree(A->v64); dfree(A->v32); dfree(A->v32p); dfree(A->diag);
+    dfree(A->sptr); dfree(A->soff); dfree(A->offs); dfree(A->col);
+    dfree(A->v64); dfree(A->v32); dfree(A->v32p); dfree(A->diag);
     delete A;
 }
 
-extern "C" amp_status amp_matrix_info(amp_matrix A, int64_t *n, int64_t *nnz, int64_t *slots, int64_t *bytes) {
-    if (!A) return fail(AMP_ERR_ARG, "amp_matrix_info: null handle");
-    if (n) *n = A->n;
-    if (nnz) *nnz = A->nnz;
-    if (slots) *slots = A->slots;
-    if (bytes) *bytes = A->bytes;
+extern "C" amp_status amp_matrix_info(amp_matrix A, amp_matrix_stats *out) {
+    if (!A || !out) return fail(AMP_ERR_ARG, "amp_matrix_info: null argument");
+    out->n = A->n;
+    out->nnz = A->nnz;
+    out->slots = A->slots;
+    out->bytes = A->bytes;
+    out->nslices = A->nslices;
+    out->offset_slices = A->offset_slices;
+    out->meta_bytes = A->meta_bytes;
     return AMP_OK;
 }
 
@@ -513,6 +644,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->batch = 0;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
+    o->scalar_history = nullptr;
 }
 
 extern "C" amp_status amp_options_preset(amp_options *o, int preset) {
@@ -538,8 +670,9 @@ static amp_status check_options(const amp_options &o) {
         return fail(AMP_ERR_ARG, "options: C, tau_zs, tau_zh must be >= 0");
     if (o.T_z < -60 || o.T_z > 15 || o.T_p < -60 || o.T_p > 15)
         return fail(AMP_ERR_ARG, "options: T_z, T_p must be in -60..15");
-    if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0)
+    if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0 || o.group_rows < 0)
         return fail(AMP_ERR_ARG, "options: negative count");
+    if (o.group_rows % NT) return fail(AMP_ERR_ARG, "options: group_rows must be a multiple of 256");
     return AMP_OK;
 }
 
@@ -562,6 +695,11 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.extra16 = M ? M->extra16 : 0;
     c.g_stream = A ? grid_stream(A->np) : 1;
     c.g_slice = A ? grid_slices(A->nslices) : 1;
+    if (A && o.group_rows > 0) {
+        // one work-group count for every kernel: G = ceil(np / group_rows)
+        const int64_t g = (A->np + o.group_rows - 1) / o.group_rows;
+        c.g_stream = c.g_slice = (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+    }
     c.g_pre = (M && M->kind == AMP_PC_CHEBYSHEV && M->degree > 1) ? c.g_slice : c.g_stream;
     c.C = o.C;
     c.tau_zs = o.tau_zs;
@@ -571,6 +709,7 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.ring = A ? A->w.ring : nullptr;
     c.delta_history = o.delta_history;
     c.prec_history = o.prec_history;
+    c.scalar_history = o.scalar_history;
     return c;
 }
 
@@ -765,6 +904,221 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
 }
 
 // ----------------------------------------------------------------------------
+// batched solve
+// ----------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kDefaultGroupRows = 4096;
+
+bool terminal(int status) { return status == CONVERGED || status == MAXIT || status == BREAKDOWN; }
+
+// Device and pinned buffers of one batched solve, released on every exit path.
+struct BatchBufs {
+    SysDesc *sd = nullptr;
+    Task *tasks = nullptr, *tasks_all = nullptr;
+    St *gath = nullptr;
+    double *red = nullptr;
+    St *snap = nullptr;       // pinned [2][nsys]
+    Task *stage = nullptr;    // pinned [2][cap]
+    double *hred = nullptr;   // pinned [nsys]
+    hipEvent_t ev[2] = {nullptr, nullptr}, evs[2] = {nullptr, nullptr};
+    ~BatchBufs() {
+        dfree(sd); dfree(tasks); dfree(tasks_all); dfree(gath); dfree(red);
+        if (snap) (void)hipHostFree(snap);
+        if (stage) (void)hipHostFree(stage);
+        if (hred) (void)hipHostFree(hred);
+        for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+        for (auto &e : evs) if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Task list of the live systems, ordered by system so that consecutive
+// logical work-group indices (one XCD's share) cover whole systems; padded
+// with sys = -1 to a multiple of the XCD count.
+void build_tasks(const std::vector<int> &G, const std::vector<char> &live, std::vector<Task> &out) {
+    out.clear();
+    for (size_t s = 0; s < G.size(); ++s)
+        if (live[s])
+            for (int lb = 0; lb < G[s]; ++lb) out.push_back(Task{(int)s, lb});
+    while (out.size() % NXCD) out.push_back(Task{-1, 0});
+}
+
+}  // namespace
+
+extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const amp_precond *M,
+                                            const double *const *b, double *const *x, const double *tol,
+                                            int maxit, const amp_options *opt, amp_result *res, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (nsys < 1) return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: nsys must be >= 1");
+    if (!A || !M || !b || !x || !tol) return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: null argument");
+    if (maxit < 0) return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: maxit must be >= 0");
+    amp_options o;
+    if (opt) o = *opt;
+    else amp_options_default(&o);
+    AMP_TRY(check_options(o));
+    if (o.delta_history || o.prec_history || o.scalar_history)
+        return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: histories are not supported");
+    if (o.rr_period > 0) return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: rr_period is not supported");
+    if (o.group_rows == 0) o.group_rows = kDefaultGroupRows;
+    {
+        std::vector<amp_matrix> seen(A, A + nsys);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: a matrix handle appears twice");
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (!A[i] || !M[i] || !b[i] || !x[i])
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: null handle or vector for system " + std::to_string(i));
+        if (M[i]->A != A[i])
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: preconditioner of system " + std::to_string(i) +
+                                         " was built for another matrix");
+        if (M[i]->kind == AMP_PC_CHEBYSHEV)
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: Chebyshev preconditioners are not supported");
+        if (!(tol[i] > 0.0) || !std::isfinite(tol[i]))
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: tol must be positive");
+    }
+    hipStream_t st = as_stream(stream);
+    for (int i = 0; i < nsys; ++i) AMP_TRY(ensure_work(A[i], st));
+
+    // per-system descriptors and work-group counts
+    std::vector<SysDesc> hsd(nsys);
+    std::vector<int> G(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        SysDesc &d = hsd[i];
+        std::memset(&d, 0, sizeof(d));
+        d.c = make_cfg(o, A[i], M[i], tol[i], maxit);   // one work-group count G for every kernel
+        G[i] = d.c.g_stream;
+        d.A = A[i]->sell();
+        d.B = make_bufs(A[i], M[i]);
+        d.st = A[i]->w.st;
+        d.bw = A[i]->w.b;
+        d.b_in = b[i];
+        d.x_io = x[i];
+        d.n = A[i]->n;
+    }
+    std::vector<char> live(nsys, 1);
+    std::vector<Task> all;
+    build_tasks(G, live, all);
+    const size_t cap = all.size();
+
+    BatchBufs bb;
+    AMP_TRY(dalloc(&bb.sd, nsys));
+    AMP_TRY(dalloc(&bb.tasks, cap));
+    AMP_TRY(dalloc(&bb.tasks_all, cap));
+    AMP_TRY(dalloc(&bb.gath, nsys));
+    AMP_TRY(dalloc(&bb.red, nsys));
+    AMP_HIP(hipHostMalloc((void **)&bb.snap, 2 * nsys * sizeof(St), hipHostMallocDefault));
+    AMP_HIP(hipHostMalloc((void **)&bb.stage, 2 * cap * sizeof(Task), hipHostMallocDefault));
+    AMP_HIP(hipHostMalloc((void **)&bb.hred, nsys * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) {
+        AMP_HIP(hipEventCreateWithFlags(&bb.ev[i], hipEventDisableTiming));
+        AMP_HIP(hipEventCreateWithFlags(&bb.evs[i], hipEventDisableTiming));
+    }
+    AMP_HIP(hipMemcpyAsync(bb.sd, hsd.data(), nsys * sizeof(SysDesc), hipMemcpyHostToDevice, st));
+    AMP_HIP(hipMemcpyAsync(bb.tasks_all, all.data(), cap * sizeof(Task), hipMemcpyHostToDevice, st));
+    AMP_HIP(hipMemcpyAsync(bb.tasks, all.data(), cap * sizeof(Task), hipMemcpyHostToDevice, st));
+    // the host vectors above are pageable: wait before they can go out of scope or change
+    AMP_HIP(hipStreamSynchronize(st));
+
+    const St s0 = init_state(o);
+    const unsigned gall = (unsigned)cap;
+    k_batch_prep<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all, s0, ST_INIT);
+    k_batch_init<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
+    AMP_HIP(hipGetLastError());
+
+    int in = ST_INIT;
+    unsigned ntask = gall;
+    const int batch = o.batch > 0 ? o.batch : 8;
+    int pending = -1, stage_next = 0, nlive = nsys;
+    std::vector<St> fin(nsys);
+    std::vector<Task> cur_tasks;
+    auto enqueue_batch = [&](int slot) -> amp_status {
+        for (int i = 0; i < batch; ++i) {
+            k_batch_precond<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, in, ST_PRE);
+            k_batch_spmv<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, ST_PRE, ST_SPMV);
+            k_batch_update<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, ST_SPMV, ST_RES);
+            in = ST_RES;
+        }
+        // termination check of every system that asks for it
+        k_batch_true_res<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, 0, in, ST_PREI);
+        in = ST_PREI;
+        k_batch_gather<<<(unsigned)((nsys + NT - 1) / NT), NT, 0, st>>>(bb.sd, nsys, in, bb.gath);
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipMemcpyAsync(bb.snap + (size_t)slot * nsys, bb.gath, nsys * sizeof(St), hipMemcpyDeviceToHost, st));
+        AMP_HIP(hipEventRecord(bb.ev[slot], st));
+        return AMP_OK;
+    };
+    for (;;) {
+        const int sl = (pending >= 0) ? (pending ^ 1) : 0;
+        AMP_TRY(enqueue_batch(sl));
+        if (pending < 0) {
+            pending = sl;
+            continue;
+        }
+        AMP_HIP(hipEventSynchronize(bb.ev[pending]));
+        const St *snap = bb.snap + (size_t)pending * nsys;
+        pending = sl;
+        int stopped = 0;
+        for (int i = 0; i < nsys; ++i) {
+            if (live[i] && terminal(snap[i].status)) {
+                live[i] = 0;
+                fin[i] = snap[i];
+                ++stopped;
+            }
+        }
+        nlive -= stopped;
+        if (nlive == 0) break;
+        if (stopped) {
+            // drop the stopped systems from every launch enqueued from now on
+            build_tasks(G, live, cur_tasks);
+            Task *stg = bb.stage + (size_t)stage_next * cap;
+            AMP_HIP(hipEventSynchronize(bb.evs[stage_next]));
+            std::memcpy(stg, cur_tasks.data(), cur_tasks.size() * sizeof(Task));
+            AMP_HIP(hipMemcpyAsync(bb.tasks, stg, cur_tasks.size() * sizeof(Task), hipMemcpyHostToDevice, st));
+            AMP_HIP(hipEventRecord(bb.evs[stage_next], st));
+            stage_next ^= 1;
+            ntask = (unsigned)cur_tasks.size();
+        }
+    }
+    AMP_HIP(hipEventSynchronize(bb.ev[pending]));
+
+    // solutions out, and the FP64 true residual of every returned x
+    k_batch_copy_out<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
+    k_batch_report<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
+    k_batch_reduce_report<<<(unsigned)nsys, NT, 0, st>>>(bb.sd, nsys, bb.red);
+    AMP_HIP(hipGetLastError());
+    AMP_HIP(hipMemcpyAsync(bb.hred, bb.red, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipStreamSynchronize(st));
+
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    amp_status worst = AMP_OK;
+    for (int i = 0; i < nsys; ++i) {
+        const St &c = fin[i];
+        amp_status rs = AMP_OK;
+        if (c.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
+        else if (c.status == BREAKDOWN) rs = AMP_ERR_BREAKDOWN;
+        if (rs == AMP_ERR_BREAKDOWN || (rs == AMP_ERR_NOT_CONVERGED && worst == AMP_OK)) worst = rs;
+        if (res) {
+            amp_result &r = res[i];
+            r.iters = c.iters;
+            r.status = rs;
+            r.bnorm = c.bnorm;
+            r.rel_res_updated = c.bnorm > 0 ? c.delta / c.bnorm : 0.0;
+            r.rel_res_true = c.bnorm > 0 ? std::sqrt(bb.hred[i]) / c.bnorm : 0.0;
+            r.k_z32 = c.k_z32;
+            r.k_z16 = c.k_z16;
+            r.k_r32 = c.k_r32;
+            r.n_replacements = c.n_repl;
+            r.t_solve_ms = ms;
+        }
+    }
+    if (worst == AMP_ERR_NOT_CONVERGED) g_last_error = "amp_pcg_solve_batched: a system did not converge within maxit";
+    if (worst == AMP_ERR_BREAKDOWN) g_last_error = "amp_pcg_solve_batched: a system broke down";
+    return worst;
+}
+
+// ----------------------------------------------------------------------------
 // single-kernel entry points (tests, measurement)
 // ----------------------------------------------------------------------------
 
@@ -956,24 +1310,7 @@ extern "C" amp_status amp_matrix_update_values(amp_matrix A, const amp_csr *csr,
         return fail(AMP_ERR_ARG, "amp_matrix_update_values: null argument");
     if (csr->n != A->n || csr->nnz != A->nnz)
         return fail(AMP_ERR_ARG, "amp_matrix_update_values: size differs from the handle's");
-    hipStream_t st = as_stream(stream);
-    int *err = nullptr;
-    AMP_TRY(dalloc(&err, 1));
-    if (hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess) {
-        dfree(err);
-        return fail(AMP_ERR_HIP, "amp_matrix_update_values: memset failed");
-    }
-    k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
-                                                          A->sptr, A->col, A->v64, A->v32, A->v32p, A->diag, err);
-    int herr = 0;
-    hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipError_t e2 = hipStreamSynchronize(st);
-    dfree(err);
-    if (e1 != hipSuccess || e2 != hipSuccess) return fail(AMP_ERR_HIP, "amp_matrix_update_values: fill failed");
-    if (herr & 4) return fail(AMP_ERR_ARG, "amp_matrix_update_values: row lengths differ from the handle's");
-    if (herr & 1) return fail(AMP_ERR_ARG, "amp_matrix_update_values: column index out of range");
-    if (herr & 2) return fail(AMP_ERR_ARG, "amp_matrix_update_values: missing or non-positive diagonal entry");
-    return AMP_OK;
+    return fill_values(A, csr, as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------
@@ -990,6 +1327,7 @@ extern "C" amp_status amp_selector_replay(const double *delta, int len, double b
     AMP_TRY(check_options(o));
     o.delta_history = nullptr;
     o.prec_history = nullptr;
+    o.scalar_history = nullptr;
     Cfg c = make_cfg(o, nullptr, nullptr, tol, len);
     std::vector<double> ring(kRing, 0.0);
     St s = init_state(o);

@@ -38,7 +38,7 @@ def _need(t: torch.Tensor, dtype, n=None, name="tensor"):
 class Matrix:
     """Solver-side matrix (sliced ELL, FP64 and FP32 value planes)."""
 
-    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor):
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, offsets: bool = True):
         L = B.load()
         n = row_ptr.numel() - 1
         _need(row_ptr, torch.int32, name="row_ptr")
@@ -46,27 +46,28 @@ class Matrix:
         _need(val, torch.float64, col_idx.numel(), name="val")
         csr = B.Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
         h = ctypes.c_void_p()
-        B.check(L.amp_matrix_create(ctypes.byref(csr), _stream(), ctypes.byref(h)), "amp_matrix_create")
+        B.check(L.amp_matrix_create_ex(ctypes.byref(csr), 0 if offsets else 1, _stream(), ctypes.byref(h)),
+                "amp_matrix_create")
         self._h = h
         self.n = n
         self.nnz = col_idx.numel()
 
     @classmethod
-    def from_csr(cls, csr, device="cuda"):
+    def from_csr(cls, csr, device="cuda", offsets: bool = True):
         """From a workloads.CSR (host numpy arrays)."""
         rp = torch.from_numpy(csr.row_ptr).to(device)
         ci = torch.from_numpy(csr.col_idx).to(device)
         v = torch.from_numpy(csr.val).to(device)
-        return cls(rp, ci, v)
+        return cls(rp, ci, v, offsets=offsets)
 
     @property
     def handle(self):
         return self._h
 
     def info(self):
-        vals = [ctypes.c_int64() for _ in range(4)]
-        B.check(B.load().amp_matrix_info(self._h, *[ctypes.byref(v) for v in vals]), "amp_matrix_info")
-        return dict(n=vals[0].value, nnz=vals[1].value, slots=vals[2].value, bytes=vals[3].value)
+        st = B.MatrixStats()
+        B.check(B.load().amp_matrix_info(self._h, ctypes.byref(st)), "amp_matrix_info")
+        return {name: getattr(st, name) for name, _ in B.MatrixStats._fields_}
 
     def spmv(self, p: torch.Tensor, u_r: int = 64, diff: bool = True):
         """q = A p with the solver's kernel; p's dtype selects its storage
@@ -129,12 +130,14 @@ def solve(A: Matrix, M: Preconditioner, b: torch.Tensor, x0: torch.Tensor | None
     x = torch.zeros_like(b) if x0 is None else x0.detach().clone()
     _need(x, torch.float64, A.n, "x0")
     o = B.make_options(preset, **opts)
-    dh = ph = None
+    dh = ph = sh = None
     if history:
         dh = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device)
         ph = torch.full((max(maxit, 1),), -1, dtype=torch.int32, device=b.device)
+        sh = torch.full((4 * max(maxit, 1),), float("nan"), dtype=torch.float64, device=b.device)
         o.delta_history = dh.data_ptr()
         o.prec_history = ph.data_ptr()
+        o.scalar_history = sh.data_ptr()
     res = B.Result()
     st = L.amp_pcg_solve(A.handle, M.handle, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(o),
                          ctypes.byref(res), _stream())
@@ -149,7 +152,42 @@ def solve(A: Matrix, M: Preconditioner, b: torch.Tensor, x0: torch.Tensor | None
         ph_h = ph[:it].cpu().numpy()
         info["uz"] = (ph_h & 0xFF).tolist()
         info["ur"] = (ph_h >> 8).tolist()
+        scal = sh[: 4 * it].cpu().numpy().reshape(-1, 4)
+        info["omega"], info["rho"], info["gamma"], info["alpha"] = (scal[:, j] for j in range(4))
     return x, info
+
+
+def solve_batched(As, Ms, bs, x0s=None, tol=1e-10, maxit: int = 5000, preset: str = "amp64",
+                  raise_on_error: bool = False, **opts):
+    """Solve the independent systems As[i] x = bs[i] in one lockstep batched
+    solve.  tol: a float or one per system.  Returns (xs, infos, status)."""
+    L = B.load()
+    n = len(As)
+    if not (len(Ms) == len(bs) == n) or n == 0:
+        raise ValueError("As, Ms and bs must be non-empty and of equal length")
+    xs = []
+    for i in range(n):
+        _need(bs[i], torch.float64, As[i].n, f"b[{i}]")
+        x = torch.zeros_like(bs[i]) if x0s is None or x0s[i] is None else x0s[i].detach().clone()
+        _need(x, torch.float64, As[i].n, f"x0[{i}]")
+        xs.append(x)
+    tols = [float(tol)] * n if isinstance(tol, (int, float)) else [float(t) for t in tol]
+    vp = ctypes.c_void_p
+    a_arr = (vp * n)(*[A.handle.value for A in As])
+    m_arr = (vp * n)(*[M.handle.value for M in Ms])
+    b_arr = (vp * n)(*[b.data_ptr() for b in bs])
+    x_arr = (vp * n)(*[x.data_ptr() for x in xs])
+    t_arr = (ctypes.c_double * n)(*tols)
+    res = (B.Result * n)()
+    o = B.make_options(preset, **opts)
+    st = L.amp_pcg_solve_batched(n, a_arr, m_arr, b_arr, x_arr, t_arr, int(maxit), ctypes.byref(o), res,
+                                 _stream())
+    if st in (B.AMP_ERR_ARG, B.AMP_ERR_HIP, B.AMP_ERR_OOM) or (raise_on_error and st != B.AMP_OK):
+        B.check(st, "amp_pcg_solve_batched")
+    infos = [dict(status=r.status, iters=r.iters, relres=r.rel_res_updated, relres_true=r.rel_res_true,
+                  bnorm=r.bnorm, k_z32=r.k_z32, k_z16=r.k_z16, k_r32=r.k_r32, replacements=r.n_replacements,
+                  t_solve_ms=r.t_solve_ms) for r in res]
+    return xs, infos, st
 
 
 def selector_replay(delta, bnorm: float, tol: float, preset: str = "amp64", **opts):

@@ -51,6 +51,33 @@ def test_spmv_integer_exact(amp, m, u_r, diff, u_p):
     assert g.item() == float(ref @ p)
 
 
+@pytest.mark.parametrize("case", ["poisson37", "blocky24", "q1_10", "dense12"])
+@pytest.mark.parametrize("u_r,diff,u_p", [(64, False, 64), (64, False, 16), (32, True, 16), (32, False, 32)])
+def test_offset_slices_match_index_slices(amp, case, u_r, diff, u_p):
+    # shared per-slice column offsets only change how columns are found:
+    # the nonzero terms are added in the same order, so results are identical
+    _say(f"offset vs index slices {case} u_r={u_r} diff={diff} u_p={u_p}")
+    if case == "poisson37":
+        A = P.stencil_poisson2d(37)
+    elif case == "blocky24":
+        A = P.blocky_diffusion3d_system(24, 4)[0]
+    elif case == "q1_10":
+        A = P.q1_anisotropic(10)
+    else:
+        A = P.dense_to_csr(P.spectrum_matrix(np.linspace(1, 3, 12), seed=(320, 0)))
+    p = np.random.default_rng([321, 0]).standard_normal(A.n).astype({64: np.float64, 32: np.float32, 16: np.float16}[u_p])
+    Mo = amp.Matrix.from_csr(A, offsets=True)
+    Mi = amp.Matrix.from_csr(A, offsets=False)
+    io, ii = Mo.info(), Mi.info()
+    if case != "dense12":
+        assert io["offset_slices"] > 0
+    assert ii["offset_slices"] == 0
+    qo, go = Mo.spmv(torch.tensor(p, device="cuda"), u_r=u_r, diff=diff)
+    qi, gi = Mi.spmv(torch.tensor(p, device="cuda"), u_r=u_r, diff=diff)
+    assert torch.equal(qo, qi)
+    assert go.item() == gi.item()
+
+
 def test_spmv_fp64_matches_oracle(amp):
     _say("spmv fp64 vs oracle, blocky 24^3")
     A, _, _ = P.blocky_diffusion3d_system(24, 4)
@@ -111,3 +138,18 @@ def test_matrix_handle_rejects_bad_input(amp):
     bad = P.CSR(3, np.array([0, 1, 2, 3], np.int32), np.array([0, 5, 2], np.int32), np.ones(3))
     with pytest.raises(B.AmpError):
         amp.Matrix.from_csr(bad)
+    # row pointers out of order / past nnz, unsorted and duplicate columns:
+    # all rejected by the device-side check before any entry is gathered
+    cases = [
+        ([0, 2, 1, 4], [0, 1, 1, 2]),
+        ([0, 2, 3, 9], [0, 1, 1, 2]),
+        ([0, 2, 3, 4], [1, 0, 1, 2]),
+        ([0, 2, 3, 4], [0, 0, 1, 2]),
+    ]
+    for rp, ci in cases:
+        _say(f"reject rp={rp} ci={ci}")
+        c = P.CSR(3, np.array(rp, np.int32), np.array(ci, np.int32), np.array([2.0, -1.0, 2.0, 2.0]))
+        for offsets in (True, False):
+            with pytest.raises(B.AmpError) as e:
+                amp.Matrix.from_csr(c, offsets=offsets)
+            assert e.value.status == B.AMP_ERR_ARG

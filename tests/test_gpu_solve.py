@@ -118,6 +118,12 @@ def test_amp_matches_model(amp, case, preset, kw):
     bad = np.nonzero(rel > 1e-3)[0]
     _say(f"  gpu iters {info['iters']} model {ref.iters}; first |delta| divergence > 1e-3 at "
          f"{bad[0] if bad.size else None}; early rel diffs {np.array2string(rel[:12], precision=1)}")
+    k = min(12, len(ref.omega), len(info["omega"]))
+    _say(f"  omega gpu {np.log2(info['omega'][:k]).astype(int).tolist()} model "
+         f"{np.log2(np.asarray(ref.omega[:k])).astype(int).tolist()}")
+    for name in ("rho", "gamma", "alpha"):
+        g_, m_ = np.asarray(info[name][:k]), np.asarray(getattr(ref, name)[:k])
+        _say(f"  {name} rel diff {np.array2string(np.abs(g_ - m_) / np.abs(m_), precision=1)}")
     # the GPU's own history through the oracle's selector reproduces its switch points
     kz32, kz16, kr = am.replay_switches(list(info["delta"][:info["iters"]]), info["bnorm"], 1e-10,
                                         am.options(preset, **kw))

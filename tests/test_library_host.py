@@ -73,3 +73,29 @@ def test_option_validation():
         S.selector_replay([1.0, 0.5], 1.0, 1e-10, "amp64", u0=8)
     with pytest.raises(B.AmpError):
         S.selector_replay([1.0], 0.0, 1e-10, "amp64")
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    # the binding's struct mirrors must have the C compiler's sizes and offsets
+    structs = {"amp_csr": B.Csr, "amp_options": B.Options, "amp_result": B.Result,
+               "amp_matrix_stats": B.MatrixStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "amp_pcg.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
