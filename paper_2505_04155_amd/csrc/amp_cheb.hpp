@@ -55,7 +55,7 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
         for (int e = 0; e < VEC; ++e) {
             const TR re = (TR)rv.v[e];
             rr.v[e] = re;
-            const TZ y = (TZ)(re * w);
+            const TZ y = narrow<TZ>(re * w);
             vv.v[e] = iv.v[e] * (CZ)y;
         }
         st4(v, i, vv);
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64,
         const double si = isq64[row];
         for (int j = 0; j < w; ++j) {
             const int64_t sidx = base + (int64_t)j * SLICE;
-            b16[sidx] = (half_t)((A.v64[sidx] * si) * isq64[sc(j)]);
+            b16[sidx] = narrow<half_t>((A.v64[sidx] * si) * isq64[sc(j)]);
         }
     }
 }

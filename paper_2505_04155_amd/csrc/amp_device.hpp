@@ -19,6 +19,29 @@ constexpr int GMAX = 1024;   // upper bound on work-groups of a reducing kernel
 constexpr int PAD = NT * VEC;  // internal vectors are padded to a multiple of this
 constexpr int NXCD = 8;      // accelerator complex dies; work-groups are dealt to them round-robin
 
+// Round x to the storage type T once, to nearest even.  FP64 -> FP16 is not
+// a plain cast (that rounds to FP32 first and then to FP16: two roundings):
+// x is rounded to FP32 with round-to-odd (the RNE result, moved to its odd
+// neighbour towards x when inexact and even), and that value rounded to
+// FP16; with 24 >= 11 + 2 significand bits the result is the correctly
+// rounded FP16 value of x (Boldo and Melquiond, "When double rounding is
+// odd", 2005).
+template <typename T>
+__device__ __forceinline__ T narrow(double x) {
+    return (T)x;
+}
+template <>
+__device__ __forceinline__ _Float16 narrow<_Float16>(double x) {
+    float f = (float)x;
+    if ((double)f != x && !__builtin_isinf(f) && !__builtin_isnan(f) && !(__float_as_uint(f) & 1u))
+        f = nextafterf(f, (double)f < x ? __builtin_inff() : -__builtin_inff());
+    return (_Float16)f;
+}
+template <typename T>
+__device__ __forceinline__ T narrow(float x) {
+    return (T)x;
+}
+
 template <int U> struct Prec;
 template <> struct Prec<64> { typedef double T; typedef double C; };
 template <> struct Prec<32> { typedef float T; typedef float C; };

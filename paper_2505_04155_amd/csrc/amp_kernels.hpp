@@ -272,7 +272,7 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
         for (int e = 0; e < VEC; ++e) {
             const TR re = (TR)rv.v[e];
             rr.v[e] = re;
-            const TZ y = (TZ)(re * w);                 // computed in u_r, stored in u_z
+            const TZ y = narrow<TZ>(re * w);           // computed in u_r, stored in u_z
             const TZ ze = (TZ)((CZ)y * (CZ)dd.v[e]);   // computed and stored in u_z
             zz.v[e] = ze;
             rho += (double)re * (double)ze;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np, Wg 
         const V4<TPS> a = ld4(po, i);
         V4<TZ> b;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) b.v[e] = (TZ)a.v[e];
+        for (int e = 0; e < VEC; ++e) b.v[e] = narrow<TZ>(a.v[e]);
         st4(pn, i, b);
     }
 }
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(NT) k_precond_fixed(Bufs B, int64_t np, double
         V4<TZ> zz;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const TZ y = (TZ)(rv.v[e] * w);
+            const TZ y = narrow<TZ>(rv.v[e] * w);
             zz.v[e] = (TZ)((CZ)y * (CZ)dd.v[e]);
             rho += (double)rv.v[e] * (double)zz.v[e];
         }

@@ -515,7 +515,7 @@ __global__ void k_identity_setup(int64_t n, int64_t np, double *d64, float *d32,
 
 __global__ void k_scale_to_half(const double *d64, int64_t np, double scale, half_t *d16) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < np) d16[i] = (half_t)(d64[i] * scale);
+    if (i < np) d16[i] = narrow<half_t>(d64[i] * scale);
 }
 
 // Values of the preconditioner that depend on A's entries (also rerun by

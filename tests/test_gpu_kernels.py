@@ -129,6 +129,34 @@ def test_jacobi_apply_matches_model(amp, u_r, u_z):
     assert rho.item() == pytest.approx(rho_ref, rel=1e-13)
 
 
+def _near_half_ties(seed):
+    g = np.random.default_rng([seed, 0])
+    x = g.standard_normal(20000) * 2.0 ** g.integers(-26, 15, 20000)
+    h = x.astype(np.float16).astype(np.float64)
+    ulp = np.spacing(np.abs(x.astype(np.float16))).astype(np.float64)
+    ties = np.sign(x) * (np.abs(h) + ulp / 2)
+    xs = np.concatenate([x, ties, ties * (1 + 2.0 ** -40), ties * (1 - 2.0 ** -40), ties * (1 + 2.0 ** -29),
+                         ties * (1 - 2.0 ** -29), [0.0, -0.0, 1e-300, -1e-300, 2.0 ** -25,
+                                                  2.0 ** -25 * (1 + 2.0 ** -50), 65519.99, -65519.99]])
+    return xs[np.abs(xs) < 65504]
+
+
+def test_fp64_to_fp16_rounds_once(amp):
+    # identity preconditioner and omega = 1: z = fl16(r) rounded directly
+    # from FP64 (a cast through FP32 would round twice near FP16 ties)
+    _say("fp64 -> fp16 single rounding")
+    xs = _near_half_ties(310)
+    n = xs.size
+    I = P.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    M = amp.Matrix.from_csr(I)
+    pc = amp.Preconditioner(M, "identity")
+    z, _ = pc.apply(torch.tensor(xs, device="cuda"), u_z=16, omega=1.0)
+    got = z.cpu().numpy()
+    ref = xs.astype(np.float16)
+    assert np.array_equal(got.view(np.uint16), ref.view(np.uint16))
+    assert np.count_nonzero(xs.astype(np.float32).astype(np.float16) != ref) > 1000   # the cases matter
+
+
 def test_matrix_handle_rejects_bad_input(amp):
     from paper_2505_04155_amd import binding as B
     A = P.dense_to_csr(np.diag([1.0, -2.0, 3.0]))
