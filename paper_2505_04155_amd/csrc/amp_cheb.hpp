@@ -107,9 +107,9 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 }
 
 // One step k of the recurrence for this work-group's slices.
-template <int UZ>
-__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int first,
-                                               int last, int din, double &rho, double &mz) {
+template <int UZ, bool FIRST>
+__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int last,
+                                               int din, double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
     const CZ *v = (const CZ *)P.v;
@@ -122,32 +122,38 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     TZ *z = (TZ *)B.z[pslot(UZ)];
     const int ur = s.ur;
-    auto dval = [&](int64_t j) -> CZ { return first ? v[j] * inv_theta : dk[j]; };
+    const bool first = FIRST;
+    auto dval = [&](int64_t j) -> CZ {
+        if (FIRST) return v[j] * inv_theta;
+        return dk[j];
+    };
     int64_t slo_, shi_;
     block_range(P.nslices, 1, wg.lb, wg.G, slo_, shi_);
     const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     for (int64_t sl = sfirst; sl < shi_; sl += NT / WAVE) {
         const int lane = threadIdx.x % WAVE;
         const int64_t row = sl * SLICE + lane, base = P.sptr[sl] + lane;
-        const int wd = (int)((P.sptr[sl + 1] - P.sptr[sl]) / SLICE);
-        const SliceCols sc = slice_cols(P.sptr, P.col, P.soff, P.offs, P.np, sl, lane);
+        const int wd = __builtin_amdgcn_readfirstlane((int)((P.sptr[sl + 1] - P.sptr[sl]) / SLICE));
         CZ acc = (CZ)0;
-        int j = 0;
-        for (; j + 4 <= wd; j += 4) {
-            int64_t cc[4];
-            CZ bv[4];
+        with_cols(P.sptr, P.col, P.soff, P.offs, P.np, sl, lane, [&](const auto &sc) {
+            for (int j0 = 0; j0 < wd; j0 += kChunk) {
+                int64_t cc[kChunk];
+                bool dg[kChunk];
+                CZ bv[kChunk], dj[kChunk];
+                sc.chunk(j0, wd, cc, dg);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cc[u] = sc(j + u);
-                bv[u] = (CZ)P.b16[base + (int64_t)(j + u) * SLICE];
+                for (int u = 0; u < kChunk; ++u) {
+                    const int j = j0 + u < wd ? j0 + u : wd - 1;
+                    bv[u] = (CZ)P.b16[base + (int64_t)j * SLICE];
+                    dj[u] = dval(cc[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const CZ t = acc + bv[u] * dj[u];
+                    acc = (j0 + u < wd) ? t : acc;
+                }
             }
-            CZ dj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) dj[u] = dval(cc[u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc += bv[u] * dj[u];
-        }
-        for (; j < wd; ++j) acc += (CZ)P.b16[base + (int64_t)j * SLICE] * dval(sc(j));
+        });
         const CZ d0 = dval(row);
         const CZ wk = first ? (CZ)0 + d0 : w[row];
         const CZ w1 = first ? wk : wk + d0;
@@ -181,9 +187,15 @@ __global__ void __launch_bounds__(NT) k_cheb_step(Bufs B, Cheb P, int k, int fir
         return;
     }
     double rho = 0.0, mz = 0.0;
-    if (s.uz == 64) cheb_step_body<64>(s, B, P, wg, k, first, last, din, rho, mz);
-    else if (s.uz == 32) cheb_step_body<32>(s, B, P, wg, k, first, last, din, rho, mz);
-    else cheb_step_body<16>(s, B, P, wg, k, first, last, din, rho, mz);
+#define AMP_CS(UZ)                                                      \
+    do {                                                                \
+        if (first) cheb_step_body<UZ, true>(s, B, P, wg, k, last, din, rho, mz);  \
+        else cheb_step_body<UZ, false>(s, B, P, wg, k, last, din, rho, mz);       \
+    } while (0)
+    if (s.uz == 64) AMP_CS(64);
+    else if (s.uz == 32) AMP_CS(32);
+    else AMP_CS(16);
+#undef AMP_CS
     if (last) {
         rho = block_sum(rho);
         mz = block_max(mz);
@@ -258,13 +270,20 @@ __global__ void __launch_bounds__(NT) k_cheb_isq(const double *diag, int64_t n, 
 __global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64, half_t *b16) {
     int64_t slo_, shi_;
     block_range(A.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
-    for (int64_t sl = slo_ + threadIdx.x / WAVE; sl < shi_; sl += NT / WAVE) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
+    for (int64_t sl = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < shi_; sl += NT / WAVE) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w);
         const double si = isq64[row];
-        for (int j = 0; j < w; ++j) {
-            const int64_t sidx = base + (int64_t)j * SLICE;
-            b16[sidx] = narrow<half_t>((A.v64[sidx] * si) * isq64[sc(j)]);
-        }
+        AMP_WITH_COLS(A, sl, lane, sc) {
+            for (int j0 = 0; j0 < w; j0 += kChunk) {
+                int64_t cc[kChunk];
+                bool dg[kChunk];
+                sc.chunk(j0, w, cc, dg);
+                for (int u = 0; u < kChunk && j0 + u < w; ++u) {
+                    const int64_t sidx = base + (int64_t)(j0 + u) * SLICE;
+                    b16[sidx] = narrow<half_t>((A.v64[sidx] * si) * isq64[cc[u]]);
+                }
+            }
+        });
     }
 }
 

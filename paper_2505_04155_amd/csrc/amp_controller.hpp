@@ -70,6 +70,8 @@ AMP_HD inline int ceil_log2(double v) {
     return (m == 0.5) ? e - 1 : e;
 }
 
+// (the library is compiled with -ffp-contract=off; the pragma keeps this
+// header exact when it is included elsewhere)
 #pragma clang fp contract(off)
 
 // eq. (eta_k): eps32 * sum_{t=k-d}^{k} ((3+C) delta_{t-1} + (2+C) delta_t);
@@ -178,7 +180,5 @@ AMP_HD inline void finish_iteration(St &s, const Cfg &c, const double *ring, dou
     }
     prepare_iteration(s, c, ring, s.iters);
 }
-
-#pragma clang fp contract(on)
 
 }  // namespace amp

@@ -70,32 +70,53 @@ struct Sell {
 
 constexpr int kOffMax = 32;  // longest per-slice offset list
 
-// Column of slot j of one row in one slice (both storage modes).
-struct SliceCols {
-    const int32_t *col;   // index mode: &col[sptr[s] + lane]
-    const int32_t *offs;  // offset mode: &offs[soff[s]]
-    int64_t row, np;
-    bool omode;
-    __device__ __forceinline__ int64_t operator()(int j) const {
-        if (omode) {
-            const int64_t c = row + offs[j];
-            return (c >= 0 && c < np) ? c : row;
-        }
-        return col[(int64_t)j * 64];
-    }
-    __device__ __forceinline__ bool is_diag(int j, int64_t c) const { return omode ? offs[j] == 0 : c == row; }
+// Columns of slots j0 .. j0 + kChunk - 1 of one row of a slice, one functor
+// per storage mode.  Slots at or past the row width w give a valid column
+// (the caller adds nothing for them).
+constexpr int kChunk = 8;
+
+struct alignas(32) Off8 {
+    int32_t o[kChunk];
 };
 
-__device__ __forceinline__ SliceCols slice_cols(const int64_t *sptr, const int32_t *col, const int32_t *soff,
-                                                const int32_t *offs, int64_t np, int64_t sl, int lane) {
-    SliceCols sc;
-    const int32_t so = soff[sl];
-    sc.omode = so >= 0;
-    sc.offs = offs + (so >= 0 ? so : 0);
-    sc.col = col + sptr[sl] + lane;
-    sc.row = sl * 64 + lane;
-    sc.np = np;
-    return sc;
+struct OffCols {
+    const int32_t *offs;  // the slice's offset list: 32-byte aligned, padded with 0 to a multiple of kChunk
+    int64_t row, np;
+    __device__ __forceinline__ void chunk(int j0, int /*w*/, int64_t *c, bool *dg) const {
+        const Off8 o = *reinterpret_cast<const Off8 *>(offs + j0);   // one scalar load of 8 offsets
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int64_t cc = row + o.o[u];
+            c[u] = (cc >= 0 && cc < np) ? cc : row;
+            dg[u] = o.o[u] == 0;
+        }
+    }
+};
+
+struct IdxCols {
+    const int32_t *col;   // &col[sptr[s] + lane]
+    int64_t row;
+    __device__ __forceinline__ void chunk(int j0, int w, int64_t *c, bool *dg) const {
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u < w ? j0 + u : w - 1;
+            c[u] = col[(int64_t)j * SLICE];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) dg[u] = c[u] == row;
+    }
+};
+
+// f(cols) with the column functor of slice sl's mode.  The mode is uniform
+// over the wave (one slice per wave), so each mode's loop is compiled
+// without per-slot branches.
+template <typename F>
+__device__ __forceinline__ void with_cols(const int64_t *sptr, const int32_t *col, const int32_t *soff,
+                                          const int32_t *offs, int64_t np, int64_t sl, int lane, F &&f) {
+    const int32_t so = __builtin_amdgcn_readfirstlane(soff[sl]);   // multiple of kChunk, or -1
+    const int64_t row = sl * SLICE + lane;
+    if (so >= 0) f(OffCols{offs + so, row, np});
+    else f(IdxCols{col + sptr[sl] + lane, row});
 }
 
 // Work-group index with consecutive indices on one XCD: dispatch deals

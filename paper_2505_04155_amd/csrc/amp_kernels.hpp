@@ -86,63 +86,66 @@ __device__ __forceinline__ void record_delta(const Cfg &c, int i, double d, Wg w
 // sliced-ELL row products
 // ----------------------------------------------------------------------------
 
+// Slots are read in chunks of kChunk: the chunk's values and gathers are
+// all issued before the first product is added, so a wave keeps up to
+// 2 kChunk loads in flight.  Slots past the row width repeat a valid slot's
+// loads (cache hits) and add nothing; the sum runs in slot order.
+
 // q_i = sum_j a_ij p_j with FP64 values and accumulation, slot order.
-template <typename PF>
-__device__ __forceinline__ double row_dot64(const Sell &A, const SliceCols &sc, int64_t base, int w, PF pval) {
+template <typename CS, typename PF>
+__device__ __forceinline__ double row_dot64(const Sell &A, const CS &sc, int64_t base, int w, PF pval) {
     double acc = 0.0;
-    int j = 0;
-    for (; j + 4 <= w; j += 4) {
-        int64_t c[4];
-        double v[4];
+    for (int j0 = 0; j0 < w; j0 += kChunk) {
+        int64_t c[kChunk];
+        bool dg[kChunk];
+        double v[kChunk], pj[kChunk];
+        sc.chunk(j0, w, c, dg);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = sc(j + u);
-            v[u] = A.v64[base + (int64_t)(j + u) * SLICE];
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u < w ? j0 + u : w - 1;
+            v[u] = A.v64[base + (int64_t)j * SLICE];
+            pj[u] = (double)pval(c[u]);
         }
-        double pj[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pj[u] = (double)pval(c[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u] * pj[u];
+        for (int u = 0; u < kChunk; ++u) {
+            const double t = acc + v[u] * pj[u];
+            acc = (j0 + u < w) ? t : acc;
+        }
     }
-    for (; j < w; ++j) acc += A.v64[base + (int64_t)j * SLICE] * (double)pval(sc(j));
     return acc;
 }
 
 // FP32 values and accumulation.  DIFF: off-diagonal slots add a_ij (p_j - p_i)
 // in slot order, then the diagonal slot's row sum s_i adds s_i p_i; padding
 // slots (value 0) add 0 exactly.  Otherwise the textbook form.
-template <bool DIFF, typename PF>
-__device__ __forceinline__ float row_dot32(const Sell &A, const SliceCols &sc, int64_t base, int w, float pi,
-                                           PF pval) {
+template <bool DIFF, typename CS, typename PF>
+__device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t base, int w, float pi, PF pval) {
     const float *vals = DIFF ? A.v32 : A.v32p;
     float acc = 0.0f, dterm = 0.0f;
-    int j = 0;
-    for (; j + 4 <= w; j += 4) {
-        int64_t c[4];
-        float v[4];
+    for (int j0 = 0; j0 < w; j0 += kChunk) {
+        int64_t c[kChunk];
+        bool dg[kChunk];
+        float v[kChunk], pj[kChunk];
+        sc.chunk(j0, w, c, dg);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = sc(j + u);
-            v[u] = vals[base + (int64_t)(j + u) * SLICE];
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u < w ? j0 + u : w - 1;
+            v[u] = vals[base + (int64_t)j * SLICE];
+            pj[u] = (float)pval(c[u]);
         }
-        float pj[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pj[u] = (float)pval(c[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (!DIFF) acc += v[u] * pj[u];
-            else if (sc.is_diag(j + u, c[u])) dterm += v[u] * pj[u];
-            else acc += v[u] * (pj[u] - pi);
+        for (int u = 0; u < kChunk; ++u) {
+            const bool in = j0 + u < w;
+            if (!DIFF) {
+                const float t = acc + v[u] * pj[u];
+                acc = in ? t : acc;
+            } else {
+                const float td = dterm + v[u] * pj[u];
+                const float to = acc + v[u] * (pj[u] - pi);
+                dterm = (in && dg[u]) ? td : dterm;
+                acc = (in && !dg[u]) ? to : acc;
+            }
         }
-    }
-    for (; j < w; ++j) {
-        const int64_t c = sc(j);
-        const float v = vals[base + (int64_t)j * SLICE];
-        const float pj = (float)pval(c);
-        if (!DIFF) acc += v * pj;
-        else if (sc.is_diag(j, c)) dterm += v * pj;
-        else acc += v * (pj - pi);
     }
     return DIFF ? dterm + acc : acc;
 }
@@ -154,11 +157,13 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const SliceCols &sc, i
     const int64_t sfirst_ = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   \
     for (int64_t sl = sfirst_; sl < shi_; sl += NT / WAVE)
 
-#define AMP_SLICE_ROW(A, sl, lane, row, base, w, sc)                                     \
+#define AMP_SLICE_ROW(A, sl, lane, row, base, w)                                         \
     const int lane = threadIdx.x % WAVE;                                                 \
     const int64_t row = (sl) * SLICE + lane, base = (A).sptr[sl] + lane;                 \
-    const int w = (int)(((A).sptr[(sl) + 1] - (A).sptr[sl]) / SLICE);                    \
-    const SliceCols sc = slice_cols((A).sptr, (A).col, (A).soff, (A).offs, (A).np, sl, lane)
+    const int w = __builtin_amdgcn_readfirstlane((int)(((A).sptr[(sl) + 1] - (A).sptr[sl]) / SLICE))
+
+#define AMP_WITH_COLS(A, sl, lane, sc) \
+    with_cols((A).sptr, (A).col, (A).soff, (A).offs, (A).np, sl, lane, [&](const auto &sc)
 
 // ----------------------------------------------------------------------------
 // k_init: r0 = b - A x0 in FP64; partials ||r0||^2, ||b||^2, max|r0|
@@ -169,8 +174,10 @@ __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) 
     double *r = (double *)B.r[0];
     const double *x = B.x;
     AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
-        const double t = B.b[row] - row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; });
+        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+        double ax = 0.0;
+        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
+        const double t = B.b[row] - ax;
         r[row] = t;
         sr += t * t;
         sb += B.b[row] * B.b[row];
@@ -350,10 +357,9 @@ __global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const
 // k_spmv: p = z + beta p_{k-1} (u_z), q = A p (u_r), gamma = q^T p
 // ----------------------------------------------------------------------------
 
-template <int UZ, int UR, bool DIFF>
+template <int UZ, int UR, bool DIFF, bool FIRST>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
-                                            void *qv, bool first, double beta_d, double &gam,
-                                            double &mp) {
+                                            void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
     typedef typename Prec<UR>::T TQ;
@@ -363,17 +369,19 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     TQ *q = (TQ *)qv;
     const CZ beta = (CZ)beta_d;
     auto pval = [&](int64_t c) -> TZ {
-        if (first) return z[c];
+        if (FIRST) return z[c];
         return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
     };
     AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
+        AMP_SLICE_ROW(A, sl, lane, row, base, w);
         const TZ pi = pval(row);
         if (pn) pn[row] = pi;
         mp = fmax(mp, fabs((double)pi));
-        TQ qq;
-        if (UR == 64) qq = (TQ)row_dot64(A, sc, base, w, pval);
-        else qq = (TQ)row_dot32<DIFF>(A, sc, base, w, (float)pi, pval);
+        TQ qq = 0;
+        AMP_WITH_COLS(A, sl, lane, sc) {
+            if constexpr (UR == 64) qq = (TQ)row_dot64(A, sc, base, w, pval);
+            else qq = (TQ)row_dot32<DIFF>(A, sc, base, w, (float)pi, pval);
+        });
         q[row] = qq;
         gam += (double)qq * (double)pi;
     }
@@ -405,8 +413,15 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     const int uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
     const bool first = (s.k == 0);
     double gam = 0.0, mp = 0.0;
-#define AMP_SP(UZ, UR, DF) \
-    spmv_p_body<UZ, UR, DF>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], first, s.beta, gam, mp)
+#define AMP_SP(UZ, UR, DF)                                                                                       \
+    do {                                                                                                        \
+        if (first)                                                                                              \
+            spmv_p_body<UZ, UR, DF, true>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], s.beta, \
+                                          gam, mp);                                                             \
+        else                                                                                                    \
+            spmv_p_body<UZ, UR, DF, false>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],       \
+                                           s.beta, gam, mp);                                                    \
+    } while (0)
     if (ur == 64) {
         if (uz == 64) AMP_SP(64, 64, false);
         else if (uz == 32) AMP_SP(32, 64, false);
@@ -441,7 +456,8 @@ __global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, const void *z, const 
                                                    int first, double beta, double *part) {
     double gam = 0.0, mp = 0.0;
     const Wg wg = grid_wg();
-    spmv_p_body<UZ, UR, DIFF>(A, wg, z, po, pn, q, first != 0, beta, gam, mp);
+    if (first) spmv_p_body<UZ, UR, DIFF, true>(A, wg, z, po, pn, q, beta, gam, mp);
+    else spmv_p_body<UZ, UR, DIFF, false>(A, wg, z, po, pn, q, beta, gam, mp);
     gam = block_sum(gam);
     if (threadIdx.x == 0 && part) part[wg.lb] = gam;
 }
@@ -546,8 +562,10 @@ __device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, Wg w
     TR *r = (TR *)B.r[pslot(RS)];
     const double *x = B.x;
     AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, sc);
-        const double t = B.b[row] - row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; });
+        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+        double ax = 0.0;
+        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
+        const double t = B.b[row] - ax;
         const TR tr = (TR)t;
         if (write) r[row] = tr;
         st += t * t;

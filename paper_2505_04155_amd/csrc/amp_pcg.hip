@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -285,12 +286,6 @@ __global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, in
     ucount[s] = cnt;
 }
 
-__global__ void k_copy_offsets(const int32_t *soff, const int32_t *ucount, const int32_t *uoffs, int64_t nslices,
-                               int32_t *offs) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices || soff[s] < 0) return;
-    for (int j = 0; j < ucount[s]; ++j) offs[soff[s] + j] = uoffs[s * kOffMax + j];
-}
 
 // One thread per (padded) row: copy its entries into its slice's column-major
 // slots (index mode: entry order; offset mode: the slot of the entry's
@@ -411,25 +406,43 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     }
     k_slice_scan<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, A->n, ns, maxlen, ucount,
                                                              uoffs);
-    std::vector<int32_t> hml(ns), huc(ns), hso(ns);
+    std::vector<int32_t> hml(ns), huc(ns), hso(ns), hu((size_t)ns * kOffMax);
     std::vector<int64_t> hp(ns + 1);
     if (hipMemcpyAsync(hml.data(), maxlen, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(huc.data(), ucount, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hu.data(), uoffs, hu.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         free_scan();
         return bail(fail(AMP_ERR_HIP, "amp_matrix_create: reading the slice scan failed"));
     }
-    // offset mode when the slice's offset list costs at most two padding slots per row
+    free_scan();
+    // Offset mode when the slice's offset list costs at most two padding
+    // slots per row.  Equal lists are stored once; each list starts at a
+    // multiple of kChunk entries (32 bytes) and is padded with 0 to a
+    // multiple of kChunk, so a kernel reads kChunk offsets in one load.
     const bool allow = !(flags & 1);
-    int64_t noffs = 0;
+    std::vector<int32_t> hoffs;
+    std::map<std::vector<int32_t>, int32_t> lists;
     hp[0] = 0;
     for (int64_t i = 0; i < ns; ++i) {
         const bool om = allow && huc[i] > 0 && huc[i] <= hml[i] + 2;
-        hso[i] = om ? (int32_t)noffs : -1;
-        if (om) { noffs += huc[i]; A->offset_slices += 1; }
+        hso[i] = -1;
+        if (om) {
+            std::vector<int32_t> key(hu.begin() + i * kOffMax, hu.begin() + i * kOffMax + huc[i]);
+            auto it = lists.find(key);
+            if (it == lists.end()) {
+                const int32_t at = (int32_t)hoffs.size();
+                hoffs.insert(hoffs.end(), key.begin(), key.end());
+                hoffs.resize(round_up((int64_t)hoffs.size(), kChunk), 0);
+                it = lists.emplace(std::move(key), at).first;
+            }
+            hso[i] = it->second;
+            A->offset_slices += 1;
+        }
         const int64_t w = om ? huc[i] : hml[i];
         hp[i + 1] = hp[i] + w * SLICE;
     }
+    const int64_t noffs = (int64_t)hoffs.size();
     A->slots = hp[ns];
     {
         int64_t index_slots = 0;
@@ -437,26 +450,20 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
             if (hso[i] < 0) index_slots += hp[i + 1] - hp[i];
         A->meta_bytes = 4 * index_slots + 4 * noffs + 12 * ns + 8;
     }
-    if (A->slots >= ((int64_t)1 << 31) * 2) {
-        free_scan();
-        return bail(fail(AMP_ERR_ARG, "amp_matrix_create: too many slots"));
-    }
+    if (A->slots >= ((int64_t)1 << 31) * 2) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: too many slots"));
     if ((s = dalloc(&A->sptr, ns + 1)) != AMP_OK || (s = dalloc(&A->soff, ns)) != AMP_OK ||
-        (s = dalloc(&A->offs, noffs > 0 ? noffs : 1)) != AMP_OK || (s = dalloc(&A->col, A->slots)) != AMP_OK ||
-        (s = dalloc(&A->v64, A->slots)) != AMP_OK || (s = dalloc(&A->v32, A->slots)) != AMP_OK ||
-        (s = dalloc(&A->v32p, A->slots)) != AMP_OK || (s = dalloc(&A->diag, A->np)) != AMP_OK) {
-        free_scan();
+        (s = dalloc(&A->offs, round_up(std::max<int64_t>(noffs, 1), kChunk))) != AMP_OK ||
+        (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->v32, A->slots)) != AMP_OK || (s = dalloc(&A->v32p, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->diag, A->np)) != AMP_OK)
         return bail(s);
-    }
     A->bytes = (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
     if (hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess) {
-        free_scan();
+        hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (noffs > 0 &&
+         hipMemcpyAsync(A->offs, hoffs.data(), noffs * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess))
         return bail(fail(AMP_ERR_HIP, "amp_matrix_create: upload of slice tables failed"));
-    }
-    k_copy_offsets<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(A->soff, ucount, uoffs, ns, A->offs);
     s = fill_values(A, csr, st);   // synchronises the stream (the host tables stay alive until then)
-    free_scan();
     if (s != AMP_OK) return bail(s);
     *out = A;
     return AMP_OK;
