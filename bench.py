@@ -43,6 +43,29 @@ def spmv_algorithmic_bytes(n, nnz, meta_bytes, b_val, b_z, b_q):
     return nnz * b_val + meta_bytes + n * (3 * b_z + b_q)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_fixed_fv3d128_hbm_counters.txt")
+
+
+def stored_traffic():
+    """HBM bytes per launch of the product-step kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (each scaled by the factor a
+    plain copy of known size gives), or None when the summary is missing or
+    was taken on other kernel sources than the library built here."""
+    from paper_2505_04155_amd import build
+    try:
+        fields = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    key, _, val = line.partition(" ")
+                    fields[key] = val.strip()
+    except OSError:
+        return None
+    if fields.get("source_digest") != build.source_digest():
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
+
+
 def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, meta_bytes):
     """Average duration (ms) of the library's product-step kernel over reps
     back-to-back launches, and its algorithmic bytes per launch."""
@@ -189,7 +212,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": stored_traffic(),
             "avg_kernel_us": round(spmv_ms * 1e3, 3),
             "algorithmic_bytes_per_launch": spmv_bytes,
         },

@@ -203,4 +203,38 @@ __device__ __forceinline__ double reduce_max(const double *part, int G) {
     return block_max(s);
 }
 
+// NS sums followed by NM maxima of partial arrays (part[t * GMAX + i]) in
+// one pass and one exchange; each result equals that of reduce_sum /
+// reduce_max on its array (same per-thread order, same tree).
+template <int NS, int NM>
+__device__ __forceinline__ void reduce_parts(const double *part, int G, double *out) {
+    constexpr int K = NS + NM, NW = NT / WAVE;
+    __shared__ double sh[K][NW];
+    double v[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) v[t] = 0.0;
+    for (int i = threadIdx.x; i < G; i += NT) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const double x = part[t * GMAX + i];
+            v[t] = (t < NS) ? v[t] + x : fmax(v[t], x);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) v[t] = (t < NS) ? wave_sum(v[t]) : wave_max(v[t]);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) sh[t][w] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        double r = 0.0;
+        for (int i = 0; i < NW; ++i) r = (t < NS) ? r + sh[t][i] : fmax(r, sh[t][i]);
+        out[t] = r;
+    }
+}
+
 }  // namespace amp

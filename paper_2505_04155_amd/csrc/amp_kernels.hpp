@@ -203,10 +203,12 @@ __global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) { init_stage(A, B, 
 __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B, Wg wg) {
     __shared__ int rec;
     __shared__ double recv;
+    __shared__ double ring[kRing];   // the residual-norm window, read in parallel for the controller
+    for (int i = threadIdx.x; i < kRing; i += NT) ring[i] = c.ring[i];
     const int G = (s.kind == RES_UPDATE) ? c.g_stream : c.g_slice;
-    const double a = reduce_sum(B.part_res, G);
-    const double b = reduce_sum(B.part_res + GMAX, G);
-    const double m = reduce_max(B.part_res + 2 * GMAX, G);
+    double tot[3];
+    reduce_parts<2, 1>(B.part_res, G, tot);   // its barrier also publishes ring[]
+    const double a = tot[0], b = tot[1], m = tot[2];
     if (threadIdx.x == 0) {
         rec = -1;
         if (s.kind == RES_INIT) {
@@ -220,13 +222,13 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             recv = s.delta;
             if (s.delta <= s.tol_b) s.status = CONVERGED;
             else if (c.maxit <= 0) s.status = MAXIT;
-            else prepare_iteration(s, c, c.ring, 0);
+            else prepare_iteration(s, c, ring, 0);
         } else if (s.kind == RES_UPDATE || s.kind == RES_PERIODIC) {
             const double d = sqrt(s.kind == RES_UPDATE ? a : b);
             if (s.kind == RES_PERIODIC) s.n_repl += 1;
             rec = s.iters;
             recv = d;
-            finish_iteration(s, c, c.ring, d, m);
+            finish_iteration(s, c, ring, d, m);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
             s.true_res = sqrt(a);
             if (s.true_res <= s.tol_b) {
@@ -243,7 +245,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
                     s.status = MAXIT;
                 } else {
                     s.status = RUNNING;
-                    prepare_iteration(s, c, c.ring, s.iters);
+                    prepare_iteration(s, c, ring, s.iters);
                 }
             }
         }
@@ -395,8 +397,9 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         store_state(s, out, wg);
         return;
     }
-    const double rho = reduce_sum(B.part_pre, c.g_pre);
-    const double mz = reduce_max(B.part_pre + GMAX, c.g_pre);
+    double tot[2];
+    reduce_parts<1, 1>(B.part_pre, c.g_pre, tot);
+    const double rho = tot[0], mz = tot[1];
     if (threadIdx.x == 0) {
         s.rho_prev = s.rho;
         s.rho = rho;
@@ -501,8 +504,9 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
         store_state(s, out, wg);
         return;
     }
-    const double gam = reduce_sum(B.part_spmv, c.g_slice);
-    const double mp = reduce_max(B.part_spmv + GMAX, c.g_slice);
+    double tot[2];
+    reduce_parts<1, 1>(B.part_spmv, c.g_slice, tot);
+    const double gam = tot[0], mp = tot[1];
     if (threadIdx.x == 0) {
         s.gamma = gam;
         s.alpha = s.rho / gam;
