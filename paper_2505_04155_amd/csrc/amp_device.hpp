@@ -11,7 +11,10 @@ namespace amp {
 
 typedef _Float16 half_t;
 
-constexpr int NT = 256;      // threads per work-group of every kernel
+#ifndef AMP_NT
+#define AMP_NT 256
+#endif
+constexpr int NT = AMP_NT;   // threads per work-group of every iteration kernel (a multiple of 64)
 constexpr int WAVE = 64;     // CDNA wavefront width
 constexpr int SLICE = 64;    // sliced-ELL slice height (one row per lane)
 constexpr int VEC = 4;       // consecutive elements per thread in streaming kernels

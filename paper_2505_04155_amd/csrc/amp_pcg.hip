@@ -679,7 +679,7 @@ static amp_status check_options(const amp_options &o) {
         return fail(AMP_ERR_ARG, "options: T_z, T_p must be in -60..15");
     if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0 || o.group_rows < 0)
         return fail(AMP_ERR_ARG, "options: negative count");
-    if (o.group_rows % NT) return fail(AMP_ERR_ARG, "options: group_rows must be a multiple of 256");
+    if (o.group_rows % 256) return fail(AMP_ERR_ARG, "options: group_rows must be a multiple of 256");
     return AMP_OK;
 }
 
