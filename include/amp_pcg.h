@@ -103,6 +103,8 @@ typedef struct {
                                runs G = ceil(n_padded / group_rows) work-groups (at most 1024).
                                Default 0: automatic (single solve: per-kernel counts filling the
                                chip; batched solve: 4096) */
+    int graph;              /* 1: replay batches of 8 iterations from a captured HIP graph cached in the
+                               matrix handle (single solve without rr_period; default 0) */
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
     double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -84,6 +85,11 @@ struct Work {
     St *st = nullptr;             // state chain: [init, pre, spmv, res, tr, report]
     St *snap = nullptr;           // pinned host snapshots [2]
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // captured batch of iterations (see get_graph)
+    hipStream_t cs = nullptr, cap = nullptr;   // solve stream and capture stream (default priority)
+    hipEvent_t join[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;           // launch arguments the graph was captured with
 };
 
 enum {
@@ -112,6 +118,7 @@ struct amp_matrix_s {
 struct amp_precond_s {
     amp_matrix A = nullptr;
     int kind = 0, degree = 0;
+    uint64_t generation = 0;   // changes whenever the preconditioner's data is (re)computed
     double lam_lo = 0, lam_hi = 0;
     double *d64 = nullptr;
     float *d32 = nullptr;
@@ -157,6 +164,14 @@ static void free_work(Work &w) {
     w.snap = nullptr;
     for (auto &e : w.ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    for (auto &e : w.join)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
+    w.gexec = nullptr;
+    w.gkey.clear();
+    if (w.cs) (void)hipStreamDestroy(w.cs);
+    if (w.cap) (void)hipStreamDestroy(w.cap);
+    w.cs = w.cap = nullptr;
 }
 
 static amp_status ensure_work(amp_matrix A, hipStream_t st) {
@@ -527,7 +542,10 @@ __global__ void k_scale_to_half(const double *d64, int64_t np, double scale, hal
 
 // Values of the preconditioner that depend on A's entries (also rerun by
 // amp_precond_update after amp_matrix_update_values).
+static std::atomic<uint64_t> g_generation{0};
+
 static amp_status setup_values(amp_precond M, hipStream_t st) {
+    M->generation = ++g_generation;
     amp_matrix A = M->A;
     const int64_t np = A->np;
     const unsigned g = (unsigned)((np + 255) / 256);
@@ -649,6 +667,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->max_replacements = 3;
     o->rr_period = 0;
     o->batch = 0;
+    o->graph = 0;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;
@@ -679,6 +698,7 @@ static amp_status check_options(const amp_options &o) {
         return fail(AMP_ERR_ARG, "options: T_z, T_p must be in -60..15");
     if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0 || o.group_rows < 0)
         return fail(AMP_ERR_ARG, "options: negative count");
+    if (o.graph != 0 && o.graph != 1) return fail(AMP_ERR_ARG, "options: graph must be 0 or 1");
     if (o.group_rows % 256) return fail(AMP_ERR_ARG, "options: group_rows must be a multiple of 256");
     return AMP_OK;
 }
@@ -788,6 +808,79 @@ static amp_status enqueue_iterations(Driver &d, int count) {
     return AMP_OK;
 }
 
+// ----------------------------------------------------------------------------
+// captured batches of iterations
+// ----------------------------------------------------------------------------
+
+constexpr int kGraphIters = 8;   // iterations per captured graph
+
+// Everything a captured batch's kernel arguments depend on.
+static std::vector<unsigned char> graph_key(const Driver &d) {
+    std::vector<unsigned char> k;
+    auto add = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        k.insert(k.end(), c, c + n);
+    };
+    add(&d.cfg, sizeof(Cfg));
+    add(&d.B, sizeof(Bufs));
+    add(&d.S, sizeof(Sell));
+    add(&d.gs, sizeof(int));
+    add(&d.gl, sizeof(int));
+    add(&d.M, sizeof(d.M));
+    add(&d.M->generation, sizeof(uint64_t));
+    return k;
+}
+
+// The handle's graph of kGraphIters iterations starting from the state slot
+// ST_RES, captured (on a stream of its own, nothing executes) when the
+// launch arguments differ from the cached graph's.  The graph holds kernel
+// launches only.
+static amp_status get_graph(Driver &d) {
+    Work &w = d.A->w;
+    std::vector<unsigned char> key = graph_key(d);
+    if (w.gexec && key == w.gkey) return AMP_OK;
+    if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
+    w.gexec = nullptr;
+    w.gkey.clear();
+    Driver c = d;
+    c.st = w.cap;
+    c.in = &w.st[ST_RES];
+    c.host_k = 0;
+    AMP_HIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
+    const amp_status s = enqueue_iterations(c, kGraphIters);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(w.cap, &g);
+    if (s != AMP_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return s != AMP_OK ? s : fail(AMP_ERR_HIP, std::string("capturing iterations: ") + hipGetErrorString(e));
+    }
+    const hipError_t e2 = hipGraphInstantiate(&w.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        w.gexec = nullptr;
+        return fail(AMP_ERR_HIP, std::string("instantiating the iteration graph: ") + hipGetErrorString(e2));
+    }
+    w.gkey = std::move(key);
+    return AMP_OK;
+}
+
+// count iterations: eagerly until the chain reaches ST_RES, then whole graphs,
+// then eagerly again for the remainder.
+static amp_status enqueue_batch(Driver &d, int count, bool graph) {
+    if (!graph) return enqueue_iterations(d, count);
+    Work &w = d.A->w;
+    if (count > 0 && d.in != &w.st[ST_RES]) {
+        AMP_TRY(enqueue_iterations(d, 1));
+        --count;
+    }
+    for (; count >= kGraphIters; count -= kGraphIters) {
+        AMP_HIP(hipGraphLaunch(w.gexec, d.st));
+        d.host_k += kGraphIters;
+    }
+    if (count > 0) AMP_TRY(enqueue_iterations(d, count));
+    return AMP_OK;
+}
+
 static amp_status snapshot(Driver &d, int slot) {
     Work &w = d.A->w;
     AMP_HIP(hipMemcpyAsync(&w.snap[slot], d.in, sizeof(St), hipMemcpyDeviceToHost, d.st));
@@ -813,6 +906,18 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
+    const bool graph = o.graph && o.rr_period == 0;
+    hipStream_t user = d.st;
+    if (graph) {
+        // the solve runs on the handle's own stream, ordered after and before the caller's
+        if (!w.cs) AMP_HIP(hipStreamCreateWithFlags(&w.cs, hipStreamNonBlocking));
+        if (!w.cap) AMP_HIP(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+        for (auto &e : w.join)
+            if (!e) AMP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        AMP_HIP(hipEventRecord(w.join[0], user));
+        AMP_HIP(hipStreamWaitEvent(w.cs, w.join[0], 0));
+        d.st = w.cs;
+    }
     const int64_t n = A->n;
     d.cfg = make_cfg(o, A, M, tol, maxit);
     d.S = A->sell();
@@ -820,6 +925,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.gs = d.cfg.g_stream;
     d.gl = d.cfg.g_slice;
     d.host_k = 0;
+    if (graph) AMP_TRY(get_graph(d));
 
     const St s0 = init_state(o);
     AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
@@ -831,14 +937,14 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
 
     // Pipelined batches: batch j+1 is enqueued before batch j's state is
     // read; once the state leaves RUNNING every further kernel returns at once.
-    int batch = o.batch > 0 ? o.batch : 4;
+    int batch = o.batch > 0 ? o.batch : (graph ? kGraphIters : 4);
     int pending = -1;              // snapshot slot of the batch in flight
     int last_iters = 0;
     double last_delta = -1.0;
     St cur = s0;
     for (;;) {
         const int sl = (pending >= 0) ? (pending ^ 1) : 0;
-        AMP_TRY(enqueue_iterations(d, batch));
+        AMP_TRY(enqueue_batch(d, batch, graph));
         AMP_TRY(snapshot(d, sl));
         if (pending < 0) {
             pending = sl;
@@ -855,6 +961,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
                 if (rate > 0.0 && rate < 1.0)
                     left = (int)std::ceil(std::log(tol * cur.bnorm / cur.delta) / std::log(rate));
                 batch = std::max(4, std::min(256, left / 2 + 1));
+                if (graph) batch = (int)round_up(batch, kGraphIters);
             }
             if (cur.iters > last_iters) {
                 last_iters = cur.iters;
@@ -871,7 +978,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
             AMP_HIP(hipGetLastError());
             d.in = &w.st[ST_TR];
             d.host_k = cur.iters;
-            batch = 4;
+            batch = graph ? kGraphIters : 4;
             continue;
         }
         break;
@@ -887,6 +994,10 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
         AMP_HIP(hipMemcpyAsync(&t2, w.scalar, sizeof(double), hipMemcpyDeviceToHost, d.st));
         AMP_HIP(hipStreamSynchronize(d.st));
         true_res = std::sqrt(t2);
+    }
+    if (graph) {
+        AMP_HIP(hipEventRecord(w.join[1], d.st));
+        AMP_HIP(hipStreamWaitEvent(user, w.join[1], 0));
     }
     AMP_HIP(hipStreamSynchronize(d.st));
 

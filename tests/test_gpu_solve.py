@@ -220,6 +220,46 @@ def test_periodic_replacement_matches_model(amp):
     assert info["relres_true"] <= 1e-10
 
 
+# ------------------------------------------------------------------ captured graphs
+
+@pytest.mark.parametrize("case,preset", [("poisson64", "amp16"), ("blocky24", "amp64"), ("poisson37", "pcg64")])
+def test_graph_replay_matches_eager(amp, case, preset):
+    # replays of the captured batch equal the eager launches bit for bit, with
+    # eager solves between replays, and a changed tolerance re-captures
+    _say(f"graph vs eager {case} {preset}")
+    A, b = CASES[case]()
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "jacobi")
+    bt = torch.tensor(b, device="cuda")
+    for tol in (1e-10, 1e-6, 1e-10):
+        x0, i0 = amp.solve(M, pc, bt, tol=tol, preset=preset)
+        for rep in range(3):
+            xg, ig = amp.solve(M, pc, bt, tol=tol, preset=preset, graph=1)
+            torch.cuda.synchronize()
+            _say(f"  tol {tol} replay {rep}: iters {ig['iters']} (eager {i0['iters']})")
+            assert ig["status"] == i0["status"] == 0
+            assert ig["iters"] == i0["iters"]
+            for key in ("k_z32", "k_z16", "k_r32", "replacements"):
+                assert ig[key] == i0[key], key
+            assert torch.equal(xg, x0)
+            xe, ie = amp.solve(M, pc, bt, tol=tol, preset=preset)
+            torch.cuda.synchronize()
+            assert torch.equal(xe, x0)
+
+
+def test_graph_replay_chebyshev(amp):
+    _say("graph vs eager, chebyshev")
+    A, b, _, (lo, hi) = P.q1_system(20)
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    bt = torch.tensor(b, device="cuda")
+    x0, i0 = amp.solve(M, pc, bt, preset="amp16")
+    for rep in range(2):
+        xg, ig = amp.solve(M, pc, bt, preset="amp16", graph=1)
+        torch.cuda.synchronize()
+        assert ig["iters"] == i0["iters"] and torch.equal(xg, x0)
+
+
 # ------------------------------------------------------------------ full-size workload
 
 def test_blocky128_full_size(amp):
