@@ -22,6 +22,7 @@ struct SysDesc {
     const double *b_in; // caller's right-hand side (n entries)
     double *x_io;       // caller's x0 in, solution out (n entries)
     int64_t n;
+    int solo;           // solved by one work-group of k_batch_solo, not by the lockstep kernels
 };
 
 // A work-group's assignment; sys < 0 marks padding.
@@ -90,10 +91,17 @@ __global__ void __launch_bounds__(NT) k_batch_reduce_report(const SysDesc *sd, i
     if (threadIdx.x == 0) out[sys] = t;
 }
 
-// State slot `slot` of every system into one array (for one host copy).
+// State slot `slot` of every lockstep system (of every single-work-group
+// system when slot is ST_FIN) into one array, for one host copy.
 __global__ void __launch_bounds__(NT) k_batch_gather(const SysDesc *sd, int nsys, int slot, St *out) {
     const int sys = blockIdx.x * NT + threadIdx.x;
-    if (sys < nsys) out[sys] = sd[sys].st[slot];
+    if (sys < nsys && (sd[sys].solo != 0) == (slot == ST_FIN)) out[sys] = sd[sys].st[slot];
+}
+
+// The small systems: one work-group each runs its whole solve.
+__global__ void __launch_bounds__(NT) k_batch_solo(const SysDesc *sd, const int *list, int cap) {
+    const SysDesc &d = sd[list[blockIdx.x]];
+    solo_solve(d.c, d.A, d.B, d.st, cap);
 }
 
 __global__ void __launch_bounds__(NT) k_batch_copy_out(const SysDesc *sd, const Task *tasks) {

@@ -26,6 +26,12 @@
 
 namespace amp {
 
+// State slots of a solve (the chain each kernel reads from and writes to).
+enum Slot : int {
+    ST_INIT = 0, ST_PRE = 1, ST_SPMV = 2, ST_RES = 3, ST_TR = 4, ST_REPORT = 5,
+    ST_PREI = 6, ST_CH0 = 7, ST_CH1 = 8, ST_FIN = 9, ST_COUNT = 10
+};
+
 // Working vectors, indexed by precision slot (0: FP64, 1: FP32, 2: FP16).
 // All are padded to np elements; p is double-buffered.
 struct Bufs {
@@ -610,6 +616,49 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
 __global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
     true_res_stage(c, A, B, mode, in, out, grid_wg());
 }
+
+// ----------------------------------------------------------------------------
+// single-work-group solve: the stages above in a loop inside one launch
+// ----------------------------------------------------------------------------
+
+// One work-group runs a whole solve from the state in st[ST_INIT] (r0 and
+// its partials already formed with G = 1): the same stages, on the same
+// state slots, in the same order as the host would enqueue them with one
+// work-group per kernel, so the result is bitwise that sequence's.  The
+// loop ends when the state stops (converged, maxit, breakdown) or after
+// `cap` passes; the last state is copied to st[ST_FIN] (with status MAXIT
+// if the cap was reached while running).
+__device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bufs &B, St *st, int cap) {
+    const Wg wg{0, 1};
+    __shared__ int status;
+    int in = ST_INIT, last = ST_INIT;
+    for (int pass = 0; pass < cap; ++pass) {
+        precond_stage(c, B, A.np, st + in, st + ST_PRE, wg);
+        __syncthreads();
+        if (threadIdx.x == 0) status = st[ST_PRE].status;
+        __syncthreads();
+        last = ST_PRE;
+        if (status == NEED_VERIFY) {
+            true_res_stage(c, A, B, 0, st + ST_PRE, st + ST_TR, wg);
+            __syncthreads();
+            in = last = ST_TR;
+            continue;
+        }
+        if (status != RUNNING) break;
+        spmv_stage(c, A, B, st + ST_PRE, st + ST_SPMV, wg);
+        __syncthreads();
+        update_stage(c, B, A.np, st + ST_SPMV, st + ST_RES, wg);
+        __syncthreads();
+        in = last = ST_RES;
+    }
+    if (threadIdx.x == 0) {
+        St f = st[last];
+        if (f.status == RUNNING || f.status == NEED_VERIFY) f.status = MAXIT;
+        st[ST_FIN] = f;
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_solo(Cfg c, Sell A, Bufs B, St *st, int cap) { solo_solve(c, A, B, st, cap); }
 
 // Fixed-order total of G partials into *out (one work-group).
 __global__ void __launch_bounds__(NT) k_reduce_to(const double *part, int G, int is_max, double *out) {

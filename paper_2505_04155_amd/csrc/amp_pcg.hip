@@ -92,10 +92,6 @@ struct Work {
     std::vector<unsigned char> gkey;           // launch arguments the graph was captured with
 };
 
-enum {
-    ST_INIT = 0, ST_PRE = 1, ST_SPMV = 2, ST_RES = 3, ST_TR = 4, ST_REPORT = 5,
-    ST_PREI = 6, ST_CH0 = 7, ST_CH1 = 8, ST_COUNT = 9
-};
 
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
@@ -668,6 +664,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->rr_period = 0;
     o->batch = 0;
     o->graph = 0;
+    o->solo_rows = 16384;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;
@@ -696,7 +693,7 @@ static amp_status check_options(const amp_options &o) {
         return fail(AMP_ERR_ARG, "options: C, tau_zs, tau_zh must be >= 0");
     if (o.T_z < -60 || o.T_z > 15 || o.T_p < -60 || o.T_p > 15)
         return fail(AMP_ERR_ARG, "options: T_z, T_p must be in -60..15");
-    if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0 || o.group_rows < 0)
+    if (o.max_replacements < 0 || o.rr_period < 0 || o.batch < 0 || o.group_rows < 0 || o.solo_rows < 0)
         return fail(AMP_ERR_ARG, "options: negative count");
     if (o.graph != 0 && o.graph != 1) return fail(AMP_ERR_ARG, "options: graph must be 0 or 1");
     if (o.group_rows % 256) return fail(AMP_ERR_ARG, "options: group_rows must be a multiple of 256");
@@ -888,6 +885,16 @@ static amp_status snapshot(Driver &d, int slot) {
     return AMP_OK;
 }
 
+// Systems small enough for one work-group to iterate on its own (Jacobi or
+// identity, no periodic replacement).
+static bool solo_eligible(const amp_options &o, amp_matrix A, amp_precond M) {
+    return o.solo_rows > 0 && A->np <= o.solo_rows && o.rr_period == 0 && M->kind != AMP_PC_CHEBYSHEV;
+}
+
+// Upper bound on the single-work-group loop's passes: maxit iterations plus
+// two passes per termination check; the controller stops the loop first.
+static int solo_cap(const amp_options &o, int maxit) { return maxit + 2 * (o.max_replacements + 2) + 8; }
+
 extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
                                     int maxit, const amp_options *opt, amp_result *res, void *stream) {
     auto t0 = std::chrono::steady_clock::now();
@@ -906,7 +913,8 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
-    const bool graph = o.graph && o.rr_period == 0;
+    const bool solo = solo_eligible(o, A, M);
+    const bool graph = o.graph && o.rr_period == 0 && !solo;
     hipStream_t user = d.st;
     if (graph) {
         // the solve runs on the handle's own stream, ordered after and before the caller's
@@ -920,6 +928,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     }
     const int64_t n = A->n;
     d.cfg = make_cfg(o, A, M, tol, maxit);
+    if (solo) d.cfg.g_stream = d.cfg.g_slice = d.cfg.g_pre = 1;
     d.S = A->sell();
     d.B = make_bufs(A, M);
     d.gs = d.cfg.g_stream;
@@ -934,6 +943,16 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     k_init<<<d.gl, NT, 0, d.st>>>(d.S, d.B);
     AMP_HIP(hipGetLastError());
     d.in = &w.st[ST_INIT];
+    St cur = s0;
+    if (solo) {
+        // one work-group, one launch: the whole iteration loop runs on the device
+        k_solo<<<1, NT, 0, d.st>>>(d.cfg, d.S, d.B, w.st, solo_cap(o, maxit));
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipMemcpyAsync(&w.snap[0], &w.st[ST_FIN], sizeof(St), hipMemcpyDeviceToHost, d.st));
+        AMP_HIP(hipStreamSynchronize(d.st));
+        cur = w.snap[0];
+        d.in = &w.st[ST_FIN];
+    }
 
     // Pipelined batches: batch j+1 is enqueued before batch j's state is
     // read; once the state leaves RUNNING every further kernel returns at once.
@@ -941,8 +960,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     int pending = -1;              // snapshot slot of the batch in flight
     int last_iters = 0;
     double last_delta = -1.0;
-    St cur = s0;
-    for (;;) {
+    for (; !solo;) {
         const int sl = (pending >= 0) ? (pending ^ 1) : 0;
         AMP_TRY(enqueue_batch(d, batch, graph));
         AMP_TRY(snapshot(d, sl));
@@ -1035,19 +1053,26 @@ bool terminal(int status) { return status == CONVERGED || status == MAXIT || sta
 struct BatchBufs {
     SysDesc *sd = nullptr;
     Task *tasks = nullptr, *tasks_all = nullptr;
+    int *solo = nullptr;
+    hipStream_t side = nullptr;
     St *gath = nullptr;
     double *red = nullptr;
     St *snap = nullptr;       // pinned [2][nsys]
     Task *stage = nullptr;    // pinned [2][cap]
     double *hred = nullptr;   // pinned [nsys]
-    hipEvent_t ev[2] = {nullptr, nullptr}, evs[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr}, evs[2] = {nullptr, nullptr}, evt[2] = {nullptr, nullptr};
     ~BatchBufs() {
-        dfree(sd); dfree(tasks); dfree(tasks_all); dfree(gath); dfree(red);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        dfree(sd); dfree(tasks); dfree(tasks_all); dfree(gath); dfree(red); dfree(solo);
         if (snap) (void)hipHostFree(snap);
         if (stage) (void)hipHostFree(stage);
         if (hred) (void)hipHostFree(hred);
         for (auto &e : ev) if (e) (void)hipEventDestroy(e);
         for (auto &e : evs) if (e) (void)hipEventDestroy(e);
+        for (auto &e : evt) if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -1101,11 +1126,18 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 
     // per-system descriptors and work-group counts
     std::vector<SysDesc> hsd(nsys);
-    std::vector<int> G(nsys);
+    std::vector<int> G(nsys), solo_list;
+    std::vector<char> live(nsys, 1);
     for (int i = 0; i < nsys; ++i) {
         SysDesc &d = hsd[i];
         std::memset(&d, 0, sizeof(d));
         d.c = make_cfg(o, A[i], M[i], tol[i], maxit);   // one work-group count G for every kernel
+        if (solo_eligible(o, A[i], M[i])) {
+            d.c.g_stream = d.c.g_slice = d.c.g_pre = 1;
+            d.solo = 1;
+            live[i] = 0;
+            solo_list.push_back(i);
+        }
         G[i] = d.c.g_stream;
         d.A = A[i]->sell();
         d.B = make_bufs(A[i], M[i]);
@@ -1115,10 +1147,11 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
         d.x_io = x[i];
         d.n = A[i]->n;
     }
-    std::vector<char> live(nsys, 1);
-    std::vector<Task> all;
-    build_tasks(G, live, all);
+    std::vector<Task> all, lock;
+    build_tasks(G, std::vector<char>(nsys, 1), all);
+    build_tasks(G, live, lock);
     const size_t cap = all.size();
+    const int nsolo = (int)solo_list.size();
 
     BatchBufs bb;
     AMP_TRY(dalloc(&bb.sd, nsys));
@@ -1126,16 +1159,20 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
     AMP_TRY(dalloc(&bb.tasks_all, cap));
     AMP_TRY(dalloc(&bb.gath, nsys));
     AMP_TRY(dalloc(&bb.red, nsys));
+    AMP_TRY(dalloc(&bb.solo, std::max(nsolo, 1)));
     AMP_HIP(hipHostMalloc((void **)&bb.snap, 2 * nsys * sizeof(St), hipHostMallocDefault));
     AMP_HIP(hipHostMalloc((void **)&bb.stage, 2 * cap * sizeof(Task), hipHostMallocDefault));
     AMP_HIP(hipHostMalloc((void **)&bb.hred, nsys * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 2; ++i) {
         AMP_HIP(hipEventCreateWithFlags(&bb.ev[i], hipEventDisableTiming));
         AMP_HIP(hipEventCreateWithFlags(&bb.evs[i], hipEventDisableTiming));
+        AMP_HIP(hipEventCreateWithFlags(&bb.evt[i], hipEventDisableTiming));
     }
     AMP_HIP(hipMemcpyAsync(bb.sd, hsd.data(), nsys * sizeof(SysDesc), hipMemcpyHostToDevice, st));
     AMP_HIP(hipMemcpyAsync(bb.tasks_all, all.data(), cap * sizeof(Task), hipMemcpyHostToDevice, st));
-    AMP_HIP(hipMemcpyAsync(bb.tasks, all.data(), cap * sizeof(Task), hipMemcpyHostToDevice, st));
+    AMP_HIP(hipMemcpyAsync(bb.tasks, lock.data(), lock.size() * sizeof(Task), hipMemcpyHostToDevice, st));
+    if (nsolo > 0)
+        AMP_HIP(hipMemcpyAsync(bb.solo, solo_list.data(), nsolo * sizeof(int), hipMemcpyHostToDevice, st));
     // the host vectors above are pageable: wait before they can go out of scope or change
     AMP_HIP(hipStreamSynchronize(st));
 
@@ -1145,10 +1182,20 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
     k_batch_init<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
     AMP_HIP(hipGetLastError());
 
+    if (nsolo > 0) {
+        // the small systems iterate on their own work-groups, on a second stream
+        AMP_HIP(hipStreamCreateWithFlags(&bb.side, hipStreamNonBlocking));
+        AMP_HIP(hipEventRecord(bb.evs[0], st));
+        AMP_HIP(hipStreamWaitEvent(bb.side, bb.evs[0], 0));
+        k_batch_solo<<<(unsigned)nsolo, NT, 0, bb.side>>>(bb.sd, bb.solo, solo_cap(o, maxit));
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipEventRecord(bb.evs[1], bb.side));
+    }
+
     int in = ST_INIT;
-    unsigned ntask = gall;
+    unsigned ntask = (unsigned)lock.size();
     const int batch = o.batch > 0 ? o.batch : 8;
-    int pending = -1, stage_next = 0, nlive = nsys;
+    int pending = -1, stage_next = 0, nlive = nsys - nsolo;
     std::vector<St> fin(nsys);
     std::vector<Task> cur_tasks;
     auto enqueue_batch = [&](int slot) -> amp_status {
@@ -1167,7 +1214,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
         AMP_HIP(hipEventRecord(bb.ev[slot], st));
         return AMP_OK;
     };
-    for (;;) {
+    for (; nlive > 0;) {
         const int sl = (pending >= 0) ? (pending ^ 1) : 0;
         AMP_TRY(enqueue_batch(sl));
         if (pending < 0) {
@@ -1191,15 +1238,23 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
             // drop the stopped systems from every launch enqueued from now on
             build_tasks(G, live, cur_tasks);
             Task *stg = bb.stage + (size_t)stage_next * cap;
-            AMP_HIP(hipEventSynchronize(bb.evs[stage_next]));
+            AMP_HIP(hipEventSynchronize(bb.evt[stage_next]));
             std::memcpy(stg, cur_tasks.data(), cur_tasks.size() * sizeof(Task));
             AMP_HIP(hipMemcpyAsync(bb.tasks, stg, cur_tasks.size() * sizeof(Task), hipMemcpyHostToDevice, st));
-            AMP_HIP(hipEventRecord(bb.evs[stage_next], st));
+            AMP_HIP(hipEventRecord(bb.evt[stage_next], st));
             stage_next ^= 1;
             ntask = (unsigned)cur_tasks.size();
         }
     }
-    AMP_HIP(hipEventSynchronize(bb.ev[pending]));
+    if (pending >= 0) AMP_HIP(hipEventSynchronize(bb.ev[pending]));
+    if (nsolo > 0) {
+        AMP_HIP(hipStreamWaitEvent(st, bb.evs[1], 0));
+        k_batch_gather<<<(unsigned)((nsys + NT - 1) / NT), NT, 0, st>>>(bb.sd, nsys, ST_FIN, bb.gath);
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipMemcpyAsync(bb.snap, bb.gath, nsys * sizeof(St), hipMemcpyDeviceToHost, st));
+        AMP_HIP(hipStreamSynchronize(st));
+        for (int i : solo_list) fin[i] = bb.snap[i];
+    }
 
     // solutions out, and the FP64 true residual of every returned x
     k_batch_copy_out<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);

@@ -47,17 +47,19 @@ def _handles(amp, systems):
 
 
 def _mixed_systems():
-    out = [P.poisson2d_system(m)[:2] for m in (20, 37, 64)]
-    out += P.batched_systems(count=5, side_min=16, side_max=96)
+    # small systems (one work-group each by default) and larger ones (lockstep)
+    out = [P.poisson2d_system(m)[:2] for m in (20, 37, 64, 150)]
+    out += P.batched_systems(count=5, side_min=16, side_max=160)
     A, _, _ = P.poisson2d_system(24)
     out.append((A, np.zeros(A.n)))                    # zero right-hand side: 0 iterations
-    out.append(P.blocky_diffusion3d_system(16, 4)[:2])
+    out.append(P.blocky_diffusion3d_system(32, 8)[:2])
     return out
 
 
-@pytest.mark.parametrize("preset", ["amp64", "amp16", "pcg64"])
-def test_batched_matches_single_bitwise(amp, preset):
-    _say(f"batched vs single, {preset}")
+@pytest.mark.parametrize("preset,solo_rows", [("amp64", 16384), ("amp16", 16384), ("pcg64", 16384),
+                                              ("amp64", 0), ("amp16", 0)])
+def test_batched_matches_single_bitwise(amp, preset, solo_rows):
+    _say(f"batched vs single, {preset}, solo_rows {solo_rows}")
     systems = _mixed_systems()
     Ms, Ps, bs = _handles(amp, systems)
     # exact start for one system: x0 = x*, so r0 = 0 exactly
@@ -67,14 +69,15 @@ def test_batched_matches_single_bitwise(amp, preset):
     Ps.append(amp.Preconditioner(M3, "jacobi"))
     bs.append(torch.tensor(b3, device="cuda"))
     x0s = [None] * (len(Ms) - 1) + [torch.tensor(xs3, device="cuda")]
-    xs, infos, st = amp.solve_batched(Ms, Ps, bs, x0s=x0s, tol=1e-10, maxit=5000, preset=preset)
+    xs, infos, st = amp.solve_batched(Ms, Ps, bs, x0s=x0s, tol=1e-10, maxit=5000, preset=preset,
+                                      solo_rows=solo_rows)
     torch.cuda.synchronize()
     assert st == 0, [i["status"] for i in infos]
     zero_rhs = len(_mixed_systems()) - 2
     assert infos[-1]["iters"] == 0 and infos[zero_rhs]["iters"] == 0
     for i in range(len(Ms)):
         x1, i1 = amp.solve(Ms[i], Ps[i], bs[i], x0=x0s[i], tol=1e-10, maxit=5000, preset=preset,
-                           group_rows=GROUP_ROWS)
+                           group_rows=GROUP_ROWS, solo_rows=solo_rows)
         torch.cuda.synchronize()
         _say(f"  system {i}: n={Ms[i].n} batched iters {infos[i]['iters']} single {i1['iters']}")
         assert infos[i]["iters"] == i1["iters"]
@@ -114,6 +117,9 @@ def test_batched_full_workload(amp):
     iters = np.array([i["iters"] for i in infos])
     _say(f"  status {st}, iterations min {iters.min()} median {int(np.median(iters))} max {iters.max()}, "
          f"{infos[0]['t_solve_ms']:.1f} ms")
+    xs2, infos2, st2 = amp.solve_batched(Ms, Ps, bs, tol=1e-10, maxit=20000, preset="amp64", solo_rows=0)
+    _say(f"  all lockstep: status {st2}, {infos2[0]['t_solve_ms']:.1f} ms")
+    assert st2 == 0 and max(i["relres_true"] for i in infos2) <= 1e-10
     assert st == 0
     assert max(i["relres_true"] for i in infos) <= 1e-10
     # sampled systems against the oracle: smallest, median, largest

@@ -220,6 +220,43 @@ def test_periodic_replacement_matches_model(amp):
     assert info["relres_true"] <= 1e-10
 
 
+# ------------------------------------------------------------------ single-work-group solve
+
+@pytest.mark.parametrize("case,preset", [("poisson64", "amp64"), ("poisson64", "amp16"), ("poisson37", "pcg64"),
+                                         ("blocky24", "amp_ur"), ("blocky24", "amp16")])
+def test_single_workgroup_solve_matches_kernel_sequence(amp, case, preset):
+    # one launch looping on the device == the host-enqueued kernels with one
+    # work-group each, bit for bit (including the termination check)
+    _say(f"solo vs kernel sequence {case} {preset}")
+    A, b = CASES[case]()
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "jacobi")
+    bt = torch.tensor(b, device="cuda")
+    x1, i1 = amp.solve(M, pc, bt, preset=preset, solo_rows=1 << 20, history=True)
+    x2, i2 = amp.solve(M, pc, bt, preset=preset, solo_rows=0, group_rows=1 << 30, history=True)
+    torch.cuda.synchronize()
+    _say(f"  iters {i1['iters']} / {i2['iters']}, t {i1['t_solve_ms']:.2f} / {i2['t_solve_ms']:.2f} ms")
+    assert i1["status"] == i2["status"] == 0
+    assert i1["iters"] == i2["iters"]
+    for key in ("k_z32", "k_z16", "k_r32", "replacements", "relres_true"):
+        assert i1[key] == i2[key], key
+    assert np.array_equal(i1["delta"], i2["delta"])
+    assert torch.equal(x1, x2)
+    assert i1["relres_true"] <= 1e-10
+
+
+def test_single_workgroup_solve_maxit(amp):
+    # (breakdown on the single-work-group path: test_breakdown_on_indefinite_matrix,
+    # whose small system takes that path by default)
+    _say("solo: maxit")
+    A, b = CASES["poisson37"]()
+    x, info = _gpu_solve(amp, A, b, "amp64", maxit=7)
+    assert info["status"] == 2 and info["iters"] == 7
+    x2, info2 = _gpu_solve(amp, A, b, "amp64", maxit=7, solo_rows=0, group_rows=1 << 30)
+    assert info2["status"] == 2 and info2["iters"] == 7
+    assert np.array_equal(x, x2)
+
+
 # ------------------------------------------------------------------ captured graphs
 
 @pytest.mark.parametrize("case,preset", [("poisson64", "amp16"), ("blocky24", "amp64"), ("poisson37", "pcg64")])
@@ -232,9 +269,9 @@ def test_graph_replay_matches_eager(amp, case, preset):
     pc = amp.Preconditioner(M, "jacobi")
     bt = torch.tensor(b, device="cuda")
     for tol in (1e-10, 1e-6, 1e-10):
-        x0, i0 = amp.solve(M, pc, bt, tol=tol, preset=preset)
+        x0, i0 = amp.solve(M, pc, bt, tol=tol, preset=preset, solo_rows=0)
         for rep in range(3):
-            xg, ig = amp.solve(M, pc, bt, tol=tol, preset=preset, graph=1)
+            xg, ig = amp.solve(M, pc, bt, tol=tol, preset=preset, graph=1, solo_rows=0)
             torch.cuda.synchronize()
             _say(f"  tol {tol} replay {rep}: iters {ig['iters']} (eager {i0['iters']})")
             assert ig["status"] == i0["status"] == 0
@@ -242,7 +279,7 @@ def test_graph_replay_matches_eager(amp, case, preset):
             for key in ("k_z32", "k_z16", "k_r32", "replacements"):
                 assert ig[key] == i0[key], key
             assert torch.equal(xg, x0)
-            xe, ie = amp.solve(M, pc, bt, tol=tol, preset=preset)
+            xe, ie = amp.solve(M, pc, bt, tol=tol, preset=preset, solo_rows=0)
             torch.cuda.synchronize()
             assert torch.equal(xe, x0)
 
