@@ -108,7 +108,7 @@ typedef struct {
     int solo_rows;          /* a system with at most this many (padded) rows, Jacobi or identity and
                                rr_period = 0, is solved by one work-group in one launch (the kernel
                                sequence with one work-group per kernel, in a loop on the device);
-                               0 disables (default 16384) */
+                               0 disables (default 0) */
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
     double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */

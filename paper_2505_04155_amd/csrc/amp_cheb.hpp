@@ -137,7 +137,7 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
         CZ acc = (CZ)0;
         with_cols(P.sptr, P.col, P.soff, P.offs, P.np, sl, lane, [&](const auto &sc) {
             for (int j0 = 0; j0 < wd; j0 += kChunk) {
-                int64_t cc[kChunk];
+                int32_t cc[kChunk];
                 bool dg[kChunk];
                 CZ bv[kChunk], dj[kChunk];
                 sc.chunk(j0, wd, cc, dg);
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64,
         const double si = isq64[row];
         AMP_WITH_COLS(A, sl, lane, sc) {
             for (int j0 = 0; j0 < w; j0 += kChunk) {
-                int64_t cc[kChunk];
+                int32_t cc[kChunk];
                 bool dg[kChunk];
                 sc.chunk(j0, w, cc, dg);
                 for (int u = 0; u < kChunk && j0 + u < w; ++u) {

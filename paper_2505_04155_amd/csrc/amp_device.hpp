@@ -18,7 +18,11 @@ constexpr int NT = AMP_NT;   // threads per work-group of every iteration kernel
 constexpr int WAVE = 64;     // CDNA wavefront width
 constexpr int SLICE = 64;    // sliced-ELL slice height (one row per lane)
 constexpr int VEC = 4;       // consecutive elements per thread in streaming kernels
-constexpr int GMAX = 1024;   // upper bound on work-groups of a reducing kernel
+#ifndef AMP_GMAX
+#define AMP_GMAX 1024
+#endif
+constexpr int GMAX = AMP_GMAX;   // upper bound on work-groups of a reducing kernel
+constexpr int GSTREAM = 1024;    // upper bound on work-groups of a streaming kernel
 constexpr int PAD = NT * VEC;  // internal vectors are padded to a multiple of this
 constexpr int NXCD = 8;      // accelerator complex dies; work-groups are dealt to them round-robin
 
@@ -76,21 +80,24 @@ constexpr int kOffMax = 32;  // longest per-slice offset list
 // Columns of slots j0 .. j0 + kChunk - 1 of one row of a slice, one functor
 // per storage mode.  Slots at or past the row width w give a valid column
 // (the caller adds nothing for them).
-constexpr int kChunk = 8;
+#ifndef AMP_CHUNK
+#define AMP_CHUNK 4
+#endif
+constexpr int kChunk = AMP_CHUNK;   // 4 or 8
 
-struct alignas(32) Off8 {
+struct alignas(4 * kChunk) OffChunk {
     int32_t o[kChunk];
 };
 
 struct OffCols {
-    const int32_t *offs;  // the slice's offset list: 32-byte aligned, padded with 0 to a multiple of kChunk
+    const int32_t *offs;  // the slice's offset list: aligned to and padded with 0 to a multiple of kChunk
     int64_t row, np;
-    __device__ __forceinline__ void chunk(int j0, int /*w*/, int64_t *c, bool *dg) const {
-        const Off8 o = *reinterpret_cast<const Off8 *>(offs + j0);   // one scalar load of 8 offsets
+    __device__ __forceinline__ void chunk(int j0, int /*w*/, int32_t *c, bool *dg) const {
+        const OffChunk o = *reinterpret_cast<const OffChunk *>(offs + j0);   // one scalar load
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
             const int64_t cc = row + o.o[u];
-            c[u] = (cc >= 0 && cc < np) ? cc : row;
+            c[u] = (int32_t)((cc >= 0 && cc < np) ? cc : row);
             dg[u] = o.o[u] == 0;
         }
     }
@@ -99,7 +106,7 @@ struct OffCols {
 struct IdxCols {
     const int32_t *col;   // &col[sptr[s] + lane]
     int64_t row;
-    __device__ __forceinline__ void chunk(int j0, int w, int64_t *c, bool *dg) const {
+    __device__ __forceinline__ void chunk(int j0, int w, int32_t *c, bool *dg) const {
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
             const int j = j0 + u < w ? j0 + u : w - 1;

@@ -102,7 +102,7 @@ template <typename CS, typename PF>
 __device__ __forceinline__ double row_dot64(const Sell &A, const CS &sc, int64_t base, int w, PF pval) {
     double acc = 0.0;
     for (int j0 = 0; j0 < w; j0 += kChunk) {
-        int64_t c[kChunk];
+        int32_t c[kChunk];
         bool dg[kChunk];
         double v[kChunk], pj[kChunk];
         sc.chunk(j0, w, c, dg);
@@ -129,7 +129,7 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t 
     const float *vals = DIFF ? A.v32 : A.v32p;
     float acc = 0.0f, dterm = 0.0f;
     for (int j0 = 0; j0 < w; j0 += kChunk) {
-        int64_t c[kChunk];
+        int32_t c[kChunk];
         bool dg[kChunk];
         float v[kChunk], pj[kChunk];
         sc.chunk(j0, w, c, dg);

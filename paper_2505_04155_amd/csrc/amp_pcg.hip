@@ -146,7 +146,9 @@ static int fit_grid(int64_t g) {
     return (int)g;
 }
 
-static int grid_stream(int64_t np) { return fit_grid((np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC)); }
+static int grid_stream(int64_t np) {
+    return std::min(GSTREAM, fit_grid((np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC)));
+}
 
 static int grid_slices(int64_t nslices) { return fit_grid((nslices + NT / WAVE - 1) / (NT / WAVE)); }
 
@@ -397,6 +399,8 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     if (csr->n <= 0) return fail(AMP_ERR_ARG, "amp_matrix_create: n must be positive");
     if (csr->nnz < csr->n || csr->nnz >= ((int64_t)1 << 31))
         return fail(AMP_ERR_ARG, "amp_matrix_create: need n <= nnz < 2^31");
+    if ((int64_t)csr->n > ((int64_t)1 << 31) - 1 - 2 * PAD)
+        return fail(AMP_ERR_ARG, "amp_matrix_create: n too large for int32 row indices after padding");
     hipStream_t st = as_stream(stream);
     amp_matrix A = new amp_matrix_s();
     auto bail = [&](amp_status s) { amp_matrix_destroy(A); return s; };
@@ -429,7 +433,7 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     free_scan();
     // Offset mode when the slice's offset list costs at most two padding
     // slots per row.  Equal lists are stored once; each list starts at a
-    // multiple of kChunk entries (32 bytes) and is padded with 0 to a
+    // multiple of kChunk entries (aligned for one load) and is padded with 0 to a
     // multiple of kChunk, so a kernel reads kChunk offsets in one load.
     const bool allow = !(flags & 1);
     std::vector<int32_t> hoffs;
@@ -664,7 +668,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->rr_period = 0;
     o->batch = 0;
     o->graph = 0;
-    o->solo_rows = 16384;
+    o->solo_rows = 0;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;

@@ -245,16 +245,20 @@ def test_single_workgroup_solve_matches_kernel_sequence(amp, case, preset):
     assert i1["relres_true"] <= 1e-10
 
 
-def test_single_workgroup_solve_maxit(amp):
-    # (breakdown on the single-work-group path: test_breakdown_on_indefinite_matrix,
-    # whose small system takes that path by default)
-    _say("solo: maxit")
+def test_single_workgroup_solve_maxit_and_breakdown(amp):
+    _say("solo: maxit and breakdown")
+    from paper_2505_04155_amd import binding as B
     A, b = CASES["poisson37"]()
-    x, info = _gpu_solve(amp, A, b, "amp64", maxit=7)
-    assert info["status"] == 2 and info["iters"] == 7
+    x, info = _gpu_solve(amp, A, b, "amp64", maxit=7, solo_rows=1 << 20)
+    assert info["status"] == B.AMP_ERR_NOT_CONVERGED and info["iters"] == 7
     x2, info2 = _gpu_solve(amp, A, b, "amp64", maxit=7, solo_rows=0, group_rows=1 << 30)
-    assert info2["status"] == 2 and info2["iters"] == 7
+    assert info2["status"] == B.AMP_ERR_NOT_CONVERGED and info2["iters"] == 7
     assert np.array_equal(x, x2)
+    D = np.array([[1.0, 3.0, 0.0], [3.0, 1.0, 0.0], [0.0, 0.0, 1.0]])   # indefinite
+    x, info = _gpu_solve(amp, P.dense_to_csr(D), np.array([1.0, -1.0, 0.0]), "pcg64", kind="identity",
+                         solo_rows=1 << 20)
+    assert info["status"] == B.AMP_ERR_BREAKDOWN
+    assert np.all(np.isfinite(x))
 
 
 # ------------------------------------------------------------------ captured graphs
