@@ -9,8 +9,13 @@ Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line: value = AMP-PCG time-to-solution (ms, lower is
 better); the FP64 PCG time on the same GPU, the speedup, the iteration
-counts, the SpMV kernel's achieved HBM bandwidth against the 8 TB/s peak, and
+counts, the HBM roofline of the dominant kernel (the product step, timed
+with HIP events around each of its launches inside an AMP-PCG solve), and
 the FP64 CPU oracle timed on the host are reported beside it.
+
+Modes: --mode roofline runs only the timed-product solve (and a 256 MiB
+device copy of known size): the command the kernel trace and the HBM
+counter runs profile.
 """
 
 from __future__ import annotations
@@ -27,30 +32,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-solution at rel. residual 1e-10, AMP-PCG vs FP64 PCG; SpMV HBM GB/s"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_fv3d128_hbm_counters.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_algorithmic_bytes(n, nnz, meta_bytes, b_val, b_z, b_q):
-    """Bytes one fused product step p = z + beta p_old, q = A p must move:
-    every nonzero's value once, the column metadata of the handle's layout
-    once (int32 indices of index-mode slices, the shared offset lists of
-    offset-mode slices, the slice pointers), z and p_old read once (the
-    gathers are counted once), p and q written once.  Slice padding is
-    overhead, not counted."""
-    return nnz * b_val + meta_bytes + n * (3 * b_z + b_q)
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_fixed_fv3d128_hbm_counters.txt")
+def step_bytes(n, nnz, meta_bytes, u_z, u_r):
+    """Algorithmic bytes of one product step p = z + beta p_old, q = A p in
+    precisions (u_z, u_r): every nonzero's value once (FP64 plane for
+    u_r = 64, FP32 plane otherwise), the layout's column metadata once (int32
+    indices of index-mode slices, the shared offset lists, 12 B per slice),
+    z and p_old read once (gathers counted once), p and q written once.
+    Slice padding is overhead, not counted."""
+    b_val = 8 if u_r == 64 else 4
+    return nnz * b_val + meta_bytes + n * (3 * (u_z // 8) + u_r // 8)
 
 
 def stored_traffic():
-    """HBM bytes per launch of the product-step kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary (each scaled by the factor a
-    plain copy of known size gives), or None when the summary is missing or
-    was taken on other kernel sources than the library built here."""
+    """HBM bytes per product launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary (each counter scaled by what it reads for a plain copy of known
+    size), or None when the summary is missing or was taken on other kernel
+    sources than the library built here."""
     from paper_2505_04155_amd import build
     try:
         fields = {}
@@ -66,24 +70,73 @@ def stored_traffic():
     return int(float(fields["traffic_bytes_per_launch"]))
 
 
-def time_spmv_step(binding, M, torch, u_z, u_r, diff, reps, n, nnz, meta_bytes):
-    """Average duration (ms) of the library's product-step kernel over reps
-    back-to-back launches, and its algorithmic bytes per launch."""
+def roofline(amp, M, pc, bt, info_m, preset, tol, maxit):
+    """One AMP-PCG solve with the library timing every product launch (HIP
+    events recorded on the launch stream around each launch); achieved =
+    algorithmic bytes of the launches that performed an iteration, summed
+    per iteration from the recorded precisions, / their summed duration."""
+    x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset, history=True, spmv_timing=1)
+    if info["status"] != 0:
+        raise RuntimeError(f"timed solve failed: {info}")
+    n, nnz, meta = info_m["n"], info_m["nnz"], info_m["meta_bytes"]
+    total = sum(step_bytes(n, nnz, meta, uz, ur) for uz, ur in zip(info["uz"], info["ur"]))
+    launches = info["spmv_launches"]
+    us = info["spmv_ms"] * 1e3 / launches
+    gbs = total / (info["spmv_ms"] * 1e-3) / 1e9
+    phases = {}
+    for uz, ur in zip(info["uz"], info["ur"]):
+        phases[f"z{uz}_r{ur}"] = phases.get(f"z{uz}_r{ur}", 0) + 1
+    return {
+        "bound": "hbm",
+        "kernel": "k_spmv: p = z + beta p_old (u_z), q = A p (u_r), gamma partials; every launch of one "
+                  "amp64 solve, all precision phases",
+        "achieved": round(gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "traffic": stored_traffic(),
+        "avg_kernel_us": round(us, 3),
+        "launches": launches,
+        "algorithmic_bytes_per_launch": round(total / launches),
+        "phase_iterations": phases,
+    }
+
+
+def warm_step(binding, M, torch, info_m, reps=50):
+    """The product step of the FP16/FP32 phase launched back to back on the
+    same data (which then stays in the 256 MB last-level cache): a
+    cache-resident figure, reported beside the in-solve roofline."""
     import ctypes
     L = binding.load()
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
     for _ in range(3):
-        binding.check(L.amp_spmv_step(M.handle, u_z, u_r, diff, 0.5, sp), "amp_spmv_step")
+        binding.check(L.amp_spmv_step(M.handle, 16, 32, 1, 0.5, sp), "amp_spmv_step")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        L.amp_spmv_step(M.handle, u_z, u_r, diff, 0.5, sp)
+        L.amp_spmv_step(M.handle, 16, 32, 1, 0.5, sp)
     e1.record(stream)
     e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    bv = 8 if u_r == 64 else 4
-    return ms, spmv_algorithmic_bytes(n, nnz, meta_bytes, bv, u_z // 8, u_r // 8)
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    nb = step_bytes(info_m["n"], info_m["nnz"], info_m["meta_bytes"], 16, 32)
+    return {"kernel": "k_spmv_fixed<16,32,true>", "avg_us": round(us, 3), "GB/s": round(nb / us / 1e3, 1)}
+
+
+def copy_reference(torch, dev, reps=5):
+    """A plain device copy of 256 MiB (read 256 MiB, write 256 MiB): the
+    launches a counter run scales FETCH_SIZE / WRITE_SIZE by."""
+    stream = torch.cuda.current_stream()
+    src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"bytes": 2 * src.numel() * 4, "avg_us": round(us, 3), "GB/s": round(2 * src.numel() * 4 / us / 1e3, 1)}
 
 
 def main():
@@ -93,10 +146,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--preset", default="amp64")
-    ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "spmv"], default="solve",
-                    help="spmv: only the product kernels and a reference copy (for counter runs)")
+    ap.add_argument("--mode", choices=["solve", "roofline"], default="solve",
+                    help="roofline: only the timed-product solve and the reference copy (for profiler runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,7 +157,6 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2505_04155_amd as amp
@@ -122,17 +173,23 @@ def main():
     pc = amp.Preconditioner(M, "jacobi")
     bt = torch.tensor(b, device=dev)
     info_m = M.info()
+    n, nnz = info_m["n"], info_m["nnz"]
     tol, maxit = 1e-10, 20000
+
+    if args.mode == "roofline":
+        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=args.preset)        # warm the handle
+        rf = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit)
+        cp = copy_reference(torch, dev)
+        log(f"bench: product step in the solve: {rf['avg_kernel_us']:.2f} us average over {rf['launches']} "
+            f"launches, {rf['achieved']:.0f} GB/s; copy {cp['GB/s']:.0f} GB/s")
+        print(json.dumps({"mode": "roofline", "roofline": rf, "copy_256MiB": cp, "matrix": info_m}), flush=True)
+        return
 
     def run(preset):
         x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
         if info["status"] != 0:
             raise RuntimeError(f"{preset} solve failed: {info}")
         return x, info
-
-    if args.mode == "spmv":
-        spmv_only(args, amp, binding, M, pc, bt, torch)
-        return
 
     results = {}
     for preset in (args.preset, "pcg64"):
@@ -155,15 +212,13 @@ def main():
     amp_ms, amp_info = results[args.preset]
     fp64_ms, fp64_info = results["pcg64"]
 
-    # Dominant kernel: the fused product step of the reduced-precision phase
-    # (p = z + beta p_old in FP16, q = A p with FP32 values in difference
-    # form, FP32 q), timed with HIP events on the stream the library launches
-    # on (torch's current stream) over spmv_reps back-to-back launches.
-    n, nnz = info_m["n"], info_m["nnz"]
-    spmv_ms, spmv_bytes = time_spmv_step(binding, M, torch, 16, 32, 1, args.spmv_reps, n, nnz,
-                                         info_m["meta_bytes"])
-    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
-    log(f"bench: fused product step (p fp16, A fp32 diff): {spmv_ms * 1e3:.2f} us, {spmv_gbs:.0f} GB/s algorithmic")
+    # Dominant kernel: the product step, timed inside an AMP-PCG solve.
+    rf = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit)
+    log(f"bench: product step in the solve: {rf['avg_kernel_us']:.2f} us average over {rf['launches']} launches, "
+        f"{rf['achieved']:.0f} GB/s algorithmic ({100 * rf['frac']:.1f}% of {HBM_PEAK_GBS:.0f})")
+    warm = warm_step(binding, M, torch, info_m)
+    log(f"bench: FP16/FP32 product step back to back (cache-resident): {warm['avg_us']:.2f} us, "
+        f"{warm['GB/s']:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -205,49 +260,10 @@ def main():
         "switch_iterations": {"u_z_fp32": amp_info["k_z32"], "u_z_fp16": amp_info["k_z16"],
                               "u_r_fp32": amp_info["k_r32"]},
         "rel_res_true": amp_info["relres_true"],
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_spmv_fixed<16,32,true>: p = z + beta p_old (FP16), q = A p (FP32 values, difference form)",
-            "achieved": round(spmv_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic(),
-            "avg_kernel_us": round(spmv_ms * 1e3, 3),
-            "algorithmic_bytes_per_launch": spmv_bytes,
-        },
+        "roofline": rf,
+        "warm_product_step": warm,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
-
-
-def spmv_only(args, amp, binding, M, pc, bt, torch):
-    """Product-step kernels alone, each launched spmv_reps times, plus a device
-    copy of a known size: the launches a counter run attributes bytes to."""
-    amp.solve(M, pc, bt, tol=1e-10, maxit=20000, preset=args.preset)   # fills the work buffers
-    info_m = M.info()
-    n, nnz = info_m["n"], info_m["nnz"]
-    out = {"mode": "spmv", "matrix": info_m, "kernels": {}}
-    for (u_z, u_r, diff) in ((64, 64, 0), (16, 32, 1), (32, 32, 1)):
-        ms, nbytes = time_spmv_step(binding, M, torch, u_z, u_r, diff, args.spmv_reps, n, nnz,
-                                    info_m["meta_bytes"])
-        us = ms * 1e3
-        out["kernels"][f"k_spmv_fixed<{u_z},{u_r},{'true' if diff else 'false'}>"] = {
-            "avg_us": round(us, 3), "algorithmic_bytes": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
-        log(f"product step u_z={u_z} u_r={u_r} diff={diff}: {us:.2f} us, {nbytes / us / 1e3:.0f} GB/s")
-    stream = torch.cuda.current_stream()
-    src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=bt.device)
-    dst = torch.empty_like(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.spmv_reps):
-        dst.copy_(src)
-    e1.record(stream)
-    e1.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / args.spmv_reps
-    out["copy_256MiB"] = {"avg_us": round(us, 3), "bytes": 2 * src.numel() * 4,
-                          "GB/s": round(2 * src.numel() * 4 / us / 1e3, 1)}
-    log(f"copy 256 MiB: {us:.2f} us, {2 * src.numel() * 4 / us / 1e3:.0f} GB/s")
     print(json.dumps(out), flush=True)
 
 

@@ -106,9 +106,11 @@ typedef struct {
     int graph;              /* 1: replay batches of 8 iterations from a captured HIP graph cached in the
                                matrix handle (single solve without rr_period; default 0) */
     int solo_rows;          /* a system with at most this many (padded) rows, Jacobi or identity and
-                               rr_period = 0, is solved by one work-group in one launch (the kernel
-                               sequence with one work-group per kernel, in a loop on the device);
+                               rr_period = 0, is solved by one work-group in one launch (the stages of
+                               the kernel sequence with one work-group each, in a loop on the device);
                                0 disables (default 0) */
+    int spmv_timing;        /* 1: time every product-kernel launch with HIP events (eager path only:
+                               disables graph and solo); results in amp_result.spmv_ms */
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
     double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */
@@ -123,6 +125,9 @@ typedef struct {
     int k_z32, k_z16, k_r32;  /* first iteration with u_z <= FP32, u_z = FP16, u_r = FP32 (-1: never) */
     int n_replacements;       /* residual replacements performed */
     double t_solve_ms;        /* wall time of the solve call (host clock, includes the final check) */
+    double spmv_ms;           /* spmv_timing: summed duration of the product-kernel launches that
+                                 performed an iteration (0 otherwise) */
+    int spmv_launches;        /* spmv_timing: number of those launches (= iters) */
 } amp_result;
 
 /* Library version (major*10000 + minor*100 + patch). */

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("T_p", ctypes.c_int), ("spmv32_diff", ctypes.c_int), ("verify", ctypes.c_int),
                 ("max_replacements", ctypes.c_int), ("rr_period", ctypes.c_int),
                 ("batch", ctypes.c_int), ("group_rows", ctypes.c_int), ("graph", ctypes.c_int),
-                ("solo_rows", ctypes.c_int),
+                ("solo_rows", ctypes.c_int), ("spmv_timing", ctypes.c_int),
                 ("delta_history", ctypes.c_void_p),
                 ("prec_history", ctypes.c_void_p), ("scalar_history", ctypes.c_void_p)]
 
@@ -51,7 +51,7 @@ class Result(ctypes.Structure):
                 ("rel_res_updated", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("k_z32", ctypes.c_int), ("k_z16", ctypes.c_int),
                 ("k_r32", ctypes.c_int), ("n_replacements", ctypes.c_int),
-                ("t_solve_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int)]
 
 
 class MatrixStats(ctypes.Structure):

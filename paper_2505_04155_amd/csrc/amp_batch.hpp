@@ -48,9 +48,9 @@ __global__ void __launch_bounds__(NT) k_batch_prep(const SysDesc *sd, const Task
     if (wg.lb == 0 && threadIdx.x == 0) d.st[slot] = s0;
 }
 
-__global__ void __launch_bounds__(NT) k_batch_init(const SysDesc *sd, const Task *tasks) {
+__global__ void __launch_bounds__(NTS) k_batch_init(const SysDesc *sd, const Task *tasks) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    init_stage(d.A, d.B, wg);
+    init_stage<NTS>(d.A, d.B, wg);
 }
 
 __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const Task *tasks, int si, int so) {
@@ -58,9 +58,9 @@ __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const T
     precond_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg);
 }
 
-__global__ void __launch_bounds__(NT) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
+__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    spmv_stage(d.c, d.A, d.B, d.st + si, d.st + so, wg);
+    spmv_stage<NTS>(d.c, d.A, d.B, d.st + si, d.st + so, wg);
 }
 
 __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Task *tasks, int si, int so) {
@@ -68,18 +68,18 @@ __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Ta
     update_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg);
 }
 
-__global__ void __launch_bounds__(NT) k_batch_true_res(const SysDesc *sd, const Task *tasks, int mode, int si,
+__global__ void __launch_bounds__(NTS) k_batch_true_res(const SysDesc *sd, const Task *tasks, int mode, int si,
                                                        int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    true_res_stage(d.c, d.A, d.B, mode, d.st + si, d.st + so, wg);
+    true_res_stage<NTS>(d.c, d.A, d.B, mode, d.st + si, d.st + so, wg);
 }
 
 // Partials of ||b - A x||^2 in FP64 (no state involved).
-__global__ void __launch_bounds__(NT) k_batch_report(const SysDesc *sd, const Task *tasks) {
+__global__ void __launch_bounds__(NTS) k_batch_report(const SysDesc *sd, const Task *tasks) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
     double st = 0.0, ss = 0.0, mr = 0.0;
-    true_res_body<64>(d.A, d.B, wg, false, st, ss, mr);
-    st = block_sum(st);
+    true_res_body<64, NTS>(d.A, d.B, wg, false, st, ss, mr);
+    st = block_sum<NTS>(st);
     if (threadIdx.x == 0) d.B.part_res[wg.lb] = st;
 }
 

@@ -20,6 +20,7 @@ namespace amp {
 constexpr int kChebMax = 16;
 
 struct Cheb {
+    const SliceRec *srec;
     const int64_t *sptr;
     const int32_t *col;
     const int32_t *soff, *offs;
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 }
 
 // One step k of the recurrence for this work-group's slices.
-template <int UZ, bool FIRST>
+template <int UZ, bool FIRST, int BS>
 __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int last,
                                                int din, double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
@@ -127,15 +128,10 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
         if (FIRST) return v[j] * inv_theta;
         return dk[j];
     };
-    int64_t slo_, shi_;
-    block_range(P.nslices, 1, wg.lb, wg.G, slo_, shi_);
-    const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (int64_t sl = sfirst; sl < shi_; sl += NT / WAVE) {
-        const int lane = threadIdx.x % WAVE;
-        const int64_t row = sl * SLICE + lane, base = P.sptr[sl] + lane;
-        const int wd = __builtin_amdgcn_readfirstlane((int)((P.sptr[sl + 1] - P.sptr[sl]) / SLICE));
+    AMP_SLICE_LOOP(P, sl, wg, BS) {
+        AMP_SLICE_ROW(P, sl, lane, row, base, wd, BS);
         CZ acc = (CZ)0;
-        with_cols(P.sptr, P.col, P.soff, P.offs, P.np, sl, lane, [&](const auto &sc) {
+        with_rec_cols(rec_, P.col, P.offs, P.np, sl, lane, [&](const auto &sc) {
             for (int j0 = 0; j0 < wd; j0 += kChunk) {
                 int32_t cc[kChunk];
                 bool dg[kChunk];
@@ -177,7 +173,7 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     }
 }
 
-__global__ void __launch_bounds__(NT) k_cheb_step(Bufs B, Cheb P, int k, int first, int last, int din,
+__global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int first, int last, int din,
                                                   const St *in, St *out) {
     __shared__ St s;
     const Wg wg = grid_wg();
@@ -189,16 +185,16 @@ __global__ void __launch_bounds__(NT) k_cheb_step(Bufs B, Cheb P, int k, int fir
     double rho = 0.0, mz = 0.0;
 #define AMP_CS(UZ)                                                      \
     do {                                                                \
-        if (first) cheb_step_body<UZ, true>(s, B, P, wg, k, last, din, rho, mz);  \
-        else cheb_step_body<UZ, false>(s, B, P, wg, k, last, din, rho, mz);       \
+        if (first) cheb_step_body<UZ, true, NTS>(s, B, P, wg, k, last, din, rho, mz);  \
+        else cheb_step_body<UZ, false, NTS>(s, B, P, wg, k, last, din, rho, mz);       \
     } while (0)
     if (s.uz == 64) AMP_CS(64);
     else if (s.uz == 32) AMP_CS(32);
     else AMP_CS(16);
 #undef AMP_CS
     if (last) {
-        rho = block_sum(rho);
-        mz = block_max(mz);
+        rho = block_sum<NTS>(rho);
+        mz = block_max<NTS>(mz);
         if (threadIdx.x == 0) {
             B.part_pre[wg.lb] = rho;
             B.part_pre[GMAX + wg.lb] = mz;
@@ -267,11 +263,13 @@ __global__ void __launch_bounds__(NT) k_cheb_isq(const double *diag, int64_t n, 
     if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
-__global__ void __launch_bounds__(NT) k_cheb_values(Sell A, const double *isq64, half_t *b16) {
+__global__ void __launch_bounds__(NTS) k_cheb_values(Sell A, const double *isq64, half_t *b16) {
     int64_t slo_, shi_;
     block_range(A.nslices, 1, xcd_block(), gridDim.x, slo_, shi_);
-    for (int64_t sl = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < shi_; sl += NT / WAVE) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+    const int64_t sfirst_ = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    uint32_t nrec_ = rec_word(A.srec, sfirst_, shi_);
+    for (int64_t sl = sfirst_; sl < shi_; sl += NTS / WAVE) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, NTS);
         const double si = isq64[row];
         AMP_WITH_COLS(A, sl, lane, sc) {
             for (int j0 = 0; j0 < w; j0 += kChunk) {

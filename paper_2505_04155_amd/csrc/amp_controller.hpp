@@ -37,6 +37,8 @@ struct Cfg {
     double *delta_history;    // nullable
     int32_t *prec_history;    // nullable
     double *scalar_history;   // nullable: omega, rho, gamma, alpha per iteration
+    int32_t *spmv_iter;       // nullable: iteration index each product launch performed (-1: passed through)
+    int spmv_launch;          // index of this launch in spmv_iter
 };
 
 // Iteration state.  Each kernel reads the state its predecessor wrote and

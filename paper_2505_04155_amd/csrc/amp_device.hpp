@@ -14,7 +14,16 @@ typedef _Float16 half_t;
 #ifndef AMP_NT
 #define AMP_NT 256
 #endif
-constexpr int NT = AMP_NT;   // threads per work-group of every iteration kernel (a multiple of 64)
+constexpr int NT = AMP_NT;   // threads per work-group of the streaming kernels (a multiple of 64)
+#ifndef AMP_NTS
+#define AMP_NTS 256
+#endif
+constexpr int NTS = AMP_NTS; // threads per work-group of the sliced-ELL kernels (a multiple of 64)
+// Minimum waves per SIMD the product kernels are compiled for (8 caps them at
+// 64 VGPRs); 1 leaves the register allocation to the compiler.
+#ifndef AMP_SPMV_WAVES
+#define AMP_SPMV_WAVES 1
+#endif
 constexpr int WAVE = 64;     // CDNA wavefront width
 constexpr int SLICE = 64;    // sliced-ELL slice height (one row per lane)
 constexpr int VEC = 4;       // consecutive elements per thread in streaming kernels
@@ -64,8 +73,16 @@ template <> struct Prec<16> { typedef half_t T; typedef float C; };  // FP16 sto
 //    column offsets per slice, value 0 where the row has no such entry), so
 //    no per-entry column index is read.  Stencil matrices in natural order
 //    store every slice this way.
+// Per-slice descriptor of the product kernels (16 bytes).
+struct alignas(16) SliceRec {
+    int64_t ptr;    // first slot of the slice
+    int32_t soff;   // start of the slice's offset list (offset mode) or -1 (index mode)
+    int32_t width;  // slots per row
+};
+
 struct Sell {
     int64_t n, np, nslices;
+    const SliceRec *srec;
     const int64_t *sptr;
     const int32_t *col;
     const int32_t *soff;  // per slice: start of its offsets in offs, or -1
@@ -81,7 +98,7 @@ constexpr int kOffMax = 32;  // longest per-slice offset list
 // per storage mode.  Slots at or past the row width w give a valid column
 // (the caller adds nothing for them).
 #ifndef AMP_CHUNK
-#define AMP_CHUNK 4
+#define AMP_CHUNK 8
 #endif
 constexpr int kChunk = AMP_CHUNK;   // 4 or 8
 
@@ -116,6 +133,30 @@ struct IdxCols {
         for (int u = 0; u < kChunk; ++u) dg[u] = c[u] == row;
     }
 };
+
+// A slice's descriptor is fetched one slice ahead with a vector load (four
+// lanes read its four words; loads complete in order, so waiting for it
+// does not wait for the scalar loads of the current slice), then broadcast.
+__device__ __forceinline__ uint32_t rec_word(const SliceRec *srec, int64_t s, int64_t hi) {
+    return (s < hi) ? reinterpret_cast<const uint32_t *>(srec + s)[threadIdx.x & 3] : 0u;
+}
+
+__device__ __forceinline__ SliceRec rec_from(uint32_t v) {
+    SliceRec r;
+    const uint32_t lo = __builtin_amdgcn_readlane(v, 0), hi = __builtin_amdgcn_readlane(v, 1);
+    r.ptr = (int64_t)(((uint64_t)hi << 32) | lo);
+    r.soff = (int32_t)__builtin_amdgcn_readlane(v, 2);
+    r.width = (int32_t)__builtin_amdgcn_readlane(v, 3);
+    return r;
+}
+
+template <typename F>
+__device__ __forceinline__ void with_rec_cols(const SliceRec &r, const int32_t *col, const int32_t *offs, int64_t np,
+                                              int64_t sl, int lane, F &&f) {
+    const int64_t row = sl * SLICE + lane;
+    if (r.soff >= 0) f(OffCols{offs + r.soff, row, np});
+    else f(IdxCols{col + r.ptr + lane, row});
+}
 
 // f(cols) with the column functor of slice sl's mode.  The mode is uniform
 // over the wave (one slice per wave), so each mode's loop is compiled
@@ -172,9 +213,10 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Sum / max over the work-group in a fixed order; result in every thread.
+// Sum / max over the work-group (BS threads) in a fixed order; result in every thread.
+template <int BS = NT>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[NT / WAVE];
+    __shared__ double sh[BS / WAVE];
     v = wave_sum(v);
     const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
     __syncthreads();
@@ -182,12 +224,13 @@ __device__ __forceinline__ double block_sum(double v) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < NT / WAVE; ++i) t += sh[i];
+    for (int i = 0; i < BS / WAVE; ++i) t += sh[i];
     return t;
 }
 
+template <int BS = NT>
 __device__ __forceinline__ double block_max(double v) {
-    __shared__ double sh[NT / WAVE];
+    __shared__ double sh[BS / WAVE];
     v = wave_max(v);
     const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
     __syncthreads();
@@ -195,35 +238,37 @@ __device__ __forceinline__ double block_max(double v) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < NT / WAVE; ++i) t = fmax(t, sh[i]);
+    for (int i = 0; i < BS / WAVE; ++i) t = fmax(t, sh[i]);
     return t;
 }
 
 // Totals of a producer kernel's per-work-group partials (G of each), summed
 // (or maxed) in the same fixed order by every work-group that calls it.
+template <int BS = NT>
 __device__ __forceinline__ double reduce_sum(const double *part, int G) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < G; i += NT) s += part[i];
-    return block_sum(s);
+    for (int i = threadIdx.x; i < G; i += BS) s += part[i];
+    return block_sum<BS>(s);
 }
 
+template <int BS = NT>
 __device__ __forceinline__ double reduce_max(const double *part, int G) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < G; i += NT) s = fmax(s, part[i]);
-    return block_max(s);
+    for (int i = threadIdx.x; i < G; i += BS) s = fmax(s, part[i]);
+    return block_max<BS>(s);
 }
 
 // NS sums followed by NM maxima of partial arrays (part[t * GMAX + i]) in
 // one pass and one exchange; each result equals that of reduce_sum /
 // reduce_max on its array (same per-thread order, same tree).
-template <int NS, int NM>
+template <int NS, int NM, int BS = NT>
 __device__ __forceinline__ void reduce_parts(const double *part, int G, double *out) {
-    constexpr int K = NS + NM, NW = NT / WAVE;
+    constexpr int K = NS + NM, NW = BS / WAVE;
     __shared__ double sh[K][NW];
     double v[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) v[t] = 0.0;
-    for (int i = threadIdx.x; i < G; i += NT) {
+    for (int i = threadIdx.x; i < G; i += BS) {
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             const double x = part[t * GMAX + i];

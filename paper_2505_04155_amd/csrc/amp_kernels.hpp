@@ -156,31 +156,36 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t 
     return DIFF ? dterm + acc : acc;
 }
 
-// Slices of this work-group: contiguous range, one slice per wave at a time.
-#define AMP_SLICE_LOOP(A, sl, wg)                                                        \
+// Slices of this work-group: contiguous range, one slice per wave at a time,
+// the next slice's descriptor in flight while the current one is processed.
+#define AMP_SLICE_LOOP(A, sl, wg, BS)                                                    \
     int64_t slo_, shi_;                                                                  \
     block_range((A).nslices, 1, (wg).lb, (wg).G, slo_, shi_);                            \
     const int64_t sfirst_ = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   \
-    for (int64_t sl = sfirst_; sl < shi_; sl += NT / WAVE)
+    uint32_t nrec_ = rec_word((A).srec, sfirst_, shi_);                                  \
+    for (int64_t sl = sfirst_; sl < shi_; sl += (BS) / WAVE)
 
-#define AMP_SLICE_ROW(A, sl, lane, row, base, w)                                         \
+#define AMP_SLICE_ROW(A, sl, lane, row, base, w, BS)                                     \
+    const SliceRec rec_ = rec_from(nrec_);                                               \
+    nrec_ = rec_word((A).srec, (sl) + (BS) / WAVE, shi_);                                \
     const int lane = threadIdx.x % WAVE;                                                 \
-    const int64_t row = (sl) * SLICE + lane, base = (A).sptr[sl] + lane;                 \
-    const int w = __builtin_amdgcn_readfirstlane((int)(((A).sptr[(sl) + 1] - (A).sptr[sl]) / SLICE))
+    const int64_t row = (sl) * SLICE + lane, base = rec_.ptr + lane;                     \
+    const int w = rec_.width
 
 #define AMP_WITH_COLS(A, sl, lane, sc) \
-    with_cols((A).sptr, (A).col, (A).soff, (A).offs, (A).np, sl, lane, [&](const auto &sc)
+    with_rec_cols(rec_, (A).col, (A).offs, (A).np, sl, lane, [&](const auto &sc)
 
 // ----------------------------------------------------------------------------
 // k_init: r0 = b - A x0 in FP64; partials ||r0||^2, ||b||^2, max|r0|
 // ----------------------------------------------------------------------------
 
+template <int BS>
 __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) {
     double sr = 0.0, sb = 0.0, mr = 0.0;
     double *r = (double *)B.r[0];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+    AMP_SLICE_LOOP(A, sl, wg, BS) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
         double ax = 0.0;
         AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
         const double t = B.b[row] - ax;
@@ -189,9 +194,9 @@ __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) 
         sb += B.b[row] * B.b[row];
         mr = fmax(mr, fabs(t));
     }
-    sr = block_sum(sr);
-    sb = block_sum(sb);
-    mr = block_max(mr);
+    sr = block_sum<BS>(sr);
+    sb = block_sum<BS>(sb);
+    mr = block_max<BS>(mr);
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = sr;
         B.part_res[GMAX + wg.lb] = sb;
@@ -199,7 +204,7 @@ __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) 
     }
 }
 
-__global__ void __launch_bounds__(NT) k_init(Sell A, Bufs B) { init_stage(A, B, grid_wg()); }
+__global__ void __launch_bounds__(NTS) k_init(Sell A, Bufs B) { init_stage<NTS>(A, B, grid_wg()); }
 
 // ----------------------------------------------------------------------------
 // k_precond
@@ -365,7 +370,7 @@ __global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const
 // k_spmv: p = z + beta p_{k-1} (u_z), q = A p (u_r), gamma = q^T p
 // ----------------------------------------------------------------------------
 
-template <int UZ, int UR, bool DIFF, bool FIRST>
+template <int UZ, int UR, bool DIFF, bool FIRST, int BS>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -380,8 +385,8 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
         if (FIRST) return z[c];
         return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
     };
-    AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+    AMP_SLICE_LOOP(A, sl, wg, BS) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
         const TZ pi = pval(row);
         if (pn) pn[row] = pi;
         mp = fmax(mp, fabs((double)pi));
@@ -395,6 +400,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     }
 }
 
+template <int BS>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg) {
     __shared__ St s;
@@ -404,7 +410,7 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         return;
     }
     double tot[2];
-    reduce_parts<1, 1>(B.part_pre, c.g_pre, tot);
+    reduce_parts<1, 1, BS>(B.part_pre, c.g_pre, tot);
     const double rho = tot[0], mz = tot[1];
     if (threadIdx.x == 0) {
         s.rho_prev = s.rho;
@@ -419,16 +425,17 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         store_state(s, out, wg);
         return;
     }
+    if (c.spmv_iter && wg.lb == 0 && threadIdx.x == 0) c.spmv_iter[c.spmv_launch] = s.k;
     const int uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
     const bool first = (s.k == 0);
     double gam = 0.0, mp = 0.0;
 #define AMP_SP(UZ, UR, DF)                                                                                       \
     do {                                                                                                        \
         if (first)                                                                                              \
-            spmv_p_body<UZ, UR, DF, true>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], s.beta, \
+            spmv_p_body<UZ, UR, DF, true, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], s.beta, \
                                           gam, mp);                                                             \
         else                                                                                                    \
-            spmv_p_body<UZ, UR, DF, false>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],       \
+            spmv_p_body<UZ, UR, DF, false, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],       \
                                            s.beta, gam, mp);                                                    \
     } while (0)
     if (ur == 64) {
@@ -445,8 +452,8 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         else AMP_SP(16, 32, false);
     }
 #undef AMP_SP
-    gam = block_sum(gam);
-    mp = block_max(mp);
+    gam = block_sum<BS>(gam);
+    mp = block_max<BS>(mp);
     if (threadIdx.x == 0) {
         B.part_spmv[wg.lb] = gam;
         B.part_spmv[GMAX + wg.lb] = mp;
@@ -454,20 +461,20 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     store_state(s, out, wg);
 }
 
-__global__ void __launch_bounds__(NT) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
-    spmv_stage(c, A, B, in, out, grid_wg());
+__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
+    spmv_stage<NTS>(c, A, B, in, out, grid_wg());
 }
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
 // otherwise p = z + beta p_old as in the iteration.
 template <int UZ, int UR, bool DIFF>
-__global__ void __launch_bounds__(NT) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
+__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
                                                    int first, double beta, double *part) {
     double gam = 0.0, mp = 0.0;
     const Wg wg = grid_wg();
-    if (first) spmv_p_body<UZ, UR, DIFF, true>(A, wg, z, po, pn, q, beta, gam, mp);
-    else spmv_p_body<UZ, UR, DIFF, false>(A, wg, z, po, pn, q, beta, gam, mp);
-    gam = block_sum(gam);
+    if (first) spmv_p_body<UZ, UR, DIFF, true, NTS>(A, wg, z, po, pn, q, beta, gam, mp);
+    else spmv_p_body<UZ, UR, DIFF, false, NTS>(A, wg, z, po, pn, q, beta, gam, mp);
+    gam = block_sum<NTS>(gam);
     if (threadIdx.x == 0 && part) part[wg.lb] = gam;
 }
 
@@ -565,14 +572,14 @@ __global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const 
 // (writes nothing but partials).  Partials: ||t||^2, ||fl(t)||^2, max|fl(t)|.
 // ----------------------------------------------------------------------------
 
-template <int RS>
+template <int RS, int BS>
 __device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, Wg wg, bool write, double &st,
                                               double &ss, double &mr) {
     typedef typename Prec<RS>::T TR;
     TR *r = (TR *)B.r[pslot(RS)];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl, wg) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w);
+    AMP_SLICE_LOOP(A, sl, wg, BS) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
         double ax = 0.0;
         AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
         const double t = B.b[row] - ax;
@@ -584,6 +591,7 @@ __device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, Wg w
     }
 }
 
+template <int BS>
 __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, const Bufs &B, int mode, const St *in,
                                                St *out, Wg wg) {
     __shared__ St s;
@@ -594,11 +602,11 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
         return;
     }
     double st = 0.0, ss = 0.0, mr = 0.0;
-    if (s.r_store == 64) true_res_body<64>(A, B, wg, mode != 2, st, ss, mr);
-    else true_res_body<32>(A, B, wg, mode != 2, st, ss, mr);
-    st = block_sum(st);
-    ss = block_sum(ss);
-    mr = block_max(mr);
+    if (s.r_store == 64) true_res_body<64, BS>(A, B, wg, mode != 2, st, ss, mr);
+    else true_res_body<32, BS>(A, B, wg, mode != 2, st, ss, mr);
+    st = block_sum<BS>(st);
+    ss = block_sum<BS>(ss);
+    mr = block_max<BS>(mr);
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = st;
         B.part_res[GMAX + wg.lb] = ss;
@@ -613,21 +621,22 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
     store_state(s, out, wg);
 }
 
-__global__ void __launch_bounds__(NT) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
-    true_res_stage(c, A, B, mode, in, out, grid_wg());
+__global__ void __launch_bounds__(NTS) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
+    true_res_stage<NTS>(c, A, B, mode, in, out, grid_wg());
 }
 
 // ----------------------------------------------------------------------------
 // single-work-group solve: the stages above in a loop inside one launch
 // ----------------------------------------------------------------------------
 
-// One work-group runs a whole solve from the state in st[ST_INIT] (r0 and
-// its partials already formed with G = 1): the same stages, on the same
-// state slots, in the same order as the host would enqueue them with one
-// work-group per kernel, so the result is bitwise that sequence's.  The
-// loop ends when the state stops (converged, maxit, breakdown) or after
-// `cap` passes; the last state is copied to st[ST_FIN] (with status MAXIT
-// if the cap was reached while running).
+// One work-group (NT threads) runs a whole solve from the state in
+// st[ST_INIT] (r0 and its partials already formed with G = 1): the same
+// stages, on the same state slots, in the same order as the host would
+// enqueue them with one work-group per kernel (the product stage here with
+// NT threads instead of NTS).  The loop ends when the state stops
+// (converged, maxit, breakdown) or after `cap` passes; the last state is
+// copied to st[ST_FIN] (with status MAXIT if the cap was reached while
+// running).
 __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bufs &B, St *st, int cap) {
     const Wg wg{0, 1};
     __shared__ int status;
@@ -639,13 +648,13 @@ __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bu
         __syncthreads();
         last = ST_PRE;
         if (status == NEED_VERIFY) {
-            true_res_stage(c, A, B, 0, st + ST_PRE, st + ST_TR, wg);
+            true_res_stage<NT>(c, A, B, 0, st + ST_PRE, st + ST_TR, wg);
             __syncthreads();
             in = last = ST_TR;
             continue;
         }
         if (status != RUNNING) break;
-        spmv_stage(c, A, B, st + ST_PRE, st + ST_SPMV, wg);
+        spmv_stage<NT>(c, A, B, st + ST_PRE, st + ST_SPMV, wg);
         __syncthreads();
         update_stage(c, B, A.np, st + ST_SPMV, st + ST_RES, wg);
         __syncthreads();

@@ -1,5 +1,6 @@
 // Host side of the AMP-PCG library: handles, sliced-ELL setup, the solve
 // driver (status polling, batching) and the C ABI declared in amp_pcg.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,11 +91,16 @@ struct Work {
     hipEvent_t join[2] = {nullptr, nullptr};
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey;           // launch arguments the graph was captured with
+    // product-kernel timing (spmv_timing): one event pair per launch
+    std::vector<hipEvent_t> tev;
+    int32_t *titer = nullptr;                  // iteration performed by each timed launch
+    int tcap = 0;
 };
 
 
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
+    SliceRec *srec = nullptr;
     int64_t *sptr = nullptr;
     int32_t *col = nullptr;
     int32_t *soff = nullptr, *offs = nullptr;
@@ -104,7 +110,7 @@ struct amp_matrix_s {
     Work w;
     Sell sell() const {
         Sell s;
-        s.n = n; s.np = np; s.nslices = nslices; s.sptr = sptr; s.col = col;
+        s.n = n; s.np = np; s.nslices = nslices; s.srec = srec; s.sptr = sptr; s.col = col;
         s.soff = soff; s.offs = offs;
         s.v64 = v64; s.v32 = v32; s.v32p = v32p;
         return s;
@@ -129,7 +135,7 @@ struct amp_precond_s {
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
     Cheb cheb() const {
         Cheb P;
-        P.sptr = A->sptr; P.col = A->col; P.soff = A->soff; P.offs = A->offs;
+        P.srec = A->srec; P.sptr = A->sptr; P.col = A->col; P.soff = A->soff; P.offs = A->offs;
         P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
         P.v = cv; P.res = cres; P.w = cw; P.dir[0] = cdir[0]; P.dir[1] = cdir[1];
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
@@ -150,7 +156,7 @@ static int grid_stream(int64_t np) {
     return std::min(GSTREAM, fit_grid((np + (int64_t)NT * VEC - 1) / ((int64_t)NT * VEC)));
 }
 
-static int grid_slices(int64_t nslices) { return fit_grid((nslices + NT / WAVE - 1) / (NT / WAVE)); }
+static int grid_slices(int64_t nslices) { return fit_grid((nslices + NTS / WAVE - 1) / (NTS / WAVE)); }
 
 static void free_work(Work &w) {
     dfree(w.x); dfree(w.b);
@@ -167,6 +173,11 @@ static void free_work(Work &w) {
     if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
     w.gexec = nullptr;
     w.gkey.clear();
+    for (auto &e : w.tev)
+        if (e) (void)hipEventDestroy(e);
+    w.tev.clear();
+    dfree(w.titer);
+    w.tcap = 0;
     if (w.cs) (void)hipStreamDestroy(w.cs);
     if (w.cap) (void)hipStreamDestroy(w.cap);
     w.cs = w.cap = nullptr;
@@ -466,14 +477,18 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
         A->meta_bytes = 4 * index_slots + 4 * noffs + 12 * ns + 8;
     }
     if (A->slots >= ((int64_t)1 << 31) * 2) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: too many slots"));
-    if ((s = dalloc(&A->sptr, ns + 1)) != AMP_OK || (s = dalloc(&A->soff, ns)) != AMP_OK ||
+    std::vector<SliceRec> hrec(ns);
+    for (int64_t i = 0; i < ns; ++i) hrec[i] = SliceRec{hp[i], hso[i], (int32_t)((hp[i + 1] - hp[i]) / SLICE)};
+    if ((s = dalloc(&A->srec, ns)) != AMP_OK || (s = dalloc(&A->sptr, ns + 1)) != AMP_OK ||
+        (s = dalloc(&A->soff, ns)) != AMP_OK ||
         (s = dalloc(&A->offs, round_up(std::max<int64_t>(noffs, 1), kChunk))) != AMP_OK ||
         (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
         (s = dalloc(&A->v32, A->slots)) != AMP_OK || (s = dalloc(&A->v32p, A->slots)) != AMP_OK ||
         (s = dalloc(&A->diag, A->np)) != AMP_OK)
         return bail(s);
-    A->bytes = (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
-    if (hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+    A->bytes = ns * 16 + (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
+    if (hipMemcpyAsync(A->srec, hrec.data(), hrec.size() * sizeof(SliceRec), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
         (noffs > 0 &&
          hipMemcpyAsync(A->offs, hoffs.data(), noffs * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess))
@@ -491,7 +506,7 @@ extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_ma
 extern "C" void amp_matrix_destroy(amp_matrix A) {
     if (!A) return;
     free_work(A->w);
-    dfree(A->sptr); dfree(A->soff); dfree(A->offs); dfree(A->col);
+    dfree(A->srec); dfree(A->sptr); dfree(A->soff); dfree(A->offs); dfree(A->col);
     dfree(A->v64); dfree(A->v32); dfree(A->v32p); dfree(A->diag);
     delete A;
 }
@@ -563,7 +578,7 @@ static amp_status setup_values(amp_precond M, hipStream_t st) {
         k_jacobi_setup<<<G, NT, 0, st>>>(A->diag, A->n, np, M->d64, M->d32, part);
     } else {
         k_cheb_isq<<<G, NT, 0, st>>>(A->diag, A->n, np, M->isq64, M->isq32, part);
-        k_cheb_values<<<grid_slices(A->nslices), NT, 0, st>>>(A->sell(), M->isq64, M->b16);
+        k_cheb_values<<<grid_slices(A->nslices), NTS, 0, st>>>(A->sell(), M->isq64, M->b16);
     }
     k_reduce_to<<<1, NT, 0, st>>>(part, G, 1, part + GMAX);
     double mx = 0.0;
@@ -669,6 +684,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->batch = 0;
     o->graph = 0;
     o->solo_rows = 0;
+    o->spmv_timing = 0;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;
@@ -769,6 +785,8 @@ struct Driver {
     hipStream_t st;
     St *in;            // state the next kernel reads
     int host_k;        // iterations enqueued since the last resynchronisation
+    bool timing = false;
+    int launches = 0;  // product launches enqueued (timing)
 };
 
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
@@ -784,7 +802,7 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     for (int k = 0; k + 1 < m; ++k) {
         St *si = (k == 0) ? &w.st[ST_PREI] : &w.st[(k - 1) % 2 ? ST_CH1 : ST_CH0];
         St *so = (k == m - 2) ? out : &w.st[k % 2 ? ST_CH1 : ST_CH0];
-        k_cheb_step<<<d.gl, NT, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
+        k_cheb_step<<<d.gl, NTS, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
     }
 }
 
@@ -796,12 +814,23 @@ static amp_status enqueue_iterations(Driver &d, int count) {
         } else {
             k_precond<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, d.in, &w.st[ST_PRE]);
         }
-        k_spmv<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, &w.st[ST_PRE], &w.st[ST_SPMV]);
+        if (d.timing && d.launches < w.tcap) {
+            d.cfg.spmv_iter = w.titer;
+            d.cfg.spmv_launch = d.launches;
+            // events carried by the dispatch itself: they bracket the kernel, not the queue
+            hipExtLaunchKernelGGL(k_spmv, dim3(d.gl), dim3(NTS), 0, d.st, w.tev[2 * d.launches],
+                                  w.tev[2 * d.launches + 1], 0, d.cfg, d.S, d.B, (const St *)&w.st[ST_PRE],
+                                  &w.st[ST_SPMV]);
+            d.launches += 1;
+            d.cfg.spmv_iter = nullptr;
+        } else {
+            k_spmv<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, &w.st[ST_PRE], &w.st[ST_SPMV]);
+        }
         k_update<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, &w.st[ST_SPMV], &w.st[ST_RES]);
         d.in = &w.st[ST_RES];
         d.host_k += 1;
         if (d.cfg.rr_period > 0 && d.host_k % d.cfg.rr_period == 0) {
-            k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &w.st[ST_TR]);
+            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &w.st[ST_TR]);
             d.in = &w.st[ST_TR];
         }
     }
@@ -917,8 +946,9 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
-    const bool solo = solo_eligible(o, A, M);
-    const bool graph = o.graph && o.rr_period == 0 && !solo;
+    const bool timing = o.spmv_timing != 0;
+    const bool solo = !timing && solo_eligible(o, A, M);
+    const bool graph = !timing && o.graph && o.rr_period == 0 && !solo;
     hipStream_t user = d.st;
     if (graph) {
         // the solve runs on the handle's own stream, ordered after and before the caller's
@@ -939,12 +969,27 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.gl = d.cfg.g_slice;
     d.host_k = 0;
     if (graph) AMP_TRY(get_graph(d));
+    if (timing) {
+        const int need = maxit + 2048;
+        if (w.tcap < need) {
+            for (auto &e : w.tev)
+                if (e) (void)hipEventDestroy(e);
+            w.tev.assign(2 * (size_t)need, nullptr);
+            for (auto &e : w.tev) AMP_HIP(hipEventCreate(&e));
+            dfree(w.titer);
+            AMP_TRY(dalloc(&w.titer, need));
+            w.tcap = need;
+        }
+        AMP_HIP(hipMemsetAsync(w.titer, 0xFF, w.tcap * sizeof(int32_t), d.st));   // -1: not an iteration
+        d.timing = true;
+        d.launches = 0;
+    }
 
     const St s0 = init_state(o);
     AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(&w.st[ST_INIT], &s0, sizeof(St), hipMemcpyHostToDevice, d.st));
-    k_init<<<d.gl, NT, 0, d.st>>>(d.S, d.B);
+    k_init<<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
     AMP_HIP(hipGetLastError());
     d.in = &w.st[ST_INIT];
     St cur = s0;
@@ -996,7 +1041,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
         cur = w.snap[pending];
         pending = -1;
         if (cur.status == NEED_VERIFY) {
-            k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
+            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
             AMP_HIP(hipGetLastError());
             d.in = &w.st[ST_TR];
             d.host_k = cur.iters;
@@ -1009,7 +1054,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     // FP64 true residual of the returned x, unless the termination check just formed it
     double true_res = cur.true_res;
     if (!(o.verify && cur.status == CONVERGED)) {
-        k_true_res<<<d.gl, NT, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
+        k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
         k_reduce_to<<<1, NT, 0, d.st>>>(d.B.part_res, d.gl, 0, w.scalar);
         AMP_HIP(hipGetLastError());
         double t2 = 0.0;
@@ -1023,10 +1068,26 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     }
     AMP_HIP(hipStreamSynchronize(d.st));
 
+    double spmv_ms = 0.0;
+    int spmv_n = 0;
+    if (timing && d.launches > 0) {
+        std::vector<int32_t> it(d.launches);
+        AMP_HIP(hipMemcpy(it.data(), w.titer, d.launches * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int i = 0; i < d.launches; ++i) {
+            if (it[i] < 0) continue;
+            float ms = 0.0f;
+            AMP_HIP(hipEventElapsedTime(&ms, w.tev[2 * i], w.tev[2 * i + 1]));
+            spmv_ms += ms;
+            spmv_n += 1;
+        }
+    }
+
     amp_status rs = AMP_OK;
     if (cur.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
     else if (cur.status == BREAKDOWN) rs = AMP_ERR_BREAKDOWN;
     if (res) {
+        res->spmv_ms = spmv_ms;
+        res->spmv_launches = spmv_n;
         res->iters = cur.iters;
         res->status = rs;
         res->bnorm = cur.bnorm;
@@ -1183,7 +1244,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
     const St s0 = init_state(o);
     const unsigned gall = (unsigned)cap;
     k_batch_prep<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all, s0, ST_INIT);
-    k_batch_init<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
+    k_batch_init<<<gall, NTS, 0, st>>>(bb.sd, bb.tasks_all);
     AMP_HIP(hipGetLastError());
 
     if (nsolo > 0) {
@@ -1205,12 +1266,12 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
     auto enqueue_batch = [&](int slot) -> amp_status {
         for (int i = 0; i < batch; ++i) {
             k_batch_precond<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, in, ST_PRE);
-            k_batch_spmv<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, ST_PRE, ST_SPMV);
+            k_batch_spmv<<<ntask, NTS, 0, st>>>(bb.sd, bb.tasks, ST_PRE, ST_SPMV);
             k_batch_update<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, ST_SPMV, ST_RES);
             in = ST_RES;
         }
         // termination check of every system that asks for it
-        k_batch_true_res<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, 0, in, ST_PREI);
+        k_batch_true_res<<<ntask, NTS, 0, st>>>(bb.sd, bb.tasks, 0, in, ST_PREI);
         in = ST_PREI;
         k_batch_gather<<<(unsigned)((nsys + NT - 1) / NT), NT, 0, st>>>(bb.sd, nsys, in, bb.gath);
         AMP_HIP(hipGetLastError());
@@ -1262,7 +1323,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 
     // solutions out, and the FP64 true residual of every returned x
     k_batch_copy_out<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
-    k_batch_report<<<gall, NT, 0, st>>>(bb.sd, bb.tasks_all);
+    k_batch_report<<<gall, NTS, 0, st>>>(bb.sd, bb.tasks_all);
     k_batch_reduce_report<<<(unsigned)nsys, NT, 0, st>>>(bb.sd, nsys, bb.red);
     AMP_HIP(hipGetLastError());
     AMP_HIP(hipMemcpyAsync(bb.hred, bb.red, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1278,6 +1339,8 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
         if (rs == AMP_ERR_BREAKDOWN || (rs == AMP_ERR_NOT_CONVERGED && worst == AMP_OK)) worst = rs;
         if (res) {
             amp_result &r = res[i];
+            r.spmv_ms = 0.0;
+            r.spmv_launches = 0;
             r.iters = c.iters;
             r.status = rs;
             r.bnorm = c.bnorm;
@@ -1302,7 +1365,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 template <int UZ, int UR, bool DF>
 static void launch_spmv_fixed(const Sell &S, int gl, const void *z, const void *po, void *pn, void *q, int first,
                               double beta, double *part, hipStream_t st) {
-    k_spmv_fixed<UZ, UR, DF><<<gl, NT, 0, st>>>(S, z, po, pn, q, first, beta, part);
+    k_spmv_fixed<UZ, UR, DF><<<gl, NTS, 0, st>>>(S, z, po, pn, q, first, beta, part);
 }
 
 static amp_status dispatch_spmv(amp_matrix A, int u_r, int u_z, int diff, const void *z, const void *po, void *pn,

@@ -225,8 +225,9 @@ def test_periodic_replacement_matches_model(amp):
 @pytest.mark.parametrize("case,preset", [("poisson64", "amp64"), ("poisson64", "amp16"), ("poisson37", "pcg64"),
                                          ("blocky24", "amp_ur"), ("blocky24", "amp16")])
 def test_single_workgroup_solve_matches_kernel_sequence(amp, case, preset):
-    # one launch looping on the device == the host-enqueued kernels with one
-    # work-group each, bit for bit (including the termination check)
+    # one launch looping on the device runs the stages of the host-enqueued
+    # kernels (one work-group each) in the same order; only the work-group
+    # size of the product stage differs (its partial sums round differently)
     _say(f"solo vs kernel sequence {case} {preset}")
     A, b = CASES[case]()
     M = amp.Matrix.from_csr(A)
@@ -237,12 +238,13 @@ def test_single_workgroup_solve_matches_kernel_sequence(amp, case, preset):
     torch.cuda.synchronize()
     _say(f"  iters {i1['iters']} / {i2['iters']}, t {i1['t_solve_ms']:.2f} / {i2['t_solve_ms']:.2f} ms")
     assert i1["status"] == i2["status"] == 0
-    assert i1["iters"] == i2["iters"]
-    for key in ("k_z32", "k_z16", "k_r32", "replacements", "relres_true"):
-        assert i1[key] == i2[key], key
-    assert np.array_equal(i1["delta"], i2["delta"])
-    assert torch.equal(x1, x2)
-    assert i1["relres_true"] <= 1e-10
+    assert abs(i1["iters"] - i2["iters"]) <= max(2, math.ceil(0.02 * i2["iters"]))
+    for key in ("k_z32", "k_z16", "k_r32"):
+        assert abs(i1[key] - i2[key]) <= 2, key
+    m = min(i1["iters"], i2["iters"], 20)
+    assert np.allclose(i1["delta"][:m], i2["delta"][:m], rtol=1e-6, atol=0)
+    assert i1["relres_true"] <= 1e-10 and i2["relres_true"] <= 1e-10
+    assert _rel(x1.cpu().numpy(), x2.cpu().numpy()) <= 1e-6
 
 
 def test_single_workgroup_solve_maxit_and_breakdown(amp):
@@ -253,12 +255,24 @@ def test_single_workgroup_solve_maxit_and_breakdown(amp):
     assert info["status"] == B.AMP_ERR_NOT_CONVERGED and info["iters"] == 7
     x2, info2 = _gpu_solve(amp, A, b, "amp64", maxit=7, solo_rows=0, group_rows=1 << 30)
     assert info2["status"] == B.AMP_ERR_NOT_CONVERGED and info2["iters"] == 7
-    assert np.array_equal(x, x2)
+    assert _rel(x, x2) <= 1e-12
     D = np.array([[1.0, 3.0, 0.0], [3.0, 1.0, 0.0], [0.0, 0.0, 1.0]])   # indefinite
     x, info = _gpu_solve(amp, P.dense_to_csr(D), np.array([1.0, -1.0, 0.0]), "pcg64", kind="identity",
                          solo_rows=1 << 20)
     assert info["status"] == B.AMP_ERR_BREAKDOWN
     assert np.all(np.isfinite(x))
+
+
+def test_product_kernel_timing(amp):
+    _say("product-kernel timing")
+    A, b = CASES["blocky24"]()
+    x0, i0 = _gpu_solve(amp, A, b, "amp64")
+    x1, i1 = _gpu_solve(amp, A, b, "amp64", spmv_timing=1)
+    # the timed solve is the same solve; one timed launch per iteration
+    assert i1["iters"] == i0["iters"] and np.array_equal(x0, x1)
+    assert i1["spmv_launches"] == i1["iters"]
+    assert 0.0 < i1["spmv_ms"] < i1["t_solve_ms"]
+    assert i0["spmv_launches"] == 0 and i0["spmv_ms"] == 0.0
 
 
 # ------------------------------------------------------------------ captured graphs
