@@ -7,11 +7,13 @@ on a 128^3 grid with block coefficients 10^U, U ~ U[0, 4] on 8^3 blocks
 (N = 2,097,152, nnz = 14,581,760), Jacobi preconditioner, tol 1e-10.
 Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line: value = AMP-PCG time-to-solution (ms, lower is
-better); the FP64 PCG time on the same GPU, the speedup, the iteration
+Prints one JSON line: value = AMP-PCG(FP16) time-to-solution (ms, lower is
+better; the variant the paper times: z and p in FP16 from the start, r and q
+switching FP64 -> FP32 by the delay criterion); the stepwise AMP-PCG(FP64)
+time, the FP64 PCG time on the same GPU, the speedups, the iteration
 counts, the HBM roofline of the dominant kernel (the product step, timed
-with HIP events around each of its launches inside an AMP-PCG solve), and
-the FP64 CPU oracle timed on the host are reported beside it.
+with HIP events carried by each of its launches inside the AMP-PCG solve),
+and the FP64 CPU oracle timed on the host are reported beside it.
 
 Modes: --mode roofline runs only the timed-product solve (and a 256 MiB
 device copy of known size): the command the kernel trace and the HBM
@@ -72,9 +74,10 @@ def stored_traffic():
 
 def roofline(amp, M, pc, bt, info_m, preset, tol, maxit):
     """One AMP-PCG solve with the library timing every product launch (HIP
-    events recorded on the launch stream around each launch); achieved =
-    algorithmic bytes of the launches that performed an iteration, summed
-    per iteration from the recorded precisions, / their summed duration."""
+    events carried by the launch's own dispatch on the solve's stream);
+    achieved = algorithmic bytes of the launches that performed an
+    iteration, summed per iteration from the recorded precisions, / their
+    summed duration."""
     x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset, history=True, spmv_timing=1)
     if info["status"] != 0:
         raise RuntimeError(f"timed solve failed: {info}")
@@ -88,8 +91,8 @@ def roofline(amp, M, pc, bt, info_m, preset, tol, maxit):
         phases[f"z{uz}_r{ur}"] = phases.get(f"z{uz}_r{ur}", 0) + 1
     return {
         "bound": "hbm",
-        "kernel": "k_spmv: p = z + beta p_old (u_z), q = A p (u_r), gamma partials; every launch of one "
-                  "amp64 solve, all precision phases",
+        "kernel": f"k_spmv: p = z + beta p_old (u_z), q = A p (u_r), gamma partials; every launch of one "
+                  f"{preset} solve, all precision phases",
         "achieved": round(gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -145,7 +148,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=128)
-    ap.add_argument("--preset", default="amp64")
+    ap.add_argument("--preset", default="amp16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["solve", "roofline"], default="solve",
                     help="roofline: only the timed-product solve and the reference copy (for profiler runs)")
@@ -192,7 +195,8 @@ def main():
         return x, info
 
     results = {}
-    for preset in (args.preset, "pcg64"):
+    presets = [args.preset] + [p for p in ("amp64", "pcg64") if p != args.preset]
+    for preset in presets:
         for w in range(args.warmup):
             run(preset)
             log(f"bench: warmup {preset} {w + 1}/{args.warmup} done")
@@ -255,6 +259,9 @@ def main():
         },
         "fp64_pcg_ms": round(fp64_ms, 4),
         "speedup_vs_fp64_pcg": round(fp64_ms / amp_ms, 4),
+        "amp64_ms": round(results["amp64"][0], 4),
+        "amp64_iters": results["amp64"][1]["iters"],
+        "speedup_amp64_vs_fp64_pcg": round(fp64_ms / results["amp64"][0], 4),
         "iters": amp_info["iters"],
         "iters_fp64": fp64_info["iters"],
         "switch_iterations": {"u_z_fp32": amp_info["k_z32"], "u_z_fp16": amp_info["k_z16"],
