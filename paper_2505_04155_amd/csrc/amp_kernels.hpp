@@ -156,6 +156,52 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t 
     return DIFF ? dterm + acc : acc;
 }
 
+// The FP32 product for two rows of two slices at once (both slices in
+// offset mode, of equal width): every chunk's loads of both rows are issued
+// before either row is summed.  Each row's sum is formed exactly as by
+// row_dot32.  (For FP64 products the doubled registers cost more than the
+// overlap gains; they run one slice at a time.)
+template <bool DIFF, typename PF>
+__device__ __forceinline__ void row_dot32x2(const Sell &A, const OffCols &s1, const OffCols &s2, int64_t b1,
+                                            int64_t b2, int w, float pi1, float pi2, PF pval, float &q1,
+                                            float &q2) {
+    const float *vals = DIFF ? A.v32 : A.v32p;
+    float a1 = 0.0f, a2 = 0.0f, t1d = 0.0f, t2d = 0.0f;
+    for (int j0 = 0; j0 < w; j0 += kChunk) {
+        int32_t c1[kChunk], c2[kChunk];
+        bool d1[kChunk], d2[kChunk];
+        float v1[kChunk], v2[kChunk], p1[kChunk], p2[kChunk];
+        s1.chunk(j0, w, c1, d1);
+        s2.chunk(j0, w, c2, d2);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int j = j0 + u < w ? j0 + u : w - 1;
+            v1[u] = vals[b1 + (int64_t)j * SLICE];
+            v2[u] = vals[b2 + (int64_t)j * SLICE];
+            p1[u] = (float)pval(c1[u]);
+            p2[u] = (float)pval(c2[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const bool in = j0 + u < w;
+            if (!DIFF) {
+                const float x1 = a1 + v1[u] * p1[u], x2 = a2 + v2[u] * p2[u];
+                a1 = in ? x1 : a1;
+                a2 = in ? x2 : a2;
+            } else {
+                const float e1 = t1d + v1[u] * p1[u], o1 = a1 + v1[u] * (p1[u] - pi1);
+                const float e2 = t2d + v2[u] * p2[u], o2 = a2 + v2[u] * (p2[u] - pi2);
+                t1d = (in && d1[u]) ? e1 : t1d;
+                a1 = (in && !d1[u]) ? o1 : a1;
+                t2d = (in && d2[u]) ? e2 : t2d;
+                a2 = (in && !d2[u]) ? o2 : a2;
+            }
+        }
+    }
+    q1 = DIFF ? t1d + a1 : a1;
+    q2 = DIFF ? t2d + a2 : a2;
+}
+
 // Slices of this work-group: contiguous range, one slice per wave at a time,
 // the next slice's descriptor in flight while the current one is processed.
 #define AMP_SLICE_LOOP(A, sl, wg, BS)                                                    \
@@ -376,6 +422,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
     typedef typename Prec<UR>::T TQ;
+    typedef typename Prec<UR>::C CQ;
     const TZ *z = (const TZ *)zv;
     const TZ *po = (const TZ *)pov;
     TZ *pn = (TZ *)pnv;
@@ -385,8 +432,12 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
         if (FIRST) return z[c];
         return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
     };
-    AMP_SLICE_LOOP(A, sl, wg, BS) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
+    constexpr int NW = BS / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    // one slice: the general path (either storage mode)
+    auto one = [&](int64_t sl, const SliceRec &rec_) {
+        const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
+        const int w = rec_.width;
         const TZ pi = pval(row);
         if (pn) pn[row] = pi;
         mp = fmax(mp, fabs((double)pi));
@@ -397,6 +448,43 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
         });
         q[row] = qq;
         gam += (double)qq * (double)pi;
+    };
+    // FP32 products: slices sl and sl + NW of this wave's sequence are
+    // processed together (the sequence and every per-thread sum keep the
+    // one-at-a-time order).
+    int64_t slo_, shi_;
+    block_range(A.nslices, 1, wg.lb, wg.G, slo_, shi_);
+    const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    uint32_t nr1 = rec_word(A.srec, sfirst, shi_), nr2 = rec_word(A.srec, sfirst + NW, shi_);
+    for (int64_t sl = sfirst; sl < shi_; sl += 2 * NW) {
+        const int64_t sl2 = sl + NW;
+        const bool two = sl2 < shi_;
+        const SliceRec r1 = rec_from(nr1), r2 = rec_from(nr2);
+        nr1 = rec_word(A.srec, sl + 2 * NW, shi_);
+        nr2 = rec_word(A.srec, sl + 3 * NW, shi_);
+        if (UR == 32 && two && r1.soff >= 0 && r2.soff >= 0 && r1.width == r2.width) {
+            const int64_t row1 = sl * SLICE + lane, row2 = sl2 * SLICE + lane;
+            const TZ pi1 = pval(row1), pi2 = pval(row2);
+            const OffCols c1{A.offs + r1.soff, row1, A.np}, c2{A.offs + r2.soff, row2, A.np};
+            CQ q1 = 0, q2 = 0;
+            if constexpr (UR == 32)
+                row_dot32x2<DIFF>(A, c1, c2, r1.ptr + lane, r2.ptr + lane, r1.width, (float)pi1, (float)pi2, pval,
+                                  q1, q2);
+            const TQ qq1 = (TQ)q1, qq2 = (TQ)q2;
+            if (pn) {
+                pn[row1] = pi1;
+                pn[row2] = pi2;
+            }
+            mp = fmax(mp, fabs((double)pi1));
+            mp = fmax(mp, fabs((double)pi2));
+            q[row1] = qq1;
+            q[row2] = qq2;
+            gam += (double)qq1 * (double)pi1;
+            gam += (double)qq2 * (double)pi2;
+        } else {
+            one(sl, r1);
+            if (two) one(sl2, r2);
+        }
     }
 }
 
