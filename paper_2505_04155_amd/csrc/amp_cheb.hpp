@@ -70,13 +70,15 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
 __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int standalone, const St *in, St *out) {
     __shared__ St s;
     const Wg wg = grid_wg();
+    ResIn ri;
+    if (!standalone) res_loads(c, B, ri);
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
     }
     if (!standalone) {
-        consume_residual(s, c, B, wg);
+        consume_residual(s, c, B, wg, ri);
         __syncthreads();
         if (s.status != RUNNING) {
             store_state(s, out, wg);

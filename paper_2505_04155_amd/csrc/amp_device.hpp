@@ -258,21 +258,45 @@ __device__ __forceinline__ double reduce_max(const double *part, int G) {
     return block_max<BS>(s);
 }
 
-// NS sums followed by NM maxima of partial arrays (part[t * GMAX + i]) in
-// one pass and one exchange; each result equals that of reduce_sum /
-// reduce_max on its array (same per-thread order, same tree).
+// Partials of a producer kernel held in registers: thread t holds entries
+// t, t + BS, ... of each of K arrays.  Loading them is split from reducing
+// them so that a kernel can issue these loads together with its other
+// prologue loads (state, body data) and wait for all of them once.
+template <int K, int BS = NT>
+struct PartRegs {
+    static constexpr int J = GMAX / BS;
+    double v[K][J];
+};
+
+// Entries i < G of the arrays part[t * GMAX + i], t < K (1 <= G <= GMAX).
+// Slots past G load entry G - 1 (ignored by the reduction): every load is
+// unconditional, so all of them are in flight at once.
+template <int K, int BS = NT>
+__device__ __forceinline__ void load_parts(const double *part, int G, PartRegs<K, BS> &pr) {
+#pragma unroll
+    for (int j = 0; j < PartRegs<K, BS>::J; ++j) {
+        const int i = threadIdx.x + j * BS;
+        const int ic = i < G ? i : G - 1;
+#pragma unroll
+        for (int t = 0; t < K; ++t) pr.v[t][j] = part[t * GMAX + ic];
+    }
+}
+
+// NS sums followed by NM maxima of the first G entries of loaded partials;
+// each result equals that of reduce_sum / reduce_max on its array (same
+// per-thread order, same tree).
 template <int NS, int NM, int BS = NT>
-__device__ __forceinline__ void reduce_parts(const double *part, int G, double *out) {
+__device__ __forceinline__ void reduce_loaded(const PartRegs<NS + NM, BS> &pr, int G, double *out) {
     constexpr int K = NS + NM, NW = BS / WAVE;
     __shared__ double sh[K][NW];
     double v[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) v[t] = 0.0;
-    for (int i = threadIdx.x; i < G; i += BS) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const double x = part[t * GMAX + i];
-            v[t] = (t < NS) ? v[t] + x : fmax(v[t], x);
+    for (int j = 0; j < PartRegs<K, BS>::J; ++j) {
+        if (threadIdx.x + j * BS < G) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) v[t] = (t < NS) ? v[t] + pr.v[t][j] : fmax(v[t], pr.v[t][j]);
         }
     }
 #pragma unroll
@@ -290,6 +314,15 @@ __device__ __forceinline__ void reduce_parts(const double *part, int G, double *
         for (int i = 0; i < NW; ++i) r = (t < NS) ? r + sh[t][i] : fmax(r, sh[t][i]);
         out[t] = r;
     }
+}
+
+// NS sums followed by NM maxima of partial arrays (part[t * GMAX + i]) in
+// one pass and one exchange.
+template <int NS, int NM, int BS = NT>
+__device__ __forceinline__ void reduce_parts(const double *part, int G, double *out) {
+    PartRegs<NS + NM, BS> pr;
+    load_parts<NS + NM, BS>(part, G, pr);
+    reduce_loaded<NS, NM, BS>(pr, G, out);
 }
 
 }  // namespace amp

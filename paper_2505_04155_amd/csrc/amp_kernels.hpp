@@ -256,15 +256,30 @@ __global__ void __launch_bounds__(NTS) k_init(Sell A, Bufs B) { init_stage<NTS>(
 // k_precond
 // ----------------------------------------------------------------------------
 
+// Prologue inputs of the preconditioning kernel, loaded before the state so
+// that both round trips overlap: the residual partials (entries below the
+// larger producer grid; the reduction keeps those below the count of the
+// producer the state names) and the window of residual norms.
+struct ResIn {
+    PartRegs<3> pr;
+    double ring_v;
+};
+static_assert(kRing <= NT, "one ring entry per thread");
+
+__device__ __forceinline__ void res_loads(const Cfg &c, const Bufs &B, ResIn &ri) {
+    load_parts<3>(B.part_res, c.g_stream > c.g_slice ? c.g_stream : c.g_slice, ri.pr);
+    ri.ring_v = (threadIdx.x < kRing) ? c.ring[threadIdx.x] : 0.0;
+}
+
 // Prologue: totals of the residual partials -> controller.  Sets s.status.
-__device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B, Wg wg) {
+__device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs &B, Wg wg, const ResIn &ri) {
     __shared__ int rec;
     __shared__ double recv;
     __shared__ double ring[kRing];   // the residual-norm window, read in parallel for the controller
-    for (int i = threadIdx.x; i < kRing; i += NT) ring[i] = c.ring[i];
+    if (threadIdx.x < kRing) ring[threadIdx.x] = ri.ring_v;
     const int G = (s.kind == RES_UPDATE) ? c.g_stream : c.g_slice;
     double tot[3];
-    reduce_parts<2, 1>(B.part_res, G, tot);   // its barrier also publishes ring[]
+    reduce_loaded<2, 1>(ri.pr, G, tot);   // its barrier also publishes ring[]
     const double a = tot[0], b = tot[1], m = tot[2];
     if (threadIdx.x == 0) {
         rec = -1;
@@ -317,9 +332,40 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
     }
 }
 
+// One VEC-element chunk of a vector whose element size (8, 4 or 2 bytes) is
+// known only from the state, as raw bits: four 8-byte loads at offsets
+// clamped to the chunk, with no branch on the size, so that the loads stay
+// in flight until the bits are used.
+struct Raw {
+    uint2 w[4];
+};
+static_assert(VEC == 4, "a chunk is at most 32 bytes");
+__device__ __forceinline__ void raw_load(const void *base, int bytes, int64_t i, Raw &r) {
+    const char *p = (const char *)base + i * bytes;   // i is a multiple of VEC: 8-byte aligned
+    const int last = VEC * bytes - 8;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) r.w[h] = *(const uint2 *)(p + (8 * h < last ? 8 * h : last));
+}
+template <typename T>
+__device__ __forceinline__ V4<T> raw_as(const Raw &r) {
+    static_assert(sizeof(V4<T>) <= sizeof(Raw), "chunk fits");
+    V4<T> v;
+    __builtin_memcpy(&v, &r, sizeof(V4<T>));
+    return v;
+}
+
+// r_k and the Jacobi data for this thread's first two chunks, loaded before
+// the controller has chosen iteration k's precisions (r is held in r_store,
+// which the controller does not change; the Jacobi data in the incoming u_z,
+// used only if u_z stays).
+struct PcPre {
+    Raw r[2], d[2];
+    int uz;
+};
+
 template <int RS, int UR, int UZ>
-__device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t np, Wg wg, double &rho,
-                                             double &mz) {
+__device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t np, Wg wg, const PcPre &pre,
+                                             double &rho, double &mz) {
     typedef typename Prec<RS>::T TRS;
     typedef typename Prec<UR>::T TR;
     typedef typename Prec<UZ>::T TZ;
@@ -329,9 +375,7 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
     TZ *z = (TZ *)B.z[pslot(UZ)];
     const TZ *dv = (const TZ *)B.dinv[pslot(UZ)];
     const TR w = (TR)s.omega_eff;
-    AMP_STREAM_LOOP(i, np, wg) {
-        const V4<TRS> rv = ld4(r, i);
-        const V4<TZ> dd = ld4(dv, i);
+    auto chunk = [&](int64_t i, const V4<TRS> &rv, const V4<TZ> &dd) {
         V4<TZ> zz;
         V4<TR> rr;
 #pragma unroll
@@ -346,7 +390,16 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
         }
         st4(z, i, zz);
         if (RS != UR) st4(rn, i, rr);
+    };
+    int64_t lo, hi;
+    block_range(np, (int64_t)NT * VEC, wg.lb, wg.G, lo, hi);
+    int64_t i = lo + (int64_t)threadIdx.x * VEC;
+    if (pre.uz == UZ) {   // chunks 0 and 1 are in registers
+#pragma unroll
+        for (int j = 0; j < 2; ++j, i += (int64_t)NT * VEC)
+            if (i < hi) chunk(i, raw_as<TRS>(pre.r[j]), raw_as<TZ>(pre.d[j]));
     }
+    for (; i < hi; i += (int64_t)NT * VEC) chunk(i, ld4(r, i), ld4(dv, i));
 }
 
 // At a u_z switch p_{k-1} is first rounded to the new u_z.
@@ -368,12 +421,30 @@ __device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np, Wg 
 __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
                                               Wg wg) {
     __shared__ St s;
+    ResIn ri;
+    res_loads(c, B, ri);
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
     }
-    consume_residual(s, c, B, wg);
+    PcPre pre;
+    {
+        int64_t lo, hi;
+        block_range(np, (int64_t)NT * VEC, wg.lb, wg.G, lo, hi);
+        const int64_t i0 = lo + (int64_t)threadIdx.x * VEC;
+        pre.uz = s.uz;
+        const void *rv = B.r[pslot(s.r_store)];
+        const void *dv = B.dinv[pslot(s.uz)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            // chunks past this work-group's range load chunk 0 (unused): no branch
+            const int64_t i = i0 + (int64_t)j * NT * VEC < hi ? i0 + (int64_t)j * NT * VEC : 0;
+            raw_load(rv, s.r_store / 8, i, pre.r[j]);
+            raw_load(dv, s.uz / 8, i, pre.d[j]);
+        }
+    }
+    consume_residual(s, c, B, wg, ri);
     __syncthreads();
     if (s.status != RUNNING) {
         store_state(s, out, wg);
@@ -381,7 +452,7 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
     }
     const int rs = s.r_store, ur = s.ur, uz = s.uz;
     double rho = 0.0, mz = 0.0;
-#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, wg, rho, mz)
+#define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, wg, pre, rho, mz)
 #define AMP_PC_Z(RS, UR)                  \
     if (uz == 64) AMP_PC(RS, UR, 64);       \
     else if (uz == 32) AMP_PC(RS, UR, 32);  \
@@ -492,13 +563,15 @@ template <int BS>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg) {
     __shared__ St s;
+    PartRegs<2, BS> pr;
+    load_parts<2, BS>(B.part_pre, c.g_pre, pr);   // in flight during the state load
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
     }
     double tot[2];
-    reduce_parts<1, 1, BS>(B.part_pre, c.g_pre, tot);
+    reduce_loaded<1, 1, BS>(pr, c.g_pre, tot);
     const double rho = tot[0], mz = tot[1];
     if (threadIdx.x == 0) {
         s.rho_prev = s.rho;
@@ -570,43 +643,28 @@ __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv_fixed(Sell A, cons
 // k_update: x += alpha p (FP64), r -= alpha q (u_r); partials ||r||^2, max|r|
 // ----------------------------------------------------------------------------
 
+// The body loads for this thread's first two chunks are issued before the
+// partials of gamma are reduced; the precisions come from the incoming state
+// (the update does not change them).
 template <int UP, int UR>
-__device__ __forceinline__ void update_body(double alpha, const Bufs &B, const void *pv, int64_t np, Wg wg,
-                                            double &dd, double &mr) {
+__device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t np, St &s, const PartRegs<2> &pr,
+                                           St *out, Wg wg) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
-    const TP *p = (const TP *)pv;
+    const TP *p = (const TP *)B.p[pslot(UP)][s.pbuf ^ 1];
     TR *r = (TR *)B.r[pslot(UR)];
     const TR *q = (const TR *)B.q[pslot(UR)];
-    const TR a = (TR)alpha;
-    AMP_STREAM_LOOP(i, np, wg) {
-        const V4<TP> pv4 = ld4(p, i);
-        V4<double> xv = ld4(B.x, i);
-        V4<TR> rv = ld4(r, i);
-        const V4<TR> qv = ld4(q, i);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
-            const TR rn = (TR)(rv.v[e] - a * qv.v[e]);
-            rv.v[e] = rn;
-            dd += (double)rn * (double)rn;
-            mr = fmax(mr, fabs((double)rn));
-        }
-        st4(B.x, i, xv);
-        st4(r, i, rv);
-    }
-}
-
-__device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
-                                             Wg wg) {
-    __shared__ St s;
-    load_state(s, in);
-    if (s.status != RUNNING) {
-        store_state(s, out, wg);
-        return;
-    }
+    int64_t lo, hi;
+    block_range(np, (int64_t)NT * VEC, wg.lb, wg.G, lo, hi);
+    constexpr int64_t step = (int64_t)NT * VEC;
+    const int64_t i0 = lo + (int64_t)threadIdx.x * VEC;
+    // chunks past this work-group's range load chunk 0 (unused): no branch
+    const int64_t j0 = i0 < hi ? i0 : 0, j1 = i0 + step < hi ? i0 + step : 0;
+    const V4<TP> p0 = ld4(p, j0), p1 = ld4(p, j1);
+    const V4<double> x0 = ld4(B.x, j0), x1 = ld4(B.x, j1);
+    const V4<TR> r0 = ld4(r, j0), r1 = ld4(r, j1), q0 = ld4(q, j0), q1 = ld4(q, j1);
     double tot[2];
-    reduce_parts<1, 1>(B.part_spmv, c.g_slice, tot);
+    reduce_loaded<1, 1>(pr, c.g_slice, tot);
     const double gam = tot[0], mp = tot[1];
     if (threadIdx.x == 0) {
         s.gamma = gam;
@@ -623,18 +681,24 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
         store_state(s, out, wg);
         return;
     }
-    const int uz = s.uz, ur = s.ur;
-    const void *p = B.p[pslot(uz)][s.pbuf ^ 1];
+    const double alpha = s.alpha;
+    const TR a = (TR)alpha;
     double dd = 0.0, mr = 0.0;
-    if (ur == 64) {
-        if (uz == 64) update_body<64, 64>(s.alpha, B, p, np, wg, dd, mr);
-        else if (uz == 32) update_body<32, 64>(s.alpha, B, p, np, wg, dd, mr);
-        else update_body<16, 64>(s.alpha, B, p, np, wg, dd, mr);
-    } else {
-        if (uz == 64) update_body<64, 32>(s.alpha, B, p, np, wg, dd, mr);
-        else if (uz == 32) update_body<32, 32>(s.alpha, B, p, np, wg, dd, mr);
-        else update_body<16, 32>(s.alpha, B, p, np, wg, dd, mr);
-    }
+    auto chunk = [&](int64_t i, const V4<TP> &pv4, V4<double> xv, V4<TR> rv, const V4<TR> &qv) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
+            const TR rn = (TR)(rv.v[e] - a * qv.v[e]);
+            rv.v[e] = rn;
+            dd += (double)rn * (double)rn;
+            mr = fmax(mr, fabs((double)rn));
+        }
+        st4(B.x, i, xv);
+        st4(r, i, rv);
+    };
+    if (i0 < hi) chunk(i0, p0, x0, r0, q0);
+    if (i0 + step < hi) chunk(i0 + step, p1, x1, r1, q1);
+    for (int64_t i = i0 + 2 * step; i < hi; i += step) chunk(i, ld4(p, i), ld4(B.x, i), ld4(r, i), ld4(q, i));
     dd = block_sum(dd);
     mr = block_max(mr);
     if (threadIdx.x == 0) {
@@ -642,11 +706,33 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
         B.part_res[GMAX + wg.lb] = 0.0;
         B.part_res[2 * GMAX + wg.lb] = mr;
         s.pbuf ^= 1;
-        s.p_store = uz;
+        s.p_store = UP;
         s.iters = s.k + 1;
         s.kind = RES_UPDATE;
     }
     store_state(s, out, wg);
+}
+
+__device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
+                                             Wg wg) {
+    __shared__ St s;
+    PartRegs<2> pr;
+    load_parts<2>(B.part_spmv, c.g_slice, pr);   // in flight during the state load
+    load_state(s, in);
+    if (s.status != RUNNING) {
+        store_state(s, out, wg);
+        return;
+    }
+    const int uz = s.uz, ur = s.ur;
+    if (ur == 64) {
+        if (uz == 64) update_run<64, 64>(c, B, np, s, pr, out, wg);
+        else if (uz == 32) update_run<32, 64>(c, B, np, s, pr, out, wg);
+        else update_run<16, 64>(c, B, np, s, pr, out, wg);
+    } else {
+        if (uz == 64) update_run<64, 32>(c, B, np, s, pr, out, wg);
+        else if (uz == 32) update_run<32, 32>(c, B, np, s, pr, out, wg);
+        else update_run<16, 32>(c, B, np, s, pr, out, wg);
+    }
 }
 
 __global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
