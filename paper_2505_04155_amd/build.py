@@ -30,6 +30,8 @@ def flags() -> list[str]:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         # one rounding per operation, as the precision model prescribes
         "-ffp-contract=off",
+        # leading pointer/int kernel arguments arrive in SGPRs at launch
+        "-mllvm", "-amdgpu-kernarg-preload-count=16",
         "-fno-gpu-rdc", "-Wall", "-Wno-unused-result",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     ]

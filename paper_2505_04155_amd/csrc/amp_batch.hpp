@@ -55,17 +55,17 @@ __global__ void __launch_bounds__(NTS) k_batch_init(const SysDesc *sd, const Tas
 
 __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    precond_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg);
+    precond_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg, res_early(d.c, d.B));
 }
 
 __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    spmv_stage<NTS>(d.c, d.A, d.B, d.st + si, d.st + so, wg);
+    spmv_stage<NTS>(d.c, d.A, d.B, d.st + si, d.st + so, wg, pre_early(d.c, d.B));
 }
 
 __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    update_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg);
+    update_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg, spmv_early(d.c, d.B));
 }
 
 __global__ void __launch_bounds__(NTS) k_batch_true_res(const SysDesc *sd, const Task *tasks, int mode, int si,

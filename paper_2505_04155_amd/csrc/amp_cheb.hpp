@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
     __shared__ St s;
     const Wg wg = grid_wg();
     ResIn ri;
-    if (!standalone) res_loads(c, B, ri);
+    if (!standalone) res_loads(res_early(c, B), ri);
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);

@@ -175,11 +175,11 @@ __device__ __forceinline__ void with_cols(const int64_t *sptr, const int32_t *co
 // b % 8; renumbering gives XCD x the contiguous block range
 // [x G/8, (x+1) G/8) and thus a contiguous row range (its L2 then holds the
 // rows' neighbours).  G must be a multiple of 8 for an exact split.
-__device__ __forceinline__ int xcd_block() {
-    const int G = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int xcd_index(int b, int G) {
     if (G % NXCD) return b;
     return (b % NXCD) * (G / NXCD) + b / NXCD;
 }
+__device__ __forceinline__ int xcd_block() { return xcd_index(blockIdx.x, gridDim.x); }
 
 // A work-group's share of one system's work: logical index lb of G groups.
 // A single-system launch uses the whole grid (grid_wg); a batched launch
@@ -189,6 +189,11 @@ struct Wg {
 };
 
 __device__ __forceinline__ Wg grid_wg() { return Wg{xcd_block(), (int)gridDim.x}; }
+
+// The same for a launch whose grid size G the caller passes as an argument
+// (the iteration kernels: their first loads then wait for nothing but the
+// preloaded arguments).  G must be the launch's grid size.
+__device__ __forceinline__ Wg launch_wg(int G) { return Wg{xcd_index(blockIdx.x, G), G}; }
 
 // [lo, hi) share of `total` units for work-group lb of G, in multiples of `quantum`.
 __device__ __forceinline__ void block_range(int64_t total, int64_t quantum, int lb, int G,

@@ -70,6 +70,17 @@ __device__ __forceinline__ void st4(T *p, int64_t i, const V4<T> &x) {
 // state plumbing
 // ----------------------------------------------------------------------------
 
+// What a kernel's first memory round trip needs besides the state pointer:
+// the producer's partial arrays, how many work-groups wrote them, and the
+// residual-norm window.  The single-system kernels take these as their
+// leading scalar arguments, which the hardware preloads into registers, so
+// the first loads are issued without waiting for the argument segment.
+struct Early {
+    const double *part;
+    int g;
+    const double *ring;
+};
+
 // Load the incoming state into LDS (all threads see it after the barrier).
 __device__ __forceinline__ void load_state(St &s, const St *in) {
     if (threadIdx.x == 0) s = *in;
@@ -266,9 +277,18 @@ struct ResIn {
 };
 static_assert(kRing <= NT, "one ring entry per thread");
 
-__device__ __forceinline__ void res_loads(const Cfg &c, const Bufs &B, ResIn &ri) {
-    load_parts<3>(B.part_res, c.g_stream > c.g_slice ? c.g_stream : c.g_slice, ri.pr);
-    ri.ring_v = (threadIdx.x < kRing) ? c.ring[threadIdx.x] : 0.0;
+// The Early arguments of each stage, from the solve's configuration.
+__device__ __forceinline__ Early res_early(const Cfg &c, const Bufs &B) {
+    return Early{B.part_res, c.g_stream > c.g_slice ? c.g_stream : c.g_slice, c.ring};
+}
+__device__ __forceinline__ Early pre_early(const Cfg &c, const Bufs &B) { return Early{B.part_pre, c.g_pre, nullptr}; }
+__device__ __forceinline__ Early spmv_early(const Cfg &c, const Bufs &B) {
+    return Early{B.part_spmv, c.g_slice, nullptr};
+}
+
+__device__ __forceinline__ void res_loads(const Early &e, ResIn &ri) {
+    load_parts<3>(e.part, e.g, ri.pr);
+    ri.ring_v = (threadIdx.x < kRing) ? e.ring[threadIdx.x] : 0.0;
 }
 
 // Prologue: totals of the residual partials -> controller.  Sets s.status.
@@ -419,10 +439,10 @@ __device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np, Wg 
 }
 
 __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
-                                              Wg wg) {
+                                              Wg wg, const Early &e) {
     __shared__ St s;
     ResIn ri;
-    res_loads(c, B, ri);
+    res_loads(e, ri);
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
@@ -479,8 +499,9 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
     store_state(s, out, wg);
 }
 
-__global__ void __launch_bounds__(NT) k_precond(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
-    precond_stage(c, B, np, in, out, grid_wg());
+__global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part, int gpart, int grid,
+                                                const double *ring, Cfg c, Bufs B, int64_t np, St *out) {
+    precond_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, ring});
 }
 
 // ----------------------------------------------------------------------------
@@ -561,17 +582,17 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
 
 template <int BS>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
-                                           Wg wg) {
+                                           Wg wg, const Early &e) {
     __shared__ St s;
     PartRegs<2, BS> pr;
-    load_parts<2, BS>(B.part_pre, c.g_pre, pr);   // in flight during the state load
+    load_parts<2, BS>(e.part, e.g, pr);   // in flight during the state load
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
     }
     double tot[2];
-    reduce_loaded<1, 1, BS>(pr, c.g_pre, tot);
+    reduce_loaded<1, 1, BS>(pr, e.g, tot);
     const double rho = tot[0], mz = tot[1];
     if (threadIdx.x == 0) {
         s.rho_prev = s.rho;
@@ -622,8 +643,9 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     store_state(s, out, wg);
 }
 
-__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv(Cfg c, Sell A, Bufs B, const St *in, St *out) {
-    spmv_stage<NTS>(c, A, B, in, out, grid_wg());
+__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv(const St *in, const double *part, int gpart, int grid,
+                                                                Cfg c, Sell A, Bufs B, St *out) {
+    spmv_stage<NTS>(c, A, B, in, out, launch_wg(grid), Early{part, gpart, nullptr});
 }
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
@@ -648,7 +670,7 @@ __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv_fixed(Sell A, cons
 // (the update does not change them).
 template <int UP, int UR>
 __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t np, St &s, const PartRegs<2> &pr,
-                                           St *out, Wg wg) {
+                                           int gpart, St *out, Wg wg) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
     const TP *p = (const TP *)B.p[pslot(UP)][s.pbuf ^ 1];
@@ -664,7 +686,7 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
     const V4<double> x0 = ld4(B.x, j0), x1 = ld4(B.x, j1);
     const V4<TR> r0 = ld4(r, j0), r1 = ld4(r, j1), q0 = ld4(q, j0), q1 = ld4(q, j1);
     double tot[2];
-    reduce_loaded<1, 1>(pr, c.g_slice, tot);
+    reduce_loaded<1, 1>(pr, gpart, tot);
     const double gam = tot[0], mp = tot[1];
     if (threadIdx.x == 0) {
         s.gamma = gam;
@@ -714,10 +736,10 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
 }
 
 __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
-                                             Wg wg) {
+                                             Wg wg, const Early &e) {
     __shared__ St s;
     PartRegs<2> pr;
-    load_parts<2>(B.part_spmv, c.g_slice, pr);   // in flight during the state load
+    load_parts<2>(e.part, e.g, pr);   // in flight during the state load
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
@@ -725,18 +747,19 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
     }
     const int uz = s.uz, ur = s.ur;
     if (ur == 64) {
-        if (uz == 64) update_run<64, 64>(c, B, np, s, pr, out, wg);
-        else if (uz == 32) update_run<32, 64>(c, B, np, s, pr, out, wg);
-        else update_run<16, 64>(c, B, np, s, pr, out, wg);
+        if (uz == 64) update_run<64, 64>(c, B, np, s, pr, e.g, out, wg);
+        else if (uz == 32) update_run<32, 64>(c, B, np, s, pr, e.g, out, wg);
+        else update_run<16, 64>(c, B, np, s, pr, e.g, out, wg);
     } else {
-        if (uz == 64) update_run<64, 32>(c, B, np, s, pr, out, wg);
-        else if (uz == 32) update_run<32, 32>(c, B, np, s, pr, out, wg);
-        else update_run<16, 32>(c, B, np, s, pr, out, wg);
+        if (uz == 64) update_run<64, 32>(c, B, np, s, pr, e.g, out, wg);
+        else if (uz == 32) update_run<32, 32>(c, B, np, s, pr, e.g, out, wg);
+        else update_run<16, 32>(c, B, np, s, pr, e.g, out, wg);
     }
 }
 
-__global__ void __launch_bounds__(NT) k_update(Cfg c, Bufs B, int64_t np, const St *in, St *out) {
-    update_stage(c, B, np, in, out, grid_wg());
+__global__ void __launch_bounds__(NT) k_update(const St *in, const double *part, int gpart, int grid, Cfg c,
+                                               Bufs B, int64_t np, St *out) {
+    update_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, nullptr});
 }
 
 // ----------------------------------------------------------------------------
@@ -816,7 +839,7 @@ __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bu
     __shared__ int status;
     int in = ST_INIT, last = ST_INIT;
     for (int pass = 0; pass < cap; ++pass) {
-        precond_stage(c, B, A.np, st + in, st + ST_PRE, wg);
+        precond_stage(c, B, A.np, st + in, st + ST_PRE, wg, res_early(c, B));
         __syncthreads();
         if (threadIdx.x == 0) status = st[ST_PRE].status;
         __syncthreads();
@@ -828,9 +851,9 @@ __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bu
             continue;
         }
         if (status != RUNNING) break;
-        spmv_stage<NT>(c, A, B, st + ST_PRE, st + ST_SPMV, wg);
+        spmv_stage<NT>(c, A, B, st + ST_PRE, st + ST_SPMV, wg, pre_early(c, B));
         __syncthreads();
-        update_stage(c, B, A.np, st + ST_SPMV, st + ST_RES, wg);
+        update_stage(c, B, A.np, st + ST_SPMV, st + ST_RES, wg, spmv_early(c, B));
         __syncthreads();
         in = last = ST_RES;
     }

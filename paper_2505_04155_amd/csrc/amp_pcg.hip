@@ -812,21 +812,24 @@ static amp_status enqueue_iterations(Driver &d, int count) {
         if (d.M->kind == AMP_PC_CHEBYSHEV) {
             enqueue_chebyshev(d, 0, d.in, &w.st[ST_PRE]);
         } else {
-            k_precond<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, d.in, &w.st[ST_PRE]);
+            k_precond<<<d.gs, NT, 0, d.st>>>(d.in, d.B.part_res, std::max(d.cfg.g_stream, d.cfg.g_slice), d.gs,
+                                             d.cfg.ring, d.cfg, d.B, d.A->np, &w.st[ST_PRE]);
         }
         if (d.timing && d.launches < w.tcap) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
             hipExtLaunchKernelGGL(k_spmv, dim3(d.gl), dim3(NTS), 0, d.st, w.tev[2 * d.launches],
-                                  w.tev[2 * d.launches + 1], 0, d.cfg, d.S, d.B, (const St *)&w.st[ST_PRE],
+                                  w.tev[2 * d.launches + 1], 0, (const St *)&w.st[ST_PRE],
+                                  (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B,
                                   &w.st[ST_SPMV]);
             d.launches += 1;
             d.cfg.spmv_iter = nullptr;
         } else {
-            k_spmv<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, &w.st[ST_PRE], &w.st[ST_SPMV]);
+            k_spmv<<<d.gl, NTS, 0, d.st>>>(&w.st[ST_PRE], d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &w.st[ST_SPMV]);
         }
-        k_update<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, &w.st[ST_SPMV], &w.st[ST_RES]);
+        k_update<<<d.gs, NT, 0, d.st>>>(&w.st[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
+                                        &w.st[ST_RES]);
         d.in = &w.st[ST_RES];
         d.host_k += 1;
         if (d.cfg.rr_period > 0 && d.host_k % d.cfg.rr_period == 0) {
