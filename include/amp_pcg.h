@@ -111,6 +111,11 @@ typedef struct {
                                0 disables (default 0) */
     int spmv_timing;        /* 1: time every product-kernel launch with HIP events (eager path only:
                                disables graph and solo); results in amp_result.spmv_ms */
+    int defer_x;            /* 1 (default): the FP64 update x += alpha p is applied two iterations at a
+                               time, x_{k+1} = (x_{k-1} + alpha_{k-1} p_{k-1}) + alpha_k p_k, rounded
+                               after each step exactly as one step at a time (bitwise the same x);
+                               the pending step is applied whenever the solve stops. Ignored (0)
+                               with rr_period > 0 */
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
     double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */

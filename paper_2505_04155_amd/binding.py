@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("T_p", ctypes.c_int), ("spmv32_diff", ctypes.c_int), ("verify", ctypes.c_int),
                 ("max_replacements", ctypes.c_int), ("rr_period", ctypes.c_int),
                 ("batch", ctypes.c_int), ("group_rows", ctypes.c_int), ("graph", ctypes.c_int),
-                ("solo_rows", ctypes.c_int), ("spmv_timing", ctypes.c_int),
+                ("solo_rows", ctypes.c_int), ("spmv_timing", ctypes.c_int), ("defer_x", ctypes.c_int),
                 ("delta_history", ctypes.c_void_p),
                 ("prec_history", ctypes.c_void_p), ("scalar_history", ctypes.c_void_p)]
 

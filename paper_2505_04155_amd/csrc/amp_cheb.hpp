@@ -74,13 +74,15 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
     if (!standalone) res_loads(res_early(c, B), ri);
     load_state(s, in);
     if (s.status != RUNNING) {
+        if (!standalone) stop_flush(s, B, P.np, wg);
         store_state(s, out, wg);
         return;
     }
     if (!standalone) {
         consume_residual(s, c, B, wg, ri);
         __syncthreads();
-        if (s.status != RUNNING) {
+        if (s.status != RUNNING) {   // the solve stops here: x gets its pending step
+            stop_flush(s, B, P.np, wg);
             store_state(s, out, wg);
             return;
         }

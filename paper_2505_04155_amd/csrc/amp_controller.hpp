@@ -30,6 +30,7 @@ enum ResKind : int { RES_INIT = 0, RES_UPDATE = 1, RES_VERIFY = 2, RES_PERIODIC 
 struct Cfg {
     int u0, eta_mode, d, ell, scaling, T_z, T_p, maxit, verify, max_repl, chebyshev, diff;
     int rr_period, extra16;   // extra16: log2 of the FP16 preconditioner data's static scale
+    int defer_x;              // 1: x is updated every other iteration (two steps at once)
     int g_stream, g_slice;    // work-groups of the streaming / sliced-ELL kernels (= partial counts)
     int g_pre;                // partials written by the preconditioning stage
     double C, tau_zs, tau_zh, tol, gain;
@@ -54,7 +55,8 @@ struct St {
     int k_z32, k_z16, k_r32, n_repl;
     int e, have_e;            // pow2 scaling exponent of iteration k
     int kind;                 // ResKind of the pending residual partials
-    int pad;
+    int xp;                   // 1: x lacks alpha_{k-1} p_{k-1} (deferred to the next update)
+    int x_pu, x_pb;           // precision and buffer of that p
     double omega;             // omega_k (without the static storage scale)
     double bnorm, tol_b;
     double rho, rho_prev, beta, gamma, alpha;
@@ -63,6 +65,7 @@ struct St {
     double maxz, maxp;        // max|z^_{k-1}|, max|p^_{k-1}|
     double omega_eff;         // multiplier applied to r_k (includes the static storage scale)
     double true_res;          // last FP64 true residual norm
+    double x_alpha;           // the alpha of the deferred x update
 };
 
 // ceil(log2(v)) for finite v > 0, exact (no libm rounding).

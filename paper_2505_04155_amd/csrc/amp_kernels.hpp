@@ -100,6 +100,41 @@ __device__ __forceinline__ void record_delta(const Cfg &c, int i, double d, Wg w
 }
 
 // ----------------------------------------------------------------------------
+// deferred x update
+// ----------------------------------------------------------------------------
+
+// x += alpha p over this work-group's element range (the range every
+// streaming kernel of the system uses, so each x element is always updated
+// by the same work-group and thread).
+template <int UPP>
+__device__ __forceinline__ void flush_x_body(double alpha, const void *pv, double *x, int64_t np, Wg wg) {
+    typedef typename Prec<UPP>::T TP;
+    const TP *p = (const TP *)pv;
+    AMP_STREAM_LOOP(i, np, wg) {
+        const V4<TP> pv4 = ld4(p, i);
+        V4<double> xv = ld4(x, i);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
+        st4(x, i, xv);
+    }
+}
+
+// Apply the state's pending step alpha_{k-1} p_{k-1} to x, if any, and clear
+// it.  Every thread of the work-group calls this (it has a barrier).
+__device__ __forceinline__ void stop_flush(St &s, const Bufs &B, int64_t np, Wg wg) {
+    const int xp = s.xp, pu = s.x_pu, pb = s.x_pb;
+    const double a = s.x_alpha;
+    if (xp) {
+        const void *p = B.p[pslot(pu)][pb];
+        if (pu == 64) flush_x_body<64>(a, p, B.x, np, wg);
+        else if (pu == 32) flush_x_body<32>(a, p, B.x, np, wg);
+        else flush_x_body<16>(a, p, B.x, np, wg);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.xp = 0;
+}
+
+// ----------------------------------------------------------------------------
 // sliced-ELL row products
 // ----------------------------------------------------------------------------
 
@@ -445,6 +480,7 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
     res_loads(e, ri);
     load_state(s, in);
     if (s.status != RUNNING) {
+        stop_flush(s, B, np, wg);
         store_state(s, out, wg);
         return;
     }
@@ -466,7 +502,8 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
     }
     consume_residual(s, c, B, wg, ri);
     __syncthreads();
-    if (s.status != RUNNING) {
+    if (s.status != RUNNING) {   // the solve stops here: x gets its pending step
+        stop_flush(s, B, np, wg);
         store_state(s, out, wg);
         return;
     }
@@ -667,24 +704,51 @@ __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv_fixed(Sell A, cons
 
 // The body loads for this thread's first two chunks are issued before the
 // partials of gamma are reduced; the precisions come from the incoming state
-// (the update does not change them).
-template <int UP, int UR>
+// (the update does not change them).  XM: what happens to x (FP64).
+//   0: nothing; alpha_k p_k becomes the pending step (x is not read)
+//   1: x += alpha_k p_k
+//   2: x += alpha_{k-1} p_{k-1}, then x += alpha_k p_k (p_{k-1} in u_z as p_k)
+// Each step is rounded as on its own, so x is bitwise the same in all modes.
+template <int UP, int UR, int XM>
 __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t np, St &s, const PartRegs<2> &pr,
                                            int gpart, St *out, Wg wg) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
     const TP *p = (const TP *)B.p[pslot(UP)][s.pbuf ^ 1];
+    const TP *pq = (const TP *)B.p[pslot(UP)][s.x_pb];   // p_{k-1} (XM 2)
+    const double aq = s.x_alpha;
     TR *r = (TR *)B.r[pslot(UR)];
     const TR *q = (const TR *)B.q[pslot(UR)];
     int64_t lo, hi;
     block_range(np, (int64_t)NT * VEC, wg.lb, wg.G, lo, hi);
     constexpr int64_t step = (int64_t)NT * VEC;
     const int64_t i0 = lo + (int64_t)threadIdx.x * VEC;
+    // Chunks loaded ahead: two, or one when a chunk's operands are wide (the
+    // registers for two would lower the number of resident waves).
+    constexpr int chunk_bytes = VEC * ((XM >= 1 ? 8 + (int)sizeof(TP) : 0) + (XM == 2 ? (int)sizeof(TP) : 0) +
+                                       2 * (int)sizeof(TR));
+    constexpr int PF = chunk_bytes <= 112 ? 2 : 1;
     // chunks past this work-group's range load chunk 0 (unused): no branch
     const int64_t j0 = i0 < hi ? i0 : 0, j1 = i0 + step < hi ? i0 + step : 0;
-    const V4<TP> p0 = ld4(p, j0), p1 = ld4(p, j1);
-    const V4<double> x0 = ld4(B.x, j0), x1 = ld4(B.x, j1);
-    const V4<TR> r0 = ld4(r, j0), r1 = ld4(r, j1), q0 = ld4(q, j0), q1 = ld4(q, j1);
+    V4<TP> p0, p1, pq0, pq1;
+    V4<double> x0, x1;
+    V4<TR> r0, r1, q0, q1;
+    if (XM >= 1) {
+        p0 = ld4(p, j0);
+        x0 = ld4(B.x, j0);
+    }
+    if (XM == 2) pq0 = ld4(pq, j0);
+    r0 = ld4(r, j0);
+    q0 = ld4(q, j0);
+    if (PF == 2) {
+        if (XM >= 1) {
+            p1 = ld4(p, j1);
+            x1 = ld4(B.x, j1);
+        }
+        if (XM == 2) pq1 = ld4(pq, j1);
+        r1 = ld4(r, j1);
+        q1 = ld4(q, j1);
+    }
     double tot[2];
     reduce_loaded<1, 1>(pr, gpart, tot);
     const double gam = tot[0], mp = tot[1];
@@ -699,34 +763,53 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
         }
     }
     __syncthreads();
-    if (s.status != RUNNING) {
+    if (s.status != RUNNING) {   // breakdown: x_k is the result; it gets its pending step
+        stop_flush(s, B, np, wg);
         store_state(s, out, wg);
         return;
     }
     const double alpha = s.alpha;
     const TR a = (TR)alpha;
     double dd = 0.0, mr = 0.0;
-    auto chunk = [&](int64_t i, const V4<TP> &pv4, V4<double> xv, V4<TR> rv, const V4<TR> &qv) {
+    auto chunk = [&](int64_t i, const V4<TP> &pv4, const V4<TP> &pqv, V4<double> xv, V4<TR> rv, const V4<TR> &qv) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
+            if (XM == 2) xv.v[e] = xv.v[e] + aq * (double)pqv.v[e];
+            if (XM >= 1) xv.v[e] = xv.v[e] + alpha * (double)pv4.v[e];
             const TR rn = (TR)(rv.v[e] - a * qv.v[e]);
             rv.v[e] = rn;
             dd += (double)rn * (double)rn;
             mr = fmax(mr, fabs((double)rn));
         }
-        st4(B.x, i, xv);
+        if (XM >= 1) st4(B.x, i, xv);
         st4(r, i, rv);
     };
-    if (i0 < hi) chunk(i0, p0, x0, r0, q0);
-    if (i0 + step < hi) chunk(i0 + step, p1, x1, r1, q1);
-    for (int64_t i = i0 + 2 * step; i < hi; i += step) chunk(i, ld4(p, i), ld4(B.x, i), ld4(r, i), ld4(q, i));
+    if (i0 < hi) chunk(i0, p0, pq0, x0, r0, q0);
+    if (PF == 2 && i0 + step < hi) chunk(i0 + step, p1, pq1, x1, r1, q1);
+    for (int64_t i = i0 + PF * step; i < hi; i += step) {
+        V4<TP> pv4, pqv;
+        V4<double> xv;
+        if (XM >= 1) {
+            pv4 = ld4(p, i);
+            xv = ld4(B.x, i);
+        }
+        if (XM == 2) pqv = ld4(pq, i);
+        chunk(i, pv4, pqv, xv, ld4(r, i), ld4(q, i));
+    }
     dd = block_sum(dd);
     mr = block_max(mr);
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = dd;
         B.part_res[GMAX + wg.lb] = 0.0;
         B.part_res[2 * GMAX + wg.lb] = mr;
+        if (XM == 0) {
+            s.xp = 1;
+            s.x_pu = UP;
+            s.x_pb = s.pbuf ^ 1;
+            s.x_alpha = alpha;
+        } else {
+            s.xp = 0;
+        }
         s.pbuf ^= 1;
         s.p_store = UP;
         s.iters = s.k + 1;
@@ -741,20 +824,35 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
     PartRegs<2> pr;
     load_parts<2>(e.part, e.g, pr);   // in flight during the state load
     load_state(s, in);
-    if (s.status != RUNNING) {
+    if (s.status != RUNNING) {   // stopped in the product kernel (breakdown)
+        stop_flush(s, B, np, wg);
         store_state(s, out, wg);
         return;
     }
     const int uz = s.uz, ur = s.ur;
-    if (ur == 64) {
-        if (uz == 64) update_run<64, 64>(c, B, np, s, pr, e.g, out, wg);
-        else if (uz == 32) update_run<32, 64>(c, B, np, s, pr, e.g, out, wg);
-        else update_run<16, 64>(c, B, np, s, pr, e.g, out, wg);
+    int xm;
+    if (s.xp && s.x_pu != uz) {   // pending step in another precision (a u_z switch): apply it first
+        stop_flush(s, B, np, wg);
+        xm = 1;
     } else {
-        if (uz == 64) update_run<64, 32>(c, B, np, s, pr, e.g, out, wg);
-        else if (uz == 32) update_run<32, 32>(c, B, np, s, pr, e.g, out, wg);
-        else update_run<16, 32>(c, B, np, s, pr, e.g, out, wg);
+        xm = s.xp ? 2 : (c.defer_x ? 0 : 1);
     }
+#define AMP_UPD(UP, UR)                                                            \
+    do {                                                                           \
+        if (xm == 0) update_run<UP, UR, 0>(c, B, np, s, pr, e.g, out, wg);         \
+        else if (xm == 1) update_run<UP, UR, 1>(c, B, np, s, pr, e.g, out, wg);    \
+        else update_run<UP, UR, 2>(c, B, np, s, pr, e.g, out, wg);                 \
+    } while (0)
+    if (ur == 64) {
+        if (uz == 64) AMP_UPD(64, 64);
+        else if (uz == 32) AMP_UPD(32, 64);
+        else AMP_UPD(16, 64);
+    } else {
+        if (uz == 64) AMP_UPD(64, 32);
+        else if (uz == 32) AMP_UPD(32, 32);
+        else AMP_UPD(16, 32);
+    }
+#undef AMP_UPD
 }
 
 __global__ void __launch_bounds__(NT) k_update(const St *in, const double *part, int gpart, int grid, Cfg c,
@@ -857,8 +955,10 @@ __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bu
         __syncthreads();
         in = last = ST_RES;
     }
+    __shared__ St f;
+    load_state(f, st + last);
+    stop_flush(f, B, A.np, wg);   // the cap ends a running solve: x gets its pending step
     if (threadIdx.x == 0) {
-        St f = st[last];
         if (f.status == RUNNING || f.status == NEED_VERIFY) f.status = MAXIT;
         st[ST_FIN] = f;
     }

@@ -685,6 +685,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->graph = 0;
     o->solo_rows = 0;
     o->spmv_timing = 0;
+    o->defer_x = 1;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;
@@ -736,6 +737,7 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.chebyshev = (M && M->kind == AMP_PC_CHEBYSHEV) ? 1 : 0;
     c.diff = o.spmv32_diff ? 1 : 0;
     c.rr_period = o.rr_period;
+    c.defer_x = (o.defer_x && o.rr_period == 0) ? 1 : 0;   // a periodic replacement reads x
     c.extra16 = M ? M->extra16 : 0;
     c.g_stream = A ? grid_stream(A->np) : 1;
     c.g_slice = A ? grid_slices(A->nslices) : 1;
