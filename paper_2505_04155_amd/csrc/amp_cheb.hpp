@@ -197,8 +197,10 @@ __global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int fi
     else AMP_CS(16);
 #undef AMP_CS
     if (last) {
-        rho = block_sum<NTS>(rho);
-        mz = block_max<NTS>(mz);
+        double v2[2] = {rho, mz};
+        block_reduce<1, 1, NTS>(v2);
+        rho = v2[0];
+        mz = v2[1];
         if (threadIdx.x == 0) {
             B.part_pre[wg.lb] = rho;
             B.part_pre[GMAX + wg.lb] = mz;
@@ -243,8 +245,10 @@ __global__ void __launch_bounds__(NT) k_cheb_deg1(Bufs B, Cheb P, const St *in, 
     if (s.uz == 64) cheb_deg1_body<64>(s, B, P, wg, rho, mz);
     else if (s.uz == 32) cheb_deg1_body<32>(s, B, P, wg, rho, mz);
     else cheb_deg1_body<16>(s, B, P, wg, rho, mz);
-    rho = block_sum(rho);
-    mz = block_max(mz);
+    double v2[2] = {rho, mz};
+    block_reduce<1, 1>(v2);
+    rho = v2[0];
+    mz = v2[1];
     if (threadIdx.x == 0) {
         B.part_pre[wg.lb] = rho;
         B.part_pre[GMAX + wg.lb] = mz;

@@ -181,6 +181,22 @@ __device__ __forceinline__ int xcd_index(int b, int G) {
 }
 __device__ __forceinline__ int xcd_block() { return xcd_index(blockIdx.x, gridDim.x); }
 
+// Read one dword of every 64-byte line of the first `bytes` bytes of the
+// kernel's argument segment (the explicit arguments).  Issued at entry,
+// these scalar loads bring the lines into the scalar cache while the first
+// global loads are in flight; without them a field first used inside a
+// later branch (the controller's configuration) costs a miss there.  The
+// caller passes the result to pin() after its first barrier.
+template <int BYTES>
+__device__ __forceinline__ uint32_t touch_args() {
+    const uint32_t *ka = (const uint32_t *)__builtin_amdgcn_kernarg_segment_ptr();
+    uint32_t acc = 0;
+#pragma unroll
+    for (int o = 0; o + 4 <= BYTES; o += 64) acc ^= ka[o / 4];
+    return acc;
+}
+__device__ __forceinline__ void pin(uint32_t v) { asm volatile("" ::"s"(v)); }
+
 // A work-group's share of one system's work: logical index lb of G groups.
 // A single-system launch uses the whole grid (grid_wg); a batched launch
 // reads (system, lb) from its task table and G from the system's config.
@@ -245,6 +261,30 @@ __device__ __forceinline__ double block_max(double v) {
 #pragma unroll
     for (int i = 0; i < BS / WAVE; ++i) t = fmax(t, sh[i]);
     return t;
+}
+
+// NS sums followed by NM maxima over the work-group in one exchange; each
+// result equals that of block_sum / block_max on its value (same order).
+template <int NS, int NM, int BS = NT>
+__device__ __forceinline__ void block_reduce(double *v) {
+    constexpr int K = NS + NM, NW = BS / WAVE;
+    __shared__ double sh[K][NW];
+#pragma unroll
+    for (int t = 0; t < K; ++t) v[t] = (t < NS) ? wave_sum(v[t]) : wave_max(v[t]);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) sh[t][w] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) r = (t < NS) ? r + sh[t][i] : fmax(r, sh[t][i]);
+        v[t] = r;
+    }
 }
 
 // Totals of a producer kernel's per-work-group partials (G of each), summed

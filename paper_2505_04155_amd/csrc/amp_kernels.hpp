@@ -79,6 +79,7 @@ struct Early {
     const double *part;
     int g;
     const double *ring;
+    uint32_t touched;   // touch_args() of the kernel (0 where there is none)
 };
 
 // Load the incoming state into LDS (all threads see it after the barrier).
@@ -286,9 +287,11 @@ __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) 
         sb += B.b[row] * B.b[row];
         mr = fmax(mr, fabs(t));
     }
-    sr = block_sum<BS>(sr);
-    sb = block_sum<BS>(sb);
-    mr = block_max<BS>(mr);
+    double v3[3] = {sr, sb, mr};
+    block_reduce<2, 1, BS>(v3);
+    sr = v3[0];
+    sb = v3[1];
+    mr = v3[2];
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = sr;
         B.part_res[GMAX + wg.lb] = sb;
@@ -314,11 +317,13 @@ static_assert(kRing <= NT, "one ring entry per thread");
 
 // The Early arguments of each stage, from the solve's configuration.
 __device__ __forceinline__ Early res_early(const Cfg &c, const Bufs &B) {
-    return Early{B.part_res, c.g_stream > c.g_slice ? c.g_stream : c.g_slice, c.ring};
+    return Early{B.part_res, c.g_stream > c.g_slice ? c.g_stream : c.g_slice, c.ring, 0u};
 }
-__device__ __forceinline__ Early pre_early(const Cfg &c, const Bufs &B) { return Early{B.part_pre, c.g_pre, nullptr}; }
+__device__ __forceinline__ Early pre_early(const Cfg &c, const Bufs &B) {
+    return Early{B.part_pre, c.g_pre, nullptr, 0u};
+}
 __device__ __forceinline__ Early spmv_early(const Cfg &c, const Bufs &B) {
-    return Early{B.part_spmv, c.g_slice, nullptr};
+    return Early{B.part_spmv, c.g_slice, nullptr, 0u};
 }
 
 __device__ __forceinline__ void res_loads(const Early &e, ResIn &ri) {
@@ -337,45 +342,52 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
     reduce_loaded<2, 1>(ri.pr, G, tot);   // its barrier also publishes ring[]
     const double a = tot[0], b = tot[1], m = tot[2];
     if (threadIdx.x == 0) {
-        rec = -1;
-        if (s.kind == RES_INIT) {
-            s.bnorm = sqrt(b);
-            s.tol_b = c.tol * s.bnorm;
-            s.delta = sqrt(a);
-            s.true_res = s.delta;   // r0 = b - A x0 is formed in FP64: it is the true residual
-            s.maxr = m;
-            s.maxr_prev = m;
-            rec = 0;
-            recv = s.delta;
-            if (s.delta <= s.tol_b) s.status = CONVERGED;
-            else if (c.maxit <= 0) s.status = MAXIT;
-            else prepare_iteration(s, c, ring, 0);
-        } else if (s.kind == RES_UPDATE || s.kind == RES_PERIODIC) {
-            const double d = sqrt(s.kind == RES_UPDATE ? a : b);
-            if (s.kind == RES_PERIODIC) s.n_repl += 1;
-            rec = s.iters;
-            recv = d;
-            finish_iteration(s, c, ring, d, m);
+        // the controller runs on a register copy of the state (the LDS copy
+        // would put a round trip on every field it reads and updates)
+        St cs = s;
+        int rk = -1;
+        double rv = 0.0;
+        if (cs.kind == RES_INIT) {
+            cs.bnorm = sqrt(b);
+            cs.tol_b = c.tol * cs.bnorm;
+            cs.delta = sqrt(a);
+            cs.true_res = cs.delta;   // r0 = b - A x0 is formed in FP64: it is the true residual
+            cs.maxr = m;
+            cs.maxr_prev = m;
+            rk = 0;
+            rv = cs.delta;
+            if (cs.delta <= cs.tol_b) cs.status = CONVERGED;
+            else if (c.maxit <= 0) cs.status = MAXIT;
+            else prepare_iteration(cs, c, ring, 0);
+        } else if (cs.kind == RES_UPDATE || cs.kind == RES_PERIODIC) {
+            const double d = sqrt(cs.kind == RES_UPDATE ? a : b);
+            if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
+            rk = cs.iters;
+            rv = d;
+            finish_iteration(cs, c, ring, d, m);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
-            s.true_res = sqrt(a);
-            if (s.true_res <= s.tol_b) {
-                s.status = CONVERGED;
-            } else if (s.n_repl >= c.max_repl) {
-                s.status = MAXIT;
+            cs.true_res = sqrt(a);
+            if (cs.true_res <= cs.tol_b) {
+                cs.status = CONVERGED;
+            } else if (cs.n_repl >= c.max_repl) {
+                cs.status = MAXIT;
             } else {
-                s.n_repl += 1;
-                s.delta = sqrt(b);
-                s.maxr = m;
-                rec = s.iters;
-                recv = s.delta;
-                if (s.iters >= c.maxit) {
-                    s.status = MAXIT;
+                cs.n_repl += 1;
+                cs.delta = sqrt(b);
+                cs.maxr = m;
+                rk = cs.iters;
+                rv = cs.delta;
+                if (cs.iters >= c.maxit) {
+                    cs.status = MAXIT;
                 } else {
-                    s.status = RUNNING;
-                    prepare_iteration(s, c, ring, s.iters);
+                    cs.status = RUNNING;
+                    prepare_iteration(cs, c, ring, cs.iters);
                 }
             }
         }
+        s = cs;
+        rec = rk;
+        recv = rv;
     }
     __syncthreads();
     if (threadIdx.x == 0 && rec >= 0) {
@@ -479,6 +491,7 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
     ResIn ri;
     res_loads(e, ri);
     load_state(s, in);
+    pin(e.touched);
     if (s.status != RUNNING) {
         stop_flush(s, B, np, wg);
         store_state(s, out, wg);
@@ -525,8 +538,10 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
         else if (s.p_store == 64) convert_p<64, 16>(B, s.pbuf, np, wg);
         else convert_p<32, 16>(B, s.pbuf, np, wg);
     }
-    rho = block_sum(rho);
-    mz = block_max(mz);
+    double v2[2] = {rho, mz};
+    block_reduce<1, 1>(v2);
+    rho = v2[0];
+    mz = v2[1];
     if (threadIdx.x == 0) {
         B.part_pre[wg.lb] = rho;
         B.part_pre[GMAX + wg.lb] = mz;
@@ -538,7 +553,8 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
 
 __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part, int gpart, int grid,
                                                 const double *ring, Cfg c, Bufs B, int64_t np, St *out) {
-    precond_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, ring});
+    precond_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, ring,
+                  touch_args<32 + sizeof(Cfg) + sizeof(Bufs)>()});
 }
 
 // ----------------------------------------------------------------------------
@@ -624,6 +640,7 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     PartRegs<2, BS> pr;
     load_parts<2, BS>(e.part, e.g, pr);   // in flight during the state load
     load_state(s, in);
+    pin(e.touched);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
@@ -671,8 +688,10 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         else AMP_SP(16, 32, false);
     }
 #undef AMP_SP
-    gam = block_sum<BS>(gam);
-    mp = block_max<BS>(mp);
+    double v2[2] = {gam, mp};
+    block_reduce<1, 1, BS>(v2);
+    gam = v2[0];
+    mp = v2[1];
     if (threadIdx.x == 0) {
         B.part_spmv[wg.lb] = gam;
         B.part_spmv[GMAX + wg.lb] = mp;
@@ -682,7 +701,8 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
 
 __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv(const St *in, const double *part, int gpart, int grid,
                                                                 Cfg c, Sell A, Bufs B, St *out) {
-    spmv_stage<NTS>(c, A, B, in, out, launch_wg(grid), Early{part, gpart, nullptr});
+    spmv_stage<NTS>(c, A, B, in, out, launch_wg(grid),
+                    Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
 }
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
@@ -796,8 +816,10 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
         if (XM == 2) pqv = ld4(pq, i);
         chunk(i, pv4, pqv, xv, ld4(r, i), ld4(q, i));
     }
-    dd = block_sum(dd);
-    mr = block_max(mr);
+    double v2[2] = {dd, mr};
+    block_reduce<1, 1>(v2);
+    dd = v2[0];
+    mr = v2[1];
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = dd;
         B.part_res[GMAX + wg.lb] = 0.0;
@@ -824,6 +846,7 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
     PartRegs<2> pr;
     load_parts<2>(e.part, e.g, pr);   // in flight during the state load
     load_state(s, in);
+    pin(e.touched);
     if (s.status != RUNNING) {   // stopped in the product kernel (breakdown)
         stop_flush(s, B, np, wg);
         store_state(s, out, wg);
@@ -857,7 +880,8 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
 
 __global__ void __launch_bounds__(NT) k_update(const St *in, const double *part, int gpart, int grid, Cfg c,
                                                Bufs B, int64_t np, St *out) {
-    update_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, nullptr});
+    update_stage(c, B, np, in, out, launch_wg(grid),
+                 Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Bufs)>()});
 }
 
 // ----------------------------------------------------------------------------
@@ -899,9 +923,11 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
     double st = 0.0, ss = 0.0, mr = 0.0;
     if (s.r_store == 64) true_res_body<64, BS>(A, B, wg, mode != 2, st, ss, mr);
     else true_res_body<32, BS>(A, B, wg, mode != 2, st, ss, mr);
-    st = block_sum<BS>(st);
-    ss = block_sum<BS>(ss);
-    mr = block_max<BS>(mr);
+    double v3[3] = {st, ss, mr};
+    block_reduce<2, 1, BS>(v3);
+    st = v3[0];
+    ss = v3[1];
+    mr = v3[2];
     if (threadIdx.x == 0) {
         B.part_res[wg.lb] = st;
         B.part_res[GMAX + wg.lb] = ss;
