@@ -126,9 +126,12 @@ AMP_HD inline void select_precision(double nu, int u0, double tau_zs, double tau
 
 // Decide (u_z, u_r, omega) of iteration k from delta_k = s.delta, max|r_k| =
 // s.maxr and the previous iteration's maxima.  Latched: precisions never rise.
-AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, int k) {
+// eta_pre: the delay indicator of (k, delta_k) when the caller has already
+// formed it (the device does, in parallel), else null.
+AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, int k,
+                                     const double *eta_pre = nullptr) {
     s.k = k;
-    double eta = eta_value(c, ring, k, s.delta);
+    double eta = (eta_pre && c.eta_mode == ETA_DELAY) ? *eta_pre : eta_value(c, ring, k, s.delta);
     int suz, sur;
     select_precision(s.delta / s.bnorm, c.u0, c.tau_zs, c.tau_zh, eta, s.tol_b, &suz, &sur);
     s.uz = lower_prec(s.uz, suz);
@@ -167,7 +170,7 @@ AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, in
 // Consume the residual of the iteration just finished (iteration iters-1):
 // test for convergence and prepare the next iteration.
 AMP_HD inline void finish_iteration(St &s, const Cfg &c, const double *ring, double delta_new,
-                                    double maxr_new) {
+                                    double maxr_new, const double *eta_pre = nullptr) {
     s.maxr_prev = s.maxr;
     s.maxr = maxr_new;
     s.delta = delta_new;
@@ -183,7 +186,7 @@ AMP_HD inline void finish_iteration(St &s, const Cfg &c, const double *ring, dou
         s.status = MAXIT;
         return;
     }
-    prepare_iteration(s, c, ring, s.iters);
+    prepare_iteration(s, c, ring, s.iters, eta_pre);
 }
 
 }  // namespace amp

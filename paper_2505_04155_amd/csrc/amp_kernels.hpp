@@ -341,7 +341,26 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
     double tot[3];
     reduce_loaded<2, 1>(ri.pr, G, tot);   // its barrier also publishes ring[]
     const double a = tot[0], b = tot[1], m = tot[2];
+    // eq. (eta_k), delay form, for the iteration the controller prepares next
+    // (k = iters, delta_k from these totals): lane j of wave 0 forms term j
+    // of the window as the serial evaluation would, lane 0 adds the terms in
+    // window order (the same sum, without a serial chain of LDS reads)
+    const int kk = (s.kind == RES_INIT) ? 0 : s.iters;
+    const bool par = c.eta_mode == ETA_DELAY && c.d < WAVE && kk - c.d - 1 >= 0;
+    double term = 0.0;
+    if (par && threadIdx.x <= c.d) {
+        const double dk = sqrt(s.kind == RES_UPDATE ? a : b);
+        const int t = kk - c.d + threadIdx.x;
+        const double dt = (t == kk) ? dk : ring[t % kRing];
+        term = (3.0 + c.C) * ring[(t - 1) % kRing] + (2.0 + c.C) * dt;
+    }
     if (threadIdx.x == 0) {
+        double eta_pre = INFINITY;   // eta_delay's value before the window is complete
+        if (par) {
+            double sum = 0.0;
+            for (int j = 0; j <= c.d; ++j) sum = sum + readlane_f64(term, j);
+            eta_pre = kEps32 * sum;
+        }
         // the controller runs on a register copy of the state (the LDS copy
         // would put a round trip on every field it reads and updates)
         St cs = s;
@@ -358,13 +377,13 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             rv = cs.delta;
             if (cs.delta <= cs.tol_b) cs.status = CONVERGED;
             else if (c.maxit <= 0) cs.status = MAXIT;
-            else prepare_iteration(cs, c, ring, 0);
+            else prepare_iteration(cs, c, ring, 0, &eta_pre);
         } else if (cs.kind == RES_UPDATE || cs.kind == RES_PERIODIC) {
             const double d = sqrt(cs.kind == RES_UPDATE ? a : b);
             if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
             rk = cs.iters;
             rv = d;
-            finish_iteration(cs, c, ring, d, m);
+            finish_iteration(cs, c, ring, d, m, &eta_pre);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
             cs.true_res = sqrt(a);
             if (cs.true_res <= cs.tol_b) {
@@ -381,7 +400,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
                     cs.status = MAXIT;
                 } else {
                     cs.status = RUNNING;
-                    prepare_iteration(cs, c, ring, cs.iters);
+                    prepare_iteration(cs, c, ring, cs.iters, &eta_pre);
                 }
             }
         }
@@ -645,34 +664,39 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         store_state(s, out, wg);
         return;
     }
+    // Every thread forms beta from the totals (no broadcast step); the state
+    // fields it needs are read before the reduction's barriers, after which
+    // only thread 0 writes the state.
+    const double rho_prev = s.rho;
+    const int k = s.k, uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
     double tot[2];
     reduce_loaded<1, 1, BS>(pr, e.g, tot);
     const double rho = tot[0], mz = tot[1];
+    const double beta = (k > 0) ? rho / rho_prev : 0.0;
+    const bool brk = !(rho > 0.0) || !isfinite(beta);
     if (threadIdx.x == 0) {
-        s.rho_prev = s.rho;
+        s.rho_prev = rho_prev;
         s.rho = rho;
-        s.beta = (s.k > 0) ? rho / s.rho_prev : 0.0;
+        s.beta = beta;
         s.maxz = mz;
-        if (!(rho > 0.0) || !isfinite(s.beta)) s.status = BREAKDOWN;
-        if (wg.lb == 0 && c.scalar_history) c.scalar_history[4 * s.k + 1] = rho;
+        if (brk) s.status = BREAKDOWN;
+        if (wg.lb == 0 && c.scalar_history) c.scalar_history[4 * k + 1] = rho;
     }
-    __syncthreads();
-    if (s.status != RUNNING) {
+    if (brk) {
         store_state(s, out, wg);
         return;
     }
-    if (c.spmv_iter && wg.lb == 0 && threadIdx.x == 0) c.spmv_iter[c.spmv_launch] = s.k;
-    const int uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
-    const bool first = (s.k == 0);
+    if (c.spmv_iter && wg.lb == 0 && threadIdx.x == 0) c.spmv_iter[c.spmv_launch] = k;
+    const bool first = (k == 0);
     double gam = 0.0, mp = 0.0;
 #define AMP_SP(UZ, UR, DF)                                                                                       \
     do {                                                                                                        \
         if (first)                                                                                              \
-            spmv_p_body<UZ, UR, DF, true, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], s.beta, \
+            spmv_p_body<UZ, UR, DF, true, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, \
                                           gam, mp);                                                             \
         else                                                                                                    \
             spmv_p_body<UZ, UR, DF, false, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],       \
-                                           s.beta, gam, mp);                                                    \
+                                           beta, gam, mp);                                                      \
     } while (0)
     if (ur == 64) {
         if (uz == 64) AMP_SP(64, 64, false);
@@ -734,7 +758,9 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
                                            int gpart, St *out, Wg wg) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T TR;
-    const TP *p = (const TP *)B.p[pslot(UP)][s.pbuf ^ 1];
+    const int pbuf = s.pbuf, k = s.k;
+    const double rho = s.rho;
+    const TP *p = (const TP *)B.p[pslot(UP)][pbuf ^ 1];
     const TP *pq = (const TP *)B.p[pslot(UP)][s.x_pb];   // p_{k-1} (XM 2)
     const double aq = s.x_alpha;
     TR *r = (TR *)B.r[pslot(UR)];
@@ -769,26 +795,29 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
         r1 = ld4(r, j1);
         q1 = ld4(q, j1);
     }
+    // every thread forms alpha from the totals (the state fields it needs
+    // were read above, before the reduction's barriers)
     double tot[2];
     reduce_loaded<1, 1>(pr, gpart, tot);
     const double gam = tot[0], mp = tot[1];
+    const double alpha = rho / gam;
+    const bool brk = !(gam > 0.0) || !isfinite(alpha);
     if (threadIdx.x == 0) {
         s.gamma = gam;
-        s.alpha = s.rho / gam;
+        s.alpha = alpha;
         s.maxp = mp;
-        if (!(gam > 0.0) || !isfinite(s.alpha)) s.status = BREAKDOWN;
+        if (brk) s.status = BREAKDOWN;
         if (wg.lb == 0 && c.scalar_history) {
-            c.scalar_history[4 * s.k + 2] = gam;
-            c.scalar_history[4 * s.k + 3] = s.alpha;
+            c.scalar_history[4 * k + 2] = gam;
+            c.scalar_history[4 * k + 3] = alpha;
         }
     }
-    __syncthreads();
-    if (s.status != RUNNING) {   // breakdown: x_k is the result; it gets its pending step
+    if (brk) {   // breakdown: x_k is the result; it gets its pending step
+        __syncthreads();
         stop_flush(s, B, np, wg);
         store_state(s, out, wg);
         return;
     }
-    const double alpha = s.alpha;
     const TR a = (TR)alpha;
     double dd = 0.0, mr = 0.0;
     auto chunk = [&](int64_t i, const V4<TP> &pv4, const V4<TP> &pqv, V4<double> xv, V4<TR> rv, const V4<TR> &qv) {
@@ -827,14 +856,14 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
         if (XM == 0) {
             s.xp = 1;
             s.x_pu = UP;
-            s.x_pb = s.pbuf ^ 1;
+            s.x_pb = pbuf ^ 1;
             s.x_alpha = alpha;
         } else {
             s.xp = 0;
         }
-        s.pbuf ^= 1;
+        s.pbuf = pbuf ^ 1;
         s.p_store = UP;
-        s.iters = s.k + 1;
+        s.iters = k + 1;
         s.kind = RES_UPDATE;
     }
     store_state(s, out, wg);
