@@ -230,16 +230,42 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
+// A double moved across lanes by a DPP pattern; lanes of rows outside
+// ROW_MASK receive `ident`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v, double ident) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, ident);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, CTRL, ROW_MASK,
+                                                              0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
+                                                              CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Wave-wide sum / maximum (all 64 lanes active), in a fixed tree of DPP
+// steps: pairs, quads, half-rows, rows of 16, then rows 0+1 into row 1,
+// rows 2+3 into row 3, and row 1 into rows 2-3; lane 63 holds the total,
+// which every lane receives.  Every lane's result is the same value.
+static_assert(WAVE == 64, "wave64 reduction");
+__device__ __forceinline__ double wave_sum(double v) {
+    v = v + dpp_f64<0xB1, 0xF>(v, 0.0);    // quad_perm [1,0,3,2]
+    v = v + dpp_f64<0x4E, 0xF>(v, 0.0);    // quad_perm [2,3,0,1]
+    v = v + dpp_f64<0x141, 0xF>(v, 0.0);   // row_half_mirror
+    v = v + dpp_f64<0x140, 0xF>(v, 0.0);   // row_mirror
+    v = v + dpp_f64<0x142, 0xA>(v, 0.0);   // row_bcast:15 into rows 1, 3
+    v = v + dpp_f64<0x143, 0xC>(v, 0.0);   // row_bcast:31 into rows 2, 3
+    return readlane_f64(v, WAVE - 1);
+}
+
+// (maxima of absolute values: 0 is the identity)
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
+    v = fmax(v, dpp_f64<0xB1, 0xF>(v, 0.0));
+    v = fmax(v, dpp_f64<0x4E, 0xF>(v, 0.0));
+    v = fmax(v, dpp_f64<0x141, 0xF>(v, 0.0));
+    v = fmax(v, dpp_f64<0x140, 0xF>(v, 0.0));
+    v = fmax(v, dpp_f64<0x142, 0xA>(v, 0.0));
+    v = fmax(v, dpp_f64<0x143, 0xC>(v, 0.0));
+    return readlane_f64(v, WAVE - 1);
 }
 
 // Sum / max over the work-group (BS threads) in a fixed order; result in every thread.
