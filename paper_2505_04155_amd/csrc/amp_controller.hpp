@@ -14,6 +14,9 @@
 #else
 #define AMP_HD
 #endif
+// branch hints: the common path of an iteration is laid out contiguously
+#define AMP_LIKELY(x) __builtin_expect(!!(x), 1)
+#define AMP_UNLIKELY(x) __builtin_expect(!!(x), 0)
 
 namespace amp {
 
@@ -131,7 +134,7 @@ AMP_HD inline void select_precision(double nu, int u0, double tau_zs, double tau
 AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, int k,
                                      const double *eta_pre = nullptr) {
     s.k = k;
-    double eta = (eta_pre && c.eta_mode == ETA_DELAY) ? *eta_pre : eta_value(c, ring, k, s.delta);
+    double eta = AMP_LIKELY(eta_pre && c.eta_mode == ETA_DELAY) ? *eta_pre : eta_value(c, ring, k, s.delta);
     int suz, sur;
     select_precision(s.delta / s.bnorm, c.u0, c.tau_zs, c.tau_zh, eta, s.tol_b, &suz, &sur);
     s.uz = lower_prec(s.uz, suz);
@@ -141,9 +144,9 @@ AMP_HD inline void prepare_iteration(St &s, const Cfg &c, const double *ring, in
     if (s.ur <= 32 && s.k_r32 < 0) s.k_r32 = k;
 
     double omega;
-    if (c.scaling == SCALE_PAPER) {
+    if (AMP_UNLIKELY(c.scaling == SCALE_PAPER)) {
         omega = 1.0 / s.delta;
-    } else if (c.scaling == SCALE_NONE) {
+    } else if (AMP_UNLIKELY(c.scaling == SCALE_NONE)) {
         omega = 1.0;
     } else {
         int e;
@@ -174,15 +177,15 @@ AMP_HD inline void finish_iteration(St &s, const Cfg &c, const double *ring, dou
     s.maxr_prev = s.maxr;
     s.maxr = maxr_new;
     s.delta = delta_new;
-    if (delta_new <= s.tol_b) {
+    if (AMP_UNLIKELY(delta_new <= s.tol_b)) {
         s.status = c.verify ? NEED_VERIFY : CONVERGED;
         return;
     }
-    if (!isfinite(delta_new)) {
+    if (AMP_UNLIKELY(!isfinite(delta_new))) {
         s.status = BREAKDOWN;
         return;
     }
-    if (s.iters >= c.maxit) {
+    if (AMP_UNLIKELY(s.iters >= c.maxit)) {
         s.status = MAXIT;
         return;
     }

@@ -366,7 +366,13 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
         St cs = s;
         int rk = -1;
         double rv = 0.0;
-        if (cs.kind == RES_INIT) {
+        if (AMP_LIKELY(cs.kind == RES_UPDATE || cs.kind == RES_PERIODIC)) {
+            const double d = sqrt(cs.kind == RES_UPDATE ? a : b);
+            if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
+            rk = cs.iters;
+            rv = d;
+            finish_iteration(cs, c, ring, d, m, &eta_pre);
+        } else if (cs.kind == RES_INIT) {
             cs.bnorm = sqrt(b);
             cs.tol_b = c.tol * cs.bnorm;
             cs.delta = sqrt(a);
@@ -378,12 +384,6 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             if (cs.delta <= cs.tol_b) cs.status = CONVERGED;
             else if (c.maxit <= 0) cs.status = MAXIT;
             else prepare_iteration(cs, c, ring, 0, &eta_pre);
-        } else if (cs.kind == RES_UPDATE || cs.kind == RES_PERIODIC) {
-            const double d = sqrt(cs.kind == RES_UPDATE ? a : b);
-            if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
-            rk = cs.iters;
-            rv = d;
-            finish_iteration(cs, c, ring, d, m, &eta_pre);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
             cs.true_res = sqrt(a);
             if (cs.true_res <= cs.tol_b) {
