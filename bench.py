@@ -162,6 +162,7 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import paper_2505_04155_amd as amp
@@ -208,17 +209,17 @@ def main():
         t0 = time.perf_counter()
         infos = []
         for s in range(args.steps):
-            _, info = run(preset)
+            x, info = run(preset)
             infos.append(info)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ms = (t1 - t0) * 1e3 / args.steps
-        results[preset] = (ms, infos[-1])
+        results[preset] = (ms, infos[-1], x)
         log(f"bench: {preset}: {ms:.3f} ms/solve, {infos[-1]['iters']} iterations, "
             f"switches z32={infos[-1]['k_z32']} z16={infos[-1]['k_z16']} r32={infos[-1]['k_r32']}")
 
-    amp_ms, amp_info = results[args.preset]
-    fp64_ms, fp64_info = results["pcg64"]
+    amp_ms, amp_info, _ = results[args.preset]
+    fp64_ms, fp64_info, _ = results["pcg64"]
 
     # Dominant kernel: the product step, timed inside an AMP-PCG solve.
     rf = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit)
@@ -241,6 +242,11 @@ def main():
                "sample": f"one full FP64 PCG solve (Alg. 1, Jacobi) of the same system: "
                          f"{io['iters']} iterations"}
         log(f"bench: CPU oracle {cpu['value']:.1f} ms, {io['iters']} iterations")
+        # every timed solve's final iterate against the oracle's (both stop at tol 1e-10)
+        xon = float(np.linalg.norm(xo))
+        cpu["oracle_iters"] = io["iters"]
+        cpu["rel_err_vs_oracle"] = {p: float(np.linalg.norm(r[2].cpu().numpy() - xo) / xon) for p, r in results.items()}
+        log(f"bench: relative error against the oracle's solution: {cpu['rel_err_vs_oracle']}")
 
     out = {
         "metric": METRIC,
