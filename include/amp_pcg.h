@@ -236,6 +236,33 @@ amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const amp_precon
                                  amp_result *res, void *stream);
 
 /*
+ * Rows-per-work-group autotuner.  Every kernel gives each work-group a
+ * contiguous share of a system's rows (slices of 64 rows, one row per lane),
+ * and opt->group_rows fixes that share: fewer rows per work-group put more
+ * work-groups in flight, more rows amortise each work-group's fixed costs
+ * (state load, reductions, controller).  For each of the ncand candidate
+ * values (0: the automatic choice; else a positive multiple of 256) this
+ * runs the solve itself -- amp_pcg_solve when nsys = 1, amp_pcg_solve_batched
+ * otherwise -- from x = 0: once with at most `iters` iterations (warm-up),
+ * then three times each with none and with `iters`, timed with the host
+ * clock; the difference of the least times, per iteration performed, is the
+ * candidate's time (the per-call set-up and final check cancel).  *best receives the
+ * candidate with the least time per iteration; ms_per_iter (host array of
+ * ncand, nullable) the measured times.  A, M, b,
+ * tol as for amp_pcg_solve_batched (host arrays of nsys); x: host array of
+ * nsys device FP64 vectors used as scratch (overwritten; their contents on
+ * entry are ignored).  opt as for the solves (group_rows is set per
+ * candidate; histories must be NULL).  The runs' own status (not converged,
+ * breakdown) does not matter.  Host-synchronous.  Errors: AMP_ERR_ARG for
+ * nsys < 1, iters < 1, ncand < 1, null pointers or a bad candidate; any
+ * error a solve returns other than not-converged or breakdown.
+ */
+amp_status amp_tune_group_rows(int nsys, const amp_matrix *A, const amp_precond *M, const double *const *b,
+                               double *const *x, const double *tol, int iters, const int *candidates,
+                               int ncand, const amp_options *opt, int *best, double *ms_per_iter,
+                               void *stream);
+
+/*
  * One product q = A p with the solver's own kernel, for tests and
  * measurement.  u_r selects the value plane and arithmetic (64: FP64
  * values and accumulation; 32: FP32 values and accumulation, in

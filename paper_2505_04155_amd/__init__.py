@@ -6,7 +6,9 @@ arXiv:2505.04155) as hand-written HIP kernels behind a C ABI
 Python entry points (argument marshalling only):
 
 * :class:`Matrix`, :class:`Preconditioner`, :func:`solve`, :func:`solve_batched`
+* :func:`tune_group_rows` (rows-per-work-group autotuner, run on the device)
 * :func:`selector_replay`, :func:`paper_kernel_bytes` (host-only helpers)
 """
 
-from .solver import Matrix, Preconditioner, solve, solve_batched, selector_replay, paper_kernel_bytes  # noqa: F401
+from .solver import (Matrix, Preconditioner, solve, solve_batched, tune_group_rows,  # noqa: F401
+                     selector_replay, paper_kernel_bytes)

@@ -1396,6 +1396,69 @@ static amp_status dispatch_spmv(amp_matrix A, int u_r, int u_z, int diff, const 
     return AMP_OK;
 }
 
+// ----------------------------------------------------------------------------
+// rows-per-work-group autotuner
+// ----------------------------------------------------------------------------
+
+extern "C" amp_status amp_tune_group_rows(int nsys, const amp_matrix *A, const amp_precond *M,
+                                          const double *const *b, double *const *x, const double *tol, int iters,
+                                          const int *candidates, int ncand, const amp_options *opt, int *best,
+                                          double *ms_per_iter, void *stream) {
+    if (nsys < 1 || iters < 1 || ncand < 1)
+        return fail(AMP_ERR_ARG, "amp_tune_group_rows: nsys, iters and ncand must be >= 1");
+    if (!A || !M || !b || !x || !tol || !candidates || !best)
+        return fail(AMP_ERR_ARG, "amp_tune_group_rows: null argument");
+    for (int c = 0; c < ncand; ++c)
+        if (candidates[c] < 0 || candidates[c] % 256)
+            return fail(AMP_ERR_ARG, "amp_tune_group_rows: a candidate is neither 0 nor a positive multiple of 256");
+    for (int i = 0; i < nsys; ++i)
+        if (!A[i] || !x[i]) return fail(AMP_ERR_ARG, "amp_tune_group_rows: null handle or vector");
+    amp_options o;
+    if (opt) o = *opt;
+    else amp_options_default(&o);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<amp_result> res(nsys);
+    double best_ms = 0.0;
+    // one run from x = 0 with at most `maxit` iterations: host time and lockstep iterations
+    auto run = [&](int maxit, double &ms, int &steps) -> amp_status {
+        for (int i = 0; i < nsys; ++i) AMP_HIP(hipMemsetAsync(x[i], 0, A[i]->n * sizeof(double), st));
+        AMP_HIP(hipStreamSynchronize(st));
+        const auto t0 = std::chrono::steady_clock::now();
+        const amp_status rs = (nsys == 1)
+                                  ? amp_pcg_solve(A[0], M[0], b[0], x[0], tol[0], maxit, &o, res.data(), stream)
+                                  : amp_pcg_solve_batched(nsys, A, M, b, x, tol, maxit, &o, res.data(), stream);
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rs != AMP_OK && rs != AMP_ERR_NOT_CONVERGED && rs != AMP_ERR_BREAKDOWN) return rs;
+        steps = 0;
+        for (int i = 0; i < nsys; ++i) steps = std::max(steps, res[i].iters);
+        return AMP_OK;
+    };
+    for (int c = 0; c < ncand; ++c) {
+        o.group_rows = candidates[c];
+        // warm-up, then a run without iterations (the per-call costs: set-up,
+        // r0, the final check) and a run with them; the difference is the
+        // iterations' time
+        // (each the least of three runs)
+        double ms = 1e300, ms0 = 1e300, t = 0.0;
+        int steps = 0, s0 = 0;
+        AMP_TRY(run(iters, t, steps));
+        for (int rep = 0; rep < 3; ++rep) {
+            AMP_TRY(run(0, t, s0));
+            ms0 = std::min(ms0, t);
+            AMP_TRY(run(iters, t, steps));
+            ms = std::min(ms, t);
+        }
+        const double per = std::max(0.0, ms - ms0) / std::max(1, steps);
+        if (ms_per_iter) ms_per_iter[c] = per;
+        if (c == 0 || per < best_ms) {
+            best_ms = per;
+            *best = candidates[c];
+        }
+    }
+    g_last_error.clear();
+    return AMP_OK;
+}
+
 extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,
                                void *stream) {
     if (!A) return fail(AMP_ERR_ARG, "amp_spmv: null matrix");

@@ -191,6 +191,39 @@ def solve_batched(As, Ms, bs, x0s=None, tol=1e-10, maxit: int = 5000, preset: st
     return xs, infos, st
 
 
+def tune_group_rows(As, Ms, bs, tol=1e-10, iters: int = 32, candidates=(0, 1024, 2048, 4096, 8192),
+                    preset: str = "amp64", **opts):
+    """Rows-per-work-group autotuner (amp_tune_group_rows): times at most
+    `iters` iterations of the solve -- single when one system is given,
+    batched otherwise -- for each candidate group_rows (0: automatic) and
+    returns (best, {candidate: ms per iteration}).  As, Ms, bs: a handle /
+    tensor or equal-length lists of them."""
+    L = B.load()
+    if isinstance(As, Matrix):
+        As, Ms, bs = [As], [Ms], [bs]
+    n = len(As)
+    if not (len(Ms) == len(bs) == n) or n == 0:
+        raise ValueError("As, Ms and bs must be non-empty and of equal length")
+    for i in range(n):
+        _need(bs[i], torch.float64, As[i].n, f"b[{i}]")
+    xs = [torch.empty_like(b) for b in bs]   # scratch
+    tols = [float(tol)] * n if isinstance(tol, (int, float)) else [float(t) for t in tol]
+    cands = [int(c) for c in candidates]
+    vp = ctypes.c_void_p
+    a_arr = (vp * n)(*[A.handle.value for A in As])
+    m_arr = (vp * n)(*[M.handle.value for M in Ms])
+    b_arr = (vp * n)(*[b.data_ptr() for b in bs])
+    x_arr = (vp * n)(*[x.data_ptr() for x in xs])
+    t_arr = (ctypes.c_double * n)(*tols)
+    c_arr = (ctypes.c_int * len(cands))(*cands)
+    ms = (ctypes.c_double * len(cands))()
+    best = ctypes.c_int()
+    o = B.make_options(preset, **opts)
+    B.check(L.amp_tune_group_rows(n, a_arr, m_arr, b_arr, x_arr, t_arr, int(iters), c_arr, len(cands),
+                                  ctypes.byref(o), ctypes.byref(best), ms, _stream()), "amp_tune_group_rows")
+    return best.value, {c: ms[i] for i, c in enumerate(cands)}
+
+
 def selector_replay(delta, bnorm: float, tol: float, preset: str = "amp64", **opts):
     """Host-only replay of the device controller's latched selector."""
     L = B.load()
