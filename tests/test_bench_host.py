@@ -1,0 +1,63 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU refusal, the product
+step's byte model against sums written out by hand, and the guard that keeps
+a stored HBM-traffic summary from being reported for other kernel sources."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_step_bytes_by_hand():
+    # 128^3 7-point workload, all slices in offset mode
+    n, nnz, meta = 2097152, 14581760, 393512
+    # FP16 z, p (three vectors of 2 B: z, p_old read, p written) and FP64 A, q (8 B)
+    assert bench.step_bytes(n, nnz, meta, 16, 64) == nnz * 8 + meta + n * (2 + 2 + 2 + 8)
+    # FP16 z, p and FP32 A, q
+    assert bench.step_bytes(n, nnz, meta, 16, 32) == nnz * 4 + meta + n * (2 + 2 + 2 + 4)
+    # FP64 PCG: 8 B everywhere
+    assert bench.step_bytes(n, nnz, meta, 64, 64) == nnz * 8 + meta + n * 32
+    # the amp16 solve's launch-weighted mean (666 FP64-product, 835 FP32-product iterations)
+    mean = (666 * bench.step_bytes(n, nnz, meta, 16, 64) + 835 * bench.step_bytes(n, nnz, meta, 16, 32)) / 1501
+    assert abs(mean - 109294085) < 1.0
+
+
+def test_stored_traffic_requires_matching_sources(monkeypatch, tmp_path):
+    from paper_2505_04155_amd import build
+    f = tmp_path / "counters.txt"
+    f.write_text("# header\nsource_digest abc123\nkernel k_spmv\ntraffic_bytes_per_launch 112041016\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(build, "source_digest", lambda: "abc123")
+    assert bench.stored_traffic() == 112041016
+    monkeypatch.setattr(build, "source_digest", lambda: "other")
+    assert bench.stored_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.stored_traffic() is None
+
+
+def test_committed_summary_is_parseable():
+    fields = {}
+    with open(os.path.join(ROOT, "profiles", "k_spmv_fv3d128_hbm_counters.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, _, v = line.partition(" ")
+                fields[k] = v.strip()
+    assert fields["kernel"] == "k_spmv"
+    assert len(fields["source_digest"]) == 16
+    t = int(float(fields["traffic_bytes_per_launch"]))
+    # within a few percent of the algorithmic bytes of the same launches
+    assert 1.0 <= t / 109294085 <= 1.1
