@@ -112,9 +112,11 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 }
 
 // One step k of the recurrence for this work-group's slices.
-template <int UZ, bool FIRST, int BS>
-__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int last,
-                                               int din, double &rho, double &mz) {
+// RLAST: 0 for an inner step; for the last step, the precision of r (the
+// step then forms z and the partials of rho = r^T z).
+template <int UZ, bool FIRST, int RLAST, int BS>
+__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int din,
+                                               double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
     const CZ *v = (const CZ *)P.v;
@@ -126,38 +128,53 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     const CZ c1 = (CZ)P.c1[k], c2 = (CZ)P.c2[k];
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     TZ *z = (TZ *)B.z[pslot(UZ)];
-    const int ur = s.ur;
+    typedef typename Prec<(RLAST == 64 ? 64 : 32)>::T TRL;
+    const TRL *rl = (const TRL *)B.r[pslot(RLAST == 64 ? 64 : 32)];
     const bool first = FIRST;
+    constexpr bool last = RLAST != 0;
     auto dval = [&](int64_t j) -> CZ {
         if (FIRST) return v[j] * inv_theta;
         return dk[j];
     };
     AMP_SLICE_LOOP(P, sl, wg, BS) {
         AMP_SLICE_ROW(P, sl, lane, row, base, wd, BS);
+        // the row's own operands are loaded before the product, so their
+        // latency overlaps it
+        const CZ d0 = dval(row);
+        const CZ wk = first ? (CZ)0 + d0 : w[row];
+        const CZ rk = first ? v[row] : res[row];
+        CZ isq_r = (CZ)0;
+        double rr = 0.0;
+        if (last) {
+            isq_r = isq[row];
+            rr = (double)rl[row];
+        }
         CZ acc = (CZ)0;
+        // two chunks of slots per pass: all their value loads and gathers are
+        // issued before the first product is added (slots past the width
+        // repeat a valid slot's loads and add nothing; the sum runs in slot
+        // order)
         with_rec_cols(rec_, P.col, P.offs, P.np, sl, lane, [&](const auto &sc) {
-            for (int j0 = 0; j0 < wd; j0 += kChunk) {
-                int32_t cc[kChunk];
-                bool dg[kChunk];
-                CZ bv[kChunk], dj[kChunk];
+            for (int j0 = 0; j0 < wd; j0 += 2 * kChunk) {
+                int32_t cc[2 * kChunk];
+                bool dg[2 * kChunk];
+                CZ bv[2 * kChunk], dj[2 * kChunk];
                 sc.chunk(j0, wd, cc, dg);
+                sc.chunk(j0 + kChunk < wd ? j0 + kChunk : j0, wd, cc + kChunk, dg + kChunk);
 #pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
+                for (int u = 0; u < 2 * kChunk; ++u) {
                     const int j = j0 + u < wd ? j0 + u : wd - 1;
                     bv[u] = (CZ)P.b16[base + (int64_t)j * SLICE];
                     dj[u] = dval(cc[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
+                for (int u = 0; u < 2 * kChunk; ++u) {
                     const CZ t = acc + bv[u] * dj[u];
                     acc = (j0 + u < wd) ? t : acc;
                 }
             }
         });
-        const CZ d0 = dval(row);
-        const CZ wk = first ? (CZ)0 + d0 : w[row];
         const CZ w1 = first ? wk : wk + d0;
-        const CZ rk = first ? v[row] : res[row];
         const CZ r1 = rk - acc;
         const CZ d1 = c1 * d0 + c2 * r1;
         if (!last) {
@@ -166,11 +183,8 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
             dn[row] = d1;
         } else {
             const CZ wm = w1 + d1;
-            const TZ zz = (TZ)(isq[row] * wm);
+            const TZ zz = (TZ)(isq_r * wm);
             z[row] = zz;
-            double rr;
-            if (ur == 64) rr = ((const double *)B.r[0])[row];
-            else rr = (double)((const float *)B.r[1])[row];
             rho += rr * (double)zz;
             mz = fmax(mz, fabs((double)zz));
         }
@@ -187,15 +201,22 @@ __global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int fi
         return;
     }
     double rho = 0.0, mz = 0.0;
+#define AMP_CS_L(UZ, RL)                                                                \
+    do {                                                                                \
+        if (first) cheb_step_body<UZ, true, RL, NTS>(s, B, P, wg, k, din, rho, mz);     \
+        else cheb_step_body<UZ, false, RL, NTS>(s, B, P, wg, k, din, rho, mz);          \
+    } while (0)
 #define AMP_CS(UZ)                                                      \
     do {                                                                \
-        if (first) cheb_step_body<UZ, true, NTS>(s, B, P, wg, k, last, din, rho, mz);  \
-        else cheb_step_body<UZ, false, NTS>(s, B, P, wg, k, last, din, rho, mz);       \
+        if (!last) AMP_CS_L(UZ, 0);                                     \
+        else if (s.ur == 64) AMP_CS_L(UZ, 64);                          \
+        else AMP_CS_L(UZ, 32);                                          \
     } while (0)
     if (s.uz == 64) AMP_CS(64);
     else if (s.uz == 32) AMP_CS(32);
     else AMP_CS(16);
 #undef AMP_CS
+#undef AMP_CS_L
     if (last) {
         double v2[2] = {rho, mz};
         block_reduce<1, 1, NTS>(v2);
