@@ -485,7 +485,16 @@ __device__ __forceinline__ void precond_body(const St &s, const Bufs &B, int64_t
         for (int j = 0; j < 2; ++j, i += (int64_t)NT * VEC)
             if (i < hi) chunk(i, raw_as<TRS>(pre.r[j]), raw_as<TZ>(pre.d[j]));
     }
-    for (; i < hi; i += (int64_t)NT * VEC) chunk(i, ld4(r, i), ld4(dv, i));
+    // the rest of the range (large systems), two chunks per pass with all
+    // their loads issued first
+    constexpr int64_t step = (int64_t)NT * VEC;
+    for (; i + step < hi; i += 2 * step) {
+        const V4<TRS> ra = ld4(r, i), rb = ld4(r, i + step);
+        const V4<TZ> da = ld4(dv, i), db = ld4(dv, i + step);
+        chunk(i, ra, da);
+        chunk(i + step, rb, db);
+    }
+    if (i < hi) chunk(i, ld4(r, i), ld4(dv, i));
 }
 
 // At a u_z switch p_{k-1} is first rounded to the new u_z.
@@ -835,7 +844,28 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
     };
     if (i0 < hi) chunk(i0, p0, pq0, x0, r0, q0);
     if (PF == 2 && i0 + step < hi) chunk(i0 + step, p1, pq1, x1, r1, q1);
-    for (int64_t i = i0 + PF * step; i < hi; i += step) {
+    // the rest of the range (large systems): two chunks per pass with all
+    // their loads issued first where two chunks were loaded ahead above
+    // (the register budget is the same), else one
+    int64_t i = i0 + PF * step;
+    for (; PF == 2 && i + step < hi; i += 2 * step) {
+        V4<TP> pa, pb, pqa, pqb;
+        V4<double> xa, xb;
+        if (XM >= 1) {
+            pa = ld4(p, i);
+            pb = ld4(p, i + step);
+            xa = ld4(B.x, i);
+            xb = ld4(B.x, i + step);
+        }
+        if (XM == 2) {
+            pqa = ld4(pq, i);
+            pqb = ld4(pq, i + step);
+        }
+        const V4<TR> ra = ld4(r, i), rb = ld4(r, i + step), qa = ld4(q, i), qb = ld4(q, i + step);
+        chunk(i, pa, pqa, xa, ra, qa);
+        chunk(i + step, pb, pqb, xb, rb, qb);
+    }
+    for (; i < hi; i += step) {
         V4<TP> pv4, pqv;
         V4<double> xv;
         if (XM >= 1) {
