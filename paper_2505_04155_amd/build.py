@@ -47,15 +47,24 @@ def sources_mtime() -> float:
 KERNEL_HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space (string literals in these
+    headers hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_digest() -> str:
-    """SHA-256 over the sources that define the iteration kernels (device
-    headers) and the compiler flags: names the kernel build a stored
-    measurement of those kernels belongs to."""
+    """SHA-256 over the code of the sources that define the iteration kernels
+    (device headers, comments and layout ignored) and the compiler flags:
+    names the kernel build a stored measurement of those kernels belongs to."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_HEADERS:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+            h.update(f.encode() + b"\0" + _code_only(fh.read()).encode())
     h.update(" ".join(f for f in flags() if not f.startswith("/")).encode())
     return h.hexdigest()[:16]
 

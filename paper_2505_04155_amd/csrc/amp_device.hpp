@@ -395,13 +395,4 @@ __device__ __forceinline__ void reduce_loaded(const PartRegs<NS + NM, BS> &pr, i
     }
 }
 
-// NS sums followed by NM maxima of partial arrays (part[t * GMAX + i]) in
-// one pass and one exchange.
-template <int NS, int NM, int BS = NT>
-__device__ __forceinline__ void reduce_parts(const double *part, int G, double *out) {
-    PartRegs<NS + NM, BS> pr;
-    load_parts<NS + NM, BS>(part, G, pr);
-    reduce_loaded<NS, NM, BS>(pr, G, out);
-}
-
 }  // namespace amp

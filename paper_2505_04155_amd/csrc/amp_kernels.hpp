@@ -9,7 +9,8 @@
 //              on the fly at the gathered columns), q = A p (u_r), partials
 //              of gamma = q^T p
 //   k_update   [prologue: gamma, alpha]
-//              x += alpha p (FP64), r -= alpha q (u_r), partials of ||r||^2
+//              r -= alpha q (u_r), partials of ||r||^2; x += alpha p (FP64)
+//              applied two iterations at a time (see update_run)
 //
 // plus k_init (r0 = b - A x0) and k_true_res (FP64 b - A x for the
 // termination check, periodic replacement, or a report).
@@ -19,7 +20,9 @@
 // adds all of them in the same fixed order and evaluates the controller
 // from identical inputs, so all reach identical decisions.  Work-group 0
 // writes the resulting state to a buffer that no work-group of the same
-// kernel reads.
+// kernel reads.  Each kernel issues its partial loads together with the
+// state load, and the streaming kernels their first body loads before the
+// reduction (a barrier waits only for LDS, so these stay in flight).
 #pragma once
 
 #include "amp_device.hpp"
