@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-solution at rel. residual 1e-10, AMP-PCG vs FP64 PCG; SpMV HBM GB/s"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_fv3d128_hbm_counters.txt")
+Q1_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_q1_256_hbm_counters.txt")
 
 
 def log(msg):
@@ -52,7 +53,7 @@ def step_bytes(n, nnz, meta_bytes, u_z, u_r):
     return nnz * b_val + meta_bytes + n * (3 * (u_z // 8) + u_r // 8)
 
 
-def stored_traffic():
+def stored_traffic(path=None):
     """HBM bytes per product launch from the committed FETCH_SIZE / WRITE_SIZE
     summary (each counter scaled by what it reads for a plain copy of known
     size), or None when the summary is missing or was taken on other kernel
@@ -60,7 +61,7 @@ def stored_traffic():
     from paper_2505_04155_amd import build
     try:
         fields = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             for line in f:
                 if line.strip() and not line.startswith("#"):
                     key, _, val = line.partition(" ")
@@ -72,7 +73,7 @@ def stored_traffic():
     return int(float(fields["traffic_bytes_per_launch"]))
 
 
-def roofline(amp, M, pc, bt, info_m, preset, tol, maxit):
+def roofline(amp, M, pc, bt, info_m, preset, tol, maxit, traffic_file=None):
     """One AMP-PCG solve with the library timing every product launch (HIP
     events carried by the launch's own dispatch on the solve's stream);
     achieved = algorithmic bytes of the launches that performed an
@@ -97,7 +98,7 @@ def roofline(amp, M, pc, bt, info_m, preset, tol, maxit):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(gbs / HBM_PEAK_GBS, 4),
-        "traffic": stored_traffic(),
+        "traffic": stored_traffic(traffic_file),
         "avg_kernel_us": round(us, 3),
         "launches": launches,
         "algorithmic_bytes_per_launch": round(total / launches),
@@ -144,6 +145,46 @@ def copy_reference(torch, dev, reps=5, mib=256):
     return {"bytes": 2 * src.numel() * 4, "avg_us": round(us, 3), "GB/s": round(2 * src.numel() * 4 / us / 1e3, 1)}
 
 
+def q1_mode(args, amp, torch, np, P, dev, tol=1e-10, maxit=20000):
+    """The anisotropic Q1 stiffness workload (27-point, 256^3 interior nodes,
+    x* ~ U[-1, 1], b = A x*) with the degree-4 Chebyshev preconditioner: one
+    timed solve per preset after a warm-up, the in-solve product roofline,
+    and the reference copy a counter run scales by.  One JSON line."""
+    m = args.q1_grid
+    log(f"bench: generating the Q1 {m}^3 system")
+    A, b, xs, (lo, hi) = P.q1_system(m)
+    M = amp.Matrix.from_csr(A, device=dev)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    bt = torch.tensor(b, device=dev)
+    info_m = M.info()
+    n, nnz = A.n, A.nnz
+    del A
+    out = {"mode": "q1", "workload": f"Q1 anisotropic diffusion (1, 1e-2, 1e-3), {m}^3 interior nodes, N={n}, "
+                                     f"nnz={nnz}, degree-4 Chebyshev on [lam_lo, 1.05 lam_hi], tol {tol}"}
+    xsn = float(np.linalg.norm(xs))
+    for preset in (args.preset, "pcg64"):
+        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if info["status"] != 0:
+            raise RuntimeError(f"{preset} solve failed: {info}")
+        err = float(np.linalg.norm(x.cpu().numpy() - xs) / xsn)
+        out[preset] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res_true": info["relres_true"],
+                       "rel_err_vs_xstar": err,
+                       "switch_iterations": [info["k_z32"], info["k_z16"], info["k_r32"]]}
+        log(f"bench: Q1 {preset}: {ms:.1f} ms, {info['iters']} iterations, error vs x* {err:.2e}")
+    out["speedup_vs_fp64_pcg"] = round(out["pcg64"]["ms"] / out[args.preset]["ms"], 4)
+    out["roofline"] = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit, traffic_file=Q1_TRAFFIC_FILE)
+    log(f"bench: Q1 product step in the solve: {out['roofline']['avg_kernel_us']:.1f} us, "
+        f"{out['roofline']['achieved']:.0f} GB/s")
+    out["copy_256MiB"] = copy_reference(torch, dev)
+    out["matrix"] = info_m
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,8 +193,10 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--preset", default="amp16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "roofline"], default="solve",
-                    help="roofline: only the timed-product solve and the reference copy (for profiler runs)")
+    ap.add_argument("--mode", choices=["solve", "roofline", "q1"], default="solve",
+                    help="roofline: only the timed-product solve and the reference copy (for profiler runs); "
+                         "q1: the anisotropic Q1 workload with the degree-4 Chebyshev preconditioner")
+    ap.add_argument("--q1-grid", type=int, default=256, help="interior nodes per direction of the Q1 workload")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -172,6 +215,10 @@ def main():
     binding.load(build_if_missing=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.mode == "q1":
+        q1_mode(args, amp, torch, np, P, dev)
+        return
 
     log(f"bench: generating the {args.grid}^3 system")
     A, b, _ = P.blocky_diffusion3d_system(args.grid, 8)
