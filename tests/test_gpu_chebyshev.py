@@ -40,10 +40,12 @@ def _say(msg):
     print(msg, flush=True)
 
 
+@pytest.mark.parametrize("offsets", [True, False])
 @pytest.mark.parametrize("degree", [1, 2, 4])
 @pytest.mark.parametrize("u_r,u_z", [(64, 64), (64, 16), (32, 32), (32, 16)])
-def test_chebyshev_apply_matches_model(amp, degree, u_r, u_z):
-    _say(f"chebyshev apply degree={degree} u_r={u_r} u_z={u_z}")
+def test_chebyshev_apply_matches_model(amp, degree, u_r, u_z, offsets):
+    # offsets=False keeps every slice in index mode (per-entry columns)
+    _say(f"chebyshev apply degree={degree} u_r={u_r} u_z={u_z} offsets={offsets}")
     A, b, xs, (lo, hi) = P.q1_system(18)
     S = A.to_scipy()
     C = am.Chebyshev(S, lo, hi, degree)
@@ -51,7 +53,7 @@ def test_chebyshev_apply_matches_model(amp, degree, u_r, u_z):
     omega = 2.0 ** 7
     y = am.fl(am.fl(r.astype(NP[u_r]) * NP[u_r](omega), u_r), u_z)
     zref = C.apply(y, u_z).astype(np.float64)
-    M = amp.Matrix.from_csr(A)
+    M = amp.Matrix.from_csr(A, offsets=offsets)
     pc = amp.Preconditioner(M, "chebyshev", degree=degree, lam_lo=lo, lam_hi=hi)
     z, rho = pc.apply(torch.tensor(r, device="cuda"), u_z=u_z, omega=omega)
     zh = z.cpu().numpy().astype(np.float64)
@@ -62,14 +64,15 @@ def test_chebyshev_apply_matches_model(amp, degree, u_r, u_z):
     assert rho.item() == pytest.approx(float(r.astype(np.float64) @ zh), rel=1e-12)
 
 
+@pytest.mark.parametrize("offsets", [True, False])
 @pytest.mark.parametrize("preset", ["pcg64", "amp64", "amp16"])
-def test_chebyshev_solve_parity(amp, preset):
-    _say(f"chebyshev solve {preset}")
+def test_chebyshev_solve_parity(amp, preset, offsets):
+    _say(f"chebyshev solve {preset} offsets={offsets}")
     A, b, xs, (lo, hi) = P.q1_system(24)
     S = A.to_scipy()
     xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=lo, lam_hi=hi)
     ref = am.amp_pcg(S, b, tol=1e-10, maxit=5000, M=am.Chebyshev(S, lo, hi, 4), opt=am.options(preset))
-    M = amp.Matrix.from_csr(A)
+    M = amp.Matrix.from_csr(A, offsets=offsets)
     pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
     x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=5000, preset=preset,
                         history=True)
@@ -86,6 +89,25 @@ def test_chebyshev_solve_parity(amp, preset):
     assert (kz32, kz16, kr) == (info["k_z32"], info["k_z16"], info["k_r32"])
     kappa = 1.25 * hi / lo                       # bound for the preconditioned operator
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 2e-10
+
+
+@pytest.mark.parametrize("offsets", [True, False])
+def test_chebyshev_poisson_short_rows(amp, offsets):
+    # 5-point rows (one partial chunk of slots) in both layouts; the bounds of
+    # D^-1 A for the 2-D Poisson stencil are 1 -/+ cos(pi / (m + 1)), and
+    # B = D^-1/2 A D^-1/2 (entries 1 and -1/4) is exact in FP16
+    m = 48
+    A, b, xs = P.poisson2d_system(m)
+    lo, hi = 1.0 - math.cos(math.pi / (m + 1)), 1.0 + math.cos(math.pi / (m + 1))
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=lo, lam_hi=hi)
+    M = amp.Matrix.from_csr(A, offsets=offsets)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=5000, preset="pcg64")
+    _say(f"chebyshev poisson {m} offsets={offsets}: {info['iters']} iterations (oracle {io['iters']})")
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10
+    assert abs(info["iters"] - io["iters"]) <= 2
+    # both stop at ||r|| <= 1e-10 ||b||: solutions agree within 2 tol kappa(A), kappa(A) = hi / lo
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 2e-10 * (hi / lo) * np.linalg.norm(xo)
 
 
 def test_q1_full_size(amp):
