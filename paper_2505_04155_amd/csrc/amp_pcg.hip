@@ -1,5 +1,5 @@
-// Host side of the AMP-PCG library: handles, sliced-ELL setup, the solve
-// driver (status polling, batching) and the C ABI declared in amp_pcg.h.
+// Host side of the AMP-PCG library: handles, sliced-ELL setup, the host loop
+// of a solve (status polling, batching) and the C ABI declared in amp_pcg.h.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
