@@ -332,3 +332,43 @@ def test_blocky128_full_size(amp):
     x64, i64 = _gpu_solve(amp, A, b, "pcg64", maxit=20000)
     assert i64["iters"] == io["iters"]
     assert _rel(x64, xo) <= 1e-9
+
+
+# ------------------------------------------------------------------ failure injection
+
+@pytest.mark.parametrize("preset", ["pcg64", "amp16"])
+def test_nan_in_rhs_is_a_breakdown(amp, preset):
+    # a NaN in b makes rho non-finite in the first product: the solve stops
+    # with a breakdown and returns the last finite iterate (here x0)
+    _say(f"failure injection: NaN in b, {preset}")
+    from paper_2505_04155_amd import binding as B
+    A, b, _ = P.poisson2d_system(20)
+    b = b.copy()
+    b[57] = np.nan
+    x0 = np.random.default_rng([320]).standard_normal(A.n)
+    x, info = _gpu_solve(amp, A, b, preset, maxit=50, x0=x0)
+    assert info["status"] == B.AMP_ERR_BREAKDOWN
+    assert np.array_equal(x, x0)
+
+
+def test_nan_system_in_a_batch(amp):
+    # one system of a batch breaks down; the others converge as on their own
+    # (same rows per work-group as the batched default, 4096)
+    _say("failure injection: NaN in one system of a batch")
+    from paper_2505_04155_amd import binding as B
+    systems = [P.poisson2d_system(m)[:2] for m in (16, 24, 32)]
+    bad = systems[1][1].copy()
+    bad[3] = np.nan
+    systems[1] = (systems[1][0], bad)
+    Ms = [amp.Matrix.from_csr(A) for A, _ in systems]
+    Ps = [amp.Preconditioner(M, "jacobi") for M in Ms]
+    bs = [torch.tensor(b, device="cuda") for _, b in systems]
+    xs, infos, st = amp.solve_batched(Ms, Ps, bs, tol=1e-10, maxit=500, preset="amp64")
+    torch.cuda.synchronize()
+    assert st == B.AMP_ERR_BREAKDOWN
+    assert infos[1]["status"] == B.AMP_ERR_BREAKDOWN
+    for i in (0, 2):
+        x1, i1 = amp.solve(Ms[i], Ps[i], bs[i], tol=1e-10, maxit=500, preset="amp64", group_rows=4096)
+        torch.cuda.synchronize()
+        assert infos[i]["status"] == 0 and infos[i]["iters"] == i1["iters"]
+        assert torch.equal(xs[i], x1)
