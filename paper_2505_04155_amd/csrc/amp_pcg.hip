@@ -1032,7 +1032,10 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
                 int left = 256;
                 if (rate > 0.0 && rate < 1.0)
                     left = (int)std::ceil(std::log(tol * cur.bnorm / cur.delta) / std::log(rate));
-                batch = std::max(4, std::min(256, left / 2 + 1));
+                // a quarter of the predicted remainder: the batch queued behind the
+                // one being read then overshoots convergence by a few iterations
+                // (half of it left ~130 pass-through iterations on a 1500-iteration solve)
+                batch = std::max(4, std::min(256, left / 4 + 1));
                 if (graph) batch = (int)round_up(batch, kGraphIters);
             }
             if (cur.iters > last_iters) {
