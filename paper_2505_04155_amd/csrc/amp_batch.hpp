@@ -25,16 +25,27 @@ struct SysDesc {
     int solo;           // solved by one work-group of k_batch_solo, not by the lockstep kernels
 };
 
-// A work-group's assignment; sys < 0 marks padding.
+// A work-group's assignment; sys < 0 marks padding.  Besides (system,
+// logical index) it carries what an iteration kernel's first loads need --
+// the system's work-group count, state slots, partial arrays and residual
+// window -- so that those loads wait only for the task, not for the
+// system's descriptor.
 struct Task {
-    int sys, lb;
+    int sys, lb, g, pad;
+    St *st;
+    const double *part_res, *part_pre, *part_spmv, *ring;
 };
 
-#define AMP_BATCH_TASK(sd, tasks, d, wg)                  \
-    const Task t_ = (tasks)[xcd_block()];                 \
-    if (t_.sys < 0) return;                               \
-    const SysDesc &d = (sd)[t_.sys];                      \
-    const Wg wg{t_.lb, d.c.g_stream}
+// Every field of the task is used before the padding test, so the compiler
+// loads the whole task at once instead of after the branch.
+#define AMP_BATCH_TASK(sd, tasks, d, wg)                                                     \
+    const Task t_ = (tasks)[xcd_block()];                                                    \
+    pin((uint32_t)t_.lb ^ (uint32_t)t_.g ^ (uint32_t)(uintptr_t)t_.st ^                     \
+        (uint32_t)(uintptr_t)t_.part_res ^ (uint32_t)(uintptr_t)t_.part_pre ^              \
+        (uint32_t)(uintptr_t)t_.part_spmv ^ (uint32_t)(uintptr_t)t_.ring);                 \
+    if (t_.sys < 0) return;                                                                  \
+    const SysDesc &d = (sd)[t_.sys];                                                         \
+    const Wg wg{t_.lb, t_.g}
 
 // Copy b and x0 into the padded work vectors; lb 0 writes the initial state.
 __global__ void __launch_bounds__(NT) k_batch_prep(const SysDesc *sd, const Task *tasks, St s0, int slot) {
@@ -55,17 +66,17 @@ __global__ void __launch_bounds__(NTS) k_batch_init(const SysDesc *sd, const Tas
 
 __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    precond_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg, res_early(d.c, d.B));
+    precond_stage(d.c, d.B, d.A.np, t_.st + si, t_.st + so, wg, Early{t_.part_res, t_.g, t_.ring, 0u});
 }
 
 __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    spmv_stage<NTS>(d.c, d.A, d.B, d.st + si, d.st + so, wg, pre_early(d.c, d.B));
+    spmv_stage<NTS>(d.c, d.A, d.B, t_.st + si, t_.st + so, wg, Early{t_.part_pre, t_.g, nullptr, 0u});
 }
 
 __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    update_stage(d.c, d.B, d.A.np, d.st + si, d.st + so, wg, spmv_early(d.c, d.B));
+    update_stage(d.c, d.B, d.A.np, t_.st + si, t_.st + so, wg, Early{t_.part_spmv, t_.g, nullptr, 0u});
 }
 
 __global__ void __launch_bounds__(NTS) k_batch_true_res(const SysDesc *sd, const Task *tasks, int mode, int si,

@@ -1152,12 +1152,15 @@ struct BatchBufs {
 // Task list of the live systems, ordered by system so that consecutive
 // logical work-group indices (one XCD's share) cover whole systems; padded
 // with sys = -1 to a multiple of the XCD count.
-void build_tasks(const std::vector<int> &G, const std::vector<char> &live, std::vector<Task> &out) {
+void build_tasks(const std::vector<SysDesc> &sd, const std::vector<char> &live, std::vector<Task> &out) {
     out.clear();
-    for (size_t s = 0; s < G.size(); ++s)
-        if (live[s])
-            for (int lb = 0; lb < G[s]; ++lb) out.push_back(Task{(int)s, lb});
-    while (out.size() % NXCD) out.push_back(Task{-1, 0});
+    for (size_t s = 0; s < sd.size(); ++s) {
+        if (!live[s]) continue;
+        const SysDesc &d = sd[s];
+        for (int lb = 0; lb < d.c.g_stream; ++lb)
+            out.push_back(Task{(int)s, lb, d.c.g_stream, 0, d.st, d.B.part_res, d.B.part_pre, d.B.part_spmv, d.c.ring});
+    }
+    while (out.size() % NXCD) out.push_back(Task{-1, 0, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr});
 }
 
 }  // namespace
@@ -1199,7 +1202,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 
     // per-system descriptors and work-group counts
     std::vector<SysDesc> hsd(nsys);
-    std::vector<int> G(nsys), solo_list;
+    std::vector<int> solo_list;
     std::vector<char> live(nsys, 1);
     for (int i = 0; i < nsys; ++i) {
         SysDesc &d = hsd[i];
@@ -1211,7 +1214,6 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
             live[i] = 0;
             solo_list.push_back(i);
         }
-        G[i] = d.c.g_stream;
         d.A = A[i]->sell();
         d.B = make_bufs(A[i], M[i]);
         d.st = A[i]->w.st;
@@ -1221,8 +1223,8 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
         d.n = A[i]->n;
     }
     std::vector<Task> all, lock;
-    build_tasks(G, std::vector<char>(nsys, 1), all);
-    build_tasks(G, live, lock);
+    build_tasks(hsd, std::vector<char>(nsys, 1), all);
+    build_tasks(hsd, live, lock);
     const size_t cap = all.size();
     const int nsolo = (int)solo_list.size();
 
@@ -1309,7 +1311,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
         if (nlive == 0) break;
         if (stopped) {
             // drop the stopped systems from every launch enqueued from now on
-            build_tasks(G, live, cur_tasks);
+            build_tasks(hsd, live, cur_tasks);
             Task *stg = bb.stage + (size_t)stage_next * cap;
             AMP_HIP(hipEventSynchronize(bb.evt[stage_next]));
             std::memcpy(stg, cur_tasks.data(), cur_tasks.size() * sizeof(Task));
