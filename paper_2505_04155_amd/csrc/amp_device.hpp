@@ -113,8 +113,10 @@ struct OffCols {
         const OffChunk o = *reinterpret_cast<const OffChunk *>(offs + j0);   // one scalar load
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            const int64_t cc = row + o.o[u];
-            c[u] = (int32_t)((cc >= 0 && cc < np) ? cc : row);
+            // row + o in [0, np) as one unsigned 32-bit test: row < np < 2^31
+            // and |o| < 2^31, so a negative sum wraps to at least 2^31
+            const uint32_t cc = (uint32_t)row + (uint32_t)o.o[u];
+            c[u] = (int32_t)(cc < (uint32_t)np ? cc : (uint32_t)row);
             dg[u] = o.o[u] == 0;
         }
     }
