@@ -71,7 +71,8 @@ typedef enum {
 
 /* Matrix in CSR form, all arrays device pointers: row_ptr[n+1], col_idx[nnz],
  * val[nnz].  Columns strictly ascending within each row (no duplicates), the
- * diagonal present, nnz < 2^31.
+ * diagonal present, nnz < 2^31, n <= 2^29 - 1024 (the product kernels gather
+ * vector entries by 32-bit byte offsets).
  * The values are read once by amp_matrix_create (no reference is kept). */
 typedef struct {
     int32_t n;
@@ -163,9 +164,9 @@ amp_status amp_options_preset(amp_options *opt, int preset);
  * The CSR is validated on the device before any entry is read through it:
  * row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing; columns in [0, n) and
  * strictly ascending within each row.
- * Errors: AMP_ERR_ARG for n <= 0, nnz < n, nnz >= 2^31, null pointers, a CSR
- * failing the validation above, or a missing or non-positive diagonal
- * entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
+ * Errors: AMP_ERR_ARG for n <= 0, n > 2^29 - 1024, nnz < n, nnz >= 2^31,
+ * null pointers, a CSR failing the validation above, or a missing or
+ * non-positive diagonal entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
  */
 amp_status amp_matrix_create(const amp_csr *A, void *stream, amp_matrix *out);
 /* As amp_matrix_create; flags bit 0 keeps every slice in index mode (no

@@ -33,6 +33,9 @@ constexpr int VEC = 4;       // consecutive elements per thread in streaming ker
 constexpr int GMAX = AMP_GMAX;   // upper bound on work-groups of a reducing kernel
 constexpr int GSTREAM = 1024;    // upper bound on work-groups of a streaming kernel
 constexpr int PAD = NT * VEC;  // internal vectors are padded to a multiple of this
+// Largest n: padded vectors hold at most 2^29 entries, so the byte offset of
+// any gathered FP64 entry fits 32 bits (at32).
+constexpr int64_t kMaxRows = ((int64_t)1 << 29) - PAD;
 constexpr int NXCD = 8;      // accelerator complex dies; work-groups are dealt to them round-robin
 
 // Round x to the storage type T once, to nearest even.  FP64 -> FP16 is not
@@ -93,6 +96,15 @@ struct Sell {
 };
 
 constexpr int kOffMax = 32;  // longest per-slice offset list
+
+// a[i] through a 32-bit byte offset from a base pointer the whole wave
+// shares: the load takes its base from scalar registers and one offset
+// register per lane, with no 64-bit address arithmetic per slot.  For
+// gathers by row index: i < np <= 2^29 keeps i * sizeof(T) below 2^32.
+template <typename T>
+__device__ __forceinline__ T at32(const T *a, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + i * (uint32_t)sizeof(T));
+}
 
 // Columns of slots j0 .. j0 + kChunk - 1 of one row of a slice, one functor
 // per storage mode.  Slots at or past the row width w give a valid column

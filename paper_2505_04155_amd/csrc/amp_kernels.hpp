@@ -605,8 +605,8 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     TQ *q = (TQ *)qv;
     const CZ beta = (CZ)beta_d;
     auto pval = [&](int64_t c) -> TZ {
-        if (FIRST) return z[c];
-        return (TZ)((CZ)z[c] + beta * (CZ)po[c]);
+        if (FIRST) return at32(z, (uint32_t)c);
+        return (TZ)((CZ)at32(z, (uint32_t)c) + beta * (CZ)at32(po, (uint32_t)c));
     };
     constexpr int NW = BS / WAVE;
     const int lane = threadIdx.x % WAVE;

@@ -410,8 +410,9 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     if (csr->n <= 0) return fail(AMP_ERR_ARG, "amp_matrix_create: n must be positive");
     if (csr->nnz < csr->n || csr->nnz >= ((int64_t)1 << 31))
         return fail(AMP_ERR_ARG, "amp_matrix_create: need n <= nnz < 2^31");
-    if ((int64_t)csr->n > ((int64_t)1 << 31) - 1 - 2 * PAD)
-        return fail(AMP_ERR_ARG, "amp_matrix_create: n too large for int32 row indices after padding");
+    if ((int64_t)csr->n > kMaxRows)
+        return fail(AMP_ERR_ARG, "amp_matrix_create: n above the row limit 2^29 - " + std::to_string(PAD) +
+                                     " (gathers use 32-bit byte offsets)");
     hipStream_t st = as_stream(stream);
     amp_matrix A = new amp_matrix_s();
     auto bail = [&](amp_status s) { amp_matrix_destroy(A); return s; };

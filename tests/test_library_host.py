@@ -99,3 +99,20 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+@pytest.mark.parametrize("n,nnz", [(0, 1), (2 ** 29 - 1024 + 1, 2 ** 29), (2 ** 29, 2 ** 29), (1000, 2 ** 31),
+                                   (1000, 999)])
+def test_matrix_size_limits_rejected_before_any_device_access(n, nnz):
+    # the size checks come first: the (never dereferenced) pointers below are
+    # not device memory, and no GPU is needed
+    L = B.load()
+    csr = B.Csr(n=n, nnz=nnz, row_ptr=16, col_idx=16, val=16)
+    h = ctypes.c_void_p()
+    st = L.amp_matrix_create_ex(ctypes.byref(csr), 0, None, ctypes.byref(h))
+    assert st == B.AMP_ERR_ARG
+    assert not h.value
+    msg = B.last_error()
+    assert msg.startswith("amp_matrix_create")
+    if 0 < n <= nnz < 2 ** 31:
+        assert "2^29" in msg
