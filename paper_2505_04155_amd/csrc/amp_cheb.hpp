@@ -137,6 +137,7 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
         return dk[j];
     };
     AMP_SLICE_LOOP(P, sl, wg, BS) {
+        progress_prio(sl - slo_, shi_ - slo_);
         AMP_SLICE_ROW(P, sl, lane, row, base, wd, BS);
         // the row's own operands are loaded before the product, so their
         // latency overlaps it

@@ -97,6 +97,19 @@ struct Sell {
 
 constexpr int kOffMax = 32;  // longest per-slice offset list
 
+// Issue priority from a wave's progress through its work-group's range.
+// The work-groups sharing a CU start together, but the hardware favours the
+// oldest waves: left alone, the first work-group finishes microseconds
+// before the last, and the CU runs that tail with few loads in flight.  A
+// wave that is ahead lowers its priority so the others catch up.  Timing
+// only: no result depends on it.
+__device__ __forceinline__ void progress_prio(int64_t done, int64_t span) {
+    if (done * 4 >= span * 3) __builtin_amdgcn_s_setprio(0);
+    else if (done * 2 >= span) __builtin_amdgcn_s_setprio(1);
+    else if (done * 4 >= span) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(3);
+}
+
 // a[i] through a 32-bit byte offset from a base pointer the whole wave
 // shares: the load takes its base from scalar registers and one offset
 // register per lane, with no 64-bit address arithmetic per slot.  For

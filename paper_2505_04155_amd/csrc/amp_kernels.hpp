@@ -633,6 +633,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     uint32_t nr1 = rec_word(A.srec, sfirst, shi_), nr2 = rec_word(A.srec, sfirst + NW, shi_);
     for (int64_t sl = sfirst; sl < shi_; sl += 2 * NW) {
+        progress_prio(sl - slo_, shi_ - slo_);
         const int64_t sl2 = sl + NW;
         const bool two = sl2 < shi_;
         const SliceRec r1 = rec_from(nr1), r2 = rec_from(nr2);
