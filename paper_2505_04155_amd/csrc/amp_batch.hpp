@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const T
 
 __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    spmv_stage<NTS>(d.c, d.A, d.B, t_.st + si, t_.st + so, wg, Early{t_.part_pre, t_.g, nullptr, 0u});
+    spmv_stage<NTS, false>(d.c, d.A, d.B, t_.st + si, t_.st + so, wg, Early{t_.part_pre, t_.g, nullptr, 0u});
 }
 
 __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Task *tasks, int si, int so) {

@@ -592,7 +592,9 @@ __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part
 // k_spmv: p = z + beta p_{k-1} (u_z), q = A p (u_r), gamma = q^T p
 // ----------------------------------------------------------------------------
 
-template <int UZ, int UR, bool DIFF, bool FIRST, int BS>
+// PRIO: issue priority by progress (progress_prio); off where the
+// work-groups sharing a CU belong to different systems with unequal work.
+template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -633,7 +635,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     uint32_t nr1 = rec_word(A.srec, sfirst, shi_), nr2 = rec_word(A.srec, sfirst + NW, shi_);
     for (int64_t sl = sfirst; sl < shi_; sl += 2 * NW) {
-        progress_prio(sl - slo_, shi_ - slo_);
+        if (PRIO) progress_prio(sl - slo_, shi_ - slo_);
         const int64_t sl2 = sl + NW;
         const bool two = sl2 < shi_;
         const SliceRec r1 = rec_from(nr1), r2 = rec_from(nr2);
@@ -665,7 +667,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     }
 }
 
-template <int BS>
+template <int BS, bool PRIO = true>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg, const Early &e) {
     __shared__ St s;
@@ -705,11 +707,11 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
 #define AMP_SP(UZ, UR, DF)                                                                                       \
     do {                                                                                                        \
         if (first)                                                                                              \
-            spmv_p_body<UZ, UR, DF, true, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, \
-                                          gam, mp);                                                             \
+            spmv_p_body<UZ, UR, DF, true, BS, PRIO>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], \
+                                                beta, gam, mp);                                                 \
         else                                                                                                    \
-            spmv_p_body<UZ, UR, DF, false, BS>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],       \
-                                           beta, gam, mp);                                                      \
+            spmv_p_body<UZ, UR, DF, false, BS, PRIO>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],                \
+                                                 B.q[pslot(UR)], beta, gam, mp);                                \
     } while (0)
     if (ur == 64) {
         if (uz == 64) AMP_SP(64, 64, false);
