@@ -70,6 +70,14 @@ design notes):
   b - A x is formed in FP64.  If it is above tol ||b||, r is replaced by it
   and the iteration continues (at most ``max_replacements`` times).  With
   ``verify=False`` the model stops exactly as Alg. 3 does.
+* Residual replacement (mentioned in Sections 1.1 and 3.1 as a way to keep
+  the recurrence residual close to the true one): at the iteration k where
+  u_r first drops to FP32, r_k is not the FP64 recurrence residual rounded
+  to FP32 but the true residual fl32(b - A x_k), formed in FP64
+  (``rr_switch=True``, default).  delta_k keeps the recurrence value that
+  drove the decision; z_k, rho_k and everything after use the replaced
+  r_k.  ``rr_period = K > 0`` also replaces r by fl_{u_r}(b - A x) after
+  every K-th iteration.
 * A pre-loop test returns 0 iterations when ||r_0|| <= tol ||b||.
 """
 
@@ -116,6 +124,7 @@ class AmpOptions:
     verify: bool = True
     max_replacements: int = 3
     rr_period: int = 0          # 0: no periodic replacement
+    rr_switch: bool = True      # replace r by fl32(b - A x) at the u_r switch
     spmv32: str = "diff"        # diff | plain
 
 
@@ -414,7 +423,11 @@ def amp_pcg(A, b, x0=None, tol=1e-10, maxit=5000, M=None, opt: AmpOptions | None
         maxr = float(np.max(np.abs(r.astype(np.float64))))   # max|r_k| as stored
         if ur != ur_prev:
             res.k_r32 = k
-            r = fl(r, ur)              # r_k now held in u_{r,k}
+            if opt.rr_switch:          # r_k replaced by the true residual, held in u_{r,k}
+                r = fl(b - A @ x, ur)
+                replacements += 1
+            else:                      # r_k now held in u_{r,k}
+                r = fl(r, ur)
         res.uz.append(uz)
         res.ur.append(ur)
         cr = NP[ur]
