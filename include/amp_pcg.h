@@ -120,6 +120,10 @@ typedef struct {
     double *delta_history;  /* nullable device buffer, maxit+1 doubles: ||r_k|| for k = 0..iters */
     int32_t *prec_history;  /* nullable device buffer, maxit ints: u_z | (u_r << 8) of iteration k */
     double *scalar_history; /* nullable device buffer, 4*maxit doubles: omega_k, rho_k, gamma_k, alpha_k */
+    int rr_switch;          /* 1 (default): at the iteration whose u_r first drops to FP32, r is replaced
+                               by fl32(b - A x), formed with FP64 values and accumulation (residual
+                               replacement, Sections 1.1 and 3.1), instead of the recurrence residual
+                               rounded to FP32; counted in n_replacements. 0: rounded recurrence residual */
 } amp_options;
 
 typedef struct {

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("batch", ctypes.c_int), ("group_rows", ctypes.c_int), ("graph", ctypes.c_int),
                 ("solo_rows", ctypes.c_int), ("spmv_timing", ctypes.c_int), ("defer_x", ctypes.c_int),
                 ("delta_history", ctypes.c_void_p),
-                ("prec_history", ctypes.c_void_p), ("scalar_history", ctypes.c_void_p)]
+                ("prec_history", ctypes.c_void_p), ("scalar_history", ctypes.c_void_p),
+                ("rr_switch", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):

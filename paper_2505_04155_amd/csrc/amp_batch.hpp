@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(NTS) k_batch_init(const SysDesc *sd, const Tas
 
 __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    precond_stage(d.c, d.B, d.A.np, t_.st + si, t_.st + so, wg, Early{t_.part_res, t_.g, t_.ring, 0u});
+    precond_stage(d.c, d.A, d.B, d.A.np, t_.st + si, t_.st + so, wg, Early{t_.part_res, t_.g, t_.ring, 0u});
 }
 
 __global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(NT) k_batch_gather(const SysDesc *sd, int nsys
 // The small systems: one work-group each runs its whole solve.
 __global__ void __launch_bounds__(NT) k_batch_solo(const SysDesc *sd, const int *list, int cap) {
     const SysDesc &d = sd[list[blockIdx.x]];
-    solo_solve(d.c, d.A, d.B, d.st, cap);
+    solo_solve<false>(d.c, d.A, d.B, d.st, cap);
 }
 
 __global__ void __launch_bounds__(NT) k_batch_copy_out(const SysDesc *sd, const Task *tasks) {

@@ -67,7 +67,8 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
 // First kernel of a Chebyshev application inside the iteration: controller
 // prologue (like k_precond), then v.  standalone != 0 skips the prologue and
 // uses the incoming state's precisions and omega as given.
-__global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int standalone, const St *in, St *out) {
+__global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int standalone, const St *in, St *out,
+                                                  Sell A) {
     __shared__ St s;
     const Wg wg = grid_wg();
     ResIn ri;
@@ -87,7 +88,13 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
             return;
         }
     }
-    const int rs = s.r_store, ur = s.ur, uz = s.uz;
+    int rs = s.r_store;
+    const int ur = s.ur, uz = s.uz;
+    if (!standalone && switch_replaces(c, s)) {   // r_k := fl32(b - A x_k)
+        switch_replace(A, B, s, P.np, wg);
+        rs = 32;
+        if (threadIdx.x == 0) s.n_repl += 1;
+    }
 #define AMP_CV(RS, UR, UZ) cheb_v_body<RS, UR, UZ>(s, B, P, wg)
 #define AMP_CV_Z(RS, UR)                  \
     if (uz == 64) AMP_CV(RS, UR, 64);       \

@@ -358,7 +358,10 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
         term = (3.0 + c.C) * ring[(t - 1) % kRing] + (2.0 + c.C) * dt;
     }
     if (threadIdx.x == 0) {
-        double eta_pre = INFINITY;   // eta_delay's value before the window is complete
+        // the parallel form covers windows of at most WAVE terms; longer ones
+        // (d >= WAVE) and the other indicators are evaluated serially by the
+        // controller itself (a null eta_pre)
+        double eta_pre = INFINITY;
         if (par) {
             double sum = 0.0;
             for (int j = 0; j <= c.d; ++j) sum = sum + readlane_f64(term, j);
@@ -374,7 +377,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
             rk = cs.iters;
             rv = d;
-            finish_iteration(cs, c, ring, d, m, &eta_pre);
+            finish_iteration(cs, c, ring, d, m, par ? &eta_pre : nullptr);
         } else if (cs.kind == RES_INIT) {
             cs.bnorm = sqrt(b);
             cs.tol_b = c.tol * cs.bnorm;
@@ -386,7 +389,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             rv = cs.delta;
             if (cs.delta <= cs.tol_b) cs.status = CONVERGED;
             else if (c.maxit <= 0) cs.status = MAXIT;
-            else prepare_iteration(cs, c, ring, 0, &eta_pre);
+            else prepare_iteration(cs, c, ring, 0, par ? &eta_pre : nullptr);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
             cs.true_res = sqrt(a);
             if (cs.true_res <= cs.tol_b) {
@@ -403,7 +406,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
                     cs.status = MAXIT;
                 } else {
                     cs.status = RUNNING;
-                    prepare_iteration(cs, c, ring, cs.iters, &eta_pre);
+                    prepare_iteration(cs, c, ring, cs.iters, par ? &eta_pre : nullptr);
                 }
             }
         }
@@ -516,8 +519,55 @@ __device__ __forceinline__ void convert_p(const Bufs &B, int pb, int64_t np, Wg 
     }
 }
 
-__device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64_t np, const St *in, St *out,
-                                              Wg wg, const Early &e) {
+// Residual replacement at the u_r switch (the alternative to carrying the
+// recurrence residual that Sections 1.1 and 3.1 mention): on the iteration
+// whose u_r first drops to FP32, r_k is fl32(b - A x_k), formed with the
+// FP64 values and FP64 accumulation, instead of the recurrence residual
+// rounded to FP32.  delta_k keeps the recurrence value that drove the
+// decision.  Rows of this work-group's element range [lo, hi) (whole
+// slices: lo and hi are multiples of NT VEC), one slice per wave; x_k at a
+// gathered column includes a pending deferred step alpha_{k-1} p_{k-1},
+// rounded exactly as stop_flush applies it.
+template <int PU>
+__device__ __forceinline__ void switch_replace_body(const Sell &A, const Bufs &B, const St &s, int64_t lo,
+                                                    int64_t hi) {
+    typedef typename Prec<PU == 0 ? 64 : PU>::T TP;
+    const TP *pp = (const TP *)B.p[pslot(PU == 0 ? 64 : PU)][s.x_pb];
+    const double a = s.x_alpha;
+    const double *x = B.x;
+    float *r = (float *)B.r[1];
+    auto xval = [&](int64_t c) -> double {
+        if (PU == 0) return x[c];
+        return x[c] + a * (double)pp[c];
+    };
+    const int64_t s0 = lo / SLICE, s1 = (hi / SLICE < A.nslices) ? hi / SLICE : A.nslices;
+    const int lane = threadIdx.x % WAVE;
+    for (int64_t sl = s0 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < s1; sl += NT / WAVE) {
+        const SliceRec rec_ = A.srec[sl];
+        const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
+        double ax = 0.0;
+        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, rec_.width, xval); });
+        r[row] = (float)(B.b[row] - ax);
+    }
+}
+
+__device__ __forceinline__ void switch_replace(const Sell &A, const Bufs &B, const St &s, int64_t np, Wg wg) {
+    int64_t lo, hi;
+    block_range(np, (int64_t)NT * VEC, wg.lb, wg.G, lo, hi);
+    if (!s.xp) switch_replace_body<0>(A, B, s, lo, hi);
+    else if (s.x_pu == 64) switch_replace_body<64>(A, B, s, lo, hi);
+    else if (s.x_pu == 32) switch_replace_body<32>(A, B, s, lo, hi);
+    else switch_replace_body<16>(A, B, s, lo, hi);
+    __syncthreads();   // the rows' residuals are read by other threads of the work-group
+}
+
+// Whether this iteration replaces r (its u_r has just dropped to FP32).
+__device__ __forceinline__ bool switch_replaces(const Cfg &c, const St &s) {
+    return c.rr_switch && s.r_store == 64 && s.ur == 32;
+}
+
+__device__ __forceinline__ void precond_stage(const Cfg &c, const Sell &A, const Bufs &B, int64_t np, const St *in,
+                                              St *out, Wg wg, const Early &e) {
     __shared__ St s;
     ResIn ri;
     res_loads(e, ri);
@@ -551,7 +601,14 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
         store_state(s, out, wg);
         return;
     }
-    const int rs = s.r_store, ur = s.ur, uz = s.uz;
+    int rs = s.r_store;
+    const int ur = s.ur, uz = s.uz;
+    if (switch_replaces(c, s)) {   // r_k := fl32(b - A x_k); the preloaded chunks are not used
+        switch_replace(A, B, s, np, wg);
+        rs = 32;
+        pre.uz = 0;
+        if (threadIdx.x == 0) s.n_repl += 1;
+    }
     double rho = 0.0, mz = 0.0;
 #define AMP_PC(RS, UR, UZ) precond_body<RS, UR, UZ>(s, B, np, wg, pre, rho, mz)
 #define AMP_PC_Z(RS, UR)                  \
@@ -583,8 +640,8 @@ __device__ __forceinline__ void precond_stage(const Cfg &c, const Bufs &B, int64
 }
 
 __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part, int gpart, int grid,
-                                                const double *ring, Cfg c, Bufs B, int64_t np, St *out) {
-    precond_stage(c, B, np, in, out, launch_wg(grid), Early{part, gpart, ring,
+                                                const double *ring, Cfg c, Bufs B, int64_t np, St *out, Sell A) {
+    precond_stage(c, A, B, np, in, out, launch_wg(grid), Early{part, gpart, ring,
                   touch_args<32 + sizeof(Cfg) + sizeof(Bufs)>()});
 }
 
@@ -1023,12 +1080,15 @@ __global__ void __launch_bounds__(NTS) k_true_res(Cfg c, Sell A, Bufs B, int mod
 // (converged, maxit, breakdown) or after `cap` passes; the last state is
 // copied to st[ST_FIN] (with status MAXIT if the cap was reached while
 // running).
+// PRIO: issue priority by progress in the product stage (off where the
+// work-groups sharing a CU belong to different systems).
+template <bool PRIO = true>
 __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bufs &B, St *st, int cap) {
     const Wg wg{0, 1};
     __shared__ int status;
     int in = ST_INIT, last = ST_INIT;
     for (int pass = 0; pass < cap; ++pass) {
-        precond_stage(c, B, A.np, st + in, st + ST_PRE, wg, res_early(c, B));
+        precond_stage(c, A, B, A.np, st + in, st + ST_PRE, wg, res_early(c, B));
         __syncthreads();
         if (threadIdx.x == 0) status = st[ST_PRE].status;
         __syncthreads();
@@ -1040,7 +1100,7 @@ __device__ __forceinline__ void solo_solve(const Cfg &c, const Sell &A, const Bu
             continue;
         }
         if (status != RUNNING) break;
-        spmv_stage<NT>(c, A, B, st + ST_PRE, st + ST_SPMV, wg, pre_early(c, B));
+        spmv_stage<NT, PRIO>(c, A, B, st + ST_PRE, st + ST_SPMV, wg, pre_early(c, B));
         __syncthreads();
         update_stage(c, B, A.np, st + ST_SPMV, st + ST_RES, wg, spmv_early(c, B));
         __syncthreads();

@@ -687,6 +687,7 @@ extern "C" void amp_options_default(amp_options *o) {
     o->solo_rows = 0;
     o->spmv_timing = 0;
     o->defer_x = 1;
+    o->rr_switch = 1;
     o->delta_history = nullptr;
     o->prec_history = nullptr;
     o->scalar_history = nullptr;
@@ -739,6 +740,7 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.diff = o.spmv32_diff ? 1 : 0;
     c.rr_period = o.rr_period;
     c.defer_x = (o.defer_x && o.rr_period == 0) ? 1 : 0;   // a periodic replacement reads x
+    c.rr_switch = o.rr_switch ? 1 : 0;
     c.extra16 = M ? M->extra16 : 0;
     c.g_stream = A ? grid_stream(A->np) : 1;
     c.g_slice = A ? grid_slices(A->nslices) : 1;
@@ -797,7 +799,7 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     Work &w = d.A->w;
     const Cheb P = d.M->cheb();
     const int m = d.M->degree;
-    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, P, standalone, in, &w.st[ST_PREI]);
+    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, P, standalone, in, &w.st[ST_PREI], d.S);
     if (m == 1) {
         k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, P, &w.st[ST_PREI], out);
         return;
@@ -816,7 +818,7 @@ static amp_status enqueue_iterations(Driver &d, int count) {
             enqueue_chebyshev(d, 0, d.in, &w.st[ST_PRE]);
         } else {
             k_precond<<<d.gs, NT, 0, d.st>>>(d.in, d.B.part_res, std::max(d.cfg.g_stream, d.cfg.g_slice), d.gs,
-                                             d.cfg.ring, d.cfg, d.B, d.A->np, &w.st[ST_PRE]);
+                                             d.cfg.ring, d.cfg, d.B, d.A->np, &w.st[ST_PRE], d.S);
         }
         if (d.timing && d.launches < w.tcap) {
             d.cfg.spmv_iter = w.titer;

@@ -154,6 +154,60 @@ def test_amp64_vs_fp64_oracle(amp, case):
     assert _rel(x, xo) <= 1e-5
 
 
+@pytest.mark.parametrize("d", [63, 64, 80, 100])
+def test_long_delay_window_switches_like_the_replay(amp, d):
+    # delay windows of at least a wave's width take the controller's serial
+    # evaluation of eq. (eta_k); the switch must still happen where the
+    # selector replayed over the GPU's own history puts it, and near the model's
+    _say(f"long delay window d={d}")
+    A, b = CASES["blocky32"]()
+    x, info = _gpu_solve(amp, A, b, "amp64", d=d)
+    ref = am.amp_pcg(A.to_scipy(), b, tol=1e-10, maxit=5000, opt=am.options("amp64", d=d))
+    _say(f"  gpu k_r32 {info['k_r32']} iters {info['iters']}; model k_r32 {ref.k_r32} iters {ref.iters}")
+    assert info["status"] == 0
+    # d <= 80 switches on this system; with d = 100 the window's sum keeps eta
+    # above tol ||b|| to the end, for the model as for the GPU
+    assert (info["k_r32"] > d) if d <= 80 else (info["k_r32"] == ref.k_r32 == -1)
+    kz32, kz16, kr = am.replay_switches(list(info["delta"][:info["iters"]]), info["bnorm"], 1e-10,
+                                        am.options("amp64", d=d))
+    assert (kz32, kz16, kr) == (info["k_z32"], info["k_z16"], info["k_r32"])
+    assert abs(info["k_r32"] - ref.k_r32) <= 2
+    assert info["relres_true"] <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["poisson64", "blocky32"])
+@pytest.mark.parametrize("rr_switch", [0, 1])
+def test_switch_replacement_matches_model(amp, case, rr_switch):
+    # at the u_r switch r is replaced by fl32(b - A x) (rr_switch = 1, the
+    # default) or rounded from the recurrence (0); either way the GPU follows
+    # the model with the same option, and the replacement is counted once
+    _say(f"switch replacement {case} rr_switch={rr_switch}")
+    A, b = CASES[case]()
+    ref = am.amp_pcg(A.to_scipy(), b, tol=1e-10, maxit=5000, opt=am.options("amp16", rr_switch=bool(rr_switch)))
+    x, info = _gpu_solve(amp, A, b, "amp16", rr_switch=rr_switch)
+    _say(f"  gpu iters {info['iters']} repl {info['replacements']}; model iters {ref.iters} repl {ref.replacements}")
+    assert info["status"] == 0 and ref.status == 0 and info["k_r32"] >= 0
+    assert abs(info["k_r32"] - ref.k_r32) <= 2
+    assert abs(info["iters"] - ref.iters) <= max(2, math.ceil(0.02 * ref.iters))
+    assert info["replacements"] == ref.replacements
+    assert info["replacements"] >= rr_switch
+    assert info["relres_true"] <= 1e-10
+    assert _rel(x, ref.x) <= 1e-7
+
+
+def test_switch_replacement_is_the_true_residual(amp):
+    # with u_r fixed to FP32 from the first iteration the switch happens at
+    # k = 0, where fl32(b - A x0) is exactly the FP64 r0 rounded: both options
+    # give bitwise the same solve
+    _say("switch replacement at k = 0")
+    A, b = CASES["blocky24"]()
+    x1, i1 = _gpu_solve(amp, A, b, "amp16", eta="fixed32", rr_switch=1)
+    x0, i0 = _gpu_solve(amp, A, b, "amp16", eta="fixed32", rr_switch=0)
+    assert i1["k_r32"] == 0 and i0["k_r32"] == 0
+    assert i1["iters"] == i0["iters"] and np.array_equal(x1, x0)
+    assert i1["replacements"] == i0["replacements"] + 1
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_zero_rhs_and_exact_start(amp):
