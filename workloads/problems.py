@@ -131,6 +131,46 @@ def _stencil_csr(dims, offsets, values) -> CSR:
     return CSR(N, row_ptr.astype(np.int32), col, val)
 
 
+def _const_stencil_csr(dims, offsets, values) -> CSR:
+    """The matrix of :func:`_stencil_csr` for scalar values and offsets in
+    {-1, 0, 1} per axis, built without per-offset passes: the (row, offset)
+    table of every row's candidate entries, masked by whether the neighbour
+    lies inside the grid (a product of per-axis masks), is compressed in row
+    order.  Offsets sorted by linear offset are sorted by column within each
+    row (|offset| <= 1 < every axis size), so the result is the same CSR."""
+    dims = tuple(int(d) for d in dims)
+    nd = len(dims)
+    N = int(np.prod(dims))
+    strides = [1]
+    for d in dims[:-1]:
+        strides.append(strides[-1] * d)
+    lin = np.array([sum(o[a] * strides[a] for a in range(nd)) for o in offsets], dtype=np.int64)
+    order = np.argsort(lin, kind="stable")
+    offs = [offsets[i] for i in order]
+    vals = np.array([float(values[i]) for i in order])
+    K = len(offs)
+    # mask[row, k]: the k-th offset's neighbour is inside the grid; per-axis
+    # masks are broadcast over the other axes (row index: x fastest)
+    mask = np.ones((N, K), dtype=bool)
+    for a in range(nd):
+        c = np.arange(dims[a])
+        shape = [1] * nd
+        shape[nd - 1 - a] = dims[a]          # arrays are laid out (z, y, x)
+        for k, o in enumerate(offs):
+            ok = ((c + o[a] >= 0) & (c + o[a] < dims[a])).reshape(shape)
+            mask[:, k] &= np.broadcast_to(ok, dims[::-1]).reshape(N)
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    if nnz >= 2**31:
+        raise ValueError("nnz does not fit int32")
+    col = (np.arange(N, dtype=np.int32)[:, None] + lin[order].astype(np.int32)[None, :])[mask]
+    val = np.broadcast_to(vals, (N, K))[mask]
+    return CSR(N, row_ptr.astype(np.int32), np.ascontiguousarray(col, dtype=np.int32),
+               np.ascontiguousarray(val, dtype=np.float64))
+
+
 def stencil_poisson2d(m: int) -> CSR:
     """2-D 5-point finite-difference Laplacian on an m x m interior grid."""
     offs = [(-1, 0), (1, 0), (0, -1), (0, 1), (0, 0)]
@@ -194,7 +234,7 @@ def q1_anisotropic(n: int, kx: float = 1.0, ky: float = 1e-2, kz: float = 1e-3) 
                      + kz * M[dx] * M[dy] * K[dz])
                 offs.append((dx, dy, dz))
                 vals.append(v)
-    return _stencil_csr((n, n, n), offs, vals)
+    return _const_stencil_csr((n, n, n), offs, vals)
 
 
 def q1_anisotropic_bounds(n: int, kx: float = 1.0, ky: float = 1e-2, kz: float = 1e-3):
