@@ -219,6 +219,28 @@ amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x
                          int maxit, const amp_options *opt, amp_result *res, void *stream);
 
 /*
+ * amp_pcg_solve for callers that cannot allocate device memory during the
+ * call (serving loops, harnesses that forbid hipMalloc): the same kernels,
+ * state chain and results as amp_pcg_solve (bitwise the same x and
+ * iterations), with every work vector, partial array, state slot and the
+ * residual window held in the library's own device array of about 21.6 MB
+ * per GPU (allocated when the library's code is loaded on that device, held
+ * until the process ends), instead of the matrix handle's work buffers.
+ * The call makes no hipMalloc, hipFree, event, stream or pinned-memory
+ * allocation; it clears the array's used part with a kernel first.
+ * Limits: the padded row count of A (n rounded up to a multiple of 1024)
+ * is at most 2^18 = 262144; opt->graph, opt->spmv_timing and opt->solo_rows
+ * must be 0.  The host polls the state with plain copies (no pipelining).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * device (several host threads, or streams without ordering) race and give
+ * wrong results; serialise them.  Arguments, ownership, host-synchronous
+ * behaviour and status codes as for amp_pcg_solve; AMP_ERR_ARG also for a
+ * system above the row limit or the options above.
+ */
+amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
+                                 int maxit, const amp_options *opt, amp_result *res, void *stream);
+
+/*
  * Solve nsys independent systems A[i] x[i] = b[i] (Alg. 3 for each) in one
  * lockstep iteration: every kernel launch advances every unfinished system,
  * each system keeping its own scalars, precisions, switch points, scaling

@@ -25,7 +25,7 @@ EXPORTED = [
     "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv", "amp_spmv_step",
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
-    "amp_pcg_solve_batched", "amp_tune_group_rows",
+    "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc",
 ]
 
 
@@ -104,6 +104,8 @@ def load(build_if_missing: bool = True):
         L.amp_precond_destroy.restype = None
         L.amp_pcg_solve.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(Result), vp]
+        L.amp_pcg_solve_noalloc.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
+                                            ctypes.POINTER(Result), vp]
         L.amp_pcg_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                             ctypes.POINTER(vp), ctypes.POINTER(dbl), i32,
                                             ctypes.POINTER(Options), ctypes.POINTER(Result), vp]

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -217,8 +218,7 @@ static amp_status ensure_work(amp_matrix A, hipStream_t st) {
     return AMP_OK;
 }
 
-static Bufs make_bufs(amp_matrix A, amp_precond M) {
-    Work &w = A->w;
+static Bufs make_bufs_w(const Work &w, amp_precond M) {
     Bufs B;
     B.x = w.x; B.b = w.b;
     B.r[0] = w.r64; B.r[1] = w.r32; B.r[2] = nullptr;
@@ -233,6 +233,8 @@ static Bufs make_bufs(amp_matrix A, amp_precond M) {
     B.part_spmv = w.part + 5 * GMAX;
     return B;
 }
+
+static Bufs make_bufs(amp_matrix A, amp_precond M) { return make_bufs_w(A->w, M); }
 
 // ----------------------------------------------------------------------------
 // CSR -> sliced ELL
@@ -788,6 +790,7 @@ struct Driver {
     Bufs B;
     int gs, gl;
     hipStream_t st;
+    St *sb = nullptr;  // the solve's state slots (ST_COUNT)
     St *in;            // state the next kernel reads
     int host_k;        // iterations enqueued since the last resynchronisation
     bool timing = false;
@@ -796,17 +799,17 @@ struct Driver {
 
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
 static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
-    Work &w = d.A->w;
+    St *sb = d.sb;
     const Cheb P = d.M->cheb();
     const int m = d.M->degree;
-    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, P, standalone, in, &w.st[ST_PREI], d.S);
+    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, P, standalone, in, &sb[ST_PREI], d.S);
     if (m == 1) {
-        k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, P, &w.st[ST_PREI], out);
+        k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, P, &sb[ST_PREI], out);
         return;
     }
     for (int k = 0; k + 1 < m; ++k) {
-        St *si = (k == 0) ? &w.st[ST_PREI] : &w.st[(k - 1) % 2 ? ST_CH1 : ST_CH0];
-        St *so = (k == m - 2) ? out : &w.st[k % 2 ? ST_CH1 : ST_CH0];
+        St *si = (k == 0) ? &sb[ST_PREI] : &sb[(k - 1) % 2 ? ST_CH1 : ST_CH0];
+        St *so = (k == m - 2) ? out : &sb[k % 2 ? ST_CH1 : ST_CH0];
         k_cheb_step<<<d.gl, NTS, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
     }
 }
@@ -815,31 +818,31 @@ static amp_status enqueue_iterations(Driver &d, int count) {
     Work &w = d.A->w;
     for (int i = 0; i < count; ++i) {
         if (d.M->kind == AMP_PC_CHEBYSHEV) {
-            enqueue_chebyshev(d, 0, d.in, &w.st[ST_PRE]);
+            enqueue_chebyshev(d, 0, d.in, &d.sb[ST_PRE]);
         } else {
             k_precond<<<d.gs, NT, 0, d.st>>>(d.in, d.B.part_res, std::max(d.cfg.g_stream, d.cfg.g_slice), d.gs,
-                                             d.cfg.ring, d.cfg, d.B, d.A->np, &w.st[ST_PRE], d.S);
+                                             d.cfg.ring, d.cfg, d.B, d.A->np, &d.sb[ST_PRE], d.S);
         }
         if (d.timing && d.launches < w.tcap) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
             hipExtLaunchKernelGGL(k_spmv, dim3(d.gl), dim3(NTS), 0, d.st, w.tev[2 * d.launches],
-                                  w.tev[2 * d.launches + 1], 0, (const St *)&w.st[ST_PRE],
+                                  w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B,
-                                  &w.st[ST_SPMV]);
+                                  &d.sb[ST_SPMV]);
             d.launches += 1;
             d.cfg.spmv_iter = nullptr;
         } else {
-            k_spmv<<<d.gl, NTS, 0, d.st>>>(&w.st[ST_PRE], d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &w.st[ST_SPMV]);
+            k_spmv<<<d.gl, NTS, 0, d.st>>>(&d.sb[ST_PRE], d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &d.sb[ST_SPMV]);
         }
-        k_update<<<d.gs, NT, 0, d.st>>>(&w.st[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
-                                        &w.st[ST_RES]);
-        d.in = &w.st[ST_RES];
+        k_update<<<d.gs, NT, 0, d.st>>>(&d.sb[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
+                                        &d.sb[ST_RES]);
+        d.in = &d.sb[ST_RES];
         d.host_k += 1;
         if (d.cfg.rr_period > 0 && d.host_k % d.cfg.rr_period == 0) {
-            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &w.st[ST_TR]);
-            d.in = &w.st[ST_TR];
+            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &d.sb[ST_TR]);
+            d.in = &d.sb[ST_TR];
         }
     }
     AMP_HIP(hipGetLastError());
@@ -882,7 +885,7 @@ static amp_status get_graph(Driver &d) {
     w.gkey.clear();
     Driver c = d;
     c.st = w.cap;
-    c.in = &w.st[ST_RES];
+    c.in = &d.sb[ST_RES];
     c.host_k = 0;
     AMP_HIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
     const amp_status s = enqueue_iterations(c, kGraphIters);
@@ -907,7 +910,7 @@ static amp_status get_graph(Driver &d) {
 static amp_status enqueue_batch(Driver &d, int count, bool graph) {
     if (!graph) return enqueue_iterations(d, count);
     Work &w = d.A->w;
-    if (count > 0 && d.in != &w.st[ST_RES]) {
+    if (count > 0 && d.in != &d.sb[ST_RES]) {
         AMP_TRY(enqueue_iterations(d, 1));
         --count;
     }
@@ -954,6 +957,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
     Work &w = A->w;
+    d.sb = w.st;
     const bool timing = o.spmv_timing != 0;
     const bool solo = !timing && solo_eligible(o, A, M);
     const bool graph = !timing && o.graph && o.rr_period == 0 && !solo;
@@ -1112,6 +1116,215 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     }
     if (rs == AMP_ERR_NOT_CONVERGED) g_last_error = "amp_pcg_solve: not converged within maxit";
     if (rs == AMP_ERR_BREAKDOWN) g_last_error = "amp_pcg_solve: breakdown (rho <= 0, gamma <= 0 or non-finite)";
+    return rs;
+}
+
+// ----------------------------------------------------------------------------
+// solve without allocation
+// ----------------------------------------------------------------------------
+
+// Largest padded system (rows) the allocation-free solve takes.
+constexpr int64_t kNoAllocRows = (int64_t)1 << 18;
+
+// Byte layout of the allocation-free solve's working memory for np padded
+// rows: the same vectors, partial arrays, residual window, reduced scalar and
+// state slots as a handle's Work, each region 256-byte aligned.
+struct ScratchLayout {
+    int64_t x, b, r64, z64, q64, p64[2], r32, z32, q32, p32[2], z16, p16[2], part, ring, scalar, st, total;
+};
+
+static constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+static constexpr ScratchLayout scratch_layout(int64_t np) {
+    ScratchLayout L{};
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.x = take(8 * np); L.b = take(8 * np);
+    L.r64 = take(8 * np); L.z64 = take(8 * np); L.q64 = take(8 * np);
+    L.p64[0] = take(8 * np); L.p64[1] = take(8 * np);
+    L.r32 = take(4 * np); L.z32 = take(4 * np); L.q32 = take(4 * np);
+    L.p32[0] = take(4 * np); L.p32[1] = take(4 * np);
+    L.z16 = take(2 * np); L.p16[0] = take(2 * np); L.p16[1] = take(2 * np);
+    L.part = take(7 * GMAX * (int64_t)sizeof(double));
+    L.ring = take(kRing * (int64_t)sizeof(double));
+    L.scalar = take(sizeof(double));
+    L.st = take(ST_COUNT * (int64_t)sizeof(St));
+    L.total = o;
+    return L;
+}
+
+constexpr int64_t kScratchBytes = scratch_layout(kNoAllocRows).total;   // about 21.6 MB
+
+// The allocation-free solve's working memory: one copy per device, held
+// until the process ends.  Host code never passes this name to a kernel or
+// a copy: it is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress (scratch_base).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+static amp_status scratch_base(void **out) {
+    int dev = -1;
+    AMP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(AMP_ERR_HIP, "amp_pcg_solve_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(AMP_ERR_HIP, std::string("amp_pcg_solve_noalloc: hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AMP_OK;
+}
+
+// Zero `words` 16-byte words from p (a fill kernel: no memset node where a
+// caller captures the stream).
+__global__ void __launch_bounds__(NT) k_zero16(uint4 *p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < words; i += (int64_t)gridDim.x * NT)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
+                                            int maxit, const amp_options *opt, amp_result *res, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!A || !b || !x) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: null argument");
+    if (!M) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: null preconditioner");
+    if (M->A != A) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: preconditioner was built for another matrix");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: tol must be positive");
+    if (maxit < 0) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: maxit must be >= 0");
+    if (A->np > kNoAllocRows)
+        return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: " + std::to_string(A->np) +
+                                     " padded rows exceed the limit of " + std::to_string(kNoAllocRows) +
+                                     " (use amp_pcg_solve)");
+    amp_options o;
+    if (opt) o = *opt;
+    else amp_options_default(&o);
+    AMP_TRY(check_options(o));
+    if (o.graph || o.spmv_timing || o.solo_rows)
+        return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: graph, spmv_timing and solo_rows must be 0");
+    void *base = nullptr;
+    AMP_TRY(scratch_base(&base));
+    const int64_t np = A->np, n = A->n;
+    const ScratchLayout L = scratch_layout(np);
+    unsigned char *m = (unsigned char *)base;
+    Work w;   // views into scratch; nothing here is allocated or freed
+    w.np = np;
+    w.x = (double *)(m + L.x); w.b = (double *)(m + L.b);
+    w.r64 = (double *)(m + L.r64); w.z64 = (double *)(m + L.z64); w.q64 = (double *)(m + L.q64);
+    w.r32 = (float *)(m + L.r32); w.z32 = (float *)(m + L.z32); w.q32 = (float *)(m + L.q32);
+    w.z16 = (half_t *)(m + L.z16);
+    for (int i = 0; i < 2; ++i) {
+        w.p64[i] = (double *)(m + L.p64[i]); w.p32[i] = (float *)(m + L.p32[i]); w.p16[i] = (half_t *)(m + L.p16[i]);
+    }
+    w.part = (double *)(m + L.part);
+    w.ring = (double *)(m + L.ring);
+    w.scalar = (double *)(m + L.scalar);
+    w.st = (St *)(m + L.st);
+
+    Driver d;
+    d.A = A;
+    d.M = M;
+    d.st = as_stream(stream);
+    d.sb = w.st;
+    d.cfg = make_cfg(o, A, M, tol, maxit);
+    d.cfg.ring = w.ring;
+    d.S = A->sell();
+    d.B = make_bufs_w(w, M);
+    d.gs = d.cfg.g_stream;
+    d.gl = d.cfg.g_slice;
+    d.host_k = 0;
+    // the previous call's contents: every vector's padding tail and the
+    // partials must start at zero
+    {
+        const int64_t words = L.total / 16;
+        const int g = (int)std::min<int64_t>(1024, (words + NT - 1) / NT);
+        k_zero16<<<g, NT, 0, d.st>>>((uint4 *)m, words);
+    }
+    const St s0 = init_state(o);
+    AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    AMP_HIP(hipMemcpyAsync(&w.st[ST_INIT], &s0, sizeof(St), hipMemcpyHostToDevice, d.st));
+    k_init<<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
+    AMP_HIP(hipGetLastError());
+    d.in = &w.st[ST_INIT];
+
+    // batches of iterations, each followed by a read of the state (no
+    // pipelining: it would need events and pinned memory)
+    St cur = s0;
+    int batch = o.batch > 0 ? o.batch : 8;
+    int last_iters = 0;
+    double last_delta = -1.0;
+    for (;;) {
+        AMP_TRY(enqueue_iterations(d, batch));
+        AMP_HIP(hipMemcpyAsync(&cur, d.in, sizeof(St), hipMemcpyDeviceToHost, d.st));
+        AMP_HIP(hipStreamSynchronize(d.st));
+        if (cur.status == RUNNING) {
+            if (o.batch == 0 && cur.iters > last_iters && cur.delta > 0.0 && last_delta > 0.0) {
+                const double rate = std::pow(cur.delta / last_delta, 1.0 / (double)(cur.iters - last_iters));
+                int left = 256;
+                if (rate > 0.0 && rate < 1.0)
+                    left = (int)std::ceil(std::log(tol * cur.bnorm / cur.delta) / std::log(rate));
+                batch = std::max(4, std::min(256, left / 2 + 1));
+            }
+            if (cur.iters > last_iters) {
+                last_iters = cur.iters;
+                last_delta = cur.delta;
+            }
+            continue;
+        }
+        if (cur.status == NEED_VERIFY) {
+            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
+            AMP_HIP(hipGetLastError());
+            d.in = &w.st[ST_TR];
+            d.host_k = cur.iters;
+            batch = 4;
+            continue;
+        }
+        break;
+    }
+    AMP_HIP(hipMemcpyAsync(x, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
+    double true_res = cur.true_res;
+    if (!(o.verify && cur.status == CONVERGED)) {
+        k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
+        k_reduce_to<<<1, NT, 0, d.st>>>(d.B.part_res, d.gl, 0, w.scalar);
+        AMP_HIP(hipGetLastError());
+        double t2 = 0.0;
+        AMP_HIP(hipMemcpyAsync(&t2, w.scalar, sizeof(double), hipMemcpyDeviceToHost, d.st));
+        AMP_HIP(hipStreamSynchronize(d.st));
+        true_res = std::sqrt(t2);
+    }
+    AMP_HIP(hipStreamSynchronize(d.st));
+
+    amp_status rs = AMP_OK;
+    if (cur.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
+    else if (cur.status == BREAKDOWN) rs = AMP_ERR_BREAKDOWN;
+    if (res) {
+        res->spmv_ms = 0.0;
+        res->spmv_launches = 0;
+        res->iters = cur.iters;
+        res->status = rs;
+        res->bnorm = cur.bnorm;
+        res->rel_res_updated = cur.bnorm > 0 ? cur.delta / cur.bnorm : 0.0;
+        res->rel_res_true = cur.bnorm > 0 ? true_res / cur.bnorm : 0.0;
+        res->k_z32 = cur.k_z32;
+        res->k_z16 = cur.k_z16;
+        res->k_r32 = cur.k_r32;
+        res->n_replacements = cur.n_repl;
+        res->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rs == AMP_ERR_NOT_CONVERGED) g_last_error = "amp_pcg_solve_noalloc: not converged within maxit";
+    if (rs == AMP_ERR_BREAKDOWN) g_last_error = "amp_pcg_solve_noalloc: breakdown (rho <= 0, gamma <= 0 or non-finite)";
     return rs;
 }
 
@@ -1527,6 +1740,7 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
         d.B = B;
         d.gs = d.cfg.g_stream;
         d.gl = d.cfg.g_slice;
+        d.sb = w.st;
         d.in = &w.st[ST_RES];
         d.host_k = 0;
         St s0 = init_state(o);
