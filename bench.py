@@ -1,28 +1,36 @@
 #!/usr/bin/env python3
 """Time-to-solution of AMP-PCG versus FP64 PCG on one MI355X.
 
-A step is one complete solve (all kernels of the hot path, from r0 = b - A x0
-to the verified solution) of the 3-D 7-point finite-volume diffusion system
-on a 128^3 grid with block coefficients 10^U, U ~ U[0, 4] on 8^3 blocks
-(N = 2,097,152, nnz = 14,581,760), Jacobi preconditioner, tol 1e-10.
-Inputs are resident in HBM before the timed region starts.
+A step is one complete solve (every kernel of the hot path, from r0 = b - A x0
+to the verified solution) of the anisotropic Q1 system: trilinear finite
+elements for -div(diag(1, 1e-2, 1e-3) grad u) on the unit cube, 256^3
+interior nodes (N = 16,777,216, nnz = 449,455,096), with the degree-4
+Chebyshev polynomial preconditioner (B = D^{-1/2} A D^{-1/2} stored in FP16),
+x* ~ U[-1, 1], b = A x*, x0 = 0, tol 1e-10.  Inputs are resident in HBM
+before the timed region starts.
 
-Prints one JSON line: value = AMP-PCG(FP16) time-to-solution (ms, lower is
-better; the variant the paper times: z and p in FP16 from the start, r and q
-switching FP64 -> FP32 by the delay criterion); the stepwise AMP-PCG(FP64)
-time, the FP64 PCG time on the same GPU, the speedups, the iteration
-counts, the HBM roofline of the dominant kernel (the product step, timed
-with HIP events carried by each of its launches inside the AMP-PCG solve),
-and the FP64 CPU oracle timed on the host are reported beside it.
+One JSON line: value = AMP-PCG(FP16) time-to-solution (ms, lower is better;
+the variant the paper times: z and p in FP16 from the start, r and q
+switching FP64 -> FP32 by the delay criterion).  Beside it: the stepwise
+AMP-PCG(FP64) and PCG(FP64) times on the same GPU (PCG(FP64) applies the same
+preconditioner -- the polynomial in FP64 arithmetic on the FP16-stored B),
+iteration counts and switch points, each preset's error against x* and its
+bound against the FP64 oracle's solution, the HBM roofline of the dominant
+kernel (the Chebyshev step, every launch of one AMP-PCG(FP16) solve timed by
+HIP events carried by its own dispatch) with the product kernel's beside
+it, the library's stream probes as the measured ceiling, the FP64 CPU oracle
+timed on the host on a bounded sample, and the 128^3 finite-volume workload
+as a secondary measurement.
 
-Modes: --mode roofline runs only the timed-product solve (and a 256 MiB
-device copy of known size): the command the kernel trace and the HBM
-counter runs profile.
+Modes: --mode roofline runs only the timed solve and the probes (the command
+the kernel-trace and counter runs profile); --mode fv128 the 128^3 workload
+alone.
 """
 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -34,34 +42,59 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-solution at rel. residual 1e-10, AMP-PCG vs FP64 PCG; SpMV HBM GB/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_fv3d128_hbm_counters.txt")
-Q1_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_q1_256_hbm_counters.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILES = {
+    ("q1", "k_cheb_step"): os.path.join(PROFILES, "k_cheb_step_q1_256_hbm_counters.txt"),
+    ("q1", "k_spmv"): os.path.join(PROFILES, "k_spmv_q1_256_hbm_counters.txt"),
+    ("fv128", "k_spmv"): os.path.join(PROFILES, "k_spmv_fv3d128_hbm_counters.txt"),
+}
+Q1_GOLDEN = os.path.join(ROOT, "tests", "golden", "q1_256_chebyshev4.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ----------------------------------------------------------------------------
+# algorithmic bytes (values, column metadata, each vector read once and
+# written once; gathers counted once; slice padding not counted)
+# ----------------------------------------------------------------------------
+
 def step_bytes(n, nnz, meta_bytes, u_z, u_r):
-    """Algorithmic bytes of one product step p = z + beta p_old, q = A p in
-    precisions (u_z, u_r): every nonzero's value once (FP64 plane for
-    u_r = 64, FP32 plane otherwise), the layout's column metadata once (int32
-    indices of index-mode slices, the shared offset lists, 12 B per slice),
-    z and p_old read once (gathers counted once), p and q written once.
-    Slice padding is overhead, not counted."""
+    """One product step p = z + beta p_old, q = A p in (u_z, u_r): every
+    nonzero's value once (FP64 plane for u_r = 64, FP32 plane otherwise),
+    the column metadata once, z and p_old read, p and q written."""
     b_val = 8 if u_r == 64 else 4
     return nnz * b_val + meta_bytes + n * (3 * (u_z // 8) + u_r // 8)
 
 
-def stored_traffic(path=None):
-    """HBM bytes per product launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary (each counter scaled by what it reads for a plain copy of known
-    size), or None when the summary is missing or was taken on other kernel
-    sources than the library built here."""
+def cheb_iteration_bytes(n, nnz, meta_bytes, u_z, u_r, degree=4):
+    """The degree - 1 polynomial-step launches of one preconditioner
+    application in (u_z, u_r): each reads B's FP16 values and the column
+    metadata once; the work vectors are held in c = 8 bytes (u_z = FP64) or
+    4 (otherwise).  First step: reads v, writes w, res, dir (4c); inner
+    steps: read dir, w, res, write w, res, dir (6c); last step: reads dir,
+    w, res, D^{-1/2} (4c) and r (u_r), writes z (u_z)."""
+    c = 8 if u_z == 64 else 4
+    m = degree - 1
+    if m < 1:
+        return 0
+    if m == 1:   # one step, first and last: reads v and D^{-1/2}, r; writes z
+        vec = 2 * c + u_r // 8 + u_z // 8
+    else:
+        vec = 4 * c + (m - 2) * 6 * c + 4 * c + u_r // 8 + u_z // 8
+    return m * (2 * nnz + meta_bytes) + n * vec
+
+
+def stored_traffic(path):
+    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary
+    (each counter scaled by what it reads for the library's copy probe of
+    known size), or None when the summary is missing or was taken on other
+    kernel sources than the library built here."""
     from paper_2505_04155_amd import build
     try:
         fields = {}
-        with open(path or TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if line.strip() and not line.startswith("#"):
                     key, _, val = line.partition(" ")
@@ -73,130 +106,222 @@ def stored_traffic(path=None):
     return int(float(fields["traffic_bytes_per_launch"]))
 
 
-def roofline(amp, M, pc, bt, info_m, preset, tol, maxit, traffic_file=None):
-    """One AMP-PCG solve with the library timing every product launch (HIP
-    events carried by the launch's own dispatch on the solve's stream);
-    achieved = algorithmic bytes of the launches that performed an
-    iteration, summed per iteration from the recorded precisions, / their
-    summed duration."""
+def _phases(info):
+    out = {}
+    for uz, ur in zip(info["uz"], info["ur"]):
+        out[f"z{uz}_r{ur}"] = out.get(f"z{uz}_r{ur}", 0) + 1
+    return out
+
+
+def timed_solve(amp, M, pc, bt, preset, tol, maxit):
+    """One solve with every product and Chebyshev-step launch timed by HIP
+    events carried by the launch's own dispatch on the solve's stream."""
     x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset, history=True, spmv_timing=1)
     if info["status"] != 0:
         raise RuntimeError(f"timed solve failed: {info}")
-    n, nnz, meta = info_m["n"], info_m["nnz"], info_m["meta_bytes"]
-    total = sum(step_bytes(n, nnz, meta, uz, ur) for uz, ur in zip(info["uz"], info["ur"]))
-    launches = info["spmv_launches"]
-    us = info["spmv_ms"] * 1e3 / launches
-    gbs = total / (info["spmv_ms"] * 1e-3) / 1e9
-    phases = {}
-    for uz, ur in zip(info["uz"], info["ur"]):
-        phases[f"z{uz}_r{ur}"] = phases.get(f"z{uz}_r{ur}", 0) + 1
+    return info
+
+
+def roofline_entry(kernel, total_bytes, total_ms, launches, traffic, phases):
+    gbs = total_bytes / (total_ms * 1e-3) / 1e9
     return {
         "bound": "hbm",
-        "kernel": f"k_spmv: p = z + beta p_old (u_z), q = A p (u_r), gamma partials; every launch of one "
-                  f"{preset} solve, all precision phases",
+        "kernel": kernel,
         "achieved": round(gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(gbs / HBM_PEAK_GBS, 4),
-        "traffic": stored_traffic(traffic_file),
-        "avg_kernel_us": round(us, 3),
+        "traffic": traffic,
+        "avg_kernel_us": round(total_ms * 1e3 / launches, 3),
         "launches": launches,
-        "algorithmic_bytes_per_launch": round(total / launches),
+        "algorithmic_bytes_per_launch": round(total_bytes / launches),
         "phase_iterations": phases,
     }
 
 
-def warm_step(binding, M, torch, info_m, reps=50):
-    """The product step of the FP16/FP32 phase launched back to back on the
-    same data (which then stays in the 256 MB last-level cache): a
-    cache-resident figure, reported beside the in-solve roofline."""
-    import ctypes
+def rooflines(info, info_m, workload, degree=None):
+    n, nnz, meta = info_m["n"], info_m["nnz"], info_m["meta_bytes"]
+    prec = list(zip(info["uz"], info["ur"]))
+    ph = _phases(info)
+    sp_bytes = sum(step_bytes(n, nnz, meta, uz, ur) for uz, ur in prec)
+    sp = roofline_entry(
+        "k_spmv: p = z + beta p_old (u_z), q = A p (u_r), gamma partials; every launch of the timed solve",
+        sp_bytes, info["spmv_ms"], info["spmv_launches"], stored_traffic(TRAFFIC_FILES[(workload, "k_spmv")]), ph)
+    if degree is None or info.get("cheb_launches", 0) == 0:
+        return sp, None
+    ch_bytes = sum(cheb_iteration_bytes(n, nnz, meta, uz, ur, degree) for uz, ur in prec)
+    ch = roofline_entry(
+        "k_cheb_step: one step of the Chebyshev recurrence on the FP16 B (the last one forms z and rho "
+        "partials); every launch of the timed solve",
+        ch_bytes, info["cheb_ms"], info["cheb_launches"],
+        stored_traffic(TRAFFIC_FILES[(workload, "k_cheb_step")]), ph)
+    return ch, sp
+
+
+# ----------------------------------------------------------------------------
+# the library's stream probes (ceiling reference, counter scaling)
+# ----------------------------------------------------------------------------
+
+def stream_probe(torch, dev, mode, mib, reps=5):
+    from paper_2505_04155_amd import binding
     L = binding.load()
+    nbytes = mib * 1024 * 1024
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src) if mode == 1 else torch.zeros(4, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
-    for _ in range(3):
-        binding.check(L.amp_spmv_step(M.handle, 16, 32, 1, 0.5, sp), "amp_spmv_step")
+
+    def launch():
+        binding.check(L.amp_stream_probe(mode, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                         nbytes, sp), "amp_stream_probe")
+    launch()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        L.amp_spmv_step(M.handle, 16, 32, 1, 0.5, sp)
+        launch()
     e1.record(stream)
     e1.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / reps
-    nb = step_bytes(info_m["n"], info_m["nnz"], info_m["meta_bytes"], 16, 32)
-    return {"kernel": "k_spmv_fixed<16,32,true>", "avg_us": round(us, 3), "GB/s": round(nb / us / 1e3, 1)}
+    moved = nbytes * (2 if mode == 1 else 1)
+    del src, dst
+    return {"kernel": "k_stream_copy" if mode == 1 else "k_stream_read", "bytes": moved,
+            "avg_us": round(us, 3), "GB/s": round(moved / us / 1e3, 1)}
 
 
-def copy_reference(torch, dev, reps=5, mib=256):
-    """A plain device copy of `mib` MiB (read and write that much).  The
-    256 MiB copy is the launch a counter run scales FETCH_SIZE / WRITE_SIZE
-    by; a 4 GiB copy, far beyond the 256 MB memory-side cache, gives the
-    streaming rate of HBM itself."""
-    stream = torch.cuda.current_stream()
-    src = torch.empty(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record(stream)
-    e1.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / reps
-    return {"bytes": 2 * src.numel() * 4, "avg_us": round(us, 3), "GB/s": round(2 * src.numel() * 4 / us / 1e3, 1)}
+def probes(torch, dev):
+    return {"read_4GiB": stream_probe(torch, dev, 0, 4096, reps=3),
+            "copy_4GiB": stream_probe(torch, dev, 1, 4096, reps=3),
+            "copy_256MiB": stream_probe(torch, dev, 1, 256)}
 
 
-def q1_mode(args, amp, torch, np, P, dev, tol=1e-10, maxit=20000):
-    """The anisotropic Q1 stiffness workload (27-point, 256^3 interior nodes,
-    x* ~ U[-1, 1], b = A x*) with the degree-4 Chebyshev preconditioner: one
-    timed solve per preset after a warm-up, the in-solve product roofline,
-    and the reference copy a counter run scales by.  One JSON line."""
-    m = args.q1_grid
-    log(f"bench: generating the Q1 {m}^3 system")
-    A, b, xs, (lo, hi) = P.q1_system(m)
-    M = amp.Matrix.from_csr(A, device=dev)
-    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
-    bt = torch.tensor(b, device=dev)
-    info_m = M.info()
-    n, nnz = A.n, A.nnz
-    del A
-    out = {"mode": "q1", "workload": f"Q1 anisotropic diffusion (1, 1e-2, 1e-3), {m}^3 interior nodes, N={n}, "
-                                     f"nnz={nnz}, degree-4 Chebyshev on [lam_lo, 1.05 lam_hi], tol {tol}"}
-    xsn = float(np.linalg.norm(xs))
-    for preset in (args.preset, "pcg64"):
-        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+# ----------------------------------------------------------------------------
+# timing
+# ----------------------------------------------------------------------------
+
+def time_presets(amp, torch, M, pc, bt, presets, steps, warmup, tol, maxit):
+    results = {}
+    for preset in presets:
+        def run():
+            x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+            if info["status"] != 0:
+                raise RuntimeError(f"{preset} solve failed: {info}")
+            return x, info
+        for w in range(warmup):
+            run()
+            log(f"bench: warmup {preset} {w + 1}/{warmup} done")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
+        for _ in range(steps):
+            x, info = run()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
-        if info["status"] != 0:
-            raise RuntimeError(f"{preset} solve failed: {info}")
-        err = float(np.linalg.norm(x.cpu().numpy() - xs) / xsn)
-        out[preset] = {"ms": round(ms, 3), "iters": info["iters"], "rel_res_true": info["relres_true"],
-                       "rel_err_vs_xstar": err,
-                       "switch_iterations": [info["k_z32"], info["k_z16"], info["k_r32"]]}
-        log(f"bench: Q1 {preset}: {ms:.1f} ms, {info['iters']} iterations, error vs x* {err:.2e}")
-    out["speedup_vs_fp64_pcg"] = round(out["pcg64"]["ms"] / out[args.preset]["ms"], 4)
-    out["roofline"] = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit, traffic_file=Q1_TRAFFIC_FILE)
-    log(f"bench: Q1 product step in the solve: {out['roofline']['avg_kernel_us']:.1f} us, "
-        f"{out['roofline']['achieved']:.0f} GB/s")
-    out["copy_256MiB"] = copy_reference(torch, dev)
-    out["matrix"] = info_m
-    print(json.dumps(out), flush=True)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        results[preset] = (ms, info, x)
+        log(f"bench: {preset}: {ms:.3f} ms/solve, {info['iters']} iterations, "
+            f"switches z32={info['k_z32']} z16={info['k_z16']} r32={info['k_r32']}")
+    return results
 
+
+def oracle_threads():
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def golden_q1():
+    fields = {}
+    with open(Q1_GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, _, v = line.partition(" ")
+                fields[k] = float(v)
+    return fields
+
+
+def q1_cpu_baseline(A, b, lo, hi, oracle_iters, k1=2, k2=12):
+    """The FP64 oracle (Alg. 1 with the same degree-4 Chebyshev definition,
+    FP64 throughout) on the same system, timed for k1 and k2 iterations; the
+    per-iteration slope times the oracle's full iteration count plus the
+    k1-run's fixed part gives the full solve's time."""
+    from oracle import cpcg
+    threads = oracle_threads()
+    cpcg.lib().oracle_set_threads(threads)
+    t = {}
+    for k in (k1, k2):
+        t0 = time.perf_counter()
+        cpcg.pcg(A, b, tol=1e-10, maxit=k, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=lo, lam_hi=hi)
+        t[k] = (time.perf_counter() - t0) * 1e3
+        log(f"bench: CPU oracle, {k} iterations: {t[k]:.0f} ms ({threads} threads)")
+    per_it = (t[k2] - t[k1]) / (k2 - k1)
+    total = t[k1] + per_it * (oracle_iters - k1)
+    return {"value": round(total, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 PCG (Alg. 1) with the degree-4 Chebyshev preconditioner on the same 256^3 system, "
+                      f"timed for {k1} and {k2} iterations ({t[k1]:.0f} and {t[k2]:.0f} ms); the per-iteration "
+                      f"slope scaled to the oracle's {oracle_iters} iterations to convergence",
+            "ms_per_iteration": round(per_it, 2), "cpu_model": cpu_model()}
+
+
+def fv128_measurement(amp, torch, np, P, dev, steps, warmup, with_oracle=True, grid=128):
+    """The 128^3 blocky finite-volume workload (Jacobi): time per preset,
+    product-kernel roofline, error against the oracle's solution."""
+    log(f"bench: generating the {grid}^3 finite-volume system")
+    A, b, _ = P.blocky_diffusion3d_system(grid, 8)
+    M = amp.Matrix.from_csr(A, device=dev)
+    pc = amp.Preconditioner(M, "jacobi")
+    bt = torch.tensor(b, device=dev)
+    info_m = M.info()
+    tol, maxit = 1e-10, 20000
+    res = time_presets(amp, torch, M, pc, bt, ("amp16", "pcg64"), steps, warmup, tol, maxit)
+    info = timed_solve(amp, M, pc, bt, "amp16", tol, maxit)
+    sp, _ = rooflines(info, info_m, "fv128")
+    out = {"workload": f"3-D 7-point FV diffusion {grid}^3, coefficients 10^U(0,4) on 8^3 blocks, "
+                       f"N={info_m['n']}, nnz={info_m['nnz']}, Jacobi, tol 1e-10, b ~ N(0,1)",
+           "amp16_ms": round(res["amp16"][0], 3), "pcg64_ms": round(res["pcg64"][0], 3),
+           "speedup_vs_fp64_pcg": round(res["pcg64"][0] / res["amp16"][0], 4),
+           "amp16_iters": res["amp16"][1]["iters"], "pcg64_iters": res["pcg64"][1]["iters"],
+           "roofline": sp}
+    if with_oracle:
+        from oracle import cpcg
+        cpcg.lib().oracle_set_threads(oracle_threads())
+        t0 = time.perf_counter()
+        xo, io = cpcg.pcg(A, b, tol=tol, maxit=maxit)
+        out["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        out["oracle_iters"] = io["iters"]
+        xon = float(np.linalg.norm(xo))
+        out["rel_err_vs_oracle"] = {p: float(np.linalg.norm(r[2].cpu().numpy() - xo) / xon) for p, r in res.items()}
+        log(f"bench: 128^3 relative error against the oracle's solution: {out['rel_err_vs_oracle']}")
+    return out
+
+
+# ----------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--preset", default="amp16")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "roofline", "q1"], default="solve",
-                    help="roofline: only the timed-product solve and the reference copy (for profiler runs); "
-                         "q1: the anisotropic Q1 workload with the degree-4 Chebyshev preconditioner")
     ap.add_argument("--q1-grid", type=int, default=256, help="interior nodes per direction of the Q1 workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 finite-volume measurement")
+    ap.add_argument("--no-oracle-solution", action="store_true",
+                    help="skip the oracle's full solve of the Q1 system (the exact errors against it)")
+    ap.add_argument("--mode", choices=["solve", "roofline", "fv128"], default="solve",
+                    help="roofline: only the timed solve and the stream probes (for profiler runs); "
+                         "fv128: the 128^3 finite-volume workload alone")
+    ap.add_argument("--workload", choices=["q1", "fv128"], default="q1", help="workload of --mode roofline")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -215,118 +340,138 @@ def main():
     binding.load(build_if_missing=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    tol, maxit = 1e-10, 20000
 
-    if args.mode == "q1":
-        q1_mode(args, amp, torch, np, P, dev)
+    if args.mode == "fv128":
+        print(json.dumps(fv128_measurement(amp, torch, np, P, dev, args.steps, args.warmup)), flush=True)
+        return
+    if args.mode == "roofline" and args.workload == "fv128":
+        A, b, _ = P.blocky_diffusion3d_system(128, 8)
+        M = amp.Matrix.from_csr(A, device=dev)
+        pc = amp.Preconditioner(M, "jacobi")
+        bt = torch.tensor(b, device=dev)
+        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=args.preset)
+        info = timed_solve(amp, M, pc, bt, args.preset, tol, maxit)
+        sp, _ = rooflines(info, M.info(), "fv128")
+        pr = {"copy_256MiB": stream_probe(torch, dev, 1, 256)}
+        log(f"bench: product step {sp['avg_kernel_us']:.2f} us, {sp['achieved']:.0f} GB/s")
+        print(json.dumps({"mode": "roofline", "workload": "fv128", "roofline": sp, "probes": pr}), flush=True)
         return
 
-    log(f"bench: generating the {args.grid}^3 system")
-    A, b, _ = P.blocky_diffusion3d_system(args.grid, 8)
+    m = args.q1_grid
+    log(f"bench: generating the Q1 {m}^3 system")
+    t0 = time.perf_counter()
+    A, b, xs, (lo, hi) = P.q1_system(m)
+    log(f"bench: generated in {time.perf_counter() - t0:.1f} s; uploading")
     M = amp.Matrix.from_csr(A, device=dev)
-    pc = amp.Preconditioner(M, "jacobi")
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
     bt = torch.tensor(b, device=dev)
     info_m = M.info()
     n, nnz = info_m["n"], info_m["nnz"]
-    tol, maxit = 1e-10, 20000
+    workload = (f"Q1 trilinear FEM, anisotropic diffusion diag(1, 1e-2, 1e-3), {m}^3 interior nodes, N={n}, "
+                f"nnz={nnz}, degree-4 Chebyshev preconditioner (FP16 B) on [lam_min, 1.05 lam_max] of D^-1 A, "
+                f"x* ~ U[-1,1], b = A x*, tol 1e-10")
 
     if args.mode == "roofline":
-        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=args.preset)        # warm the handle
-        rf = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit)
-        cp = copy_reference(torch, dev)
-        cp4 = copy_reference(torch, dev, reps=3, mib=4096)
-        log(f"bench: product step in the solve: {rf['avg_kernel_us']:.2f} us average over {rf['launches']} "
-            f"launches, {rf['achieved']:.0f} GB/s; copy 256 MiB {cp['GB/s']:.0f} GB/s, 4 GiB {cp4['GB/s']:.0f} GB/s")
-        print(json.dumps({"mode": "roofline", "roofline": rf, "copy_256MiB": cp, "copy_4GiB": cp4, "matrix": info_m}),
-              flush=True)
+        amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=args.preset)   # warm the handle
+        info = timed_solve(amp, M, pc, bt, args.preset, tol, maxit)
+        ch, sp = rooflines(info, info_m, "q1", degree=4)
+        pr = probes(torch, dev)
+        log(f"bench: Chebyshev step {ch['avg_kernel_us']:.1f} us ({ch['achieved']:.0f} GB/s), product "
+            f"{sp['avg_kernel_us']:.1f} us ({sp['achieved']:.0f} GB/s); read probe {pr['read_4GiB']['GB/s']:.0f}, "
+            f"copy probe {pr['copy_4GiB']['GB/s']:.0f} GB/s")
+        print(json.dumps({"mode": "roofline", "workload": workload, "roofline": ch, "roofline_k_spmv": sp,
+                          "probes": pr, "matrix": info_m}), flush=True)
         return
 
-    def run(preset):
-        x, info = amp.solve(M, pc, bt, tol=tol, maxit=maxit, preset=preset)
-        if info["status"] != 0:
-            raise RuntimeError(f"{preset} solve failed: {info}")
-        return x, info
-
-    results = {}
     presets = [args.preset] + [p for p in ("amp64", "pcg64") if p != args.preset]
-    for preset in presets:
-        for w in range(args.warmup):
-            run(preset)
-            log(f"bench: warmup {preset} {w + 1}/{args.warmup} done")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = []
-        for s in range(args.steps):
-            x, info = run(preset)
-            infos.append(info)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms = (t1 - t0) * 1e3 / args.steps
-        results[preset] = (ms, infos[-1], x)
-        log(f"bench: {preset}: {ms:.3f} ms/solve, {infos[-1]['iters']} iterations, "
-            f"switches z32={infos[-1]['k_z32']} z16={infos[-1]['k_z16']} r32={infos[-1]['k_r32']}")
+    results = time_presets(amp, torch, M, pc, bt, presets, args.steps, args.warmup, tol, maxit)
+    gold = golden_q1() if m == 256 else None
+    xsn = float(np.linalg.norm(xs))
+    err_xs = {p: float(np.linalg.norm(r[2].cpu().numpy() - xs) / xsn) for p, r in results.items()}
+    log(f"bench: relative error against x*: {err_xs}")
+    err_or = None
+    if gold:
+        # ||x - x_o|| <= ||x - x*|| + ||x_o - x*|| and ||x_o|| >= ||x*|| (1 - e_o)
+        eo = gold["err_vs_xstar"]
+        err_or = {p: (e + eo) / (1.0 - eo) for p, e in err_xs.items()}
 
     amp_ms, amp_info, _ = results[args.preset]
     fp64_ms, fp64_info, _ = results["pcg64"]
 
-    # Dominant kernel: the product step, timed inside an AMP-PCG solve.
-    rf = roofline(amp, M, pc, bt, info_m, args.preset, tol, maxit)
-    log(f"bench: product step in the solve: {rf['avg_kernel_us']:.2f} us average over {rf['launches']} launches, "
-        f"{rf['achieved']:.0f} GB/s algorithmic ({100 * rf['frac']:.1f}% of {HBM_PEAK_GBS:.0f})")
-    warm = warm_step(binding, M, torch, info_m)
-    log(f"bench: FP16/FP32 product step back to back (cache-resident): {warm['avg_us']:.2f} us, "
-        f"{warm['GB/s']:.0f} GB/s")
+    info = timed_solve(amp, M, pc, bt, args.preset, tol, maxit)
+    ch, sp = rooflines(info, info_m, "q1", degree=4)
+    log(f"bench: Chebyshev step in the solve: {ch['avg_kernel_us']:.1f} us, {ch['achieved']:.0f} GB/s "
+        f"({100 * ch['frac']:.1f}% of {HBM_PEAK_GBS:.0f}); product step {sp['avg_kernel_us']:.1f} us, "
+        f"{sp['achieved']:.0f} GB/s")
+    pr = probes(torch, dev)
+    log(f"bench: stream probes: read {pr['read_4GiB']['GB/s']:.0f} GB/s, copy {pr['copy_4GiB']['GB/s']:.0f} GB/s")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and gold:
+        cpu = q1_cpu_baseline(A, b, lo, hi, int(gold["iters"]))
+        log(f"bench: CPU oracle (scaled sample) {cpu['value']:.0f} ms")
+    oracle = None
+    if not args.no_oracle_solution:
+        # the oracle's own solution of the same system, for the error of
+        # every timed solve against it
         from oracle import cpcg
-        threads = len(os.sched_getaffinity(0))
-        cpcg.lib().oracle_set_threads(threads)
-        log(f"bench: CPU oracle (FP64 PCG, {threads} threads)")
+        cpcg.lib().oracle_set_threads(oracle_threads())
+        log("bench: CPU oracle, full solve for the parity figures")
         t0 = time.perf_counter()
-        xo, io = cpcg.pcg(A, b, tol=tol, maxit=maxit)
-        t1 = time.perf_counter()
-        cpu = {"value": round((t1 - t0) * 1e3, 3), "unit": "ms", "cores": threads, "kind": "oracle",
-               "sample": f"one full FP64 PCG solve (Alg. 1, Jacobi) of the same system: "
-                         f"{io['iters']} iterations"}
-        log(f"bench: CPU oracle {cpu['value']:.1f} ms, {io['iters']} iterations")
-        # every timed solve's final iterate against the oracle's (both stop at tol 1e-10)
+        xo, io = cpcg.pcg(A, b, tol=tol, maxit=maxit, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=lo, lam_hi=hi)
+        oms = (time.perf_counter() - t0) * 1e3
         xon = float(np.linalg.norm(xo))
-        cpu["oracle_iters"] = io["iters"]
-        cpu["rel_err_vs_oracle"] = {p: float(np.linalg.norm(r[2].cpu().numpy() - xo) / xon) for p, r in results.items()}
-        log(f"bench: relative error against the oracle's solution: {cpu['rel_err_vs_oracle']}")
+        oracle = {"iters": io["iters"], "ms": round(oms, 1), "threads": oracle_threads(),
+                  "rel_res_true": io["relres_true"],
+                  "rel_err_vs_xstar": float(np.linalg.norm(xo - xs) / xsn),
+                  "rel_err_vs_oracle": {p: float(np.linalg.norm(r[2].cpu().numpy() - xo) / xon)
+                                        for p, r in results.items()}}
+        log(f"bench: oracle {io['iters']} iterations in {oms:.0f} ms; relative error against its solution: "
+            f"{oracle['rel_err_vs_oracle']}")
+
+    del A
+    secondary = None
+    if not args.no_secondary:
+        del M, pc, bt
+        torch.cuda.empty_cache()
+        secondary = fv128_measurement(amp, torch, np, P, dev, args.steps, args.warmup,
+                                      with_oracle=not args.no_cpu_baseline)
 
     out = {
         "metric": METRIC,
-        "value": round(amp_ms, 4),
+        "value": round(amp_ms, 3),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(amp_ms, 4),
+        "ms_per_step": round(amp_ms, 3),
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64+f32+f16",
         "data": "synthetic",
-        "config": {
-            "workload": f"3-D 7-point FV diffusion {args.grid}^3, coefficients 10^U(0,4) on 8^3 blocks, "
-                        f"N={n}, nnz={nnz}, Jacobi, tol 1e-10, b ~ N(0,1)",
-            "preset": args.preset,
-            "parallelism": "single GPU",
-        },
-        "fp64_pcg_ms": round(fp64_ms, 4),
+        "config": {"workload": workload, "preset": args.preset, "parallelism": "single GPU"},
+        "fp64_pcg_ms": round(fp64_ms, 3),
+        "fp64_pcg_note": "PCG(FP64): every vector and scalar FP64, the same preconditioner (Chebyshev "
+                         "polynomial in FP64 arithmetic on the FP16-stored B)",
         "speedup_vs_fp64_pcg": round(fp64_ms / amp_ms, 4),
-        "amp64_ms": round(results["amp64"][0], 4),
-        "amp64_iters": results["amp64"][1]["iters"],
+        "amp64_ms": round(results["amp64"][0], 3),
         "speedup_amp64_vs_fp64_pcg": round(fp64_ms / results["amp64"][0], 4),
-        "iters": amp_info["iters"],
-        "iters_fp64": fp64_info["iters"],
-        "switch_iterations": {"u_z_fp32": amp_info["k_z32"], "u_z_fp16": amp_info["k_z16"],
-                              "u_r_fp32": amp_info["k_r32"]},
-        "rel_res_true": amp_info["relres_true"],
-        "roofline": rf,
-        "warm_product_step": warm,
+        "iters": {p: r[1]["iters"] for p, r in results.items()},
+        "oracle_iters": int(gold["iters"]) if gold else None,
+        "switch_iterations": {p: {"u_z_fp32": r[1]["k_z32"], "u_z_fp16": r[1]["k_z16"], "u_r_fp32": r[1]["k_r32"]}
+                              for p, r in results.items()},
+        "rel_res_true": {p: r[1]["relres_true"] for p, r in results.items()},
+        "rel_err_vs_xstar": err_xs,
+        "rel_err_vs_oracle": oracle["rel_err_vs_oracle"] if oracle else None,
+        "rel_err_vs_oracle_bound": err_or,
+        "oracle_solve": oracle,
+        "roofline": ch,
+        "roofline_k_spmv": sp,
+        "probes": pr,
         "cpu_baseline": cpu,
+        "secondary_fv128": secondary,
     }
     print(json.dumps(out), flush=True)
 

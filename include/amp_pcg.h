@@ -110,8 +110,9 @@ typedef struct {
                                rr_period = 0, is solved by one work-group in one launch (the stages of
                                the kernel sequence with one work-group each, in a loop on the device);
                                0 disables (default 0) */
-    int spmv_timing;        /* 1: time every product-kernel launch with HIP events (eager path only:
-                               disables graph and solo); results in amp_result.spmv_ms */
+    int spmv_timing;        /* 1: time every product-kernel launch (and every Chebyshev polynomial-step
+                               launch) with HIP events carried by the dispatch (eager path only:
+                               disables graph and solo); results in amp_result.spmv_ms, cheb_ms */
     int defer_x;            /* 1 (default): the FP64 update x += alpha p is applied two iterations at a
                                time, x_{k+1} = (x_{k-1} + alpha_{k-1} p_{k-1}) + alpha_k p_k, rounded
                                after each step exactly as one step at a time (bitwise the same x);
@@ -138,6 +139,9 @@ typedef struct {
     double spmv_ms;           /* spmv_timing: summed duration of the product-kernel launches that
                                  performed an iteration (0 otherwise) */
     int spmv_launches;        /* spmv_timing: number of those launches (= iters) */
+    double cheb_ms;           /* spmv_timing with a Chebyshev preconditioner of degree m > 1: summed
+                                 duration of the polynomial-step launches that performed an iteration */
+    int cheb_launches;        /* spmv_timing: number of those launches (= iters * (m - 1)) */
 } amp_result;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -384,6 +388,18 @@ amp_status amp_selector_replay(const double *delta, int len, double bnorm, doubl
  * u_z: out[0..3] = zamx, innerProd, axpy, updatePCG.  Needs no GPU.
  */
 amp_status amp_paper_kernel_bytes(int u_z, int u_r, double out[4]);
+
+/*
+ * Measurement: stream `bytes` bytes through HBM with the library's own
+ * probe kernels -- mode 0 reads src once (dst: a device word the kernel
+ * may write, so no load can be dropped), mode 1 copies src to dst.  16-byte
+ * loads and stores, four in flight per thread, up to 2048 work-groups of
+ * 256 threads.  It gives the bandwidth ceiling the solver's kernels are
+ * compared with, and the known-size launch that hardware byte counters are
+ * scaled by.  Device pointers, 16-byte aligned; bytes a positive multiple
+ * of 16.  Enqueued on stream, not synchronised.  Errors: AMP_ERR_ARG.
+ */
+amp_status amp_stream_probe(int mode, const void *src, void *dst, int64_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

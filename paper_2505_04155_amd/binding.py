@@ -25,7 +25,7 @@ EXPORTED = [
     "amp_precond_create", "amp_precond_destroy", "amp_pcg_solve", "amp_spmv", "amp_spmv_step",
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
-    "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc",
+    "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
 ]
 
 
@@ -52,7 +52,8 @@ class Result(ctypes.Structure):
                 ("rel_res_updated", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("k_z32", ctypes.c_int), ("k_z16", ctypes.c_int),
                 ("k_r32", ctypes.c_int), ("n_replacements", ctypes.c_int),
-                ("t_solve_ms", ctypes.c_double), ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int)]
+                ("t_solve_ms", ctypes.c_double), ("spmv_ms", ctypes.c_double), ("spmv_launches", ctypes.c_int),
+                ("cheb_ms", ctypes.c_double), ("cheb_launches", ctypes.c_int)]
 
 
 class MatrixStats(ctypes.Structure):
@@ -104,6 +105,7 @@ def load(build_if_missing: bool = True):
         L.amp_precond_destroy.restype = None
         L.amp_pcg_solve.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                     ctypes.POINTER(Result), vp]
+        L.amp_stream_probe.argtypes = [i32, vp, vp, i64, vp]
         L.amp_pcg_solve_noalloc.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                             ctypes.POINTER(Result), vp]
         L.amp_pcg_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),

@@ -44,7 +44,7 @@ def sources_mtime() -> float:
     return max(os.path.getmtime(p) for p in paths)
 
 
-KERNEL_HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp"]
+KERNEL_HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp", "amp_cheb.hpp"]
 
 
 def _code_only(text: str) -> str:

@@ -30,6 +30,8 @@ struct Cheb {
     void *v, *res, *w;       // work vectors (np doubles each, read as float for FP32)
     void *dir[2];
     int64_t np, nslices;
+    int32_t *step_iter;      // nullable: iteration each timed step launch performed (-1: passed through)
+    int step_launch;         // index of this launch in step_iter
     int degree;
     double inv_theta;
     double c1[kChebMax], c2[kChebMax];
@@ -208,6 +210,7 @@ __global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int fi
         store_state(s, out, wg);
         return;
     }
+    if (P.step_iter && wg.lb == 0 && threadIdx.x == 0) P.step_iter[P.step_launch] = s.k;
     double rho = 0.0, mz = 0.0;
 #define AMP_CS_L(UZ, RL)                                                                \
     do {                                                                                \

@@ -96,6 +96,10 @@ struct Work {
     std::vector<hipEvent_t> tev;
     int32_t *titer = nullptr;                  // iteration performed by each timed launch
     int tcap = 0;
+    // Chebyshev step timing: the same per launch
+    std::vector<hipEvent_t> cev;
+    int32_t *citer = nullptr;
+    int ccap = 0;
 };
 
 
@@ -140,6 +144,7 @@ struct amp_precond_s {
         P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
         P.v = cv; P.res = cres; P.w = cw; P.dir[0] = cdir[0]; P.dir[1] = cdir[1];
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
+        P.step_iter = nullptr; P.step_launch = 0;
         for (int i = 0; i < kChebMax; ++i) { P.c1[i] = c1[i]; P.c2[i] = c2[i]; }
         return P;
     }
@@ -179,6 +184,11 @@ static void free_work(Work &w) {
     w.tev.clear();
     dfree(w.titer);
     w.tcap = 0;
+    for (auto &e : w.cev)
+        if (e) (void)hipEventDestroy(e);
+    w.cev.clear();
+    dfree(w.citer);
+    w.ccap = 0;
     if (w.cs) (void)hipStreamDestroy(w.cs);
     if (w.cap) (void)hipStreamDestroy(w.cap);
     w.cs = w.cap = nullptr;
@@ -795,6 +805,7 @@ struct Driver {
     int host_k;        // iterations enqueued since the last resynchronisation
     bool timing = false;
     int launches = 0;  // product launches enqueued (timing)
+    int claunches = 0; // Chebyshev step launches enqueued (timing)
 };
 
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
@@ -810,7 +821,19 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     for (int k = 0; k + 1 < m; ++k) {
         St *si = (k == 0) ? &sb[ST_PREI] : &sb[(k - 1) % 2 ? ST_CH1 : ST_CH0];
         St *so = (k == m - 2) ? out : &sb[k % 2 ? ST_CH1 : ST_CH0];
-        k_cheb_step<<<d.gl, NTS, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
+        Work &w = d.A->w;
+        if (d.timing && d.claunches < w.ccap) {
+            Cheb Pt = P;
+            Pt.step_iter = w.citer;
+            Pt.step_launch = d.claunches;
+            // events carried by the dispatch itself: they bracket the kernel, not the queue
+            hipExtLaunchKernelGGL(k_cheb_step, dim3(d.gl), dim3(NTS), 0, d.st, w.cev[2 * d.claunches],
+                                  w.cev[2 * d.claunches + 1], 0, d.B, Pt, k, (int)(k == 0), (int)(k == m - 2),
+                                  k % 2, (const St *)si, so);
+            d.claunches += 1;
+        } else {
+            k_cheb_step<<<d.gl, NTS, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
+        }
     }
 }
 
@@ -993,8 +1016,22 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
             w.tcap = need;
         }
         AMP_HIP(hipMemsetAsync(w.titer, 0xFF, w.tcap * sizeof(int32_t), d.st));   // -1: not an iteration
+        if (M->kind == AMP_PC_CHEBYSHEV && M->degree > 1) {
+            const int cneed = need * (M->degree - 1);
+            if (w.ccap < cneed) {
+                for (auto &e : w.cev)
+                    if (e) (void)hipEventDestroy(e);
+                w.cev.assign(2 * (size_t)cneed, nullptr);
+                for (auto &e : w.cev) AMP_HIP(hipEventCreate(&e));
+                dfree(w.citer);
+                AMP_TRY(dalloc(&w.citer, cneed));
+                w.ccap = cneed;
+            }
+            AMP_HIP(hipMemsetAsync(w.citer, 0xFF, w.ccap * sizeof(int32_t), d.st));
+        }
         d.timing = true;
         d.launches = 0;
+        d.claunches = 0;
     }
 
     const St s0 = init_state(o);
@@ -1097,12 +1134,28 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
         }
     }
 
+    double cheb_ms = 0.0;
+    int cheb_n = 0;
+    if (timing && d.claunches > 0) {
+        std::vector<int32_t> it(d.claunches);
+        AMP_HIP(hipMemcpy(it.data(), w.citer, d.claunches * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int i = 0; i < d.claunches; ++i) {
+            if (it[i] < 0) continue;
+            float ms = 0.0f;
+            AMP_HIP(hipEventElapsedTime(&ms, w.cev[2 * i], w.cev[2 * i + 1]));
+            cheb_ms += ms;
+            cheb_n += 1;
+        }
+    }
+
     amp_status rs = AMP_OK;
     if (cur.status == MAXIT) rs = AMP_ERR_NOT_CONVERGED;
     else if (cur.status == BREAKDOWN) rs = AMP_ERR_BREAKDOWN;
     if (res) {
         res->spmv_ms = spmv_ms;
         res->spmv_launches = spmv_n;
+        res->cheb_ms = cheb_ms;
+        res->cheb_launches = cheb_n;
         res->iters = cur.iters;
         res->status = rs;
         res->bnorm = cur.bnorm;
@@ -1312,6 +1365,8 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
     if (res) {
         res->spmv_ms = 0.0;
         res->spmv_launches = 0;
+        res->cheb_ms = 0.0;
+        res->cheb_launches = 0;
         res->iters = cur.iters;
         res->status = rs;
         res->bnorm = cur.bnorm;
@@ -1567,6 +1622,8 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
             amp_result &r = res[i];
             r.spmv_ms = 0.0;
             r.spmv_launches = 0;
+            r.cheb_ms = 0.0;
+            r.cheb_launches = 0;
             r.iters = c.iters;
             r.status = rs;
             r.bnorm = c.bnorm;
@@ -1883,6 +1940,64 @@ extern "C" amp_status amp_paper_kernel_bytes(int u_z, int u_r, double out[4]) {
     out[1] = bz + br;                 // innerProd: read z, r
     out[2] = 3 * bz;                  // axpy: read z, p, write p
     out[3] = 3 * br + 16 + bz;        // updatePCG: read r, q, x, p; write r, x
+    return AMP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// HBM stream probes (measurement): the bandwidth ceiling the solver's kernels
+// are compared with, and the known-size launch hardware counters are scaled by
+// ----------------------------------------------------------------------------
+
+constexpr int kProbeThreads = 256;
+constexpr int kProbeUnroll = 4;
+
+// Read every 16-byte word of src once (four loads in flight per thread);
+// the xor of the words decides one store, so no load can be dropped.
+__global__ void __launch_bounds__(kProbeThreads) k_stream_read(const uint4 *src, int64_t words, uint32_t *sink) {
+    const int64_t stride = (int64_t)gridDim.x * kProbeThreads;
+    int64_t i = (int64_t)blockIdx.x * kProbeThreads + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + (kProbeUnroll - 1) * stride < words; i += kProbeUnroll * stride) {
+        uint4 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; i < words; i += stride) {
+        const uint4 v = src[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;
+}
+
+// dst = src, 16-byte words, four in flight per thread.
+__global__ void __launch_bounds__(kProbeThreads) k_stream_copy(const uint4 *src, uint4 *dst, int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * kProbeThreads;
+    int64_t i = (int64_t)blockIdx.x * kProbeThreads + threadIdx.x;
+    for (; i + (kProbeUnroll - 1) * stride < words; i += kProbeUnroll * stride) {
+        uint4 v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; ++u) dst[i + u * stride] = v[u];
+    }
+    for (; i < words; i += stride) dst[i] = src[i];
+}
+
+extern "C" amp_status amp_stream_probe(int mode, const void *src, void *dst, int64_t bytes, void *stream) {
+    if (mode != 0 && mode != 1) return fail(AMP_ERR_ARG, "amp_stream_probe: mode must be 0 (read) or 1 (copy)");
+    if (!src || !dst) return fail(AMP_ERR_ARG, "amp_stream_probe: null pointer");
+    if (bytes <= 0 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return fail(AMP_ERR_ARG, "amp_stream_probe: bytes and pointers must be positive multiples of 16");
+    const int64_t words = bytes / 16;
+    // eight work-groups per CU on the 256-CU part: enough loads in flight
+    // to cover HBM latency
+    const int g = (int)std::min<int64_t>(2048, (words + kProbeThreads - 1) / kProbeThreads);
+    hipStream_t st = as_stream(stream);
+    if (mode == 0) k_stream_read<<<g, kProbeThreads, 0, st>>>((const uint4 *)src, words, (uint32_t *)dst);
+    else k_stream_copy<<<g, kProbeThreads, 0, st>>>((const uint4 *)src, (uint4 *)dst, words);
+    AMP_HIP(hipGetLastError());
     return AMP_OK;
 }
 

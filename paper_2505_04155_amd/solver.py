@@ -146,7 +146,7 @@ def solve(A: Matrix, M: Preconditioner, b: torch.Tensor, x0: torch.Tensor | None
     info = dict(status=st, iters=res.iters, relres=res.rel_res_updated, relres_true=res.rel_res_true,
                 bnorm=res.bnorm, k_z32=res.k_z32, k_z16=res.k_z16, k_r32=res.k_r32,
                 replacements=res.n_replacements, t_solve_ms=res.t_solve_ms, spmv_ms=res.spmv_ms,
-                spmv_launches=res.spmv_launches)
+                spmv_launches=res.spmv_launches, cheb_ms=res.cheb_ms, cheb_launches=res.cheb_launches)
     if history:
         it = res.iters
         info["delta"] = dh[: it + 1].cpu().numpy()

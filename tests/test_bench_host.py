@@ -36,17 +36,28 @@ def test_step_bytes_by_hand():
     assert abs(mean - 109294085) < 1.0
 
 
+def test_cheb_bytes_by_hand():
+    # 256^3 Q1 workload, degree 4: three step launches per application
+    n, nnz, meta = 16777216, 449455096, 2062568
+    # FP16 z (FP32 work vectors): B values 2 B per nonzero in each of the three
+    # launches; vectors: first 4 x 4 B, inner 6 x 4 B, last 4 x 4 B + r (4) + z (2)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 32) == 3 * (2 * nnz + meta) + n * (16 + 24 + 16 + 4 + 2)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 64) == 3 * (2 * nnz + meta) + n * (16 + 24 + 16 + 8 + 2)
+    # FP64 z: FP64 work vectors
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 64, 64) == 3 * (2 * nnz + meta) + n * (32 + 48 + 32 + 8 + 8)
+    # degree 2: one step that is first and last
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 32, 32, degree=2) == 2 * nnz + meta + n * (8 + 4 + 4)
+
+
 def test_stored_traffic_requires_matching_sources(monkeypatch, tmp_path):
     from paper_2505_04155_amd import build
     f = tmp_path / "counters.txt"
     f.write_text("# header\nsource_digest abc123\nkernel k_spmv\ntraffic_bytes_per_launch 112041016\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     monkeypatch.setattr(build, "source_digest", lambda: "abc123")
-    assert bench.stored_traffic() == 112041016
+    assert bench.stored_traffic(str(f)) == 112041016
     monkeypatch.setattr(build, "source_digest", lambda: "other")
-    assert bench.stored_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.stored_traffic() is None
+    assert bench.stored_traffic(str(f)) is None
+    assert bench.stored_traffic(str(tmp_path / "missing.txt")) is None
 
 
 def test_committed_summary_is_parseable():
