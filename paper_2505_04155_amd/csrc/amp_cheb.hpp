@@ -11,6 +11,15 @@
 // for u_z = FP32 / FP16); B products accumulate in that precision; z is
 // rounded to u_z.  One streaming kernel forms v, then m-1 product kernels
 // each take one step; the last one also forms z and the partials of rho.
+//
+// The gathered vectors (v, dir) of each precision are separate allocations
+// with a zero margin of `guard` elements before and after (guard >= the
+// largest |column offset| of any offset-mode slice).  An offset-mode slot
+// then reads its neighbour at row + offset without a range test: a slot
+// whose neighbour lies outside [0, np) has B value 0 and reads a zero of the
+// margin.  Each such gather addresses a wave-uniform base (vector + offset)
+// plus one per-lane row offset shared by all slots, and each FP16 value load
+// the slice's uniform base plus the lane's offset.
 #pragma once
 
 #include "amp_kernels.hpp"
@@ -19,17 +28,36 @@ namespace amp {
 
 constexpr int kChebMax = 16;
 
+// Threads of the polynomial-step kernel and the minimum waves per SIMD it
+// is compiled for (8 caps it at 64 VGPRs: 8 work-groups' worth of loads in
+// flight per CU instead of 4).
+#ifndef AMP_NTC
+#define AMP_NTC 512
+#endif
+constexpr int NTC = AMP_NTC;
+#ifndef AMP_CHEB_WAVES
+#define AMP_CHEB_WAVES 8
+#endif
+
+// Column-offset lists as constant-address-space memory (they do not change
+// during a launch): wave-uniform reads of them compile to scalar loads.
+typedef const __attribute__((address_space(4))) int32_t *KOffs;
+
 struct Cheb {
     const SliceRec *srec;
     const int64_t *sptr;
     const int32_t *col;
     const int32_t *soff, *offs;
+    KOffs koffs;             // offs, for the scalar reads of the step kernel
     const half_t *b16;       // B's values in FP16
     const double *isq64;     // D^{-1/2}
     const float *isq32;
-    void *v, *res, *w;       // work vectors (np doubles each, read as float for FP32)
-    void *dir[2];
+    // work vectors by precision (0: FP64, 1: FP32), np entries each; v and
+    // dir carry the zero margins described above
+    void *v[2], *res[2], *w[2];
+    void *dir[2][2];
     int64_t np, nslices;
+    int64_t guard;           // zero margin of v and dir, in elements
     int32_t *step_iter;      // nullable: iteration each timed step launch performed (-1: passed through)
     int step_launch;         // index of this launch in step_iter
     int degree;
@@ -46,7 +74,7 @@ __device__ __forceinline__ void cheb_v_body(const St &s, const Bufs &B, const Ch
     typedef typename Prec<UZ>::C CZ;
     const TRS *r = (const TRS *)B.r[pslot(RS)];
     TR *rn = (TR *)B.r[pslot(UR)];
-    CZ *v = (CZ *)P.v;
+    CZ *v = (CZ *)P.v[UZ == 64 ? 0 : 1];
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     const TR w = (TR)s.omega_eff;
     AMP_STREAM_LOOP(i, P.np, wg) {
@@ -124,85 +152,150 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 // RLAST: 0 for an inner step; for the last step, the precision of r (the
 // step then forms z and the partials of rho = r^T z).
 template <int UZ, bool FIRST, int RLAST, int BS>
-__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, int k, int din,
-                                               double &rho, double &mz) {
+__device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, double c1d,
+                                               double c2d, int din, double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
-    const CZ *v = (const CZ *)P.v;
-    CZ *res = (CZ *)P.res;
-    CZ *w = (CZ *)P.w;
-    const CZ *dk = (const CZ *)P.dir[din];
-    CZ *dn = (CZ *)P.dir[din ^ 1];
+    constexpr int cp = (UZ == 64) ? 0 : 1;
+    const CZ *v = (const CZ *)P.v[cp];
+    CZ *res = (CZ *)P.res[cp];
+    CZ *w = (CZ *)P.w[cp];
+    // (selects, not indexing: an argument array indexed at run time would be
+    // copied to private memory)
+    const CZ *dk = (const CZ *)(din ? P.dir[cp][1] : P.dir[cp][0]);
+    CZ *dn = (CZ *)(din ? P.dir[cp][0] : P.dir[cp][1]);
+    const CZ *g = FIRST ? v : dk;   // the gathered vector
     const CZ inv_theta = (CZ)P.inv_theta;
-    const CZ c1 = (CZ)P.c1[k], c2 = (CZ)P.c2[k];
+    const CZ c1 = (CZ)c1d, c2 = (CZ)c2d;
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     TZ *z = (TZ *)B.z[pslot(UZ)];
     typedef typename Prec<(RLAST == 64 ? 64 : 32)>::T TRL;
     const TRL *rl = (const TRL *)B.r[pslot(RLAST == 64 ? 64 : 32)];
-    const bool first = FIRST;
     constexpr bool last = RLAST != 0;
-    auto dval = [&](int64_t j) -> CZ {
-        if (FIRST) return v[j] * inv_theta;
-        return dk[j];
-    };
+    // the direction at a gathered entry (the first step's is v / theta)
+    auto dfrom = [&](CZ gv) -> CZ { return FIRST ? gv * inv_theta : gv; };
     AMP_SLICE_LOOP(P, sl, wg, BS) {
         progress_prio(sl - slo_, shi_ - slo_);
         AMP_SLICE_ROW(P, sl, lane, row, base, wd, BS);
         // the row's own operands are loaded before the product, so their
         // latency overlaps it
-        const CZ d0 = dval(row);
-        const CZ wk = first ? (CZ)0 + d0 : w[row];
-        const CZ rk = first ? v[row] : res[row];
+        const uint32_t ru = (uint32_t)row;   // row < np <= 2^29: 32-bit byte offsets
+        const CZ d0 = dfrom(at32(g, ru));
+        const CZ wk = FIRST ? (CZ)0 + d0 : at32((const CZ *)w, ru);
+        const CZ rk = FIRST ? at32(v, ru) : at32((const CZ *)res, ru);
         CZ isq_r = (CZ)0;
         double rr = 0.0;
         if (last) {
-            isq_r = isq[row];
-            rr = (double)rl[row];
+            isq_r = at32(isq, ru);
+            rr = (double)at32(rl, ru);
         }
         CZ acc = (CZ)0;
         // two chunks of slots per pass: all their value loads and gathers are
         // issued before the first product is added (slots past the width
         // repeat a valid slot's loads and add nothing; the sum runs in slot
         // order)
-        with_rec_cols(rec_, P.col, P.offs, P.np, sl, lane, [&](const auto &sc) {
+        if (rec_.soff >= 0) {
+            // the gathered entry of slot j is gb[rowg + offset_j]: gb is the
+            // start of the vector's leading margin, rowg = row + guard, so the
+            // index is never negative and one 32-bit add forms each offset
+            const KOffs ol = P.koffs + rec_.soff;
+            const half_t *bsl = P.b16 + rec_.ptr;   // the slice's values, slot j at bsl[64 j + lane]
+            const CZ *gb = g - P.guard;
+            const uint32_t rowg = (uint32_t)(row + P.guard);
             for (int j0 = 0; j0 < wd; j0 += 2 * kChunk) {
-                int32_t cc[2 * kChunk];
-                bool dg[2 * kChunk];
-                CZ bv[2 * kChunk], dj[2 * kChunk];
-                sc.chunk(j0, wd, cc, dg);
-                sc.chunk(j0 + kChunk < wd ? j0 + kChunk : j0, wd, cc + kChunk, dg + kChunk);
+                const bool full = j0 + 2 * kChunk <= wd;
+                const int j1 = j0 + kChunk < wd ? j0 + kChunk : j0;
+                OffChunk oa, ob;   // scalar loads
 #pragma unroll
-                for (int u = 0; u < 2 * kChunk; ++u) {
+                for (int u = 0; u < kChunk; ++u) {
+                    oa.o[u] = ol[j0 + u];
+                    ob.o[u] = ol[j1 + u];
+                }
+                half_t bv[2 * kChunk];   // converted at use: two values per register while in flight
+                CZ dj[2 * kChunk];
+                if (full) {
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) {
+                        bv[u] = at32(bsl, (uint32_t)(lane + (j0 + u) * SLICE));
+                        bv[kChunk + u] = at32(bsl, (uint32_t)(lane + (j0 + kChunk + u) * SLICE));
+                        dj[u] = at32(gb, rowg + (uint32_t)oa.o[u]);
+                        dj[kChunk + u] = at32(gb, rowg + (uint32_t)ob.o[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2 * kChunk; ++u) acc = acc + (CZ)bv[u] * dfrom(dj[u]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) {
+                        const int ja = j0 + u < wd ? j0 + u : wd - 1, jb = j1 + u < wd ? j1 + u : wd - 1;
+                        bv[u] = at32(bsl, (uint32_t)(lane + ja * SLICE));
+                        bv[kChunk + u] = at32(bsl, (uint32_t)(lane + jb * SLICE));
+                        dj[u] = at32(gb, rowg + (uint32_t)oa.o[u]);
+                        dj[kChunk + u] = at32(gb, rowg + (uint32_t)ob.o[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2 * kChunk; ++u) {
+                        const CZ t = acc + (CZ)bv[u] * dfrom(dj[u]);
+                        acc = (j0 + u < wd) ? t : acc;
+                    }
+                }
+            }
+        } else {
+            // index mode (general sparsity, not the stencil workloads): one
+            // chunk of slots per pass keeps the register budget of the
+            // offset-mode loop
+            const IdxCols sc{P.col + rec_.ptr + lane, row};
+            for (int j0 = 0; j0 < wd; j0 += kChunk) {
+                int32_t cc[kChunk];
+                bool dg[kChunk];
+                half_t bv[kChunk];
+                CZ dj[kChunk];
+                sc.chunk(j0, wd, cc, dg);
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
                     const int j = j0 + u < wd ? j0 + u : wd - 1;
-                    bv[u] = (CZ)P.b16[base + (int64_t)j * SLICE];
-                    dj[u] = dval(cc[u]);
+                    bv[u] = P.b16[base + (int64_t)j * SLICE];
+                    dj[u] = at32(g, (uint32_t)cc[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < 2 * kChunk; ++u) {
-                    const CZ t = acc + bv[u] * dj[u];
+                for (int u = 0; u < kChunk; ++u) {
+                    const CZ t = acc + (CZ)bv[u] * dfrom(dj[u]);
                     acc = (j0 + u < wd) ? t : acc;
                 }
             }
-        });
-        const CZ w1 = first ? wk : wk + d0;
+        }
+        const CZ w1 = FIRST ? wk : wk + d0;
         const CZ r1 = rk - acc;
         const CZ d1 = c1 * d0 + c2 * r1;
         if (!last) {
-            w[row] = w1;
-            res[row] = r1;
-            dn[row] = d1;
+            st32(w, ru, w1);
+            st32(res, ru, r1);
+            st32(dn, ru, d1);
         } else {
             const CZ wm = w1 + d1;
             const TZ zz = (TZ)(isq_r * wm);
-            z[row] = zz;
+            st32(z, ru, zz);
             rho += rr * (double)zz;
             mz = fmax(mz, fabs((double)zz));
         }
     }
 }
 
-__global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int first, int last, int din,
-                                                  const St *in, St *out) {
+// One launch of step k.  STEP: 0 the first step (k = 0), 1 an inner step,
+// 2 the last step (forms z and the partials of rho), 3 both first and last
+// (degree 2).  UZF: the u_z of every iteration when the solve's options fix
+// it (u0 = FP16; or no u_z threshold can be crossed), so that only that
+// precision's path is compiled and the kernel needs fewer registers; 0
+// reads u_z from the state.  A state whose u_z differs from UZF can only
+// come from a non-finite residual (the selector's comparisons fail): it
+// ends the solve as a breakdown.
+// c1, c2: the recurrence coefficients of step k.
+// (the last step also carries the rho reduction and both r precisions:
+// it is compiled for 6 waves per SIMD, at most 80 VGPRs, without spills;
+// the FP64 work-vector variants for 4)
+template <int UZF, int STEP>
+__global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? (STEP >= 2 ? 6 : AMP_CHEB_WAVES) : 4)
+    k_cheb_step(Bufs B, Cheb P, double c1, double c2, int din, const St *in, St *out) {
+    constexpr bool FIRST = STEP == 0 || STEP == 3, LAST = STEP >= 2;
     __shared__ St s;
     const Wg wg = grid_wg();
     load_state(s, in);
@@ -210,27 +303,32 @@ __global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int fi
         store_state(s, out, wg);
         return;
     }
+    if (UZF != 0 && s.uz != UZF) {
+        __syncthreads();
+        if (threadIdx.x == 0) s.status = BREAKDOWN;
+        store_state(s, out, wg);
+        return;
+    }
     if (P.step_iter && wg.lb == 0 && threadIdx.x == 0) P.step_iter[P.step_launch] = s.k;
     double rho = 0.0, mz = 0.0;
-#define AMP_CS_L(UZ, RL)                                                                \
-    do {                                                                                \
-        if (first) cheb_step_body<UZ, true, RL, NTS>(s, B, P, wg, k, din, rho, mz);     \
-        else cheb_step_body<UZ, false, RL, NTS>(s, B, P, wg, k, din, rho, mz);          \
+#define AMP_CS(UZ)                                                                                  \
+    do {                                                                                            \
+        if (!LAST) cheb_step_body<UZ, FIRST, 0, NTC>(s, B, P, wg, c1, c2, din, rho, mz);            \
+        else if (s.ur == 64) cheb_step_body<UZ, FIRST, 64, NTC>(s, B, P, wg, c1, c2, din, rho, mz); \
+        else cheb_step_body<UZ, FIRST, 32, NTC>(s, B, P, wg, c1, c2, din, rho, mz);                 \
     } while (0)
-#define AMP_CS(UZ)                                                      \
-    do {                                                                \
-        if (!last) AMP_CS_L(UZ, 0);                                     \
-        else if (s.ur == 64) AMP_CS_L(UZ, 64);                          \
-        else AMP_CS_L(UZ, 32);                                          \
-    } while (0)
-    if (s.uz == 64) AMP_CS(64);
-    else if (s.uz == 32) AMP_CS(32);
-    else AMP_CS(16);
+    if constexpr (UZF == 64) AMP_CS(64);
+    else if constexpr (UZF == 32) AMP_CS(32);
+    else if constexpr (UZF == 16) AMP_CS(16);
+    else {
+        if (s.uz == 64) AMP_CS(64);
+        else if (s.uz == 32) AMP_CS(32);
+        else AMP_CS(16);
+    }
 #undef AMP_CS
-#undef AMP_CS_L
-    if (last) {
+    if (LAST) {
         double v2[2] = {rho, mz};
-        block_reduce<1, 1, NTS>(v2);
+        block_reduce<1, 1, NTC>(v2);
         rho = v2[0];
         mz = v2[1];
         if (threadIdx.x == 0) {
@@ -241,13 +339,33 @@ __global__ void __launch_bounds__(NTS) k_cheb_step(Bufs B, Cheb P, int k, int fi
     store_state(s, out, wg);
 }
 
+typedef void (*ChebStepFn)(Bufs, Cheb, double, double, int, const St *, St *);
+
+// The step kernel for (UZF, STEP).
+inline ChebStepFn cheb_step_fn(int uzf, int step) {
+#define AMP_F(U)                                        \
+    switch (step) {                                     \
+        case 0: return k_cheb_step<U, 0>;               \
+        case 1: return k_cheb_step<U, 1>;               \
+        case 2: return k_cheb_step<U, 2>;               \
+        default: return k_cheb_step<U, 3>;              \
+    }
+    switch (uzf) {
+        case 16: AMP_F(16)
+        case 32: AMP_F(32)
+        case 64: AMP_F(64)
+        default: AMP_F(0)
+    }
+#undef AMP_F
+}
+
 // Degree 1: z = fl_uz(isq (.) (v / theta)), no product with B.
 template <int UZ>
 __device__ __forceinline__ void cheb_deg1_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, double &rho,
                                                double &mz) {
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
-    const CZ *v = (const CZ *)P.v;
+    const CZ *v = (const CZ *)P.v[UZ == 64 ? 0 : 1];
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
     const CZ inv_theta = (CZ)P.inv_theta;
     TZ *z = (TZ *)B.z[pslot(UZ)];

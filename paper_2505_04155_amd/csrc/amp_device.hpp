@@ -119,6 +119,12 @@ __device__ __forceinline__ T at32(const T *a, uint32_t i) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + i * (uint32_t)sizeof(T));
 }
 
+// a[i] = v through a 32-bit byte offset (as at32).
+template <typename T>
+__device__ __forceinline__ void st32(T *a, uint32_t i, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(a) + i * (uint32_t)sizeof(T)) = v;
+}
+
 // Columns of slots j0 .. j0 + kChunk - 1 of one row of a slice, one functor
 // per storage mode.  Slots at or past the row width w give a valid column
 // (the caller adds nothing for them).

@@ -105,6 +105,7 @@ struct Work {
 
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
+    int64_t guard = 0;   // largest |column offset| of an offset-mode slice, rounded up to 64
     SliceRec *srec = nullptr;
     int64_t *sptr = nullptr;
     int32_t *col = nullptr;
@@ -136,15 +137,23 @@ struct amp_precond_s {
     half_t *b16 = nullptr;
     double *isq64 = nullptr;
     float *isq32 = nullptr;
-    double *cv = nullptr, *cres = nullptr, *cw = nullptr, *cdir[2] = {nullptr, nullptr};
+    // work vectors: one zeroed block per precision, laid out
+    // [G][v][G][dir0][G][dir1][G][res][w] (G = the matrix's guard)
+    double *cblk64 = nullptr;
+    float *cblk32 = nullptr;
+    void *cv[2] = {nullptr, nullptr}, *cres[2] = {nullptr, nullptr}, *cw[2] = {nullptr, nullptr};
+    void *cdir[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
     Cheb cheb() const {
         Cheb P;
         P.srec = A->srec; P.sptr = A->sptr; P.col = A->col; P.soff = A->soff; P.offs = A->offs;
+        P.koffs = reinterpret_cast<KOffs>(reinterpret_cast<uintptr_t>(A->offs));
         P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
-        P.v = cv; P.res = cres; P.w = cw; P.dir[0] = cdir[0]; P.dir[1] = cdir[1];
+        for (int i = 0; i < 2; ++i) {
+            P.v[i] = cv[i]; P.res[i] = cres[i]; P.w[i] = cw[i]; P.dir[i][0] = cdir[i][0]; P.dir[i][1] = cdir[i][1];
+        }
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
-        P.step_iter = nullptr; P.step_launch = 0;
+        P.step_iter = nullptr; P.step_launch = 0; P.guard = A->guard;
         for (int i = 0; i < kChebMax; ++i) { P.c1[i] = c1[i]; P.c2[i] = c2[i]; }
         return P;
     }
@@ -482,6 +491,11 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
         hp[i + 1] = hp[i] + w * SLICE;
     }
     const int64_t noffs = (int64_t)hoffs.size();
+    {
+        int64_t mo = 0;
+        for (const int32_t o : hoffs) mo = std::max<int64_t>(mo, o < 0 ? -(int64_t)o : (int64_t)o);
+        A->guard = round_up(mo, 64);
+    }
     A->slots = hp[ns];
     {
         int64_t index_slots = 0;
@@ -636,10 +650,23 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         M->lam_lo = lam_lo;
         M->lam_hi = lam_hi;
         if ((s = dalloc(&M->b16, A->slots)) != AMP_OK || (s = dalloc(&M->isq64, np)) != AMP_OK ||
-            (s = dalloc(&M->isq32, np)) != AMP_OK || (s = dalloc(&M->cv, np)) != AMP_OK ||
-            (s = dalloc(&M->cres, np)) != AMP_OK || (s = dalloc(&M->cw, np)) != AMP_OK ||
-            (s = dalloc(&M->cdir[0], np)) != AMP_OK || (s = dalloc(&M->cdir[1], np)) != AMP_OK)
+            (s = dalloc(&M->isq32, np)) != AMP_OK)
             return bail(s);
+        const int64_t G = A->guard, blk = 4 * G + 5 * np;
+        if ((s = dalloc(&M->cblk64, blk)) != AMP_OK || (s = dalloc(&M->cblk32, blk)) != AMP_OK) return bail(s);
+        if (hipMemsetAsync(M->cblk64, 0, blk * sizeof(double), st) != hipSuccess ||
+            hipMemsetAsync(M->cblk32, 0, blk * sizeof(float), st) != hipSuccess)
+            return bail(fail(AMP_ERR_HIP, "amp_precond_create: clearing the work vectors failed"));
+        M->cv[0] = M->cblk64 + G;
+        M->cdir[0][0] = M->cblk64 + 2 * G + np;
+        M->cdir[0][1] = M->cblk64 + 3 * G + 2 * np;
+        M->cres[0] = M->cblk64 + 4 * G + 3 * np;
+        M->cw[0] = M->cblk64 + 4 * G + 4 * np;
+        M->cv[1] = M->cblk32 + G;
+        M->cdir[1][0] = M->cblk32 + 2 * G + np;
+        M->cdir[1][1] = M->cblk32 + 3 * G + 2 * np;
+        M->cres[1] = M->cblk32 + 4 * G + 3 * np;
+        M->cw[1] = M->cblk32 + 4 * G + 4 * np;
         // coefficients of the three-term recurrence
         const double theta = 0.5 * (lam_hi + lam_lo), delta = 0.5 * (lam_hi - lam_lo), sigma = theta / delta;
         double rho = 1.0 / sigma;
@@ -669,7 +696,7 @@ extern "C" void amp_precond_destroy(amp_precond M) {
     if (!M) return;
     dfree(M->d64); dfree(M->d32); dfree(M->d16);
     dfree(M->b16); dfree(M->isq64); dfree(M->isq32);
-    dfree(M->cv); dfree(M->cres); dfree(M->cw); dfree(M->cdir[0]); dfree(M->cdir[1]);
+    dfree(M->cblk64); dfree(M->cblk32);
     delete M;
 }
 
@@ -806,7 +833,18 @@ struct Driver {
     bool timing = false;
     int launches = 0;  // product launches enqueued (timing)
     int claunches = 0; // Chebyshev step launches enqueued (timing)
+    int uzf = 0;       // u_z of every iteration when the options fix it, else 0
 };
+
+// The u_z every iteration of a solve with these options uses, or 0 if the
+// selector can lower it: u_z starts at u0 and drops only when nu_k falls
+// below a positive threshold (nu_k >= 0 for a finite residual).
+static int fixed_uz(const amp_options &o) {
+    if (o.u0 == 16) return 16;
+    if (o.u0 == 32 && !(o.tau_zh > 0.0)) return 32;
+    if (o.u0 == 64 && !(o.tau_zs > 0.0) && !(o.tau_zh > 0.0)) return 64;
+    return 0;
+}
 
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
 static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
@@ -821,18 +859,21 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     for (int k = 0; k + 1 < m; ++k) {
         St *si = (k == 0) ? &sb[ST_PREI] : &sb[(k - 1) % 2 ? ST_CH1 : ST_CH0];
         St *so = (k == m - 2) ? out : &sb[k % 2 ? ST_CH1 : ST_CH0];
+        const int step = (k == 0 && k == m - 2) ? 3 : (k == m - 2) ? 2 : (k == 0) ? 0 : 1;
+        const ChebStepFn fn = cheb_step_fn(d.uzf, step);
         Work &w = d.A->w;
         if (d.timing && d.claunches < w.ccap) {
             Cheb Pt = P;
             Pt.step_iter = w.citer;
             Pt.step_launch = d.claunches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
-            hipExtLaunchKernelGGL(k_cheb_step, dim3(d.gl), dim3(NTS), 0, d.st, w.cev[2 * d.claunches],
-                                  w.cev[2 * d.claunches + 1], 0, d.B, Pt, k, (int)(k == 0), (int)(k == m - 2),
-                                  k % 2, (const St *)si, so);
+            hipExtLaunchKernelGGL(fn, dim3(d.gl), dim3(NTC), 0, d.st, w.cev[2 * d.claunches],
+                                  w.cev[2 * d.claunches + 1], 0, d.B, Pt, P.c1[k], P.c2[k], k % 2,
+                                  (const St *)si, so);
             d.claunches += 1;
         } else {
-            k_cheb_step<<<d.gl, NTS, 0, d.st>>>(d.B, P, k, k == 0, k == m - 2, k % 2, si, so);
+            hipLaunchKernelGGL(fn, dim3(d.gl), dim3(NTC), 0, d.st, d.B, P, P.c1[k], P.c2[k], k % 2, (const St *)si,
+                               so);
         }
     }
 }
@@ -997,6 +1038,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     }
     const int64_t n = A->n;
     d.cfg = make_cfg(o, A, M, tol, maxit);
+    d.uzf = fixed_uz(o);
     if (solo) d.cfg.g_stream = d.cfg.g_slice = d.cfg.g_pre = 1;
     d.S = A->sell();
     d.B = make_bufs(A, M);
@@ -1291,6 +1333,7 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
     d.st = as_stream(stream);
     d.sb = w.st;
     d.cfg = make_cfg(o, A, M, tol, maxit);
+    d.uzf = fixed_uz(o);
     d.cfg.ring = w.ring;
     d.S = A->sell();
     d.B = make_bufs_w(w, M);
@@ -1793,6 +1836,7 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
         d.M = M;
         d.st = st;
         d.cfg = make_cfg(o, A, M, 1.0, 1);
+        d.uzf = u_z;
         d.S = A->sell();
         d.B = B;
         d.gs = d.cfg.g_stream;
