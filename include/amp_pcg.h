@@ -227,7 +227,7 @@ amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b, double *x
  * call (serving loops, harnesses that forbid hipMalloc): the same kernels,
  * state chain and results as amp_pcg_solve (bitwise the same x and
  * iterations), with every work vector, partial array, state slot and the
- * residual window held in the library's own device array of about 21.6 MB
+ * residual window held in the library's own device array of about 25 MB
  * per GPU (allocated when the library's code is loaded on that device, held
  * until the process ends), instead of the matrix handle's work buffers.
  * The call makes no hipMalloc, hipFree, event, stream or pinned-memory

@@ -38,10 +38,11 @@ constexpr int NTC = AMP_NTC;
 #ifndef AMP_CHEB_WAVES
 #define AMP_CHEB_WAVES 8
 #endif
-
-// Column-offset lists as constant-address-space memory (they do not change
-// during a launch): wave-uniform reads of them compile to scalar loads.
-typedef const __attribute__((address_space(4))) int32_t *KOffs;
+// 1: slices dealt to waves round-robin within each XCD's share
+// (xcd_wave_slices); 0: contiguous ranges per work-group
+#ifndef AMP_CHEB_STRIDED
+#define AMP_CHEB_STRIDED 1
+#endif
 
 struct Cheb {
     const SliceRec *srec;
@@ -174,9 +175,23 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     constexpr bool last = RLAST != 0;
     // the direction at a gathered entry (the first step's is v / theta)
     auto dfrom = [&](CZ gv) -> CZ { return FIRST ? gv * inv_theta : gv; };
+#if AMP_CHEB_STRIDED
+    int64_t sfirst_, sstep_, shi_;
+    xcd_wave_slices(P.nslices, wg, BS / WAVE, __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), sfirst_, sstep_,
+                    shi_);
+    uint32_t nrec_ = rec_word(P.srec, sfirst_, shi_);
+    for (int64_t sl = sfirst_; sl < shi_; sl += sstep_) {
+        progress_prio(sl - sfirst_, shi_ - sfirst_);
+        const SliceRec rec_ = rec_from(nrec_);
+        nrec_ = rec_word(P.srec, sl + sstep_, shi_);
+        const int lane = threadIdx.x % WAVE;
+        const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
+        const int wd = rec_.width;
+#else
     AMP_SLICE_LOOP(P, sl, wg, BS) {
         progress_prio(sl - slo_, shi_ - slo_);
         AMP_SLICE_ROW(P, sl, lane, row, base, wd, BS);
+#endif
         // the row's own operands are loaded before the product, so their
         // latency overlaps it
         const uint32_t ru = (uint32_t)row;   // row < np <= 2^29: 32-bit byte offsets

@@ -19,10 +19,17 @@ constexpr int NT = AMP_NT;   // threads per work-group of the streaming kernels 
 #define AMP_NTS 256
 #endif
 constexpr int NTS = AMP_NTS; // threads per work-group of the sliced-ELL kernels (a multiple of 64)
-// Minimum waves per SIMD the product kernels are compiled for (8 caps them at
-// 64 VGPRs); 1 leaves the register allocation to the compiler.
+// Threads per work-group of the iteration's product kernel, and the minimum
+// waves per SIMD its FP16/FP32 variants are compiled for.  Measured on the
+// 256^3 Q1 solve (product launch average): 16 slots per pass at 4 waves
+// 626 us, at 5 or 6 waves 637-658 us; 8 slots per pass 649 us at 4-6
+// waves and 773 us at 8 (64 VGPRs); 24 or 32 slots per pass 880-1256 us.
+#ifndef AMP_NTP
+#define AMP_NTP 512
+#endif
+constexpr int NTP = AMP_NTP;
 #ifndef AMP_SPMV_WAVES
-#define AMP_SPMV_WAVES 1
+#define AMP_SPMV_WAVES 4
 #endif
 constexpr int WAVE = 64;     // CDNA wavefront width
 constexpr int SLICE = 64;    // sliced-ELL slice height (one row per lane)
@@ -83,6 +90,10 @@ struct alignas(16) SliceRec {
     int32_t width;  // slots per row
 };
 
+// Column-offset lists as constant-address-space memory (they do not change
+// during a launch): wave-uniform reads of them compile to scalar loads.
+typedef const __attribute__((address_space(4))) int32_t *KOffs;
+
 struct Sell {
     int64_t n, np, nslices;
     const SliceRec *srec;
@@ -90,6 +101,8 @@ struct Sell {
     const int32_t *col;
     const int32_t *soff;  // per slice: start of its offsets in offs, or -1
     const int32_t *offs;
+    KOffs koffs;          // offs, for scalar reads
+    int64_t guard;        // zero margin (elements) around the gathered z and p vectors
     const double *v64;   // FP64 values
     const float *v32;    // FP32 values, diagonal slot = fl32(row sum) (difference form)
     const float *v32p;   // FP32 values, plain
@@ -253,6 +266,27 @@ __device__ __forceinline__ void block_range(int64_t total, int64_t quantum, int 
     const int64_t u1 = u0 + per + (lb < rem ? 1 : 0);
     lo = u0 * quantum;
     hi = u1 * quantum < total ? u1 * quantum : total;
+}
+
+// Slices of one wave when the work is dealt per XCD: XCD x (logical
+// work-groups [x G/8, (x+1) G/8), see xcd_index) owns the x-th eighth of the
+// slices, and that share is dealt round-robin to the XCD's waves, so the
+// slices in flight on an XCD at any moment are one compact window (compact
+// DRAM pages; the window's neighbours are in the XCD's L2).  The wave's
+// slices are first, first + stride, ... below hi.
+__device__ __forceinline__ void xcd_wave_slices(int64_t nslices, Wg wg, int nw, int wave, int64_t &first,
+                                                int64_t &stride, int64_t &hi) {
+    if (wg.G >= NXCD && wg.G % NXCD == 0) {
+        const int per = wg.G / NXCD, x = wg.lb / per, lbx = wg.lb % per;
+        int64_t lo;
+        block_range(nslices, 1, x, NXCD, lo, hi);
+        first = lo + (int64_t)lbx * nw + wave;
+        stride = (int64_t)per * nw;
+    } else {
+        first = (int64_t)wg.lb * nw + wave;
+        stride = (int64_t)wg.G * nw;
+        hi = nslices;
+    }
 }
 
 // Lane l's value of v (l uniform).

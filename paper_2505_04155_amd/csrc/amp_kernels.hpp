@@ -206,52 +206,6 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t 
     return DIFF ? dterm + acc : acc;
 }
 
-// The FP32 product for two rows of two slices at once (both slices in
-// offset mode, of equal width): every chunk's loads of both rows are issued
-// before either row is summed.  Each row's sum is formed exactly as by
-// row_dot32.  (For FP64 products the doubled registers cost more than the
-// overlap gains; they run one slice at a time.)
-template <bool DIFF, typename PF>
-__device__ __forceinline__ void row_dot32x2(const Sell &A, const OffCols &s1, const OffCols &s2, int64_t b1,
-                                            int64_t b2, int w, float pi1, float pi2, PF pval, float &q1,
-                                            float &q2) {
-    const float *vals = DIFF ? A.v32 : A.v32p;
-    float a1 = 0.0f, a2 = 0.0f, t1d = 0.0f, t2d = 0.0f;
-    for (int j0 = 0; j0 < w; j0 += kChunk) {
-        int32_t c1[kChunk], c2[kChunk];
-        bool d1[kChunk], d2[kChunk];
-        float v1[kChunk], v2[kChunk], p1[kChunk], p2[kChunk];
-        s1.chunk(j0, w, c1, d1);
-        s2.chunk(j0, w, c2, d2);
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const int j = j0 + u < w ? j0 + u : w - 1;
-            v1[u] = vals[b1 + (int64_t)j * SLICE];
-            v2[u] = vals[b2 + (int64_t)j * SLICE];
-            p1[u] = (float)pval(c1[u]);
-            p2[u] = (float)pval(c2[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const bool in = j0 + u < w;
-            if (!DIFF) {
-                const float x1 = a1 + v1[u] * p1[u], x2 = a2 + v2[u] * p2[u];
-                a1 = in ? x1 : a1;
-                a2 = in ? x2 : a2;
-            } else {
-                const float e1 = t1d + v1[u] * p1[u], o1 = a1 + v1[u] * (p1[u] - pi1);
-                const float e2 = t2d + v2[u] * p2[u], o2 = a2 + v2[u] * (p2[u] - pi2);
-                t1d = (in && d1[u]) ? e1 : t1d;
-                a1 = (in && !d1[u]) ? o1 : a1;
-                t2d = (in && d2[u]) ? e2 : t2d;
-                a2 = (in && !d2[u]) ? o2 : a2;
-            }
-        }
-    }
-    q1 = DIFF ? t1d + a1 : a1;
-    q2 = DIFF ? t2d + a2 : a2;
-}
-
 // Slices of this work-group: contiguous range, one slice per wave at a time,
 // the next slice's descriptor in flight while the current one is processed.
 #define AMP_SLICE_LOOP(A, sl, wg, BS)                                                    \
@@ -649,6 +603,22 @@ __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part
 // k_spmv: p = z + beta p_{k-1} (u_z), q = A p (u_r), gamma = q^T p
 // ----------------------------------------------------------------------------
 
+// Slots per pass of the product's offset-mode loop (8: one chunk, 16: two).
+#ifndef AMP_SPMV_SPC
+#define AMP_SPMV_SPC 16
+#endif
+
+// p = z + beta p_old (u_z) for the work-group's rows, q = A p (u_r) with the
+// p entries recomputed at every gathered column, gamma and max|p| partials.
+// Offset-mode slices read their neighbours from the guarded views of z and
+// p_old (index = column + guard, no range test: a slot whose column lies
+// outside [0, np) has value 0 and reads a zero of the margin); the values
+// load from the slice's scalar base plus the lane's offset, the offsets are
+// scalar loads.  Sums run in slot order as in row_dot64 / row_dot32: FP64
+// values and accumulation for u_r = FP64; FP32 for u_r = FP32, in the
+// row-sum/difference form when DIFF (off-diagonal slots add
+// a_ij (p_j - p_i), then the diagonal slot's row sum adds s_i p_i).
+// Slices are dealt per XCD (xcd_wave_slices).
 // PRIO: issue priority by progress (progress_prio); off where the
 // work-groups sharing a CU belong to different systems with unequal work.
 template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true>
@@ -657,74 +627,103 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     typedef typename Prec<UZ>::T TZ;
     typedef typename Prec<UZ>::C CZ;
     typedef typename Prec<UR>::T TQ;
-    typedef typename Prec<UR>::C CQ;
-    const TZ *z = (const TZ *)zv;
-    const TZ *po = (const TZ *)pov;
+    typedef typename Prec<UR>::C CA;   // value plane and accumulation type
+    const TZ *zg = (const TZ *)zv - A.guard;
+    const TZ *pg = (const TZ *)pov - A.guard;
     TZ *pn = (TZ *)pnv;
     TQ *q = (TQ *)qv;
+    const CA *vals = (UR == 64) ? (const CA *)A.v64 : (DIFF ? (const CA *)A.v32 : (const CA *)A.v32p);
     const CZ beta = (CZ)beta_d;
-    auto pval = [&](int64_t c) -> TZ {
-        if (FIRST) return at32(z, (uint32_t)c);
-        return (TZ)((CZ)at32(z, (uint32_t)c) + beta * (CZ)at32(po, (uint32_t)c));
+    constexpr int SPC = AMP_SPMV_SPC, NW = BS / WAVE, NCH = SPC / kChunk;
+    static_assert(SPC % kChunk == 0 && SPC >= kChunk, "whole chunks per pass");
+    // p at guarded index i
+    auto pval = [&](uint32_t i) -> TZ {
+        if (FIRST) return at32(zg, i);
+        return (TZ)((CZ)at32(zg, i) + beta * (CZ)at32(pg, i));
     };
-    constexpr int NW = BS / WAVE;
     const int lane = threadIdx.x % WAVE;
-    // one slice: the general path (either storage mode)
-    auto one = [&](int64_t sl, const SliceRec &rec_) {
-        const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
-        const int w = rec_.width;
-        const TZ pi = pval(row);
-        if (pn) pn[row] = pi;
+    int64_t sfirst, sstep, shi;
+    xcd_wave_slices(A.nslices, wg, NW, __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), sfirst, sstep, shi);
+    uint32_t nrec = rec_word(A.srec, sfirst, shi);
+    for (int64_t sl = sfirst; sl < shi; sl += sstep) {
+        if (PRIO) progress_prio(sl - sfirst, shi - sfirst);
+        const SliceRec rec = rec_from(nrec);
+        nrec = rec_word(A.srec, sl + sstep, shi);
+        const int64_t row = sl * SLICE + lane;
+        const uint32_t ru = (uint32_t)row, rowg = (uint32_t)(row + A.guard);   // < 2^31
+        const int w = rec.width;
+        const TZ pi = pval(rowg);
+        if (pn) st32(pn, ru, pi);
         mp = fmax(mp, fabs((double)pi));
-        TQ qq = 0;
-        AMP_WITH_COLS(A, sl, lane, sc) {
-            if constexpr (UR == 64) qq = (TQ)row_dot64(A, sc, base, w, pval);
-            else qq = (TQ)row_dot32<DIFF>(A, sc, base, w, (float)pi, pval);
-        });
-        q[row] = qq;
-        gam += (double)qq * (double)pi;
-    };
-    // FP32 products: slices sl and sl + NW of this wave's sequence are
-    // processed together (the sequence and every per-thread sum keep the
-    // one-at-a-time order).
-    int64_t slo_, shi_;
-    block_range(A.nslices, 1, wg.lb, wg.G, slo_, shi_);
-    const int64_t sfirst = slo_ + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    uint32_t nr1 = rec_word(A.srec, sfirst, shi_), nr2 = rec_word(A.srec, sfirst + NW, shi_);
-    for (int64_t sl = sfirst; sl < shi_; sl += 2 * NW) {
-        if (PRIO) progress_prio(sl - slo_, shi_ - slo_);
-        const int64_t sl2 = sl + NW;
-        const bool two = sl2 < shi_;
-        const SliceRec r1 = rec_from(nr1), r2 = rec_from(nr2);
-        nr1 = rec_word(A.srec, sl + 2 * NW, shi_);
-        nr2 = rec_word(A.srec, sl + 3 * NW, shi_);
-        if (UR == 32 && two && r1.soff >= 0 && r2.soff >= 0 && r1.width == r2.width) {
-            const int64_t row1 = sl * SLICE + lane, row2 = sl2 * SLICE + lane;
-            const TZ pi1 = pval(row1), pi2 = pval(row2);
-            const OffCols c1{A.offs + r1.soff, row1, A.np}, c2{A.offs + r2.soff, row2, A.np};
-            CQ q1 = 0, q2 = 0;
-            if constexpr (UR == 32)
-                row_dot32x2<DIFF>(A, c1, c2, r1.ptr + lane, r2.ptr + lane, r1.width, (float)pi1, (float)pi2, pval,
-                                  q1, q2);
-            const TQ qq1 = (TQ)q1, qq2 = (TQ)q2;
-            if (pn) {
-                pn[row1] = pi1;
-                pn[row2] = pi2;
+        const CA pic = (CA)pi;
+        CA acc = (CA)0, dterm = (CA)0;
+        auto add = [&](CA v, CA pj, bool dg, bool in) {
+            if (UR == 64 || !DIFF) {
+                const CA t = acc + v * pj;
+                acc = in ? t : acc;
+            } else {
+                const CA td = dterm + v * pj;
+                const CA to = acc + v * (pj - pic);
+                dterm = (in && dg) ? td : dterm;
+                acc = (in && !dg) ? to : acc;
             }
-            mp = fmax(mp, fabs((double)pi1));
-            mp = fmax(mp, fabs((double)pi2));
-            q[row1] = qq1;
-            q[row2] = qq2;
-            gam += (double)qq1 * (double)pi1;
-            gam += (double)qq2 * (double)pi2;
+        };
+        if (rec.soff >= 0) {
+            const KOffs ol = A.koffs + rec.soff;
+            const CA *vs = vals + rec.ptr;   // the slice's values, slot j at vs[64 j + lane]
+            for (int j0 = 0; j0 < w; j0 += SPC) {
+                // a chunk's offsets come from the list only where it has them
+                // (lists are padded to whole chunks); a chunk past the width
+                // reuses the first chunk's
+                int32_t o[SPC];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int jc = (j0 + ch * kChunk < w) ? j0 + ch * kChunk : j0;
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) o[ch * kChunk + u] = ol[jc + u];   // scalar loads
+                }
+                CA v[SPC];
+                TZ pj[SPC];
+                const bool full = j0 + SPC <= w;
+#pragma unroll
+                for (int u = 0; u < SPC; ++u) {
+                    const int j = full ? j0 + u : (j0 + u < w ? j0 + u : w - 1);
+                    v[u] = at32(vs, (uint32_t)(lane + j * SLICE));
+                    pj[u] = pval(rowg + (uint32_t)o[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < SPC; ++u) add(v[u], (CA)pj[u], o[u] == 0, full || j0 + u < w);
+            }
         } else {
-            one(sl, r1);
-            if (two) one(sl2, r2);
+            const IdxCols sc{A.col + rec.ptr + lane, row};
+            const int64_t base = rec.ptr + lane;
+            for (int j0 = 0; j0 < w; j0 += kChunk) {
+                int32_t c[kChunk];
+                bool dg[kChunk];
+                CA v[kChunk];
+                TZ pj[kChunk];
+                sc.chunk(j0, w, c, dg);
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const int j = j0 + u < w ? j0 + u : w - 1;
+                    v[u] = vals[base + (int64_t)j * SLICE];
+                    pj[u] = pval((uint32_t)(c[u] + A.guard));
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) add(v[u], (CA)pj[u], dg[u], j0 + u < w);
+            }
         }
+        const TQ qq = (TQ)((UR == 32 && DIFF) ? dterm + acc : acc);
+        st32(q, ru, qq);
+        gam += (double)qq * (double)pi;
     }
 }
 
-template <int BS, bool PRIO = true>
+// UZF: the u_z of every iteration when the solve's options fix it (only
+// that precision's bodies are compiled), else 0 (read from the state).  A
+// state whose u_z differs from UZF can only come from a non-finite residual:
+// it ends the solve as a breakdown.
+template <int BS, bool PRIO = true, int UZF = 0>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg, const Early &e) {
     __shared__ St s;
@@ -759,6 +758,11 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
         return;
     }
     if (c.spmv_iter && wg.lb == 0 && threadIdx.x == 0) c.spmv_iter[c.spmv_launch] = k;
+    if (UZF != 0 && uz != UZF) {
+        if (threadIdx.x == 0) s.status = BREAKDOWN;
+        store_state(s, out, wg);
+        return;
+    }
     const bool first = (k == 0);
     double gam = 0.0, mp = 0.0;
 #define AMP_SP(UZ, UR, DF)                                                                                       \
@@ -770,19 +774,21 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
             spmv_p_body<UZ, UR, DF, false, BS, PRIO>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],                \
                                                  B.q[pslot(UR)], beta, gam, mp);                                \
     } while (0)
-    if (ur == 64) {
-        if (uz == 64) AMP_SP(64, 64, false);
-        else if (uz == 32) AMP_SP(32, 64, false);
-        else AMP_SP(16, 64, false);
-    } else if (c.diff) {
-        if (uz == 64) AMP_SP(64, 32, true);
-        else if (uz == 32) AMP_SP(32, 32, true);
-        else AMP_SP(16, 32, true);
-    } else {
-        if (uz == 64) AMP_SP(64, 32, false);
-        else if (uz == 32) AMP_SP(32, 32, false);
-        else AMP_SP(16, 32, false);
+#define AMP_SP_R(UZ)                          \
+    do {                                      \
+        if (ur == 64) AMP_SP(UZ, 64, false);  \
+        else if (c.diff) AMP_SP(UZ, 32, true); \
+        else AMP_SP(UZ, 32, false);           \
+    } while (0)
+    if constexpr (UZF == 64) AMP_SP_R(64);
+    else if constexpr (UZF == 32) AMP_SP_R(32);
+    else if constexpr (UZF == 16) AMP_SP_R(16);
+    else {
+        if (uz == 64) AMP_SP_R(64);
+        else if (uz == 32) AMP_SP_R(32);
+        else AMP_SP_R(16);
     }
+#undef AMP_SP_R
 #undef AMP_SP
     double v2[2] = {gam, mp};
     block_reduce<1, 1, BS>(v2);
@@ -795,16 +801,28 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     store_state(s, out, wg);
 }
 
-__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv(const St *in, const double *part, int gpart, int grid,
-                                                                Cfg c, Sell A, Bufs B, St *out) {
-    spmv_stage<NTS>(c, A, B, in, out, launch_wg(grid),
-                    Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
+template <int UZF>
+__global__ void __launch_bounds__(NTP, (UZF == 16 || UZF == 32) ? AMP_SPMV_WAVES : 4)
+    k_spmv(const St *in, const double *part, int gpart, int grid, Cfg c, Sell A, Bufs B, St *out) {
+    spmv_stage<NTP, true, UZF>(c, A, B, in, out, launch_wg(grid),
+                               Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
+}
+
+typedef void (*SpmvFn)(const St *, const double *, int, int, Cfg, Sell, Bufs, St *);
+
+inline SpmvFn spmv_fn(int uzf) {
+    switch (uzf) {
+        case 16: return k_spmv<16>;
+        case 32: return k_spmv<32>;
+        case 64: return k_spmv<64>;
+        default: return k_spmv<0>;
+    }
 }
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
 // otherwise p = z + beta p_old as in the iteration.
 template <int UZ, int UR, bool DIFF>
-__global__ void __launch_bounds__(NTS, AMP_SPMV_WAVES) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
+__global__ void __launch_bounds__(NTS) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
                                                    int first, double beta, double *part) {
     double gam = 0.0, mp = 0.0;
     const Wg wg = grid_wg();

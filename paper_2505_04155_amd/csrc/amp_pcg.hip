@@ -74,6 +74,9 @@ static inline bool valid_prec(int u) { return u == 64 || u == 32 || u == 16; }
 
 struct Work {
     int64_t np = 0;
+    // z and the two p buffers of each precision, gathered by the product
+    // kernel: one zeroed block per precision, [G][z][G][p0][G][p1][G]
+    void *gblk[3] = {nullptr, nullptr, nullptr};
     double *x = nullptr, *b = nullptr;
     double *r64 = nullptr, *z64 = nullptr, *q64 = nullptr;
     float *r32 = nullptr, *z32 = nullptr, *q32 = nullptr;
@@ -118,6 +121,8 @@ struct amp_matrix_s {
         Sell s;
         s.n = n; s.np = np; s.nslices = nslices; s.srec = srec; s.sptr = sptr; s.col = col;
         s.soff = soff; s.offs = offs;
+        s.koffs = reinterpret_cast<KOffs>(reinterpret_cast<uintptr_t>(offs));
+        s.guard = guard;
         s.v64 = v64; s.v32 = v32; s.v32p = v32p;
         return s;
     }
@@ -175,9 +180,11 @@ static int grid_slices(int64_t nslices) { return fit_grid((nslices + NTS / WAVE 
 
 static void free_work(Work &w) {
     dfree(w.x); dfree(w.b);
-    dfree(w.r64); dfree(w.z64); dfree(w.q64);
-    dfree(w.r32); dfree(w.z32); dfree(w.q32); dfree(w.z16);
-    for (int i = 0; i < 2; ++i) { dfree(w.p64[i]); dfree(w.p32[i]); dfree(w.p16[i]); }
+    dfree(w.r64); dfree(w.q64);
+    dfree(w.r32); dfree(w.q32);
+    for (auto &g : w.gblk) dfree(g);
+    w.z64 = nullptr; w.z32 = nullptr; w.z16 = nullptr;
+    for (int i = 0; i < 2; ++i) { w.p64[i] = nullptr; w.p32[i] = nullptr; w.p16[i] = nullptr; }
     dfree(w.part); dfree(w.ring); dfree(w.scalar); dfree(w.st);
     if (w.snap) (void)hipHostFree(w.snap);
     w.snap = nullptr;
@@ -206,14 +213,24 @@ static void free_work(Work &w) {
 static amp_status ensure_work(amp_matrix A, hipStream_t st) {
     Work &w = A->w;
     if (w.st) return AMP_OK;
-    const int64_t np = A->np;
+    const int64_t np = A->np, G = A->guard, gb = 3 * np + 4 * G;
     w.np = np;
     AMP_TRY(dalloc(&w.x, np)); AMP_TRY(dalloc(&w.b, np));
-    AMP_TRY(dalloc(&w.r64, np)); AMP_TRY(dalloc(&w.z64, np)); AMP_TRY(dalloc(&w.q64, np));
-    AMP_TRY(dalloc(&w.r32, np)); AMP_TRY(dalloc(&w.z32, np)); AMP_TRY(dalloc(&w.q32, np));
-    AMP_TRY(dalloc(&w.z16, np));
-    for (int i = 0; i < 2; ++i) {
-        AMP_TRY(dalloc(&w.p64[i], np)); AMP_TRY(dalloc(&w.p32[i], np)); AMP_TRY(dalloc(&w.p16[i], np));
+    AMP_TRY(dalloc(&w.r64, np)); AMP_TRY(dalloc(&w.q64, np));
+    AMP_TRY(dalloc(&w.r32, np)); AMP_TRY(dalloc(&w.q32, np));
+    {
+        double *g64 = nullptr;
+        float *g32 = nullptr;
+        half_t *g16 = nullptr;
+        AMP_TRY(dalloc(&g64, gb)); w.gblk[0] = g64;
+        AMP_TRY(dalloc(&g32, gb)); w.gblk[1] = g32;
+        AMP_TRY(dalloc(&g16, gb)); w.gblk[2] = g16;
+        AMP_HIP(hipMemsetAsync(g64, 0, gb * 8, st));
+        AMP_HIP(hipMemsetAsync(g32, 0, gb * 4, st));
+        AMP_HIP(hipMemsetAsync(g16, 0, gb * 2, st));
+        w.z64 = g64 + G; w.p64[0] = g64 + 2 * G + np; w.p64[1] = g64 + 3 * G + 2 * np;
+        w.z32 = g32 + G; w.p32[0] = g32 + 2 * G + np; w.p32[1] = g32 + 3 * G + 2 * np;
+        w.z16 = g16 + G; w.p16[0] = g16 + 2 * G + np; w.p16[1] = g16 + 3 * G + 2 * np;
     }
     AMP_TRY(dalloc(&w.part, 7 * GMAX)); AMP_TRY(dalloc(&w.ring, kRing));
     AMP_TRY(dalloc(&w.scalar, 1)); AMP_TRY(dalloc(&w.st, ST_COUNT));
@@ -221,19 +238,15 @@ static amp_status ensure_work(amp_matrix A, hipStream_t st) {
     for (auto &e : w.ev) AMP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // zero every vector once: the padding tail stays zero for the handle's life
     AMP_HIP(hipMemsetAsync(w.x, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.b, 0, np * 8, st));
-    AMP_HIP(hipMemsetAsync(w.r64, 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.z64, 0, np * 8, st));
+    AMP_HIP(hipMemsetAsync(w.r64, 0, np * 8, st));
     AMP_HIP(hipMemsetAsync(w.q64, 0, np * 8, st));
-    AMP_HIP(hipMemsetAsync(w.r32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.z32, 0, np * 4, st));
-    AMP_HIP(hipMemsetAsync(w.q32, 0, np * 4, st)); AMP_HIP(hipMemsetAsync(w.z16, 0, np * 2, st));
-    for (int i = 0; i < 2; ++i) {
-        AMP_HIP(hipMemsetAsync(w.p64[i], 0, np * 8, st)); AMP_HIP(hipMemsetAsync(w.p32[i], 0, np * 4, st));
-        AMP_HIP(hipMemsetAsync(w.p16[i], 0, np * 2, st));
-    }
+    AMP_HIP(hipMemsetAsync(w.r32, 0, np * 4, st));
+    AMP_HIP(hipMemsetAsync(w.q32, 0, np * 4, st));
     AMP_HIP(hipMemsetAsync(w.part, 0, 7 * GMAX * sizeof(double), st));
     AMP_HIP(hipMemsetAsync(w.ring, 0, kRing * sizeof(double), st));
     AMP_HIP(hipMemsetAsync(w.st, 0, ST_COUNT * sizeof(St), st));
     AMP_HIP(hipStreamSynchronize(st));
-    A->bytes += np * (8 * 5 + 4 * 3 + 2 + 2 * (8 + 4 + 2));
+    A->bytes += np * (8 * 5 + 4 * 3 + 2 + 2 * (8 + 4 + 2)) + 4 * G * (8 + 4 + 2);
     return AMP_OK;
 }
 
@@ -891,14 +904,15 @@ static amp_status enqueue_iterations(Driver &d, int count) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
-            hipExtLaunchKernelGGL(k_spmv, dim3(d.gl), dim3(NTS), 0, d.st, w.tev[2 * d.launches],
+            hipExtLaunchKernelGGL(spmv_fn(d.uzf), dim3(d.gl), dim3(NTP), 0, d.st, w.tev[2 * d.launches],
                                   w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B,
                                   &d.sb[ST_SPMV]);
             d.launches += 1;
             d.cfg.spmv_iter = nullptr;
         } else {
-            k_spmv<<<d.gl, NTS, 0, d.st>>>(&d.sb[ST_PRE], d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &d.sb[ST_SPMV]);
+            hipLaunchKernelGGL(spmv_fn(d.uzf), dim3(d.gl), dim3(NTP), 0, d.st, (const St *)&d.sb[ST_PRE],
+                               (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &d.sb[ST_SPMV]);
         }
         k_update<<<d.gs, NT, 0, d.st>>>(&d.sb[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
                                         &d.sb[ST_RES]);
@@ -1225,12 +1239,14 @@ constexpr int64_t kNoAllocRows = (int64_t)1 << 18;
 // rows: the same vectors, partial arrays, residual window, reduced scalar and
 // state slots as a handle's Work, each region 256-byte aligned.
 struct ScratchLayout {
-    int64_t x, b, r64, z64, q64, p64[2], r32, z32, q32, p32[2], z16, p16[2], part, ring, scalar, st, total;
+    int64_t x, b, r64, q64, r32, q32, g64, g32, g16, part, ring, scalar, st, total;
 };
 
 static constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-static constexpr ScratchLayout scratch_layout(int64_t np) {
+// z, p0, p1 of each precision sit in one block [G][z][G][p0][G][p1][G] with
+// the matrix's guard G (zero margins, as a handle's work buffers).
+static constexpr ScratchLayout scratch_layout(int64_t np, int64_t G) {
     ScratchLayout L{};
     int64_t o = 0;
     auto take = [&](int64_t bytes) {
@@ -1239,11 +1255,11 @@ static constexpr ScratchLayout scratch_layout(int64_t np) {
         return at;
     };
     L.x = take(8 * np); L.b = take(8 * np);
-    L.r64 = take(8 * np); L.z64 = take(8 * np); L.q64 = take(8 * np);
-    L.p64[0] = take(8 * np); L.p64[1] = take(8 * np);
-    L.r32 = take(4 * np); L.z32 = take(4 * np); L.q32 = take(4 * np);
-    L.p32[0] = take(4 * np); L.p32[1] = take(4 * np);
-    L.z16 = take(2 * np); L.p16[0] = take(2 * np); L.p16[1] = take(2 * np);
+    L.r64 = take(8 * np); L.q64 = take(8 * np);
+    L.r32 = take(4 * np); L.q32 = take(4 * np);
+    L.g64 = take(8 * (3 * np + 4 * G));
+    L.g32 = take(4 * (3 * np + 4 * G));
+    L.g16 = take(2 * (3 * np + 4 * G));
     L.part = take(7 * GMAX * (int64_t)sizeof(double));
     L.ring = take(kRing * (int64_t)sizeof(double));
     L.scalar = take(sizeof(double));
@@ -1252,7 +1268,8 @@ static constexpr ScratchLayout scratch_layout(int64_t np) {
     return L;
 }
 
-constexpr int64_t kScratchBytes = scratch_layout(kNoAllocRows).total;   // about 21.6 MB
+constexpr int64_t kNoAllocGuard = (int64_t)1 << 16;   // largest column-offset margin it takes
+constexpr int64_t kScratchBytes = scratch_layout(kNoAllocRows, kNoAllocGuard).total;   // about 25 MB
 
 // The allocation-free solve's working memory: one copy per device, held
 // until the process ends.  Host code never passes this name to a kernel or
@@ -1302,6 +1319,9 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
         return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: " + std::to_string(A->np) +
                                      " padded rows exceed the limit of " + std::to_string(kNoAllocRows) +
                                      " (use amp_pcg_solve)");
+    if (scratch_layout(A->np, A->guard).total > kScratchBytes)
+        return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: the matrix's column offsets need more working memory "
+                                 "than the limit of " + std::to_string(kScratchBytes) + " bytes (use amp_pcg_solve)");
     amp_options o;
     if (opt) o = *opt;
     else amp_options_default(&o);
@@ -1310,17 +1330,21 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
         return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: graph, spmv_timing and solo_rows must be 0");
     void *base = nullptr;
     AMP_TRY(scratch_base(&base));
-    const int64_t np = A->np, n = A->n;
-    const ScratchLayout L = scratch_layout(np);
+    const int64_t np = A->np, n = A->n, G = A->guard;
+    const ScratchLayout L = scratch_layout(np, G);
     unsigned char *m = (unsigned char *)base;
     Work w;   // views into scratch; nothing here is allocated or freed
     w.np = np;
     w.x = (double *)(m + L.x); w.b = (double *)(m + L.b);
-    w.r64 = (double *)(m + L.r64); w.z64 = (double *)(m + L.z64); w.q64 = (double *)(m + L.q64);
-    w.r32 = (float *)(m + L.r32); w.z32 = (float *)(m + L.z32); w.q32 = (float *)(m + L.q32);
-    w.z16 = (half_t *)(m + L.z16);
-    for (int i = 0; i < 2; ++i) {
-        w.p64[i] = (double *)(m + L.p64[i]); w.p32[i] = (float *)(m + L.p32[i]); w.p16[i] = (half_t *)(m + L.p16[i]);
+    w.r64 = (double *)(m + L.r64); w.q64 = (double *)(m + L.q64);
+    w.r32 = (float *)(m + L.r32); w.q32 = (float *)(m + L.q32);
+    {
+        double *g64 = (double *)(m + L.g64);
+        float *g32 = (float *)(m + L.g32);
+        half_t *g16 = (half_t *)(m + L.g16);
+        w.z64 = g64 + G; w.p64[0] = g64 + 2 * G + np; w.p64[1] = g64 + 3 * G + 2 * np;
+        w.z32 = g32 + G; w.p32[0] = g32 + 2 * G + np; w.p32[1] = g32 + 3 * G + 2 * np;
+        w.z16 = g16 + G; w.p16[0] = g16 + 2 * G + np; w.p16[1] = g16 + 3 * G + 2 * np;
     }
     w.part = (double *)(m + L.part);
     w.ring = (double *)(m + L.ring);
@@ -1583,6 +1607,9 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 
     int in = ST_INIT;
     unsigned ntask = (unsigned)lock.size();
+    const int uzf = fixed_uz(o);
+    void (*batch_spmv_fn)(const SysDesc *, const Task *, int, int) =
+        uzf == 16 ? k_batch_spmv<16> : uzf == 32 ? k_batch_spmv<32> : uzf == 64 ? k_batch_spmv<64> : k_batch_spmv<0>;
     const int batch = o.batch > 0 ? o.batch : 8;
     int pending = -1, stage_next = 0, nlive = nsys - nsolo;
     std::vector<St> fin(nsys);
@@ -1590,7 +1617,8 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
     auto enqueue_batch = [&](int slot) -> amp_status {
         for (int i = 0; i < batch; ++i) {
             k_batch_precond<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, in, ST_PRE);
-            k_batch_spmv<<<ntask, NTS, 0, st>>>(bb.sd, bb.tasks, ST_PRE, ST_SPMV);
+            hipLaunchKernelGGL(batch_spmv_fn, dim3(ntask), dim3(NTP), 0, st, (const SysDesc *)bb.sd,
+                               (const Task *)bb.tasks, (int)ST_PRE, (int)ST_SPMV);
             k_batch_update<<<ntask, NT, 0, st>>>(bb.sd, bb.tasks, ST_SPMV, ST_RES);
             in = ST_RES;
         }
