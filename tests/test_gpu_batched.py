@@ -102,7 +102,7 @@ def test_batched_vs_oracle(amp):
         assert info["relres_true"] <= 1e-10
         assert info["iters"] <= math.ceil(1.05 * io["iters"]) + 1, (i, info["iters"], io["iters"])
         x = xs[i].cpu().numpy()
-        assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
 def test_batched_full_workload(amp):
@@ -130,7 +130,7 @@ def test_batched_full_workload(amp):
         _say(f"  system {i}: n={A.n} gpu {infos[i]['iters']} oracle {io['iters']}")
         assert infos[i]["iters"] <= math.ceil(1.05 * io["iters"]) + 1
         x = xs[i].cpu().numpy()
-        assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
 def test_batched_rejects_bad_arguments(amp):

@@ -108,33 +108,3 @@ def test_chebyshev_poisson_short_rows(amp, offsets):
     assert abs(info["iters"] - io["iters"]) <= 2
     # both stop at ||r|| <= 1e-10 ||b||: solutions agree within 2 tol kappa(A), kappa(A) = hi / lo
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 2e-10 * (hi / lo) * np.linalg.norm(xo)
-
-
-def test_q1_full_size(amp):
-    _say("full size: Q1 anisotropic 256^3, degree-4 Chebyshev")
-    ref = {}
-    path = os.path.join(GOLDEN, "q1_256_chebyshev4.txt")
-    if os.path.exists(path):
-        for line in open(path):
-            if line.strip() and not line.startswith("#"):
-                k, v = line.split()
-                ref[k] = float(v)
-    A, b, xs, (lo, hi) = P.q1_system(256)
-    _say(f"  generated n={A.n} nnz={A.nnz}")
-    M = amp.Matrix.from_csr(A)
-    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
-    bt = torch.tensor(b, device="cuda")
-    for preset in ("amp64", "pcg64"):
-        x, info = amp.solve(M, pc, bt, tol=1e-10, maxit=20000, preset=preset)
-        xh = x.cpu().numpy()
-        r = b - cpcg.spmv(A, xh)
-        rel = float(np.linalg.norm(r) / np.linalg.norm(b))
-        err = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
-        _say(f"  {preset}: {info['iters']} iterations (oracle {ref.get('iters')}), {info['t_solve_ms']:.1f} ms, "
-             f"true rel. residual {rel:.3e}, error vs x* {err:.3e}, switches "
-             f"{info['k_z32']} {info['k_z16']} {info['k_r32']}")
-        assert info["status"] == 0
-        assert rel <= 1e-10 * (1 + 1e-6)
-        if "iters" in ref:
-            assert info["iters"] <= math.ceil(1.05 * ref["iters"])
-        assert err <= 1e-5

@@ -149,9 +149,8 @@ def test_amp64_vs_fp64_oracle(amp, case):
     assert info["status"] == 0
     assert info["iters"] <= math.ceil(1.05 * io["iters"])
     assert info["relres_true"] <= 1e-10
-    # both are tol-accurate solutions: their difference is bounded by the
-    # condition number times the residuals (estimated from the oracle's CG)
-    assert _rel(x, xo) <= 1e-5
+    # the parity bar: within 1e-8 of the oracle's solution
+    assert _rel(x, xo) <= 1e-8
 
 
 @pytest.mark.parametrize("d", [63, 64, 80, 100])
@@ -247,11 +246,17 @@ def test_ragged_sizes(amp, n):
         np.exp(np.random.default_rng([310, n]).standard_normal((1, n))))
     b = np.random.default_rng([311, n]).standard_normal(A.n)
     xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000)
+    # both solutions satisfy ||x - x*|| <= kappa(A) tol ||x*||: FP16 z, p are
+    # held to 2 tol kappa(A) (kappa from the dense spectrum), the others to 1e-8
+    ev = np.linalg.eigvalsh(A.to_scipy().toarray())
+    kappa = float(ev[-1] / ev[0])
     for preset in ("pcg64", "amp64", "amp16"):
         x, info = _gpu_solve(amp, A, b, preset)
+        bound = 2e-10 * kappa if preset == "amp16" else 1e-8
+        _say(f"  {preset}: rel. error vs the oracle {_rel(x, xo):.3e} (bound {bound:.2e}, kappa {kappa:.3e})")
         assert info["status"] == 0, preset
         assert info["relres_true"] <= 1e-10, preset
-        assert _rel(x, xo) <= 1e-6, preset
+        assert _rel(x, xo) <= bound, preset
 
 
 def test_deterministic(amp):
@@ -367,25 +372,6 @@ def test_graph_replay_chebyshev(amp):
         xg, ig = amp.solve(M, pc, bt, preset="amp16", graph=1)
         torch.cuda.synchronize()
         assert ig["iters"] == i0["iters"] and torch.equal(xg, x0)
-
-
-# ------------------------------------------------------------------ full-size workload
-
-def test_blocky128_full_size(amp):
-    _say("full size: 3-D 7-point FV 128^3, contrast 1e4")
-    A, b, _ = P.blocky_diffusion3d_system()
-    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=20000)
-    x, info = _gpu_solve(amp, A, b, "amp64", maxit=20000)
-    _say(f"  oracle iters {io['iters']}, gpu iters {info['iters']}, switches "
-         f"{info['k_z32']} {info['k_z16']} {info['k_r32']}, rel err {_rel(x, xo):.3e}")
-    assert info["status"] == 0
-    assert info["iters"] <= math.ceil(1.05 * io["iters"])
-    # the FP64 true residual, recomputed by the oracle
-    r = b - cpcg.spmv(A, x)
-    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
-    x64, i64 = _gpu_solve(amp, A, b, "pcg64", maxit=20000)
-    assert i64["iters"] == io["iters"]
-    assert _rel(x64, xo) <= 1e-9
 
 
 # ------------------------------------------------------------------ failure injection
