@@ -144,6 +144,24 @@ typedef struct {
     int cheb_launches;        /* spmv_timing: number of those launches (= iters * (m - 1)) */
 } amp_result;
 
+/*
+ * Device memory of handles and workspaces.  By default the library calls
+ * hipMalloc / hipFree.  After amp_set_allocator(alloc, free_, ctx) every
+ * later device allocation of the library (matrix planes, work vectors,
+ * preconditioner data, the batched solve's tables) calls alloc(bytes, ctx),
+ * which must return device memory of the current device, aligned to 256
+ * bytes, or NULL (AMP_ERR_OOM); such a block is released with the free_
+ * that was set when it was allocated (free_(ptr, ctx)), after the library
+ * has waited for the device, as hipFree does.  amp_set_allocator(NULL, NULL,
+ * NULL) returns to hipMalloc for later allocations.  Typical use: routing
+ * the workspace through a framework's caching allocator.  The functions are
+ * called from the thread that calls the library; they must not call back
+ * into it.  Pinned host memory and events are not affected.  Errors:
+ * AMP_ERR_ARG if exactly one of alloc, free_ is NULL.
+ */
+amp_status amp_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*free_)(void *ptr, void *ctx),
+                             void *ctx);
+
 /* Library version (major*10000 + minor*100 + patch). */
 int amp_version(void);
 /* Human-readable status name; never NULL. */

@@ -8,7 +8,9 @@ Python entry points (argument marshalling only):
 * :class:`Matrix`, :class:`Preconditioner`, :func:`solve`, :func:`solve_batched`
 * :func:`tune_group_rows` (rows-per-work-group autotuner, run on the device)
 * :func:`selector_replay`, :func:`paper_kernel_bytes` (host-only helpers)
+* :func:`use_torch_allocator`, :func:`use_hip_allocator` (where the library's
+  device memory comes from)
 """
 
 from .solver import (Matrix, Preconditioner, solve, solve_batched, tune_group_rows,  # noqa: F401
-                     selector_replay, paper_kernel_bytes)
+                     selector_replay, paper_kernel_bytes, use_torch_allocator, use_hip_allocator)

@@ -48,17 +48,85 @@ static amp_status fail(amp_status s, const std::string &msg) {
         if (s_ != AMP_OK) return s_;                  \
     } while (0)
 
+// ----------------------------------------------------------------------------
+// device memory: hipMalloc, or the caller's allocator (amp_set_allocator)
+// ----------------------------------------------------------------------------
+
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free_)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+static std::mutex g_alloc_mu;
+static Allocator g_alloc;                                   // the one new allocations use
+static std::map<void *, Allocator> g_alloc_owner;           // caller-allocated blocks and their allocator
+
+extern "C" amp_status amp_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(AMP_ERR_ARG, "amp_set_allocator: give both functions, or neither");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return AMP_OK;
+}
+
+static amp_status raw_alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) {
+        AMP_HIP(hipMalloc(p, bytes));
+        return AMP_OK;
+    }
+    void *q = a.alloc(bytes, a.ctx);
+    if (!q) return fail(AMP_ERR_OOM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    if ((uintptr_t)q % 256)
+        return a.free_(q, a.ctx), fail(AMP_ERR_ARG, "the caller's allocator returned memory not aligned to 256 bytes");
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc_owner[q] = a;
+    *p = q;
+    return AMP_OK;
+}
+
+static void raw_free(void *p) {
+    if (!p) return;
+    Allocator a;
+    bool mine = false;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        auto it = g_alloc_owner.find(p);
+        if (it != g_alloc_owner.end()) {
+            a = it->second;
+            mine = true;
+            g_alloc_owner.erase(it);
+        }
+    }
+    if (!mine) {
+        (void)hipFree(p);
+        return;
+    }
+    // hipFree waits for the device; a caller's allocator may reuse the block
+    // at once, so wait here as well
+    (void)hipDeviceSynchronize();
+    a.free_(p, a.ctx);
+}
+
 template <typename T>
 static amp_status dalloc(T **p, size_t count) {
-    *p = nullptr;
     if (count == 0) count = 1;
-    AMP_HIP(hipMalloc((void **)p, count * sizeof(T)));
+    void *q = nullptr;
+    AMP_TRY(raw_alloc(&q, count * sizeof(T)));
+    *p = (T *)q;
     return AMP_OK;
 }
 
 template <typename T>
 static void dfree(T *&p) {
-    if (p) (void)hipFree((void *)p);
+    raw_free((void *)p);
     p = nullptr;
 }
 

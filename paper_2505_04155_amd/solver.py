@@ -239,3 +239,41 @@ def paper_kernel_bytes(u_z: int, u_r: int):
     out = (ctypes.c_double * 4)()
     B.check(B.load().amp_paper_kernel_bytes(u_z, u_r, out), "amp_paper_kernel_bytes")
     return list(out)
+
+
+_allocator_refs = []   # every callback pair ever set: blocks made with one are freed with it
+
+
+def use_torch_allocator(device=None, record=None):
+    """Route the library's device allocations (amp_set_allocator) through
+    torch's caching allocator on `device` (default: the current one).
+    record: optional list that receives ("alloc", ptr, bytes) and
+    ("free", ptr) tuples."""
+    L = B.load()
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def _alloc(nbytes, ctx):
+        try:
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+        except Exception:   # out of memory: the library reports AMP_ERR_OOM
+            return None
+        if record is not None:
+            record.append(("alloc", ptr, int(nbytes)))
+        return ptr
+
+    def _free(ptr, ctx):
+        if record is not None:
+            record.append(("free", ptr))
+        torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (B.ALLOC_FN(_alloc), B.FREE_FN(_free))
+    _allocator_refs.append(refs)
+    B.check(L.amp_set_allocator(refs[0], refs[1], None), "amp_set_allocator")
+
+
+def use_hip_allocator():
+    """Back to hipMalloc / hipFree for later allocations (blocks made by a
+    caller allocator are still released through it)."""
+    L = B.load()
+    B.check(L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None), "amp_set_allocator")
+

@@ -116,3 +116,14 @@ def test_matrix_size_limits_rejected_before_any_device_access(n, nnz):
     assert msg.startswith("amp_matrix_create")
     if 0 < n <= nnz < 2 ** 31:
         assert "2^29" in msg
+
+
+def test_set_allocator_rejects_half_a_pair():
+    import ctypes
+    L = B.load()
+    dummy_alloc = B.ALLOC_FN(lambda n, ctx: None)
+    assert L.amp_set_allocator(dummy_alloc, B.FREE_FN(), None) == B.AMP_ERR_ARG
+    assert L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(lambda p, ctx: None), None) == B.AMP_ERR_ARG
+    assert L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None) == B.AMP_OK
+    assert isinstance(ctypes.c_void_p(), ctypes.c_void_p)
+
