@@ -217,12 +217,22 @@ amp_status amp_matrix_info(amp_matrix A, amp_matrix_stats *out);
  * z = D^{-1/2} s(B) D^{-1/2} y, B = D^{-1/2} A D^{-1/2} stored in FP16,
  * s the degree-(degree-1) polynomial with 1 - t s(t) = T_degree((theta - t)/
  * delta)/T_degree(theta/delta) on [lam_lo, lam_hi] (eigenvalue bounds of
- * D^{-1} A).  AMP_PC_IDENTITY: M = I.  Host-synchronous.
- * Errors: AMP_ERR_ARG for an unknown kind, degree outside 1..16, or
- * Chebyshev bounds not satisfying 0 < lam_lo < lam_hi.
+ * D^{-1} A).  A bound given as <= 0 is estimated (the paper gives no rule;
+ * Section 5.3 uses Chebyshev only as a smoother): 24 Lanczos steps in FP64
+ * on D^{-1/2} A D^{-1/2} from a fixed counter-based start vector
+ * (splitmix64), lam_hi = 1.05 x the largest Ritz value, lam_lo = lam_hi / 30;
+ * amp_precond_bounds reports the values used.  AMP_PC_IDENTITY: M = I.
+ * Host-synchronous.
+ * Errors: AMP_ERR_ARG for an unknown kind, degree outside 1..16, non-finite
+ * bounds, or bounds (given or estimated) not satisfying 0 < lam_lo < lam_hi.
  */
 amp_status amp_precond_create(amp_matrix A, int kind, int degree, double lam_lo, double lam_hi,
                               void *stream, amp_precond *out);
+/* The interval a Chebyshev preconditioner uses (given or estimated), and
+ * the Lanczos Ritz extremes it was estimated from (0 when both bounds were
+ * given); ritz_min, ritz_max nullable.  Host-only read of the handle.
+ * Errors: AMP_ERR_ARG for null pointers or another preconditioner kind. */
+amp_status amp_precond_bounds(amp_precond M, double *lam_lo, double *lam_hi, double *ritz_min, double *ritz_max);
 void amp_precond_destroy(amp_precond M);
 
 /*

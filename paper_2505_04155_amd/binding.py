@@ -26,7 +26,7 @@ EXPORTED = [
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
     "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
-    "amp_set_allocator",
+    "amp_set_allocator", "amp_precond_bounds",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -111,6 +111,8 @@ def load(build_if_missing: bool = True):
                                     ctypes.POINTER(Result), vp]
         L.amp_stream_probe.argtypes = [i32, vp, vp, i64, vp]
         L.amp_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+        L.amp_precond_bounds.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                         ctypes.POINTER(dbl)]
         L.amp_pcg_solve_noalloc.argtypes = [vp, vp, vp, vp, dbl, i32, ctypes.POINTER(Options),
                                             ctypes.POINTER(Result), vp]
         L.amp_pcg_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),

@@ -217,6 +217,8 @@ struct amp_precond_s {
     void *cv[2] = {nullptr, nullptr}, *cres[2] = {nullptr, nullptr}, *cw[2] = {nullptr, nullptr};
     void *cdir[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
+    int est_hi = 0, est_lo = 0;       // bounds estimated by the Lanczos process (lam <= 0 given)
+    double ritz_min = 0.0, ritz_max = 0.0;
     Cheb cheb() const {
         Cheb P;
         P.srec = A->srec; P.sptr = A->sptr; P.col = A->col; P.soff = A->soff; P.offs = A->offs;
@@ -663,6 +665,190 @@ __global__ void k_scale_to_half(const double *d64, int64_t np, double scale, hal
     if (i < np) d16[i] = narrow<half_t>(d64[i] * scale);
 }
 
+// ----------------------------------------------------------------------------
+// Chebyshev interval from the Lanczos process (when the caller gives none)
+// ----------------------------------------------------------------------------
+//
+// D^{-1} A is similar to B = D^{-1/2} A D^{-1/2}; 24 Lanczos steps on B from a
+// counter-based start vector give Ritz values inside its spectrum, the top
+// one close to lambda_max.  lam_hi = 1.05 x that value and lam_lo =
+// lam_hi / 30 (the Chebyshev polynomial then treats the upper part of the
+// spectrum; the preconditioner stays positive definite below lam_lo).  All
+// in FP64 with fixed-order reductions.
+
+constexpr int kLanczosSteps = 24;
+constexpr double kLanczosHiMargin = 1.05, kLanczosLoRatio = 30.0;
+
+// splitmix64's output at counter c with seed 0 (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators", 2014).
+__host__ __device__ inline uint64_t splitmix64_at(uint64_t c) {
+    uint64_t z = c * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// v_i = 2 (splitmix64(i + 1) >> 11) 2^-53 - 1 for i < n, 0 beyond; partials of sum v_i^2.
+__global__ void __launch_bounds__(NT) k_lz_start(int64_t n, int64_t np, double *v, double *part) {
+    double sq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < np; i += (int64_t)gridDim.x * NT) {
+        double u = 0.0;
+        if (i < n) u = 2.0 * ((double)(splitmix64_at((uint64_t)i + 1) >> 11) * 0x1p-53) - 1.0;
+        v[i] = u;
+        sq += u * u;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.x] = sq;
+}
+
+// w = D^{-1/2} A D^{-1/2} v (FP64 values and accumulation, slot order);
+// partials of w^T v.
+__global__ void __launch_bounds__(NTS) k_lz_apply(Sell A, const double *isq, const double *v, double *w,
+                                                  double *part) {
+    const Wg wg = grid_wg();
+    double dot = 0.0;
+    AMP_SLICE_LOOP(A, sl, wg, NTS) {
+        AMP_SLICE_ROW(A, sl, lane, row, base, wd, NTS);
+        double ax = 0.0;
+        AMP_WITH_COLS(A, sl, lane, sc) {
+            ax = row_dot64(A, sc, base, wd, [&](int64_t c) { return isq[c] * v[c]; });
+        });
+        const double wi = isq[row] * ax;
+        w[row] = wi;
+        dot += wi * v[row];
+    }
+    dot = block_sum<NTS>(dot);
+    if (threadIdx.x == 0) part[wg.lb] = dot;
+}
+
+// w = (w - alpha v) - beta v_prev; partials of sum w_i^2.
+__global__ void __launch_bounds__(NT) k_lz_axpy(int64_t np, double *w, const double *v, const double *vp,
+                                                double alpha, double beta, double *part) {
+    double sq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < np; i += (int64_t)gridDim.x * NT) {
+        const double t = (w[i] - alpha * v[i]) - beta * vp[i];
+        w[i] = t;
+        sq += t * t;
+    }
+    sq = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.x] = sq;
+}
+
+__global__ void __launch_bounds__(NT) k_lz_div(int64_t np, double *v, double d) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < np; i += (int64_t)gridDim.x * NT) v[i] = v[i] / d;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (Sturm sequence of its LDL^T pivots;
+// Barth, Martin and Wilkinson, 1967).
+static int sturm_count(const std::vector<double> &a, const std::vector<double> &b, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// The k-th smallest eigenvalue (0-based) by bisection inside the
+// Gershgorin interval, to the last bits.
+static double tridiag_eigenvalue(const std::vector<double> &a, const std::vector<double> &b, int k) {
+    const size_t m = a.size();
+    double lo = a[0], hi = a[0];
+    for (size_t i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, mid) > k) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Fixed-order total of G partials, read back to the host.
+static amp_status reduce_read(const double *part, int G, double *scratch, double *out, hipStream_t st) {
+    k_reduce_to<<<1, NT, 0, st>>>(part, G, 0, scratch);
+    AMP_HIP(hipGetLastError());
+    AMP_HIP(hipMemcpyAsync(out, scratch, sizeof(double), hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipStreamSynchronize(st));
+    return AMP_OK;
+}
+
+// Ritz extremes of the Lanczos process on B (isq = D^{-1/2} already formed).
+static amp_status lanczos_ritz(amp_precond M, hipStream_t st, double *tmin, double *tmax) {
+    amp_matrix A = M->A;
+    const int64_t n = A->n, np = A->np;
+    const int gs = fit_grid((np + NT - 1) / NT), gl = grid_slices(A->nslices);
+    double *buf = nullptr, *part = nullptr;
+    AMP_TRY(dalloc(&buf, 3 * np));
+    amp_status s = dalloc(&part, GMAX + 1);
+    if (s != AMP_OK) {
+        dfree(buf);
+        return s;
+    }
+    auto done = [&](amp_status r) {
+        dfree(buf);
+        dfree(part);
+        return r;
+    };
+    double *vp = buf, *v = buf + np, *w = buf + 2 * np;
+    if (hipMemsetAsync(vp, 0, np * sizeof(double), st) != hipSuccess)
+        return done(fail(AMP_ERR_HIP, "Lanczos: clearing a vector failed"));
+    k_lz_start<<<gs, NT, 0, st>>>(n, np, v, part);
+    double sq = 0.0;
+    if ((s = reduce_read(part, gs, part + GMAX, &sq, st)) != AMP_OK) return done(s);
+    if (!(sq > 0.0)) return done(fail(AMP_ERR_ARG, "Lanczos: empty start vector"));
+    k_lz_div<<<gs, NT, 0, st>>>(np, v, std::sqrt(sq));
+    std::vector<double> alpha, beta;
+    double b = 0.0, amax = 0.0;
+    const int steps = (int)std::min<int64_t>(kLanczosSteps, n);
+    const Sell S = A->sell();
+    for (int j = 0; j < steps; ++j) {
+        k_lz_apply<<<gl, NTS, 0, st>>>(S, M->isq64, v, w, part);
+        double a = 0.0;
+        if ((s = reduce_read(part, gl, part + GMAX, &a, st)) != AMP_OK) return done(s);
+        k_lz_axpy<<<gs, NT, 0, st>>>(np, w, v, vp, a, b, part);
+        double wn = 0.0;
+        if ((s = reduce_read(part, gs, part + GMAX, &wn, st)) != AMP_OK) return done(s);
+        wn = std::sqrt(wn);
+        alpha.push_back(a);
+        amax = std::max(amax, std::fabs(a));
+        if (!std::isfinite(a) || !std::isfinite(wn)) return done(fail(AMP_ERR_ARG, "Lanczos: non-finite value"));
+        if (j == steps - 1 || wn <= 1e-14 * amax) break;
+        beta.push_back(wn);
+        k_lz_div<<<gs, NT, 0, st>>>(np, w, wn);
+        double *t = vp;
+        vp = v;
+        v = w;
+        w = t;
+        b = wn;
+    }
+    AMP_HIP(hipGetLastError());
+    *tmin = tridiag_eigenvalue(alpha, beta, 0);
+    *tmax = tridiag_eigenvalue(alpha, beta, (int)alpha.size() - 1);
+    return done(AMP_OK);
+}
+
+// Coefficients of the three-term recurrence on [lam_lo, lam_hi].
+static void cheb_coefficients(amp_precond M) {
+    const double lam_lo = M->lam_lo, lam_hi = M->lam_hi;
+    const double theta = 0.5 * (lam_hi + lam_lo), delta = 0.5 * (lam_hi - lam_lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    M->inv_theta = 1.0 / theta;
+    for (int k = 0; k + 1 < M->degree; ++k) {
+        const double rho_n = 1.0 / (2.0 * sigma - rho);
+        M->c1[k] = rho_n * rho;
+        M->c2[k] = 2.0 * rho_n / delta;
+        rho = rho_n;
+    }
+}
+
 // Values of the preconditioner that depend on A's entries (also rerun by
 // amp_precond_update after amp_matrix_update_values).
 static std::atomic<uint64_t> g_generation{0};
@@ -701,6 +887,17 @@ static amp_status setup_values(amp_precond M, hipStream_t st) {
         k_scale_to_half<<<g, 256, 0, st>>>(M->d64, np, std::ldexp(1.0, M->extra16), M->d16);
         AMP_HIP(hipStreamSynchronize(st));
     } else {
+        if (M->est_hi || M->est_lo) {
+            double tmin = 0.0, tmax = 0.0;
+            AMP_TRY(lanczos_ritz(M, st, &tmin, &tmax));
+            M->ritz_min = tmin;
+            M->ritz_max = tmax;
+            if (M->est_hi) M->lam_hi = kLanczosHiMargin * tmax;
+            if (M->est_lo) M->lam_lo = M->lam_hi / kLanczosLoRatio;
+            if (!(M->lam_lo > 0.0) || !(M->lam_hi > M->lam_lo) || !std::isfinite(M->lam_hi))
+                return fail(AMP_ERR_ARG, "amp_precond_create: estimated bounds do not satisfy 0 < lam_lo < lam_hi");
+        }
+        cheb_coefficients(M);
         M->gain = mx * mx / M->lam_lo;  // |s(t)| <= 1/lam_lo on [lam_lo, lam_hi], times max D^{-1}
         M->extra16 = 0;
     }
@@ -716,8 +913,10 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         return fail(AMP_ERR_ARG, "amp_precond_create: unknown preconditioner kind");
     if (kind == AMP_PC_CHEBYSHEV) {
         if (degree < 1 || degree > kChebMax) return fail(AMP_ERR_ARG, "amp_precond_create: degree must be in 1..16");
-        if (!(lam_lo > 0.0) || !(lam_hi > lam_lo) || !std::isfinite(lam_hi))
-            return fail(AMP_ERR_ARG, "amp_precond_create: need 0 < lam_lo < lam_hi");
+        if (!std::isfinite(lam_lo) || !std::isfinite(lam_hi))
+            return fail(AMP_ERR_ARG, "amp_precond_create: bounds must be finite");
+        if (lam_lo > 0.0 && lam_hi > 0.0 && !(lam_hi > lam_lo))
+            return fail(AMP_ERR_ARG, "amp_precond_create: need lam_lo < lam_hi");
     }
     hipStream_t st = as_stream(stream);
     amp_precond M = new amp_precond_s();
@@ -730,6 +929,8 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         M->degree = degree;
         M->lam_lo = lam_lo;
         M->lam_hi = lam_hi;
+        M->est_hi = !(lam_hi > 0.0);
+        M->est_lo = !(lam_lo > 0.0);
         if ((s = dalloc(&M->b16, A->slots)) != AMP_OK || (s = dalloc(&M->isq64, np)) != AMP_OK ||
             (s = dalloc(&M->isq32, np)) != AMP_OK)
             return bail(s);
@@ -748,16 +949,6 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         M->cdir[1][1] = M->cblk32 + 3 * G + 2 * np;
         M->cres[1] = M->cblk32 + 4 * G + 3 * np;
         M->cw[1] = M->cblk32 + 4 * G + 4 * np;
-        // coefficients of the three-term recurrence
-        const double theta = 0.5 * (lam_hi + lam_lo), delta = 0.5 * (lam_hi - lam_lo), sigma = theta / delta;
-        double rho = 1.0 / sigma;
-        M->inv_theta = 1.0 / theta;
-        for (int k = 0; k + 1 < degree; ++k) {
-            const double rho_n = 1.0 / (2.0 * sigma - rho);
-            M->c1[k] = rho_n * rho;
-            M->c2[k] = 2.0 * rho_n / delta;
-            rho = rho_n;
-        }
     } else {
         if ((s = dalloc(&M->d64, np)) != AMP_OK || (s = dalloc(&M->d32, np)) != AMP_OK ||
             (s = dalloc(&M->d16, np)) != AMP_OK)
@@ -765,6 +956,17 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
     }
     if ((s = setup_values(M, st)) != AMP_OK) return bail(s);
     *out = M;
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_precond_bounds(amp_precond M, double *lam_lo, double *lam_hi, double *ritz_min,
+                                         double *ritz_max) {
+    if (!M || !lam_lo || !lam_hi) return fail(AMP_ERR_ARG, "amp_precond_bounds: null argument");
+    if (M->kind != AMP_PC_CHEBYSHEV) return fail(AMP_ERR_ARG, "amp_precond_bounds: not a Chebyshev preconditioner");
+    *lam_lo = M->lam_lo;
+    *lam_hi = M->lam_hi;
+    if (ritz_min) *ritz_min = M->ritz_min;
+    if (ritz_max) *ritz_max = M->ritz_max;
     return AMP_OK;
 }
 

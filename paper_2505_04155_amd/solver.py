@@ -104,6 +104,14 @@ class Preconditioner:
     def handle(self):
         return self._h
 
+    def bounds(self):
+        """Chebyshev: (lam_lo, lam_hi, ritz_min, ritz_max) -- the interval
+        used (given, or estimated when a bound was passed as <= 0) and the
+        Lanczos Ritz extremes it came from."""
+        vals = [ctypes.c_double() for _ in range(4)]
+        B.check(B.load().amp_precond_bounds(self._h, *[ctypes.byref(v) for v in vals]), "amp_precond_bounds")
+        return tuple(v.value for v in vals)
+
     def apply(self, r: torch.Tensor, u_z: int, omega: float = 1.0):
         """z = M^{-1} fl_{u_z}(fl_{u_r}(omega r)); r's dtype gives u_r.  Returns (z, rho)."""
         u_r = {torch.float64: 64, torch.float32: 32}[r.dtype]

@@ -108,3 +108,60 @@ def test_chebyshev_poisson_short_rows(amp, offsets):
     assert abs(info["iters"] - io["iters"]) <= 2
     # both stop at ||r|| <= 1e-10 ||b||: solutions agree within 2 tol kappa(A), kappa(A) = hi / lo
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 2e-10 * (hi / lo) * np.linalg.norm(xo)
+
+
+# ------------------------------------------------------------------ estimated bounds
+
+def _q1(n):
+    return P.q1_anisotropic(n)
+
+
+@pytest.mark.parametrize("case", ["q1_20", "q1_64", "q1_256", "blocky24"])
+def test_estimated_bounds(amp, case):
+    # lam <= 0 asks the library for the interval: its Lanczos Ritz extremes
+    # equal the oracle's (same steps and start vector, independent code) to
+    # rounding, and for the Q1 operator the interval holds the closed-form
+    # top of the spectrum within the 5% margin
+    from oracle import eigbounds as E
+    _say(f"estimated Chebyshev bounds {case}")
+    if case.startswith("q1"):
+        n = int(case[3:])
+        A = _q1(n)
+        exact = P.q1_anisotropic_bounds(n)
+    else:
+        A, _, _ = P.blocky_diffusion3d_system(24, 4)
+        exact = None
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=0.0, lam_hi=0.0)
+    lo, hi, tmin, tmax = pc.bounds()
+    _say(f"  gpu: ritz [{tmin:.6e}, {tmax:.6e}] -> [{lo:.6e}, {hi:.6e}]")
+    if A.n <= 300000:
+        (olo, ohi), (otmin, otmax) = E.chebyshev_bounds(A.to_scipy())
+        _say(f"  oracle: ritz [{otmin:.6e}, {otmax:.6e}]")
+        assert tmax == pytest.approx(otmax, rel=1e-9)
+        assert tmin == pytest.approx(otmin, rel=1e-7)
+    assert hi == pytest.approx(1.05 * tmax, rel=1e-15) and lo == pytest.approx(hi / 30.0, rel=1e-15)
+    if exact is not None:
+        _say(f"  closed form: [{exact[0]:.6e}, {exact[1]:.6e}]")
+        assert exact[0] * (1 - 1e-12) <= tmin and tmax <= exact[1] * (1 + 1e-12)
+        assert exact[1] <= hi <= 1.05 * exact[1] * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("preset", ["pcg64", "amp64", "amp16"])
+def test_solve_with_estimated_bounds(amp, preset):
+    # each side estimates its own interval; the solves agree to the parity bar
+    from oracle import eigbounds as E
+    _say(f"solve with estimated bounds, Q1 32^3, {preset}")
+    A = _q1(32)
+    xs = np.random.default_rng([330]).uniform(-1.0, 1.0, A.n)
+    b = A.to_scipy() @ xs
+    (olo, ohi), _ = E.chebyshev_bounds(A.to_scipy())
+    xo, io = cpcg.pcg(A, b, tol=1e-10, maxit=5000, precond=cpcg.PC_CHEBYSHEV, degree=4, lam_lo=olo, lam_hi=ohi)
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "chebyshev", degree=4)
+    x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=5000, preset=preset)
+    err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    _say(f"  gpu {info['iters']} iterations, oracle {io['iters']}; rel. error vs the oracle {err:.3e}")
+    assert info["status"] == 0 and io["status"] == 0
+    assert info["iters"] <= math.ceil(1.05 * io["iters"])
+    assert err <= 1e-8
