@@ -86,6 +86,30 @@ def cheb_iteration_bytes(n, nnz, meta_bytes, u_z, u_r, degree=4):
     return m * (2 * nnz + meta_bytes) + n * vec
 
 
+def jacobi_iteration_bytes(n, nnz, meta_bytes, u_z, u_r):
+    """One Jacobi-preconditioned iteration's three kernels in (u_z, u_r):
+    preconditioning reads r and dinv and writes z; the product step as
+    step_bytes; the update reads r and q and writes r, and every other
+    iteration reads and writes x and reads the two pending p (8 + u_z / 8
+    bytes per row per iteration on average)."""
+    bz, br = u_z // 8, u_r // 8
+    return n * (br + 2 * bz) + step_bytes(n, nnz, meta_bytes, u_z, u_r) + n * (3 * br + 8 + bz)
+
+
+def phase_iterations(info, preset):
+    """(u_z, u_r) -> iterations of one solve, from its switch points."""
+    it, kz32, kz16, kr = info["iters"], info["k_z32"], info["k_z16"], info["k_r32"]
+    out = {}
+    for k in range(it):
+        if preset == "amp16":
+            uz = 16
+        else:
+            uz = 16 if 0 <= kz16 <= k else 32 if 0 <= kz32 <= k else 64
+        ur = 32 if 0 <= kr <= k else 64
+        out[(uz, ur)] = out.get((uz, ur), 0) + 1
+    return out
+
+
 def stored_traffic(path):
     """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary
     (each counter scaled by what it reads for the library's copy probe of
@@ -305,6 +329,46 @@ def fv128_measurement(amp, torch, np, P, dev, steps, warmup, with_oracle=True, g
     return out
 
 
+def batched_measurement(amp, torch, np, P, dev, steps, warmup):
+    """The 512-system batched workload (2-D five-point FV, sides log-uniform
+    in [32, 512], kappa = exp(N(0, 1.5^2)) per cell, Jacobi): batched
+    time-to-solution per preset and the aggregate algorithmic bandwidth
+    (every system's iterations priced at their precisions)."""
+    log("bench: generating the 512-system batched workload")
+    systems = P.batched_systems()
+    Ms = [amp.Matrix.from_csr(A, device=dev) for A, _ in systems]
+    Ps = [amp.Preconditioner(M, "jacobi") for M in Ms]
+    bs = [torch.tensor(b, device=dev) for _, b in systems]
+    infos_m = [M.info() for M in Ms]
+    out = {"workload": f"{len(systems)} 2-D 5-point FV systems, sides round(exp(U[ln 32, ln 512])), "
+                       f"kappa = exp(N(0, 1.5^2)) per cell, b ~ N(0,1), Jacobi, tol 1e-10 each; "
+                       f"{sum(A.n for A, _ in systems)} rows in all"}
+    for preset in ("amp16", "amp64", "pcg64"):
+        for _ in range(warmup):
+            amp.solve_batched(Ms, Ps, bs, tol=1e-10, maxit=20000, preset=preset)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            xs, infos, st = amp.solve_batched(Ms, Ps, bs, tol=1e-10, maxit=20000, preset=preset)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if st != 0:
+            raise RuntimeError(f"batched {preset}: status {st}")
+        nbytes = 0
+        for im, inf in zip(infos_m, infos):
+            for (uz, ur), k in phase_iterations(inf, preset).items():
+                nbytes += k * jacobi_iteration_bytes(im["n"], im["nnz"], im["meta_bytes"], uz, ur)
+        iters = [i["iters"] for i in infos]
+        out[preset] = {"ms": round(ms, 2), "algorithmic_GB": round(nbytes / 1e9, 2),
+                       "aggregate_GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                       "iters_min_median_max": [int(min(iters)), int(np.median(iters)), int(max(iters))],
+                       "max_rel_res_true": max(i["relres_true"] for i in infos)}
+        log(f"bench: batched {preset}: {ms:.1f} ms, {out[preset]['aggregate_GB_per_s']:.0f} GB/s aggregate")
+    out["speedup_amp16_vs_fp64_pcg"] = round(out["pcg64"]["ms"] / out["amp16"]["ms"], 4)
+    out["speedup_amp64_vs_fp64_pcg"] = round(out["pcg64"]["ms"] / out["amp64"]["ms"], 4)
+    return out
+
+
 # ----------------------------------------------------------------------------
 
 def main():
@@ -316,11 +380,12 @@ def main():
     ap.add_argument("--q1-grid", type=int, default=256, help="interior nodes per direction of the Q1 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 finite-volume measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batched measurement")
     ap.add_argument("--no-oracle-solution", action="store_true",
                     help="skip the oracle's full solve of the Q1 system (the exact errors against it)")
-    ap.add_argument("--mode", choices=["solve", "roofline", "fv128"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched"], default="solve",
                     help="roofline: only the timed solve and the stream probes (for profiler runs); "
-                         "fv128: the 128^3 finite-volume workload alone")
+                         "fv128: the 128^3 finite-volume workload alone; batched: the 512-system workload alone")
     ap.add_argument("--workload", choices=["q1", "fv128"], default="q1", help="workload of --mode roofline")
     args = ap.parse_args()
 
@@ -344,6 +409,9 @@ def main():
 
     if args.mode == "fv128":
         print(json.dumps(fv128_measurement(amp, torch, np, P, dev, args.steps, args.warmup)), flush=True)
+        return
+    if args.mode == "batched":
+        print(json.dumps(batched_measurement(amp, torch, np, P, dev, args.steps, args.warmup)), flush=True)
         return
     if args.mode == "roofline" and args.workload == "fv128":
         A, b, _ = P.blocky_diffusion3d_system(128, 8)
@@ -437,6 +505,10 @@ def main():
         torch.cuda.empty_cache()
         secondary = fv128_measurement(amp, torch, np, P, dev, args.steps, args.warmup,
                                       with_oracle=not args.no_cpu_baseline)
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        batched = batched_measurement(amp, torch, np, P, dev, 1, 1)
 
     out = {
         "metric": METRIC,
@@ -472,6 +544,7 @@ def main():
         "probes": pr,
         "cpu_baseline": cpu,
         "secondary_fv128": secondary,
+        "secondary_batched": batched,
     }
     print(json.dumps(out), flush=True)
 

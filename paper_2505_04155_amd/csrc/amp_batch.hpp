@@ -70,12 +70,14 @@ __global__ void __launch_bounds__(NT) k_batch_precond(const SysDesc *sd, const T
 }
 
 // (the same block size and u_z specialisation as k_spmv, so a system's
-// partial sums are those of its single solve)
+// partial sums are those of its single solve; one chunk of slots per pass
+// -- the order of the sums does not depend on it -- keeps the kernel within
+// the register budget of 4 waves per SIMD)
 template <int UZF>
-__global__ void __launch_bounds__(NTP, (UZF == 16 || UZF == 32) ? AMP_SPMV_WAVES : 4)
-    k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
+__global__ void __launch_bounds__(NTP, 4) k_batch_spmv(const SysDesc *sd, const Task *tasks, int si, int so) {
     AMP_BATCH_TASK(sd, tasks, d, wg);
-    spmv_stage<NTP, false, UZF>(d.c, d.A, d.B, t_.st + si, t_.st + so, wg, Early{t_.part_pre, t_.g, nullptr, 0u});
+    spmv_stage<NTP, false, UZF, kChunk>(d.c, d.A, d.B, t_.st + si, t_.st + so, wg,
+                                        Early{t_.part_pre, t_.g, nullptr, 0u});
 }
 
 __global__ void __launch_bounds__(NT) k_batch_update(const SysDesc *sd, const Task *tasks, int si, int so) {

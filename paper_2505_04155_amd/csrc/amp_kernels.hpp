@@ -25,6 +25,8 @@
 // reduction (a barrier waits only for LDS, so these stay in flight).
 #pragma once
 
+#include <type_traits>
+
 #include "amp_device.hpp"
 
 namespace amp {
@@ -312,14 +314,16 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
         term = (3.0 + c.C) * ring[(t - 1) % kRing] + (2.0 + c.C) * dt;
     }
     if (threadIdx.x == 0) {
-        // the parallel form covers windows of at most WAVE terms; longer ones
-        // (d >= WAVE) and the other indicators are evaluated serially by the
-        // controller itself (a null eta_pre)
+        // the parallel form covers windows of at most WAVE terms; a longer
+        // one (d >= WAVE) is summed serially here, from the same window and
+        // delta_k (the other indicators are evaluated by the controller)
         double eta_pre = INFINITY;
         if (par) {
             double sum = 0.0;
             for (int j = 0; j <= c.d; ++j) sum = sum + readlane_f64(term, j);
             eta_pre = kEps32 * sum;
+        } else if (c.eta_mode == ETA_DELAY) {
+            eta_pre = eta_delay(ring, kk, c.d, c.C, sqrt(s.kind == RES_UPDATE ? a : b));
         }
         // the controller runs on a register copy of the state (the LDS copy
         // would put a round trip on every field it reads and updates)
@@ -331,7 +335,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             if (cs.kind == RES_PERIODIC) cs.n_repl += 1;
             rk = cs.iters;
             rv = d;
-            finish_iteration(cs, c, ring, d, m, par ? &eta_pre : nullptr);
+            finish_iteration(cs, c, ring, d, m, &eta_pre);
         } else if (cs.kind == RES_INIT) {
             cs.bnorm = sqrt(b);
             cs.tol_b = c.tol * cs.bnorm;
@@ -343,7 +347,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
             rv = cs.delta;
             if (cs.delta <= cs.tol_b) cs.status = CONVERGED;
             else if (c.maxit <= 0) cs.status = MAXIT;
-            else prepare_iteration(cs, c, ring, 0, par ? &eta_pre : nullptr);
+            else prepare_iteration(cs, c, ring, 0, &eta_pre);
         } else {  // RES_VERIFY: a = ||t||^2 (exact t), b = ||fl(t)||^2
             cs.true_res = sqrt(a);
             if (cs.true_res <= cs.tol_b) {
@@ -360,7 +364,7 @@ __device__ __forceinline__ void consume_residual(St &s, const Cfg &c, const Bufs
                     cs.status = MAXIT;
                 } else {
                     cs.status = RUNNING;
-                    prepare_iteration(cs, c, ring, cs.iters, par ? &eta_pre : nullptr);
+                    prepare_iteration(cs, c, ring, cs.iters, &eta_pre);
                 }
             }
         }
@@ -486,7 +490,10 @@ template <int PU>
 __device__ __forceinline__ void switch_replace_body(const Sell &A, const Bufs &B, const St &s, int64_t lo,
                                                     int64_t hi) {
     typedef typename Prec<PU == 0 ? 64 : PU>::T TP;
-    const TP *pp = (const TP *)B.p[pslot(PU == 0 ? 64 : PU)][s.x_pb];
+    // (a select, not an index: an argument array indexed at run time is
+    // copied to private memory)
+    constexpr int ps = pslot(PU == 0 ? 64 : PU);
+    const TP *pp = (const TP *)(s.x_pb ? B.p[ps][1] : B.p[ps][0]);
     const double a = s.x_alpha;
     const double *x = B.x;
     float *r = (float *)B.r[1];
@@ -496,11 +503,23 @@ __device__ __forceinline__ void switch_replace_body(const Sell &A, const Bufs &B
     };
     const int64_t s0 = lo / SLICE, s1 = (hi / SLICE < A.nslices) ? hi / SLICE : A.nslices;
     const int lane = threadIdx.x % WAVE;
+    // one slot at a time (this runs once per solve; a lean loop keeps the
+    // preconditioning kernel's register budget); the sum runs in slot order
+    // with one rounding per operation, as row_dot64
     for (int64_t sl = s0 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < s1; sl += NT / WAVE) {
         const SliceRec rec_ = A.srec[sl];
         const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
         double ax = 0.0;
-        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, rec_.width, xval); });
+        for (int j = 0; j < rec_.width; ++j) {
+            int64_t c;
+            if (rec_.soff >= 0) {
+                const int64_t cc = row + A.offs[rec_.soff + j];
+                c = (cc >= 0 && cc < A.np) ? cc : row;
+            } else {
+                c = A.col[base + (int64_t)j * SLICE];
+            }
+            ax = ax + A.v64[base + (int64_t)j * SLICE] * xval(c);
+        }
         r[row] = (float)(B.b[row] - ax);
     }
 }
@@ -621,7 +640,9 @@ __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part
 // Slices are dealt per XCD (xcd_wave_slices).
 // PRIO: issue priority by progress (progress_prio); off where the
 // work-groups sharing a CU belong to different systems with unequal work.
-template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true>
+// SPC: slots per pass (whole chunks); it changes only how many loads are in
+// flight, never the order of the sums.
+template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true, int SPC = AMP_SPMV_SPC>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -634,7 +655,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
     TQ *q = (TQ *)qv;
     const CA *vals = (UR == 64) ? (const CA *)A.v64 : (DIFF ? (const CA *)A.v32 : (const CA *)A.v32p);
     const CZ beta = (CZ)beta_d;
-    constexpr int SPC = AMP_SPMV_SPC, NW = BS / WAVE, NCH = SPC / kChunk;
+    constexpr int NW = BS / WAVE, NCH = SPC / kChunk;
     static_assert(SPC % kChunk == 0 && SPC >= kChunk, "whole chunks per pass");
     // p at guarded index i
     auto pval = [&](uint32_t i) -> TZ {
@@ -671,29 +692,38 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
         if (rec.soff >= 0) {
             const KOffs ol = A.koffs + rec.soff;
             const CA *vs = vals + rec.ptr;   // the slice's values, slot j at vs[64 j + lane]
-            for (int j0 = 0; j0 < w; j0 += SPC) {
-                // a chunk's offsets come from the list only where it has them
-                // (lists are padded to whole chunks); a chunk past the width
-                // reuses the first chunk's
-                int32_t o[SPC];
+            // one pass over slots [j0, j0 + NC kChunk): offsets (scalar loads;
+            // a chunk past the width reuses the first chunk's), then every
+            // value load and gather, then the sums in slot order
+            auto pass = [&](auto ncc, int j0) {
+                constexpr int NC = decltype(ncc)::value, PS = NC * kChunk;
+                int32_t o[PS];
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
+                for (int ch = 0; ch < NC; ++ch) {
                     const int jc = (j0 + ch * kChunk < w) ? j0 + ch * kChunk : j0;
 #pragma unroll
-                    for (int u = 0; u < kChunk; ++u) o[ch * kChunk + u] = ol[jc + u];   // scalar loads
+                    for (int u = 0; u < kChunk; ++u) o[ch * kChunk + u] = ol[jc + u];
                 }
-                CA v[SPC];
-                TZ pj[SPC];
-                const bool full = j0 + SPC <= w;
+                CA v[PS];
+                TZ pj[PS];
+                const bool full = j0 + PS <= w;
 #pragma unroll
-                for (int u = 0; u < SPC; ++u) {
+                for (int u = 0; u < PS; ++u) {
                     const int j = full ? j0 + u : (j0 + u < w ? j0 + u : w - 1);
                     v[u] = at32(vs, (uint32_t)(lane + j * SLICE));
                     pj[u] = pval(rowg + (uint32_t)o[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < SPC; ++u) add(v[u], (CA)pj[u], o[u] == 0, full || j0 + u < w);
+                for (int u = 0; u < PS; ++u) add(v[u], (CA)pj[u], o[u] == 0, full || j0 + u < w);
+            };
+            // passes of NCH chunks while more than one chunk's slots remain,
+            // then single chunks (short rows issue no repeated loads for a
+            // second chunk)
+            int j0 = 0;
+            if constexpr (NCH > 1) {
+                for (; w - j0 > kChunk; j0 += SPC) pass(std::integral_constant<int, NCH>{}, j0);
             }
+            for (; j0 < w; j0 += kChunk) pass(std::integral_constant<int, 1>{}, j0);
         } else {
             const IdxCols sc{A.col + rec.ptr + lane, row};
             const int64_t base = rec.ptr + lane;
@@ -723,7 +753,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
 // that precision's bodies are compiled), else 0 (read from the state).  A
 // state whose u_z differs from UZF can only come from a non-finite residual:
 // it ends the solve as a breakdown.
-template <int BS, bool PRIO = true, int UZF = 0>
+template <int BS, bool PRIO = true, int UZF = 0, int SPC = AMP_SPMV_SPC>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg, const Early &e) {
     __shared__ St s;
@@ -765,14 +795,14 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     }
     const bool first = (k == 0);
     double gam = 0.0, mp = 0.0;
-#define AMP_SP(UZ, UR, DF)                                                                                       \
-    do {                                                                                                        \
-        if (first)                                                                                              \
-            spmv_p_body<UZ, UR, DF, true, BS, PRIO>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], \
-                                                beta, gam, mp);                                                 \
-        else                                                                                                    \
-            spmv_p_body<UZ, UR, DF, false, BS, PRIO>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],                \
-                                                 B.q[pslot(UR)], beta, gam, mp);                                \
+#define AMP_SP(UZ, UR, DF)                                                                                \
+    do {                                                                                                 \
+        if (first)                                                                                       \
+            spmv_p_body<UZ, UR, DF, true, BS, PRIO, SPC>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],     \
+                                                         B.q[pslot(UR)], beta, gam, mp);                 \
+        else                                                                                             \
+            spmv_p_body<UZ, UR, DF, false, BS, PRIO, SPC>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],    \
+                                                          B.q[pslot(UR)], beta, gam, mp);                \
     } while (0)
 #define AMP_SP_R(UZ)                          \
     do {                                      \

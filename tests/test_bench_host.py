@@ -72,3 +72,18 @@ def test_committed_summary_is_parseable():
     t = int(float(fields["traffic_bytes_per_launch"]))
     # within a few percent of the algorithmic bytes of the same launches
     assert 1.0 <= t / 109294085 <= 1.1
+
+
+def test_jacobi_iteration_bytes_by_hand():
+    # 128^3 7-point workload: preconditioning 4 + 2 + 2, product 4 nnz + meta
+    # + 10 per row, update 12 + (16 + 2 x 2) / 2 per row
+    n, nnz, meta = 2097152, 14581760, 393512
+    assert bench.jacobi_iteration_bytes(n, nnz, meta, 16, 32) == n * 8 + nnz * 4 + meta + n * 10 + n * 22
+    assert bench.jacobi_iteration_bytes(n, nnz, meta, 64, 64) == n * 24 + nnz * 8 + meta + n * 32 + n * 40
+
+
+def test_phase_iterations_from_switch_points():
+    info = {"iters": 10, "k_z32": 2, "k_z16": 5, "k_r32": 7}
+    assert bench.phase_iterations(info, "amp64") == {(64, 64): 2, (32, 64): 3, (16, 64): 2, (16, 32): 3}
+    assert bench.phase_iterations(info, "amp16") == {(16, 64): 7, (16, 32): 3}
+    assert bench.phase_iterations({"iters": 4, "k_z32": -1, "k_z16": -1, "k_r32": -1}, "pcg64") == {(64, 64): 4}
