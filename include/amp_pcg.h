@@ -181,7 +181,9 @@ amp_status amp_options_preset(amp_options *opt, int preset);
  * matrix-vector product is computed in u_r).  Converts to sliced ELL (slice
  * height 64, rows in natural order) with an FP64 value plane (products in
  * FP64) and an FP32 plane (products in FP32; the diagonal slot holds the
- * FP64 row sum rounded to FP32 for the difference form).  A slice whose rows
+ * FP64 row sum rounded to FP32 for the difference form).  The textbook FP32
+ * plane (fl32 of every value, for spmv32_diff = 0) is built from the FP64
+ * plane by the first solve or product that uses it.  A slice whose rows
  * share a short list of column offsets (col - row, at most 32, at most two
  * more than its longest row) stores that list once instead of a column index
  * per entry (stencil matrices: every slice); other slices keep int32 column

@@ -422,7 +422,7 @@ __global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, in
 // diagonal, 4 entry that does not fit the slice layout.
 __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, int64_t n, int64_t np,
                        const int64_t *sptr, const int32_t *soff, const int32_t *offs, int32_t *col, double *v64,
-                       float *v32, float *v32p, double *diag, int *err) {
+                       float *v32, double *diag, int *err) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= np) return;
     const int64_t s = row / SLICE, lane = row % SLICE;
@@ -447,7 +447,6 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
         col[slot] = (int32_t)row;
         v64[slot] = 0.0;
         v32[slot] = 0.0f;
-        v32p[slot] = 0.0f;
     }
     for (int j = 0; j < len; ++j) {
         const int32_t c = ci[beg + j];
@@ -467,7 +466,6 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
         const int64_t slot = b + (int64_t)js * SLICE;
         col[slot] = c;
         v64[slot] = v;
-        v32p[slot] = (float)v;
         if (c == row) {
             has_diag = true;
             d = v;
@@ -494,7 +492,7 @@ static amp_status fill_values(amp_matrix A, const amp_csr *csr, hipStream_t st) 
     }
     k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
                                                           A->sptr, A->soff, A->offs, A->col, A->v64, A->v32,
-                                                          A->v32p, A->diag, err);
+                                                          A->diag, err);
     int herr = 0;
     hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
     hipError_t e2 = hipStreamSynchronize(st);
@@ -503,6 +501,25 @@ static amp_status fill_values(amp_matrix A, const amp_csr *csr, hipStream_t st) 
     if (herr & 4) return fail(AMP_ERR_ARG, "matrix fill: entries do not fit the handle's slice layout");
     if (herr & 1) return fail(AMP_ERR_ARG, "matrix fill: column index out of range");
     if (herr & 2) return fail(AMP_ERR_ARG, "matrix fill: missing or non-positive diagonal entry");
+    return AMP_OK;
+}
+
+// The textbook-form FP32 plane: fl32 of every FP64 slot (padding stays 0).
+__global__ void k_plain_plane(const double *v64, int64_t slots, float *v32p) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (int64_t)gridDim.x * blockDim.x)
+        v32p[i] = (float)v64[i];
+}
+
+// Built the first time a solve or product asks for the textbook FP32 form
+// (spmv32_diff = 0): a handle used only with the default row-sum form, or
+// only in FP64, never holds it.
+static amp_status ensure_plain_plane(amp_matrix A, hipStream_t st) {
+    if (A->v32p) return AMP_OK;
+    AMP_TRY(dalloc(&A->v32p, A->slots));
+    k_plain_plane<<<1024, 256, 0, st>>>(A->v64, A->slots, A->v32p);
+    AMP_HIP(hipGetLastError());
+    AMP_HIP(hipStreamSynchronize(st));
+    A->bytes += A->slots * 4;
     return AMP_OK;
 }
 
@@ -593,10 +610,10 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
         (s = dalloc(&A->soff, ns)) != AMP_OK ||
         (s = dalloc(&A->offs, round_up(std::max<int64_t>(noffs, 1), kChunk))) != AMP_OK ||
         (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
-        (s = dalloc(&A->v32, A->slots)) != AMP_OK || (s = dalloc(&A->v32p, A->slots)) != AMP_OK ||
+        (s = dalloc(&A->v32, A->slots)) != AMP_OK ||
         (s = dalloc(&A->diag, A->np)) != AMP_OK)
         return bail(s);
-    A->bytes = ns * 16 + (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4 + 4) + A->np * 8;
+    A->bytes = ns * 16 + (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4) + A->np * 8;
     if (hipMemcpyAsync(A->srec, hrec.data(), hrec.size() * sizeof(SliceRec), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -1304,6 +1321,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     d.M = M;
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
+    if (!o.spmv32_diff && o.eta_mode != AMP_UR_FIXED64) AMP_TRY(ensure_plain_plane(A, d.st));
     Work &w = A->w;
     d.sb = w.st;
     const bool timing = o.spmv_timing != 0;
@@ -1598,6 +1616,9 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
     AMP_TRY(check_options(o));
     if (o.graph || o.spmv_timing || o.solo_rows)
         return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: graph, spmv_timing and solo_rows must be 0");
+    if (!o.spmv32_diff && o.eta_mode != AMP_UR_FIXED64 && !A->v32p)
+        return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: the textbook FP32 value plane (spmv32_diff = 0) is built "
+                                 "by the first amp_pcg_solve or amp_spmv that uses it; run one first");
     void *base = nullptr;
     AMP_TRY(scratch_base(&base));
     const int64_t np = A->np, n = A->n, G = A->guard;
@@ -1806,7 +1827,10 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
             return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: tol must be positive");
     }
     hipStream_t st = as_stream(stream);
-    for (int i = 0; i < nsys; ++i) AMP_TRY(ensure_work(A[i], st));
+    for (int i = 0; i < nsys; ++i) {
+        AMP_TRY(ensure_work(A[i], st));
+        if (!o.spmv32_diff && o.eta_mode != AMP_UR_FIXED64) AMP_TRY(ensure_plain_plane(A[i], st));
+    }
 
     // per-system descriptors and work-group counts
     std::vector<SysDesc> hsd(nsys);
@@ -2084,6 +2108,7 @@ extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const v
     if ((u_r != 64 && u_r != 32) || !valid_prec(u_p)) return fail(AMP_ERR_ARG, "amp_spmv: bad precision");
     hipStream_t st = as_stream(stream);
     AMP_TRY(ensure_work(A, st));
+    if (u_r == 32 && !diff) AMP_TRY(ensure_plain_plane(A, st));
     Work &w = A->w;
     Bufs B = make_bufs(A, nullptr);
     const int64_t n = A->n;
@@ -2105,6 +2130,7 @@ extern "C" amp_status amp_spmv_step(amp_matrix A, int u_z, int u_r, int diff, do
     if ((u_r != 64 && u_r != 32) || !valid_prec(u_z)) return fail(AMP_ERR_ARG, "amp_spmv_step: bad precision");
     hipStream_t st = as_stream(stream);
     AMP_TRY(ensure_work(A, st));
+    if (u_r == 32 && !diff) AMP_TRY(ensure_plain_plane(A, st));
     Bufs B = make_bufs(A, nullptr);
     const int ps = pslot(u_z);
     return dispatch_spmv(A, u_r, u_z, diff, B.z[ps], B.p[ps][0], B.p[ps][1], B.q[pslot(u_r)], 0, beta,
@@ -2239,7 +2265,14 @@ extern "C" amp_status amp_matrix_update_values(amp_matrix A, const amp_csr *csr,
         return fail(AMP_ERR_ARG, "amp_matrix_update_values: null argument");
     if (csr->n != A->n || csr->nnz != A->nnz)
         return fail(AMP_ERR_ARG, "amp_matrix_update_values: size differs from the handle's");
-    return fill_values(A, csr, as_stream(stream));
+    hipStream_t st = as_stream(stream);
+    AMP_TRY(fill_values(A, csr, st));
+    if (A->v32p) {   // keep a textbook plane that exists in step with the new values
+        k_plain_plane<<<1024, 256, 0, st>>>(A->v64, A->slots, A->v32p);
+        AMP_HIP(hipGetLastError());
+        AMP_HIP(hipStreamSynchronize(st));
+    }
+    return AMP_OK;
 }
 
 // ----------------------------------------------------------------------------

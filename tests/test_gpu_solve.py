@@ -412,3 +412,22 @@ def test_nan_system_in_a_batch(amp):
         torch.cuda.synchronize()
         assert infos[i]["status"] == 0 and infos[i]["iters"] == i1["iters"]
         assert torch.equal(xs[i], x1)
+
+
+def test_textbook_plane_built_on_first_use(amp):
+    # the textbook FP32 plane (spmv32 = plain) is built from the FP64 plane by
+    # the first solve that uses it; default-form and FP64 solves never hold it
+    _say("textbook FP32 plane on first use")
+    A, b = CASES["blocky24"]()
+    M = amp.Matrix.from_csr(A)
+    pc = amp.Preconditioner(M, "jacobi")
+    bt = torch.tensor(b, device="cuda")
+    amp.solve(M, pc, bt, preset="amp64")
+    amp.solve(M, pc, bt, preset="pcg64", spmv32="plain")
+    held = M.info()["bytes"]
+    x1, i1 = amp.solve(M, pc, bt, preset="amp64", spmv32="plain")
+    assert M.info()["bytes"] == held + 4 * M.info()["slots"]
+    x2, i2 = amp.solve(M, pc, bt, preset="amp64", spmv32="plain")
+    torch.cuda.synchronize()
+    assert M.info()["bytes"] == held + 4 * M.info()["slots"]
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2) and i1["status"] == 0
