@@ -17,8 +17,8 @@
  *   - "stream": a hipStream_t passed as void* (NULL = the legacy default
  *     stream).  All device work is enqueued on it; calls documented as
  *     host-synchronous wait for their own work before returning.
- *   - Handles (amp_matrix, amp_precond) own device memory allocated with
- *     hipMalloc and are freed by their destroy call.  A handle may be used
+ *   - Handles (amp_matrix, amp_precond) own device memory (hipMalloc, or the
+ *     caller's allocator: amp_set_allocator) and free it in their destroy call.  A handle may be used
  *     by one solve at a time.
  *   - Precisions are named by bit width: 64 = IEEE double, 32 = single,
  *     16 = half.
@@ -196,10 +196,37 @@ amp_status amp_options_preset(amp_options *opt, int preset);
  * null pointers, a CSR failing the validation above, or a missing or
  * non-positive diagonal entry; AMP_ERR_OOM / AMP_ERR_HIP from the runtime.
  */
-amp_status amp_matrix_create(const amp_csr *A, void *stream, amp_matrix *out);
-/* As amp_matrix_create; flags bit 0 keeps every slice in index mode (no
- * shared per-slice column-offset lists). */
+typedef struct {
+    int lanes_per_row;  /* 1 (default): one row per lane, slices of 64 rows; 2, 4, 8 or 16: that many lanes share
+                           a row (slices of 64 / lanes rows, entry e of a row in the row's lane e mod lanes),
+                           for long rows; 0: chosen from the mean row length (1 up to 32 entries, else the power
+                           of two leaving 8 to 16 entries per lane).  More than one lane per row implies index
+                           mode, and is not accepted by the Chebyshev preconditioner or the batched solve */
+    int offset_mode;    /* 1 (default): slices whose rows share a short column-offset list store it once; 0: a
+                           column index per entry everywhere */
+} amp_matrix_tuning;
+/* Fill *t with the defaults (one lane per row, offset mode allowed). */
+void amp_matrix_tuning_default(amp_matrix_tuning *t);
+/* tuning: nullable (defaults).  Errors as listed above, and AMP_ERR_ARG for
+ * lanes_per_row outside {0, 1, 2, 4, 8, 16}. */
+amp_status amp_matrix_create(const amp_csr *A, const amp_matrix_tuning *tuning, void *stream, amp_matrix *out);
+/* As amp_matrix_create with one lane per row; flags bit 0 keeps every slice
+ * in index mode (no shared per-slice column-offset lists). */
 amp_status amp_matrix_create_ex(const amp_csr *A, int flags, void *stream, amp_matrix *out);
+/*
+ * Lanes-per-row autotuner: for each of the ncand candidates (values as
+ * amp_matrix_tuning.lanes_per_row, 0 excluded) build the handle of A with
+ * that layout (offset mode allowed where the layout permits) and time reps
+ * launches of each of the two products an AMP-PCG(FP16) solve runs -- FP64
+ * values with FP16 p, and FP32 row-sum form with FP16 p -- with HIP events,
+ * after a warm-up launch.  *best receives the candidate with the least summed
+ * time; us_per_product (host array of ncand, nullable) the mean of the two
+ * per launch, in microseconds.  Each handle is destroyed before the next is
+ * built.  Host-synchronous.  Errors: AMP_ERR_ARG for null pointers, ncand < 1,
+ * reps < 1 or a bad candidate; any error of amp_matrix_create.
+ */
+amp_status amp_tune_lanes(const amp_csr *A, const int *candidates, int ncand, int reps, int *best,
+                          double *us_per_product, void *stream);
 void amp_matrix_destroy(amp_matrix A);
 /* Layout of a matrix handle. */
 typedef struct {
@@ -210,6 +237,7 @@ typedef struct {
     int64_t offset_slices;  /* slices stored with a shared column-offset list */
     int64_t meta_bytes;     /* column metadata one product reads: 4 B per index-mode slot,
                                the offset lists, 12 B per slice of pointers, plus 8 */
+    int64_t lanes_per_row;  /* lanes sharing one row (1, 2, 4, 8 or 16) */
 } amp_matrix_stats;
 amp_status amp_matrix_info(amp_matrix A, amp_matrix_stats *out);
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "amp_precond_apply", "amp_selector_replay", "amp_paper_kernel_bytes",
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
     "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
-    "amp_set_allocator", "amp_precond_bounds",
+    "amp_set_allocator", "amp_precond_bounds", "amp_matrix_tuning_default", "amp_tune_lanes",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -62,7 +62,11 @@ class Result(ctypes.Structure):
 
 class MatrixStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
-                ("n", "nnz", "slots", "bytes", "nslices", "offset_slices", "meta_bytes")]
+                ("n", "nnz", "slots", "bytes", "nslices", "offset_slices", "meta_bytes", "lanes_per_row")]
+
+
+class MatrixTuning(ctypes.Structure):
+    _fields_ = [("lanes_per_row", ctypes.c_int), ("offset_mode", ctypes.c_int)]
 
 
 _lib = None
@@ -99,7 +103,11 @@ def load(build_if_missing: bool = True):
         L.amp_options_default.argtypes = [ctypes.POINTER(Options)]
         L.amp_options_default.restype = None
         L.amp_options_preset.argtypes = [ctypes.POINTER(Options), i32]
-        L.amp_matrix_create.argtypes = [ctypes.POINTER(Csr), vp, ctypes.POINTER(vp)]
+        L.amp_matrix_create.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(MatrixTuning), vp, ctypes.POINTER(vp)]
+        L.amp_matrix_tuning_default.argtypes = [ctypes.POINTER(MatrixTuning)]
+        L.amp_matrix_tuning_default.restype = None
+        L.amp_tune_lanes.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(dbl), vp]
         L.amp_matrix_create_ex.argtypes = [ctypes.POINTER(Csr), i32, vp, ctypes.POINTER(vp)]
         L.amp_matrix_destroy.argtypes = [vp]
         L.amp_matrix_destroy.restype = None

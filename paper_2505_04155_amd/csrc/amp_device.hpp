@@ -103,6 +103,7 @@ struct Sell {
     const int32_t *offs;
     KOffs koffs;          // offs, for scalar reads
     int64_t guard;        // zero margin (elements) around the gathered z and p vectors
+    int lgL;              // log2 of the lanes per row (0: one row per lane; > 0 only with index-mode slices)
     const double *v64;   // FP64 values
     const float *v32;    // FP32 values, diagonal slot = fl32(row sum) (difference form)
     const float *v32p;   // FP32 values, plain

@@ -228,24 +228,70 @@ __device__ __forceinline__ float row_dot32(const Sell &A, const CS &sc, int64_t 
     with_rec_cols(rec_, (A).col, (A).offs, (A).np, sl, lane, [&](const auto &sc)
 
 // ----------------------------------------------------------------------------
+// several lanes per row
+// ----------------------------------------------------------------------------
+//
+// A matrix built with L = 2^lgL lanes per row (for long rows; index mode
+// only) has slices of 64 / L rows: entry e of the slice's g-th row sits in
+// lane g L + (e mod L), slot e / L.  A lane sums its own slots in slot order;
+// the row's total is then formed by xor-butterfly shuffles across its L
+// lanes, which gives every lane of the row the same bits (each pairwise add
+// is commutative).
+
+// Sum of v over the lanes of each row (all lanes of a row receive it).
+__device__ __forceinline__ double row_lanes_sum(double v, int lgL) {
+    for (int m = 1; m < (1 << lgL); m <<= 1) v = v + __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ float row_lanes_sum(float v, int lgL) {
+    for (int m = 1; m < (1 << lgL); m <<= 1) v = v + __shfl_xor(v, m);
+    return v;
+}
+
+// FP64 products q_i = sum_j a_ij pval(j) of this work-group's slices, one
+// slice per wave at a time; f(row, sub, q_i) is called on every lane (sub:
+// the lane's index within its row, 0 for one row per lane).
+template <int BS, bool LANES, typename PF, typename F>
+__device__ __forceinline__ void rows_dot64(const Sell &A, Wg wg, PF pval, F f) {
+    if constexpr (!LANES) {
+        AMP_SLICE_LOOP(A, sl, wg, BS) {
+            AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
+            double ax = 0.0;
+            AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, pval); });
+            f(row, 0, ax);
+        }
+    } else {
+        const int lgL = A.lgL;
+        int64_t slo, shi;
+        block_range(A.nslices, 1, wg.lb, wg.G, slo, shi);
+        const int lane = threadIdx.x % WAVE;
+        for (int64_t sl = slo + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < shi; sl += BS / WAVE) {
+            const SliceRec rec = A.srec[sl];
+            const int64_t row = sl * (SLICE >> lgL) + (lane >> lgL);
+            const IdxCols sc{A.col + rec.ptr + lane, row};
+            const double ax = row_lanes_sum(row_dot64(A, sc, rec.ptr + lane, rec.width, pval), lgL);
+            f(row, lane & ((1 << lgL) - 1), ax);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // k_init: r0 = b - A x0 in FP64; partials ||r0||^2, ||b||^2, max|r0|
 // ----------------------------------------------------------------------------
 
-template <int BS>
+template <int BS, bool LANES = false>
 __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) {
     double sr = 0.0, sb = 0.0, mr = 0.0;
     double *r = (double *)B.r[0];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl, wg, BS) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
-        double ax = 0.0;
-        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
+    rows_dot64<BS, LANES>(A, wg, [&](int64_t c) { return x[c]; }, [&](int64_t row, int sub, double ax) {
+        if (sub != 0) return;
         const double t = B.b[row] - ax;
         r[row] = t;
         sr += t * t;
         sb += B.b[row] * B.b[row];
         mr = fmax(mr, fabs(t));
-    }
+    });
     double v3[3] = {sr, sb, mr};
     block_reduce<2, 1, BS>(v3);
     sr = v3[0];
@@ -258,7 +304,8 @@ __device__ __forceinline__ void init_stage(const Sell &A, const Bufs &B, Wg wg) 
     }
 }
 
-__global__ void __launch_bounds__(NTS) k_init(Sell A, Bufs B) { init_stage<NTS>(A, B, grid_wg()); }
+template <bool LANES>
+__global__ void __launch_bounds__(NTS) k_init(Sell A, Bufs B) { init_stage<NTS, LANES>(A, B, grid_wg()); }
 
 // ----------------------------------------------------------------------------
 // k_precond
@@ -501,14 +548,15 @@ __device__ __forceinline__ void switch_replace_body(const Sell &A, const Bufs &B
         if (PU == 0) return x[c];
         return x[c] + a * (double)pp[c];
     };
-    const int64_t s0 = lo / SLICE, s1 = (hi / SLICE < A.nslices) ? hi / SLICE : A.nslices;
+    const int lgL = A.lgL, R = SLICE >> lgL;   // rows per slice (several lanes per row: see rows_dot64)
+    const int64_t s0 = lo / R, s1 = (hi / R < A.nslices) ? hi / R : A.nslices;
     const int lane = threadIdx.x % WAVE;
     // one slot at a time (this runs once per solve; a lean loop keeps the
     // preconditioning kernel's register budget); the sum runs in slot order
     // with one rounding per operation, as row_dot64
     for (int64_t sl = s0 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); sl < s1; sl += NT / WAVE) {
         const SliceRec rec_ = A.srec[sl];
-        const int64_t row = sl * SLICE + lane, base = rec_.ptr + lane;
+        const int64_t row = sl * R + (lane >> lgL), base = rec_.ptr + lane;
         double ax = 0.0;
         for (int j = 0; j < rec_.width; ++j) {
             int64_t c;
@@ -520,7 +568,8 @@ __device__ __forceinline__ void switch_replace_body(const Sell &A, const Bufs &B
             }
             ax = ax + A.v64[base + (int64_t)j * SLICE] * xval(c);
         }
-        r[row] = (float)(B.b[row] - ax);
+        ax = row_lanes_sum(ax, lgL);
+        if ((lane & ((1 << lgL) - 1)) == 0) r[row] = (float)(B.b[row] - ax);
     }
 }
 
@@ -642,7 +691,10 @@ __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part
 // work-groups sharing a CU belong to different systems with unequal work.
 // SPC: slots per pass (whole chunks); it changes only how many loads are in
 // flight, never the order of the sums.
-template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true, int SPC = AMP_SPMV_SPC>
+// LANES: the matrix may have several lanes per row (index-mode slices only;
+// see rows_dot64).
+template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true, int SPC = AMP_SPMV_SPC,
+          bool LANES = false>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -670,12 +722,14 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
         if (PRIO) progress_prio(sl - sfirst, shi - sfirst);
         const SliceRec rec = rec_from(nrec);
         nrec = rec_word(A.srec, sl + sstep, shi);
-        const int64_t row = sl * SLICE + lane;
+        const int lgL = LANES ? A.lgL : 0;
+        const int64_t row = LANES ? sl * (SLICE >> lgL) + (lane >> lgL) : sl * SLICE + lane;
+        const bool lead = !LANES || (lane & ((1 << lgL) - 1)) == 0;   // the lane that writes the row's results
         const uint32_t ru = (uint32_t)row, rowg = (uint32_t)(row + A.guard);   // < 2^31
         const int w = rec.width;
         const TZ pi = pval(rowg);
-        if (pn) st32(pn, ru, pi);
-        mp = fmax(mp, fabs((double)pi));
+        if (pn && lead) st32(pn, ru, pi);
+        if (lead) mp = fmax(mp, fabs((double)pi));
         const CA pic = (CA)pi;
         CA acc = (CA)0, dterm = (CA)0;
         auto add = [&](CA v, CA pj, bool dg, bool in) {
@@ -689,7 +743,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
                 acc = (in && !dg) ? to : acc;
             }
         };
-        if (rec.soff >= 0) {
+        if (!LANES && rec.soff >= 0) {
             const KOffs ol = A.koffs + rec.soff;
             const CA *vs = vals + rec.ptr;   // the slice's values, slot j at vs[64 j + lane]
             // one pass over slots [j0, j0 + NC kChunk): offsets (scalar loads;
@@ -743,9 +797,15 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
                 for (int u = 0; u < kChunk; ++u) add(v[u], (CA)pj[u], dg[u], j0 + u < w);
             }
         }
+        if constexpr (LANES) {   // the row's total over its lanes
+            acc = row_lanes_sum(acc, lgL);
+            if (UR == 32 && DIFF) dterm = row_lanes_sum(dterm, lgL);
+        }
         const TQ qq = (TQ)((UR == 32 && DIFF) ? dterm + acc : acc);
-        st32(q, ru, qq);
-        gam += (double)qq * (double)pi;
+        if (lead) {
+            st32(q, ru, qq);
+            gam += (double)qq * (double)pi;
+        }
     }
 }
 
@@ -753,7 +813,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
 // that precision's bodies are compiled), else 0 (read from the state).  A
 // state whose u_z differs from UZF can only come from a non-finite residual:
 // it ends the solve as a breakdown.
-template <int BS, bool PRIO = true, int UZF = 0, int SPC = AMP_SPMV_SPC>
+template <int BS, bool PRIO = true, int UZF = 0, int SPC = AMP_SPMV_SPC, bool LANES = false>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg, const Early &e) {
     __shared__ St s;
@@ -798,11 +858,11 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
 #define AMP_SP(UZ, UR, DF)                                                                                \
     do {                                                                                                 \
         if (first)                                                                                       \
-            spmv_p_body<UZ, UR, DF, true, BS, PRIO, SPC>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],     \
-                                                         B.q[pslot(UR)], beta, gam, mp);                 \
+            spmv_p_body<UZ, UR, DF, true, BS, PRIO, SPC, LANES>(A, wg, B.z[ps], B.p[ps][pb],              \
+                                                         B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, gam, mp); \
         else                                                                                             \
-            spmv_p_body<UZ, UR, DF, false, BS, PRIO, SPC>(A, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1],    \
-                                                          B.q[pslot(UR)], beta, gam, mp);                \
+            spmv_p_body<UZ, UR, DF, false, BS, PRIO, SPC, LANES>(A, wg, B.z[ps], B.p[ps][pb],             \
+                                                          B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, gam, mp); \
     } while (0)
 #define AMP_SP_R(UZ)                          \
     do {                                      \
@@ -831,16 +891,21 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     store_state(s, out, wg);
 }
 
-template <int UZF>
+template <int UZF, bool LANES = false>
 __global__ void __launch_bounds__(NTP, (UZF == 16 || UZF == 32) ? AMP_SPMV_WAVES : 4)
     k_spmv(const St *in, const double *part, int gpart, int grid, Cfg c, Sell A, Bufs B, St *out) {
-    spmv_stage<NTP, true, UZF>(c, A, B, in, out, launch_wg(grid),
-                               Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
+    spmv_stage<NTP, true, UZF, AMP_SPMV_SPC, LANES>(
+        c, A, B, in, out, launch_wg(grid),
+        Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
 }
 
 typedef void (*SpmvFn)(const St *, const double *, int, int, Cfg, Sell, Bufs, St *);
 
-inline SpmvFn spmv_fn(int uzf) {
+// The product kernel for the options' fixed u_z (0: read from the state)
+// and the matrix's lanes per row (any layout with lanes > 1 takes the
+// general u_z path: its long rows make the product bound by the values).
+inline SpmvFn spmv_fn(int uzf, bool lanes = false) {
+    if (lanes) return k_spmv<0, true>;
     switch (uzf) {
         case 16: return k_spmv<16>;
         case 32: return k_spmv<32>;
@@ -851,13 +916,13 @@ inline SpmvFn spmv_fn(int uzf) {
 
 // Stand-alone product (tests, measurement): with first = true, q = A z;
 // otherwise p = z + beta p_old as in the iteration.
-template <int UZ, int UR, bool DIFF>
+template <int UZ, int UR, bool DIFF, bool LANES = false>
 __global__ void __launch_bounds__(NTS) k_spmv_fixed(Sell A, const void *z, const void *po, void *pn, void *q,
                                                    int first, double beta, double *part) {
     double gam = 0.0, mp = 0.0;
     const Wg wg = grid_wg();
-    if (first) spmv_p_body<UZ, UR, DIFF, true, NTS>(A, wg, z, po, pn, q, beta, gam, mp);
-    else spmv_p_body<UZ, UR, DIFF, false, NTS>(A, wg, z, po, pn, q, beta, gam, mp);
+    if (first) spmv_p_body<UZ, UR, DIFF, true, NTS, true, AMP_SPMV_SPC, LANES>(A, wg, z, po, pn, q, beta, gam, mp);
+    else spmv_p_body<UZ, UR, DIFF, false, NTS, true, AMP_SPMV_SPC, LANES>(A, wg, z, po, pn, q, beta, gam, mp);
     gam = block_sum<NTS>(gam);
     if (threadIdx.x == 0 && part) part[wg.lb] = gam;
 }
@@ -1061,26 +1126,24 @@ __global__ void __launch_bounds__(NT) k_update(const St *in, const double *part,
 // (writes nothing but partials).  Partials: ||t||^2, ||fl(t)||^2, max|fl(t)|.
 // ----------------------------------------------------------------------------
 
-template <int RS, int BS>
+template <int RS, int BS, bool LANES = false>
 __device__ __forceinline__ void true_res_body(const Sell &A, const Bufs &B, Wg wg, bool write, double &st,
                                               double &ss, double &mr) {
     typedef typename Prec<RS>::T TR;
     TR *r = (TR *)B.r[pslot(RS)];
     const double *x = B.x;
-    AMP_SLICE_LOOP(A, sl, wg, BS) {
-        AMP_SLICE_ROW(A, sl, lane, row, base, w, BS);
-        double ax = 0.0;
-        AMP_WITH_COLS(A, sl, lane, sc) { ax = row_dot64(A, sc, base, w, [&](int64_t c) { return x[c]; }); });
+    rows_dot64<BS, LANES>(A, wg, [&](int64_t c) { return x[c]; }, [&](int64_t row, int sub, double ax) {
+        if (sub != 0) return;
         const double t = B.b[row] - ax;
         const TR tr = (TR)t;
         if (write) r[row] = tr;
         st += t * t;
         ss += (double)tr * (double)tr;
         mr = fmax(mr, fabs((double)tr));
-    }
+    });
 }
 
-template <int BS>
+template <int BS, bool LANES = false>
 __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, const Bufs &B, int mode, const St *in,
                                                St *out, Wg wg) {
     __shared__ St s;
@@ -1091,8 +1154,8 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
         return;
     }
     double st = 0.0, ss = 0.0, mr = 0.0;
-    if (s.r_store == 64) true_res_body<64, BS>(A, B, wg, mode != 2, st, ss, mr);
-    else true_res_body<32, BS>(A, B, wg, mode != 2, st, ss, mr);
+    if (s.r_store == 64) true_res_body<64, BS, LANES>(A, B, wg, mode != 2, st, ss, mr);
+    else true_res_body<32, BS, LANES>(A, B, wg, mode != 2, st, ss, mr);
     double v3[3] = {st, ss, mr};
     block_reduce<2, 1, BS>(v3);
     st = v3[0];
@@ -1112,8 +1175,9 @@ __device__ __forceinline__ void true_res_stage(const Cfg &c, const Sell &A, cons
     store_state(s, out, wg);
 }
 
+template <bool LANES>
 __global__ void __launch_bounds__(NTS) k_true_res(Cfg c, Sell A, Bufs B, int mode, const St *in, St *out) {
-    true_res_stage<NTS>(c, A, B, mode, in, out, grid_wg());
+    true_res_stage<NTS, LANES>(c, A, B, mode, in, out, grid_wg());
 }
 
 // ----------------------------------------------------------------------------

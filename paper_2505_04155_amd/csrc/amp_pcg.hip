@@ -177,6 +177,7 @@ struct Work {
 struct amp_matrix_s {
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
     int64_t guard = 0;   // largest |column offset| of an offset-mode slice, rounded up to 64
+    int lgL = 0;         // log2 of the lanes per row
     SliceRec *srec = nullptr;
     int64_t *sptr = nullptr;
     int32_t *col = nullptr;
@@ -191,6 +192,7 @@ struct amp_matrix_s {
         s.soff = soff; s.offs = offs;
         s.koffs = reinterpret_cast<KOffs>(reinterpret_cast<uintptr_t>(offs));
         s.guard = guard;
+        s.lgL = lgL;
         s.v64 = v64; s.v32 = v32; s.v32p = v32p;
         return s;
     }
@@ -386,17 +388,18 @@ static amp_status check_csr(const amp_csr *csr, hipStream_t st, const char *who)
 
 // One thread per slice: the longest row, and the sorted union of the column
 // offsets (col - row) of the slice's rows (count -1 when it exceeds kOffMax).
-__global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, int64_t nslices, int32_t *maxlen,
-                             int32_t *ucount, int32_t *uoffs) {
+__global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, int64_t nslices, int lgL,
+                             int32_t *maxlen, int32_t *ucount, int32_t *uoffs) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
-    int32_t w = 0, cnt = 0;
+    const int R = SLICE >> lgL, L = 1 << lgL;   // rows per slice, lanes per row
+    int32_t w = 0, cnt = lgL > 0 ? -1 : 0;      // several lanes per row: index mode
     int32_t *u = uoffs + s * kOffMax;
-    for (int l = 0; l < SLICE; ++l) {
-        const int64_t row = s * SLICE + l;
+    for (int l = 0; l < R; ++l) {
+        const int64_t row = s * R + l;
         if (row >= n) break;
-        const int32_t beg = rp[row], len = rp[row + 1] - beg;
-        w = len > w ? len : w;
+        const int32_t beg = rp[row], len = rp[row + 1] - beg, lw = (len + L - 1) / L;
+        w = lw > w ? lw : w;
         for (int j = 0; j < len && cnt >= 0; ++j) {
             const int64_t o64 = (int64_t)ci[beg + j] - row;
             if (o64 < INT32_MIN || o64 > INT32_MAX) { cnt = -1; break; }
@@ -420,14 +423,17 @@ __global__ void k_slice_scan(const int32_t *rp, const int32_t *ci, int64_t n, in
 // offset), form the FP64 row sum, check columns, the diagonal and the slot
 // structure.  err bits: 1 column out of range, 2 missing or non-positive
 // diagonal, 4 entry that does not fit the slice layout.
-__global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, int64_t n, int64_t np,
+__global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, int64_t n, int64_t np, int lgL,
                        const int64_t *sptr, const int32_t *soff, const int32_t *offs, int32_t *col, double *v64,
                        float *v32, double *diag, int *err) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= np) return;
-    const int64_t s = row / SLICE, lane = row % SLICE;
+    // the row's lanes: g L .. g L + L - 1 of slice s; entry e in lane
+    // g L + (e mod L), slot e / L (one lane per row: lane g, slot e)
+    const int R = SLICE >> lgL, L = 1 << lgL;
+    const int64_t s = row / R, g = row % R;
     const int w = (int)((sptr[s + 1] - sptr[s]) / SLICE);
-    const int64_t b = sptr[s] + lane;
+    const int64_t b = sptr[s] + g * L;
     const int32_t so = soff[s];
     int len = 0, beg = 0;
     double rs = 0.0, d = 0.0;
@@ -435,7 +441,7 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
     if (row < n) {
         beg = rp[row];
         len = rp[row + 1] - beg;
-        if (len > w) {
+        if ((len + L - 1) / L > w) {
             atomicOr(err, 4);
             return;
         }
@@ -443,10 +449,12 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
     }
     // empty slots first
     for (int j = 0; j < w; ++j) {
-        const int64_t slot = b + (int64_t)j * SLICE;
-        col[slot] = (int32_t)row;
-        v64[slot] = 0.0;
-        v32[slot] = 0.0f;
+        for (int t = 0; t < L; ++t) {
+            const int64_t slot = b + (int64_t)j * SLICE + t;
+            col[slot] = (int32_t)row;
+            v64[slot] = 0.0;
+            v32[slot] = 0.0f;
+        }
     }
     for (int j = 0; j < len; ++j) {
         const int32_t c = ci[beg + j];
@@ -463,7 +471,7 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
                 return;
             }
         }
-        const int64_t slot = b + (int64_t)js * SLICE;
+        const int64_t slot = b + (int64_t)(js >> lgL) * SLICE + (js & (L - 1));
         col[slot] = c;
         v64[slot] = v;
         if (c == row) {
@@ -491,8 +499,8 @@ static amp_status fill_values(amp_matrix A, const amp_csr *csr, hipStream_t st) 
         return fail(AMP_ERR_HIP, "matrix fill: memset failed");
     }
     k_fill<<<(unsigned)((A->np + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, csr->val, A->n, A->np,
-                                                          A->sptr, A->soff, A->offs, A->col, A->v64, A->v32,
-                                                          A->diag, err);
+                                                          A->lgL, A->sptr, A->soff, A->offs, A->col, A->v64,
+                                                          A->v32, A->diag, err);
     int herr = 0;
     hipError_t e1 = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
     hipError_t e2 = hipStreamSynchronize(st);
@@ -523,7 +531,9 @@ static amp_status ensure_plain_plane(amp_matrix A, hipStream_t st) {
     return AMP_OK;
 }
 
-extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *stream, amp_matrix *out) {
+// lgL: log2 of the lanes per row; offsets: allow offset-mode slices (only
+// with one lane per row).
+static amp_status create_matrix(const amp_csr *csr, int lgL, bool offsets, void *stream, amp_matrix *out) {
     if (!out) return fail(AMP_ERR_ARG, "amp_matrix_create: out is NULL");
     *out = nullptr;
     if (!csr || !csr->row_ptr || !csr->col_idx || !csr->val)
@@ -539,8 +549,9 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     auto bail = [&](amp_status s) { amp_matrix_destroy(A); return s; };
     A->n = csr->n;
     A->nnz = csr->nnz;
+    A->lgL = lgL;
     A->np = round_up(A->n, PAD);
-    A->nslices = A->np / SLICE;
+    A->nslices = A->np / (SLICE >> lgL);
     const int64_t ns = A->nslices;
 
     amp_status s = check_csr(csr, st, "amp_matrix_create");
@@ -552,8 +563,8 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
         free_scan();
         return bail(s);
     }
-    k_slice_scan<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, A->n, ns, maxlen, ucount,
-                                                             uoffs);
+    k_slice_scan<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(csr->row_ptr, csr->col_idx, A->n, ns, lgL, maxlen,
+                                                             ucount, uoffs);
     std::vector<int32_t> hml(ns), huc(ns), hso(ns), hu((size_t)ns * kOffMax);
     std::vector<int64_t> hp(ns + 1);
     if (hipMemcpyAsync(hml.data(), maxlen, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -568,7 +579,7 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     // slots per row.  Equal lists are stored once; each list starts at a
     // multiple of kChunk entries (aligned for one load) and is padded with 0 to a
     // multiple of kChunk, so a kernel reads kChunk offsets in one load.
-    const bool allow = !(flags & 1);
+    const bool allow = offsets && lgL == 0;
     std::vector<int32_t> hoffs;
     std::map<std::vector<int32_t>, int32_t> lists;
     hp[0] = 0;
@@ -626,8 +637,40 @@ extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *
     return AMP_OK;
 }
 
-extern "C" amp_status amp_matrix_create(const amp_csr *csr, void *stream, amp_matrix *out) {
-    return amp_matrix_create_ex(csr, 0, stream, out);
+extern "C" void amp_matrix_tuning_default(amp_matrix_tuning *t) {
+    if (!t) return;
+    t->lanes_per_row = 1;
+    t->offset_mode = 1;
+}
+
+// Lanes per row from the mean row length: one lane while rows are short
+// (<= 32 entries on average), else the power of two that leaves each lane
+// 8 to 16 entries (at most 16 lanes).
+static int auto_lanes(const amp_csr *csr) {
+    const double mean = (double)csr->nnz / (double)csr->n;
+    int L = 1;
+    if (mean > 32.0)
+        while (L < 16 && mean / L > 16.0) L *= 2;
+    return L;
+}
+
+extern "C" amp_status amp_matrix_create(const amp_csr *csr, const amp_matrix_tuning *tuning, void *stream,
+                                        amp_matrix *out) {
+    amp_matrix_tuning t;
+    amp_matrix_tuning_default(&t);
+    if (tuning) t = *tuning;
+    if (!csr) return fail(AMP_ERR_ARG, "amp_matrix_create: null CSR");
+    int L = t.lanes_per_row;
+    if (L == 0 && csr->n > 0) L = auto_lanes(csr);
+    int lgL = -1;
+    for (int k = 0; k <= 4; ++k)
+        if (L == (1 << k)) lgL = k;
+    if (lgL < 0) return fail(AMP_ERR_ARG, "amp_matrix_create: lanes_per_row must be 0, 1, 2, 4, 8 or 16");
+    return create_matrix(csr, lgL, t.offset_mode != 0, stream, out);
+}
+
+extern "C" amp_status amp_matrix_create_ex(const amp_csr *csr, int flags, void *stream, amp_matrix *out) {
+    return create_matrix(csr, 0, !(flags & 1), stream, out);
 }
 
 extern "C" void amp_matrix_destroy(amp_matrix A) {
@@ -647,6 +690,7 @@ extern "C" amp_status amp_matrix_info(amp_matrix A, amp_matrix_stats *out) {
     out->nslices = A->nslices;
     out->offset_slices = A->offset_slices;
     out->meta_bytes = A->meta_bytes;
+    out->lanes_per_row = 1 << A->lgL;
     return AMP_OK;
 }
 
@@ -930,6 +974,8 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         return fail(AMP_ERR_ARG, "amp_precond_create: unknown preconditioner kind");
     if (kind == AMP_PC_CHEBYSHEV) {
         if (degree < 1 || degree > kChebMax) return fail(AMP_ERR_ARG, "amp_precond_create: degree must be in 1..16");
+        if (A->lgL > 0)
+            return fail(AMP_ERR_ARG, "amp_precond_create: the Chebyshev preconditioner needs one lane per row");
         if (!std::isfinite(lam_lo) || !std::isfinite(lam_hi))
             return fail(AMP_ERR_ARG, "amp_precond_create: bounds must be finite");
         if (lam_lo > 0.0 && lam_hi > 0.0 && !(lam_hi > lam_lo))
@@ -1146,6 +1192,17 @@ static int fixed_uz(const amp_options &o) {
     return 0;
 }
 
+// r0 = b - A x0, and the FP64 true residual (mode as k_true_res), for the
+// matrix's lanes per row.
+static void launch_init(Driver &d) {
+    if (d.S.lgL > 0) k_init<true><<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
+    else k_init<false><<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
+}
+static void launch_true_res(Driver &d, int mode, const St *in, St *out) {
+    if (d.S.lgL > 0) k_true_res<true><<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, mode, in, out);
+    else k_true_res<false><<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, mode, in, out);
+}
+
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
 static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     St *sb = d.sb;
@@ -1191,14 +1248,14 @@ static amp_status enqueue_iterations(Driver &d, int count) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
-            hipExtLaunchKernelGGL(spmv_fn(d.uzf), dim3(d.gl), dim3(NTP), 0, d.st, w.tev[2 * d.launches],
+            hipExtLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0), dim3(d.gl), dim3(NTP), 0, d.st, w.tev[2 * d.launches],
                                   w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B,
                                   &d.sb[ST_SPMV]);
             d.launches += 1;
             d.cfg.spmv_iter = nullptr;
         } else {
-            hipLaunchKernelGGL(spmv_fn(d.uzf), dim3(d.gl), dim3(NTP), 0, d.st, (const St *)&d.sb[ST_PRE],
+            hipLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0), dim3(d.gl), dim3(NTP), 0, d.st, (const St *)&d.sb[ST_PRE],
                                (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &d.sb[ST_SPMV]);
         }
         k_update<<<d.gs, NT, 0, d.st>>>(&d.sb[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
@@ -1206,7 +1263,7 @@ static amp_status enqueue_iterations(Driver &d, int count) {
         d.in = &d.sb[ST_RES];
         d.host_k += 1;
         if (d.cfg.rr_period > 0 && d.host_k % d.cfg.rr_period == 0) {
-            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 1, d.in, &d.sb[ST_TR]);
+            launch_true_res(d, 1, d.in, &d.sb[ST_TR]);
             d.in = &d.sb[ST_TR];
         }
     }
@@ -1297,7 +1354,8 @@ static amp_status snapshot(Driver &d, int slot) {
 // Systems small enough for one work-group to iterate on its own (Jacobi or
 // identity, no periodic replacement).
 static bool solo_eligible(const amp_options &o, amp_matrix A, amp_precond M) {
-    return o.solo_rows > 0 && A->np <= o.solo_rows && o.rr_period == 0 && M->kind != AMP_PC_CHEBYSHEV;
+    return o.solo_rows > 0 && A->np <= o.solo_rows && o.rr_period == 0 && M->kind != AMP_PC_CHEBYSHEV &&
+           A->lgL == 0;
 }
 
 // Upper bound on the single-work-group loop's passes: maxit iterations plus
@@ -1382,7 +1440,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(&w.st[ST_INIT], &s0, sizeof(St), hipMemcpyHostToDevice, d.st));
-    k_init<<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
+    launch_init(d);
     AMP_HIP(hipGetLastError());
     d.in = &w.st[ST_INIT];
     St cur = s0;
@@ -1437,7 +1495,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
         cur = w.snap[pending];
         pending = -1;
         if (cur.status == NEED_VERIFY) {
-            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
+            launch_true_res(d, 0, d.in, &w.st[ST_TR]);
             AMP_HIP(hipGetLastError());
             d.in = &w.st[ST_TR];
             d.host_k = cur.iters;
@@ -1450,7 +1508,7 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     // FP64 true residual of the returned x, unless the termination check just formed it
     double true_res = cur.true_res;
     if (!(o.verify && cur.status == CONVERGED)) {
-        k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
+        launch_true_res(d, 2, d.in, &w.st[ST_REPORT]);
         k_reduce_to<<<1, NT, 0, d.st>>>(d.B.part_res, d.gl, 0, w.scalar);
         AMP_HIP(hipGetLastError());
         double t2 = 0.0;
@@ -1666,7 +1724,7 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
     AMP_HIP(hipMemcpyAsync(w.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(w.x, x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     AMP_HIP(hipMemcpyAsync(&w.st[ST_INIT], &s0, sizeof(St), hipMemcpyHostToDevice, d.st));
-    k_init<<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
+    launch_init(d);
     AMP_HIP(hipGetLastError());
     d.in = &w.st[ST_INIT];
 
@@ -1695,7 +1753,7 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
             continue;
         }
         if (cur.status == NEED_VERIFY) {
-            k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 0, d.in, &w.st[ST_TR]);
+            launch_true_res(d, 0, d.in, &w.st[ST_TR]);
             AMP_HIP(hipGetLastError());
             d.in = &w.st[ST_TR];
             d.host_k = cur.iters;
@@ -1707,7 +1765,7 @@ extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const d
     AMP_HIP(hipMemcpyAsync(x, w.x, n * sizeof(double), hipMemcpyDeviceToDevice, d.st));
     double true_res = cur.true_res;
     if (!(o.verify && cur.status == CONVERGED)) {
-        k_true_res<<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, 2, d.in, &w.st[ST_REPORT]);
+        launch_true_res(d, 2, d.in, &w.st[ST_REPORT]);
         k_reduce_to<<<1, NT, 0, d.st>>>(d.B.part_res, d.gl, 0, w.scalar);
         AMP_HIP(hipGetLastError());
         double t2 = 0.0;
@@ -1823,6 +1881,9 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
                                          " was built for another matrix");
         if (M[i]->kind == AMP_PC_CHEBYSHEV)
             return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: Chebyshev preconditioners are not supported");
+        if (A[i]->lgL > 0)
+            return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: system " + std::to_string(i) +
+                                         " has several lanes per row (one is needed)");
         if (!(tol[i] > 0.0) || !std::isfinite(tol[i]))
             return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: tol must be positive");
     }
@@ -2013,7 +2074,8 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
 template <int UZ, int UR, bool DF>
 static void launch_spmv_fixed(const Sell &S, int gl, const void *z, const void *po, void *pn, void *q, int first,
                               double beta, double *part, hipStream_t st) {
-    k_spmv_fixed<UZ, UR, DF><<<gl, NTS, 0, st>>>(S, z, po, pn, q, first, beta, part);
+    if (S.lgL > 0) k_spmv_fixed<UZ, UR, DF, true><<<gl, NTS, 0, st>>>(S, z, po, pn, q, first, beta, part);
+    else k_spmv_fixed<UZ, UR, DF, false><<<gl, NTS, 0, st>>>(S, z, po, pn, q, first, beta, part);
 }
 
 static amp_status dispatch_spmv(amp_matrix A, int u_r, int u_z, int diff, const void *z, const void *po, void *pn,
@@ -2100,6 +2162,65 @@ extern "C" amp_status amp_tune_group_rows(int nsys, const amp_matrix *A, const a
     }
     g_last_error.clear();
     return AMP_OK;
+}
+
+extern "C" amp_status amp_tune_lanes(const amp_csr *csr, const int *candidates, int ncand, int reps, int *best,
+                                      double *us_per_product, void *stream) {
+    if (!csr || !candidates || !best || ncand < 1 || reps < 1)
+        return fail(AMP_ERR_ARG, "amp_tune_lanes: null pointer or count < 1");
+    for (int c = 0; c < ncand; ++c) {
+        const int L = candidates[c];
+        if (L != 1 && L != 2 && L != 4 && L != 8 && L != 16)
+            return fail(AMP_ERR_ARG, "amp_tune_lanes: candidates must be 1, 2, 4, 8 or 16");
+    }
+    hipStream_t st = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    AMP_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(AMP_ERR_HIP, "amp_tune_lanes: hipEventCreate failed");
+    }
+    auto done = [&](amp_status r) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return r;
+    };
+    double best_t = INFINITY;
+    for (int c = 0; c < ncand; ++c) {
+        amp_matrix_tuning t;
+        amp_matrix_tuning_default(&t);
+        t.lanes_per_row = candidates[c];
+        amp_matrix A = nullptr;
+        amp_status s = amp_matrix_create(csr, &t, stream, &A);
+        if (s != AMP_OK) return done(s);
+        s = ensure_work(A, st);
+        double total = 0.0;
+        for (int ur = 64; s == AMP_OK && ur >= 32; ur -= 32) {
+            const Bufs B = make_bufs(A, nullptr);
+            auto launch = [&]() {
+                return dispatch_spmv(A, ur, 16, 1, B.z[2], B.p[2][0], B.p[2][1], B.q[pslot(ur)], 0, 0.5, B.part_spmv, st);
+            };
+            if ((s = launch()) != AMP_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { s = fail(AMP_ERR_HIP, "amp_tune_lanes: event record"); break; }
+            for (int r = 0; r < reps && s == AMP_OK; ++r) s = launch();
+            if (s != AMP_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                s = fail(AMP_ERR_HIP, "amp_tune_lanes: event timing");
+                break;
+            }
+            total += ms * 1e3 / reps;
+        }
+        amp_matrix_destroy(A);
+        if (s != AMP_OK) return done(s);
+        if (us_per_product) us_per_product[c] = total / 2.0;
+        if (total < best_t) {
+            best_t = total;
+            *best = candidates[c];
+        }
+    }
+    return done(AMP_OK);
 }
 
 extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,

@@ -38,27 +38,33 @@ def _need(t: torch.Tensor, dtype, n=None, name="tensor"):
 class Matrix:
     """Solver-side matrix (sliced ELL, FP64 and FP32 value planes)."""
 
-    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, offsets: bool = True):
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, offsets: bool = True,
+                 lanes: int = 1):
+        """lanes: lanes per row (1, 2, 4, 8, 16; 0 = chosen from the mean row length)."""
         L = B.load()
         n = row_ptr.numel() - 1
         _need(row_ptr, torch.int32, name="row_ptr")
         _need(col_idx, torch.int32, name="col_idx")
         _need(val, torch.float64, col_idx.numel(), name="val")
         csr = B.Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
+        t = B.MatrixTuning()
+        L.amp_matrix_tuning_default(ctypes.byref(t))
+        t.lanes_per_row = int(lanes)
+        t.offset_mode = 1 if offsets else 0
         h = ctypes.c_void_p()
-        B.check(L.amp_matrix_create_ex(ctypes.byref(csr), 0 if offsets else 1, _stream(), ctypes.byref(h)),
+        B.check(L.amp_matrix_create(ctypes.byref(csr), ctypes.byref(t), _stream(), ctypes.byref(h)),
                 "amp_matrix_create")
         self._h = h
         self.n = n
         self.nnz = col_idx.numel()
 
     @classmethod
-    def from_csr(cls, csr, device="cuda", offsets: bool = True):
+    def from_csr(cls, csr, device="cuda", offsets: bool = True, lanes: int = 1):
         """From a workloads.CSR (host numpy arrays)."""
         rp = torch.from_numpy(csr.row_ptr).to(device)
         ci = torch.from_numpy(csr.col_idx).to(device)
         v = torch.from_numpy(csr.val).to(device)
-        return cls(rp, ci, v, offsets=offsets)
+        return cls(rp, ci, v, offsets=offsets, lanes=lanes)
 
     @property
     def handle(self):
@@ -284,4 +290,21 @@ def use_hip_allocator():
     caller allocator are still released through it)."""
     L = B.load()
     B.check(L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None), "amp_set_allocator")
+
+
+def tune_lanes(csr, candidates=(1, 2, 4, 8, 16), reps: int = 20, device="cuda"):
+    """Lanes-per-row autotuner (amp_tune_lanes) for a workloads.CSR: returns
+    (best, {candidate: microseconds per product})."""
+    L = B.load()
+    rp = torch.from_numpy(csr.row_ptr).to(device)
+    ci = torch.from_numpy(csr.col_idx).to(device)
+    v = torch.from_numpy(csr.val).to(device)
+    c = B.Csr(csr.n, ci.numel(), rp.data_ptr(), ci.data_ptr(), v.data_ptr())
+    cands = [int(x) for x in candidates]
+    arr = (ctypes.c_int * len(cands))(*cands)
+    us = (ctypes.c_double * len(cands))()
+    best = ctypes.c_int()
+    B.check(L.amp_tune_lanes(ctypes.byref(c), arr, len(cands), int(reps), ctypes.byref(best), us, _stream()),
+            "amp_tune_lanes")
+    return best.value, {x: us[i] for i, x in enumerate(cands)}
 

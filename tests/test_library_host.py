@@ -78,7 +78,7 @@ def test_option_validation():
 def test_ctypes_structs_match_the_header(tmp_path):
     # the binding's struct mirrors must have the C compiler's sizes and offsets
     structs = {"amp_csr": B.Csr, "amp_options": B.Options, "amp_result": B.Result,
-               "amp_matrix_stats": B.MatrixStats}
+               "amp_matrix_stats": B.MatrixStats, "amp_matrix_tuning": B.MatrixTuning}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "amp_pcg.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -126,4 +126,29 @@ def test_set_allocator_rejects_half_a_pair():
     assert L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(lambda p, ctx: None), None) == B.AMP_ERR_ARG
     assert L.amp_set_allocator(B.ALLOC_FN(), B.FREE_FN(), None) == B.AMP_OK
     assert isinstance(ctypes.c_void_p(), ctypes.c_void_p)
+
+
+@pytest.mark.parametrize("lanes", [-1, 3, 5, 32])
+def test_lanes_per_row_validated_before_any_device_access(lanes):
+    L = B.load()
+    t = B.MatrixTuning()
+    L.amp_matrix_tuning_default(ctypes.byref(t))
+    assert (t.lanes_per_row, t.offset_mode) == (1, 1)
+    t.lanes_per_row = lanes
+    csr = B.Csr(n=100, nnz=300, row_ptr=16, col_idx=16, val=16)
+    h = ctypes.c_void_p()
+    assert L.amp_matrix_create(ctypes.byref(csr), ctypes.byref(t), None, ctypes.byref(h)) == B.AMP_ERR_ARG
+    assert not h.value
+    assert "lanes_per_row" in B.last_error()
+
+
+def test_tune_lanes_rejects_bad_candidates():
+    L = B.load()
+    csr = B.Csr(n=100, nnz=300, row_ptr=16, col_idx=16, val=16)
+    best = ctypes.c_int(-7)
+    for cands, reps in (([1, 3], 5), ([0], 5), ([1, 2], 0)):
+        arr = (ctypes.c_int * len(cands))(*cands)
+        assert L.amp_tune_lanes(ctypes.byref(csr), arr, len(cands), reps, ctypes.byref(best), None, None) == \
+            B.AMP_ERR_ARG
+    assert best.value == -7
 

@@ -272,6 +272,45 @@ def dense_to_csr(A: np.ndarray) -> CSR:
     return CSR(n, np.array(rp, dtype=np.int32), np.array(ci, dtype=np.int32), np.array(vv))
 
 
+def long_row_spd(n: int, mean_row: int = 200, band: int | None = None, seed: int = 0,
+                 integer: bool = False) -> CSR:
+    """A symmetric, strictly diagonally dominant (hence SPD) matrix with long,
+    ragged rows: every row i draws k_i ~ U{mean_row/4, ..., 3 mean_row/4}
+    upper-triangle columns i + d, d ~ U{1, ..., band} (band = 4 mean_row),
+    duplicates and columns past n dropped, and the pattern is mirrored, so a
+    row holds about mean_row off-diagonal entries.  Off-diagonal values are
+    -U(0.1, 1) (integer: -U{1, ..., 4}); the diagonal is 1 + the row's sum of
+    |a_ij|.  With integer=True every product with an integer vector of
+    moderate size is exact in FP64 (and in FP32 below 2^24)."""
+    band = band or 4 * mean_row
+    g = rng_for(6, seed, n)
+    q = max(1, mean_row // 4)
+    k = g.integers(q, 3 * q + 1, size=n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = rows + g.integers(1, band + 1, size=rows.size)
+    keep = cols < n
+    key = np.unique(rows[keep] * n + cols[keep])
+    r, c = key // n, key % n
+    v = -g.integers(1, 5, size=key.size).astype(np.float64) if integer else -g.uniform(0.1, 1.0, key.size)
+    diag = 1.0 + np.bincount(r, weights=-v, minlength=n) + np.bincount(c, weights=-v, minlength=n)
+    R = np.concatenate([r, c, np.arange(n)])
+    C = np.concatenate([c, r, np.arange(n)])
+    V = np.concatenate([v, v, diag])
+    order = np.argsort(R * n + C, kind="stable")
+    R, C, V = R[order], C[order], V[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(R, minlength=n), out=rp[1:])
+    return CSR(n, rp.astype(np.int32), C.astype(np.int32), V)
+
+
+def long_row_system(n: int = 65536, mean_row: int = 200, seed: int = 0):
+    """long_row_spd with b ~ N(0, 1): the long-row workload the lanes-per-row
+    layout is for."""
+    A = long_row_spd(n, mean_row, seed=seed)
+    b = rng_for(6, 1, seed, n).standard_normal(n)
+    return A, b
+
+
 # ---------------------------------------------------------------------------
 # the paper's spectrum-prescribed examples (Section 2 and Section 5)
 # ---------------------------------------------------------------------------
