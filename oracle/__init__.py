@@ -11,6 +11,9 @@ the GPU solver (``paper_2505_04155_amd``) and never imports it.
   precision selector.
 * :mod:`oracle.adjoint`   -- FP64 reference of the differentiable solve's
   gradient (adjoint solve + per-face chain rule).
+* :mod:`oracle.eigbounds` -- Lanczos estimate of the Chebyshev interval.
+* :mod:`oracle.hexop`     -- the matrix-free order-N hexahedral screened
+  Poisson operator (GLL points, trilinear element maps), its diagonal.
 """
 
 from . import cpcg  # noqa: F401

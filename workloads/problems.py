@@ -311,6 +311,25 @@ def long_row_system(n: int = 65536, mean_row: int = 200, seed: int = 0):
     return A, b
 
 
+def hex_vertices(E, perturb: float = 0.2, seed: int = 0) -> np.ndarray:
+    """Vertices of an Ex x Ey x Ez box mesh of [-0.5, 0.5]^3: the uniform
+    grid with every vertex off the boundary moved by perturb h U(-1, 1) per
+    coordinate (h the element width), so the element maps are trilinear, not
+    affine; boundary vertices stay (the box keeps its faces).  Returns an
+    ((Ex+1)(Ey+1)(Ez+1), 3) float64 array, x fastest."""
+    Ex, Ey, Ez = E
+    g = rng_for(7, seed, Ex, Ey, Ez)
+    axes = [np.linspace(-0.5, 0.5, m + 1) for m in (Ex, Ey, Ez)]
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    V = np.stack([X, Y, Z], axis=-1)
+    h = np.array([1.0 / Ex, 1.0 / Ey, 1.0 / Ez])
+    d = perturb * h * g.uniform(-1.0, 1.0, V.shape)
+    inner = np.zeros(V.shape[:3], dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    V[inner] += d[inner]
+    return V.reshape(-1, 3)
+
+
 # ---------------------------------------------------------------------------
 # the paper's spectrum-prescribed examples (Section 2 and Section 5)
 # ---------------------------------------------------------------------------
