@@ -297,6 +297,53 @@ def q1_cpu_baseline(A, b, lo, hi, oracle_iters, k1=2, k2=12):
             "ms_per_iteration": round(per_it, 2), "cpu_model": cpu_model()}
 
 
+# the paper's per-kernel times of Ax for Ex. jac libp (A100, 21.7e6 unknowns,
+# Fig. fig:performance_runtime), microseconds: context only
+PAPER_AX_US = {"p64_q64": 1804.797, "p16_q64": 1685.107, "p16_q32": 812.908}
+FP64_VECTOR_PEAK = 78.6e12
+FP32_VECTOR_PEAK = 157.3e12
+
+
+def hex_measurement(amp, torch, np, P, dev, reps=20, E=(40, 40, 40), order=7):
+    """The matrix-free order-7 hexahedral operator of Ex. jac libp on the
+    paper's 40^3-element mesh (trilinear elements, vertices perturbed by
+    0.2 h): each phase's storage/arithmetic pair timed over `reps` applies
+    (zero fill of q, the element kernel, the mu sum) with HIP events on the
+    launching stream, against the chip's vector peak of the arithmetic."""
+    V = P.hex_vertices(E, 0.2, 0)
+    H = amp.HexOperator(torch.tensor(V, device=dev), E, order=order, lam=1e3)
+    rng = np.random.default_rng(84)
+    p64 = torch.tensor(rng.standard_normal(H.n), device=dev)
+    flops = H.flops_per_element * H.elements
+    out = {"workload": f"screened Poisson -Laplace u + 1e3 u, order {order}, {E[0]}x{E[1]}x{E[2]} trilinear "
+                       f"hexahedra of [-0.5,0.5]^3 (interior vertices moved by 0.2 h), n={H.n}, "
+                       f"{H.local} local nodes, geometric factors formed per quadrature point",
+           "flops_per_element": H.flops_per_element, "phases": {}}
+    stream = torch.cuda.current_stream()
+    for name, up, ur in (("p64_q64", 64, 64), ("p16_q64", 16, 64), ("p16_q32", 16, 32)):
+        p = p64.to({64: torch.float64, 16: torch.float16}[up])
+        H.apply(p, u_r=ur)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            H.apply(p, u_r=ur)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        peak = FP64_VECTOR_PEAK if ur == 64 else FP32_VECTOR_PEAK
+        # algorithmic bytes: p read once (its storage), q written once (u_r)
+        nbytes = H.n * (up // 8 + ur // 8)
+        out["phases"][name] = {
+            "us_per_apply": round(us, 2),
+            "roofline": {"bound": "alu", "achieved": round(flops / (us * 1e-6) / 1e12, 2), "peak": peak / 1e12,
+                         "unit": "TFLOP/s", "frac": round(flops / (us * 1e-6) / peak, 4),
+                         "algorithmic_GB_per_s": round(nbytes / (us * 1e-6) / 1e9, 1)},
+            "paper_a100_us": PAPER_AX_US[name],
+        }
+        log(f"bench: hex Ax {name}: {us:.1f} us per apply, {flops / (us * 1e-6) / 1e12:.2f} TFLOP/s")
+    return out
+
+
 def fv128_measurement(amp, torch, np, P, dev, steps, warmup, with_oracle=True, grid=128):
     """The 128^3 blocky finite-volume workload (Jacobi): time per preset,
     product-kernel roofline, error against the oracle's solution."""
@@ -383,9 +430,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batched measurement")
     ap.add_argument("--no-oracle-solution", action="store_true",
                     help="skip the oracle's full solve of the Q1 system (the exact errors against it)")
-    ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched", "hex"], default="solve",
                     help="roofline: only the timed solve and the stream probes (for profiler runs); "
-                         "fv128: the 128^3 finite-volume workload alone; batched: the 512-system workload alone")
+                         "fv128: the 128^3 finite-volume workload alone; batched: the 512-system workload alone; "
+                         "hex: the matrix-free order-7 hexahedral operator alone")
     ap.add_argument("--workload", choices=["q1", "fv128"], default="q1", help="workload of --mode roofline")
     args = ap.parse_args()
 
@@ -412,6 +460,9 @@ def main():
         return
     if args.mode == "batched":
         print(json.dumps(batched_measurement(amp, torch, np, P, dev, args.steps, args.warmup)), flush=True)
+        return
+    if args.mode == "hex":
+        print(json.dumps({"mode": "hex", **hex_measurement(amp, torch, np, P, dev)}), flush=True)
         return
     if args.mode == "roofline" and args.workload == "fv128":
         A, b, _ = P.blocky_diffusion3d_system(128, 8)

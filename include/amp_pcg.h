@@ -459,6 +459,63 @@ amp_status amp_paper_kernel_bytes(int u_z, int u_r, double out[4]);
  */
 amp_status amp_stream_probe(int mode, const void *src, void *dst, int64_t bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Matrix-free high-order hexahedral operator (Section 5.5, Ex. jac libp:
+ * the screened Poisson equation -Laplace(u) + lambda u = f on a box,
+ * tensor-product elements of order N with Gauss-Lobatto-Legendre points
+ * and quadrature, each element the trilinear image of the reference cube,
+ * homogeneous Dirichlet conditions; the paper's Ax kernel, Table
+ * tab:pcg_cost, with mu = p^T q).
+ *
+ * Mesh: ex x ey x ez elements; the global nodes form the
+ * (N ex + 1) x (N ey + 1) x (N ez + 1) grid, x fastest, and local node
+ * (i, j, k) of element (a, b, c) is grid node (a N + i, b N + j, c N + k).
+ * The unknowns are the grid nodes off the boundary, in grid order: node
+ * (gx, gy, gz) has index (gx-1) + (N ex - 1)((gy-1) + (N ey - 1)(gz-1)),
+ * n = (N ex - 1)(N ey - 1)(N ez - 1).  The element maps come from the
+ * vertex array verts: row vx + (ex+1)(vy + (ey+1) vz) holds vertex
+ * (vx, vy, vz) as (x, y, z); corner (a, b, c) of element (ex, ey, ez) is
+ * vertex (ex + a, ey + b, ez + c).  Geometric factors are formed at every
+ * quadrature point from the element's 8 vertices; nothing per node is
+ * stored.
+ * ------------------------------------------------------------------------ */
+typedef struct amp_hexop_s *amp_hexop;
+
+typedef struct {
+    int64_t n;          /* unknowns */
+    int64_t elements;   /* ex ey ez */
+    int64_t local;      /* element-local nodes: elements (N+1)^3 */
+    int order;          /* N */
+    double lambda;
+    double flops_per_element;   /* arithmetic of one element application (multiply and add counted
+                                   separately) as the operator's definition states it: (264 for N = 7:
+                                   12 (N+1) + 19 for the contractions and the mass term, 149 for the
+                                   geometric factors) per local node */
+} amp_hexop_stats;
+
+/* Create the operator.  order: 3 or 7.  verts: device pointer to
+ * (ex+1)(ey+1)(ez+1) x 3 doubles, copied (the caller keeps ownership).
+ * lambda >= 0.  Errors: AMP_ERR_ARG for counts < 1, an order not built,
+ * n < 1, more than 2^31 - 1 elements or unknowns, a null pointer, a
+ * negative or non-finite lambda, or an element map whose Jacobian
+ * determinant is not positive at every quadrature point (checked on the
+ * device); AMP_ERR_OOM / AMP_ERR_HIP.  Host-synchronous. */
+amp_status amp_hexop_create(int ex, int ey, int ez, int order, const double *verts, double lambda, void *stream,
+                            amp_hexop *out);
+void amp_hexop_destroy(amp_hexop H);
+amp_status amp_hexop_info(amp_hexop H, amp_hexop_stats *out);
+/* q = A p (device vectors of n entries): p stored in u_p (64, 32 or 16:
+ * double, float, _Float16), q and the arithmetic in u_r (64 or 32).
+ * mu (device, nullable): one double, p^T q from per-element partials
+ * p_e^T A_e p_e summed in element order.  q's shared nodes are summed by
+ * atomic adds in no fixed order (exact to rounding, not bitwise
+ * reproducible).  Enqueued on stream, not synchronised.  Errors:
+ * AMP_ERR_ARG for a bad precision or null p / q. */
+amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void *p, void *q, double *mu, void *stream);
+/* diag (device, n doubles) = the diagonal of A, in FP64 (for the Jacobi
+ * preconditioner).  Enqueued on stream, not synchronised. */
+amp_status amp_hexop_diagonal(amp_hexop H, double *diag, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,4 +15,4 @@ Python entry points (argument marshalling only):
 
 from .solver import (Matrix, Preconditioner, solve, solve_batched, tune_group_rows,  # noqa: F401
                      selector_replay, paper_kernel_bytes, use_torch_allocator, use_hip_allocator,
-                     tune_lanes)
+                     tune_lanes, HexOperator)

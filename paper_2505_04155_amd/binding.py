@@ -27,6 +27,7 @@ EXPORTED = [
     "amp_matrix_update_values", "amp_precond_update", "amp_fv_nnz", "amp_fv_csr", "amp_fv_grad_theta",
     "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
     "amp_set_allocator", "amp_precond_bounds", "amp_matrix_tuning_default", "amp_tune_lanes",
+    "amp_hexop_create", "amp_hexop_destroy", "amp_hexop_info", "amp_hexop_apply", "amp_hexop_diagonal",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -63,6 +64,11 @@ class Result(ctypes.Structure):
 class MatrixStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("n", "nnz", "slots", "bytes", "nslices", "offset_slices", "meta_bytes", "lanes_per_row")]
+
+
+class HexStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("elements", ctypes.c_int64), ("local", ctypes.c_int64),
+                ("order", ctypes.c_int), ("lambda_", ctypes.c_double), ("flops_per_element", ctypes.c_double)]
 
 
 class MatrixTuning(ctypes.Structure):
@@ -104,6 +110,12 @@ def load(build_if_missing: bool = True):
         L.amp_options_default.restype = None
         L.amp_options_preset.argtypes = [ctypes.POINTER(Options), i32]
         L.amp_matrix_create.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(MatrixTuning), vp, ctypes.POINTER(vp)]
+        L.amp_hexop_create.argtypes = [i32, i32, i32, i32, vp, dbl, vp, ctypes.POINTER(vp)]
+        L.amp_hexop_destroy.argtypes = [vp]
+        L.amp_hexop_destroy.restype = None
+        L.amp_hexop_info.argtypes = [vp, ctypes.POINTER(HexStats)]
+        L.amp_hexop_apply.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        L.amp_hexop_diagonal.argtypes = [vp, vp, vp]
         L.amp_matrix_tuning_default.argtypes = [ctypes.POINTER(MatrixTuning)]
         L.amp_matrix_tuning_default.restype = None
         L.amp_tune_lanes.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32),

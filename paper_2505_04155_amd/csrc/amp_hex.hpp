@@ -1,0 +1,247 @@
+// Matrix-free order-N hexahedral screened Poisson operator (Section 5.5,
+// Ex. jac libp): q = A p with A = sum over elements of D^T G D + lambda M on
+// the GLL points of each element, the geometric factors of each element's
+// trilinear map formed at every quadrature point from its 8 vertices (24
+// values per element) instead of being stored, and mu = p^T q.
+//
+// Mesh: a box of Ex x Ey x Ez elements; global nodes on the
+// (N Ex + 1) x (N Ey + 1) x (N Ez + 1) grid (x fastest), local node (i, j, k)
+// of element (ex, ey, ez) is grid node (ex N + i, ey N + j, ez N + k); the
+// unknowns are the grid nodes off the boundary (homogeneous Dirichlet), in
+// grid order.  No index arrays: every map is arithmetic.
+//
+// One work-group per element, one thread per local node ((N+1)^3 threads;
+// for N = 7 each wave holds one k-plane).  The element's p values are
+// gathered to LDS; each thread forms the reference gradient from its three
+// grid lines, applies G (from the Jacobian of the trilinear map at its
+// point, formed in registers), and the transposed derivative reads the
+// other threads' fluxes from LDS.  Results are summed into q by atomic adds
+// (q is zeroed first): shared face, edge and corner nodes receive 2 to 8
+// contributions in an order that is not fixed, so q is exact to rounding but
+// not bitwise reproducible.  mu comes from per-element partials p_e^T (A_e
+// p_e) summed in element order (deterministic).
+//
+// Precision: UP is the storage of p (64, 32 or 16), UR the arithmetic and
+// storage of q (64 or 32); the geometric factors and contractions run in UR.
+// Contractions are written as fused multiply-adds (this operator is bound by
+// arithmetic, not by the one-rounding-per-operation rules of the solver's
+// vector kernels).
+#pragma once
+
+#include "amp_device.hpp"
+
+namespace amp {
+
+constexpr int kHexMaxOrder = 7;
+
+// Device view of an operator handle.
+struct HexView {
+    int ex, ey, ez;            // elements per direction
+    int64_t n;                 // unknowns: (N ex - 1)(N ey - 1)(N ez - 1)
+    const double *verts;       // ((ex+1)(ey+1)(ez+1), 3), x fastest
+    const double *tab;         // GLL nodes [N+1], weights [N+1], D [(N+1)^2] (D[m][j] = l_j'(x_m))
+    double lam;
+};
+
+template <typename T>
+__device__ __forceinline__ T hex_fma(T a, T b, T c) {
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float hex_fma<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+
+// The unknown index of grid node (gx, gy, gz), or -1 on the boundary.
+template <int N>
+__device__ __forceinline__ int64_t hex_dof(const HexView &h, int gx, int gy, int gz) {
+    const int mx = N * h.ex, my = N * h.ey, mz = N * h.ez;
+    if (gx <= 0 || gy <= 0 || gz <= 0 || gx >= mx || gy >= my || gz >= mz) return -1;
+    return (int64_t)(gx - 1) + (int64_t)(mx - 1) * ((int64_t)(gy - 1) + (int64_t)(my - 1) * (gz - 1));
+}
+
+// Geometric factors at reference point (r, s, t) of the element whose
+// corner (a, b, c) is X[c][b][a][d]: G = w det(J) J^-1 J^-T (six entries,
+// rr rs rt ss st tt) and w det(J).  J^-1 = adj(J) / det(J), so
+// G = (w / det(J)) adj(J) adj(J)^T.
+template <typename T>
+__device__ __forceinline__ void hex_geometry(const double (&X)[2][2][2][3], T r, T s, T t, T w, T (&G)[6],
+                                             T &wdet) {
+    const T hr[2] = {(T)0.5 * ((T)1 - r), (T)0.5 * ((T)1 + r)};
+    const T hs[2] = {(T)0.5 * ((T)1 - s), (T)0.5 * ((T)1 + s)};
+    const T ht[2] = {(T)0.5 * ((T)1 - t), (T)0.5 * ((T)1 + t)};
+    T J[3][3];   // J[d][q] = dx_d / d(r, s, t)_q
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T jr = 0, js = 0, jt = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                // x_d(r) along the r-line at (s, t) corner pair (b, c), etc.
+                jr = hex_fma((T)0.5 * ((T)X[c][b][1][d] - (T)X[c][b][0][d]), hs[b] * ht[c], jr);
+                js = hex_fma((T)0.5 * ((T)X[c][1][b][d] - (T)X[c][0][b][d]), hr[b] * ht[c], js);
+                jt = hex_fma((T)0.5 * ((T)X[1][c][b][d] - (T)X[0][c][b][d]), hr[b] * hs[c], jt);
+            }
+        J[d][0] = jr;
+        J[d][1] = js;
+        J[d][2] = jt;
+    }
+    // cofactors C[d][q] (adj(J) = C^T)
+    T C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    wdet = w * det;
+    const T f = w / det;
+    // (J^-1)[q][d] = C[d][q] / det:  G[p][q] = (w / det) sum_d C[d][p] C[d][q]
+    G[0] = f * (C[0][0] * C[0][0] + C[1][0] * C[1][0] + C[2][0] * C[2][0]);
+    G[1] = f * (C[0][0] * C[0][1] + C[1][0] * C[1][1] + C[2][0] * C[2][1]);
+    G[2] = f * (C[0][0] * C[0][2] + C[1][0] * C[1][2] + C[2][0] * C[2][2]);
+    G[3] = f * (C[0][1] * C[0][1] + C[1][1] * C[1][1] + C[2][1] * C[2][1]);
+    G[4] = f * (C[0][1] * C[0][2] + C[1][1] * C[1][2] + C[2][1] * C[2][2]);
+    G[5] = f * (C[0][2] * C[0][2] + C[1][2] * C[1][2] + C[2][2] * C[2][2]);
+}
+
+// The element's corner coordinates (wave-uniform loads).
+__device__ __forceinline__ void hex_corners(const HexView &h, int ex, int ey, int ez, double (&X)[2][2][2][3]) {
+    const int vx = h.ex + 1, vy = h.ey + 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int64_t v = (int64_t)(ex + a) + (int64_t)vx * ((ey + b) + (int64_t)vy * (ez + c));
+#pragma unroll
+                for (int d = 0; d < 3; ++d) X[c][b][a][d] = h.verts[3 * v + d];
+            }
+}
+
+// The element of this work-group (blocks dealt so that consecutive
+// elements, which share nodes, run on the same XCD).
+__device__ __forceinline__ void hex_element(const HexView &h, int &ex, int &ey, int &ez) {
+    const int e = xcd_block();
+    ex = e % h.ex;
+    ey = (e / h.ex) % h.ey;
+    ez = e / (h.ex * h.ey);
+}
+
+// q += A_e p_e for this work-group's element; part[e] = p_e^T (A_e p_e).
+template <int N, int UP, int UR>
+__global__ void __launch_bounds__((N + 1) * (N + 1) * (N + 1))
+    k_hex_ax(HexView h, const void *pv, void *qv, double *part) {
+    typedef typename Prec<UP>::T TP;
+    typedef typename Prec<UR>::T T;
+    constexpr int N1 = N + 1, NN = N1 * N1 * N1;
+    __shared__ T s_u[NN], s_f[3][NN], s_D[N1 * N1], s_x[N1], s_w[N1];
+    const TP *p = (const TP *)pv;
+    T *q = (T *)qv;
+    const int tid = threadIdx.x;
+    const int i = tid % N1, j = (tid / N1) % N1, k = tid / (N1 * N1);
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    if (tid < N1 * N1) s_D[tid] = (T)h.tab[2 * N1 + tid];
+    if (tid < N1) {
+        s_x[tid] = (T)h.tab[tid];
+        s_w[tid] = (T)h.tab[N1 + tid];
+    }
+    const int64_t dof = hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k);
+    const T u = (dof >= 0) ? (T)p[dof] : (T)0;
+    s_u[tid] = u;
+    double X[2][2][2][3];
+    hex_corners(h, ex, ey, ez, X);
+    __syncthreads();
+    T G[6], wdet;
+    hex_geometry<T>(X, s_x[i], s_x[j], s_x[k], s_w[i] * s_w[j] * s_w[k], G, wdet);
+    // reference gradient along the three grid lines through the node
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        ur = hex_fma(s_D[i * N1 + m], s_u[(k * N1 + j) * N1 + m], ur);
+        us = hex_fma(s_D[j * N1 + m], s_u[(k * N1 + m) * N1 + i], us);
+        ut = hex_fma(s_D[k * N1 + m], s_u[(m * N1 + j) * N1 + i], ut);
+    }
+    s_f[0][tid] = hex_fma(G[0], ur, hex_fma(G[1], us, G[2] * ut));
+    s_f[1][tid] = hex_fma(G[1], ur, hex_fma(G[3], us, G[4] * ut));
+    s_f[2][tid] = hex_fma(G[2], ur, hex_fma(G[4], us, G[5] * ut));
+    __syncthreads();
+    T au = wdet * (T)h.lam * u;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        au = hex_fma(s_D[m * N1 + i], s_f[0][(k * N1 + j) * N1 + m], au);
+        au = hex_fma(s_D[m * N1 + j], s_f[1][(k * N1 + m) * N1 + i], au);
+        au = hex_fma(s_D[m * N1 + k], s_f[2][(m * N1 + j) * N1 + i], au);
+    }
+    if (dof >= 0) unsafeAtomicAdd(q + dof, au);
+    const double mu = block_sum<NN>((double)u * (double)au);
+    if (tid == 0) part[(int64_t)ez * h.ex * h.ey + (int64_t)ey * h.ex + ex] = mu;
+}
+
+// diag += the diagonal of A_e (FP64): for local node (a, b, c) the reference
+// gradient of its basis function is nonzero only on the three grid lines
+// through it, so A_e's diagonal entry is sum_m D[m][a]^2 G_rr(m, b, c) +
+// sum_m D[m][b]^2 G_ss(a, m, c) + sum_m D[m][c]^2 G_tt(a, b, m) + 2 D[a][a]
+// D[b][b] G_rs + 2 D[a][a] D[c][c] G_rt + 2 D[b][b] D[c][c] G_st (at the node
+// itself) + lambda w det(J).
+template <int N>
+__global__ void __launch_bounds__((N + 1) * (N + 1) * (N + 1)) k_hex_diag(HexView h, double *diag) {
+    constexpr int N1 = N + 1, NN = N1 * N1 * N1;
+    __shared__ double s_g[3][NN];
+    const int tid = threadIdx.x;
+    const int i = tid % N1, j = (tid / N1) % N1, k = tid / (N1 * N1);
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    const double *xg = h.tab, *wg = h.tab + N1, *D = h.tab + 2 * N1;
+    double X[2][2][2][3];
+    hex_corners(h, ex, ey, ez, X);
+    double G[6], wdet;
+    hex_geometry<double>(X, xg[i], xg[j], xg[k], wg[i] * wg[j] * wg[k], G, wdet);
+    s_g[0][tid] = G[0];
+    s_g[1][tid] = G[3];
+    s_g[2][tid] = G[5];
+    __syncthreads();
+    double d = h.lam * wdet;
+    for (int m = 0; m < N1; ++m) {
+        d += D[m * N1 + i] * D[m * N1 + i] * s_g[0][(k * N1 + j) * N1 + m];
+        d += D[m * N1 + j] * D[m * N1 + j] * s_g[1][(k * N1 + m) * N1 + i];
+        d += D[m * N1 + k] * D[m * N1 + k] * s_g[2][(m * N1 + j) * N1 + i];
+    }
+    const double di = D[i * N1 + i], dj = D[j * N1 + j], dk = D[k * N1 + k];
+    d += 2.0 * di * dj * G[1] + 2.0 * di * dk * G[2] + 2.0 * dj * dk * G[4];
+    const int64_t dof = hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k);
+    if (dof >= 0) unsafeAtomicAdd(diag + dof, d);
+}
+
+template <typename T>
+__global__ void k_hex_zero(T *a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = (T)0;
+}
+
+// out[0] = sum of part[0 .. n) in index order (one thread: the element
+// partials of mu, a few tens of thousands).
+__global__ void k_hex_sum(const double *part, int64_t n, double *out) {
+    __shared__ double sh[NT];
+    double s = 0.0;
+    // fixed order: thread t sums its contiguous share, then the shares in order
+    const int64_t per = (n + NT - 1) / NT;
+    const int64_t lo = (int64_t)threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+    for (int64_t e = lo; e < hi; ++e) s += part[e];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT; ++w) t += sh[w];
+        out[0] = t;
+    }
+}
+
+}  // namespace amp

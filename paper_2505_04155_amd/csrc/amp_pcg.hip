@@ -17,6 +17,7 @@
 #include "amp_batch.hpp"
 #include "amp_cheb.hpp"
 #include "amp_fv.hpp"
+#include "amp_hex.hpp"
 #include "amp_kernels.hpp"
 #include "amp_pcg.h"
 
@@ -2512,3 +2513,204 @@ extern "C" const char *amp_status_string(amp_status s) {
 }
 
 extern "C" const char *amp_last_error(void) { return g_last_error.c_str(); }
+
+// ----------------------------------------------------------------------------
+// matrix-free hexahedral operator
+// ----------------------------------------------------------------------------
+
+struct amp_hexop_s {
+    int ex = 0, ey = 0, ez = 0, order = 0;
+    double lam = 0.0;
+    int64_t n = 0;
+    double *verts = nullptr, *tab = nullptr, *part = nullptr;
+};
+
+// GLL nodes of order N (the end points and the roots of P_N', by Newton's
+// method from the Chebyshev-Lobatto points, P_N'' from Legendre's equation
+// (1 - x^2) P'' = 2 x P' - N (N + 1) P), weights 2 / (N (N + 1) P_N(x)^2)
+// and D[m][j] = l_j'(x_m) (barycentric form, diagonal from zero row sums).
+static void gll_tables(int N, std::vector<double> &tab) {
+    auto legendre = [&](double x, double &P, double &dP) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= N; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        P = (N == 0) ? 1.0 : p1;
+        // P_N' = N (x P_N - P_{N-1}) / (x^2 - 1) off the end points
+        dP = N * (x * p1 - p0) / (x * x - 1.0);
+    };
+    const int n1 = N + 1;
+    std::vector<double> x(n1), w(n1);
+    x[0] = -1.0;
+    x[N] = 1.0;
+    for (int j = 1; j < N; ++j) {
+        double t = -std::cos(M_PI * j / N);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(t, P, dP);
+            const double d2P = (2.0 * t * dP - N * (N + 1.0) * P) / (1.0 - t * t);
+            const double step = dP / d2P;
+            t -= step;
+            if (std::fabs(step) < 1e-16) break;
+        }
+        x[j] = t;
+    }
+    for (int j = 0; j < n1; ++j) {
+        double P, dP;
+        legendre(x[j], P, dP);
+        w[j] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+    std::vector<double> c(n1, 1.0);
+    for (int j = 0; j < n1; ++j)
+        for (int k = 0; k < n1; ++k)
+            if (k != j) c[j] *= x[j] - x[k];
+    tab.assign(2 * n1 + n1 * n1, 0.0);
+    for (int j = 0; j < n1; ++j) {
+        tab[j] = x[j];
+        tab[n1 + j] = w[j];
+    }
+    for (int m = 0; m < n1; ++m) {
+        double diag = 0.0;
+        for (int j = 0; j < n1; ++j) {
+            if (j == m) continue;
+            const double v = (c[m] / c[j]) / (x[m] - x[j]);
+            tab[2 * n1 + m * n1 + j] = v;
+            diag -= v;
+        }
+        tab[2 * n1 + m * n1 + m] = diag;
+    }
+}
+
+static HexView hex_view(amp_hexop H) {
+    return HexView{H->ex, H->ey, H->ez, H->n, H->verts, H->tab, H->lam};
+}
+
+// err |= 1 where w det(J) <= 0 (or is not finite) at a quadrature point.
+template <int N>
+__global__ void __launch_bounds__((N + 1) * (N + 1) * (N + 1)) k_hex_check(HexView h, int *err) {
+    constexpr int N1 = N + 1;
+    const int tid = threadIdx.x;
+    const int i = tid % N1, j = (tid / N1) % N1, k = tid / (N1 * N1);
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    double X[2][2][2][3];
+    hex_corners(h, ex, ey, ez, X);
+    double G[6], wdet;
+    hex_geometry<double>(X, h.tab[i], h.tab[j], h.tab[k], 1.0, G, wdet);
+    if (!(wdet > 0.0) || !isfinite(wdet)) atomicOr(err, 1);
+}
+
+extern "C" amp_status amp_hexop_create(int ex, int ey, int ez, int order, const double *verts, double lambda,
+                                       void *stream, amp_hexop *out) {
+    if (!out) return fail(AMP_ERR_ARG, "amp_hexop_create: out is NULL");
+    *out = nullptr;
+    if (!verts) return fail(AMP_ERR_ARG, "amp_hexop_create: null vertex array");
+    if (ex < 1 || ey < 1 || ez < 1) return fail(AMP_ERR_ARG, "amp_hexop_create: element counts must be >= 1");
+    if (order != 3 && order != 7) return fail(AMP_ERR_ARG, "amp_hexop_create: order must be 3 or 7");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(AMP_ERR_ARG, "amp_hexop_create: lambda must be finite and >= 0");
+    const int64_t elements = (int64_t)ex * ey * ez;
+    const int64_t n = ((int64_t)order * ex - 1) * ((int64_t)order * ey - 1) * ((int64_t)order * ez - 1);
+    if (elements >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31))
+        return fail(AMP_ERR_ARG, "amp_hexop_create: more than 2^31 - 1 elements or unknowns");
+    if (n < 1) return fail(AMP_ERR_ARG, "amp_hexop_create: no unknowns");
+    hipStream_t st = as_stream(stream);
+    amp_hexop H = new amp_hexop_s();
+    auto bail = [&](amp_status s) { amp_hexop_destroy(H); return s; };
+    H->ex = ex; H->ey = ey; H->ez = ez; H->order = order; H->lam = lambda; H->n = n;
+    std::vector<double> tab;
+    gll_tables(order, tab);
+    const int64_t nv = 3 * (int64_t)(ex + 1) * (ey + 1) * (ez + 1);
+    amp_status s;
+    int *err = nullptr;
+    if ((s = dalloc(&H->verts, nv)) != AMP_OK || (s = dalloc(&H->tab, tab.size())) != AMP_OK ||
+        (s = dalloc(&H->part, elements)) != AMP_OK || (s = dalloc(&err, 1)) != AMP_OK) {
+        dfree(err);
+        return bail(s);
+    }
+    int herr = 0;
+    hipError_t e = hipMemcpyAsync(H->verts, verts, nv * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(H->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(err, &herr, sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        const HexView v = hex_view(H);
+        if (order == 7) k_hex_check<7><<<(unsigned)elements, 512, 0, st>>>(v, err);
+        else k_hex_check<3><<<(unsigned)elements, 64, 0, st>>>(v, err);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(err);
+    if (e != hipSuccess) return bail(fail(AMP_ERR_HIP, std::string("amp_hexop_create: ") + hipGetErrorString(e)));
+    if (herr) return bail(fail(AMP_ERR_ARG, "amp_hexop_create: an element map has a non-positive Jacobian"));
+    *out = H;
+    return AMP_OK;
+}
+
+extern "C" void amp_hexop_destroy(amp_hexop H) {
+    if (!H) return;
+    dfree(H->verts);
+    dfree(H->tab);
+    dfree(H->part);
+    delete H;
+}
+
+extern "C" amp_status amp_hexop_info(amp_hexop H, amp_hexop_stats *out) {
+    if (!H || !out) return fail(AMP_ERR_ARG, "amp_hexop_info: null argument");
+    const int n1 = H->order + 1;
+    out->n = H->n;
+    out->elements = (int64_t)H->ex * H->ey * H->ez;
+    out->local = out->elements * n1 * n1 * n1;
+    out->order = H->order;
+    out->lambda = H->lam;
+    out->flops_per_element = (double)(12 * n1 + 19 + 149) * n1 * n1 * n1;
+    return AMP_OK;
+}
+
+template <int N>
+static void launch_hex_ax(const HexView &v, int64_t elements, int up, int ur, const void *p, void *q, double *part,
+                          hipStream_t st) {
+    constexpr int T = (N + 1) * (N + 1) * (N + 1);
+    const unsigned g = (unsigned)elements;
+    if (ur == 64) {
+        if (up == 64) k_hex_ax<N, 64, 64><<<g, T, 0, st>>>(v, p, q, part);
+        else if (up == 32) k_hex_ax<N, 32, 64><<<g, T, 0, st>>>(v, p, q, part);
+        else k_hex_ax<N, 16, 64><<<g, T, 0, st>>>(v, p, q, part);
+    } else {
+        if (up == 32) k_hex_ax<N, 32, 32><<<g, T, 0, st>>>(v, p, q, part);
+        else k_hex_ax<N, 16, 32><<<g, T, 0, st>>>(v, p, q, part);
+    }
+}
+
+extern "C" amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void *p, void *q, double *mu,
+                                      void *stream) {
+    if (!H || !p || !q) return fail(AMP_ERR_ARG, "amp_hexop_apply: null argument");
+    if ((u_r != 64 && u_r != 32) || (u_p != 64 && u_p != 32 && u_p != 16) || (u_r == 32 && u_p == 64))
+        return fail(AMP_ERR_ARG, "amp_hexop_apply: u_r must be 64 or 32 and u_p 64, 32 or 16 (not above u_r)");
+    hipStream_t st = as_stream(stream);
+    const int64_t elements = (int64_t)H->ex * H->ey * H->ez;
+    const unsigned gz = (unsigned)std::min<int64_t>(2048, (H->n + 255) / 256);
+    if (u_r == 64) k_hex_zero<double><<<gz, 256, 0, st>>>((double *)q, H->n);
+    else k_hex_zero<float><<<gz, 256, 0, st>>>((float *)q, H->n);
+    const HexView v = hex_view(H);
+    if (H->order == 7) launch_hex_ax<7>(v, elements, u_p, u_r, p, q, H->part, st);
+    else launch_hex_ax<3>(v, elements, u_p, u_r, p, q, H->part, st);
+    if (mu) k_hex_sum<<<1, NT, 0, st>>>(H->part, elements, mu);
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_hexop_diagonal(amp_hexop H, double *diag, void *stream) {
+    if (!H || !diag) return fail(AMP_ERR_ARG, "amp_hexop_diagonal: null argument");
+    hipStream_t st = as_stream(stream);
+    const int64_t elements = (int64_t)H->ex * H->ey * H->ez;
+    k_hex_zero<double><<<(unsigned)std::min<int64_t>(2048, (H->n + 255) / 256), 256, 0, st>>>(diag, H->n);
+    const HexView v = hex_view(H);
+    if (H->order == 7) k_hex_diag<7><<<(unsigned)elements, 512, 0, st>>>(v, diag);
+    else k_hex_diag<3><<<(unsigned)elements, 64, 0, st>>>(v, diag);
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+

@@ -308,3 +308,45 @@ def tune_lanes(csr, candidates=(1, 2, 4, 8, 16), reps: int = 20, device="cuda"):
             "amp_tune_lanes")
     return best.value, {x: us[i] for i, x in enumerate(cands)}
 
+
+class HexOperator:
+    """Matrix-free order-N hexahedral screened Poisson operator
+    (amp_hexop_*): q = A p on the interior nodes of an ex x ey x ez box mesh
+    whose element maps come from the vertex array ((ex+1)(ey+1)(ez+1), 3)."""
+
+    def __init__(self, verts: torch.Tensor, E, order: int = 7, lam: float = 1e3):
+        L = B.load()
+        _need(verts, torch.float64, name="verts")
+        ex, ey, ez = (int(e) for e in E)
+        h = ctypes.c_void_p()
+        B.check(L.amp_hexop_create(ex, ey, ez, int(order), _ptr(verts), float(lam), _stream(), ctypes.byref(h)),
+                "amp_hexop_create")
+        self._h = h
+        st = B.HexStats()
+        B.check(L.amp_hexop_info(h, ctypes.byref(st)), "amp_hexop_info")
+        self.n, self.elements, self.local = st.n, st.elements, st.local
+        self.order, self.lam, self.flops_per_element = st.order, st.lambda_, st.flops_per_element
+        self.device = verts.device
+
+    def apply(self, p: torch.Tensor, u_r: int = 64, mu: bool = True):
+        """q = A p with p's dtype as its storage precision and u_r the
+        arithmetic and q precision; returns (q, mu tensor or None)."""
+        u_p = {torch.float64: 64, torch.float32: 32, torch.float16: 16}[p.dtype]
+        _need(p, p.dtype, self.n, "p")
+        q = torch.empty(self.n, dtype=_TORCH[u_r], device=p.device)
+        m = torch.zeros(1, dtype=torch.float64, device=p.device) if mu else None
+        B.check(B.load().amp_hexop_apply(self._h, u_p, u_r, _ptr(p), _ptr(q), _ptr(m) if mu else None, _stream()),
+                "amp_hexop_apply")
+        return q, m
+
+    def diagonal(self):
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        B.check(B.load().amp_hexop_diagonal(self._h, _ptr(d), _stream()), "amp_hexop_diagonal")
+        return d
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and B._lib is not None and not sys.is_finalizing():
+            B._lib.amp_hexop_destroy(h)
+            self._h = None
+
