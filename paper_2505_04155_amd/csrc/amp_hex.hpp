@@ -10,15 +10,14 @@
 // unknowns are the grid nodes off the boundary (homogeneous Dirichlet), in
 // grid order.  No index arrays: every map is arithmetic.
 //
-// One work-group per element, one thread per local node ((N+1)^3 threads;
-// for N = 7 each wave holds one k-plane).  The element's p values are
-// gathered to LDS; each thread forms the reference gradient from its three
-// grid lines, applies G (from the Jacobian of the trilinear map at its
-// point, formed in registers), and the transposed derivative reads the
-// other threads' fluxes from LDS.  Results are summed into q by atomic adds
-// (q is zeroed first): shared face, edge and corner nodes receive 2 to 8
+// One work-group per element, (N+1)^2 threads (N = 7: one wave), thread
+// (i, j) owning the grid line (i, j, 0..N) (k_hex_ax).  The element's p
+// values are gathered to LDS; the reference gradient, G (from the Jacobian
+// of the trilinear map at each point, formed in registers) and the
+// transposed derivative follow the line.  Results are summed into q (zeroed
+// first) by atomic adds: shared face, edge and corner nodes receive 2 to 8
 // contributions in an order that is not fixed, so q is exact to rounding but
-// not bitwise reproducible.  mu comes from per-element partials p_e^T (A_e
+// not bitwise reproducible there.  mu comes from per-element partials p_e^T (A_e
 // p_e) summed in element order (deterministic).
 //
 // Precision: UP is the storage of p (64, 32 or 16), UR the arithmetic and
@@ -135,54 +134,162 @@ __device__ __forceinline__ void hex_element(const HexView &h, int &ex, int &ey, 
 }
 
 // q += A_e p_e for this work-group's element; part[e] = p_e^T (A_e p_e).
+// One wave per element (N = 7: 64 threads), thread (i, j) owning the grid
+// line of nodes (i, j, 0..N): its p values, t-derivatives and t-fluxes stay
+// in registers, so only the r- and s-contractions read LDS (32 reads per
+// node instead of 96 for one thread per node).  The Jacobian's k-independent
+// parts are formed once per line: dx/dr and dx/ds are linear in t, dx/dt
+// does not depend on t.  The rows and columns of D for the thread's own i
+// and j are held in registers; those for the loop's k are wave-uniform.
+// Placement of D: 1, the thread's rows and columns in registers; 0, one LDS
+// copy per work-group (fewer registers, more resident waves).
+#ifndef AMP_HEX_DREG
+#define AMP_HEX_DREG 1
+#endif
+// 1: the r-fluxes of plane k overwrite p's plane k once the wave has read it
+// (one wave per element, so in order), saving a third of the LDS.
+#ifndef AMP_HEX_ALIAS
+#define AMP_HEX_ALIAS 0
+#endif
 template <int N, int UP, int UR>
-__global__ void __launch_bounds__((N + 1) * (N + 1) * (N + 1))
+__global__ void __launch_bounds__((N + 1) * (N + 1))
     k_hex_ax(HexView h, const void *pv, void *qv, double *part) {
     typedef typename Prec<UP>::T TP;
     typedef typename Prec<UR>::T T;
-    constexpr int N1 = N + 1, NN = N1 * N1 * N1;
-    __shared__ T s_u[NN], s_f[3][NN], s_D[N1 * N1], s_x[N1], s_w[N1];
+    constexpr int N1 = N + 1, NP = N1 * N1;
+    static_assert(NP <= WAVE, "one wave per element");
+    __shared__ T s_u[N1 * NP], s_fs[N1 * NP];
+    __shared__ T s_fr_own[AMP_HEX_ALIAS ? 1 : N1 * NP];
+    __shared__ T s_D[N1 * N1];
+    __shared__ double s_mu[NP];
+    T *const s_fr = AMP_HEX_ALIAS ? s_u : s_fr_own;
     const TP *p = (const TP *)pv;
     T *q = (T *)qv;
     const int tid = threadIdx.x;
-    const int i = tid % N1, j = (tid / N1) % N1, k = tid / (N1 * N1);
+    const int i = tid % N1, j = tid / N1;
     int ex, ey, ez;
     hex_element(h, ex, ey, ez);
-    if (tid < N1 * N1) s_D[tid] = (T)h.tab[2 * N1 + tid];
-    if (tid < N1) {
-        s_x[tid] = (T)h.tab[tid];
-        s_w[tid] = (T)h.tab[N1 + tid];
+    const double *xg = h.tab, *wg = h.tab + N1, *Dg = h.tab + 2 * N1;
+    // this line's p and unknown indices
+    T u[N1];
+    int64_t dof[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        dof[k] = hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k);
+        u[k] = (dof[k] >= 0) ? (T)p[dof[k]] : (T)0;
+        s_u[k * NP + tid] = u[k];
     }
-    const int64_t dof = hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k);
-    const T u = (dof >= 0) ? (T)p[dof] : (T)0;
-    s_u[tid] = u;
+    T Di[N1], Dj[N1], DTi[N1], DTj[N1];
+    if constexpr (AMP_HEX_DREG) {
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            Di[m] = (T)Dg[i * N1 + m];
+            Dj[m] = (T)Dg[j * N1 + m];
+            DTi[m] = (T)Dg[m * N1 + i];
+            DTj[m] = (T)Dg[m * N1 + j];
+        }
+    } else {
+        for (int e = tid; e < N1 * N1; e += NP) s_D[e] = (T)Dg[e];
+    }
+    // D[a][b] for the thread's own row/column indices
+    auto dd = [&](const T *reg, int a, int b, int m) -> T {
+        if constexpr (AMP_HEX_DREG) return reg[m];
+        else return s_D[a * N1 + b];
+    };
+    // Jacobian pieces of the line (i, j): dx_d/dr = Pr0[d] ht0 + Pr1[d] ht1,
+    // dx_d/ds = Ps0[d] ht0 + Ps1[d] ht1, dx_d/dt = Jt[d]
     double X[2][2][2][3];
     hex_corners(h, ex, ey, ez, X);
-    __syncthreads();
-    T G[6], wdet;
-    hex_geometry<T>(X, s_x[i], s_x[j], s_x[k], s_w[i] * s_w[j] * s_w[k], G, wdet);
-    // reference gradient along the three grid lines through the node
-    T ur = 0, us = 0, ut = 0;
+    const T r = (T)xg[i], s = (T)xg[j];
+    const T hr[2] = {(T)0.5 * ((T)1 - r), (T)0.5 * ((T)1 + r)};
+    const T hs[2] = {(T)0.5 * ((T)1 - s), (T)0.5 * ((T)1 + s)};
+    T Pr[2][3], Ps[2][3], Jt[3];
 #pragma unroll
-    for (int m = 0; m < N1; ++m) {
-        ur = hex_fma(s_D[i * N1 + m], s_u[(k * N1 + j) * N1 + m], ur);
-        us = hex_fma(s_D[j * N1 + m], s_u[(k * N1 + m) * N1 + i], us);
-        ut = hex_fma(s_D[k * N1 + m], s_u[(m * N1 + j) * N1 + i], ut);
-    }
-    s_f[0][tid] = hex_fma(G[0], ur, hex_fma(G[1], us, G[2] * ut));
-    s_f[1][tid] = hex_fma(G[1], ur, hex_fma(G[3], us, G[4] * ut));
-    s_f[2][tid] = hex_fma(G[2], ur, hex_fma(G[4], us, G[5] * ut));
-    __syncthreads();
-    T au = wdet * (T)h.lam * u;
+    for (int d = 0; d < 3; ++d) {
 #pragma unroll
-    for (int m = 0; m < N1; ++m) {
-        au = hex_fma(s_D[m * N1 + i], s_f[0][(k * N1 + j) * N1 + m], au);
-        au = hex_fma(s_D[m * N1 + j], s_f[1][(k * N1 + m) * N1 + i], au);
-        au = hex_fma(s_D[m * N1 + k], s_f[2][(m * N1 + j) * N1 + i], au);
+        for (int c = 0; c < 2; ++c) {
+            Pr[c][d] = hex_fma((T)0.5 * ((T)X[c][0][1][d] - (T)X[c][0][0][d]), hs[0],
+                               (T)0.5 * ((T)X[c][1][1][d] - (T)X[c][1][0][d]) * hs[1]);
+            Ps[c][d] = hex_fma((T)0.5 * ((T)X[c][1][0][d] - (T)X[c][0][0][d]), hr[0],
+                               (T)0.5 * ((T)X[c][1][1][d] - (T)X[c][0][1][d]) * hr[1]);
+        }
+        T jt = 0;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                jt = hex_fma((T)0.5 * ((T)X[1][b][a][d] - (T)X[0][b][a][d]), hr[a] * hs[b], jt);
+        Jt[d] = jt;
     }
-    if (dof >= 0) unsafeAtomicAdd(q + dof, au);
-    const double mu = block_sum<NN>((double)u * (double)au);
-    if (tid == 0) part[(int64_t)ez * h.ex * h.ey + (int64_t)ey * h.ex + ex] = mu;
+    const T wij = (T)wg[i] * (T)wg[j];
+    __syncthreads();
+    T ft[N1], au[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            ur = hex_fma(dd(Di, i, m, m), s_u[k * NP + j * N1 + m], ur);
+            us = hex_fma(dd(Dj, j, m, m), s_u[k * NP + m * N1 + i], us);
+            ut = hex_fma((T)Dg[k * N1 + m], u[m], ut);
+        }
+        const T t = (T)xg[k];
+        const T ht0 = (T)0.5 * ((T)1 - t), ht1 = (T)0.5 * ((T)1 + t);
+        T J[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            J[d][0] = hex_fma(Pr[0][d], ht0, Pr[1][d] * ht1);
+            J[d][1] = hex_fma(Ps[0][d], ht0, Ps[1][d] * ht1);
+            J[d][2] = Jt[d];
+        }
+        T C[3][3];
+        C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const T det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+        const T w = wij * (T)wg[k];
+        const T f = w / det;
+        // grad_x u = J^-T (ur, us, ut) = C (ur, us, ut) / det; the fluxes are
+        // G (ur, us, ut) = (w / det) C^T C (ur, us, ut)
+        const T g0 = hex_fma(C[0][0], ur, hex_fma(C[0][1], us, C[0][2] * ut));
+        const T g1 = hex_fma(C[1][0], ur, hex_fma(C[1][1], us, C[1][2] * ut));
+        const T g2 = hex_fma(C[2][0], ur, hex_fma(C[2][1], us, C[2][2] * ut));
+        s_fr[k * NP + tid] = f * hex_fma(C[0][0], g0, hex_fma(C[1][0], g1, C[2][0] * g2));
+        s_fs[k * NP + tid] = f * hex_fma(C[0][1], g0, hex_fma(C[1][1], g1, C[2][1] * g2));
+        ft[k] = f * hex_fma(C[0][2], g0, hex_fma(C[1][2], g1, C[2][2] * g2));
+        au[k] = w * det * (T)h.lam * u[k];
+    }
+    __syncthreads();
+    double mu = 0.0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T a = au[k];
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            a = hex_fma(dd(DTi, m, i, m), s_fr[k * NP + j * N1 + m], a);
+            a = hex_fma(dd(DTj, m, j, m), s_fs[k * NP + m * N1 + i], a);
+            a = hex_fma((T)Dg[m * N1 + k], ft[m], a);
+        }
+        // (every node by atomic add: a plain store for the nodes inside the
+        // element, whose only contributor this element is, was measured 2.3x
+        // slower -- the divergent branch around the atomic)
+        if (dof[k] >= 0) unsafeAtomicAdd(q + dof[k], a);
+        mu += (double)u[k] * (double)a;
+    }
+    // per-element partial, summed over the lines in thread order
+    s_mu[tid] = mu;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int l = 0; l < NP; ++l) t += s_mu[l];
+        part[(int64_t)ez * h.ex * h.ey + (int64_t)ey * h.ex + ex] = t;
+    }
 }
 
 // diag += the diagonal of A_e (FP64): for local node (a, b, c) the reference
@@ -226,20 +333,19 @@ __global__ void k_hex_zero(T *a, int64_t n) {
         a[i] = (T)0;
 }
 
-// out[0] = sum of part[0 .. n) in index order (one thread: the element
-// partials of mu, a few tens of thousands).
-__global__ void k_hex_sum(const double *part, int64_t n, double *out) {
-    __shared__ double sh[NT];
+// out[0] = sum of part[0 .. n): thread t sums part[t], part[t + 1024], ...
+// (coalesced), then thread 0 adds the 1024 sums in thread order -- a fixed
+// order, so the result is reproducible.
+constexpr int kHexSumThreads = 1024;
+__global__ void __launch_bounds__(kHexSumThreads) k_hex_sum(const double *part, int64_t n, double *out) {
+    __shared__ double sh[kHexSumThreads];
     double s = 0.0;
-    // fixed order: thread t sums its contiguous share, then the shares in order
-    const int64_t per = (n + NT - 1) / NT;
-    const int64_t lo = (int64_t)threadIdx.x * per, hi = lo + per < n ? lo + per : n;
-    for (int64_t e = lo; e < hi; ++e) s += part[e];
+    for (int64_t e = threadIdx.x; e < n; e += kHexSumThreads) s += part[e];
     sh[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < NT; ++w) t += sh[w];
+        for (int w = 0; w < kHexSumThreads; ++w) t += sh[w];
         out[0] = t;
     }
 }

@@ -2672,7 +2672,7 @@ extern "C" amp_status amp_hexop_info(amp_hexop H, amp_hexop_stats *out) {
 template <int N>
 static void launch_hex_ax(const HexView &v, int64_t elements, int up, int ur, const void *p, void *q, double *part,
                           hipStream_t st) {
-    constexpr int T = (N + 1) * (N + 1) * (N + 1);
+    constexpr int T = (N + 1) * (N + 1);
     const unsigned g = (unsigned)elements;
     if (ur == 64) {
         if (up == 64) k_hex_ax<N, 64, 64><<<g, T, 0, st>>>(v, p, q, part);
@@ -2697,7 +2697,7 @@ extern "C" amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void 
     const HexView v = hex_view(H);
     if (H->order == 7) launch_hex_ax<7>(v, elements, u_p, u_r, p, q, H->part, st);
     else launch_hex_ax<3>(v, elements, u_p, u_r, p, q, H->part, st);
-    if (mu) k_hex_sum<<<1, NT, 0, st>>>(H->part, elements, mu);
+    if (mu) k_hex_sum<<<1, kHexSumThreads, 0, st>>>(H->part, elements, mu);
     AMP_HIP(hipGetLastError());
     return AMP_OK;
 }
