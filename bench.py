@@ -428,6 +428,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 finite-volume measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batched measurement")
+    ap.add_argument("--no-hex", action="store_true", help="skip the matrix-free hexahedral operator measurement")
     ap.add_argument("--no-oracle-solution", action="store_true",
                     help="skip the oracle's full solve of the Q1 system (the exact errors against it)")
     ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched", "hex"], default="solve",
@@ -560,6 +561,10 @@ def main():
     if not args.no_batched:
         torch.cuda.empty_cache()
         batched = batched_measurement(amp, torch, np, P, dev, 1, 1)
+    hexop = None
+    if not args.no_hex:
+        torch.cuda.empty_cache()
+        hexop = hex_measurement(amp, torch, np, P, dev)
 
     out = {
         "metric": METRIC,
@@ -596,6 +601,7 @@ def main():
         "cpu_baseline": cpu,
         "secondary_fv128": secondary,
         "secondary_batched": batched,
+        "secondary_hex_ax": hexop,
     }
     print(json.dumps(out), flush=True)
 
