@@ -515,6 +515,19 @@ amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void *p, void *q
 /* diag (device, n doubles) = the diagonal of A, in FP64 (for the Jacobi
  * preconditioner).  Enqueued on stream, not synchronised. */
 amp_status amp_hexop_diagonal(amp_hexop H, double *diag, void *stream);
+/* A matrix handle that wraps the operator, for amp_pcg_solve with the
+ * Jacobi (its diagonal, from amp_hexop_diagonal) or identity preconditioner:
+ * AMP-PCG on the matrix-free operator, the paper's Ex. jac libp.  The
+ * solve's product is then the element kernel with p = z + beta p_old formed
+ * at every gathered node, q summed by atomic adds (the update clears it for
+ * the next product), gamma = sum_e p_e^T A_e p_e in element order; the x
+ * update is not deferred, and r is not replaced at the u_r switch (the
+ * option is ignored).  The operator must outlive the handle (it is not
+ * owned).  amp_spmv, amp_spmv_step, amp_matrix_update_values, the batched
+ * and allocation-free solves, the Chebyshev preconditioner, periodic
+ * replacement, graph replay and group_rows refuse such a handle
+ * (AMP_ERR_ARG).  Host-synchronous. */
+amp_status amp_matrix_from_hexop(amp_hexop H, void *stream, amp_matrix *out);
 
 #ifdef __cplusplus
 }

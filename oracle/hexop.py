@@ -194,3 +194,36 @@ class HexMesh:
         n1 = self.N + 1
         per_node = 3 * 2 * n1 + 15 + 3 * 2 * n1 + 2 + 2 + (72 + 12 + 27 + 5 + 1 + 32)
         return per_node * n1 ** 3
+
+
+def pcg(mesh: HexMesh, b, tol: float = 1e-10, maxit: int = 5000, jacobi: bool = True):
+    """Alg. 1 (FP64 PCG) on the matrix-free operator with the Jacobi
+    preconditioner M = diag(A) (or M = I), x0 = 0, stopped when
+    ||r_k|| <= tol ||b||.  Returns (x, {"iters", "relres", "relres_true"})."""
+    b = np.asarray(b, dtype=np.float64)
+    dinv = 1.0 / mesh.diagonal() if jacobi else np.ones_like(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = float(np.sqrt(b @ b))
+    info = {"iters": 0}
+    if np.sqrt(r @ r) <= tol * bnorm:
+        info.update(relres=float(np.sqrt(r @ r)) / bnorm, relres_true=float(np.sqrt(r @ r)) / bnorm)
+        return x, info
+    p = None
+    rho_prev = None
+    k = 0
+    for k in range(1, maxit + 1):
+        z = dinv * r
+        rho = float(r @ z)
+        p = z.copy() if p is None else z + (rho / rho_prev) * p
+        q = mesh.apply(p)
+        alpha = rho / float(q @ p)
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_prev = rho
+        if np.sqrt(r @ r) <= tol * bnorm:
+            break
+    t = b - mesh.apply(x)
+    info.update(iters=k, relres=float(np.sqrt(r @ r)) / bnorm, relres_true=float(np.sqrt(t @ t)) / bnorm)
+    return x, info
+

@@ -28,6 +28,7 @@ EXPORTED = [
     "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
     "amp_set_allocator", "amp_precond_bounds", "amp_matrix_tuning_default", "amp_tune_lanes",
     "amp_hexop_create", "amp_hexop_destroy", "amp_hexop_info", "amp_hexop_apply", "amp_hexop_diagonal",
+    "amp_matrix_from_hexop",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -116,6 +117,7 @@ def load(build_if_missing: bool = True):
         L.amp_hexop_info.argtypes = [vp, ctypes.POINTER(HexStats)]
         L.amp_hexop_apply.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.amp_hexop_diagonal.argtypes = [vp, vp, vp]
+        L.amp_matrix_from_hexop.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.amp_matrix_tuning_default.argtypes = [ctypes.POINTER(MatrixTuning)]
         L.amp_matrix_tuning_default.restype = None
         L.amp_tune_lanes.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32),

@@ -35,6 +35,7 @@ struct Cfg {
     int rr_period, extra16;   // extra16: log2 of the FP16 preconditioner data's static scale
     int defer_x;              // 1: x is updated every other iteration (two steps at once)
     int rr_switch;            // 1: r is replaced by fl32(b - A x) at the u_r switch
+    int zero_q;               // 1: the update clears q after reading it (matrix-free product; x every iteration)
     int g_stream, g_slice;    // work-groups of the streaming / sliced-ELL kernels (= partial counts)
     int g_pre;                // partials written by the preconditioning stage
     double C, tau_zs, tau_zh, tol, gain;

@@ -10,11 +10,11 @@
 // unknowns are the grid nodes off the boundary (homogeneous Dirichlet), in
 // grid order.  No index arrays: every map is arithmetic.
 //
-// One work-group per element, (N+1)^2 threads (N = 7: one wave), thread
-// (i, j) owning the grid line (i, j, 0..N) (k_hex_ax).  The element's p
-// values are gathered to LDS; the reference gradient, G (from the Jacobian
-// of the trilinear map at each point, formed in registers) and the
-// transposed derivative follow the line.  Results are summed into q (zeroed
+// One wave per element, lane (i, j) owning the grid line (i, j, 0..N)
+// (hex_wave_apply).  The element's p values are gathered to LDS; the
+// reference gradient, G (from the Jacobian of the trilinear map at each
+// point, formed in registers) and the transposed derivative follow the
+// line.  Results are summed into q (zeroed
 // first) by atomic adds: shared face, edge and corner nodes receive 2 to 8
 // contributions in an order that is not fixed, so q is exact to rounding but
 // not bitwise reproducible there.  mu comes from per-element partials p_e^T (A_e
@@ -133,73 +133,58 @@ __device__ __forceinline__ void hex_element(const HexView &h, int &ex, int &ey, 
     ez = e / (h.ex * h.ey);
 }
 
-// q += A_e p_e for this work-group's element; part[e] = p_e^T (A_e p_e).
-// One wave per element (N = 7: 64 threads), thread (i, j) owning the grid
-// line of nodes (i, j, 0..N): its p values, t-derivatives and t-fluxes stay
-// in registers, so only the r- and s-contractions read LDS (32 reads per
-// node instead of 96 for one thread per node).  The Jacobian's k-independent
-// parts are formed once per line: dx/dr and dx/ds are linear in t, dx/dt
-// does not depend on t.  The rows and columns of D for the thread's own i
-// and j are held in registers; those for the loop's k are wave-uniform.
-// Placement of D: 1, the thread's rows and columns in registers; 0, one LDS
-// copy per work-group (fewer registers, more resident waves).
-#ifndef AMP_HEX_DREG
-#define AMP_HEX_DREG 1
-#endif
-// 1: the r-fluxes of plane k overwrite p's plane k once the wave has read it
-// (one wave per element, so in order), saving a third of the LDS.
-#ifndef AMP_HEX_ALIAS
-#define AMP_HEX_ALIAS 0
-#endif
-template <int N, int UP, int UR>
-__global__ void __launch_bounds__((N + 1) * (N + 1))
-    k_hex_ax(HexView h, const void *pv, void *qv, double *part) {
-    typedef typename Prec<UP>::T TP;
-    typedef typename Prec<UR>::T T;
+// LDS of one element application (one wave): p on the element's nodes and
+// the r- and s-fluxes.
+template <int N, typename T>
+struct HexLds {
+    static constexpr int NN = (N + 1) * (N + 1) * (N + 1);
+    T u[NN], fr[NN], fs[NN];
+};
+
+// A_e u_e for element (ex, ey, ez) by the calling wave: lane l < (N+1)^2
+// owns the grid line (i, j) = (l mod (N+1), l div (N+1)) of nodes
+// (i, j, 0..N); its values, t-derivatives and t-fluxes stay in registers,
+// so only the r- and s-contractions read LDS (32 reads per node).  The
+// Jacobian's k-independent parts are formed once per line: dx/dr and dx/ds
+// are linear in t, dx/dt does not depend on t.  D's rows and columns for the
+// lane's own i and j are held in registers; those for the loop's k are
+// wave-uniform.
+//   fetch(k, dof) -> T   the line's value at node k (called for dof >= 0;
+//                        boundary nodes hold 0)
+//   emit(k, dof, a, u)   the line's result a = (A_e u_e) at node k and its
+//                        value u (called for dof >= 0)
+// Every thread of the work-group calls this the same number of times
+// (active = false where a wave has no element this time; (ex, ey, ez) must
+// still name a valid element): it contains two work-group barriers.
+template <int N, typename T, typename Fetch, typename Emit>
+__device__ __forceinline__ void hex_wave_apply(const HexView &h, bool active, int ex, int ey, int ez,
+                                               HexLds<N, T> &L, Fetch fetch, Emit emit) {
     constexpr int N1 = N + 1, NP = N1 * N1;
     static_assert(NP <= WAVE, "one wave per element");
-    __shared__ T s_u[N1 * NP], s_fs[N1 * NP];
-    __shared__ T s_fr_own[AMP_HEX_ALIAS ? 1 : N1 * NP];
-    __shared__ T s_D[N1 * N1];
-    __shared__ double s_mu[NP];
-    T *const s_fr = AMP_HEX_ALIAS ? s_u : s_fr_own;
-    const TP *p = (const TP *)pv;
-    T *q = (T *)qv;
-    const int tid = threadIdx.x;
-    const int i = tid % N1, j = tid / N1;
-    int ex, ey, ez;
-    hex_element(h, ex, ey, ez);
+    const int lane = threadIdx.x % WAVE;
+    const bool line = active && lane < NP;
+    const int i = lane % N1, j = (lane / N1) % N1;
     const double *xg = h.tab, *wg = h.tab + N1, *Dg = h.tab + 2 * N1;
-    // this line's p and unknown indices
     T u[N1];
     int64_t dof[N1];
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-        dof[k] = hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k);
-        u[k] = (dof[k] >= 0) ? (T)p[dof[k]] : (T)0;
-        s_u[k * NP + tid] = u[k];
+        dof[k] = line ? hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k) : -1;
+        u[k] = (dof[k] >= 0) ? fetch(k, dof[k]) : (T)0;
+        if (line) L.u[k * NP + lane] = u[k];
     }
     T Di[N1], Dj[N1], DTi[N1], DTj[N1];
-    if constexpr (AMP_HEX_DREG) {
 #pragma unroll
-        for (int m = 0; m < N1; ++m) {
-            Di[m] = (T)Dg[i * N1 + m];
-            Dj[m] = (T)Dg[j * N1 + m];
-            DTi[m] = (T)Dg[m * N1 + i];
-            DTj[m] = (T)Dg[m * N1 + j];
-        }
-    } else {
-        for (int e = tid; e < N1 * N1; e += NP) s_D[e] = (T)Dg[e];
+    for (int m = 0; m < N1; ++m) {
+        Di[m] = (T)Dg[i * N1 + m];
+        Dj[m] = (T)Dg[j * N1 + m];
+        DTi[m] = (T)Dg[m * N1 + i];
+        DTj[m] = (T)Dg[m * N1 + j];
     }
-    // D[a][b] for the thread's own row/column indices
-    auto dd = [&](const T *reg, int a, int b, int m) -> T {
-        if constexpr (AMP_HEX_DREG) return reg[m];
-        else return s_D[a * N1 + b];
-    };
     // Jacobian pieces of the line (i, j): dx_d/dr = Pr0[d] ht0 + Pr1[d] ht1,
     // dx_d/ds = Ps0[d] ht0 + Ps1[d] ht1, dx_d/dt = Jt[d]
     double X[2][2][2][3];
-    hex_corners(h, ex, ey, ez, X);
+    hex_corners(h, ex, ey, ez, X);   // (ex, ey, ez) is a valid element also when !active
     const T r = (T)xg[i], s = (T)xg[j];
     const T hr[2] = {(T)0.5 * ((T)1 - r), (T)0.5 * ((T)1 + r)};
     const T hs[2] = {(T)0.5 * ((T)1 - s), (T)0.5 * ((T)1 + s)};
@@ -229,8 +214,8 @@ __global__ void __launch_bounds__((N + 1) * (N + 1))
         T ur = 0, us = 0, ut = 0;
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            ur = hex_fma(dd(Di, i, m, m), s_u[k * NP + j * N1 + m], ur);
-            us = hex_fma(dd(Dj, j, m, m), s_u[k * NP + m * N1 + i], us);
+            ur = hex_fma(Di[m], L.u[k * NP + j * N1 + m], ur);
+            us = hex_fma(Dj[m], L.u[k * NP + m * N1 + i], us);
             ut = hex_fma((T)Dg[k * N1 + m], u[m], ut);
         }
         const T t = (T)xg[k];
@@ -260,32 +245,62 @@ __global__ void __launch_bounds__((N + 1) * (N + 1))
         const T g0 = hex_fma(C[0][0], ur, hex_fma(C[0][1], us, C[0][2] * ut));
         const T g1 = hex_fma(C[1][0], ur, hex_fma(C[1][1], us, C[1][2] * ut));
         const T g2 = hex_fma(C[2][0], ur, hex_fma(C[2][1], us, C[2][2] * ut));
-        s_fr[k * NP + tid] = f * hex_fma(C[0][0], g0, hex_fma(C[1][0], g1, C[2][0] * g2));
-        s_fs[k * NP + tid] = f * hex_fma(C[0][1], g0, hex_fma(C[1][1], g1, C[2][1] * g2));
+        if (line) {
+            L.fr[k * NP + lane] = f * hex_fma(C[0][0], g0, hex_fma(C[1][0], g1, C[2][0] * g2));
+            L.fs[k * NP + lane] = f * hex_fma(C[0][1], g0, hex_fma(C[1][1], g1, C[2][1] * g2));
+        }
         ft[k] = f * hex_fma(C[0][2], g0, hex_fma(C[1][2], g1, C[2][2] * g2));
         au[k] = w * det * (T)h.lam * u[k];
     }
     __syncthreads();
-    double mu = 0.0;
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
         T a = au[k];
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            a = hex_fma(dd(DTi, m, i, m), s_fr[k * NP + j * N1 + m], a);
-            a = hex_fma(dd(DTj, m, j, m), s_fs[k * NP + m * N1 + i], a);
+            a = hex_fma(DTi[m], L.fr[k * NP + j * N1 + m], a);
+            a = hex_fma(DTj[m], L.fs[k * NP + m * N1 + i], a);
             a = hex_fma((T)Dg[m * N1 + k], ft[m], a);
         }
-        // (every node by atomic add: a plain store for the nodes inside the
-        // element, whose only contributor this element is, was measured 2.3x
-        // slower -- the divergent branch around the atomic)
-        if (dof[k] >= 0) unsafeAtomicAdd(q + dof[k], a);
-        mu += (double)u[k] * (double)a;
+        if (dof[k] >= 0) emit(k, dof[k], a, u[k]);
     }
-    // per-element partial, summed over the lines in thread order
-    s_mu[tid] = mu;
+}
+
+// Whether local node (i, j, k) of element (ex, ey, ez) is the one copy of
+// its grid node that writes per-node results: the element with the lowest
+// index along each direction that contains it.
+template <int N>
+__device__ __forceinline__ bool hex_owner(const HexView &h, int ex, int ey, int ez, int i, int j, int k) {
+    return (i < N || ex == h.ex - 1) && (j < N || ey == h.ey - 1) && (k < N || ez == h.ez - 1);
+}
+
+// q += A_e p_e for this work-group's element; part[e] = p_e^T (A_e p_e).
+// One wave per work-group and element.  Shared nodes are summed into q by
+// atomic adds in no fixed order (a plain store for the nodes inside the
+// element, whose only contributor it is, measured 2.3x slower: the divergent
+// branch around the atomic).
+template <int N, int UP, int UR>
+__global__ void __launch_bounds__((N + 1) * (N + 1))
+    k_hex_ax(HexView h, const void *pv, void *qv, double *part) {
+    typedef typename Prec<UP>::T TP;
+    typedef typename Prec<UR>::T T;
+    constexpr int NP = (N + 1) * (N + 1);
+    __shared__ HexLds<N, T> L;
+    __shared__ double s_mu[NP];
+    const TP *p = (const TP *)pv;
+    T *q = (T *)qv;
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    double mu = 0.0;
+    hex_wave_apply<N, T>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return (T)p[dof]; },
+                         [&](int, int64_t dof, T a, T u) {
+                             unsafeAtomicAdd(q + dof, a);
+                             mu += (double)u * (double)a;
+                         });
+    // per-element partial, summed over the lines in lane order
+    s_mu[threadIdx.x] = mu;
     __syncthreads();
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         double t = 0.0;
         for (int l = 0; l < NP; ++l) t += s_mu[l];
         part[(int64_t)ez * h.ex * h.ey + (int64_t)ey * h.ex + ex] = t;

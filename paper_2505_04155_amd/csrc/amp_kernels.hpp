@@ -938,7 +938,8 @@ __global__ void __launch_bounds__(NTS) k_spmv_fixed(Sell A, const void *z, const
 //   1: x += alpha_k p_k
 //   2: x += alpha_{k-1} p_{k-1}, then x += alpha_k p_k (p_{k-1} in u_z as p_k)
 // Each step is rounded as on its own, so x is bitwise the same in all modes.
-template <int UP, int UR, int XM>
+// ZQ: clear q after reading it (the matrix-free product sums into q).
+template <int UP, int UR, int XM, bool ZQ = false>
 __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t np, St &s, const PartRegs<2> &pr,
                                            int gpart, St *out, Wg wg) {
     typedef typename Prec<UP>::T TP;
@@ -1017,6 +1018,12 @@ __device__ __forceinline__ void update_run(const Cfg &c, const Bufs &B, int64_t 
         }
         if (XM >= 1) st4(B.x, i, xv);
         st4(r, i, rv);
+        if (ZQ) {
+            V4<TR> zero;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) zero.v[e] = (TR)0;
+            st4((TR *)q, i, zero);
+        }
     };
     if (i0 < hi) chunk(i0, p0, pq0, x0, r0, q0);
     if (PF == 2 && i0 + step < hi) chunk(i0 + step, p1, pq1, x1, r1, q1);
@@ -1095,11 +1102,12 @@ __device__ __forceinline__ void update_stage(const Cfg &c, const Bufs &B, int64_
     } else {
         xm = s.xp ? 2 : (c.defer_x ? 0 : 1);
     }
-#define AMP_UPD(UP, UR)                                                            \
-    do {                                                                           \
-        if (xm == 0) update_run<UP, UR, 0>(c, B, np, s, pr, e.g, out, wg);         \
-        else if (xm == 1) update_run<UP, UR, 1>(c, B, np, s, pr, e.g, out, wg);    \
-        else update_run<UP, UR, 2>(c, B, np, s, pr, e.g, out, wg);                 \
+#define AMP_UPD(UP, UR)                                                                    \
+    do {                                                                                   \
+        if (c.zero_q) update_run<UP, UR, 1, true>(c, B, np, s, pr, e.g, out, wg);          \
+        else if (xm == 0) update_run<UP, UR, 0>(c, B, np, s, pr, e.g, out, wg);            \
+        else if (xm == 1) update_run<UP, UR, 1>(c, B, np, s, pr, e.g, out, wg);            \
+        else update_run<UP, UR, 2>(c, B, np, s, pr, e.g, out, wg);                         \
     } while (0)
     if (ur == 64) {
         if (uz == 64) AMP_UPD(64, 64);

@@ -17,7 +17,7 @@
 #include "amp_batch.hpp"
 #include "amp_cheb.hpp"
 #include "amp_fv.hpp"
-#include "amp_hex.hpp"
+#include "amp_hexsolve.hpp"
 #include "amp_kernels.hpp"
 #include "amp_pcg.h"
 
@@ -175,7 +175,19 @@ struct Work {
 };
 
 
+struct amp_hexop_s {
+    int ex = 0, ey = 0, ez = 0, order = 0;
+    double lam = 0.0;
+    int64_t n = 0;
+    double *verts = nullptr, *tab = nullptr, *part = nullptr;
+};
+
+static HexView hex_view(amp_hexop H) {
+    return HexView{H->ex, H->ey, H->ez, H->n, H->verts, H->tab, H->lam};
+}
+
 struct amp_matrix_s {
+    amp_hexop hex = nullptr;   // matrix-free operator this handle wraps (not owned), else null
     int64_t n = 0, np = 0, nnz = 0, nslices = 0, slots = 0, bytes = 0, offset_slices = 0, meta_bytes = 0;
     int64_t guard = 0;   // largest |column offset| of an offset-mode slice, rounded up to 64
     int lgL = 0;         // log2 of the lanes per row
@@ -977,6 +989,7 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         if (degree < 1 || degree > kChebMax) return fail(AMP_ERR_ARG, "amp_precond_create: degree must be in 1..16");
         if (A->lgL > 0)
             return fail(AMP_ERR_ARG, "amp_precond_create: the Chebyshev preconditioner needs one lane per row");
+        if (A->hex) return fail(AMP_ERR_ARG, "amp_precond_create: the Chebyshev preconditioner needs a stored matrix");
         if (!std::isfinite(lam_lo) || !std::isfinite(lam_hi))
             return fail(AMP_ERR_ARG, "amp_precond_create: bounds must be finite");
         if (lam_lo > 0.0 && lam_hi > 0.0 && !(lam_hi > lam_lo))
@@ -1109,6 +1122,12 @@ static amp_status check_options(const amp_options &o) {
     return AMP_OK;
 }
 
+// Work-groups of the matrix-free kernels: enough for one element per wave, at most GMAX.
+static int hex_grid(amp_hexop H) {
+    const int64_t elements = (int64_t)H->ex * H->ey * H->ez;
+    return fit_grid((elements + kHexWaves - 1) / kHexWaves);
+}
+
 static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double tol, int maxit) {
     Cfg c;
     std::memset(&c, 0, sizeof(c));
@@ -1134,6 +1153,16 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
         // one work-group count for every kernel: G = ceil(np / group_rows)
         const int64_t g = (A->np + o.group_rows - 1) / o.group_rows;
         c.g_stream = c.g_slice = (int)std::max<int64_t>(1, std::min<int64_t>(GMAX, g));
+    }
+    if (A && A->hex) {
+        // the matrix-free product: its own grid (each work-group takes
+        // elements in turn), q cleared by the update, x updated every
+        // iteration; no replacement at the switch (it needs A x inside the
+        // preconditioning kernel)
+        c.g_slice = hex_grid(A->hex);
+        c.zero_q = 1;
+        c.defer_x = 0;
+        c.rr_switch = 0;
     }
     c.g_pre = (M && M->kind == AMP_PC_CHEBYSHEV && M->degree > 1) ? c.g_slice : c.g_stream;
     c.C = o.C;
@@ -1195,11 +1224,31 @@ static int fixed_uz(const amp_options &o) {
 
 // r0 = b - A x0, and the FP64 true residual (mode as k_true_res), for the
 // matrix's lanes per row.
+// (a matrix-free handle: t = A x into the cleared FP64 q, then the residual
+// from t; both q precisions are cleared at the start of a solve)
 static void launch_init(Driver &d) {
+    if (d.A->hex) {
+        const int64_t np = d.A->np;
+        const unsigned gz = (unsigned)std::min<int64_t>(2048, (np + 255) / 256);
+        k_hex_zero<double><<<gz, 256, 0, d.st>>>((double *)d.B.q[0], np);
+        k_hex_zero<float><<<gz, 256, 0, d.st>>>((float *)d.B.q[1], np);
+        const HexView hv = hex_view(d.A->hex);
+        if (d.A->hex->order == 7) k_hex_xapply<7><<<d.gl, NTH, 0, d.st>>>(hv, d.B, -1, nullptr);
+        else k_hex_xapply<3><<<d.gl, NTH, 0, d.st>>>(hv, d.B, -1, nullptr);
+        k_hex_init_finish<<<d.gl, NT, 0, d.st>>>(d.B, np);
+        return;
+    }
     if (d.S.lgL > 0) k_init<true><<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
     else k_init<false><<<d.gl, NTS, 0, d.st>>>(d.S, d.B);
 }
 static void launch_true_res(Driver &d, int mode, const St *in, St *out) {
+    if (d.A->hex) {
+        const HexView hv = hex_view(d.A->hex);
+        if (d.A->hex->order == 7) k_hex_xapply<7><<<d.gl, NTH, 0, d.st>>>(hv, d.B, mode, in);
+        else k_hex_xapply<3><<<d.gl, NTH, 0, d.st>>>(hv, d.B, mode, in);
+        k_hex_true_res_finish<<<d.gl, NT, 0, d.st>>>(d.cfg, d.B, d.A->np, mode, in, out);
+        return;
+    }
     if (d.S.lgL > 0) k_true_res<true><<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, mode, in, out);
     else k_true_res<false><<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, mode, in, out);
 }
@@ -1245,7 +1294,23 @@ static amp_status enqueue_iterations(Driver &d, int count) {
             k_precond<<<d.gs, NT, 0, d.st>>>(d.in, d.B.part_res, std::max(d.cfg.g_stream, d.cfg.g_slice), d.gs,
                                              d.cfg.ring, d.cfg, d.B, d.A->np, &d.sb[ST_PRE], d.S);
         }
-        if (d.timing && d.launches < w.tcap) {
+        if (d.A->hex) {
+            const HexView hv = hex_view(d.A->hex);
+            const HexSpmvFn fn = hex_spmv_fn(d.A->hex->order, d.uzf);
+            if (d.timing && d.launches < w.tcap) {
+                d.cfg.spmv_iter = w.titer;
+                d.cfg.spmv_launch = d.launches;
+                hipExtLaunchKernelGGL(fn, dim3(d.gl), dim3(NTH), 0, d.st, w.tev[2 * d.launches],
+                                      w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
+                                      (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, hv, d.B,
+                                      &d.sb[ST_SPMV]);
+                d.launches += 1;
+                d.cfg.spmv_iter = nullptr;
+            } else {
+                hipLaunchKernelGGL(fn, dim3(d.gl), dim3(NTH), 0, d.st, (const St *)&d.sb[ST_PRE],
+                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, hv, d.B, &d.sb[ST_SPMV]);
+            }
+        } else if (d.timing && d.launches < w.tcap) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
@@ -1356,7 +1421,7 @@ static amp_status snapshot(Driver &d, int slot) {
 // identity, no periodic replacement).
 static bool solo_eligible(const amp_options &o, amp_matrix A, amp_precond M) {
     return o.solo_rows > 0 && A->np <= o.solo_rows && o.rr_period == 0 && M->kind != AMP_PC_CHEBYSHEV &&
-           A->lgL == 0;
+           A->lgL == 0 && !A->hex;
 }
 
 // Upper bound on the single-work-group loop's passes: maxit iterations plus
@@ -1375,12 +1440,15 @@ extern "C" amp_status amp_pcg_solve(amp_matrix A, amp_precond M, const double *b
     if (opt) o = *opt;
     else amp_options_default(&o);
     AMP_TRY(check_options(o));
+    if (A->hex && (M->kind == AMP_PC_CHEBYSHEV || o.rr_period > 0 || o.graph || o.group_rows > 0))
+        return fail(AMP_ERR_ARG, "amp_pcg_solve: a matrix-free handle takes the Jacobi or identity preconditioner, "
+                                 "without periodic replacement, graph replay or group_rows");
     Driver d;
     d.A = A;
     d.M = M;
     d.st = as_stream(stream);
     AMP_TRY(ensure_work(A, d.st));
-    if (!o.spmv32_diff && o.eta_mode != AMP_UR_FIXED64) AMP_TRY(ensure_plain_plane(A, d.st));
+    if (!A->hex && !o.spmv32_diff && o.eta_mode != AMP_UR_FIXED64) AMP_TRY(ensure_plain_plane(A, d.st));
     Work &w = A->w;
     d.sb = w.st;
     const bool timing = o.spmv_timing != 0;
@@ -1656,6 +1724,7 @@ __global__ void __launch_bounds__(NT) k_zero16(uint4 *p, int64_t words) {
 
 extern "C" amp_status amp_pcg_solve_noalloc(amp_matrix A, amp_precond M, const double *b, double *x, double tol,
                                             int maxit, const amp_options *opt, amp_result *res, void *stream) {
+    if (A && A->hex) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: not for a matrix-free handle");
     auto t0 = std::chrono::steady_clock::now();
     if (!A || !b || !x) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: null argument");
     if (!M) return fail(AMP_ERR_ARG, "amp_pcg_solve_noalloc: null preconditioner");
@@ -1882,6 +1951,7 @@ extern "C" amp_status amp_pcg_solve_batched(int nsys, const amp_matrix *A, const
                                          " was built for another matrix");
         if (M[i]->kind == AMP_PC_CHEBYSHEV)
             return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: Chebyshev preconditioners are not supported");
+        if (A[i]->hex) return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: a matrix-free handle cannot be batched");
         if (A[i]->lgL > 0)
             return fail(AMP_ERR_ARG, "amp_pcg_solve_batched: system " + std::to_string(i) +
                                          " has several lanes per row (one is needed)");
@@ -2226,6 +2296,7 @@ extern "C" amp_status amp_tune_lanes(const amp_csr *csr, const int *candidates, 
 
 extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const void *p, void *q, double *gamma,
                                void *stream) {
+    if (A && A->hex) return fail(AMP_ERR_ARG, "amp_spmv: not for a matrix-free handle (amp_hexop_apply)");
     if (!A) return fail(AMP_ERR_ARG, "amp_spmv: null matrix");
     if ((u_r != 64 && u_r != 32) || !valid_prec(u_p)) return fail(AMP_ERR_ARG, "amp_spmv: bad precision");
     hipStream_t st = as_stream(stream);
@@ -2248,6 +2319,7 @@ extern "C" amp_status amp_spmv(amp_matrix A, int u_r, int u_p, int diff, const v
 }
 
 extern "C" amp_status amp_spmv_step(amp_matrix A, int u_z, int u_r, int diff, double beta, void *stream) {
+    if (A && A->hex) return fail(AMP_ERR_ARG, "amp_spmv_step: not for a matrix-free handle");
     if (!A) return fail(AMP_ERR_ARG, "amp_spmv_step: null matrix");
     if ((u_r != 64 && u_r != 32) || !valid_prec(u_z)) return fail(AMP_ERR_ARG, "amp_spmv_step: bad precision");
     hipStream_t st = as_stream(stream);
@@ -2383,6 +2455,7 @@ extern "C" amp_status amp_fv_grad_theta(int dim, int nx, int ny, int nz, const f
 }
 
 extern "C" amp_status amp_matrix_update_values(amp_matrix A, const amp_csr *csr, void *stream) {
+    if (A && A->hex) return fail(AMP_ERR_ARG, "amp_matrix_update_values: not for a matrix-free handle");
     if (!A || !csr || !csr->row_ptr || !csr->col_idx || !csr->val)
         return fail(AMP_ERR_ARG, "amp_matrix_update_values: null argument");
     if (csr->n != A->n || csr->nnz != A->nnz)
@@ -2518,13 +2591,6 @@ extern "C" const char *amp_last_error(void) { return g_last_error.c_str(); }
 // matrix-free hexahedral operator
 // ----------------------------------------------------------------------------
 
-struct amp_hexop_s {
-    int ex = 0, ey = 0, ez = 0, order = 0;
-    double lam = 0.0;
-    int64_t n = 0;
-    double *verts = nullptr, *tab = nullptr, *part = nullptr;
-};
-
 // GLL nodes of order N (the end points and the roots of P_N', by Newton's
 // method from the Chebyshev-Lobatto points, P_N'' from Legendre's equation
 // (1 - x^2) P'' = 2 x P' - N (N + 1) P), weights 2 / (N (N + 1) P_N(x)^2)
@@ -2581,10 +2647,6 @@ static void gll_tables(int N, std::vector<double> &tab) {
         }
         tab[2 * n1 + m * n1 + m] = diag;
     }
-}
-
-static HexView hex_view(amp_hexop H) {
-    return HexView{H->ex, H->ey, H->ez, H->n, H->verts, H->tab, H->lam};
 }
 
 // err |= 1 where w det(J) <= 0 (or is not finite) at a quadrature point.
@@ -2699,6 +2761,42 @@ extern "C" amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void 
     else launch_hex_ax<3>(v, elements, u_p, u_r, p, q, H->part, st);
     if (mu) k_hex_sum<<<1, kHexSumThreads, 0, st>>>(H->part, elements, mu);
     AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}
+
+// Padding rows of a matrix-free handle's diagonal: 1.
+__global__ void k_hex_pad_diag(double *diag, int64_t n, int64_t np) {
+    const int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) diag[i] = 1.0;
+}
+
+extern "C" amp_status amp_matrix_from_hexop(amp_hexop H, void *stream, amp_matrix *out) {
+    if (!out) return fail(AMP_ERR_ARG, "amp_matrix_from_hexop: out is NULL");
+    *out = nullptr;
+    if (!H) return fail(AMP_ERR_ARG, "amp_matrix_from_hexop: null operator");
+    hipStream_t st = as_stream(stream);
+    amp_matrix A = new amp_matrix_s();
+    A->hex = H;
+    A->n = H->n;
+    A->np = round_up(H->n, PAD);
+    A->nnz = 0;
+    amp_status s = dalloc(&A->diag, A->np);
+    if (s == AMP_OK) s = amp_hexop_diagonal(H, A->diag, stream);
+    if (s == AMP_OK) {
+        if (A->np > A->n) k_hex_pad_diag<<<(unsigned)((A->np - A->n + 255) / 256), 256, 0, st>>>(A->diag, A->n, A->np);
+        const hipError_t e = hipGetLastError();
+        if (e == hipSuccess) {
+            if (hipStreamSynchronize(st) != hipSuccess) s = fail(AMP_ERR_HIP, "amp_matrix_from_hexop: synchronisation");
+        } else {
+            s = fail(AMP_ERR_HIP, std::string("amp_matrix_from_hexop: ") + hipGetErrorString(e));
+        }
+    }
+    if (s != AMP_OK) {
+        amp_matrix_destroy(A);
+        return s;
+    }
+    A->bytes = A->np * 8;
+    *out = A;
     return AMP_OK;
 }
 

@@ -59,6 +59,19 @@ class Matrix:
         self.nnz = col_idx.numel()
 
     @classmethod
+    def from_hexop(cls, H):
+        """A handle over a HexOperator (matrix-free; Jacobi or identity
+        preconditioner).  Keeps H alive."""
+        m = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        B.check(B.load().amp_matrix_from_hexop(H._h, _stream(), ctypes.byref(h)), "amp_matrix_from_hexop")
+        m._h = h
+        m.n = H.n
+        m.nnz = 0
+        m._hexop = H
+        return m
+
+    @classmethod
     def from_csr(cls, csr, device="cuda", offsets: bool = True, lanes: int = 1):
         """From a workloads.CSR (host numpy arrays)."""
         rp = torch.from_numpy(csr.row_ptr).to(device)

@@ -139,3 +139,38 @@ def test_refused_arguments(amp):
     H = amp.HexOperator(Vt, E, order=3)
     with pytest.raises(B.AmpError, match="u_r"):
         H.apply(torch.zeros(H.n, dtype=torch.float64, device="cuda"), u_r=32)
+
+
+@pytest.mark.parametrize("N,E", [(7, (4, 3, 3)), (3, (6, 5, 4))])
+@pytest.mark.parametrize("preset", ["pcg64", "amp64", "amp16"])
+def test_matrix_free_solve_parity(amp, N, E, preset):
+    from oracle import hexop
+    V, H = _op(amp, E, N, seed=3)
+    m = HexMesh(V, E, N=N, lam=1e3)
+    b = np.random.default_rng([85, N]).standard_normal(m.n)
+    xo, io = hexop.pcg(m, b, tol=1e-10, maxit=5000)
+    M = amp.Matrix.from_hexop(H)
+    pc = amp.Preconditioner(M, "jacobi")
+    x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=5000, preset=preset)
+    err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    _say(f"matrix-free solve N={N} E={E} {preset}: {info['iters']} iterations (oracle {io['iters']}), "
+         f"rel. error vs the oracle {err:.2e}, true rel. residual {info['relres_true']:.2e}")
+    assert info["status"] == 0
+    assert info["relres_true"] <= 1e-10
+    assert info["iters"] <= int(np.ceil(1.05 * io["iters"]))
+    assert err <= 1e-8
+
+
+def test_matrix_free_handle_refusals(amp):
+    from paper_2505_04155_amd import binding as B
+    V, H = _op(amp, (2, 2, 2), 3)
+    M = amp.Matrix.from_hexop(H)
+    with pytest.raises(B.AmpError, match="stored matrix"):
+        amp.Preconditioner(M, "chebyshev", degree=2, lam_lo=0.1, lam_hi=2.0)
+    pc = amp.Preconditioner(M, "jacobi")
+    b = torch.ones(H.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.AmpError, match="matrix-free"):
+        amp.solve(M, pc, b, tol=1e-10, maxit=100, preset="amp64", rr_period=5)
+    with pytest.raises(B.AmpError, match="matrix-free"):
+        M.spmv(b)
+

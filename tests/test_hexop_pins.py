@@ -179,3 +179,21 @@ def test_flop_count_formula():
     # 2(N+1) per gradient component both ways, 15 for G, 2 + 2 for the
     # mass term and the sum, 149 for the geometric factors
     assert m.flops_per_element() == (6 * 8 + 15 + 6 * 8 + 4 + 149) * 512
+
+
+def test_matrix_free_pcg_equals_assembled_pcg():
+    # Alg. 1 on the operator against the C oracle's PCG on the assembled
+    # matrix (the operator applied to unit vectors), Jacobi both ways
+    from oracle import cpcg, hexop
+    from workloads.problems import dense_to_csr
+    E = (2, 3, 2)
+    m = HexMesh(hex_vertices(E, 0.2, seed=5), E, N=3, lam=1e3)
+    A = np.column_stack([m.apply(e) for e in np.eye(m.n)])
+    b = np.random.default_rng(75).standard_normal(m.n)
+    x1, i1 = hexop.pcg(m, b, tol=1e-10, maxit=500)
+    x2, i2 = cpcg.pcg(dense_to_csr(A), b, tol=1e-10, maxit=500)
+    assert i1["iters"] == i2["iters"]
+    assert i1["relres_true"] <= 1e-10
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2)
+    assert np.allclose(A @ x1, b, atol=1e-9 * np.abs(b).max())
+
