@@ -304,7 +304,7 @@ FP64_VECTOR_PEAK = 78.6e12
 FP32_VECTOR_PEAK = 157.3e12
 
 
-def hex_measurement(amp, torch, np, P, dev, reps=20, E=(40, 40, 40), order=7):
+def hex_measurement(amp, torch, np, P, dev, reps=20, E=(40, 40, 40), order=7, solve=True):
     """The matrix-free order-7 hexahedral operator of Ex. jac libp on the
     paper's 40^3-element mesh (trilinear elements, vertices perturbed by
     0.2 h): each phase's storage/arithmetic pair timed over `reps` applies
@@ -341,6 +341,30 @@ def hex_measurement(amp, torch, np, P, dev, reps=20, E=(40, 40, 40), order=7):
             "paper_a100_us": PAPER_AX_US[name],
         }
         log(f"bench: hex Ax {name}: {us:.1f} us per apply, {flops / (us * 1e-6) / 1e12:.2f} TFLOP/s")
+    if solve:
+        # Jacobi-PCG on the operator (the paper's Ex. jac libp): FP64 PCG and
+        # AMP-PCG(FP16) with the delay and the linear u_r criterion
+        M = amp.Matrix.from_hexop(H)
+        pc = amp.Preconditioner(M, "jacobi")
+        b = torch.tensor(np.random.default_rng(86).standard_normal(H.n), device=dev)
+        runs = {}
+        for name, preset, kw in (("pcg64", "pcg64", {}), ("amp16", "amp16", {}),
+                                 ("amp16_linear", "amp16", {"eta": "linear"})):
+            amp.solve(M, pc, b, tol=1e-10, maxit=20000, preset=preset, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = amp.solve(M, pc, b, tol=1e-10, maxit=20000, preset=preset, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            ti = amp.solve(M, pc, b, tol=1e-10, maxit=20000, preset=preset, spmv_timing=1, **kw)[1]
+            runs[name] = {"ms": round(ms, 2), "iters": info["iters"], "k_r32": info["k_r32"],
+                          "rel_res_true": info["relres_true"],
+                          "product_us": round(ti["spmv_ms"] * 1e3 / max(1, ti["spmv_launches"]), 2)}
+            log(f"bench: matrix-free solve {name}: {ms:.1f} ms, {info['iters']} iterations, "
+                f"u_r FP32 from {info['k_r32']}")
+        runs["speedup_amp16_vs_fp64_pcg"] = round(runs["pcg64"]["ms"] / runs["amp16"]["ms"], 4)
+        runs["speedup_amp16_linear_vs_fp64_pcg"] = round(runs["pcg64"]["ms"] / runs["amp16_linear"]["ms"], 4)
+        out["solve"] = runs
     return out
 
 
