@@ -355,7 +355,17 @@ constexpr int kHexSumThreads = 1024;
 __global__ void __launch_bounds__(kHexSumThreads) k_hex_sum(const double *part, int64_t n, double *out) {
     __shared__ double sh[kHexSumThreads];
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < n; e += kHexSumThreads) s += part[e];
+    // eight loads in flight per thread, added in index order
+    constexpr int U = 8;
+    int64_t e = threadIdx.x;
+    for (; e + (U - 1) * kHexSumThreads < n; e += U * kHexSumThreads) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = part[e + u * kHexSumThreads];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; e < n; e += kHexSumThreads) s += part[e];
     sh[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
