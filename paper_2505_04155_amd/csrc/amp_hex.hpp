@@ -139,16 +139,15 @@ template <int N, typename T>
 struct HexLds {
     static constexpr int NN = (N + 1) * (N + 1) * (N + 1);
     T u[NN], fr[NN], fs[NN];
+    T D[(N + 1) * (N + 1)];   // D[m][j] = l_j'(x_m)
 };
 
 // A_e u_e for element (ex, ey, ez) by the calling wave: lane l < (N+1)^2
 // owns the grid line (i, j) = (l mod (N+1), l div (N+1)) of nodes
 // (i, j, 0..N); its values, t-derivatives and t-fluxes stay in registers,
-// so only the r- and s-contractions read LDS (32 reads per node).  The
-// Jacobian's k-independent parts are formed once per line: dx/dr and dx/ds
-// are linear in t, dx/dt does not depend on t.  D's rows and columns for the
-// lane's own i and j are held in registers; those for the loop's k are
-// wave-uniform.
+// so only the r- and s-contractions read LDS.  The Jacobian's
+// k-independent parts are formed once per line: dx/dr and dx/ds are linear
+// in t, dx/dt does not depend on t.
 //   fetch(k, dof) -> T   the line's value at node k (called for dof >= 0;
 //                        boundary nodes hold 0)
 //   emit(k, dof, a, u)   the line's result a = (A_e u_e) at node k and its
@@ -156,7 +155,10 @@ struct HexLds {
 // Every thread of the work-group calls this the same number of times
 // (active = false where a wave has no element this time; (ex, ey, ez) must
 // still name a valid element): it contains two work-group barriers.
-template <int N, typename T, typename Fetch, typename Emit>
+// DREG: D's rows and columns for the lane's own i and j in registers (64
+// of the FP64 kernel's VGPRs; faster where the kernel is not limited by
+// registers), else read from the work-group's LDS copy.
+template <int N, typename T, bool DREG, typename Fetch, typename Emit>
 __device__ __forceinline__ void hex_wave_apply(const HexView &h, bool active, int ex, int ey, int ez,
                                                HexLds<N, T> &L, Fetch fetch, Emit emit) {
     constexpr int N1 = N + 1, NP = N1 * N1;
@@ -166,21 +168,34 @@ __device__ __forceinline__ void hex_wave_apply(const HexView &h, bool active, in
     const int i = lane % N1, j = (lane / N1) % N1;
     const double *xg = h.tab, *wg = h.tab + N1, *Dg = h.tab + 2 * N1;
     T u[N1];
-    int64_t dof[N1];
+    int32_t dof[N1];   // unknowns number below 2^31
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-        dof[k] = line ? hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k) : -1;
-        u[k] = (dof[k] >= 0) ? fetch(k, dof[k]) : (T)0;
+        dof[k] = line ? (int32_t)hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k) : -1;
+        u[k] = (dof[k] >= 0) ? fetch(k, (int64_t)dof[k]) : (T)0;
         if (line) L.u[k * NP + lane] = u[k];
     }
+    // D for the loop's k is wave-uniform; for the lane's i and j see DREG
     T Di[N1], Dj[N1], DTi[N1], DTj[N1];
+    if constexpr (DREG) {
 #pragma unroll
-    for (int m = 0; m < N1; ++m) {
-        Di[m] = (T)Dg[i * N1 + m];
-        Dj[m] = (T)Dg[j * N1 + m];
-        DTi[m] = (T)Dg[m * N1 + i];
-        DTj[m] = (T)Dg[m * N1 + j];
+        for (int m = 0; m < N1; ++m) {
+            Di[m] = (T)Dg[i * N1 + m];
+            Dj[m] = (T)Dg[j * N1 + m];
+            DTi[m] = (T)Dg[m * N1 + i];
+            DTj[m] = (T)Dg[m * N1 + j];
+        }
+    } else {
+        for (int e = lane; e < N1 * N1; e += WAVE) L.D[e] = (T)Dg[e];
     }
+    auto d_row = [&](const T *reg, int a, int m) -> T {   // D[a][m]
+        if constexpr (DREG) return reg[m];
+        else return L.D[a * N1 + m];
+    };
+    auto d_col = [&](const T *reg, int a, int m) -> T {   // D[m][a]
+        if constexpr (DREG) return reg[m];
+        else return L.D[m * N1 + a];
+    };
     // Jacobian pieces of the line (i, j): dx_d/dr = Pr0[d] ht0 + Pr1[d] ht1,
     // dx_d/ds = Ps0[d] ht0 + Ps1[d] ht1, dx_d/dt = Jt[d]
     double X[2][2][2][3];
@@ -214,8 +229,8 @@ __device__ __forceinline__ void hex_wave_apply(const HexView &h, bool active, in
         T ur = 0, us = 0, ut = 0;
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            ur = hex_fma(Di[m], L.u[k * NP + j * N1 + m], ur);
-            us = hex_fma(Dj[m], L.u[k * NP + m * N1 + i], us);
+            ur = hex_fma(d_row(Di, i, m), L.u[k * NP + j * N1 + m], ur);
+            us = hex_fma(d_row(Dj, j, m), L.u[k * NP + m * N1 + i], us);
             ut = hex_fma((T)Dg[k * N1 + m], u[m], ut);
         }
         const T t = (T)xg[k];
@@ -258,11 +273,11 @@ __device__ __forceinline__ void hex_wave_apply(const HexView &h, bool active, in
         T a = au[k];
 #pragma unroll
         for (int m = 0; m < N1; ++m) {
-            a = hex_fma(DTi[m], L.fr[k * NP + j * N1 + m], a);
-            a = hex_fma(DTj[m], L.fs[k * NP + m * N1 + i], a);
+            a = hex_fma(d_col(DTi, i, m), L.fr[k * NP + j * N1 + m], a);
+            a = hex_fma(d_col(DTj, j, m), L.fs[k * NP + m * N1 + i], a);
             a = hex_fma((T)Dg[m * N1 + k], ft[m], a);
         }
-        if (dof[k] >= 0) emit(k, dof[k], a, u[k]);
+        if (dof[k] >= 0) emit(k, (int64_t)dof[k], a, u[k]);
     }
 }
 
@@ -292,7 +307,7 @@ __global__ void __launch_bounds__((N + 1) * (N + 1))
     int ex, ey, ez;
     hex_element(h, ex, ey, ez);
     double mu = 0.0;
-    hex_wave_apply<N, T>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return (T)p[dof]; },
+    hex_wave_apply<N, T, false>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return (T)p[dof]; },
                          [&](int, int64_t dof, T a, T u) {
                              unsafeAtomicAdd(q + dof, a);
                              mu += (double)u * (double)a;

@@ -64,7 +64,7 @@ __device__ __forceinline__ void hex_spmv_body(const HexView &h, Wg wg, const voi
     const int lane = threadIdx.x % WAVE;
     const int i = lane % (N + 1), j = (lane / (N + 1)) % (N + 1);
     hex_elements(h, wg, [&](bool active, int ex, int ey, int ez) {
-        hex_wave_apply<N, T>(
+        hex_wave_apply<N, T, true>(
             h, active, ex, ey, ez, L[wave],
             [&](int k, int64_t dof) -> T {
                 const TZ pv = FIRST ? z[dof] : (TZ)((CZ)z[dof] + beta * (CZ)po[dof]);
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(NTH) k_hex_xapply(HexView h, Bufs B, int mode,
     double *t = (double *)B.q[0];
     const int wave = threadIdx.x / WAVE;
     hex_elements(h, wg, [&](bool active, int ex, int ey, int ez) {
-        hex_wave_apply<N, double>(h, active, ex, ey, ez, L[wave], [&](int, int64_t dof) { return x[dof]; },
+        hex_wave_apply<N, double, true>(h, active, ex, ey, ez, L[wave], [&](int, int64_t dof) { return x[dof]; },
                                   [&](int, int64_t dof, double a, double) { unsafeAtomicAdd(t + dof, a); });
     });
 }

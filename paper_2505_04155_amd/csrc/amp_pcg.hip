@@ -1122,10 +1122,22 @@ static amp_status check_options(const amp_options &o) {
     return AMP_OK;
 }
 
-// Work-groups of the matrix-free kernels: enough for one element per wave, at most GMAX.
+// Work-groups of the matrix-free kernels: as many as are resident at once
+// (their LDS allows 3 per CU for order 7), so the element loop ends in one
+// wave of work-groups instead of leaving a partial second one; at most one
+// element per wave and at most GMAX.
 static int hex_grid(amp_hexop H) {
     const int64_t elements = (int64_t)H->ex * H->ey * H->ez;
-    return fit_grid((elements + kHexWaves - 1) / kHexWaves);
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    int64_t resident = GMAX;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        const hipError_t e = (H->order == 7)
+                                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_spmv<7, 0>, NTH, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_spmv<3, 0>, NTH, 0);
+        if (e == hipSuccess && per_cu > 0) resident = (int64_t)per_cu * prop.multiProcessorCount;
+    }
+    return fit_grid(std::min<int64_t>(resident, (elements + kHexWaves - 1) / kHexWaves));
 }
 
 static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double tol, int maxit) {
