@@ -70,19 +70,25 @@ def step_bytes(n, nnz, meta_bytes, u_z, u_r):
 
 def cheb_iteration_bytes(n, nnz, meta_bytes, u_z, u_r, degree=4):
     """The degree - 1 polynomial-step launches of one preconditioner
-    application in (u_z, u_r): each reads B's FP16 values and the column
-    metadata once; the work vectors are held in c = 8 bytes (u_z = FP64) or
-    4 (otherwise).  First step: reads v, writes w, res, dir (4c); inner
-    steps: read dir, w, res, write w, res, dir (6c); last step: reads dir,
-    w, res, D^{-1/2} (4c) and r (u_r), writes z (u_z)."""
+    application in (u_z, u_r), iterate form: each reads B's FP16 values and
+    the column metadata once; the work vectors are held in c = 8 bytes
+    (u_z = FP64) or 4 (otherwise).  Step 0 gathers v and writes x_2 (2c);
+    step 1 gathers x_2, reads v and writes x_3 (3c); later inner steps also
+    read x_{k-1} (4c); the last step reads its gathered x_k, v, x_{k-1}
+    (none on step 0, v's on step 1), D^{-1/2} and r (u_r) and writes z
+    (u_z)."""
     c = 8 if u_z == 64 else 4
     m = degree - 1
     if m < 1:
         return 0
-    if m == 1:   # one step, first and last: reads v and D^{-1/2}, r; writes z
-        vec = 2 * c + u_r // 8 + u_z // 8
+    tail = c + u_r // 8 + u_z // 8          # D^{-1/2}, r and z of the last step
+    if m == 1:     # one step, first and last: gathers v
+        vec = c + tail
     else:
-        vec = 4 * c + (m - 2) * 6 * c + 4 * c + u_r // 8 + u_z // 8
+        vec = 2 * c                          # step 0
+        for k in range(1, m - 1):
+            vec += 3 * c if k == 1 else 4 * c
+        vec += (2 * c if m - 1 == 1 else 3 * c) + tail
     return m * (2 * nnz + meta_bytes) + n * vec
 
 

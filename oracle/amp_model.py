@@ -275,18 +275,20 @@ class Chebyshev:
         return 1.0 / theta, cs
 
     def _steps(self, v, Bmul, c):
+        """The Chebyshev iteration for B w = v from w = 0, written on the
+        iterates: x_0 = 0, x_1 = v / theta, and for k = 1 .. m-1
+        x_{k+1} = x_k + c1_{k-1} (x_k - x_{k-1}) + c2_{k-1} (v - B x_k);
+        w = x_m.  (With d_k = x_{k+1} - x_k and res_k = v - B x_k this is the
+        direction form d_k = c1 d_{k-1} + c2 res_k: the same polynomial.)"""
         inv_theta, cs = self.coefficients()
-        res = v
-        dirn = v * c(inv_theta)
-        w = np.zeros_like(dirn)
-        for k in range(self.m):
-            w = w + dirn
-            if k == self.m - 1:
-                break
-            c1, c2 = cs[k]
-            res = res - Bmul(dirn)
-            dirn = c(c1) * dirn + c(c2) * res
-        return w
+        x_prev = np.zeros_like(v)
+        x = v * c(inv_theta)
+        for k in range(1, self.m):
+            c1, c2 = cs[k - 1]
+            res = v - Bmul(x)
+            x_new = (x + c(c1) * (x - x_prev)) + c(c2) * res
+            x_prev, x = x, x_new
+        return x
 
     def apply(self, y_uz, uz):
         cu = compute_type(uz)

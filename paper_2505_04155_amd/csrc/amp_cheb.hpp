@@ -2,17 +2,20 @@
 // B = D^{-1/2} A D^{-1/2} stored in FP16 on A's sliced-ELL pattern, s the
 // degree-(m-1) polynomial whose residual polynomial 1 - t s(t) is the scaled
 // Chebyshev polynomial T_m((theta - t)/delta) / T_m(theta/delta) on
-// [lam_lo, lam_hi], evaluated by the three-term Chebyshev iteration for
-// B w = v from w = 0:
-//   res_0 = v, dir_0 = v / theta, w_0 = 0;  for k = 0..m-2:
-//   w_{k+1} = w_k + dir_k,  res_{k+1} = res_k - B dir_k,
-//   dir_{k+1} = c1_k dir_k + c2_k res_{k+1};   w_m = w_{m-1} + dir_{m-1}.
-// Work vectors are held in the arithmetic precision of u_z (FP64, or FP32
-// for u_z = FP32 / FP16); B products accumulate in that precision; z is
-// rounded to u_z.  One streaming kernel forms v, then m-1 product kernels
-// each take one step; the last one also forms z and the partials of rho.
+// [lam_lo, lam_hi], evaluated by the Chebyshev iteration for B w = v from
+// w = 0 written on its iterates (with d_k = x_{k+1} - x_k and
+// res_k = v - B x_k it is the direction form d_k = c1 d_{k-1} + c2 res_k):
+//   x_0 = 0, x_1 = v / theta;  for k = 1..m-1:
+//   x_{k+1} = x_k + c1_{k-1} (x_k - x_{k-1}) + c2_{k-1} (v - B x_k);  w = x_m.
+// A step reads the gathered x_k, v and x_{k-1} of its row and writes
+// x_{k+1} over x_{k-1}: 16 bytes per row in FP32 where the direction form
+// moves 24 (x_1 is v / theta, so the first two steps read less).  Work
+// vectors are held in the arithmetic precision of u_z (FP64, or FP32 for
+// u_z = FP32 / FP16); B products accumulate in that precision; z is rounded
+// to u_z.  One streaming kernel forms v, then m-1 product kernels each take
+// one step; the last one also forms z and the partials of rho.
 //
-// The gathered vectors (v, dir) of each precision are separate allocations
+// The gathered vectors (v and the two iterate buffers) of each precision are separate allocations
 // with a zero margin of `guard` elements before and after (guard >= the
 // largest |column offset| of any offset-mode slice).  An offset-mode slot
 // then reads its neighbour at row + offset without a range test: a slot
@@ -53,9 +56,9 @@ struct Cheb {
     const half_t *b16;       // B's values in FP16
     const double *isq64;     // D^{-1/2}
     const float *isq32;
-    // work vectors by precision (0: FP64, 1: FP32), np entries each; v and
-    // dir carry the zero margins described above
-    void *v[2], *res[2], *w[2];
+    // work vectors by precision (0: FP64, 1: FP32), np entries each, with
+    // the zero margins described above: v, and the two iterate buffers
+    void *v[2];
     void *dir[2][2];
     int64_t np, nslices;
     int64_t guard;           // zero margin of v and dir, in elements
@@ -159,13 +162,15 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
     typedef typename Prec<UZ>::C CZ;
     constexpr int cp = (UZ == 64) ? 0 : 1;
     const CZ *v = (const CZ *)P.v[cp];
-    CZ *res = (CZ *)P.res[cp];
-    CZ *w = (CZ *)P.w[cp];
-    // (selects, not indexing: an argument array indexed at run time would be
-    // copied to private memory)
-    const CZ *dk = (const CZ *)(din ? P.dir[cp][1] : P.dir[cp][0]);
-    CZ *dn = (CZ *)(din ? P.dir[cp][0] : P.dir[cp][1]);
-    const CZ *g = FIRST ? v : dk;   // the gathered vector
+    // step kk (0-based) of the iterate form: x_{kk+1} is gathered (kk = 0:
+    // v / theta); x_{kk} is read and x_{kk+2} written in the other buffer.
+    // din bit 0: kk odd (x_{kk+1} in dir[0]); bit 1: kk = 1 (x_{kk} = x_1 =
+    // v / theta, formed from v).  (Selects, not indexing: an argument array
+    // indexed at run time would be copied to private memory.)
+    const bool odd = (din & 1) != 0, prev_from_v = (din & 2) != 0;
+    const CZ *xk_buf = (const CZ *)(odd ? P.dir[cp][0] : P.dir[cp][1]);
+    CZ *xw = (CZ *)(odd ? P.dir[cp][1] : P.dir[cp][0]);
+    const CZ *g = FIRST ? v : xk_buf;   // the gathered vector
     const CZ inv_theta = (CZ)P.inv_theta;
     const CZ c1 = (CZ)c1d, c2 = (CZ)c2d;
     const CZ *isq = (UZ == 64) ? (const CZ *)P.isq64 : (const CZ *)P.isq32;
@@ -195,9 +200,13 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
         // the row's own operands are loaded before the product, so their
         // latency overlaps it
         const uint32_t ru = (uint32_t)row;   // row < np <= 2^29: 32-bit byte offsets
-        const CZ d0 = dfrom(at32(g, ru));
-        const CZ wk = FIRST ? (CZ)0 + d0 : at32((const CZ *)w, ru);
-        const CZ rk = FIRST ? at32(v, ru) : at32((const CZ *)res, ru);
+        const CZ gi = at32(g, ru);
+        const CZ xk = dfrom(gi);                           // x_k of the row
+        const CZ vi = FIRST ? gi : at32(v, ru);
+        CZ xkm1;                                           // x_{k-1} of the row
+        if (FIRST) xkm1 = (CZ)0;
+        else if (prev_from_v) xkm1 = vi * inv_theta;
+        else xkm1 = at32((const CZ *)xw, ru);
         CZ isq_r = (CZ)0;
         double rr = 0.0;
         if (last) {
@@ -278,16 +287,12 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
                 }
             }
         }
-        const CZ w1 = FIRST ? wk : wk + d0;
-        const CZ r1 = rk - acc;
-        const CZ d1 = c1 * d0 + c2 * r1;
+        const CZ r1 = vi - acc;
+        const CZ xn = (xk + c1 * (xk - xkm1)) + c2 * r1;   // x_{k+1}
         if (!last) {
-            st32(w, ru, w1);
-            st32(res, ru, r1);
-            st32(dn, ru, d1);
+            st32(xw, ru, xn);
         } else {
-            const CZ wm = w1 + d1;
-            const TZ zz = (TZ)(isq_r * wm);
+            const TZ zz = (TZ)(isq_r * xn);
             st32(z, ru, zz);
             rho += rr * (double)zz;
             mz = fmax(mz, fabs((double)zz));

@@ -226,10 +226,10 @@ struct amp_precond_s {
     double *isq64 = nullptr;
     float *isq32 = nullptr;
     // work vectors: one zeroed block per precision, laid out
-    // [G][v][G][dir0][G][dir1][G][res][w] (G = the matrix's guard)
+    // [G][v][G][x_a][G][x_b][G] (G = the matrix's guard)
     double *cblk64 = nullptr;
     float *cblk32 = nullptr;
-    void *cv[2] = {nullptr, nullptr}, *cres[2] = {nullptr, nullptr}, *cw[2] = {nullptr, nullptr};
+    void *cv[2] = {nullptr, nullptr};
     void *cdir[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
     int est_hi = 0, est_lo = 0;       // bounds estimated by the Lanczos process (lam <= 0 given)
@@ -240,7 +240,7 @@ struct amp_precond_s {
         P.koffs = reinterpret_cast<KOffs>(reinterpret_cast<uintptr_t>(A->offs));
         P.b16 = b16; P.isq64 = isq64; P.isq32 = isq32;
         for (int i = 0; i < 2; ++i) {
-            P.v[i] = cv[i]; P.res[i] = cres[i]; P.w[i] = cw[i]; P.dir[i][0] = cdir[i][0]; P.dir[i][1] = cdir[i][1];
+            P.v[i] = cv[i]; P.dir[i][0] = cdir[i][0]; P.dir[i][1] = cdir[i][1];
         }
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
         P.step_iter = nullptr; P.step_launch = 0; P.guard = A->guard;
@@ -1011,7 +1011,7 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         if ((s = dalloc(&M->b16, A->slots)) != AMP_OK || (s = dalloc(&M->isq64, np)) != AMP_OK ||
             (s = dalloc(&M->isq32, np)) != AMP_OK)
             return bail(s);
-        const int64_t G = A->guard, blk = 4 * G + 5 * np;
+        const int64_t G = A->guard, blk = 4 * G + 3 * np;   // [G][v][G][x_a][G][x_b][G]
         if ((s = dalloc(&M->cblk64, blk)) != AMP_OK || (s = dalloc(&M->cblk32, blk)) != AMP_OK) return bail(s);
         if (hipMemsetAsync(M->cblk64, 0, blk * sizeof(double), st) != hipSuccess ||
             hipMemsetAsync(M->cblk32, 0, blk * sizeof(float), st) != hipSuccess)
@@ -1019,13 +1019,9 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
         M->cv[0] = M->cblk64 + G;
         M->cdir[0][0] = M->cblk64 + 2 * G + np;
         M->cdir[0][1] = M->cblk64 + 3 * G + 2 * np;
-        M->cres[0] = M->cblk64 + 4 * G + 3 * np;
-        M->cw[0] = M->cblk64 + 4 * G + 4 * np;
         M->cv[1] = M->cblk32 + G;
         M->cdir[1][0] = M->cblk32 + 2 * G + np;
         M->cdir[1][1] = M->cblk32 + 3 * G + 2 * np;
-        M->cres[1] = M->cblk32 + 4 * G + 3 * np;
-        M->cw[1] = M->cblk32 + 4 * G + 4 * np;
     } else {
         if ((s = dalloc(&M->d64, np)) != AMP_OK || (s = dalloc(&M->d32, np)) != AMP_OK ||
             (s = dalloc(&M->d16, np)) != AMP_OK)
@@ -1265,6 +1261,10 @@ static void launch_true_res(Driver &d, int mode, const St *in, St *out) {
     else k_true_res<false><<<d.gl, NTS, 0, d.st>>>(d.cfg, d.S, d.B, mode, in, out);
 }
 
+// The buffer selector of Chebyshev step k (see cheb_step_body): bit 0 k
+// odd, bit 1 k = 1.
+static int cheb_din(int k) { return (k % 2) | (k == 1 ? 2 : 0); }
+
 // One Chebyshev application: v, then degree-1 steps; `in` -> `out`.
 static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     St *sb = d.sb;
@@ -1287,11 +1287,11 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
             Pt.step_launch = d.claunches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
             hipExtLaunchKernelGGL(fn, dim3(d.gl), dim3(NTC), 0, d.st, w.cev[2 * d.claunches],
-                                  w.cev[2 * d.claunches + 1], 0, d.B, Pt, P.c1[k], P.c2[k], k % 2,
+                                  w.cev[2 * d.claunches + 1], 0, d.B, Pt, P.c1[k], P.c2[k], cheb_din(k),
                                   (const St *)si, so);
             d.claunches += 1;
         } else {
-            hipLaunchKernelGGL(fn, dim3(d.gl), dim3(NTC), 0, d.st, d.B, P, P.c1[k], P.c2[k], k % 2, (const St *)si,
+            hipLaunchKernelGGL(fn, dim3(d.gl), dim3(NTC), 0, d.st, d.B, P, P.c1[k], P.c2[k], cheb_din(k), (const St *)si,
                                so);
         }
     }

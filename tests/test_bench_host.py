@@ -39,14 +39,20 @@ def test_step_bytes_by_hand():
 def test_cheb_bytes_by_hand():
     # 256^3 Q1 workload, degree 4: three step launches per application
     n, nnz, meta = 16777216, 449455096, 2062568
-    # FP16 z (FP32 work vectors): B values 2 B per nonzero in each of the three
-    # launches; vectors: first 4 x 4 B, inner 6 x 4 B, last 4 x 4 B + r (4) + z (2)
-    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 32) == 3 * (2 * nnz + meta) + n * (16 + 24 + 16 + 4 + 2)
-    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 64) == 3 * (2 * nnz + meta) + n * (16 + 24 + 16 + 8 + 2)
+    # FP16 z (FP32 work vectors), iterate form: B values 2 B per nonzero in
+    # each of the three launches; vectors: step 0 gathers v and writes x_2
+    # (2 x 4 B), step 1 gathers x_2, reads v, writes x_3 (3 x 4 B), the last
+    # step gathers x_3, reads v, x_2 and D^-1/2 (4 x 4 B), r (4 or 8) and
+    # writes z (2)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 32) == 3 * (2 * nnz + meta) + n * (8 + 12 + 16 + 4 + 2)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 64) == 3 * (2 * nnz + meta) + n * (8 + 12 + 16 + 8 + 2)
     # FP64 z: FP64 work vectors
-    assert bench.cheb_iteration_bytes(n, nnz, meta, 64, 64) == 3 * (2 * nnz + meta) + n * (32 + 48 + 32 + 8 + 8)
-    # degree 2: one step that is first and last
-    assert bench.cheb_iteration_bytes(n, nnz, meta, 32, 32, degree=2) == 2 * nnz + meta + n * (8 + 4 + 4)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 64, 64) == 3 * (2 * nnz + meta) + n * (16 + 24 + 32 + 8 + 8)
+    # degree 2: one step that is first and last (gathers v, reads D^-1/2, r; writes z)
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 32, 32, degree=2) == 2 * nnz + meta + n * (4 + 4 + 4 + 4)
+    # degree 5: a second inner step reads x_{k-1} as well
+    assert bench.cheb_iteration_bytes(n, nnz, meta, 16, 32, degree=5) == \
+        4 * (2 * nnz + meta) + n * (8 + 12 + 16 + 16 + 4 + 2)
 
 
 def test_stored_traffic_requires_matching_sources(monkeypatch, tmp_path):
