@@ -460,11 +460,11 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
         }
         for (int j = 0; j < len; ++j) rs += val[beg + j];
     }
-    // empty slots first
+    // empty slots first (col is null when every slice is in offset mode)
     for (int j = 0; j < w; ++j) {
         for (int t = 0; t < L; ++t) {
             const int64_t slot = b + (int64_t)j * SLICE + t;
-            col[slot] = (int32_t)row;
+            if (col) col[slot] = (int32_t)row;
             v64[slot] = 0.0;
             v32[slot] = 0.0f;
         }
@@ -485,7 +485,7 @@ __global__ void k_fill(const int32_t *rp, const int32_t *ci, const double *val, 
             }
         }
         const int64_t slot = b + (int64_t)(js >> lgL) * SLICE + (js & (L - 1));
-        col[slot] = c;
+        if (col) col[slot] = c;
         v64[slot] = v;
         if (c == row) {
             has_diag = true;
@@ -621,23 +621,24 @@ static amp_status create_matrix(const amp_csr *csr, int lgL, bool offsets, void 
         A->guard = round_up(mo, 64);
     }
     A->slots = hp[ns];
-    {
-        int64_t index_slots = 0;
-        for (int64_t i = 0; i < ns; ++i)
-            if (hso[i] < 0) index_slots += hp[i + 1] - hp[i];
-        A->meta_bytes = 4 * index_slots + 4 * noffs + 12 * ns + 8;
-    }
+    int64_t index_slots = 0;   // slots of index-mode slices (padding slices past n have none)
+    for (int64_t i = 0; i < ns; ++i)
+        if (hso[i] < 0) index_slots += hp[i + 1] - hp[i];
+    A->meta_bytes = 4 * index_slots + 4 * noffs + 12 * ns + 8;
     if (A->slots >= ((int64_t)1 << 31) * 2) return bail(fail(AMP_ERR_ARG, "amp_matrix_create: too many slots"));
     std::vector<SliceRec> hrec(ns);
     for (int64_t i = 0; i < ns; ++i) hrec[i] = SliceRec{hp[i], hso[i], (int32_t)((hp[i + 1] - hp[i]) / SLICE)};
     if ((s = dalloc(&A->srec, ns)) != AMP_OK || (s = dalloc(&A->sptr, ns + 1)) != AMP_OK ||
         (s = dalloc(&A->soff, ns)) != AMP_OK ||
         (s = dalloc(&A->offs, round_up(std::max<int64_t>(noffs, 1), kChunk))) != AMP_OK ||
-        (s = dalloc(&A->col, A->slots)) != AMP_OK || (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
+        // the int32 column plane only where some slice is in index mode (no
+        // kernel reads it for an offset-mode slice)
+        (index_slots > 0 && (s = dalloc(&A->col, A->slots)) != AMP_OK) ||
+        (s = dalloc(&A->v64, A->slots)) != AMP_OK ||
         (s = dalloc(&A->v32, A->slots)) != AMP_OK ||
         (s = dalloc(&A->diag, A->np)) != AMP_OK)
         return bail(s);
-    A->bytes = ns * 16 + (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * (4 + 8 + 4) + A->np * 8;
+    A->bytes = ns * 16 + (ns + 1) * 8 + ns * 4 + noffs * 4 + A->slots * ((A->col ? 4 : 0) + 8 + 4) + A->np * 8;
     if (hipMemcpyAsync(A->srec, hrec.data(), hrec.size() * sizeof(SliceRec), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->sptr, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(A->soff, hso.data(), hso.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||

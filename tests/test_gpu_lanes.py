@@ -135,3 +135,27 @@ def test_one_lane_paths_refuse_lanes(amp, int_matrix):
     b = torch.ones(int_matrix.n, dtype=torch.float64, device="cuda")
     with pytest.raises(B.AmpError, match="lanes per row"):
         amp.solve_batched([M1, M], pcs, [b, b.clone()], tol=TOL, maxit=100, preset="amp64")
+
+
+def test_offset_mode_handle_holds_no_column_plane(amp):
+    # every slice of a stencil matrix is in offset mode: the handle keeps no
+    # per-slot column index (FP64 + FP32 values only)
+    A, b, _, (lo, hi) = P.q1_system(20)
+    M = amp.Matrix.from_csr(A)
+    i = M.info()
+    # (slices of padding rows past n hold no slots, whatever their mode)
+    assert i["offset_slices"] == -(-A.n // 64)
+    ns, slots = i["nslices"], i["slots"]
+    np_ = -(-A.n // 1024) * 1024
+    assert i["bytes"] == i["meta_bytes"] + 16 * ns + 12 * slots + 8 * np_
+    # and it still solves, with the Chebyshev preconditioner too
+    pc = amp.Preconditioner(M, "chebyshev", degree=4, lam_lo=lo, lam_hi=hi)
+    x, info = amp.solve(M, pc, torch.tensor(b, device="cuda"), tol=1e-10, maxit=2000, preset="amp16")
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10
+    # an index-mode handle of the same matrix holds the columns (counted in
+    # its metadata bytes, 4 per slot)
+    Mi = amp.Matrix.from_csr(A, offsets=False)
+    ii = Mi.info()
+    assert ii["offset_slices"] == 0
+    assert ii["meta_bytes"] >= 4 * ii["slots"]
+    assert ii["bytes"] == ii["meta_bytes"] + 16 * ii["nslices"] + 12 * ii["slots"] + 8 * np_
