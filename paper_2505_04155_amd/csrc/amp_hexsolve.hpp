@@ -36,70 +36,38 @@ __device__ __forceinline__ void hex_elements(const HexView &h, Wg wg, F f) {
     }
 }
 
-// LDS of the matrix-free kernels: one HexLds per wave, sized for FP64 (one
-// array per kernel, shared by every precision's body).
+// the same for one wave (sized for FP64, used for either precision)
 template <int N>
-struct HexLdsBlock {
-    HexLds<N, double> w[kHexWaves];
+struct HexLdsBlock1 {
+    HexLds<N, double> w[1];
 };
 
-// p = z + beta p_old (u_z) at every gathered node (the owner copy stores
-// it), q += A_e p_e (u_r arithmetic, atomic adds), gamma = sum_e p_e^T A_e
-// p_e and max|p| partials.  Sums per lane run in element and node order.
-
-template <int N, int UZ, int UR, bool FIRST>
-__device__ __forceinline__ void hex_spmv_body(const HexView &h, Wg wg, const void *zv, const void *pov, void *pnv,
-                                              void *qv, double beta_d, double &gam, double &mp,
-                                              HexLdsBlock<N> &lds) {
-    typedef typename Prec<UZ>::T TZ;
-    typedef typename Prec<UZ>::C CZ;
-    typedef typename Prec<UR>::T T;
-    HexLds<N, T> *L = reinterpret_cast<HexLds<N, T> *>(&lds.w[0]);   // FP32: packed in the FP64 block
-    const TZ *z = (const TZ *)zv;
-    const TZ *po = (const TZ *)pov;
-    TZ *pn = (TZ *)pnv;
-    T *q = (T *)qv;
-    const CZ beta = (CZ)beta_d;
-    const int wave = threadIdx.x / WAVE;
-    const int lane = threadIdx.x % WAVE;
-    const int i = lane % (N + 1), j = (lane / (N + 1)) % (N + 1);
-    hex_elements(h, wg, [&](bool active, int ex, int ey, int ez) {
-        hex_wave_apply<N, T, true>(
-            h, active, ex, ey, ez, L[wave],
-            [&](int k, int64_t dof) -> T {
-                const TZ pv = FIRST ? z[dof] : (TZ)((CZ)z[dof] + beta * (CZ)po[dof]);
-                if (hex_owner<N>(h, ex, ey, ez, i, j, k)) {
-                    pn[dof] = pv;
-                    mp = fmax(mp, fabs((double)pv));
-                }
-                return (T)pv;
-            },
-            [&](int, int64_t dof, T a, T u) {
-                unsafeAtomicAdd(q + dof, a);
-                gam += (double)u * (double)a;
-            });
-    });
-}
-
-// The product stage of an iteration (as spmv_stage: beta from the rho
-// partials, breakdown checks, then the body and the gamma partials).
-template <int N, int UZF>
-__global__ void __launch_bounds__(NTH)
-    k_hex_spmv(const St *in, const double *part, int gpart, int grid, Cfg c, HexView h, Bufs B, St *out) {
+// The product of an iteration in three launches, so that the element
+// kernel runs one wave per element (the shape of the standalone operator;
+// a grid of at most GMAX multi-wave work-groups holds 256 VGPRs per lane):
+//   k_hex_beta    one work-group: beta from the rho partials, the checks of
+//                 spmv_stage, the state for the product;
+//   k_hex_elem    one wave per element: p = z + beta p_old at every gathered
+//                 node (the owner copy stores it), q += A_e p_e (atomic adds),
+//                 per-element gamma_e = p_e^T A_e p_e and max|p| of the owned
+//                 nodes;
+//   k_hex_reduce  G work-groups: each sums a contiguous range of the element
+//                 partials in element order (the update reads G partials).
+__global__ void __launch_bounds__(NT) k_hex_beta(const St *in, const double *part, int gpart, Cfg c, int uzf,
+                                                 St *out) {
     __shared__ St s;
-    __shared__ HexLdsBlock<N> lds;
-    const Wg wg = launch_wg(grid);
-    PartRegs<2, NTH> pr;
-    load_parts<2, NTH>(part, gpart, pr);
+    const Wg wg{0, 1};
+    PartRegs<2, NT> pr;
+    load_parts<2, NT>(part, gpart, pr);
     load_state(s, in);
     if (s.status != RUNNING) {
         store_state(s, out, wg);
         return;
     }
     const double rho_prev = s.rho;
-    const int k = s.k, uz = s.uz, ur = s.ur, ps = pslot(uz), pb = s.pbuf;
+    const int k = s.k;
     double tot[2];
-    reduce_loaded<1, 1, NTH>(pr, gpart, tot);
+    reduce_loaded<1, 1, NT>(pr, gpart, tot);
     const double rho = tot[0], mz = tot[1];
     const double beta = (k > 0) ? rho / rho_prev : 0.0;
     const bool brk = !(rho > 0.0) || !isfinite(beta);
@@ -109,65 +77,128 @@ __global__ void __launch_bounds__(NTH)
         s.beta = beta;
         s.maxz = mz;
         if (brk) s.status = BREAKDOWN;
-        if (wg.lb == 0 && c.scalar_history) c.scalar_history[4 * k + 1] = rho;
-    }
-    if (brk) {
-        store_state(s, out, wg);
-        return;
-    }
-    if (c.spmv_iter && wg.lb == 0 && threadIdx.x == 0) c.spmv_iter[c.spmv_launch] = k;
-    if (UZF != 0 && uz != UZF) {
-        if (threadIdx.x == 0) s.status = BREAKDOWN;
-        store_state(s, out, wg);
-        return;
-    }
-    const bool first = (k == 0);
-    double gam = 0.0, mp = 0.0;
-#define AMP_HS(UZ, UR)                                                                                      \
-    do {                                                                                                    \
-        if (first)                                                                                          \
-            hex_spmv_body<N, UZ, UR, true>(h, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, \
-                                           gam, mp, lds);                                                   \
-        else                                                                                                \
-            hex_spmv_body<N, UZ, UR, false>(h, wg, B.z[ps], B.p[ps][pb], B.p[ps][pb ^ 1], B.q[pslot(UR)],    \
-                                            beta, gam, mp, lds);                                            \
-    } while (0)
-#define AMP_HS_R(UZ)                 \
-    do {                             \
-        if (ur == 64) AMP_HS(UZ, 64); \
-        else AMP_HS(UZ, 32);          \
-    } while (0)
-    if constexpr (UZF == 64) AMP_HS_R(64);
-    else if constexpr (UZF == 32) AMP_HS_R(32);
-    else if constexpr (UZF == 16) AMP_HS_R(16);
-    else {
-        if (uz == 64) AMP_HS_R(64);
-        else if (uz == 32) AMP_HS_R(32);
-        else AMP_HS_R(16);
-    }
-#undef AMP_HS_R
-#undef AMP_HS
-    double v2[2] = {gam, mp};
-    block_reduce<1, 1, NTH>(v2);
-    if (threadIdx.x == 0) {
-        B.part_spmv[wg.lb] = v2[0];
-        B.part_spmv[GMAX + wg.lb] = v2[1];
+        if (c.scalar_history) c.scalar_history[4 * k + 1] = rho;
+        if (!brk && c.spmv_iter) c.spmv_iter[c.spmv_launch] = k;
+        if (!brk && uzf != 0 && s.uz != uzf) s.status = BREAKDOWN;   // only from a non-finite residual
     }
     store_state(s, out, wg);
 }
 
-typedef void (*HexSpmvFn)(const St *, const double *, int, int, Cfg, HexView, Bufs, St *);
+template <int N, int UZ, int UR, bool FIRST>
+__device__ __forceinline__ void hex_elem_body(const HexView &h, int ex, int ey, int ez, const Bufs &B, int pb,
+                                              double beta_d, HexLdsBlock1<N> &lds, double &gam, double &mp) {
+    typedef typename Prec<UZ>::T TZ;
+    typedef typename Prec<UZ>::C CZ;
+    typedef typename Prec<UR>::T T;
+    constexpr int ps = pslot(UZ);
+    HexLds<N, T> &L = *reinterpret_cast<HexLds<N, T> *>(&lds.w[0]);
+    const TZ *z = (const TZ *)B.z[ps];
+    const TZ *po = (const TZ *)B.p[ps][pb];
+    TZ *pn = (TZ *)B.p[ps][pb ^ 1];
+    T *q = (T *)B.q[pslot(UR)];
+    const CZ beta = (CZ)beta_d;
+    const int lane = threadIdx.x % WAVE;
+    const int i = lane % (N + 1), j = (lane / (N + 1)) % (N + 1);
+    hex_wave_apply<N, T, false>(
+        h, true, ex, ey, ez, L,
+        [&](int k, int64_t dof) -> T {
+            const TZ pv = FIRST ? z[dof] : (TZ)((CZ)z[dof] + beta * (CZ)po[dof]);
+            if (hex_owner<N>(h, ex, ey, ez, i, j, k)) {
+                pn[dof] = pv;
+                mp = fmax(mp, fabs((double)pv));
+            }
+            return (T)pv;
+        },
+        [&](int, int64_t dof, T a, T u) {
+            unsafeAtomicAdd(q + dof, a);
+            gam += (double)u * (double)a;
+        });
+}
 
-template <int N>
-inline HexSpmvFn hex_spmv_fn_n(int uzf) {
-    switch (uzf) {
-        case 16: return k_hex_spmv<N, 16>;
-        case 32: return k_hex_spmv<N, 32>;
-        case 64: return k_hex_spmv<N, 64>;
-        default: return k_hex_spmv<N, 0>;
+template <int N, int UZF>
+__global__ void __launch_bounds__((N + 1) * (N + 1)) k_hex_elem(HexView h, Bufs B, const St *st, double *epart) {
+    constexpr int NP = (N + 1) * (N + 1);
+    __shared__ St s;
+    __shared__ HexLdsBlock1<N> lds;
+    __shared__ double s_g[NP], s_m[NP];
+    load_state(s, st);
+    if (s.status != RUNNING) return;
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    const int uz = (UZF != 0) ? UZF : s.uz, ur = s.ur, pb = s.pbuf;
+    const bool first = s.k == 0;
+    const double beta = s.beta;
+    double gam = 0.0, mp = 0.0;
+#define AMP_HE(UZ, UR)                                                                          \
+    do {                                                                                        \
+        if (first) hex_elem_body<N, UZ, UR, true>(h, ex, ey, ez, B, pb, beta, lds, gam, mp);    \
+        else hex_elem_body<N, UZ, UR, false>(h, ex, ey, ez, B, pb, beta, lds, gam, mp);         \
+    } while (0)
+#define AMP_HE_R(UZ)                 \
+    do {                             \
+        if (ur == 64) AMP_HE(UZ, 64); \
+        else AMP_HE(UZ, 32);          \
+    } while (0)
+    if constexpr (UZF == 64) AMP_HE_R(64);
+    else if constexpr (UZF == 32) AMP_HE_R(32);
+    else if constexpr (UZF == 16) AMP_HE_R(16);
+    else {
+        if (uz == 64) AMP_HE_R(64);
+        else if (uz == 32) AMP_HE_R(32);
+        else AMP_HE_R(16);
+    }
+#undef AMP_HE_R
+#undef AMP_HE
+    // the element's partials, summed over its lines in lane order
+    s_g[threadIdx.x] = gam;
+    s_m[threadIdx.x] = mp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double g = 0.0, m = 0.0;
+        for (int l = 0; l < NP; ++l) {
+            g += s_g[l];
+            m = fmax(m, s_m[l]);
+        }
+        const int64_t E = (int64_t)h.ex * h.ey * h.ez, e = ((int64_t)ez * h.ey + ey) * h.ex + ex;
+        epart[e] = g;
+        epart[E + e] = m;
     }
 }
-inline HexSpmvFn hex_spmv_fn(int order, int uzf) { return order == 7 ? hex_spmv_fn_n<7>(uzf) : hex_spmv_fn_n<3>(uzf); }
+
+typedef void (*HexElemFn)(HexView, Bufs, const St *, double *);
+template <int N>
+inline HexElemFn hex_elem_fn_n(int uzf) {
+    switch (uzf) {
+        case 16: return k_hex_elem<N, 16>;
+        case 32: return k_hex_elem<N, 32>;
+        case 64: return k_hex_elem<N, 64>;
+        default: return k_hex_elem<N, 0>;
+    }
+}
+inline HexElemFn hex_elem_fn(int order, int uzf) { return order == 7 ? hex_elem_fn_n<7>(uzf) : hex_elem_fn_n<3>(uzf); }
+
+// Work-group lb of G sums the element partials of its contiguous range in
+// element order (thread t takes every NT-th element of the range, then the
+// fixed reduction tree): part[lb] = sum gamma_e, part[GMAX + lb] = max.
+__global__ void __launch_bounds__(NT) k_hex_reduce(const double *epart, int64_t E, const St *st, double *part) {
+    __shared__ St s;
+    load_state(s, st);
+    if (s.status != RUNNING) return;
+    const Wg wg = grid_wg();
+    int64_t lo, hi;
+    block_range(E, 1, wg.lb, wg.G, lo, hi);
+    double g = 0.0, m = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += NT) {
+        g += epart[e];
+        m = fmax(m, epart[E + e]);
+    }
+    double v2[2] = {g, m};
+    block_reduce<1, 1>(v2);
+    if (threadIdx.x == 0) {
+        part[wg.lb] = v2[0];
+        part[GMAX + wg.lb] = v2[1];
+    }
+}
 
 // Whether an FP64 residual kernel runs for this state (mode as k_true_res;
 // -1: r0 at the start of the solve, always).

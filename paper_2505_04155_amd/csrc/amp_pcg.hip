@@ -180,6 +180,7 @@ struct amp_hexop_s {
     double lam = 0.0;
     int64_t n = 0;
     double *verts = nullptr, *tab = nullptr, *part = nullptr;
+    double *epart = nullptr;   // per-element gamma and max|p| of the solve's product (2 x elements)
 };
 
 static HexView hex_view(amp_hexop H) {
@@ -1119,22 +1120,12 @@ static amp_status check_options(const amp_options &o) {
     return AMP_OK;
 }
 
-// Work-groups of the matrix-free kernels: as many as are resident at once
-// (their LDS allows 3 per CU for order 7), so the element loop ends in one
-// wave of work-groups instead of leaving a partial second one; at most one
-// element per wave and at most GMAX.
+// Work-groups of the matrix-free solve's streaming kernels (partial sums of
+// the product, r0 and the true residual): enough for 4 elements each, at most
+// GMAX.
 static int hex_grid(amp_hexop H) {
     const int64_t elements = (int64_t)H->ex * H->ey * H->ez;
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    int64_t resident = GMAX;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-        const hipError_t e = (H->order == 7)
-                                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_spmv<7, 0>, NTH, 0)
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_spmv<3, 0>, NTH, 0);
-        if (e == hipSuccess && per_cu > 0) resident = (int64_t)per_cu * prop.multiProcessorCount;
-    }
-    return fit_grid(std::min<int64_t>(resident, (elements + kHexWaves - 1) / kHexWaves));
+    return fit_grid((elements + kHexWaves - 1) / kHexWaves);
 }
 
 static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double tol, int maxit) {
@@ -1308,21 +1299,29 @@ static amp_status enqueue_iterations(Driver &d, int count) {
                                              d.cfg.ring, d.cfg, d.B, d.A->np, &d.sb[ST_PRE], d.S);
         }
         if (d.A->hex) {
-            const HexView hv = hex_view(d.A->hex);
-            const HexSpmvFn fn = hex_spmv_fn(d.A->hex->order, d.uzf);
-            if (d.timing && d.launches < w.tcap) {
-                d.cfg.spmv_iter = w.titer;
-                d.cfg.spmv_launch = d.launches;
-                hipExtLaunchKernelGGL(fn, dim3(d.gl), dim3(NTH), 0, d.st, w.tev[2 * d.launches],
-                                      w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
-                                      (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, hv, d.B,
-                                      &d.sb[ST_SPMV]);
-                d.launches += 1;
-                d.cfg.spmv_iter = nullptr;
-            } else {
-                hipLaunchKernelGGL(fn, dim3(d.gl), dim3(NTH), 0, d.st, (const St *)&d.sb[ST_PRE],
-                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, hv, d.B, &d.sb[ST_SPMV]);
+            // beta (one work-group), the element kernel (one wave per
+            // element; the timed launch), the partials' reduction (G groups)
+            amp_hexop H = d.A->hex;
+            const HexView hv = hex_view(H);
+            const int64_t E = (int64_t)H->ex * H->ey * H->ez;
+            const unsigned nt = (unsigned)((H->order + 1) * (H->order + 1));
+            const bool timed = d.timing && d.launches < w.tcap;
+            Cfg cb = d.cfg;
+            if (timed) {
+                cb.spmv_iter = w.titer;
+                cb.spmv_launch = d.launches;
             }
+            k_hex_beta<<<1, NT, 0, d.st>>>(&d.sb[ST_PRE], d.B.part_pre, d.cfg.g_pre, cb, d.uzf, &d.sb[ST_SPMV]);
+            const HexElemFn fe = hex_elem_fn(H->order, d.uzf);
+            if (timed) {
+                hipExtLaunchKernelGGL(fe, dim3((unsigned)E), dim3(nt), 0, d.st, w.tev[2 * d.launches],
+                                      w.tev[2 * d.launches + 1], 0, hv, d.B, (const St *)&d.sb[ST_SPMV], H->epart);
+                d.launches += 1;
+            } else {
+                hipLaunchKernelGGL(fe, dim3((unsigned)E), dim3(nt), 0, d.st, hv, d.B, (const St *)&d.sb[ST_SPMV],
+                                   H->epart);
+            }
+            k_hex_reduce<<<d.gl, NT, 0, d.st>>>(H->epart, E, &d.sb[ST_SPMV], d.B.part_spmv);
         } else if (d.timing && d.launches < w.tcap) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
@@ -2701,7 +2700,8 @@ extern "C" amp_status amp_hexop_create(int ex, int ey, int ez, int order, const 
     amp_status s;
     int *err = nullptr;
     if ((s = dalloc(&H->verts, nv)) != AMP_OK || (s = dalloc(&H->tab, tab.size())) != AMP_OK ||
-        (s = dalloc(&H->part, elements)) != AMP_OK || (s = dalloc(&err, 1)) != AMP_OK) {
+        (s = dalloc(&H->part, elements)) != AMP_OK || (s = dalloc(&H->epart, 2 * elements)) != AMP_OK ||
+        (s = dalloc(&err, 1)) != AMP_OK) {
         dfree(err);
         return bail(s);
     }
@@ -2729,6 +2729,7 @@ extern "C" void amp_hexop_destroy(amp_hexop H) {
     dfree(H->verts);
     dfree(H->tab);
     dfree(H->part);
+    dfree(H->epart);
     delete H;
 }
 
