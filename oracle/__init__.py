@@ -14,6 +14,8 @@ the GPU solver (``paper_2505_04155_amd``) and never imports it.
 * :mod:`oracle.eigbounds` -- Lanczos estimate of the Chebyshev interval.
 * :mod:`oracle.hexop`     -- the matrix-free order-N hexahedral screened
   Poisson operator (GLL points, trilinear element maps), its diagonal.
+* :mod:`oracle.pmg`       -- the p-multigrid V-cycle over polynomial orders
+  (Chebyshev-Jacobi smoothing, interpolation between orders) and PCG with it.
 """
 
 from . import cpcg  # noqa: F401
