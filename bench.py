@@ -374,6 +374,75 @@ def hex_measurement(amp, torch, np, P, dev, reps=20, E=(40, 40, 40), order=7, so
     return out
 
 
+def pmg_measurement(amp, torch, np, P, dev, E=(30, 30, 30), order=7, reps=10):
+    """The Poisson problem of Ex. linear conv2 (order 7 on 30^3 trilinear
+    hexahedra of [-0.5, 0.5]^3, interior vertices moved by 0.2 h in place of
+    the Kershaw mesh, homogeneous Dirichlet) with the p-multigrid V-cycle
+    (orders 7, 3, 1; degree-2 Chebyshev-Jacobi smoothing; a degree-8
+    Chebyshev-Jacobi polynomial on order 1 in place of algebraic multigrid):
+    FP64 PCG against AMP-PCG(FP16) with z and p in FP16 from the first
+    iteration (the linear and the delay u_r criteria), the cycle's cost in
+    FP64 and FP32, and Jacobi-PCG on the same system for reference."""
+    V = P.hex_vertices(E, 0.2, 0)
+    H = amp.HexOperator(torch.tensor(V, device=dev), E, order=order, lam=0.0)
+    M = amp.Matrix.from_hexop(H)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc = amp.Preconditioner.pmg(M)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    pi = pc.pmg_info()
+    b = torch.tensor(P.pmg_poisson_rhs(E, order), device=dev)
+    out = {"workload": f"Poisson -Laplace u = 1 + 3 pi^2 sin(pi x) sin(pi y) sin(pi z), order {order}, "
+                       f"{E[0]}x{E[1]}x{E[2]} trilinear hexahedra of [-0.5,0.5]^3 (interior vertices moved by "
+                       f"0.2 h), n={H.n}; p-multigrid V-cycle over orders {pi['orders']} (degree-2 "
+                       f"Chebyshev-Jacobi smoothing, degree-8 Chebyshev-Jacobi polynomial on the lowest order), "
+                       f"tol 1e-10",
+           "levels_n": pi["n"], "rho": [round(r, 6) for r in pi["rho"]], "gain": pi["gain"],
+           "setup_ms": round(setup_ms, 1), "preconditioner_bytes": pi["bytes"]}
+    stream = torch.cuda.current_stream()
+    r = torch.tensor(np.random.default_rng(87).standard_normal(H.n), device=dev)
+    cyc = {}
+    for prec in (64, 32):
+        pc.pmg_apply(r, prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pc.pmg_apply(r, prec)
+        e1.record(stream)
+        e1.synchronize()
+        cyc[f"fp{prec}_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+    out["cycle"] = cyc
+    log(f"bench: pMG cycle FP64 {cyc['fp64_us']} us, FP32 {cyc['fp32_us']} us")
+    runs, sol = {}, {}
+    for name, preset, kw in (("pcg64", "pcg64", {}), ("amp16_linear", "amp16", {"eta": "linear"}),
+                             ("amp16", "amp16", {}), ("amp16_r64", "amp16", {"eta": "fixed64"})):
+        amp.solve(M, pc, b, tol=1e-10, maxit=2000, preset=preset, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = amp.solve(M, pc, b, tol=1e-10, maxit=2000, preset=preset, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        sol[name] = x
+        runs[name] = {"ms": round(ms, 2), "iters": info["iters"], "k_z16": info["k_z16"], "k_r32": info["k_r32"],
+                      "rel_res_true": info["relres_true"], "status": info["status"]}
+        log(f"bench: pMG solve {name}: {ms:.1f} ms, {info['iters']} iterations, u_z FP16 from {info['k_z16']}, "
+            f"u_r FP32 from {info['k_r32']}")
+    xr = sol["pcg64"]
+    for name in ("amp16_linear", "amp16", "amp16_r64"):
+        runs[name]["rel_diff_vs_pcg64"] = float(torch.linalg.norm(sol[name] - xr) / torch.linalg.norm(xr))
+        runs[f"speedup_{name}_vs_fp64_pcg"] = round(runs["pcg64"]["ms"] / runs[name]["ms"], 4)
+    pj = amp.Preconditioner(M, "jacobi")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ij = amp.solve(M, pj, b, tol=1e-10, maxit=20000, preset="pcg64")
+    torch.cuda.synchronize()
+    runs["jacobi_pcg64"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iters": ij["iters"]}
+    log(f"bench: Jacobi-PCG(FP64) on the same system: {runs['jacobi_pcg64']['ms']} ms, {ij['iters']} iterations")
+    out["solve"] = runs
+    return out
+
+
 def fv128_measurement(amp, torch, np, P, dev, steps, warmup, with_oracle=True, grid=128):
     """The 128^3 blocky finite-volume workload (Jacobi): time per preset,
     product-kernel roofline, error against the oracle's solution."""
@@ -459,9 +528,10 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 finite-volume measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batched measurement")
     ap.add_argument("--no-hex", action="store_true", help="skip the matrix-free hexahedral operator measurement")
+    ap.add_argument("--no-pmg", action="store_true", help="skip the p-multigrid Poisson measurement")
     ap.add_argument("--no-oracle-solution", action="store_true",
                     help="skip the oracle's full solve of the Q1 system (the exact errors against it)")
-    ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched", "hex"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "roofline", "fv128", "batched", "hex", "pmg"], default="solve",
                     help="roofline: only the timed solve and the stream probes (for profiler runs); "
                          "fv128: the 128^3 finite-volume workload alone; batched: the 512-system workload alone; "
                          "hex: the matrix-free order-7 hexahedral operator alone")
@@ -494,6 +564,9 @@ def main():
         return
     if args.mode == "hex":
         print(json.dumps({"mode": "hex", **hex_measurement(amp, torch, np, P, dev)}), flush=True)
+        return
+    if args.mode == "pmg":
+        print(json.dumps({"mode": "pmg", **pmg_measurement(amp, torch, np, P, dev)}), flush=True)
         return
     if args.mode == "roofline" and args.workload == "fv128":
         A, b, _ = P.blocky_diffusion3d_system(128, 8)
@@ -595,6 +668,10 @@ def main():
     if not args.no_hex:
         torch.cuda.empty_cache()
         hexop = hex_measurement(amp, torch, np, P, dev)
+    pmg = None
+    if not args.no_pmg:
+        log("bench: p-multigrid Poisson problem")
+        pmg = pmg_measurement(amp, torch, np, P, dev)
 
     out = {
         "metric": METRIC,
@@ -632,6 +709,7 @@ def main():
         "secondary_fv128": secondary,
         "secondary_batched": batched,
         "secondary_hex_ax": hexop,
+        "secondary_pmg": pmg,
     }
     print(json.dumps(out), flush=True)
 

@@ -59,7 +59,7 @@ typedef enum {
     AMP_SCALE_NONE = 2    /* omega_k = 1 (plain PCG, Alg. 1) */
 } amp_scaling;
 
-typedef enum { AMP_PC_IDENTITY = 0, AMP_PC_JACOBI = 1, AMP_PC_CHEBYSHEV = 2 } amp_pc_kind;
+typedef enum { AMP_PC_IDENTITY = 0, AMP_PC_JACOBI = 1, AMP_PC_CHEBYSHEV = 2, AMP_PC_PMG = 3 } amp_pc_kind;
 
 /* Preset selectors of the PCG variants compared in Section 5. */
 typedef enum {
@@ -493,7 +493,8 @@ typedef struct {
                                    geometric factors) per local node */
 } amp_hexop_stats;
 
-/* Create the operator.  order: 3 or 7.  verts: device pointer to
+/* Create the operator.  order: 1, 3 or 7 (the matrix-free solve takes 3 and
+ * 7; order 1 serves the lowest level of the p-multigrid cycle).  verts: device pointer to
  * (ex+1)(ey+1)(ez+1) x 3 doubles, copied (the caller keeps ownership).
  * lambda >= 0.  Errors: AMP_ERR_ARG for counts < 1, an order not built,
  * n < 1, more than 2^31 - 1 elements or unknowns, a null pointer, a
@@ -528,6 +529,62 @@ amp_status amp_hexop_diagonal(amp_hexop H, double *diag, void *stream);
  * replacement, graph replay and group_rows refuse such a handle
  * (AMP_ERR_ARG).  Host-synchronous. */
 amp_status amp_matrix_from_hexop(amp_hexop H, void *stream, amp_matrix *out);
+
+/* ------------------------------------------------------------------------
+ * p-multigrid preconditioner for a matrix-free handle (Section 5.3, Ex.
+ * linear conv2: the preconditioner under which convergence is linear and
+ * z, p may be FP16 from the first iteration).  One V-cycle over polynomial
+ * orders orders[0] > orders[1] > ... on the operator's mesh, each level the
+ * operator rediscretised at its order with the same lambda:
+ *   V_l(f): x = S_l f; x += P_l V_{l+1}(P_l^T (f - A_l x)); x += S_l (f - A_l x)
+ * S_l: the Chebyshev iteration of degree `degree` for D^-1 A x = D^-1 f from
+ * x = 0 (D = diag(A_l)) on [lo_ratio rho_l, hi_margin rho_l], rho_l =
+ * lambda_max(D^-1 A_l).  Lowest level: the same polynomial of degree
+ * coarse_degree on [coarse_lo_ratio rho, hi_margin rho] (the paper's
+ * algebraic multigrid coarse solver is not built; a fixed polynomial keeps
+ * the cycle linear and symmetric).  P_l interpolates the coarse function at
+ * the fine GLL points element by element; P_l^T is its transpose.
+ * Arithmetic: FP64 while u_z is FP64, else FP32; z rounded to u_z.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int levels;             /* 1 .. 4 */
+    int orders[4];          /* strictly decreasing, each 1, 3 or 7; orders[0] = the operator's order */
+    int degree;             /* smoother degree, 1 .. 16 (default 2) */
+    int coarse_degree;      /* lowest level's polynomial degree, 1 .. 16 (default 8) */
+    double lo_ratio;        /* smoothing interval [lo_ratio rho, hi_margin rho] (default 0.1, 1.1) */
+    double hi_margin;
+    double coarse_lo_ratio; /* lowest level's interval [coarse_lo_ratio rho, hi_margin rho] (default 0.01) */
+    double rho[4];          /* lambda_max(D^-1 A_l) per level; <= 0: estimated by power_iters steps of
+                               the power iteration (Rayleigh quotient in the D inner product) */
+    int power_iters;        /* 1 .. 1000 (default 40) */
+} amp_pmg_params;
+
+typedef struct {
+    amp_pmg_params params;  /* as used: rho holds the values of every level */
+    double gain;            /* max|V(1)|: the scaling rule's first-iteration bound max|z| <= gain max|r| */
+    int64_t n[4];           /* unknowns per level */
+    int64_t bytes;          /* device memory held by the preconditioner */
+} amp_pmg_stats;
+
+/* Defaults: three levels (7, 3, 1), degree 2, coarse degree 8, intervals
+ * [0.1, 1.1] rho and [0.01, 1.1] rho, rho estimated with 40 steps. */
+void amp_pmg_params_default(amp_pmg_params *p);
+/* Create the preconditioner for A, a handle from amp_matrix_from_hexop
+ * (the operator's vertices and lambda are copied into the lower levels).
+ * For amp_pcg_solve with any preset; amp_precond_apply, amp_precond_update
+ * and the batched and allocation-free solves refuse it.  Errors:
+ * AMP_ERR_ARG for a handle that is not matrix-free, parameters out of
+ * range, a level without unknowns (order 1 needs at least 2 elements per
+ * direction), a non-positive diagonal or an estimate of rho that is not
+ * positive and finite; AMP_ERR_OOM / AMP_ERR_HIP.  Host-synchronous. */
+amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params *p, void *stream, amp_precond *out);
+amp_status amp_pmg_info(amp_precond M, amp_pmg_stats *out);
+/* z = V(r) (device, n doubles each), the cycle in FP64 (prec 64) or FP32
+ * (prec 32, r rounded to FP32 on entry).  Shares the preconditioner's work
+ * vectors with solves that use it: calls on one handle must not overlap.
+ * Enqueued on stream, not synchronised.  Errors: AMP_ERR_ARG for a null
+ * argument, another kind of preconditioner or a bad precision. */
+amp_status amp_pmg_apply(amp_precond M, const double *r, double *z, int prec, void *stream);
 
 #ifdef __cplusplus
 }

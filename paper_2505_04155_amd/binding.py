@@ -28,7 +28,7 @@ EXPORTED = [
     "amp_pcg_solve_batched", "amp_tune_group_rows", "amp_pcg_solve_noalloc", "amp_stream_probe",
     "amp_set_allocator", "amp_precond_bounds", "amp_matrix_tuning_default", "amp_tune_lanes",
     "amp_hexop_create", "amp_hexop_destroy", "amp_hexop_info", "amp_hexop_apply", "amp_hexop_diagonal",
-    "amp_matrix_from_hexop",
+    "amp_matrix_from_hexop", "amp_pmg_params_default", "amp_precond_create_pmg", "amp_pmg_info", "amp_pmg_apply",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -76,6 +76,17 @@ class MatrixTuning(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_int), ("offset_mode", ctypes.c_int)]
 
 
+class PmgParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("orders", ctypes.c_int * 4), ("degree", ctypes.c_int),
+                ("coarse_degree", ctypes.c_int), ("lo_ratio", ctypes.c_double), ("hi_margin", ctypes.c_double),
+                ("coarse_lo_ratio", ctypes.c_double), ("rho", ctypes.c_double * 4), ("power_iters", ctypes.c_int)]
+
+
+class PmgStats(ctypes.Structure):
+    _fields_ = [("params", PmgParams), ("gain", ctypes.c_double), ("n", ctypes.c_int64 * 4),
+                ("bytes", ctypes.c_int64)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -118,6 +129,11 @@ def load(build_if_missing: bool = True):
         L.amp_hexop_apply.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.amp_hexop_diagonal.argtypes = [vp, vp, vp]
         L.amp_matrix_from_hexop.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.amp_pmg_params_default.argtypes = [ctypes.POINTER(PmgParams)]
+        L.amp_pmg_params_default.restype = None
+        L.amp_precond_create_pmg.argtypes = [vp, ctypes.POINTER(PmgParams), vp, ctypes.POINTER(vp)]
+        L.amp_pmg_info.argtypes = [vp, ctypes.POINTER(PmgStats)]
+        L.amp_pmg_apply.argtypes = [vp, vp, vp, i32, vp]
         L.amp_matrix_tuning_default.argtypes = [ctypes.POINTER(MatrixTuning)]
         L.amp_matrix_tuning_default.restype = None
         L.amp_tune_lanes.argtypes = [ctypes.POINTER(Csr), ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32),

@@ -13,7 +13,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libamppcg.so")
 SOURCES = ["amp_pcg.hip"]
 HEADERS = ["amp_controller.hpp", "amp_device.hpp", "amp_kernels.hpp", "amp_cheb.hpp", "amp_fv.hpp",
-           "amp_batch.hpp", "amp_hex.hpp", "amp_hexsolve.hpp"]
+           "amp_batch.hpp", "amp_hex.hpp", "amp_hexsolve.hpp", "amp_pmg.hpp"]
 
 
 def hipcc() -> str:

@@ -20,6 +20,7 @@
 #include "amp_hexsolve.hpp"
 #include "amp_kernels.hpp"
 #include "amp_pcg.h"
+#include "amp_pmg.hpp"
 
 using namespace amp;
 
@@ -234,6 +235,8 @@ struct amp_precond_s {
     void *cdir[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     double inv_theta = 0.0, c1[kChebMax] = {0}, c2[kChebMax] = {0};
     int est_hi = 0, est_lo = 0;       // bounds estimated by the Lanczos process (lam <= 0 given)
+    struct PmgData *pmg = nullptr;    // AMP_PC_PMG: the levels of the cycle
+    int64_t bytes_pmg = 0;
     double ritz_min = 0.0, ritz_max = 0.0;
     Cheb cheb() const {
         Cheb P;
@@ -249,6 +252,142 @@ struct amp_precond_s {
         return P;
     }
 };
+
+// ----------------------------------------------------------------------------
+// p-multigrid preconditioner: levels and the enqueue of one cycle
+// ----------------------------------------------------------------------------
+
+// One level of the cycle.  Vectors of both precisions, `len` entries each
+// (the padded row count on level 0, whose f and x are also the solve's
+// v and pre-z vectors): f (right-hand side), x (result), ax (products,
+// cleared between them), g (the post-smoother's right-hand side) and the
+// smoother's two iterates y[0], y[1].  Index [precision]: 0 FP64, 1 FP32.
+struct PmgLvl {
+    amp_hexop H = nullptr;
+    bool own = false;              // H created for this level (levels below the finest)
+    int N = 0, deg = 0;
+    int64_t n = 0, len = 0;
+    double *dinv64 = nullptr;
+    float *dinv32 = nullptr;
+    double *blk64 = nullptr;
+    float *blk32 = nullptr;
+    void *f[2] = {}, *x[2] = {}, *ax[2] = {}, *g[2] = {};
+    void *y[2][2] = {};            // [iterate][precision]
+    double rho = 0, lo = 0, hi = 0, inv_theta = 0;
+    double c1[kPmgDegMax] = {0}, c2[kPmgDegMax] = {0};
+    double *J = nullptr;           // (N+1) x (N_{l+1}+1): interpolation from the next level
+};
+
+struct PmgData {
+    amp_pmg_params prm;
+    int L = 0;
+    PmgLvl lv[kPmgLevels];
+    double *ones64 = nullptr;      // level-0 length, all 1: the unit row scale of the v / z kernels
+    float *ones32 = nullptr;
+    double *part = nullptr;        // 2 kPmgPartMax partials
+    double gain = 0.0;
+};
+
+static void pmg_free(PmgData *P) {
+    if (!P) return;
+    for (int l = 0; l < kPmgLevels; ++l) {
+        PmgLvl &L = P->lv[l];
+        if (L.own) amp_hexop_destroy(L.H);
+        dfree(L.dinv64); dfree(L.dinv32); dfree(L.blk64); dfree(L.blk32); dfree(L.J);
+    }
+    dfree(P->ones64); dfree(P->ones32); dfree(P->part);
+    delete P;
+}
+
+static unsigned pmg_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kPmgPartMax, (n + NTV - 1) / NTV));
+}
+
+static void pmg_product(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec) {
+    const HexView hv = hex_view(L.H);
+    const unsigned E = (unsigned)((int64_t)L.H->ex * L.H->ey * L.H->ez);
+    const unsigned nt = (unsigned)((L.N + 1) * (L.N + 1));
+    if (L.N == 7) k_pmg_ax<7><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
+    else if (L.N == 3) k_pmg_ax<3><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
+    else k_pmg_ax<1><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
+}
+
+static PmgVecOp pmg_op(const PmgLvl &L) {
+    PmgVecOp o;
+    std::memset(&o, 0, sizeof(o));
+    o.n = L.n;
+    o.dinv[0] = L.dinv64;
+    o.dinv[1] = L.dinv32;
+    for (int p = 0; p < 2; ++p) o.ax[p] = L.ax[p];
+    return o;
+}
+
+// x = S f (post: x += S (f - A x), with A x in ax on entry).
+static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int prec) {
+    const int m = L.deg;
+    const unsigned g = pmg_grid(L.n);
+    PmgVecOp o = pmg_op(L);
+    o.first = 1;
+    o.a = L.inv_theta;
+    for (int p = 0; p < 2; ++p) {
+        o.rhs[p] = L.f[p];
+        if (post) o.gout[p] = L.g[p];
+        if (m > 1) o.out[p] = L.y[0][p];
+        else if (post) o.acc[p] = L.x[p];
+        else o.out[p] = L.x[p];
+    }
+    k_pmg_vec<<<g, NTV, 0, st>>>(o, s, prec);
+    for (int k = 1; k < m; ++k) {
+        pmg_product(L, L.y[(k - 1) % 2], L.ax, st, s, prec);
+        PmgVecOp q = pmg_op(L);
+        q.c1 = L.c1[k - 1];
+        q.c2 = L.c2[k - 1];
+        for (int p = 0; p < 2; ++p) {
+            q.rhs[p] = post ? L.g[p] : L.f[p];
+            q.cur[p] = L.y[(k - 1) % 2][p];
+            q.prev[p] = (k >= 2) ? L.y[(k - 2) % 2][p] : nullptr;
+            if (k + 1 < m) q.out[p] = L.y[k % 2][p];
+            else if (post) q.acc[p] = L.x[p];
+            else q.out[p] = L.x[p];
+        }
+        k_pmg_vec<<<g, NTV, 0, st>>>(q, s, prec);
+    }
+}
+
+template <int NF, int NC>
+static void pmg_transfer(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec) {
+    const unsigned E = (unsigned)((int64_t)F.H->ex * F.H->ey * F.H->ez);
+    const HexView hf = hex_view(F.H), hc = hex_view(C.H);
+    if (restrict_)
+        k_pmg_restrict<NF, NC><<<E, NTX, 0, st>>>(hf, hc, F.J, F.f[0], F.f[1], F.ax[0], F.ax[1], C.f[0], C.f[1], s,
+                                                   prec);
+    else
+        k_pmg_prolong<NF, NC><<<E, NTX, 0, st>>>(hf, hc, F.J, C.x[0], C.x[1], F.x[0], F.x[1], F.ax[0], F.ax[1], s,
+                                                  prec);
+}
+
+static void pmg_transfer_any(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec) {
+    if (F.N == 7 && C.N == 3) pmg_transfer<7, 3>(F, C, restrict_, st, s, prec);
+    else if (F.N == 7) pmg_transfer<7, 1>(F, C, restrict_, st, s, prec);
+    else pmg_transfer<3, 1>(F, C, restrict_, st, s, prec);
+}
+
+// x_l = V_l(f_l): the cycle's kernels in stream order.  s: the solve's state
+// after the controller prologue (the cycle's precision and stop flag), or
+// null with prec = 64 / 32.
+static void pmg_cycle(PmgData &P, int l, hipStream_t st, const St *s, int prec) {
+    PmgLvl &L = P.lv[l];
+    pmg_smooth(L, false, st, s, prec);
+    if (l == P.L - 1) return;
+    PmgLvl &C = P.lv[l + 1];
+    pmg_product(L, L.x, L.ax, st, s, prec);
+    k_pmg_clear<<<pmg_grid(C.n), NTV, 0, st>>>(C.f[0], C.f[1], C.n, s, prec);
+    pmg_transfer_any(L, C, true, st, s, prec);
+    pmg_cycle(P, l + 1, st, s, prec);
+    pmg_transfer_any(L, C, false, st, s, prec);
+    pmg_product(L, L.x, L.ax, st, s, prec);
+    pmg_smooth(L, true, st, s, prec);
+}
 
 // Work-group counts: enough for every unit of work, at most GMAX, and a
 // multiple of the XCD count when there are at least that many.
@@ -985,6 +1124,7 @@ extern "C" amp_status amp_precond_create(amp_matrix A, int kind, int degree, dou
     if (!out) return fail(AMP_ERR_ARG, "amp_precond_create: out is NULL");
     *out = nullptr;
     if (!A) return fail(AMP_ERR_ARG, "amp_precond_create: null matrix");
+    if (kind == AMP_PC_PMG) return fail(AMP_ERR_ARG, "amp_precond_create: use amp_precond_create_pmg");
     if (kind != AMP_PC_IDENTITY && kind != AMP_PC_JACOBI && kind != AMP_PC_CHEBYSHEV)
         return fail(AMP_ERR_ARG, "amp_precond_create: unknown preconditioner kind");
     if (kind == AMP_PC_CHEBYSHEV) {
@@ -1047,6 +1187,8 @@ extern "C" amp_status amp_precond_bounds(amp_precond M, double *lam_lo, double *
 
 extern "C" amp_status amp_precond_update(amp_precond M, void *stream) {
     if (!M) return fail(AMP_ERR_ARG, "amp_precond_update: null handle");
+    if (M->kind == AMP_PC_PMG)
+        return fail(AMP_ERR_ARG, "amp_precond_update: a p-multigrid preconditioner has no stored values to update");
     return setup_values(M, as_stream(stream));
 }
 
@@ -1055,6 +1197,7 @@ extern "C" void amp_precond_destroy(amp_precond M) {
     dfree(M->d64); dfree(M->d32); dfree(M->d16);
     dfree(M->b16); dfree(M->isq64); dfree(M->isq32);
     dfree(M->cblk64); dfree(M->cblk32);
+    pmg_free(M->pmg);
     delete M;
 }
 
@@ -1141,7 +1284,8 @@ static Cfg make_cfg(const amp_options &o, amp_matrix A, amp_precond M, double to
     c.maxit = maxit;
     c.verify = o.verify;
     c.max_repl = o.max_replacements;
-    c.chebyshev = (M && M->kind == AMP_PC_CHEBYSHEV) ? 1 : 0;
+    // the scaling rule of a non-diagonal preconditioner (the previous max|z| predicts the next)
+    c.chebyshev = (M && (M->kind == AMP_PC_CHEBYSHEV || M->kind == AMP_PC_PMG)) ? 1 : 0;
     c.diff = o.spmv32_diff ? 1 : 0;
     c.rr_period = o.rr_period;
     c.defer_x = (o.defer_x && o.rr_period == 0) ? 1 : 0;   // a periodic replacement reads x
@@ -1289,11 +1433,38 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
     }
 }
 
+// The p-multigrid preconditioner inside the iteration: the Chebyshev
+// preconditioner's first kernel (controller prologue, v = fl_uz(fl_ur(omega
+// r))) with a unit row scale writes level 0's f; the cycle; its degree-1
+// kernel with unit scale and 1/theta = 1 rounds level 0's x to z in u_z and
+// writes the partials of rho and max|z|.
+static Cheb pmg_cheb(const PmgData &P, int64_t np, bool exit) {
+    Cheb C;
+    std::memset(&C, 0, sizeof(C));
+    C.isq64 = P.ones64;
+    C.isq32 = P.ones32;
+    for (int p = 0; p < 2; ++p) C.v[p] = exit ? P.lv[0].x[p] : P.lv[0].f[p];
+    C.np = np;
+    C.degree = 1;
+    C.inv_theta = 1.0;
+    return C;
+}
+
+static void enqueue_pmg(Driver &d, St *in, St *out) {
+    PmgData &P = *d.M->pmg;
+    St *pre = &d.sb[ST_PREI];
+    k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, pmg_cheb(P, d.A->np, false), 0, in, pre, d.S);
+    pmg_cycle(P, 0, d.st, pre, 0);
+    k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, pmg_cheb(P, d.A->np, true), pre, out);
+}
+
 static amp_status enqueue_iterations(Driver &d, int count) {
     Work &w = d.A->w;
     for (int i = 0; i < count; ++i) {
         if (d.M->kind == AMP_PC_CHEBYSHEV) {
             enqueue_chebyshev(d, 0, d.in, &d.sb[ST_PRE]);
+        } else if (d.M->kind == AMP_PC_PMG) {
+            enqueue_pmg(d, d.in, &d.sb[ST_PRE]);
         } else {
             k_precond<<<d.gs, NT, 0, d.st>>>(d.in, d.B.part_res, std::max(d.cfg.g_stream, d.cfg.g_slice), d.gs,
                                              d.cfg.ring, d.cfg, d.B, d.A->np, &d.sb[ST_PRE], d.S);
@@ -2348,6 +2519,7 @@ extern "C" amp_status amp_precond_apply(amp_precond M, int u_r, int u_z, const v
     if (!M || !r || !z) return fail(AMP_ERR_ARG, "amp_precond_apply: null argument");
     if ((u_r != 64 && u_r != 32) || !valid_prec(u_z)) return fail(AMP_ERR_ARG, "amp_precond_apply: bad precision");
     if (!(omega != 0.0) || !std::isfinite(omega)) return fail(AMP_ERR_ARG, "amp_precond_apply: omega must be finite, nonzero");
+    if (M->kind == AMP_PC_PMG) return fail(AMP_ERR_ARG, "amp_precond_apply: use amp_pmg_apply for a p-multigrid preconditioner");
     amp_matrix A = M->A;
     hipStream_t st = as_stream(stream);
     AMP_TRY(ensure_work(A, st));
@@ -2682,7 +2854,7 @@ extern "C" amp_status amp_hexop_create(int ex, int ey, int ez, int order, const 
     *out = nullptr;
     if (!verts) return fail(AMP_ERR_ARG, "amp_hexop_create: null vertex array");
     if (ex < 1 || ey < 1 || ez < 1) return fail(AMP_ERR_ARG, "amp_hexop_create: element counts must be >= 1");
-    if (order != 3 && order != 7) return fail(AMP_ERR_ARG, "amp_hexop_create: order must be 3 or 7");
+    if (order != 1 && order != 3 && order != 7) return fail(AMP_ERR_ARG, "amp_hexop_create: order must be 1, 3 or 7");
     if (!(lambda >= 0.0) || !std::isfinite(lambda))
         return fail(AMP_ERR_ARG, "amp_hexop_create: lambda must be finite and >= 0");
     const int64_t elements = (int64_t)ex * ey * ez;
@@ -2712,7 +2884,8 @@ extern "C" amp_status amp_hexop_create(int ex, int ey, int ez, int order, const 
     if (e == hipSuccess) {
         const HexView v = hex_view(H);
         if (order == 7) k_hex_check<7><<<(unsigned)elements, 512, 0, st>>>(v, err);
-        else k_hex_check<3><<<(unsigned)elements, 64, 0, st>>>(v, err);
+        else if (order == 3) k_hex_check<3><<<(unsigned)elements, 64, 0, st>>>(v, err);
+        else k_hex_check<1><<<(unsigned)elements, 8, 0, st>>>(v, err);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -2772,7 +2945,8 @@ extern "C" amp_status amp_hexop_apply(amp_hexop H, int u_p, int u_r, const void 
     else k_hex_zero<float><<<gz, 256, 0, st>>>((float *)q, H->n);
     const HexView v = hex_view(H);
     if (H->order == 7) launch_hex_ax<7>(v, elements, u_p, u_r, p, q, H->part, st);
-    else launch_hex_ax<3>(v, elements, u_p, u_r, p, q, H->part, st);
+    else if (H->order == 3) launch_hex_ax<3>(v, elements, u_p, u_r, p, q, H->part, st);
+    else launch_hex_ax<1>(v, elements, u_p, u_r, p, q, H->part, st);
     if (mu) k_hex_sum<<<1, kHexSumThreads, 0, st>>>(H->part, elements, mu);
     AMP_HIP(hipGetLastError());
     return AMP_OK;
@@ -2788,6 +2962,8 @@ extern "C" amp_status amp_matrix_from_hexop(amp_hexop H, void *stream, amp_matri
     if (!out) return fail(AMP_ERR_ARG, "amp_matrix_from_hexop: out is NULL");
     *out = nullptr;
     if (!H) return fail(AMP_ERR_ARG, "amp_matrix_from_hexop: null operator");
+    if (H->order != 3 && H->order != 7)
+        return fail(AMP_ERR_ARG, "amp_matrix_from_hexop: the matrix-free solve takes orders 3 and 7");
     hipStream_t st = as_stream(stream);
     amp_matrix A = new amp_matrix_s();
     A->hex = H;
@@ -2821,8 +2997,265 @@ extern "C" amp_status amp_hexop_diagonal(amp_hexop H, double *diag, void *stream
     k_hex_zero<double><<<(unsigned)std::min<int64_t>(2048, (H->n + 255) / 256), 256, 0, st>>>(diag, H->n);
     const HexView v = hex_view(H);
     if (H->order == 7) k_hex_diag<7><<<(unsigned)elements, 512, 0, st>>>(v, diag);
-    else k_hex_diag<3><<<(unsigned)elements, 64, 0, st>>>(v, diag);
+    else if (H->order == 3) k_hex_diag<3><<<(unsigned)elements, 64, 0, st>>>(v, diag);
+    else k_hex_diag<1><<<(unsigned)elements, 8, 0, st>>>(v, diag);
     AMP_HIP(hipGetLastError());
     return AMP_OK;
 }
 
+
+// ----------------------------------------------------------------------------
+// p-multigrid preconditioner
+// ----------------------------------------------------------------------------
+
+extern "C" void amp_pmg_params_default(amp_pmg_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->levels = 3;
+    p->orders[0] = 7;
+    p->orders[1] = 3;
+    p->orders[2] = 1;
+    p->degree = 2;
+    p->coarse_degree = 8;
+    p->lo_ratio = 0.1;
+    p->hi_margin = 1.1;
+    p->coarse_lo_ratio = 0.01;
+    p->power_iters = 40;
+}
+
+// J[a][b] = l_b(x_a): the order-nc Lagrange basis on its GLL points at the
+// order-nf GLL points, by the product formula (exactly 0 and 1 where the
+// points coincide: the end points).
+static void pmg_interp(int nf, int nc, std::vector<double> &J) {
+    std::vector<double> tf, tc;
+    gll_tables(nf, tf);
+    gll_tables(nc, tc);
+    J.assign((size_t)(nf + 1) * (nc + 1), 0.0);
+    for (int a = 0; a <= nf; ++a)
+        for (int b = 0; b <= nc; ++b) {
+            double v = 1.0;
+            for (int c = 0; c <= nc; ++c)
+                if (c != b) v *= (tf[a] - tc[c]) / (tc[b] - tc[c]);
+            J[(size_t)a * (nc + 1) + b] = v;
+        }
+}
+
+// Chebyshev iteration coefficients on [lo, hi] for degree deg.
+static void pmg_coefficients(PmgLvl &L) {
+    const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo), sigma = theta / delta;
+    L.inv_theta = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k + 1 < L.deg; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        L.c1[k] = rn * rho;
+        L.c2[k] = 2.0 * rn / delta;
+        rho = rn;
+    }
+}
+
+// Sum of the partial pairs of k_pmg_power in work-group order.
+static amp_status pmg_read_pairs(PmgData &P, unsigned g, hipStream_t st, double &a, double &b) {
+    std::vector<double> h(2 * (size_t)g);
+    AMP_HIP(hipMemcpyAsync(h.data(), P.part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipStreamSynchronize(st));
+    a = b = 0.0;
+    for (unsigned i = 0; i < g; ++i) {
+        a += h[2 * i];
+        b += h[2 * i + 1];
+    }
+    return AMP_OK;
+}
+
+// rho_l by the power iteration on D^-1 A (FP64), Rayleigh quotient of the last
+// iterate.  Uses y[0] and ax of the level; leaves ax cleared.
+static amp_status pmg_estimate_rho(PmgData &P, int l, hipStream_t st, double *out) {
+    PmgLvl &L = P.lv[l];
+    const unsigned g = pmg_grid(L.n);
+    double *v = (double *)L.y[0][0], *ax = (double *)L.ax[0];
+    k_pmg_start<<<g, NTV, 0, st>>>(v, L.n);
+    double R = 0.0, scale = 1.0;
+    for (int t = 0; t < P.prm.power_iters; ++t) {
+        pmg_product(L, L.y[0], L.ax, st, nullptr, 64);
+        k_pmg_power<<<g, NTV, 0, st>>>(v, ax, L.dinv64, L.n, scale, P.part);
+        AMP_HIP(hipGetLastError());
+        double num, den;
+        AMP_TRY(pmg_read_pairs(P, g, st, num, den));
+        if (!(den > 0.0) || !(num > 0.0) || !std::isfinite(num) || !std::isfinite(den))
+            return fail(AMP_ERR_ARG, "amp_precond_create_pmg: the power iteration for rho broke down");
+        R = num / den;
+        scale = 1.0 / R;
+    }
+    *out = R;
+    return AMP_OK;
+}
+
+static amp_status pmg_check(const amp_matrix A, const amp_pmg_params &p) {
+    const char *w = "amp_precond_create_pmg: ";
+    if (!A->hex) return fail(AMP_ERR_ARG, std::string(w) + "the matrix is not a matrix-free operator");
+    if (p.levels < 1 || p.levels > kPmgLevels) return fail(AMP_ERR_ARG, std::string(w) + "levels must be 1 to 4");
+    if (p.orders[0] != A->hex->order)
+        return fail(AMP_ERR_ARG, std::string(w) + "orders[0] must be the operator's order");
+    for (int l = 0; l < p.levels; ++l) {
+        const int N = p.orders[l];
+        if (N != 1 && N != 3 && N != 7) return fail(AMP_ERR_ARG, std::string(w) + "orders must be 1, 3 or 7");
+        if (l > 0 && !(N < p.orders[l - 1])) return fail(AMP_ERR_ARG, std::string(w) + "orders must decrease");
+        if (!std::isfinite(p.rho[l])) return fail(AMP_ERR_ARG, std::string(w) + "rho must be finite");
+    }
+    if (p.degree < 1 || p.degree > kPmgDegMax || p.coarse_degree < 1 || p.coarse_degree > kPmgDegMax)
+        return fail(AMP_ERR_ARG, std::string(w) + "degrees must be 1 to 16");
+    if (!(p.lo_ratio > 0.0 && p.lo_ratio < 1.0) || !(p.coarse_lo_ratio > 0.0 && p.coarse_lo_ratio < 1.0) ||
+        !(p.hi_margin >= 1.0) || !std::isfinite(p.hi_margin))
+        return fail(AMP_ERR_ARG, std::string(w) + "need 0 < lo_ratio, coarse_lo_ratio < 1 <= hi_margin");
+    if (p.power_iters < 1 || p.power_iters > 1000) return fail(AMP_ERR_ARG, std::string(w) + "power_iters must be 1 to 1000");
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params *prm, void *stream,
+                                             amp_precond *out) {
+    if (!out) return fail(AMP_ERR_ARG, "amp_precond_create_pmg: out is NULL");
+    *out = nullptr;
+    if (!A || !prm) return fail(AMP_ERR_ARG, "amp_precond_create_pmg: null argument");
+    AMP_TRY(pmg_check(A, *prm));
+    hipStream_t st = as_stream(stream);
+    amp_precond M = new amp_precond_s();
+    auto bail = [&](amp_status s) { amp_precond_destroy(M); return s; };
+    M->A = A;
+    M->kind = AMP_PC_PMG;
+    M->degree = prm->degree;
+    M->generation = ++g_generation;
+    M->pmg = new PmgData();
+    PmgData &P = *M->pmg;
+    P.prm = *prm;
+    P.L = prm->levels;
+    amp_hexop H0 = A->hex;
+    amp_status s;
+    int *err = nullptr;
+    double *diag = nullptr;
+    if ((s = dalloc(&err, 1)) != AMP_OK || (s = dalloc(&P.part, 2 * kPmgPartMax)) != AMP_OK ||
+        (s = dalloc(&P.ones64, A->np)) != AMP_OK || (s = dalloc(&P.ones32, A->np)) != AMP_OK ||
+        (s = dalloc(&diag, A->np)) != AMP_OK) {
+        dfree(err);
+        dfree(diag);
+        return bail(s);
+    }
+    auto cleanup = [&](amp_status r) {
+        dfree(err);
+        dfree(diag);
+        return r == AMP_OK ? r : bail(r);
+    };
+    {
+        std::vector<double> one(A->np, 1.0);
+        std::vector<float> one32(A->np, 1.0f);
+        if (hipMemcpy(P.ones64, one.data(), A->np * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(P.ones32, one32.data(), A->np * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: copying the unit scale"));
+    }
+    int64_t bytes = A->np * 12 + 16 * kPmgPartMax;
+    for (int l = 0; l < P.L; ++l) {
+        PmgLvl &L = P.lv[l];
+        L.N = prm->orders[l];
+        if (l == 0) {
+            L.H = H0;
+        } else {
+            if ((s = amp_hexop_create(H0->ex, H0->ey, H0->ez, L.N, H0->verts, H0->lam, stream, &L.H)) != AMP_OK)
+                return cleanup(s);
+            L.own = true;
+        }
+        L.n = L.H->n;
+        L.len = (l == 0) ? A->np : L.n;
+        L.deg = (l == P.L - 1) ? prm->coarse_degree : prm->degree;
+        if ((s = dalloc(&L.dinv64, L.len)) != AMP_OK || (s = dalloc(&L.dinv32, L.len)) != AMP_OK ||
+            (s = dalloc(&L.blk64, 6 * L.len)) != AMP_OK || (s = dalloc(&L.blk32, 6 * L.len)) != AMP_OK)
+            return cleanup(s);
+        bytes += L.len * (12 + 6 * 12);
+        if (hipMemsetAsync(L.blk64, 0, 6 * L.len * sizeof(double), st) != hipSuccess ||
+            hipMemsetAsync(L.blk32, 0, 6 * L.len * sizeof(float), st) != hipSuccess ||
+            hipMemsetAsync(L.dinv64, 0, L.len * sizeof(double), st) != hipSuccess ||
+            hipMemsetAsync(L.dinv32, 0, L.len * sizeof(float), st) != hipSuccess ||
+            hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess)
+            return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: clearing the work vectors"));
+        void *b64[6], *b32[6];
+        for (int i = 0; i < 6; ++i) {
+            b64[i] = L.blk64 + i * L.len;
+            b32[i] = L.blk32 + i * L.len;
+        }
+        L.f[0] = b64[0]; L.x[0] = b64[1]; L.ax[0] = b64[2]; L.g[0] = b64[3]; L.y[0][0] = b64[4]; L.y[1][0] = b64[5];
+        L.f[1] = b32[0]; L.x[1] = b32[1]; L.ax[1] = b32[2]; L.g[1] = b32[3]; L.y[0][1] = b32[4]; L.y[1][1] = b32[5];
+        if ((s = amp_hexop_diagonal(L.H, diag, stream)) != AMP_OK) return cleanup(s);
+        k_pmg_dinv<<<pmg_grid(L.n), NTV, 0, st>>>(diag, L.dinv64, L.dinv32, L.n, err);
+        int herr = 0;
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: forming the diagonal"));
+        if (herr) return cleanup(fail(AMP_ERR_ARG, "amp_precond_create_pmg: a diagonal entry is not positive"));
+        if (l > 0) {
+            std::vector<double> J;
+            pmg_interp(P.lv[l - 1].N, L.N, J);
+            if ((s = dalloc(&P.lv[l - 1].J, J.size())) != AMP_OK) return cleanup(s);
+            if (hipMemcpy(P.lv[l - 1].J, J.data(), J.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: copying the interpolation table"));
+        }
+    }
+    for (int l = 0; l < P.L; ++l) {
+        PmgLvl &L = P.lv[l];
+        if (prm->rho[l] > 0.0) {
+            L.rho = prm->rho[l];
+        } else {
+            if ((s = pmg_estimate_rho(P, l, st, &L.rho)) != AMP_OK) return cleanup(s);
+        }
+        P.prm.rho[l] = L.rho;
+        L.lo = ((l == P.L - 1) ? prm->coarse_lo_ratio : prm->lo_ratio) * L.rho;
+        L.hi = prm->hi_margin * L.rho;
+        pmg_coefficients(L);
+    }
+    // gain = max|V(1)| (FP64)
+    {
+        PmgLvl &L0 = P.lv[0];
+        k_pmg_in<<<pmg_grid(L0.n), NTV, 0, st>>>(P.ones64, L0.f[0], L0.f[1], L0.n, 64);
+        pmg_cycle(P, 0, st, nullptr, 64);
+        const unsigned g = pmg_grid(L0.n);
+        k_pmg_maxabs<<<g, NTV, 0, st>>>((const double *)L0.x[0], L0.n, P.part);
+        std::vector<double> h(g);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h.data(), P.part, g * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: the first cycle failed"));
+        double m = 0.0;
+        for (double v : h) m = std::max(m, v);
+        if (!(m > 0.0) || !std::isfinite(m))
+            return cleanup(fail(AMP_ERR_ARG, "amp_precond_create_pmg: the cycle of the unit vector is not finite"));
+        P.gain = m;
+    }
+    M->gain = P.gain;
+    M->extra16 = 0;
+    M->bytes_pmg = bytes;
+    dfree(err);
+    dfree(diag);
+    *out = M;
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_pmg_info(amp_precond M, amp_pmg_stats *out) {
+    if (!M || !out) return fail(AMP_ERR_ARG, "amp_pmg_info: null argument");
+    if (M->kind != AMP_PC_PMG) return fail(AMP_ERR_ARG, "amp_pmg_info: not a p-multigrid preconditioner");
+    std::memset(out, 0, sizeof(*out));
+    out->params = M->pmg->prm;
+    out->gain = M->pmg->gain;
+    for (int l = 0; l < M->pmg->L; ++l) out->n[l] = M->pmg->lv[l].n;
+    out->bytes = M->bytes_pmg;
+    return AMP_OK;
+}
+
+extern "C" amp_status amp_pmg_apply(amp_precond M, const double *r, double *z, int prec, void *stream) {
+    if (!M || !r || !z) return fail(AMP_ERR_ARG, "amp_pmg_apply: null argument");
+    if (M->kind != AMP_PC_PMG) return fail(AMP_ERR_ARG, "amp_pmg_apply: not a p-multigrid preconditioner");
+    if (prec != 64 && prec != 32) return fail(AMP_ERR_ARG, "amp_pmg_apply: prec must be 64 or 32");
+    hipStream_t st = as_stream(stream);
+    PmgData &P = *M->pmg;
+    PmgLvl &L0 = P.lv[0];
+    k_pmg_in<<<pmg_grid(L0.n), NTV, 0, st>>>(r, L0.f[0], L0.f[1], L0.n, prec);
+    pmg_cycle(P, 0, st, nullptr, prec);
+    k_pmg_out<<<pmg_grid(L0.n), NTV, 0, st>>>(L0.x[0], L0.x[1], z, L0.n, prec);
+    AMP_HIP(hipGetLastError());
+    return AMP_OK;
+}

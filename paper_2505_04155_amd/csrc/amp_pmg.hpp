@@ -1,0 +1,319 @@
+// p-multigrid preconditioner (Section 5.3, Ex. linear conv2) for the
+// matrix-free hexahedral operator: a V-cycle over polynomial orders
+// N_0 > N_1 > ... on the same mesh, each level the operator rediscretised at
+// its order, smoothed by a Chebyshev-accelerated Jacobi polynomial, with a
+// higher-degree Chebyshev-Jacobi polynomial as the coarse solve.
+//
+// V-cycle for f on level l: x = S f; x += P V_{l+1}(P^T (f - A x));
+// x += S (f - A x).  S = s(D^-1 A) D^-1 is the Chebyshev iteration for
+// D^-1 A x = D^-1 f from x = 0 on [lo, hi]:
+//   x_1 = D^-1 f / theta;  x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (f - A x_k).
+// P interpolates the coarse function at the fine GLL points element by
+// element (1-D matrix J[a][b] = l_b(x_a) along each direction); every element
+// holding a fine node gives it the same value, so only the node's owner
+// element writes it.  P^T: each element sums J^T of its fine values weighted
+// by 1 / (number of elements sharing the node) into the coarse nodes by
+// atomic adds (exact: P[f][c] is nonzero only when every element holding f
+// also holds c).
+//
+// Every kernel takes the precision of the cycle from the solve's state (FP64
+// when u_z is FP64, else FP32; nothing at all once the solve has stopped) or,
+// standalone, from an argument.  Work vectors of both precisions exist; only
+// the active one is touched.
+#pragma once
+
+#include "amp_hex.hpp"
+#include "amp_controller.hpp"
+
+namespace amp {
+
+constexpr int kPmgLevels = 4;    // most levels of a cycle
+constexpr int kPmgDegMax = 16;   // highest smoother / coarse polynomial degree
+constexpr int NTV = 256;         // threads of the vector kernels
+constexpr int kPmgPartMax = 1024;
+
+// Precision of a cycle launch: 64 or 32, or 0 when the solve has stopped.
+__device__ __forceinline__ int pmg_prec(const St *st, int prec) {
+    if (st) {
+        if (st->status != RUNNING) return 0;
+        return st->uz == 64 ? 64 : 32;
+    }
+    return prec;
+}
+
+// One elementwise pass of the smoother.  Pointers by precision (0: FP64,
+// 1: FP32).  first: x_1 = a D^-1 g with g = rhs, or, when gout is set,
+// g = rhs - ax stored to gout (the post-smoother's right-hand side);
+// otherwise x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (rhs - ax) with
+// x_{k-1} = 0 when prev is null.  The result is stored to out, or added to
+// acc.  ax is cleared after it is read (the next product sums into it).
+struct PmgVecOp {
+    const void *dinv[2];
+    const void *rhs[2];
+    void *ax[2];
+    const void *cur[2];
+    const void *prev[2];
+    void *out[2];
+    void *gout[2];
+    void *acc[2];
+    int64_t n;
+    double a, c1, c2;
+    int first;
+};
+
+template <typename T>
+__device__ __forceinline__ void pmg_vec_body(const PmgVecOp &o, int s) {
+    const T *dinv = (const T *)o.dinv[s];
+    const T *rhs = (const T *)o.rhs[s];
+    T *ax = (T *)o.ax[s];
+    const T *cur = (const T *)o.cur[s];
+    const T *prev = (const T *)o.prev[s];
+    T *out = (T *)o.out[s];
+    T *gout = (T *)o.gout[s];
+    T *acc = (T *)o.acc[s];
+    const T a = (T)o.a, c1 = (T)o.c1, c2 = (T)o.c2;
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < o.n; i += (int64_t)gridDim.x * NTV) {
+        T xn;
+        if (o.first) {
+            T g = rhs[i];
+            if (gout) {
+                g = g - ax[i];
+                gout[i] = g;
+            }
+            xn = a * (dinv[i] * g);
+        } else {
+            const T xk = cur[i];
+            const T xp = prev ? prev[i] : (T)0;
+            xn = (xk + c1 * (xk - xp)) + c2 * (dinv[i] * (rhs[i] - ax[i]));
+        }
+        if (acc) acc[i] = acc[i] + xn;
+        else out[i] = xn;
+        ax[i] = (T)0;
+    }
+}
+
+__global__ void __launch_bounds__(NTV) k_pmg_vec(PmgVecOp o, const St *st, int prec) {
+    const int p = pmg_prec(st, prec);
+    if (p == 64) pmg_vec_body<double>(o, 0);
+    else if (p == 32) pmg_vec_body<float>(o, 1);
+}
+
+// a = 0 on n entries of the active precision.
+__global__ void __launch_bounds__(NTV) k_pmg_clear(void *a64, void *a32, int64_t n, const St *st, int prec) {
+    const int p = pmg_prec(st, prec);
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+        if (p == 64) ((double *)a64)[i] = 0.0;
+        else if (p == 32) ((float *)a32)[i] = 0.0f;
+    }
+}
+
+// out += A u on one level: one work-group (one wave) per element, atomic
+// assembly into out (cleared by the launch before).
+template <int N>
+__global__ void __launch_bounds__((N + 1) * (N + 1))
+    k_pmg_ax(HexView h, const void *u64, const void *u32, void *o64, void *o32, const St *st, int prec) {
+    const int p = pmg_prec(st, prec);
+    if (p == 0) return;   // uniform over the work-group
+    __shared__ double raw[(sizeof(HexLds<N, double>) + sizeof(double) - 1) / sizeof(double)];
+    int ex, ey, ez;
+    hex_element(h, ex, ey, ez);
+    if (p == 64) {
+        HexLds<N, double> &L = *reinterpret_cast<HexLds<N, double> *>(raw);
+        const double *u = (const double *)u64;
+        double *o = (double *)o64;
+        hex_wave_apply<N, double, false>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return u[dof]; },
+                                         [&](int, int64_t dof, double a, double) { unsafeAtomicAdd(o + dof, a); });
+    } else {
+        HexLds<N, float> &L = *reinterpret_cast<HexLds<N, float> *>(raw);
+        const float *u = (const float *)u32;
+        float *o = (float *)o32;
+        hex_wave_apply<N, float, false>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return u[dof]; },
+                                        [&](int, int64_t dof, float a, float) { unsafeAtomicAdd(o + dof, a); });
+    }
+}
+
+constexpr int NTX = 64;   // threads of the transfer kernels (one work-group per element)
+
+// Contraction of one direction of an element's tensor: dst[o][c][i] =
+// sum_m J(m, c) src[o][m][i] (TRANS: J(m, c) = J[m][c], the restriction;
+// else J(m, c) = J[c][m], the interpolation), for `outer` x `cm` x `inner`
+// outputs, src `outer` x `sm` x `inner`.
+template <typename T, bool TRANS>
+__device__ __forceinline__ void pmg_contract(const double *J, int jc, const T *src, T *dst, int outer, int sm,
+                                             int cm, int inner) {
+    const int total = outer * cm * inner;
+    for (int t = threadIdx.x; t < total; t += NTX) {
+        const int i = t % inner, c = (t / inner) % cm, o = t / (inner * cm);
+        T acc = 0;
+        for (int m = 0; m < sm; ++m) {
+            const T w = TRANS ? (T)J[m * jc + c] : (T)J[c * jc + m];
+            acc = acc + w * src[(o * sm + m) * inner + i];
+        }
+        dst[(o * cm + c) * inner + i] = acc;
+    }
+}
+
+// fc += P^T (f - ax) for this work-group's element.  J: (NF+1) x (NC+1)
+// row-major, J[a][b] = l_b(x_a).
+template <int NF, int NC, typename T>
+__device__ __forceinline__ void pmg_restrict_body(const HexView &hf, const HexView &hc, const double *J,
+                                                  const T *f, const T *ax, T *fc) {
+    constexpr int F1 = NF + 1, C1 = NC + 1;
+    __shared__ T U[F1 * F1 * F1], T1[F1 * F1 * C1], T2[F1 * C1 * C1];
+    int ex, ey, ez;
+    hex_element(hf, ex, ey, ez);
+    for (int t = threadIdx.x; t < F1 * F1 * F1; t += NTX) {
+        const int i = t % F1, j = (t / F1) % F1, k = t / (F1 * F1);
+        const int64_t dof = hex_dof<NF>(hf, ex * NF + i, ey * NF + j, ez * NF + k);
+        T v = 0;
+        if (dof >= 0) {
+            // a node on an element face, edge or corner off the boundary is
+            // shared by 2, 4 or 8 elements
+            const int mult = ((i == 0 || i == NF) ? 2 : 1) * ((j == 0 || j == NF) ? 2 : 1) * ((k == 0 || k == NF) ? 2 : 1);
+            v = (f[dof] - ax[dof]) / (T)mult;
+        }
+        U[t] = v;
+    }
+    __syncthreads();
+    pmg_contract<T, true>(J, C1, U, T1, F1 * F1, F1, C1, 1);      // i -> c
+    __syncthreads();
+    pmg_contract<T, true>(J, C1, T1, T2, F1, F1, C1, C1);         // j -> b
+    __syncthreads();
+    for (int t = threadIdx.x; t < C1 * C1 * C1; t += NTX) {       // k -> a
+        const int c = t % C1, b = (t / C1) % C1, a = t / (C1 * C1);
+        T acc = 0;
+        for (int k = 0; k < F1; ++k) acc = acc + (T)J[k * C1 + a] * T2[(k * C1 + b) * C1 + c];
+        const int64_t cd = hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a);
+        if (cd >= 0) unsafeAtomicAdd(fc + cd, acc);
+    }
+}
+
+template <int NF, int NC>
+__global__ void __launch_bounds__(NTX) k_pmg_restrict(HexView hf, HexView hc, const double *J, const void *f64,
+                                                      const void *f32, const void *ax64, const void *ax32,
+                                                      void *fc64, void *fc32, const St *st, int prec) {
+    const int p = pmg_prec(st, prec);
+    if (p == 64) pmg_restrict_body<NF, NC, double>(hf, hc, J, (const double *)f64, (const double *)ax64, (double *)fc64);
+    else if (p == 32) pmg_restrict_body<NF, NC, float>(hf, hc, J, (const float *)f32, (const float *)ax32, (float *)fc32);
+}
+
+// x += P xc at the fine nodes this element owns; ax = 0 there (the product
+// that follows sums into it).
+template <int NF, int NC, typename T>
+__device__ __forceinline__ void pmg_prolong_body(const HexView &hf, const HexView &hc, const double *J,
+                                                 const T *xc, T *x, T *ax) {
+    constexpr int F1 = NF + 1, C1 = NC + 1;
+    __shared__ T Uc[C1 * C1 * C1], V1[C1 * C1 * F1], V2[C1 * F1 * F1];
+    int ex, ey, ez;
+    hex_element(hf, ex, ey, ez);
+    for (int t = threadIdx.x; t < C1 * C1 * C1; t += NTX) {
+        const int c = t % C1, b = (t / C1) % C1, a = t / (C1 * C1);
+        const int64_t cd = hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a);
+        Uc[t] = (cd >= 0) ? xc[cd] : (T)0;
+    }
+    __syncthreads();
+    pmg_contract<T, false>(J, C1, Uc, V1, C1 * C1, C1, F1, 1);   // c -> i
+    __syncthreads();
+    pmg_contract<T, false>(J, C1, V1, V2, C1, C1, F1, F1);       // b -> j
+    __syncthreads();
+    for (int t = threadIdx.x; t < F1 * F1 * F1; t += NTX) {      // a -> k
+        const int i = t % F1, j = (t / F1) % F1, k = t / (F1 * F1);
+        if (!hex_owner<NF>(hf, ex, ey, ez, i, j, k)) continue;
+        const int64_t dof = hex_dof<NF>(hf, ex * NF + i, ey * NF + j, ez * NF + k);
+        if (dof < 0) continue;
+        T acc = 0;
+        for (int a = 0; a < C1; ++a) acc = acc + (T)J[k * C1 + a] * V2[(a * F1 + j) * F1 + i];
+        x[dof] = x[dof] + acc;
+        ax[dof] = (T)0;
+    }
+}
+
+template <int NF, int NC>
+__global__ void __launch_bounds__(NTX) k_pmg_prolong(HexView hf, HexView hc, const double *J, const void *xc64,
+                                                     const void *xc32, void *x64, void *x32, void *ax64, void *ax32,
+                                                     const St *st, int prec) {
+    const int p = pmg_prec(st, prec);
+    if (p == 64) pmg_prolong_body<NF, NC, double>(hf, hc, J, (const double *)xc64, (double *)x64, (double *)ax64);
+    else if (p == 32) pmg_prolong_body<NF, NC, float>(hf, hc, J, (const float *)xc32, (float *)x32, (float *)ax32);
+}
+
+// Standalone entry and exit: f = fl_prec(r); z = x (FP64).
+__global__ void __launch_bounds__(NTV) k_pmg_in(const double *r, void *f64, void *f32, int64_t n, int prec) {
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+        if (prec == 64) ((double *)f64)[i] = r[i];
+        else ((float *)f32)[i] = (float)r[i];
+    }
+}
+__global__ void __launch_bounds__(NTV) k_pmg_out(const void *x64, const void *x32, double *z, int64_t n, int prec) {
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+        z[i] = (prec == 64) ? ((const double *)x64)[i] : (double)((const float *)x32)[i];
+}
+
+// dinv = 1 / diag (both precisions); err |= 1 where diag <= 0 or is not finite.
+__global__ void __launch_bounds__(NTV) k_pmg_dinv(const double *diag, double *d64, float *d32, int64_t n, int *err) {
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+        const double d = diag[i];
+        if (!(d > 0.0) || !isfinite(d)) atomicOr(err, 1);
+        const double v = 1.0 / d;
+        d64[i] = v;
+        d32[i] = (float)v;
+    }
+}
+
+// Power iteration for rho = lambda_max(D^-1 A) (FP64).  Start vector: a
+// counter-based hash of the index mapped to [0.5, 1.5).
+__global__ void __launch_bounds__(NTV) k_pmg_start(double *v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+        uint64_t z = (uint64_t)i + 0x9E3779B97F4A7C15ull;   // splitmix64 finaliser
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        v[i] = 0.5 + (double)(z >> 11) * 0x1.0p-53;
+    }
+}
+
+// With ax = A v: part[2 b] = sum v ax, part[2 b + 1] = sum v^2 / dinv over
+// this work-group's entries (v^T A v and v^T D v: their ratio is the
+// Rayleigh quotient of D^-1 A in the D inner product); v = scale D^-1 ax;
+// ax = 0.
+__global__ void __launch_bounds__(NTV) k_pmg_power(double *v, double *ax, const double *dinv, int64_t n,
+                                                   double scale, double *part) {
+    __shared__ double sh[2][NTV];
+    double num = 0.0, den = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+        const double vi = v[i], ai = ax[i];
+        num += vi * ai;
+        den += vi * vi / dinv[i];
+        v[i] = scale * (dinv[i] * ai);
+        ax[i] = 0.0;
+    }
+    sh[0][threadIdx.x] = num;
+    sh[1][threadIdx.x] = den;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int t = 0; t < NTV; ++t) {
+            a += sh[0][t];
+            b += sh[1][t];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// part[b] = max |x| over this work-group's entries (FP64).
+__global__ void __launch_bounds__(NTV) k_pmg_maxabs(const double *x, int64_t n, double *part) {
+    __shared__ double sh[NTV];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+        m = fmax(m, fabs(x[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < NTV; ++k) t = fmax(t, sh[k]);
+        part[blockIdx.x] = t;
+    }
+}
+
+}  // namespace amp

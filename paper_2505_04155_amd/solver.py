@@ -119,6 +119,50 @@ class Preconditioner:
         self.A = A
         self.kind = kind
 
+    @classmethod
+    def pmg(cls, A: Matrix, orders=(7, 3, 1), degree: int = 2, coarse_degree: int = 8, lo_ratio: float = 0.1,
+            hi_margin: float = 1.1, coarse_lo_ratio: float = 0.01, rho=None, power_iters: int = 40):
+        """The p-multigrid V-cycle over the polynomial orders ``orders`` for
+        a matrix-free handle (Matrix.from_hexop): Chebyshev-Jacobi smoothing
+        of degree ``degree`` on [lo_ratio rho, hi_margin rho], a degree
+        ``coarse_degree`` polynomial on the lowest order.  ``rho``: lambda_max
+        of D^-1 A per level (None or <= 0: estimated by the power
+        iteration)."""
+        L = B.load()
+        p = B.PmgParams()
+        L.amp_pmg_params_default(ctypes.byref(p))
+        p.levels = len(orders)
+        for i, N in enumerate(orders):
+            p.orders[i] = int(N)
+        p.degree, p.coarse_degree = int(degree), int(coarse_degree)
+        p.lo_ratio, p.hi_margin, p.coarse_lo_ratio = float(lo_ratio), float(hi_margin), float(coarse_lo_ratio)
+        for i in range(len(orders)):
+            p.rho[i] = float(rho[i]) if rho is not None else 0.0
+        p.power_iters = int(power_iters)
+        h = ctypes.c_void_p()
+        B.check(L.amp_precond_create_pmg(A.handle, ctypes.byref(p), _stream(), ctypes.byref(h)),
+                "amp_precond_create_pmg")
+        self = cls.__new__(cls)
+        self._h = h
+        self.A = A
+        self.kind = "pmg"
+        return self
+
+    def pmg_info(self):
+        """{"rho", "gain", "n", "orders", "bytes"} of a p-multigrid preconditioner."""
+        st = B.PmgStats()
+        B.check(B.load().amp_pmg_info(self._h, ctypes.byref(st)), "amp_pmg_info")
+        L = st.params.levels
+        return {"rho": [st.params.rho[i] for i in range(L)], "gain": st.gain, "n": [st.n[i] for i in range(L)],
+                "orders": [st.params.orders[i] for i in range(L)], "bytes": st.bytes}
+
+    def pmg_apply(self, r: torch.Tensor, prec: int = 64):
+        """z = V(r): one cycle in FP64 (prec 64) or FP32 (prec 32); r and z FP64."""
+        _need(r, torch.float64, self.A.n, "r")
+        z = torch.empty_like(r)
+        B.check(B.load().amp_pmg_apply(self._h, _ptr(r), _ptr(z), int(prec), _stream()), "amp_pmg_apply")
+        return z
+
     @property
     def handle(self):
         return self._h

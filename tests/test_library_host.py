@@ -78,7 +78,8 @@ def test_option_validation():
 def test_ctypes_structs_match_the_header(tmp_path):
     # the binding's struct mirrors must have the C compiler's sizes and offsets
     structs = {"amp_csr": B.Csr, "amp_options": B.Options, "amp_result": B.Result,
-               "amp_matrix_stats": B.MatrixStats, "amp_matrix_tuning": B.MatrixTuning}
+               "amp_matrix_stats": B.MatrixStats, "amp_matrix_tuning": B.MatrixTuning,
+               "amp_pmg_params": B.PmgParams, "amp_pmg_stats": B.PmgStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "amp_pcg.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -152,3 +153,17 @@ def test_tune_lanes_rejects_bad_candidates():
             B.AMP_ERR_ARG
     assert best.value == -7
 
+
+
+def test_pmg_defaults_and_null_arguments():
+    L = B.load()
+    p = B.PmgParams()
+    L.amp_pmg_params_default(ctypes.byref(p))
+    assert (p.levels, list(p.orders)[:3], p.degree, p.coarse_degree, p.power_iters) == (3, [7, 3, 1], 2, 8, 40)
+    assert (p.lo_ratio, p.hi_margin, p.coarse_lo_ratio) == (0.1, 1.1, 0.01)
+    assert list(p.rho) == [0.0] * 4
+    h = ctypes.c_void_p()
+    assert L.amp_precond_create_pmg(None, ctypes.byref(p), None, ctypes.byref(h)) == B.AMP_ERR_ARG
+    assert L.amp_pmg_apply(None, None, None, 64, None) == B.AMP_ERR_ARG
+    st = B.PmgStats()
+    assert L.amp_pmg_info(None, ctypes.byref(st)) == B.AMP_ERR_ARG

@@ -330,6 +330,21 @@ def hex_vertices(E, perturb: float = 0.2, seed: int = 0) -> np.ndarray:
     return V.reshape(-1, 3)
 
 
+def pmg_poisson_rhs(E, N: int = 7) -> np.ndarray:
+    """Right-hand side of the Poisson problem of Ex. linear conv2 on the
+    interior nodes of the order-N grid of an E box mesh of [-0.5, 0.5]^3:
+    f(x, y, z) = 1 + 3 pi^2 sin(pi x) sin(pi y) sin(pi z) sampled at the
+    evenly spaced positions of the unperturbed grid, times the mean volume
+    per node (1 / (N^3 Ex Ey Ez)), in grid order (x fastest).  An input of the
+    problem's shape and smoothness, not its exact load vector."""
+    Ex, Ey, Ez = E
+    ax = [(-0.5 + np.arange(1, N * m) / (N * m)) for m in (Ex, Ey, Ez)]
+    s = [np.sin(np.pi * a) for a in ax]
+    vol = 1.0 / (N ** 3 * Ex * Ey * Ez)
+    f = 1.0 + 3.0 * np.pi ** 2 * (s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :])
+    return (vol * f).reshape(-1)
+
+
 # ---------------------------------------------------------------------------
 # the paper's spectrum-prescribed examples (Section 2 and Section 5)
 # ---------------------------------------------------------------------------
