@@ -286,6 +286,7 @@ struct PmgData {
     float *ones32 = nullptr;
     double *part = nullptr;        // 2 kPmgPartMax partials
     double gain = 0.0;
+    int hp = 0;                    // precision of the cycles being enqueued when the host knows it, else 0
 };
 
 static void pmg_free(PmgData *P) {
@@ -303,13 +304,25 @@ static unsigned pmg_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kPmgPartMax, (n + NTV - 1) / NTV));
 }
 
-static void pmg_product(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec) {
+// The product of one level: the packed element kernel of the cycle's
+// precision (hp: 64 or 32 when the host knows it; 0: both variants are
+// launched and the one that does not match the state returns at once).
+template <int N>
+static void pmg_product_n(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec,
+                          int hp) {
+    constexpr int S = (NTA / WAVE) * (WAVE / ((N + 1) * (N + 1)));
+    const int64_t E = (int64_t)L.H->ex * L.H->ey * L.H->ez;
+    const unsigned g = (unsigned)((E + S - 1) / S);
     const HexView hv = hex_view(L.H);
-    const unsigned E = (unsigned)((int64_t)L.H->ex * L.H->ey * L.H->ez);
-    const unsigned nt = (unsigned)((L.N + 1) * (L.N + 1));
-    if (L.N == 7) k_pmg_ax<7><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
-    else if (L.N == 3) k_pmg_ax<3><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
-    else k_pmg_ax<1><<<E, nt, 0, st>>>(hv, u[0], u[1], o[0], o[1], s, prec);
+    if (hp != 32) k_pmg_ax_packed<N, 64><<<g, NTA, 0, st>>>(hv, E, u[0], o[0], s, prec);
+    if (hp != 64) k_pmg_ax_packed<N, 32><<<g, NTA, 0, st>>>(hv, E, u[1], o[1], s, prec);
+}
+
+static void pmg_product(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec,
+                        int hp) {
+    if (L.N == 7) pmg_product_n<7>(L, u, o, st, s, prec, hp);
+    else if (L.N == 3) pmg_product_n<3>(L, u, o, st, s, prec, hp);
+    else pmg_product_n<1>(L, u, o, st, s, prec, hp);
 }
 
 static PmgVecOp pmg_op(const PmgLvl &L) {
@@ -323,7 +336,7 @@ static PmgVecOp pmg_op(const PmgLvl &L) {
 }
 
 // x = S f (post: x += S (f - A x), with A x in ax on entry).
-static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int prec) {
+static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int prec, int hp) {
     const int m = L.deg;
     const unsigned g = pmg_grid(L.n);
     PmgVecOp o = pmg_op(L);
@@ -338,7 +351,7 @@ static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int pr
     }
     k_pmg_vec<<<g, NTV, 0, st>>>(o, s, prec);
     for (int k = 1; k < m; ++k) {
-        pmg_product(L, L.y[(k - 1) % 2], L.ax, st, s, prec);
+        pmg_product(L, L.y[(k - 1) % 2], L.ax, st, s, prec, hp);
         PmgVecOp q = pmg_op(L);
         q.c1 = L.c1[k - 1];
         q.c2 = L.c2[k - 1];
@@ -377,16 +390,16 @@ static void pmg_transfer_any(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t s
 // null with prec = 64 / 32.
 static void pmg_cycle(PmgData &P, int l, hipStream_t st, const St *s, int prec) {
     PmgLvl &L = P.lv[l];
-    pmg_smooth(L, false, st, s, prec);
+    pmg_smooth(L, false, st, s, prec, P.hp);
     if (l == P.L - 1) return;
     PmgLvl &C = P.lv[l + 1];
-    pmg_product(L, L.x, L.ax, st, s, prec);
+    pmg_product(L, L.x, L.ax, st, s, prec, P.hp);
     k_pmg_clear<<<pmg_grid(C.n), NTV, 0, st>>>(C.f[0], C.f[1], C.n, s, prec);
     pmg_transfer_any(L, C, true, st, s, prec);
     pmg_cycle(P, l + 1, st, s, prec);
     pmg_transfer_any(L, C, false, st, s, prec);
-    pmg_product(L, L.x, L.ax, st, s, prec);
-    pmg_smooth(L, true, st, s, prec);
+    pmg_product(L, L.x, L.ax, st, s, prec, P.hp);
+    pmg_smooth(L, true, st, s, prec, P.hp);
 }
 
 // Work-group counts: enough for every unit of work, at most GMAX, and a
@@ -1453,6 +1466,7 @@ static Cheb pmg_cheb(const PmgData &P, int64_t np, bool exit) {
 static void enqueue_pmg(Driver &d, St *in, St *out) {
     PmgData &P = *d.M->pmg;
     St *pre = &d.sb[ST_PREI];
+    P.hp = (d.uzf == 64) ? 64 : (d.uzf == 16 || d.uzf == 32) ? 32 : 0;   // u_z fixed: one product variant
     k_cheb_init<<<d.gs, NT, 0, d.st>>>(d.cfg, d.B, pmg_cheb(P, d.A->np, false), 0, in, pre, d.S);
     pmg_cycle(P, 0, d.st, pre, 0);
     k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, pmg_cheb(P, d.A->np, true), pre, out);
@@ -3075,7 +3089,7 @@ static amp_status pmg_estimate_rho(PmgData &P, int l, hipStream_t st, double *ou
     k_pmg_start<<<g, NTV, 0, st>>>(v, L.n);
     double R = 0.0, scale = 1.0;
     for (int t = 0; t < P.prm.power_iters; ++t) {
-        pmg_product(L, L.y[0], L.ax, st, nullptr, 64);
+        pmg_product(L, L.y[0], L.ax, st, nullptr, 64, 64);
         k_pmg_power<<<g, NTV, 0, st>>>(v, ax, L.dinv64, L.n, scale, P.part);
         AMP_HIP(hipGetLastError());
         double num, den;
@@ -3212,6 +3226,7 @@ extern "C" amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params 
     {
         PmgLvl &L0 = P.lv[0];
         k_pmg_in<<<pmg_grid(L0.n), NTV, 0, st>>>(P.ones64, L0.f[0], L0.f[1], L0.n, 64);
+        P.hp = 64;
         pmg_cycle(P, 0, st, nullptr, 64);
         const unsigned g = pmg_grid(L0.n);
         k_pmg_maxabs<<<g, NTV, 0, st>>>((const double *)L0.x[0], L0.n, P.part);
@@ -3254,6 +3269,7 @@ extern "C" amp_status amp_pmg_apply(amp_precond M, const double *r, double *z, i
     PmgData &P = *M->pmg;
     PmgLvl &L0 = P.lv[0];
     k_pmg_in<<<pmg_grid(L0.n), NTV, 0, st>>>(r, L0.f[0], L0.f[1], L0.n, prec);
+    P.hp = prec;
     pmg_cycle(P, 0, st, nullptr, prec);
     k_pmg_out<<<pmg_grid(L0.n), NTV, 0, st>>>(L0.x[0], L0.x[1], z, L0.n, prec);
     AMP_HIP(hipGetLastError());

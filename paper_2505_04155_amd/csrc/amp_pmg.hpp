@@ -22,6 +22,8 @@
 // the active one is touched.
 #pragma once
 
+#include <type_traits>
+
 #include "amp_hex.hpp"
 #include "amp_controller.hpp"
 
@@ -107,28 +109,128 @@ __global__ void __launch_bounds__(NTV) k_pmg_clear(void *a64, void *a32, int64_t
     }
 }
 
-// out += A u on one level: one work-group (one wave) per element, atomic
-// assembly into out (cleared by the launch before).
-template <int N>
-__global__ void __launch_bounds__((N + 1) * (N + 1))
-    k_pmg_ax(HexView h, const void *u64, const void *u32, void *o64, void *o32, const St *st, int prec) {
-    const int p = pmg_prec(st, prec);
-    if (p == 0) return;   // uniform over the work-group
-    __shared__ double raw[(sizeof(HexLds<N, double>) + sizeof(double) - 1) / sizeof(double)];
-    int ex, ey, ez;
-    hex_element(h, ex, ey, ez);
-    if (p == 64) {
-        HexLds<N, double> &L = *reinterpret_cast<HexLds<N, double> *>(raw);
-        const double *u = (const double *)u64;
-        double *o = (double *)o64;
-        hex_wave_apply<N, double, false>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return u[dof]; },
-                                         [&](int, int64_t dof, double a, double) { unsafeAtomicAdd(o + dof, a); });
-    } else {
-        HexLds<N, float> &L = *reinterpret_cast<HexLds<N, float> *>(raw);
-        const float *u = (const float *)u32;
-        float *o = (float *)o32;
-        hex_wave_apply<N, float, false>(h, true, ex, ey, ez, L, [&](int, int64_t dof) { return u[dof]; },
-                                        [&](int, int64_t dof, float a, float) { unsafeAtomicAdd(o + dof, a); });
+// out += A u on one level (atomic assembly into out, cleared by the launch
+// before), several elements per wave: lanes
+// [s NP, (s+1) NP) of a wave take element slot s (NP = (N+1)^2 lanes, one per
+// grid line (i, j) of the element, as in the solve's element kernel), four
+// waves per work-group, so the orders below 7 keep every lane busy (order 3:
+// 4 elements per wave, order 1: 16).  Instantiated per precision P: the
+// launch does nothing unless the cycle runs in P (the host launches only
+// the matching variant when the solve's u_z is fixed).  D is read from LDS.
+constexpr int NTA = 256;
+
+template <int N, int P>
+__global__ void __launch_bounds__(NTA) k_pmg_ax_packed(HexView h, int64_t E, const void *uv, void *ov, const St *st,
+                                                       int prec) {
+    typedef typename std::conditional<P == 64, double, float>::type T;
+    constexpr int N1 = N + 1, NP = N1 * N1, NN = NP * N1;
+    constexpr int EPW = WAVE / NP, S = (NTA / WAVE) * EPW;   // elements per wave, per work-group
+    if (pmg_prec(st, prec) != P) return;   // uniform over the launch
+    __shared__ T Lu[S * NN], Lfr[S * NN], Lfs[S * NN];
+    __shared__ T LD[NP];
+    const T *u = (const T *)uv;
+    T *o = (T *)ov;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int slot = (tid / WAVE) * EPW + lane / NP;
+    const int l = lane % NP;
+    const bool inwave = lane < EPW * NP;   // every lane when NP divides 64
+    const int64_t e = (int64_t)xcd_block() * S + slot;
+    const bool active = inwave && e < E;
+    const int64_t ev = active ? e : E - 1;   // a valid element for the geometry
+    const int ex = (int)(ev % h.ex), ey = (int)((ev / h.ex) % h.ey), ez = (int)(ev / ((int64_t)h.ex * h.ey));
+    const int i = l % N1, j = l / N1;
+    const double *xg = h.tab, *wg = h.tab + N1, *Dg = h.tab + 2 * N1;
+    for (int t = tid; t < NP; t += NTA) LD[t] = (T)Dg[t];
+    T* const U = Lu + slot * NN;
+    T* const FR = Lfr + slot * NN;
+    T* const FS = Lfs + slot * NN;
+    T uu[N1];
+    int32_t dof[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        dof[k] = active ? (int32_t)hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k) : -1;
+        uu[k] = (dof[k] >= 0) ? u[dof[k]] : (T)0;
+        if (inwave) U[k * NP + l] = uu[k];
+    }
+    double X[2][2][2][3];
+    hex_corners(h, ex, ey, ez, X);
+    const T r = (T)xg[i], sv = (T)xg[j];
+    const T hr[2] = {(T)0.5 * ((T)1 - r), (T)0.5 * ((T)1 + r)};
+    const T hs[2] = {(T)0.5 * ((T)1 - sv), (T)0.5 * ((T)1 + sv)};
+    // dx/dr and dx/ds are linear in t along the line, dx/dt constant
+    T Pr[2][3], Ps[2][3], Jt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            Pr[c][d] = hex_fma((T)0.5 * ((T)X[c][0][1][d] - (T)X[c][0][0][d]), hs[0],
+                               (T)0.5 * ((T)X[c][1][1][d] - (T)X[c][1][0][d]) * hs[1]);
+            Ps[c][d] = hex_fma((T)0.5 * ((T)X[c][1][0][d] - (T)X[c][0][0][d]), hr[0],
+                               (T)0.5 * ((T)X[c][1][1][d] - (T)X[c][0][1][d]) * hr[1]);
+        }
+        T jt = 0;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                jt = hex_fma((T)0.5 * ((T)X[1][b][a][d] - (T)X[0][b][a][d]), hr[a] * hs[b], jt);
+        Jt[d] = jt;
+    }
+    const T wij = (T)wg[i] * (T)wg[j];
+    __syncthreads();
+    T ft[N1], au[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            ur = hex_fma(LD[i * N1 + m], U[k * NP + j * N1 + m], ur);
+            us = hex_fma(LD[j * N1 + m], U[k * NP + m * N1 + i], us);
+            ut = hex_fma((T)Dg[k * N1 + m], uu[m], ut);
+        }
+        const T t = (T)xg[k];
+        const T ht0 = (T)0.5 * ((T)1 - t), ht1 = (T)0.5 * ((T)1 + t);
+        T J[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            J[d][0] = hex_fma(Pr[0][d], ht0, Pr[1][d] * ht1);
+            J[d][1] = hex_fma(Ps[0][d], ht0, Ps[1][d] * ht1);
+            J[d][2] = Jt[d];
+        }
+        T C[3][3];   // cofactors: J^-T = C / det
+        C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const T det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+        const T w = wij * (T)wg[k];
+        const T f = w / det;
+        const T g0 = hex_fma(C[0][0], ur, hex_fma(C[0][1], us, C[0][2] * ut));
+        const T g1 = hex_fma(C[1][0], ur, hex_fma(C[1][1], us, C[1][2] * ut));
+        const T g2 = hex_fma(C[2][0], ur, hex_fma(C[2][1], us, C[2][2] * ut));
+        if (inwave) {
+            FR[k * NP + l] = f * hex_fma(C[0][0], g0, hex_fma(C[1][0], g1, C[2][0] * g2));
+            FS[k * NP + l] = f * hex_fma(C[0][1], g0, hex_fma(C[1][1], g1, C[2][1] * g2));
+        }
+        ft[k] = f * hex_fma(C[0][2], g0, hex_fma(C[1][2], g1, C[2][2] * g2));
+        au[k] = w * det * (T)h.lam * uu[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        T a = au[k];
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            a = hex_fma(LD[m * N1 + i], FR[k * NP + j * N1 + m], a);
+            a = hex_fma(LD[m * N1 + j], FS[k * NP + m * N1 + i], a);
+            a = hex_fma((T)Dg[m * N1 + k], ft[m], a);
+        }
+        if (dof[k] >= 0) unsafeAtomicAdd(o + dof[k], a);
     }
 }
 
