@@ -118,10 +118,14 @@ __global__ void __launch_bounds__(NTV) k_pmg_clear(void *a64, void *a32, int64_t
 // launch does nothing unless the cycle runs in P (the host launches only
 // the matching variant when the solve's u_z is fixed).  D is read from LDS.
 constexpr int NTA = 256;
+// minimum waves per SIMD the product is compiled for (its VGPR budget)
+#ifndef PMG_WAVES
+#define PMG_WAVES(N, P) ((N) == 7 ? ((P) == 64 ? 2 : 4) : 4)
+#endif
 
 template <int N, int P>
-__global__ void __launch_bounds__(NTA) k_pmg_ax_packed(HexView h, int64_t E, const void *uv, void *ov, const St *st,
-                                                       int prec) {
+__global__ void __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(PMG_WAVES(N, P))))
+    k_pmg_ax_packed(HexView h, int64_t E, const void *uv, void *ov, const St *st, int prec) {
     typedef typename std::conditional<P == 64, double, float>::type T;
     constexpr int N1 = N + 1, NP = N1 * N1, NN = NP * N1;
     constexpr int EPW = WAVE / NP, S = (NTA / WAVE) * EPW;   // elements per wave, per work-group
