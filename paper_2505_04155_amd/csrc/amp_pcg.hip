@@ -309,20 +309,24 @@ static unsigned pmg_grid(int64_t n) {
 // launched and the one that does not match the state returns at once).
 template <int N>
 static void pmg_product_n(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec,
-                          int hp) {
+                          int hp, bool virt) {
     constexpr int S = (NTA / WAVE) * (WAVE / ((N + 1) * (N + 1)));
     const int64_t E = (int64_t)L.H->ex * L.H->ey * L.H->ez;
     const unsigned g = (unsigned)((E + S - 1) / S);
     const HexView hv = hex_view(L.H);
-    if (hp != 32) k_pmg_ax_packed<N, 64><<<g, NTA, 0, st>>>(hv, E, u[0], o[0], s, prec);
-    if (hp != 64) k_pmg_ax_packed<N, 32><<<g, NTA, 0, st>>>(hv, E, u[1], o[1], s, prec);
+    const void *vf[2] = {virt ? L.f[0] : nullptr, virt ? L.f[1] : nullptr};
+    const void *vd[2] = {L.dinv64, L.dinv32};
+    if (hp != 32) k_pmg_ax_packed<N, 64><<<g, NTA, 0, st>>>(hv, E, u[0], o[0], vf[0], vd[0], L.inv_theta, s, prec);
+    if (hp != 64) k_pmg_ax_packed<N, 32><<<g, NTA, 0, st>>>(hv, E, u[1], o[1], vf[1], vd[1], L.inv_theta, s, prec);
 }
 
+// virt: the input is the pre-smoother's first iterate D^-1 f / theta, formed
+// at the gather (u is not read).
 static void pmg_product(PmgLvl &L, void *const u[2], void *const o[2], hipStream_t st, const St *s, int prec,
-                        int hp) {
-    if (L.N == 7) pmg_product_n<7>(L, u, o, st, s, prec, hp);
-    else if (L.N == 3) pmg_product_n<3>(L, u, o, st, s, prec, hp);
-    else pmg_product_n<1>(L, u, o, st, s, prec, hp);
+                        int hp, bool virt = false) {
+    if (L.N == 7) pmg_product_n<7>(L, u, o, st, s, prec, hp, virt);
+    else if (L.N == 3) pmg_product_n<3>(L, u, o, st, s, prec, hp, virt);
+    else pmg_product_n<1>(L, u, o, st, s, prec, hp, virt);
 }
 
 static PmgVecOp pmg_op(const PmgLvl &L) {
@@ -335,26 +339,35 @@ static PmgVecOp pmg_op(const PmgLvl &L) {
     return o;
 }
 
-// x = S f (post: x += S (f - A x), with A x in ax on entry).
+// x = S f (post: x += S (f - A x), with A x in ax on entry).  Before
+// smoothing, degree > 1: the first iterate D^-1 f / theta is not stored; the
+// first product and the first two steps form it from f (ax is clear on
+// entry: every pass that reads it clears it).
 static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int prec, int hp) {
     const int m = L.deg;
     const unsigned g = pmg_grid(L.n);
-    PmgVecOp o = pmg_op(L);
-    o.first = 1;
-    o.a = L.inv_theta;
-    for (int p = 0; p < 2; ++p) {
-        o.rhs[p] = L.f[p];
-        if (post) o.gout[p] = L.g[p];
-        if (m > 1) o.out[p] = L.y[0][p];
-        else if (post) o.acc[p] = L.x[p];
-        else o.out[p] = L.x[p];
+    const bool virt = !post && m > 1;
+    if (!virt) {
+        PmgVecOp o = pmg_op(L);
+        o.first = 1;
+        o.a = L.inv_theta;
+        for (int p = 0; p < 2; ++p) {
+            o.rhs[p] = L.f[p];
+            if (post) o.gout[p] = L.g[p];
+            if (m > 1) o.out[p] = L.y[0][p];
+            else if (post) o.acc[p] = L.x[p];
+            else o.out[p] = L.x[p];
+        }
+        k_pmg_vec<<<g, NTV, 0, st>>>(o, s, prec);
     }
-    k_pmg_vec<<<g, NTV, 0, st>>>(o, s, prec);
     for (int k = 1; k < m; ++k) {
-        pmg_product(L, L.y[(k - 1) % 2], L.ax, st, s, prec, hp);
+        pmg_product(L, L.y[(k - 1) % 2], L.ax, st, s, prec, hp, virt && k == 1);
         PmgVecOp q = pmg_op(L);
         q.c1 = L.c1[k - 1];
         q.c2 = L.c2[k - 1];
+        q.a1 = L.inv_theta;
+        q.vcur = virt && k == 1;
+        q.vprev = virt && k == 2;
         for (int p = 0; p < 2; ++p) {
             q.rhs[p] = post ? L.g[p] : L.f[p];
             q.cur[p] = L.y[(k - 1) % 2][p];

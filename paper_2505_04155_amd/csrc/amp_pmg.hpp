@@ -49,6 +49,8 @@ __device__ __forceinline__ int pmg_prec(const St *st, int prec) {
 // otherwise x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (rhs - ax) with
 // x_{k-1} = 0 when prev is null.  The result is stored to out, or added to
 // acc.  ax is cleared after it is read (the next product sums into it).
+// vcur / vprev: x_k / x_{k-1} is the pre-smoother's first iterate
+// a1 D^-1 rhs, formed here instead of read (it is never stored).
 struct PmgVecOp {
     const void *dinv[2];
     const void *rhs[2];
@@ -59,8 +61,8 @@ struct PmgVecOp {
     void *gout[2];
     void *acc[2];
     int64_t n;
-    double a, c1, c2;
-    int first;
+    double a, c1, c2, a1;
+    int first, vcur, vprev;
 };
 
 template <typename T>
@@ -84,8 +86,9 @@ __device__ __forceinline__ void pmg_vec_body(const PmgVecOp &o, int s) {
             }
             xn = a * (dinv[i] * g);
         } else {
-            const T xk = cur[i];
-            const T xp = prev ? prev[i] : (T)0;
+            const T x1 = (o.vcur || o.vprev) ? (T)o.a1 * (dinv[i] * rhs[i]) : (T)0;
+            const T xk = o.vcur ? x1 : cur[i];
+            const T xp = o.vprev ? x1 : (prev ? prev[i] : (T)0);
             xn = (xk + c1 * (xk - xp)) + c2 * (dinv[i] * (rhs[i] - ax[i]));
         }
         if (acc) acc[i] = acc[i] + xn;
@@ -117,6 +120,8 @@ __global__ void __launch_bounds__(NTV) k_pmg_clear(void *a64, void *a32, int64_t
 // 4 elements per wave, order 1: 16).  Instantiated per precision P: the
 // launch does nothing unless the cycle runs in P (the host launches only
 // the matching variant when the solve's u_z is fixed).  D is read from LDS.
+// vf non-null: u = va D^-1 vf (vd holds D^-1), the pre-smoother's first
+// iterate formed at the gather instead of read.
 constexpr int NTA = 256;
 // minimum waves per SIMD the product is compiled for (its VGPR budget)
 #ifndef PMG_WAVES
@@ -125,7 +130,8 @@ constexpr int NTA = 256;
 
 template <int N, int P>
 __global__ void __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(PMG_WAVES(N, P))))
-    k_pmg_ax_packed(HexView h, int64_t E, const void *uv, void *ov, const St *st, int prec) {
+    k_pmg_ax_packed(HexView h, int64_t E, const void *uv, void *ov, const void *vf, const void *vd, double va,
+                    const St *st, int prec) {
     typedef typename std::conditional<P == 64, double, float>::type T;
     constexpr int N1 = N + 1, NP = N1 * N1, NN = NP * N1;
     constexpr int EPW = WAVE / NP, S = (NTA / WAVE) * EPW;   // elements per wave, per work-group
@@ -133,6 +139,7 @@ __global__ void __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(PMG_WA
     __shared__ T Lu[S * NN], Lfr[S * NN], Lfs[S * NN];
     __shared__ T LD[NP];
     const T *u = (const T *)uv;
+    const T *vfp = (const T *)vf, *vdp = (const T *)vd;
     T *o = (T *)ov;
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int slot = (tid / WAVE) * EPW + lane / NP;
@@ -153,7 +160,7 @@ __global__ void __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(PMG_WA
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
         dof[k] = active ? (int32_t)hex_dof<N>(h, ex * N + i, ey * N + j, ez * N + k) : -1;
-        uu[k] = (dof[k] >= 0) ? u[dof[k]] : (T)0;
+        uu[k] = (dof[k] < 0) ? (T)0 : vfp ? (T)va * (vdp[dof[k]] * vfp[dof[k]]) : u[dof[k]];
         if (inwave) U[k * NP + l] = uu[k];
     }
     double X[2][2][2][3];
