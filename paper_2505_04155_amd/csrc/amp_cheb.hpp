@@ -62,6 +62,7 @@ struct Cheb {
     void *dir[2][2];
     int64_t np, nslices;
     int64_t guard;           // zero margin of v and dir, in elements
+    int nt;                  // 1: B and the rows' own vectors loaded with a non-temporal hint (B exceeds kMallBytes)
     int32_t *step_iter;      // nullable: iteration each timed step launch performed (-1: passed through)
     int step_launch;         // index of this launch in step_iter
     int degree;
@@ -155,7 +156,9 @@ __global__ void __launch_bounds__(NT) k_cheb_init(Cfg c, Bufs B, Cheb P, int sta
 // One step k of the recurrence for this work-group's slices.
 // RLAST: 0 for an inner step; for the last step, the precision of r (the
 // step then forms z and the partials of rho = r^T z).
-template <int UZ, bool FIRST, int RLAST, int BS>
+// NTL: B and the row's own vector entries (read once per launch) are loaded
+// with a non-temporal hint; for a B larger than the memory-side cache.
+template <int UZ, bool FIRST, int RLAST, int BS, bool NTL>
 __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const Cheb &P, Wg wg, double c1d,
                                                double c2d, int din, double &rho, double &mz) {
     typedef typename Prec<UZ>::T TZ;
@@ -202,16 +205,16 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
         const uint32_t ru = (uint32_t)row;   // row < np <= 2^29: 32-bit byte offsets
         const CZ gi = at32(g, ru);
         const CZ xk = dfrom(gi);                           // x_k of the row
-        const CZ vi = FIRST ? gi : at32(v, ru);
+        const CZ vi = FIRST ? gi : at32t<NTL>(v, ru);
         CZ xkm1;                                           // x_{k-1} of the row
         if (FIRST) xkm1 = (CZ)0;
         else if (prev_from_v) xkm1 = vi * inv_theta;
-        else xkm1 = at32((const CZ *)xw, ru);
+        else xkm1 = at32t<NTL>((const CZ *)xw, ru);
         CZ isq_r = (CZ)0;
         double rr = 0.0;
         if (last) {
-            isq_r = at32(isq, ru);
-            rr = (double)at32(rl, ru);
+            isq_r = at32t<NTL>(isq, ru);
+            rr = (double)at32t<NTL>(rl, ru);
         }
         CZ acc = (CZ)0;
         // two chunks of slots per pass: all their value loads and gathers are
@@ -240,8 +243,8 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
                 if (full) {
 #pragma unroll
                     for (int u = 0; u < kChunk; ++u) {
-                        bv[u] = at32(bsl, (uint32_t)(lane + (j0 + u) * SLICE));
-                        bv[kChunk + u] = at32(bsl, (uint32_t)(lane + (j0 + kChunk + u) * SLICE));
+                        bv[u] = at32t<NTL>(bsl, (uint32_t)(lane + (j0 + u) * SLICE));
+                        bv[kChunk + u] = at32t<NTL>(bsl, (uint32_t)(lane + (j0 + kChunk + u) * SLICE));
                         dj[u] = at32(gb, rowg + (uint32_t)oa.o[u]);
                         dj[kChunk + u] = at32(gb, rowg + (uint32_t)ob.o[u]);
                     }
@@ -251,8 +254,8 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
 #pragma unroll
                     for (int u = 0; u < kChunk; ++u) {
                         const int ja = j0 + u < wd ? j0 + u : wd - 1, jb = j1 + u < wd ? j1 + u : wd - 1;
-                        bv[u] = at32(bsl, (uint32_t)(lane + ja * SLICE));
-                        bv[kChunk + u] = at32(bsl, (uint32_t)(lane + jb * SLICE));
+                        bv[u] = at32t<NTL>(bsl, (uint32_t)(lane + ja * SLICE));
+                        bv[kChunk + u] = at32t<NTL>(bsl, (uint32_t)(lane + jb * SLICE));
                         dj[u] = at32(gb, rowg + (uint32_t)oa.o[u]);
                         dj[kChunk + u] = at32(gb, rowg + (uint32_t)ob.o[u]);
                     }
@@ -312,7 +315,7 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
 // (the last step also carries the rho reduction and both r precisions:
 // it is compiled for 6 waves per SIMD, at most 80 VGPRs, without spills;
 // the FP64 work-vector variants for 4)
-template <int UZF, int STEP>
+template <int UZF, int STEP, bool NTL>
 __global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? (STEP >= 2 ? 6 : AMP_CHEB_WAVES) : 4)
     k_cheb_step(Bufs B, Cheb P, double c1, double c2, int din, const St *in, St *out) {
     constexpr bool FIRST = STEP == 0 || STEP == 3, LAST = STEP >= 2;
@@ -333,9 +336,9 @@ __global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? (STEP >= 2 ? 6
     double rho = 0.0, mz = 0.0;
 #define AMP_CS(UZ)                                                                                  \
     do {                                                                                            \
-        if (!LAST) cheb_step_body<UZ, FIRST, 0, NTC>(s, B, P, wg, c1, c2, din, rho, mz);            \
-        else if (s.ur == 64) cheb_step_body<UZ, FIRST, 64, NTC>(s, B, P, wg, c1, c2, din, rho, mz); \
-        else cheb_step_body<UZ, FIRST, 32, NTC>(s, B, P, wg, c1, c2, din, rho, mz);                 \
+        if (!LAST) cheb_step_body<UZ, FIRST, 0, NTC, NTL>(s, B, P, wg, c1, c2, din, rho, mz);            \
+        else if (s.ur == 64) cheb_step_body<UZ, FIRST, 64, NTC, NTL>(s, B, P, wg, c1, c2, din, rho, mz); \
+        else cheb_step_body<UZ, FIRST, 32, NTC, NTL>(s, B, P, wg, c1, c2, din, rho, mz);                 \
     } while (0)
     if constexpr (UZF == 64) AMP_CS(64);
     else if constexpr (UZF == 32) AMP_CS(32);
@@ -361,21 +364,25 @@ __global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? (STEP >= 2 ? 6
 
 typedef void (*ChebStepFn)(Bufs, Cheb, double, double, int, const St *, St *);
 
-// The step kernel for (UZF, STEP).
-inline ChebStepFn cheb_step_fn(int uzf, int step) {
-#define AMP_F(U)                                        \
+// The step kernel for (UZF, STEP, non-temporal loads).
+inline ChebStepFn cheb_step_fn(int uzf, int step, bool nt) {
+#define AMP_F(U, N)                                     \
     switch (step) {                                     \
-        case 0: return k_cheb_step<U, 0>;               \
-        case 1: return k_cheb_step<U, 1>;               \
-        case 2: return k_cheb_step<U, 2>;               \
-        default: return k_cheb_step<U, 3>;              \
+        case 0: return k_cheb_step<U, 0, N>;            \
+        case 1: return k_cheb_step<U, 1, N>;            \
+        case 2: return k_cheb_step<U, 2, N>;            \
+        default: return k_cheb_step<U, 3, N>;           \
     }
+#define AMP_FN(U)              \
+    if (nt) { AMP_F(U, true) } \
+    else { AMP_F(U, false) }
     switch (uzf) {
-        case 16: AMP_F(16)
-        case 32: AMP_F(32)
-        case 64: AMP_F(64)
-        default: AMP_F(0)
+        case 16: AMP_FN(16)
+        case 32: AMP_FN(32)
+        case 64: AMP_FN(64)
+        default: AMP_FN(0)
     }
+#undef AMP_FN
 #undef AMP_F
 }
 

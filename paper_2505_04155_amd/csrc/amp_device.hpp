@@ -110,6 +110,12 @@ struct Sell {
 };
 
 constexpr int kOffMax = 32;  // longest per-slice offset list
+// Capacity of the memory-side cache.  A matrix plane larger than this is
+// streamed from HBM every application anyway, and the Chebyshev step loads
+// it with a non-temporal hint so it does not displace the gathered vectors;
+// a smaller one stays cached between applications, which the hint would
+// prevent.
+constexpr int64_t kMallBytes = (int64_t)256 << 20;
 
 // Issue priority from a wave's progress through its work-group's range.
 // The work-groups sharing a CU start together, but the hardware favours the
@@ -131,6 +137,22 @@ __device__ __forceinline__ void progress_prio(int64_t done, int64_t span) {
 template <typename T>
 __device__ __forceinline__ T at32(const T *a, uint32_t i) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + i * (uint32_t)sizeof(T));
+}
+
+// at32 with a non-temporal hint: for data streamed once per launch (matrix
+// values, a row's own vector entries), so it does not displace the gathered
+// vectors from the caches.
+template <typename T>
+__device__ __forceinline__ T at32nt(const T *a, uint32_t i) {
+    return __builtin_nontemporal_load(reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + i * (uint32_t)sizeof(T)));
+}
+
+// at32nt when NT, else at32 (chosen at compile time: a run-time choice
+// between two loads of one address may be merged into one plain load).
+template <bool NT, typename T>
+__device__ __forceinline__ T at32t(const T *a, uint32_t i) {
+    if constexpr (NT) return at32nt(a, i);
+    else return at32(a, i);
 }
 
 // a[i] = v through a 32-bit byte offset (as at32).

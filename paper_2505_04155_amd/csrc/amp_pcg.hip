@@ -248,6 +248,7 @@ struct amp_precond_s {
         }
         P.np = A->np; P.nslices = A->nslices; P.degree = degree; P.inv_theta = inv_theta;
         P.step_iter = nullptr; P.step_launch = 0; P.guard = A->guard;
+        P.nt = (A->slots * (int64_t)sizeof(half_t) > kMallBytes) ? 1 : 0;
         for (int i = 0; i < kChebMax; ++i) { P.c1[i] = c1[i]; P.c2[i] = c2[i]; }
         return P;
     }
@@ -1441,7 +1442,7 @@ static void enqueue_chebyshev(Driver &d, int standalone, St *in, St *out) {
         St *si = (k == 0) ? &sb[ST_PREI] : &sb[(k - 1) % 2 ? ST_CH1 : ST_CH0];
         St *so = (k == m - 2) ? out : &sb[k % 2 ? ST_CH1 : ST_CH0];
         const int step = (k == 0 && k == m - 2) ? 3 : (k == m - 2) ? 2 : (k == 0) ? 0 : 1;
-        const ChebStepFn fn = cheb_step_fn(d.uzf, step);
+        const ChebStepFn fn = cheb_step_fn(d.uzf, step, P.nt != 0);
         Work &w = d.A->w;
         if (d.timing && d.claunches < w.ccap) {
             Cheb Pt = P;
