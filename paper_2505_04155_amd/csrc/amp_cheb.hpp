@@ -312,11 +312,12 @@ __device__ __forceinline__ void cheb_step_body(const St &s, const Bufs &B, const
 // come from a non-finite residual (the selector's comparisons fail): it
 // ends the solve as a breakdown.
 // c1, c2: the recurrence coefficients of step k.
-// (the last step also carries the rho reduction and both r precisions:
-// it is compiled for 6 waves per SIMD, at most 80 VGPRs, without spills;
-// the FP64 work-vector variants for 4)
+// (every FP32 work-vector variant is compiled for 8 waves per SIMD, at
+// most 64 VGPRs; the last step, which also carries the rho reduction and
+// both r precisions, then spills a few registers and is still faster than
+// at 6 waves without spills; the FP64 work-vector variants for 4)
 template <int UZF, int STEP, bool NTL>
-__global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? (STEP >= 2 ? 6 : AMP_CHEB_WAVES) : 4)
+__global__ void __launch_bounds__(NTC, (UZF == 16 || UZF == 32) ? AMP_CHEB_WAVES : 4)
     k_cheb_step(Bufs B, Cheb P, double c1, double c2, int din, const St *in, St *out) {
     constexpr bool FIRST = STEP == 0 || STEP == 3, LAST = STEP >= 2;
     __shared__ St s;
