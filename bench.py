@@ -417,7 +417,7 @@ def pmg_measurement(amp, torch, np, P, dev, E=(30, 30, 30), order=7, reps=10):
     runs, sol = {}, {}
     for name, preset, kw in (("pcg64", "pcg64", {}), ("amp16_linear", "amp16", {"eta": "linear"}),
                              ("amp16", "amp16", {}), ("amp16_r64", "amp16", {"eta": "fixed64"}),
-                             ("amp32", "amp16", {"u0": 32})):
+                             ("amp32", "amp16", {"u0": 32}), ("amp64", "amp64", {})):
         amp.solve(M, pc, b, tol=1e-10, maxit=2000, preset=preset, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -430,7 +430,7 @@ def pmg_measurement(amp, torch, np, P, dev, E=(30, 30, 30), order=7, reps=10):
         log(f"bench: pMG solve {name}: {ms:.1f} ms, {info['iters']} iterations, u_z FP16 from {info['k_z16']}, "
             f"u_r FP32 from {info['k_r32']}")
     xr = sol["pcg64"]
-    for name in ("amp16_linear", "amp16", "amp16_r64", "amp32"):
+    for name in ("amp16_linear", "amp16", "amp16_r64", "amp32", "amp64"):
         runs[name]["rel_diff_vs_pcg64"] = float(torch.linalg.norm(sol[name] - xr) / torch.linalg.norm(xr))
         runs[f"speedup_{name}_vs_fp64_pcg"] = round(runs["pcg64"]["ms"] / runs[name]["ms"], 4)
     pj = amp.Preconditioner(M, "jacobi")

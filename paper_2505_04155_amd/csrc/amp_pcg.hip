@@ -3188,6 +3188,8 @@ extern "C" amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params 
             if ((s = amp_hexop_create(H0->ex, H0->ey, H0->ez, L.N, H0->verts, H0->lam, stream, &L.H)) != AMP_OK)
                 return cleanup(s);
             L.own = true;
+            const int64_t E = (int64_t)H0->ex * H0->ey * H0->ez;
+            bytes += 8 * (3 * (int64_t)(H0->ex + 1) * (H0->ey + 1) * (H0->ez + 1) + 3 * E);   // vertices, partials
         }
         L.n = L.H->n;
         L.len = (l == 0) ? A->np : L.n;
@@ -3220,6 +3222,7 @@ extern "C" amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params 
             std::vector<double> J;
             pmg_interp(P.lv[l - 1].N, L.N, J);
             if ((s = dalloc(&P.lv[l - 1].J, J.size())) != AMP_OK) return cleanup(s);
+            bytes += (int64_t)J.size() * 8;
             if (hipMemcpy(P.lv[l - 1].J, J.data(), J.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
                 return cleanup(fail(AMP_ERR_HIP, "amp_precond_create_pmg: copying the interpolation table"));
         }
