@@ -382,21 +382,31 @@ static void pmg_smooth(PmgLvl &L, bool post, hipStream_t st, const St *s, int pr
 }
 
 template <int NF, int NC>
-static void pmg_transfer(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec) {
-    const unsigned E = (unsigned)((int64_t)F.H->ex * F.H->ey * F.H->ez);
+static void pmg_transfer(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec, int hp) {
+    const int64_t E = (int64_t)F.H->ex * F.H->ey * F.H->ez;
+    const unsigned g = (unsigned)((E + XW - 1) / XW);
     const HexView hf = hex_view(F.H), hc = hex_view(C.H);
-    if (restrict_)
-        k_pmg_restrict<NF, NC><<<E, NTX, 0, st>>>(hf, hc, F.J, F.f[0], F.f[1], F.ax[0], F.ax[1], C.f[0], C.f[1], s,
-                                                   prec);
-    else
-        k_pmg_prolong<NF, NC><<<E, NTX, 0, st>>>(hf, hc, F.J, C.x[0], C.x[1], F.x[0], F.x[1], F.ax[0], F.ax[1], s,
-                                                  prec);
+    for (int P = 0; P < 2; ++P) {   // 0: FP64, 1: FP32
+        if ((P == 0 && hp == 32) || (P == 1 && hp == 64)) continue;
+        if (restrict_) {
+            if (P == 0)
+                k_pmg_restrict<NF, NC, 64><<<g, NTX, 0, st>>>(hf, hc, F.J, E, F.f[0], F.ax[0], C.f[0], s, prec);
+            else
+                k_pmg_restrict<NF, NC, 32><<<g, NTX, 0, st>>>(hf, hc, F.J, E, F.f[1], F.ax[1], C.f[1], s, prec);
+        } else {
+            if (P == 0)
+                k_pmg_prolong<NF, NC, 64><<<g, NTX, 0, st>>>(hf, hc, F.J, E, C.x[0], F.x[0], F.ax[0], s, prec);
+            else
+                k_pmg_prolong<NF, NC, 32><<<g, NTX, 0, st>>>(hf, hc, F.J, E, C.x[1], F.x[1], F.ax[1], s, prec);
+        }
+    }
 }
 
-static void pmg_transfer_any(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec) {
-    if (F.N == 7 && C.N == 3) pmg_transfer<7, 3>(F, C, restrict_, st, s, prec);
-    else if (F.N == 7) pmg_transfer<7, 1>(F, C, restrict_, st, s, prec);
-    else pmg_transfer<3, 1>(F, C, restrict_, st, s, prec);
+static void pmg_transfer_any(PmgLvl &F, PmgLvl &C, bool restrict_, hipStream_t st, const St *s, int prec,
+                             int hp) {
+    if (F.N == 7 && C.N == 3) pmg_transfer<7, 3>(F, C, restrict_, st, s, prec, hp);
+    else if (F.N == 7) pmg_transfer<7, 1>(F, C, restrict_, st, s, prec, hp);
+    else pmg_transfer<3, 1>(F, C, restrict_, st, s, prec, hp);
 }
 
 // x_l = V_l(f_l): the cycle's kernels in stream order.  s: the solve's state
@@ -409,9 +419,9 @@ static void pmg_cycle(PmgData &P, int l, hipStream_t st, const St *s, int prec) 
     PmgLvl &C = P.lv[l + 1];
     pmg_product(L, L.x, L.ax, st, s, prec, P.hp);
     k_pmg_clear<<<pmg_grid(C.n), NTV, 0, st>>>(C.f[0], C.f[1], C.n, s, prec);
-    pmg_transfer_any(L, C, true, st, s, prec);
+    pmg_transfer_any(L, C, true, st, s, prec, P.hp);
     pmg_cycle(P, l + 1, st, s, prec);
-    pmg_transfer_any(L, C, false, st, s, prec);
+    pmg_transfer_any(L, C, false, st, s, prec, P.hp);
     pmg_product(L, L.x, L.ax, st, s, prec, P.hp);
     pmg_smooth(L, true, st, s, prec, P.hp);
 }

@@ -245,17 +245,21 @@ __global__ void __launch_bounds__(NTA) __attribute__((amdgpu_waves_per_eu(PMG_WA
     }
 }
 
-constexpr int NTX = 64;   // threads of the transfer kernels (one work-group per element)
+// Transfer kernels: one wave per element, XW elements per work-group;
+// instantiated per precision P like the products (a launch whose P is not
+// the cycle's returns at once).
+constexpr int XW = 4;
+constexpr int NTX = XW * WAVE;
 
-// Contraction of one direction of an element's tensor: dst[o][c][i] =
-// sum_m J(m, c) src[o][m][i] (TRANS: J(m, c) = J[m][c], the restriction;
-// else J(m, c) = J[c][m], the interpolation), for `outer` x `cm` x `inner`
-// outputs, src `outer` x `sm` x `inner`.
+// Contraction of one direction of an element's tensor by the element's
+// wave: dst[o][c][i] = sum_m J(m, c) src[o][m][i] (TRANS: J(m, c) = J[m][c],
+// the restriction; else J(m, c) = J[c][m], the interpolation), for `outer`
+// x `cm` x `inner` outputs, src `outer` x `sm` x `inner`.
 template <typename T, bool TRANS>
 __device__ __forceinline__ void pmg_contract(const double *J, int jc, const T *src, T *dst, int outer, int sm,
-                                             int cm, int inner) {
+                                             int cm, int inner, int lane) {
     const int total = outer * cm * inner;
-    for (int t = threadIdx.x; t < total; t += NTX) {
+    for (int t = lane; t < total; t += WAVE) {
         const int i = t % inner, c = (t / inner) % cm, o = t / (inner * cm);
         T acc = 0;
         for (int m = 0; m < sm; ++m) {
@@ -266,18 +270,35 @@ __device__ __forceinline__ void pmg_contract(const double *J, int jc, const T *s
     }
 }
 
-// fc += P^T (f - ax) for this work-group's element.  J: (NF+1) x (NC+1)
-// row-major, J[a][b] = l_b(x_a).
-template <int NF, int NC, typename T>
-__device__ __forceinline__ void pmg_restrict_body(const HexView &hf, const HexView &hc, const double *J,
-                                                  const T *f, const T *ax, T *fc) {
-    constexpr int F1 = NF + 1, C1 = NC + 1;
-    __shared__ T U[F1 * F1 * F1], T1[F1 * F1 * C1], T2[F1 * C1 * C1];
+// The element of this wave (e = work-group * XW + wave; valid when e < E).
+__device__ __forceinline__ bool pmg_xfer_element(const HexView &h, int64_t E, int &ex, int &ey, int &ez) {
+    const int64_t e = (int64_t)xcd_block() * XW + threadIdx.x / WAVE;
+    const int64_t ev = e < E ? e : E - 1;
+    ex = (int)(ev % h.ex);
+    ey = (int)((ev / h.ex) % h.ey);
+    ez = (int)(ev / ((int64_t)h.ex * h.ey));
+    return e < E;
+}
+
+// fc += P^T (f - ax) for the waves' elements.  J: (NF+1) x (NC+1) row-major,
+// J[a][b] = l_b(x_a).
+template <int NF, int NC, int P>
+__global__ void __launch_bounds__(NTX) k_pmg_restrict(HexView hf, HexView hc, const double *J, int64_t E,
+                                                      const void *fv, const void *axv, void *fcv, const St *st,
+                                                      int prec) {
+    typedef typename std::conditional<P == 64, double, float>::type T;
+    constexpr int F1 = NF + 1, C1 = NC + 1, FN = F1 * F1 * F1;
+    if (pmg_prec(st, prec) != P) return;   // uniform over the launch
+    __shared__ T Us[XW * FN], T1s[XW * F1 * F1 * C1], T2s[XW * F1 * C1 * C1];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    T *U = Us + w * FN, *T1 = T1s + w * F1 * F1 * C1, *T2 = T2s + w * F1 * C1 * C1;
+    const T *f = (const T *)fv, *ax = (const T *)axv;
+    T *fc = (T *)fcv;
     int ex, ey, ez;
-    hex_element(hf, ex, ey, ez);
-    for (int t = threadIdx.x; t < F1 * F1 * F1; t += NTX) {
+    const bool valid = pmg_xfer_element(hf, E, ex, ey, ez);
+    for (int t = lane; t < FN; t += WAVE) {
         const int i = t % F1, j = (t / F1) % F1, k = t / (F1 * F1);
-        const int64_t dof = hex_dof<NF>(hf, ex * NF + i, ey * NF + j, ez * NF + k);
+        const int64_t dof = valid ? hex_dof<NF>(hf, ex * NF + i, ey * NF + j, ez * NF + k) : -1;
         T v = 0;
         if (dof >= 0) {
             // a node on an element face, edge or corner off the boundary is
@@ -288,48 +309,46 @@ __device__ __forceinline__ void pmg_restrict_body(const HexView &hf, const HexVi
         U[t] = v;
     }
     __syncthreads();
-    pmg_contract<T, true>(J, C1, U, T1, F1 * F1, F1, C1, 1);      // i -> c
+    pmg_contract<T, true>(J, C1, U, T1, F1 * F1, F1, C1, 1, lane);      // i -> c
     __syncthreads();
-    pmg_contract<T, true>(J, C1, T1, T2, F1, F1, C1, C1);         // j -> b
+    pmg_contract<T, true>(J, C1, T1, T2, F1, F1, C1, C1, lane);         // j -> b
     __syncthreads();
-    for (int t = threadIdx.x; t < C1 * C1 * C1; t += NTX) {       // k -> a
+    for (int t = lane; t < C1 * C1 * C1; t += WAVE) {                   // k -> a
         const int c = t % C1, b = (t / C1) % C1, a = t / (C1 * C1);
         T acc = 0;
         for (int k = 0; k < F1; ++k) acc = acc + (T)J[k * C1 + a] * T2[(k * C1 + b) * C1 + c];
-        const int64_t cd = hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a);
+        const int64_t cd = valid ? hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a) : -1;
         if (cd >= 0) unsafeAtomicAdd(fc + cd, acc);
     }
 }
 
-template <int NF, int NC>
-__global__ void __launch_bounds__(NTX) k_pmg_restrict(HexView hf, HexView hc, const double *J, const void *f64,
-                                                      const void *f32, const void *ax64, const void *ax32,
-                                                      void *fc64, void *fc32, const St *st, int prec) {
-    const int p = pmg_prec(st, prec);
-    if (p == 64) pmg_restrict_body<NF, NC, double>(hf, hc, J, (const double *)f64, (const double *)ax64, (double *)fc64);
-    else if (p == 32) pmg_restrict_body<NF, NC, float>(hf, hc, J, (const float *)f32, (const float *)ax32, (float *)fc32);
-}
-
-// x += P xc at the fine nodes this element owns; ax = 0 there (the product
-// that follows sums into it).
-template <int NF, int NC, typename T>
-__device__ __forceinline__ void pmg_prolong_body(const HexView &hf, const HexView &hc, const double *J,
-                                                 const T *xc, T *x, T *ax) {
-    constexpr int F1 = NF + 1, C1 = NC + 1;
-    __shared__ T Uc[C1 * C1 * C1], V1[C1 * C1 * F1], V2[C1 * F1 * F1];
+// x += P xc at the fine nodes each wave's element owns; ax = 0 there (the
+// product that follows sums into it).
+template <int NF, int NC, int P>
+__global__ void __launch_bounds__(NTX) k_pmg_prolong(HexView hf, HexView hc, const double *J, int64_t E,
+                                                     const void *xcv, void *xv, void *axv, const St *st, int prec) {
+    typedef typename std::conditional<P == 64, double, float>::type T;
+    constexpr int F1 = NF + 1, C1 = NC + 1, CN = C1 * C1 * C1;
+    if (pmg_prec(st, prec) != P) return;   // uniform over the launch
+    __shared__ T Ucs[XW * CN], V1s[XW * C1 * C1 * F1], V2s[XW * C1 * F1 * F1];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    T *Uc = Ucs + w * CN, *V1 = V1s + w * C1 * C1 * F1, *V2 = V2s + w * C1 * F1 * F1;
+    const T *xc = (const T *)xcv;
+    T *x = (T *)xv, *ax = (T *)axv;
     int ex, ey, ez;
-    hex_element(hf, ex, ey, ez);
-    for (int t = threadIdx.x; t < C1 * C1 * C1; t += NTX) {
+    const bool valid = pmg_xfer_element(hf, E, ex, ey, ez);
+    for (int t = lane; t < CN; t += WAVE) {
         const int c = t % C1, b = (t / C1) % C1, a = t / (C1 * C1);
-        const int64_t cd = hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a);
+        const int64_t cd = valid ? hex_dof<NC>(hc, ex * NC + c, ey * NC + b, ez * NC + a) : -1;
         Uc[t] = (cd >= 0) ? xc[cd] : (T)0;
     }
     __syncthreads();
-    pmg_contract<T, false>(J, C1, Uc, V1, C1 * C1, C1, F1, 1);   // c -> i
+    pmg_contract<T, false>(J, C1, Uc, V1, C1 * C1, C1, F1, 1, lane);   // c -> i
     __syncthreads();
-    pmg_contract<T, false>(J, C1, V1, V2, C1, C1, F1, F1);       // b -> j
+    pmg_contract<T, false>(J, C1, V1, V2, C1, C1, F1, F1, lane);       // b -> j
     __syncthreads();
-    for (int t = threadIdx.x; t < F1 * F1 * F1; t += NTX) {      // a -> k
+    if (!valid) return;   // after the last barrier
+    for (int t = lane; t < F1 * F1 * F1; t += WAVE) {                  // a -> k
         const int i = t % F1, j = (t / F1) % F1, k = t / (F1 * F1);
         if (!hex_owner<NF>(hf, ex, ey, ez, i, j, k)) continue;
         const int64_t dof = hex_dof<NF>(hf, ex * NF + i, ey * NF + j, ez * NF + k);
@@ -339,15 +358,6 @@ __device__ __forceinline__ void pmg_prolong_body(const HexView &hf, const HexVie
         x[dof] = x[dof] + acc;
         ax[dof] = (T)0;
     }
-}
-
-template <int NF, int NC>
-__global__ void __launch_bounds__(NTX) k_pmg_prolong(HexView hf, HexView hc, const double *J, const void *xc64,
-                                                     const void *xc32, void *x64, void *x32, void *ax64, void *ax32,
-                                                     const St *st, int prec) {
-    const int p = pmg_prec(st, prec);
-    if (p == 64) pmg_prolong_body<NF, NC, double>(hf, hc, J, (const double *)xc64, (double *)x64, (double *)ax64);
-    else if (p == 32) pmg_prolong_body<NF, NC, float>(hf, hc, J, (const float *)xc32, (float *)x32, (float *)ax32);
 }
 
 // Standalone entry and exit: f = fl_prec(r); z = x (FP64).
