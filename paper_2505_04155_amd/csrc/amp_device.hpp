@@ -111,10 +111,10 @@ struct Sell {
 
 constexpr int kOffMax = 32;  // longest per-slice offset list
 // Capacity of the memory-side cache.  A matrix plane larger than this is
-// streamed from HBM every application anyway, and the Chebyshev step loads
-// it with a non-temporal hint so it does not displace the gathered vectors;
-// a smaller one stays cached between applications, which the hint would
-// prevent.
+// streamed from HBM every application anyway, and the product and Chebyshev
+// step load it with a non-temporal hint so it does not displace the
+// gathered vectors; a smaller one stays cached between applications, which
+// the hint would prevent.
 constexpr int64_t kMallBytes = (int64_t)256 << 20;
 
 // Issue priority from a wave's progress through its work-group's range.

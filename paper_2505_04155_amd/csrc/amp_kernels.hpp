@@ -693,8 +693,10 @@ __global__ void __launch_bounds__(NT) k_precond(const St *in, const double *part
 // flight, never the order of the sums.
 // LANES: the matrix may have several lanes per row (index-mode slices only;
 // see rows_dot64).
+// NTL: the offset-mode values are loaded with a non-temporal hint (a value
+// plane larger than the memory-side cache, kMallBytes).
 template <int UZ, int UR, bool DIFF, bool FIRST, int BS, bool PRIO = true, int SPC = AMP_SPMV_SPC,
-          bool LANES = false>
+          bool LANES = false, bool NTL = false>
 __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv, const void *pov, void *pnv,
                                             void *qv, double beta_d, double &gam, double &mp) {
     typedef typename Prec<UZ>::T TZ;
@@ -764,7 +766,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
 #pragma unroll
                 for (int u = 0; u < PS; ++u) {
                     const int j = full ? j0 + u : (j0 + u < w ? j0 + u : w - 1);
-                    v[u] = at32(vs, (uint32_t)(lane + j * SLICE));
+                    v[u] = at32t<NTL>(vs, (uint32_t)(lane + j * SLICE));
                     pj[u] = pval(rowg + (uint32_t)o[u]);
                 }
 #pragma unroll
@@ -813,7 +815,7 @@ __device__ __forceinline__ void spmv_p_body(const Sell &A, Wg wg, const void *zv
 // that precision's bodies are compiled), else 0 (read from the state).  A
 // state whose u_z differs from UZF can only come from a non-finite residual:
 // it ends the solve as a breakdown.
-template <int BS, bool PRIO = true, int UZF = 0, int SPC = AMP_SPMV_SPC, bool LANES = false>
+template <int BS, bool PRIO = true, int UZF = 0, int SPC = AMP_SPMV_SPC, bool LANES = false, bool NTL = false>
 __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bufs &B, const St *in, St *out,
                                            Wg wg, const Early &e) {
     __shared__ St s;
@@ -858,10 +860,10 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
 #define AMP_SP(UZ, UR, DF)                                                                                \
     do {                                                                                                 \
         if (first)                                                                                       \
-            spmv_p_body<UZ, UR, DF, true, BS, PRIO, SPC, LANES>(A, wg, B.z[ps], B.p[ps][pb],              \
+            spmv_p_body<UZ, UR, DF, true, BS, PRIO, SPC, LANES, NTL>(A, wg, B.z[ps], B.p[ps][pb],         \
                                                          B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, gam, mp); \
         else                                                                                             \
-            spmv_p_body<UZ, UR, DF, false, BS, PRIO, SPC, LANES>(A, wg, B.z[ps], B.p[ps][pb],             \
+            spmv_p_body<UZ, UR, DF, false, BS, PRIO, SPC, LANES, NTL>(A, wg, B.z[ps], B.p[ps][pb],        \
                                                           B.p[ps][pb ^ 1], B.q[pslot(UR)], beta, gam, mp); \
     } while (0)
 #define AMP_SP_R(UZ)                          \
@@ -891,26 +893,27 @@ __device__ __forceinline__ void spmv_stage(const Cfg &c, const Sell &A, const Bu
     store_state(s, out, wg);
 }
 
-template <int UZF, bool LANES = false>
+template <int UZF, bool LANES = false, bool NTL = false>
 __global__ void __launch_bounds__(NTP, (UZF == 16 || UZF == 32) ? AMP_SPMV_WAVES : 4)
     k_spmv(const St *in, const double *part, int gpart, int grid, Cfg c, Sell A, Bufs B, St *out) {
-    spmv_stage<NTP, true, UZF, AMP_SPMV_SPC, LANES>(
+    spmv_stage<NTP, true, UZF, AMP_SPMV_SPC, LANES, NTL>(
         c, A, B, in, out, launch_wg(grid),
         Early{part, gpart, nullptr, touch_args<24 + sizeof(Cfg) + sizeof(Sell) + sizeof(Bufs)>()});
 }
 
 typedef void (*SpmvFn)(const St *, const double *, int, int, Cfg, Sell, Bufs, St *);
 
-// The product kernel for the options' fixed u_z (0: read from the state)
-// and the matrix's lanes per row (any layout with lanes > 1 takes the
-// general u_z path: its long rows make the product bound by the values).
-inline SpmvFn spmv_fn(int uzf, bool lanes = false) {
+// The product kernel for the options' fixed u_z (0: read from the state),
+// the matrix's lanes per row (any layout with lanes > 1 takes the general
+// u_z path: its long rows make the product bound by the values) and
+// whether its values are streamed with a non-temporal hint.
+inline SpmvFn spmv_fn(int uzf, bool lanes = false, bool nt = false) {
     if (lanes) return k_spmv<0, true>;
     switch (uzf) {
-        case 16: return k_spmv<16>;
-        case 32: return k_spmv<32>;
-        case 64: return k_spmv<64>;
-        default: return k_spmv<0>;
+        case 16: return nt ? k_spmv<16, false, true> : k_spmv<16>;
+        case 32: return nt ? k_spmv<32, false, true> : k_spmv<32>;
+        case 64: return nt ? k_spmv<64, false, true> : k_spmv<64>;
+        default: return nt ? k_spmv<0, false, true> : k_spmv<0>;
     }
 }
 

@@ -1496,6 +1496,10 @@ static void enqueue_pmg(Driver &d, St *in, St *out) {
     k_cheb_deg1<<<d.gs, NT, 0, d.st>>>(d.B, pmg_cheb(P, d.A->np, true), pre, out);
 }
 
+// The product streams its values with a non-temporal hint when the FP32
+// plane (and so the FP64 one) exceeds the memory-side cache.
+static bool spmv_nt(amp_matrix A) { return A->slots * (int64_t)sizeof(float) > kMallBytes; }
+
 static amp_status enqueue_iterations(Driver &d, int count) {
     Work &w = d.A->w;
     for (int i = 0; i < count; ++i) {
@@ -1535,14 +1539,14 @@ static amp_status enqueue_iterations(Driver &d, int count) {
             d.cfg.spmv_iter = w.titer;
             d.cfg.spmv_launch = d.launches;
             // events carried by the dispatch itself: they bracket the kernel, not the queue
-            hipExtLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0), dim3(d.gl), dim3(NTP), 0, d.st, w.tev[2 * d.launches],
+            hipExtLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0, spmv_nt(d.A)), dim3(d.gl), dim3(NTP), 0, d.st, w.tev[2 * d.launches],
                                   w.tev[2 * d.launches + 1], 0, (const St *)&d.sb[ST_PRE],
                                   (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B,
                                   &d.sb[ST_SPMV]);
             d.launches += 1;
             d.cfg.spmv_iter = nullptr;
         } else {
-            hipLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0), dim3(d.gl), dim3(NTP), 0, d.st, (const St *)&d.sb[ST_PRE],
+            hipLaunchKernelGGL(spmv_fn(d.uzf, d.S.lgL > 0, spmv_nt(d.A)), dim3(d.gl), dim3(NTP), 0, d.st, (const St *)&d.sb[ST_PRE],
                                (const double *)d.B.part_pre, d.cfg.g_pre, d.gl, d.cfg, d.S, d.B, &d.sb[ST_SPMV]);
         }
         k_update<<<d.gs, NT, 0, d.st>>>(&d.sb[ST_SPMV], d.B.part_spmv, d.cfg.g_slice, d.gs, d.cfg, d.B, d.A->np,
