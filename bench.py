@@ -19,12 +19,14 @@ bound against the FP64 oracle's solution, the HBM roofline of the dominant
 kernel (the Chebyshev step, every launch of one AMP-PCG(FP16) solve timed by
 HIP events carried by its own dispatch) with the product kernel's beside
 it, the library's stream probes as the measured ceiling, the FP64 CPU oracle
-timed on the host on a bounded sample, and the 128^3 finite-volume workload
-as a secondary measurement.
+timed on the host on a bounded sample, and as secondary measurements the
+128^3 finite-volume workload, the 512-system batched solve, the matrix-free
+order-7 hexahedral operator with Jacobi-PCG on it (Ex. jac libp), and the
+p-multigrid preconditioned Poisson problem (Ex. linear conv2).
 
 Modes: --mode roofline runs only the timed solve and the probes (the command
-the kernel-trace and counter runs profile); --mode fv128 the 128^3 workload
-alone.
+the kernel-trace and counter runs profile); --mode fv128, --mode batched,
+--mode hex and --mode pmg run one secondary workload alone.
 """
 
 from __future__ import annotations
