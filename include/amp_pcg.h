@@ -576,7 +576,9 @@ void amp_pmg_params_default(amp_pmg_params *p);
  * AMP_ERR_ARG for a handle that is not matrix-free, parameters out of
  * range, a level without unknowns (order 1 needs at least 2 elements per
  * direction), a non-positive diagonal or an estimate of rho that is not
- * positive and finite; AMP_ERR_OOM / AMP_ERR_HIP.  Host-synchronous. */
+ * positive and finite; AMP_ERR_OOM / AMP_ERR_HIP.  Host-synchronous.
+ * The cycle's work vectors belong to the handle: solves and amp_pmg_apply
+ * calls that use one handle must not overlap (in time or across streams). */
 amp_status amp_precond_create_pmg(amp_matrix A, const amp_pmg_params *p, void *stream, amp_precond *out);
 amp_status amp_pmg_info(amp_precond M, amp_pmg_stats *out);
 /* z = V(r) (device, n doubles each), the cycle in FP64 (prec 64) or FP32
