@@ -380,7 +380,7 @@ def pmg_measurement(amp, torch, np, P, dev, E=(30, 30, 30), order=7, reps=10):
     """The Poisson problem of Ex. linear conv2 (order 7 on 30^3 trilinear
     hexahedra of [-0.5, 0.5]^3, interior vertices moved by 0.2 h in place of
     the Kershaw mesh, homogeneous Dirichlet) with the p-multigrid V-cycle
-    (orders 7, 3, 1; degree-2 Chebyshev-Jacobi smoothing; a degree-8
+    (orders 7, 3, 1; degree-2 Chebyshev-Jacobi smoothing; a degree-16
     Chebyshev-Jacobi polynomial on order 1 in place of algebraic multigrid):
     FP64 PCG against AMP-PCG(FP16) with z and p in FP16 from the first
     iteration (the linear and the delay u_r criteria), the cycle's cost in
@@ -398,7 +398,7 @@ def pmg_measurement(amp, torch, np, P, dev, E=(30, 30, 30), order=7, reps=10):
     out = {"workload": f"Poisson -Laplace u = 1 + 3 pi^2 sin(pi x) sin(pi y) sin(pi z), order {order}, "
                        f"{E[0]}x{E[1]}x{E[2]} trilinear hexahedra of [-0.5,0.5]^3 (interior vertices moved by "
                        f"0.2 h), n={H.n}; p-multigrid V-cycle over orders {pi['orders']} (degree-2 "
-                       f"Chebyshev-Jacobi smoothing, degree-8 Chebyshev-Jacobi polynomial on the lowest order), "
+                       f"Chebyshev-Jacobi smoothing, degree-16 Chebyshev-Jacobi polynomial on the lowest order), "
                        f"tol 1e-10",
            "levels_n": pi["n"], "rho": [round(r, 6) for r in pi["rho"]], "gain": pi["gain"],
            "setup_ms": round(setup_ms, 1), "preconditioner_bytes": pi["bytes"]}

@@ -550,7 +550,7 @@ typedef struct {
     int levels;             /* 1 .. 4 */
     int orders[4];          /* strictly decreasing, each 1, 3 or 7; orders[0] = the operator's order */
     int degree;             /* smoother degree, 1 .. 16 (default 2) */
-    int coarse_degree;      /* lowest level's polynomial degree, 1 .. 16 (default 8) */
+    int coarse_degree;      /* lowest level's polynomial degree, 1 .. 16 (default 16) */
     double lo_ratio;        /* smoothing interval [lo_ratio rho, hi_margin rho] (default 0.1, 1.1) */
     double hi_margin;
     double coarse_lo_ratio; /* lowest level's interval [coarse_lo_ratio rho, hi_margin rho] (default 0.01) */
@@ -566,7 +566,7 @@ typedef struct {
     int64_t bytes;          /* device memory held by the preconditioner */
 } amp_pmg_stats;
 
-/* Defaults: three levels (7, 3, 1), degree 2, coarse degree 8, intervals
+/* Defaults: three levels (7, 3, 1), degree 2, coarse degree 16, intervals
  * [0.1, 1.1] rho and [0.01, 1.1] rho, rho estimated with 40 steps. */
 void amp_pmg_params_default(amp_pmg_params *p);
 /* Create the preconditioner for A, a handle from amp_matrix_from_hexop

@@ -108,7 +108,7 @@ class PMultigrid:
 
     kind = "pmg"
 
-    def __init__(self, fine: HexMesh, orders=(7, 3, 1), degree=2, coarse_degree=8, lo_ratio=0.1,
+    def __init__(self, fine: HexMesh, orders=(7, 3, 1), degree=2, coarse_degree=16, lo_ratio=0.1,
                  hi_margin=1.1, coarse_lo_ratio=0.01, rho=None):
         if fine.N != orders[0]:
             raise ValueError("the finest order must be the mesh's")

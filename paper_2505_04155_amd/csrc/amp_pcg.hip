@@ -3058,7 +3058,7 @@ extern "C" void amp_pmg_params_default(amp_pmg_params *p) {
     p->orders[1] = 3;
     p->orders[2] = 1;
     p->degree = 2;
-    p->coarse_degree = 8;
+    p->coarse_degree = 16;
     p->lo_ratio = 0.1;
     p->hi_margin = 1.1;
     p->coarse_lo_ratio = 0.01;

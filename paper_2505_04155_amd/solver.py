@@ -120,7 +120,7 @@ class Preconditioner:
         self.kind = kind
 
     @classmethod
-    def pmg(cls, A: Matrix, orders=(7, 3, 1), degree: int = 2, coarse_degree: int = 8, lo_ratio: float = 0.1,
+    def pmg(cls, A: Matrix, orders=(7, 3, 1), degree: int = 2, coarse_degree: int = 16, lo_ratio: float = 0.1,
             hi_margin: float = 1.1, coarse_lo_ratio: float = 0.01, rho=None, power_iters: int = 40):
         """The p-multigrid V-cycle over the polynomial orders ``orders`` for
         a matrix-free handle (Matrix.from_hexop): Chebyshev-Jacobi smoothing

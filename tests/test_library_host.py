@@ -159,7 +159,7 @@ def test_pmg_defaults_and_null_arguments():
     L = B.load()
     p = B.PmgParams()
     L.amp_pmg_params_default(ctypes.byref(p))
-    assert (p.levels, list(p.orders)[:3], p.degree, p.coarse_degree, p.power_iters) == (3, [7, 3, 1], 2, 8, 40)
+    assert (p.levels, list(p.orders)[:3], p.degree, p.coarse_degree, p.power_iters) == (3, [7, 3, 1], 2, 16, 40)
     assert (p.lo_ratio, p.hi_margin, p.coarse_lo_ratio) == (0.1, 1.1, 0.01)
     assert list(p.rho) == [0.0] * 4
     h = ctypes.c_void_p()
