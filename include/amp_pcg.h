@@ -549,8 +549,8 @@ amp_status amp_matrix_from_hexop(amp_hexop H, void *stream, amp_matrix *out);
 typedef struct {
     int levels;             /* 1 .. 4 */
     int orders[4];          /* strictly decreasing, each 1, 3 or 7; orders[0] = the operator's order */
-    int degree;             /* smoother degree, 1 .. 16 (default 2) */
-    int coarse_degree;      /* lowest level's polynomial degree, 1 .. 16 (default 16) */
+    int degree;             /* smoother degree, 1 .. 32 (default 2) */
+    int coarse_degree;      /* lowest level's polynomial degree, 1 .. 32 (default 16) */
     double lo_ratio;        /* smoothing interval [lo_ratio rho, hi_margin rho] (default 0.1, 1.1) */
     double hi_margin;
     double coarse_lo_ratio; /* lowest level's interval [coarse_lo_ratio rho, hi_margin rho] (default 0.01) */

@@ -3144,7 +3144,7 @@ static amp_status pmg_check(const amp_matrix A, const amp_pmg_params &p) {
         if (!std::isfinite(p.rho[l])) return fail(AMP_ERR_ARG, std::string(w) + "rho must be finite");
     }
     if (p.degree < 1 || p.degree > kPmgDegMax || p.coarse_degree < 1 || p.coarse_degree > kPmgDegMax)
-        return fail(AMP_ERR_ARG, std::string(w) + "degrees must be 1 to 16");
+        return fail(AMP_ERR_ARG, std::string(w) + "degrees must be 1 to 32");
     if (!(p.lo_ratio > 0.0 && p.lo_ratio < 1.0) || !(p.coarse_lo_ratio > 0.0 && p.coarse_lo_ratio < 1.0) ||
         !(p.hi_margin >= 1.0) || !std::isfinite(p.hi_margin))
         return fail(AMP_ERR_ARG, std::string(w) + "need 0 < lo_ratio, coarse_lo_ratio < 1 <= hi_margin");

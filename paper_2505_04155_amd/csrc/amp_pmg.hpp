@@ -30,7 +30,7 @@
 namespace amp {
 
 constexpr int kPmgLevels = 4;    // most levels of a cycle
-constexpr int kPmgDegMax = 16;   // highest smoother / coarse polynomial degree
+constexpr int kPmgDegMax = 32;   // highest smoother / coarse polynomial degree
 constexpr int NTV = 256;         // threads of the vector kernels
 constexpr int kPmgPartMax = 1024;
 

@@ -136,7 +136,7 @@ def test_pmg_refusals(amp):
     with pytest.raises(B.AmpError, match="orders\\[0\\]"):
         amp.Preconditioner.pmg(M, orders=(3, 1))
     with pytest.raises(B.AmpError, match="degrees"):
-        amp.Preconditioner.pmg(M, degree=17)
+        amp.Preconditioner.pmg(M, degree=33)
     # order 1 on one element per direction has no unknowns
     V1 = P.hex_vertices((1, 2, 2), 0.0)
     H1 = amp.HexOperator(torch.tensor(V1, device="cuda"), (1, 2, 2), order=7)
